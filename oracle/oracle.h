@@ -1,0 +1,108 @@
+/*
+ * oracle.h -- plain, serial, FP64 reference of one stage of the moving-mesh
+ * Godunov scheme of RICH (Yalinewich, Steinberg & Sari).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline of the benchmark may load this library.  It shares no code, header,
+ * table or helper with the device path; both read the same mesh arrays
+ * produced by the host tessellation stage.
+ *
+ * Conventions (layout of the arrays the host stage produces):
+ *   cells    px,py points; sx,sy centroids; area
+ *   edges    e_i (real cell), e_j (neighbour cell in the low 28 bits, ghost
+ *            code in the top 4: 0 interior, 1..8 periodic image shift,
+ *            9..12 reflecting wall x0,x1,y0,y1), e_len, e_fx/e_fy (midpoint,
+ *            in e_i's frame)
+ *   CSR      off[n+1], idx = 2*edge + side (side 1: the cell is e_j)
+ * State arrays are planar: Q[4*n] = M | Px | Py | E (extensive totals over the
+ * cell), X[2*n] = x | y.
+ */
+#ifndef RICH_ORACLE_H
+#define RICH_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct or_mesh {
+  int64_t n_cells, n_edges;
+  const double *px, *py, *sx, *sy, *area;
+  const int32_t *e_i, *e_j;
+  const double *e_len, *e_fx, *e_fy;
+  const int32_t *off, *idx;
+  double box[4];
+  uint32_t bc;
+} or_mesh;
+
+typedef struct or_params {
+  double gamma;    /* adiabatic index                                    */
+  double cfl;      /* Courant number (paper default 0.3)                 */
+  double theta;    /* local-limiter factor (0.5)                         */
+  double delta_v;  /* shock-detector compression threshold (0.2)        */
+  double delta_p;  /* shock-detector pressure-ratio threshold (0.7)     */
+  double chi;      /* cell-rounding speed in units of c_s (0.15)        */
+  double eta;      /* cell-rounding offset threshold in units of R (0.02) */
+  int32_t riemann; /* 0 HLLC, 1 exact                                   */
+  int32_t motion;  /* 0 static (Eulerian), 1 Lagrangian + cell rounding */
+  int32_t limiter; /* 0 switching (paper default), 1 global only, 2 local
+                      only, 3 unlimited, 4 first order                  */
+} or_params;
+
+/* status codes */
+#define OR_OK 0
+#define OR_E_INVAL -1
+#define OR_E_DOMAIN -4
+
+/* A1: primitives of extensive Q on the mesh: prim[5n] = rho|vx|vy|p|c */
+int or_primitives(const or_mesh* m, const double* Q, const or_params* p, double* prim);
+
+/* A2: mesh-point velocities w[2n] from primitives (paper section 6). */
+int or_point_velocity(const or_mesh* m, const double* prim, const or_params* p,
+                      double* w);
+
+/* A3: unlimited Green-Gauss gradients (eq. slope) of rho, vx, vy, p:
+ * grad[8n] = drho/dx | drho/dy | dvx/dx | dvx/dy | dvy/dx | dvy/dy | dp/dx | dp/dy */
+int or_gradients(const or_mesh* m, const double* prim, double* grad);
+
+/* A4: limiter factors alpha[4n] and per-cell shock flags (bit 0) */
+int or_limiter(const or_mesh* m, const double* prim, const double* grad,
+               const or_params* p, double* alpha, int32_t* flag);
+
+/* A5-A7: lab-frame flux per unit length through every edge, flux[4E] planar
+ * (mass | x-momentum | y-momentum | energy), oriented from e_i to e_j.
+ * lgrad is the limited gradient (alpha * grad), w the point velocities. */
+int or_edge_fluxes(const or_mesh* m, const double* prim, const double* lgrad,
+                   const double* w, const or_params* p, double* flux);
+
+/* Area change rate of every cell implied by the edge velocities (eq. areachange) */
+int or_area_rate(const or_mesh* m, const double* w, double* adot);
+
+/* One stage: Qout = Qbase - h * sum_edges(L F), Xout = Xbase + h w.
+ * Optional diagnostics (may be NULL): prim[5n], w[2n], alpha[4n], flag[n],
+ * flux[4E]. Returns OR_E_DOMAIN if a produced cell has M<=0, internal energy
+ * <= 0 or a non-finite value (outputs are still written). */
+int or_stage(const or_mesh* m, const double* Qsrc, const double* Qbase,
+             const double* Xbase, double h, const or_params* p, double* Qout,
+             double* Xout, double* d_prim, double* d_w, double* d_alpha,
+             int32_t* d_flag, double* d_flux);
+
+/* Courant time step of the state Q on mesh m (A0). */
+int or_cfl_dt(const or_mesh* m, const double* Q, const or_params* p, double* dt);
+
+/* One-dimensional Riemann problem in the frame of an edge.  States are
+ * (rho, u, vt, p): density, normal velocity, tangential velocity, pressure.
+ * Flux out: (mass, normal momentum, tangential momentum, energy). */
+void or_hllc(double gamma, const double* WL, const double* WR, double* F);
+/* Exact solver: flux at x/t = 0; star[2] = (p*, u*) if non-NULL; returns the
+ * Newton iteration count, or -1 when the states would create a vacuum. */
+int or_exact(double gamma, const double* WL, const double* WR, double* F, double* star);
+/* Sample the exact solution at x/t = xi: W = (rho, u, vt, p). */
+int or_exact_sample(double gamma, const double* WL, const double* WR, double xi,
+                    double* W);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

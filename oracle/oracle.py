@@ -1,0 +1,307 @@
+"""ctypes wrapper of the plain serial FP64 oracle (liboracle.so, oracle.h).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline may use this module; the product path never does.  It imports
+nothing from the device-side package: meshes are any objects carrying the
+host-stage arrays (px, py, sx, sy, area, e_i, e_j, e_len, e_fx, e_fy, off,
+idx, box, bc), and the time-centred step takes the tessellation as a callable.
+
+or_step composes two stages the way section 2.3 of the paper describes the
+"time centred fluxes" scheme: advance half a step, rebuild the mesh from the
+half-step points, compute the primitives there, apply the resulting fluxes
+to the start-of-step state with the full step, and move the points from their
+start-of-step positions with the half-step point velocities.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "oracle.c")
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+def build(force=False):
+    """Compile liboracle.so with gcc (plain C99, -O2, no FMA contraction)."""
+    if force or not os.path.exists(LIB_PATH) or \
+            os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
+               SRC_PATH, "-o", LIB_PATH + ".tmp", "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class OrMesh(C.Structure):
+    _fields_ = [
+        ("n_cells", C.c_int64), ("n_edges", C.c_int64),
+        ("px", _dp), ("py", _dp), ("sx", _dp), ("sy", _dp), ("area", _dp),
+        ("e_i", _ip), ("e_j", _ip), ("e_len", _dp), ("e_fx", _dp), ("e_fy", _dp),
+        ("off", _ip), ("idx", _ip), ("box", C.c_double * 4), ("bc", C.c_uint32),
+    ]
+
+
+class OrParams(C.Structure):
+    _fields_ = [
+        ("gamma", C.c_double), ("cfl", C.c_double), ("theta", C.c_double),
+        ("delta_v", C.c_double), ("delta_p", C.c_double), ("chi", C.c_double),
+        ("eta", C.c_double), ("riemann", C.c_int32), ("motion", C.c_int32),
+        ("limiter", C.c_int32),
+    ]
+
+
+@dataclass
+class Params:
+    """Scheme parameters; defaults are the paper's (sections 2.2, 2.3, 6)."""
+    gamma: float = 5.0 / 3.0
+    cfl: float = 0.3
+    theta: float = 0.5
+    delta_v: float = 0.2
+    delta_p: float = 0.7
+    chi: float = 0.15
+    eta: float = 0.02
+    riemann: int = 0   # 0 HLLC, 1 exact
+    motion: int = 1    # 0 static, 1 Lagrangian + cell rounding
+    limiter: int = 0   # 0 switching, 1 global, 2 local, 3 unlimited, 4 first order
+
+    def c(self):
+        return OrParams(self.gamma, self.cfl, self.theta, self.delta_v, self.delta_p,
+                        self.chi, self.eta, self.riemann, self.motion, self.limiter)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        mp, pp = C.POINTER(OrMesh), C.POINTER(OrParams)
+        L.or_primitives.argtypes = [mp, _dp, pp, _dp]
+        L.or_point_velocity.argtypes = [mp, _dp, pp, _dp]
+        L.or_gradients.argtypes = [mp, _dp, _dp]
+        L.or_limiter.argtypes = [mp, _dp, _dp, pp, _dp, _ip]
+        L.or_edge_fluxes.argtypes = [mp, _dp, _dp, _dp, pp, _dp]
+        L.or_area_rate.argtypes = [mp, _dp, _dp]
+        L.or_stage.argtypes = [mp, _dp, _dp, _dp, C.c_double, pp, _dp, _dp, _dp, _dp,
+                               _dp, _ip, _dp]
+        L.or_cfl_dt.argtypes = [mp, _dp, pp, _dp]
+        L.or_hllc.argtypes = [C.c_double, _dp, _dp, _dp]
+        L.or_hllc.restype = None
+        L.or_exact.argtypes = [C.c_double, _dp, _dp, _dp, _dp]
+        L.or_exact_sample.argtypes = [C.c_double, _dp, _dp, C.c_double, _dp]
+        for f in ("or_primitives", "or_point_velocity", "or_gradients", "or_limiter",
+                  "or_edge_fluxes", "or_area_rate", "or_stage", "or_cfl_dt", "or_exact",
+                  "or_exact_sample"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    return a.ctypes.data_as(_ip)
+
+
+class _MeshRef:
+    """Keeps the contiguous arrays alive while the C struct points at them."""
+
+    def __init__(self, mesh):
+        self.a = {}
+        for k in ("px", "py", "sx", "sy", "area", "e_len", "e_fx", "e_fy"):
+            self.a[k] = np.ascontiguousarray(getattr(mesh, k), dtype=np.float64)
+        for k in ("e_i", "e_j", "off", "idx"):
+            self.a[k] = np.ascontiguousarray(getattr(mesh, k), dtype=np.int32)
+        self.n = self.a["px"].shape[0]
+        self.ne = self.a["e_i"].shape[0]
+        self.s = OrMesh(self.n, self.ne,
+                        *[_d(self.a[k]) for k in ("px", "py", "sx", "sy", "area")],
+                        _i(self.a["e_i"]), _i(self.a["e_j"]),
+                        *[_d(self.a[k]) for k in ("e_len", "e_fx", "e_fy")],
+                        _i(self.a["off"]), _i(self.a["idx"]),
+                        (C.c_double * 4)(*mesh.box), int(mesh.bc))
+
+
+def _f64(a, shape):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    assert a.shape == shape, (a.shape, shape)
+    return a
+
+
+def primitives(mesh, Q, p: Params):
+    m = _MeshRef(mesh)
+    Q = _f64(Q, (4, m.n))
+    out = np.empty((5, m.n))
+    lib().or_primitives(C.byref(m.s), _d(Q), C.byref(p.c()), _d(out))
+    return out
+
+
+def point_velocity(mesh, prim, p: Params):
+    m = _MeshRef(mesh)
+    prim = _f64(prim, (5, m.n))
+    w = np.empty((2, m.n))
+    lib().or_point_velocity(C.byref(m.s), _d(prim), C.byref(p.c()), _d(w))
+    return w
+
+
+def gradients(mesh, prim):
+    """Unlimited gradients (8, n): d/dx, d/dy of rho, vx, vy, p."""
+    m = _MeshRef(mesh)
+    prim = _f64(prim, (5, m.n))
+    g = np.empty((8, m.n))
+    lib().or_gradients(C.byref(m.s), _d(prim), _d(g))
+    return g
+
+
+def limiter(mesh, prim, grad, p: Params):
+    m = _MeshRef(mesh)
+    prim = _f64(prim, (5, m.n))
+    grad = _f64(grad, (8, m.n))
+    alpha = np.empty((4, m.n))
+    flag = np.empty(m.n, dtype=np.int32)
+    lib().or_limiter(C.byref(m.s), _d(prim), _d(grad), C.byref(p.c()), _d(alpha),
+                     _i(flag))
+    return alpha, flag
+
+
+def edge_fluxes(mesh, prim, lgrad, w, p: Params):
+    m = _MeshRef(mesh)
+    prim, lgrad, w = _f64(prim, (5, m.n)), _f64(lgrad, (8, m.n)), _f64(w, (2, m.n))
+    F = np.empty((4, m.ne))
+    st = lib().or_edge_fluxes(C.byref(m.s), _d(prim), _d(lgrad), _d(w), C.byref(p.c()),
+                              _d(F))
+    return F, st
+
+
+def area_rate(mesh, w):
+    m = _MeshRef(mesh)
+    w = _f64(w, (2, m.n))
+    out = np.empty(m.n)
+    lib().or_area_rate(C.byref(m.s), _d(w), _d(out))
+    return out
+
+
+@dataclass
+class StageResult:
+    Q: np.ndarray
+    X: np.ndarray
+    status: int
+    prim: np.ndarray = None
+    w: np.ndarray = None
+    alpha: np.ndarray = None
+    flag: np.ndarray = None
+    flux: np.ndarray = None
+
+
+def stage(mesh, Qsrc, Qbase, Xbase, h, p: Params, diag=False) -> StageResult:
+    """One stage (mesh, Q_src, Q_base, X_base, h) -> (Q_out, X_out)."""
+    m = _MeshRef(mesh)
+    Qsrc, Qbase = _f64(Qsrc, (4, m.n)), _f64(Qbase, (4, m.n))
+    Xbase = _f64(Xbase, (2, m.n))
+    Qout = np.empty((4, m.n))
+    Xout = np.empty((2, m.n))
+    if diag:
+        prim, w = np.empty((5, m.n)), np.empty((2, m.n))
+        alpha, flag = np.empty((4, m.n)), np.empty(m.n, dtype=np.int32)
+        flux = np.empty((4, max(m.ne, 1)))
+        ptrs = (_d(prim), _d(w), _d(alpha), _i(flag), _d(flux))
+    else:
+        prim = w = alpha = flag = flux = None
+        ptrs = (None, None, None, None, None)
+    st = lib().or_stage(C.byref(m.s), _d(Qsrc), _d(Qbase), _d(Xbase), float(h),
+                        C.byref(p.c()), _d(Qout), _d(Xout), *ptrs)
+    if diag:
+        flux = flux[:, :m.ne]
+    return StageResult(Qout, Xout, st, prim, w, alpha, flag, flux)
+
+
+def cfl_dt(mesh, Q, p: Params):
+    m = _MeshRef(mesh)
+    Q = _f64(Q, (4, m.n))
+    dt = C.c_double(0.0)
+    st = lib().or_cfl_dt(C.byref(m.s), _d(Q), C.byref(p.c()), C.byref(dt))
+    return dt.value, st
+
+
+def hllc(gamma, WL, WR):
+    WL, WR = (np.ascontiguousarray(v, dtype=np.float64) for v in (WL, WR))
+    F = np.empty(4)
+    lib().or_hllc(float(gamma), _d(WL), _d(WR), _d(F))
+    return F
+
+
+def exact(gamma, WL, WR):
+    """(flux at x/t=0, p*, u*, iterations)."""
+    WL, WR = (np.ascontiguousarray(v, dtype=np.float64) for v in (WL, WR))
+    F, star = np.empty(4), np.empty(2)
+    it = lib().or_exact(float(gamma), _d(WL), _d(WR), _d(F), _d(star))
+    return F, star[0], star[1], it
+
+
+def exact_sample(gamma, WL, WR, xi):
+    WL, WR = (np.ascontiguousarray(v, dtype=np.float64) for v in (WL, WR))
+    W = np.empty(4)
+    it = lib().or_exact_sample(float(gamma), _d(WL), _d(WR), float(xi), _d(W))
+    return W, it
+
+
+def step(mesh, Q, X, dt, p: Params, tess, diag=False):
+    """Time-centred step.  `tess(px, py, box, bc)` returns the mesh of the
+    given points.  Returns (Q_new, X_new, mesh_new, mesh_half, status)."""
+    s1 = stage(mesh, Q, Q, X, 0.5 * dt, p)
+    if s1.status != 0:
+        return None, None, None, None, s1.status
+    mesh_h = tess(s1.X[0], s1.X[1], mesh.box, mesh.bc) if p.motion else mesh
+    s2 = stage(mesh_h, s1.Q, Q, X, dt, p)
+    if s2.status != 0:
+        return None, None, None, mesh_h, s2.status
+    mesh_n = tess(s2.X[0], s2.X[1], mesh.box, mesh.bc) if p.motion else mesh
+    return s2.Q, s2.X, mesh_n, mesh_h, 0
+
+
+class use_library:
+    """Context manager: route this module's calls to another build of the
+    oracle (used by the test that plants mistakes in a copy of oracle.c)."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        _lib = None
+        saved_path = LIB_PATH
+        globals()["LIB_PATH"] = self.path
+        try:
+            lib()
+        finally:
+            globals()["LIB_PATH"] = saved_path
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def build_variant(src_text, out_path):
+    """Compile oracle source text (a modified copy) to out_path."""
+    src = out_path + ".c"
+    with open(src, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC",
+                           "-shared", "-I", _HERE, src, "-o", out_path, "-lm"])
+    return out_path

@@ -1,0 +1,567 @@
+"""Pins of the oracle against facts the paper and the mathematics fix.
+
+Each pin is a plain function of the oracle module (so that the mutation test
+can run it against a copy of the oracle with a planted mistake) and raises
+AssertionError when the oracle disagrees.  What each pin fixes:
+
+  gradient_linear      eq. (slope) returns the exact gradient of a linear
+                       field (direction of r_ij, c_ij, the 1/A factor)
+  gradient_periodic    periodic images enter the gradient at the right place
+  tvd_example          section 2.2 worked example (golden values)
+  limiter_bounds       global limiter never extrapolates beyond the extrema of
+                       the neighbourhood; local limiter stays within
+                       theta*(phi_j - phi_i)
+  hllc_*               consistency, stationary contact, symmetric collision,
+                       supersonic upwinding, agreement with the exact solver
+                       for weak waves
+  exact_*              Rankine-Hugoniot conditions across the shock,
+                       isentropy and the Riemann invariant across the fan,
+                       continuity of p and u across the contact
+  area_rate_fd         eq. (areachange) equals the derivative of the
+                       re-tessellated cell areas (central differences)
+  uniform_state_moving a uniform state on a moving mesh changes each cell's
+                       totals by h * U * dA/dt (flux through moving edges)
+  uniform_flow         uniform flow is preserved (static jittered mesh, and
+                       a moving lattice)
+  advection            pure advection on a moving lattice is exact to
+                       round-off (section 4.1)
+  conservation         mass, momentum and energy totals (walls, periodic)
+  galilean             a constant boost changes nothing but the velocity and
+                       the point positions (section 4.4)
+  mirror_symmetry      a mirror-symmetric problem stays symmetric
+  point_velocity       section 6 rounding correction: none on a centroidal
+                       lattice, |w - v| = chi c_s towards the centroid
+  cfl_uniform          Courant step of a uniform state in closed form
+  sod_accuracy         2D shock tube against the exact 1D solution with
+                       eq. (Lshock), improving with resolution and better
+                       than first order
+"""
+import json
+import math
+import os
+
+import numpy as np
+
+from paper_1410_3219_amd import inputs as I
+from paper_1410_3219_amd import tess as T
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+BOX = (0.0, 0.0, 1.0, 1.0)
+
+
+def mesh(px, py, box=BOX, bc=0):
+    return T.rich_tess_build(px, py, box, bc)
+
+
+def tessf(x, y, box, bc):
+    return T.rich_tess_build(x, y, box, bc)
+
+
+def prim_array(rho, vx, vy, p, gamma):
+    rho, vx, vy, p = (np.asarray(a, dtype=np.float64) for a in (rho, vx, vy, p))
+    c = np.sqrt(gamma * p / rho)
+    return np.stack([rho, vx, vy, p, c])
+
+
+def wall_cells(m):
+    code = m.nb_code()
+    return set(m.e_i[code >= 9].tolist())
+
+
+# --------------------------------------------------------------------------
+def gradient_linear(O):
+    px, py = I.jittered_lattice(14, seed=11, jitter=0.3)
+    m = mesh(px, py)
+    gs = [(1.3, -0.7), (0.2, 0.5), (-0.4, 0.9), (2.0, 1.1)]
+    bs = [2.0, 0.1, -0.3, 5.0]
+    f = [g[0] * m.px + g[1] * m.py + b for g, b in zip(gs, bs)]
+    prim = prim_array(*f, gamma=1.4)
+    G = O.gradients(m, prim)
+    inner = np.array(sorted(set(range(m.n_cells)) - wall_cells(m)))
+    for q, g in enumerate(gs):
+        assert np.max(np.abs(G[2 * q, inner] - g[0])) < 1e-11, q
+        assert np.max(np.abs(G[2 * q + 1, inner] - g[1])) < 1e-11, q
+
+
+def gradient_periodic(O):
+    # Green-Gauss is exact for linear fields only; for a smooth periodic field
+    # the error is first order on an irregular mesh.  Images across the
+    # periodic boundary must not stand out, and the error must shrink.
+    errs = []
+    for kk in (32, 64):
+        px, py = I.jittered_lattice(kk, seed=12, jitter=0.25)
+        m = mesh(px, py, bc=1)
+        k = 2 * math.pi
+        rho = 2.0 + np.sin(k * m.px) * np.cos(k * m.py)
+        prim = prim_array(rho, np.zeros_like(rho), np.zeros_like(rho), rho, 1.4)
+        G = O.gradients(m, prim)
+        gx = k * np.cos(k * m.px) * np.cos(k * m.py)
+        gy = -k * np.sin(k * m.px) * np.sin(k * m.py)
+        err = np.maximum(np.abs(G[0] - gx), np.abs(G[1] - gy))
+        code = m.nb_code()
+        edge_cells = np.unique(np.concatenate([m.e_i[code > 0], m.nb_cell()[code > 0]]))
+        inner = np.setdiff1d(np.arange(m.n_cells), edge_cells)
+        assert err[edge_cells].max() < 1.5 * err[inner].max()
+        assert err.max() < 0.2 * k
+        errs.append(err.mean())
+    assert errs[1] < 0.7 * errs[0]
+
+
+def tvd_example(O):
+    gold = json.load(open(os.path.join(GOLDEN, "tvd_example.json")))
+    vals = np.array(gold["values"])
+    h = gold["spacing"]
+    box = (0.0, 0.0, 4 * h, 4 * h)
+    px, py = I.lattice(4, box)
+    m = mesh(px, py, box, 0)
+    col = np.floor(m.px / h).astype(int)
+    rho = vals[col]
+    one = np.ones_like(rho)
+    prim = np.stack([rho, 0 * one, 0 * one, one, one])
+    G = O.gradients(m, prim)
+    for mode, key in ((1, "global"), (2, "local")):
+        p = O.Params(limiter=mode, theta=gold["theta"])
+        alpha, flag = O.limiter(m, prim, G, p)
+        for i in range(m.n_cells):
+            if col[i] == 1:  # cell #2 of the paper, right edge at x = 2h
+                v = rho[i] + alpha[0, i] * (G[0, i] * (2 * h - m.sx[i]))
+                assert abs(v - gold[key]["cell2_right_edge"]) < 1e-13, (key, v)
+            if col[i] == 2:  # cell #3, left edge at x = 2h
+                v = rho[i] + alpha[0, i] * (G[0, i] * (2 * h - m.sx[i]))
+                assert abs(v - gold[key]["cell3_left_edge"]) < 1e-13, (key, v)
+
+
+def _face_values(m, prim, G, alpha, i):
+    out = []
+    for k in range(m.off[i], m.off[i + 1]):
+        e, side = m.idx[k] >> 1, m.idx[k] & 1
+        code = int(m.e_j.view(np.uint32)[e] >> 28)
+        fx, fy = m.e_fx[e], m.e_fy[e]
+        if side == 1 and 1 <= code <= 8:
+            kk = code - 1 if code <= 4 else code
+            fx -= (kk // 3 - 1)
+            fy -= (kk % 3 - 1)
+        j = m.e_i[e] if side == 1 else int(m.e_j.view(np.uint32)[e] & 0x0FFFFFFF)
+        out.append((j, code, fx, fy))
+    return out
+
+
+def limiter_bounds(O):
+    px, py = I.uniform_points(300, seed=13)
+    m = mesh(px, py, bc=1)
+    s = I.Stream(77)
+    vals = [1 + s.uniform(m.n_cells), s.uniform(m.n_cells, -1, 1),
+            s.uniform(m.n_cells, -1, 1), 1 + s.uniform(m.n_cells)]
+    prim = prim_array(*vals, gamma=1.4)
+    G = O.gradients(m, prim)
+    for mode in (1, 2):
+        p = O.Params(limiter=mode)
+        alpha, _ = O.limiter(m, prim, G, p)
+        assert (alpha >= 0).all() and (alpha <= 1).all()
+        for i in range(m.n_cells):
+            nbs = _face_values(m, prim, G, alpha, i)
+            for q in range(4):
+                phis = [prim[q, j] for j, _, _, _ in nbs] + [prim[q, i]]
+                lo, hi = min(phis), max(phis)
+                for j, code, fx, fy in nbs:
+                    d = alpha[q, i] * (G[2 * q, i] * (fx - m.sx[i]) + G[2 * q + 1, i] * (fy - m.sy[i]))
+                    v = prim[q, i] + d
+                    tol = 1e-12 * (1 + abs(prim[q, i]))
+                    if mode == 1:
+                        assert lo - tol <= v <= hi + tol
+                    else:
+                        bound = 0.5 * (prim[q, j] - prim[q, i])
+                        assert min(0.0, bound) - tol <= d <= max(0.0, bound) + tol
+
+
+# --------------------------------------------------------------------------
+def phys_flux(g, W):
+    rho, u, vt, p = W
+    E = p / (g - 1) + 0.5 * rho * (u * u + vt * vt)
+    return np.array([rho * u, rho * u * u + p, rho * u * vt, u * (E + p)])
+
+
+def hllc_cases(O):
+    g = 1.4
+    W = np.array([1.3, 0.4, -0.2, 0.9])
+    assert np.allclose(O.hllc(g, W, W), phys_flux(g, W), rtol=1e-14, atol=1e-15)
+    # stationary contact: only the pressure force crosses
+    F = O.hllc(g, [1.0, 0.0, 0.3, 2.0], [0.1, 0.0, -0.5, 2.0])
+    assert F[0] == 0.0 and F[2] == 0.0 and F[3] == 0.0 and abs(F[1] - 2.0) < 1e-15
+    # symmetric collision (mirror states): no mass or energy crosses
+    F = O.hllc(g, [1.0, 0.7, 0.2, 1.0], [1.0, -0.7, 0.2, 1.0])
+    assert F[0] == 0.0 and F[3] == 0.0 and F[1] > 1.0
+    # supersonic to the right / left: pure upwinding
+    WL, WR = np.array([1.0, 5.0, 0.1, 1.0]), np.array([0.5, 4.0, 0.2, 0.4])
+    assert np.allclose(O.hllc(g, WL, WR), phys_flux(g, WL), rtol=1e-15)
+    WL, WR = np.array([1.0, -5.0, 0.1, 1.0]), np.array([0.5, -4.0, 0.2, 0.4])
+    assert np.allclose(O.hllc(g, WL, WR), phys_flux(g, WR), rtol=1e-15)
+
+
+def hllc_weak_waves(O):
+    # for small jumps HLLC agrees with the exact flux to second order
+    g = 5.0 / 3.0
+    base = np.array([1.0, 0.3, 0.1, 0.6])
+    errs = []
+    for d in (1e-3, 1e-4):
+        WL = base + d * np.array([1.0, 0.5, 0.3, 2.0])
+        WR = base - d * np.array([0.5, -0.8, 0.2, 1.0])
+        F1 = O.hllc(g, WL, WR)
+        F2, _, _, it = O.exact(g, WL, WR)
+        assert it > 0
+        errs.append(np.max(np.abs(F1 - F2)))
+    assert errs[0] < 5 * 1e-3 ** 2
+    assert errs[1] < errs[0] / 30
+
+
+def _exact_profile(O, g, WL, WR, xis):
+    return np.array([O.exact_sample(g, WL, WR, x)[0] for x in xis])
+
+
+def exact_shock_tube(O):
+    """Physics of the exact solution of Sod's problem (gamma = 5/3 and 1.4)."""
+    for g in (5.0 / 3.0, 1.4):
+        WL = np.array([1.0, 0.0, 0.0, 1.0])
+        WR = np.array([0.125, 0.0, 0.0, 0.1])
+        F, ps, us, it = O.exact(g, WL, WR)
+        assert 0 < it <= 50
+        # contact: pressure and velocity continuous
+        Wl, _ = O.exact_sample(g, WL, WR, us - 1e-9)
+        Wr, _ = O.exact_sample(g, WL, WR, us + 1e-9)
+        assert abs(Wl[3] - Wr[3]) < 1e-12 and abs(Wl[1] - Wr[1]) < 1e-12
+        assert abs(Wl[3] - ps) < 1e-12 and abs(Wl[1] - us) < 1e-12
+        # right shock: locate it, then check the three jump conditions
+        xs = np.linspace(us + 1e-9, 3.0, 20001)
+        prof = _exact_profile(O, g, WL, WR, xs)
+        k = np.argmax(prof[:, 0] < 0.5 * (Wr[0] + WR[0]))
+        S = xs[k]
+        a, b = Wr, WR   # post-shock, pre-shock
+
+        def U(W):
+            rho, u, vt, p = W
+            return np.array([rho, rho * u, p / (g - 1) + 0.5 * rho * u * u])
+
+        def Fx(W):
+            return phys_flux(g, W)[[0, 1, 3]]
+        # shock speed from the mass jump, then momentum and energy must agree
+        Sm = (Fx(a)[0] - Fx(b)[0]) / (U(a)[0] - U(b)[0])
+        assert abs(Sm - S) < 2e-4
+        res = (Fx(a) - Fx(b)) - Sm * (U(a) - U(b))
+        assert np.max(np.abs(res)) < 1e-12, res
+        # left rarefaction: isentropic, u + 2c/(g-1) constant
+        cl = math.sqrt(g * WL[3] / WL[0])
+        xs = np.linspace(-cl + 1e-6, us - math.sqrt(g * ps / Wl[0]) - 1e-6, 50)
+        for x in xs:
+            W, _ = O.exact_sample(g, WL, WR, x)
+            c = math.sqrt(g * W[3] / W[0])
+            assert abs(W[3] / W[0] ** g - WL[3] / WL[0] ** g) < 1e-12
+            assert abs(W[1] + 2 * c / (g - 1) - 2 * cl / (g - 1)) < 1e-12
+            assert abs(W[1] - c - x) < 1e-12   # characteristic through the origin
+        # star region left of the contact: same entropy as the left state
+        assert abs(Wl[3] / Wl[0] ** g - WL[3] / WL[0] ** g) < 1e-12
+
+
+def exact_two_shocks(O):
+    g = 1.4
+    WL = np.array([1.0, 2.0, 0.0, 1.0])
+    WR = np.array([1.0, -2.0, 0.0, 1.0])
+    F, ps, us, it = O.exact(g, WL, WR)
+    assert abs(us) < 1e-14 and ps > 1.0
+    assert abs(F[0]) < 1e-14 and abs(F[3]) < 1e-13
+    # left shock moving left: RH between WL and the left star state
+    Wl, _ = O.exact_sample(g, WL, WR, -1e-9)
+    rho_s = Wl[0]
+    S = (rho_s * us - WL[0] * WL[1]) / (rho_s - WL[0])
+    mom = (rho_s * us * us + ps - WL[0] * WL[1] ** 2 - WL[3]) - S * (rho_s * us - WL[0] * WL[1])
+    assert abs(mom) < 1e-12
+
+
+# --------------------------------------------------------------------------
+def area_rate_fd(O):
+    px, py = I.jittered_lattice(12, seed=14, jitter=0.25)
+    m = mesh(px, py, bc=1)
+    s = I.Stream(5)
+    w = np.stack([s.uniform(m.n_cells, -1, 1), s.uniform(m.n_cells, -1, 1)])
+    ad = O.area_rate(m, w)
+    eps = 1e-5
+    mp = mesh(m.px + eps * w[0], m.py + eps * w[1], bc=1)
+    mm = mesh(m.px - eps * w[0], m.py - eps * w[1], bc=1)
+    fd = (mp.area - mm.area) / (2 * eps)
+    assert np.max(np.abs(ad - fd)) < 1e-6 * np.max(np.abs(fd)), np.max(np.abs(ad - fd))
+    # walls: a wall edge does not move normal to itself
+    px, py = I.jittered_lattice(10, seed=15, jitter=0.25)
+    m = mesh(px, py, bc=0)
+    w = np.stack([s.uniform(m.n_cells, -1, 1), s.uniform(m.n_cells, -1, 1)])
+    ad = O.area_rate(m, w)
+    mp = mesh(m.px + eps * w[0], m.py + eps * w[1], bc=0)
+    mm = mesh(m.px - eps * w[0], m.py - eps * w[1], bc=0)
+    fd = (mp.area - mm.area) / (2 * eps)
+    assert np.max(np.abs(ad - fd)) < 1e-6 * np.max(np.abs(fd))
+
+
+def uniform_state_moving(O):
+    for riemann in (0, 1):
+        px, py = I.jittered_lattice(12, seed=16, jitter=0.3)
+        m = mesh(px, py, bc=1)
+        g = 1.4
+        rho, vx, vy, pr = 1.3, 0.4, -0.2, 0.9
+        Q = I.conserved(rho, vx, vy, pr, m.area, g)
+        X = np.stack([m.px, m.py])
+        p = O.Params(gamma=g, chi=0.3, eta=0.0, riemann=riemann)
+        h = 1e-3
+        r = O.stage(m, Q, Q, X, h, p, diag=True)
+        assert r.status == 0
+        assert np.max(np.abs(r.w[0] - vx)) > 1e-3   # the rounding fix is active
+        ad = O.area_rate(m, r.w)
+        Ud = np.array([rho, rho * vx, rho * vy, pr / (g - 1) + 0.5 * rho * (vx * vx + vy * vy)])
+        dQ = r.Q - Q
+        want = h * Ud[:, None] * ad[None, :]
+        scale = h * np.max(np.abs(ad)) * np.abs(Ud)[:, None]
+        assert np.max(np.abs(dQ - want) / scale) < 1e-9
+
+
+def uniform_flow(O):
+    g = 5.0 / 3.0
+    # static jittered mesh: every flux is the same, totals are unchanged
+    P = I.uniform_flow(k=12, v=(1.0, 0.5), jitter=0.3, bc=1)
+    m = mesh(P.px, P.py, P.box, 1)
+    Q0 = P.state(m.area)
+    X = np.stack([m.px, m.py])
+    p = O.Params(gamma=g, motion=0)
+    Q = Q0
+    for _ in range(5):
+        Q, X, m, _, st = O.step(m, Q, X, 0.01, p, tessf)
+        assert st == 0
+    assert np.max(np.abs(Q - Q0) / np.abs(Q0).max(axis=1, keepdims=True)) < 1e-13
+    # moving unjittered lattice: the mesh translates, the flow is unchanged
+    P = I.uniform_flow(k=12, v=(1.0, 0.5), jitter=0.0, bc=1)
+    m = mesh(P.px, P.py, P.box, 1)
+    Q0 = P.state(m.area)
+    X0 = np.stack([m.px, m.py])
+    X = X0
+    p = O.Params(gamma=g, motion=1)
+    Q = Q0
+    t = 0.0
+    for _ in range(5):
+        Q, X, m, _, st = O.step(m, Q, X, 0.01, p, tessf)
+        assert st == 0
+        t += 0.01
+    rho = Q[0] / m.area
+    assert np.max(np.abs(rho - 1.0)) < 1e-12
+    assert np.max(np.abs(Q[1] / Q[0] - 1.0)) < 1e-12
+    assert np.max(np.abs(Q[2] / Q[0] - 0.5)) < 1e-12
+    dx = (X0[0] + t * 1.0) % 1.0 - X[0]
+    dx = (dx + 0.5) % 1.0 - 0.5
+    assert np.max(np.abs(dx)) < 1e-13
+
+
+def advection(O):
+    P = I.advection_disc(k=24)
+    m = mesh(P.px, P.py, P.box, 1)
+    Q = P.state(m.area)
+    X = np.stack([m.px, m.py])
+    rho0 = P.rho.copy()
+    p = O.Params(gamma=P.gamma, motion=1)
+    for _ in range(8):
+        dt, _ = O.cfl_dt(m, Q, p)
+        Q, X, m, _, st = O.step(m, Q, X, dt, p, tessf)
+        assert st == 0
+    rho = Q[0] / m.area
+    assert np.max(np.abs(rho - rho0) / rho0) < 1e-12
+
+
+def conservation(O):
+    # reflecting walls: mass and energy totals
+    P = I.sod(k=24, seed=21)
+    m = mesh(P.px, P.py, P.box, 0)
+    Q = P.state(m.area)
+    X = np.stack([m.px, m.py])
+    p = O.Params(gamma=P.gamma)
+    M0, E0 = Q[0].sum(), Q[3].sum()
+    for _ in range(10):
+        dt, _ = O.cfl_dt(m, Q, p)
+        Q, X, m, _, st = O.step(m, Q, X, dt, p, tessf)
+        assert st == 0
+        assert abs(Q[0].sum() - M0) < 1e-14 * 30 * M0
+        assert abs(Q[3].sum() - E0) < 1e-14 * 30 * E0
+    # periodic: mass, both momenta and energy
+    P = I.kelvin_helmholtz(k=20)
+    m = mesh(P.px, P.py, P.box, 1)
+    Q = P.state(m.area)
+    X = np.stack([m.px, m.py])
+    p = O.Params(gamma=P.gamma)
+    S0 = Q.sum(axis=1)
+    scale = np.abs(Q).sum(axis=1)
+    for _ in range(5):
+        dt, _ = O.cfl_dt(m, Q, p)
+        Q, X, m, _, st = O.step(m, Q, X, dt, p, tessf)
+        assert st == 0
+        assert np.max(np.abs(Q.sum(axis=1) - S0) / scale) < 1e-14 * 30
+
+
+def galilean(O):
+    out = []
+    V = np.array([0.37, -0.21])
+    for boost in ((0.0, 0.0), tuple(V)):
+        P = I.kelvin_helmholtz(k=16, boost=boost)
+        m = mesh(P.px, P.py, P.box, 1)
+        Q = P.state(m.area)
+        X = np.stack([m.px, m.py])
+        p = O.Params(gamma=P.gamma, motion=1)
+        for _ in range(2):
+            Q, X, m, _, st = O.step(m, Q, X, 0.004, p, tessf)
+            assert st == 0
+        prim = O.primitives(m, Q, p)
+        out.append((prim, X))
+    (p0, X0), (p1, X1) = out
+    t = 0.008
+    assert np.max(np.abs(p1[0] - p0[0])) < 1e-11
+    assert np.max(np.abs(p1[3] - p0[3])) < 1e-10
+    assert np.max(np.abs(p1[1] - V[0] - p0[1])) < 1e-11
+    assert np.max(np.abs(p1[2] - V[1] - p0[2])) < 1e-11
+    d = (X1 - X0 - t * V[:, None] + 0.5) % 1.0 - 0.5
+    assert np.max(np.abs(d)) < 1e-13
+
+
+def mirror_symmetry(O):
+    box = (-0.5, 0.0, 0.5, 1.0)
+    hx, hy = I.uniform_points(150, seed=22, box=(-0.5, 0.0, 0.0, 1.0), sort=False)
+    px = np.concatenate([hx, -hx])
+    py = np.concatenate([hy, hy])
+    n = hx.shape[0]
+    m = mesh(px, py, box, 0)
+    r2 = m.px ** 2 + (m.py - 0.5) ** 2
+    rho = 1 + 0.5 * np.exp(-r2 / 0.02)
+    pr = 1 + np.exp(-r2 / 0.01)
+    vx = 0.3 * m.px * np.exp(-r2 / 0.05)
+    vy = 0.2 * (m.py - 0.5)
+    Q = I.conserved(rho, vx, vy, pr, m.area, 5.0 / 3.0)
+    X = np.stack([m.px, m.py])
+    p = O.Params()
+    for _ in range(4):
+        dt, _ = O.cfl_dt(m, Q, p)
+        Q, X, m, _, st = O.step(m, Q, X, dt, p, tessf)
+        assert st == 0
+    a, b = np.arange(n), np.arange(n) + n
+    sc = np.abs(Q).max(axis=1)
+    assert np.max(np.abs(Q[0, a] - Q[0, b])) < 1e-12 * sc[0]
+    assert np.max(np.abs(Q[1, a] + Q[1, b])) < 1e-12 * sc[1]
+    assert np.max(np.abs(Q[2, a] - Q[2, b])) < 1e-12 * sc[2]
+    assert np.max(np.abs(Q[3, a] - Q[3, b])) < 1e-12 * sc[3]
+    assert np.max(np.abs(X[0, a] + X[0, b])) < 1e-13
+    assert np.max(np.abs(X[1, a] - X[1, b])) < 1e-13
+
+
+def shock_detector(O):
+    # section 2.2: a cell switches to the local limiter when -div v exceeds
+    # delta_v c_s / R, or when a neighbour's pressure ratio is below delta_p.
+    k = 12
+    px, py = I.lattice(k)
+    m = mesh(px, py)
+    g = 5.0 / 3.0
+    n = m.n_cells
+    R = math.sqrt((1.0 / k) ** 2 / math.pi)
+    c = 1.0
+    thr = 0.2 * c / R                       # delta_v c / R
+    inner = np.array(sorted(set(range(n)) - wall_cells(m)))
+    one = np.ones(n)
+    pr = one * (c * c / g)                  # rho = 1 -> c = 1
+    for a, want in ((2.0 * thr, 1), (0.5 * thr, 0), (-2.0 * thr, 0)):
+        # v = -(a/2) (r - centre): div v = -a, uniform pressure
+        vx, vy = -0.5 * a * (m.px - 0.5), -0.5 * a * (m.py - 0.5)
+        prim = prim_array(one, vx, vy, pr, g)
+        G = O.gradients(m, prim)
+        _, flag = O.limiter(m, prim, G, O.Params(gamma=g))
+        assert (flag[inner] == want).all(), (a, want)
+    # pressure ratio: a jump of 0.5 flags both sides, 0.8 flags nobody
+    for ratio, want in ((0.5, 1), (0.8, 0)):
+        prj = np.where(m.px < 0.5, 1.0, ratio)
+        prim = prim_array(one, 0 * one, 0 * one, prj, g)
+        G = O.gradients(m, prim)
+        _, flag = O.limiter(m, prim, G, O.Params(gamma=g))
+        at = np.abs(m.px - 0.5) < 1.0 / k
+        assert (flag[at] == want).all() and (flag[~at] == 0).all()
+
+
+def point_velocity(O):
+    g = 5.0 / 3.0
+    px, py = I.lattice(10)
+    m = mesh(px, py)
+    s = I.Stream(3)
+    vx, vy = s.uniform(m.n_cells, -1, 1), s.uniform(m.n_cells, -1, 1)
+    prim = prim_array(np.ones(m.n_cells), vx, vy, np.ones(m.n_cells), g)
+    p = O.Params(gamma=g)
+    w = O.point_velocity(m, prim, p)
+    assert (w[0] == vx).all() and (w[1] == vy).all()
+    px, py = I.jittered_lattice(10, seed=4, jitter=0.3)
+    m = mesh(px, py)
+    prim = prim_array(np.ones(m.n_cells), vx, vy, 1.0 + s.uniform(m.n_cells), g)
+    w = O.point_velocity(m, prim, p)
+    dx, dy = m.sx - m.px, m.sy - m.py
+    d = np.hypot(dx, dy)
+    R = np.sqrt(m.area / math.pi)
+    on = d > p.eta * R
+    assert on.any() and (~on).any() or on.all()
+    ux, uy = w[0] - vx, w[1] - vy
+    assert np.allclose(np.hypot(ux, uy)[on], p.chi * prim[4][on], rtol=1e-13)
+    assert np.allclose((ux * dx + uy * dy)[on], (p.chi * prim[4] * d)[on], rtol=1e-12)
+    assert (ux[~on] == 0).all()
+    w0 = O.point_velocity(m, prim, O.Params(gamma=g, motion=0))
+    assert (w0 == 0).all()
+
+
+def cfl_uniform(O):
+    k = 10
+    px, py = I.lattice(k)
+    m = mesh(px, py)
+    g = 5.0 / 3.0
+    Q = I.conserved(1.2, 0.3, -0.1, 0.7, m.area, g)
+    c = math.sqrt(g * 0.7 / 1.2)
+    R = math.sqrt((1.0 / k) ** 2 / math.pi)
+    dt, st = O.cfl_dt(m, Q, O.Params(gamma=g))   # Lagrangian: w = v
+    assert st == 0 and abs(dt - 0.3 * R / c) < 1e-15
+    dt, st = O.cfl_dt(m, Q, O.Params(gamma=g, motion=0))
+    assert abs(dt - 0.3 * R / (c + math.hypot(0.3, -0.1))) < 1e-15
+
+
+def sod_L(O, k, limiter=0, riemann=0, steps=None, t_end=0.1):
+    P = I.sod(k=k, seed=1)
+    m = mesh(P.px, P.py, P.box, 0)
+    Q = P.state(m.area)
+    X = np.stack([m.px, m.py])
+    p = O.Params(limiter=limiter, riemann=riemann)
+    t = 0.0
+    while t < t_end - 1e-12:
+        dt, _ = O.cfl_dt(m, Q, p)
+        dt = min(dt, t_end - t)
+        Q, X, m, _, st = O.step(m, Q, X, dt, p, tessf)
+        assert st == 0
+        t += dt
+    prim = O.primitives(m, Q, p)
+    g = P.gamma
+    WL, WR = np.array([1.0, 0.0, 0.0, 1.0]), np.array([0.125, 0.0, 0.0, 0.1])
+    ex = np.array([O.exact_sample(g, WL, WR, (x - 0.5) / t)[0] for x in m.px])
+    # eq. (Lshock); velocity normalised by the sound speed
+    Lr = np.mean(np.abs(prim[0] - ex[:, 0]) ** 0.25 / np.abs(ex[:, 0]) ** 0.25)
+    Lp = np.mean(np.abs(prim[3] - ex[:, 3]) ** 0.25 / np.abs(ex[:, 3]) ** 0.25)
+    cs = np.sqrt(g * ex[:, 3] / ex[:, 0])
+    Lv = np.mean(np.abs(prim[1] - ex[:, 1]) ** 0.25 / cs ** 0.25)
+    return Lr, Lp, Lv
+
+
+def sod_accuracy(O):
+    L32 = sod_L(O, 32)
+    L64 = sod_L(O, 64)
+    L64_first = sod_L(O, 64, limiter=4)
+    for a, b, c in zip(L32, L64, L64_first):
+        assert b < a          # converges
+        assert b < c          # second order beats first order
+    assert L64[0] < 0.3 and L64[1] < 0.3
+    L64_exact = sod_L(O, 64, riemann=1)
+    assert max(abs(a - b) for a, b in zip(L64, L64_exact)) < 0.05
+
+
+ALL = [gradient_linear, gradient_periodic, tvd_example, limiter_bounds, hllc_cases,
+       hllc_weak_waves, exact_shock_tube, exact_two_shocks, area_rate_fd,
+       uniform_state_moving, uniform_flow, advection, conservation, galilean,
+       mirror_symmetry, shock_detector, point_velocity, cfl_uniform, sod_accuracy]

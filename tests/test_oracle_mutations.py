@@ -1,0 +1,111 @@
+"""Planted mistakes: each plausible error in the oracle (a flipped sign, a
+dropped term, a swapped operand) must make at least one pin fail.  The
+mistakes are planted in a temporary copy of oracle.c compiled on the CPU.
+
+Not pinned: the HLLC wave-speed estimate (the paper does not state it; the
+Davis bounds are a reading), so a change there is only caught by parity."""
+import os
+
+import pytest
+
+import oracle
+import oracle_pins as pins
+
+SRC = open(oracle.SRC_PATH).read()
+
+# (name, original text, planted text, pins expected to catch it)
+MUTATIONS = [
+    ("gradient r_ij reversed",
+     "double rx = m->px[i] - v.rx, ry = m->py[i] - v.ry;",
+     "double rx = v.rx - m->px[i], ry = v.ry - m->py[i];",
+     [pins.gradient_linear]),
+    ("gradient c_ij term dropped",
+     "g[2 * q] += v.L * (dphi * cx / r - mean * rx / r);",
+     "g[2 * q] += v.L * (0.0 * cx / r - mean * rx / r);",
+     [pins.gradient_linear]),
+    ("gradient x/y swapped in c_ij",
+     "g[2 * q + 1] += v.L * (dphi * cy / r - mean * ry / r);",
+     "g[2 * q + 1] += v.L * (dphi * cx / r - mean * ry / r);",
+     [pins.gradient_linear]),
+    ("periodic shift sign on the far side",
+     "v->rx = m->px[j] - shx;",
+     "v->rx = m->px[j] + shx;",
+     [pins.gradient_periodic, pins.uniform_flow]),
+    ("global limiter uses the minimum for increases",
+     "psi = (pmax[q] - phi_i[q]) / dphi;",
+     "psi = (pmin[q] - phi_i[q]) / dphi;",
+     [pins.tvd_example, pins.limiter_bounds]),
+    ("local limiter without theta",
+     "psi = (dphi != 0.0) ? fmax(p->theta * (phi_j[q] - phi_i[q]) / dphi, 0.0) : 1.0;",
+     "psi = (dphi != 0.0) ? fmax((phi_j[q] - phi_i[q]) / dphi, 0.0) : 1.0;",
+     [pins.tvd_example, pins.limiter_bounds]),
+    ("HLLC contact speed: pressure difference reversed",
+     "double ss = (pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur)) /",
+     "double ss = (pl - pr + rl * ul * (sl - ul) - rr * ur * (sr - ur)) /",
+     [pins.hllc_weak_waves]),
+    ("HLLC star pressure sign",
+     "double ps = pk + rho * (sk - u) * (ss - u);",
+     "double ps = pk - rho * (sk - u) * (ss - u);",
+     [pins.hllc_cases, pins.hllc_weak_waves]),
+    ("exact solver shock branch: wrong B_K",
+     "double A = 2.0 / ((g + 1.0) * rk), B = (g - 1.0) / (g + 1.0) * pk;",
+     "double A = 2.0 / ((g + 1.0) * rk), B = (g + 1.0) / (g - 1.0) * pk;",
+     [pins.exact_shock_tube, pins.exact_two_shocks]),
+    ("exact solver fan: wrong density exponent",
+     "W[0] = rl * pow(c / cl, g4);",
+     "W[0] = rl * pow(c / cl, g3);",
+     [pins.exact_shock_tube]),
+    ("edge velocity: (w_j - w_i) instead of (w_i - w_j)",
+     "double a = ((wix - wjx) * cx + (wiy - wjy) * cy) / d;",
+     "double a = ((wjx - wix) * cx + (wjy - wiy) * cy) / d;",
+     [pins.uniform_state_moving]),
+    ("momentum flux not boosted back",
+     "flux[ne + e] = fpx + F[0] * wex;",
+     "flux[ne + e] = fpx;",
+     [pins.uniform_state_moving, pins.galilean]),
+    ("energy flux misses the kinetic term of the edge motion",
+     "flux[3 * ne + e] = F[3] + fpx * wex + fpy * wey + 0.5 * (wex * wex + wey * wey) * F[0];",
+     "flux[3 * ne + e] = F[3] + fpx * wex + fpy * wey;",
+     [pins.uniform_state_moving, pins.galilean]),
+    ("update sign per side reversed",
+     "double sgn = (m->idx[k] & 1) ? -1.0 : 1.0;",
+     "double sgn = (m->idx[k] & 1) ? 1.0 : -1.0;",
+     [pins.uniform_state_moving, pins.sod_accuracy]),
+    ("wall ghost does not reverse the normal velocity",
+     "WR[0] = phiL[0]; WR[1] = -WL[1];",
+     "WR[0] = phiL[0]; WR[1] = WL[1];",
+     [pins.conservation]),
+    ("rounding correction points away from the centroid",
+     "double dx = m->sx[i] - m->px[i], dy = m->sy[i] - m->py[i];\n    double d = sqrt(dx * dx + dy * dy);\n    double R = sqrt(m->area[i] / OR_PI);\n    if (d > p->eta * R) {",
+     "double dx = m->px[i] - m->sx[i], dy = m->py[i] - m->sy[i];\n    double d = sqrt(dx * dx + dy * dy);\n    double R = sqrt(m->area[i] / OR_PI);\n    if (d > p->eta * R) {",
+     [pins.point_velocity]),
+    ("shock detector ignores compression",
+     "int shock = (-(G[2] + G[5]) > p->delta_v * ci / R);",
+     "int shock = 0;",
+     [pins.shock_detector]),
+    ("shock detector: pressure ratio test inverted",
+     "if (p->delta_p > ratio) shock = 1;",
+     "if (p->delta_p < ratio) shock = 1;",
+     [pins.shock_detector]),
+    ("primitive pressure misses the kinetic energy",
+     "double pr = (p->gamma - 1.0) * (E / A - 0.5 * rho * (vx * vx + vy * vy));",
+     "double pr = (p->gamma - 1.0) * (E / A);",
+     [pins.uniform_flow, pins.cfl_uniform]),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,old,new,catchers", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(tmp_path, name, old, new, catchers):
+    assert SRC.count(old) == 1, name
+    path = oracle.build_variant(SRC.replace(old, new), os.path.join(str(tmp_path), "liboracle_mut.so"))
+    caught = []
+    with oracle.use_library(path):
+        for pin in catchers:
+            try:
+                pin(oracle)
+            except AssertionError:
+                caught.append(pin.__name__)
+            except Exception as e:  # a crash on bad numbers also counts
+                caught.append(f"{pin.__name__}:{type(e).__name__}")
+    assert caught, f"no pin caught: {name}"
