@@ -1,0 +1,179 @@
+/*
+ * rich.h -- C-ABI of the device path (librich.so): one stage and one
+ * time-centred step of the moving-mesh Godunov scheme of RICH (Yalinewich,
+ * Steinberg & Sari) on an MI355X (gfx950), for one run or a batch of
+ * independent runs.
+ *
+ * Every step of the stage runs in HIP kernels; this header carries no HIP or
+ * torch types: device pointers are plain pointers and the stream is passed as
+ * an opaque `void*` (a hipStream_t; NULL is the null stream).  The caller owns
+ * all memory it passes in; the library never frees or keeps it.
+ *
+ * Data layout (device memory, structure of arrays, FP64 values, int32 indices)
+ * is the one the host tessellation stage produces (rich_tess.h):
+ *   cells    px, py, sx, sy, area                      [n_cells]
+ *   edges    e_i, e_j (neighbour | ghost code << 28), e_len, e_fx, e_fy
+ *                                                      [n_edges], sorted by e_i
+ *   CSR      off [n_cells+1], idx [n_csr] = 2*edge+side, eoff [n_cells+1]
+ * The state of a run is the extensive cell totals M, Px, Py, E (mass,
+ * momentum, total energy integrated over each cell) and the mesh-generating
+ * points x, y.
+ *
+ * Status codes: every function returns RICH_OK (0) or a negative code; no
+ * C++ exception crosses the ABI.  Functions named *_async only enqueue work;
+ * their domain checks are read back with rich_stage_flags.
+ */
+#ifndef RICH_H
+#define RICH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RICH_OK         0
+#define RICH_E_INVAL   -1  /* null pointer, size mismatch, h/dt <= 0 or not finite */
+#define RICH_E_NOMEM   -2  /* workspace too small, allocation failed          */
+#define RICH_E_DEVICE  -3  /* HIP runtime error                               */
+#define RICH_E_DOMAIN  -4  /* a cell got M <= 0, internal energy <= 0, a non-finite
+                              value, or the exact solver met a vacuum          */
+#define RICH_E_MESH    -5  /* invalid mesh or tessellation failure             */
+
+/* Per-run flag bits reported by rich_stage_flags. */
+#define RICH_FLAG_DOMAIN 1  /* a produced cell failed the physical checks */
+#define RICH_FLAG_VACUUM 2  /* exact Riemann solver: states create a vacuum */
+
+/* Boundary kinds (same values as rich_tess.h). */
+#define RICH_BOUNDARY_WALLS    0u
+#define RICH_BOUNDARY_PERIODIC 1u
+
+/* Mesh of one run (device pointers, borrowed). */
+typedef struct rich_mesh {
+  int64_t n_cells, n_edges, n_csr;
+  const double *px, *py, *sx, *sy, *area;
+  const int32_t *e_i, *e_j;
+  const double *e_len, *e_fx, *e_fy;
+  const int32_t *off, *idx, *eoff;
+  double box[4];  /* x0, y0, x1, y1 */
+  uint32_t bc;    /* RICH_BOUNDARY_* */
+} rich_mesh;
+
+/* State of one run (device pointers, borrowed). */
+typedef struct rich_state {
+  double *M, *Px, *Py, *E;  /* extensive totals per cell */
+  double *x, *y;            /* mesh-generating points    */
+  int64_t n_cells;
+} rich_state;
+
+/* Scheme parameters.  Paper defaults: theta 0.5, delta_v 0.2, delta_p 0.7
+ * (section 2.2), Courant number 0.3 (section 2.3), chi 0.15, eta 0.02
+ * (section 6). */
+typedef struct rich_params {
+  double gamma;    /* adiabatic index of the ideal gas                     */
+  double cfl;      /* Courant number                                       */
+  double theta;    /* local (TESS) limiter factor                          */
+  double delta_v;  /* shock detector: compression threshold                */
+  double delta_p;  /* shock detector: pressure-ratio threshold             */
+  double chi;      /* cell rounding: correction speed in units of c_s      */
+  double eta;      /* cell rounding: offset threshold in units of the cell radius */
+  int32_t riemann; /* 0 HLLC (section 2.4), 1 exact                        */
+  int32_t motion;  /* 0 static mesh, 1 Lagrangian with cell rounding (section 6) */
+  int32_t limiter; /* 0 global/local switch on the shock detector (section 2.2),
+                      1 global only, 2 local only, 3 unlimited, 4 first order */
+} rich_params;
+
+/* Fill p with the paper's defaults for adiabatic index gamma. */
+void rich_params_default(rich_params* p, double gamma);
+
+/* Workspace bytes one stage of a run with n_cells cells needs (scratch for
+ * the per-cell reconstruction records, the Courant minimum and the flag word).
+ * The workspace is caller-allocated device memory, 256-byte aligned. */
+int rich_workspace_size(int64_t n_cells, size_t* bytes);
+
+/*
+ * One stage (section 2.3): on mesh m, with primitives taken from src,
+ *   out.{M,Px,Py,E}_i = base.{M,Px,Py,E}_i - h * sum over the cell's edges of
+ *                       (+/-) L_e F_e
+ *   out.{x,y}_i       = base.{x,y}_i + h * w_i   (wrapped into a periodic box)
+ * where F_e is the flux through the moving edge (sections 2.2-2.4, 5, 6).
+ * src and base are never written; out may alias neither.  Enqueued on
+ * `stream`; returns RICH_E_INVAL for bad arguments without enqueuing.
+ * The domain checks of the produced state are reported by rich_stage_flags.
+ */
+int rich_stage(const rich_mesh* m, const rich_state* src, const rich_state* base,
+               rich_state* out, double h, const rich_params* p, void* ws,
+               size_t ws_bytes, void* stream);
+
+/* Synchronise `stream` and return the flag word of the last stage that used
+ * workspace ws (RICH_FLAG_* bits; 0 when all produced cells are valid). */
+int rich_stage_flags(void* ws, void* stream, int32_t* flags);
+
+/*
+ * Courant time step (section 2.3): dt = cfl * min_i R_i / (c_i + |v_i - w_i|),
+ * R_i = sqrt(A_i / pi).  Synchronises `stream` and writes the host double *dt.
+ */
+int rich_cfl_dt(const rich_mesh* m, const rich_state* s, const rich_params* p,
+                double* dt, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Batched stage over n independent runs of any sizes, in one launch per
+ * kernel phase: meshes[r], src[r], base[r], out[r], h[r], params[r] as for
+ * rich_stage (host arrays of pointers to host structs holding device
+ * pointers).  ws is one device workspace of rich_batch_workspace_size bytes.
+ * The per-run results are bitwise identical to n separate rich_stage calls.
+ */
+int rich_batch_workspace_size(int32_t n, const int64_t* n_cells, size_t* bytes);
+int rich_stage_batch(int32_t n, const rich_mesh* const* meshes,
+                     const rich_state* const* src, const rich_state* const* base,
+                     rich_state* const* out, const double* h,
+                     const rich_params* const* params, void* ws, size_t ws_bytes,
+                     void* stream);
+/* Synchronise and read the n per-run flag words of the last batched stage. */
+int rich_batch_flags(int32_t n, void* ws, void* stream, int32_t* flags);
+
+/*
+ * Time-centred step (section 2.3) of one run with a moving mesh:
+ *   1. stage(mesh_n, Q^n, Q^n, x^n, dt/2)        -> Q^{n+1/2}, x^{n+1/2}
+ *   2. tessellate x^{n+1/2}                       -> mesh_{n+1/2}
+ *   3. stage(mesh_{n+1/2}, Q^{n+1/2}, Q^n, x^n, dt) -> Q^{n+1}, x^{n+1}
+ *   4. tessellate x^{n+1}                         -> mesh_{n+1}
+ * The tessellation is the caller's host function `tess` (the host input
+ * stage); it receives host point arrays and must fill *out with host mesh
+ * arrays that stay valid until `release` is called on it.  The library
+ * uploads them into its own device buffers (owned by ctx).  With a static
+ * mesh (params->motion == 0) no tessellation happens.
+ * The state is committed only on success; on RICH_E_DOMAIN it is unchanged.
+ */
+typedef struct rich_host_mesh_view {
+  int64_t n_cells, n_edges, n_csr;
+  const double *px, *py, *sx, *sy, *area;
+  const int32_t *e_i, *e_j;
+  const double *e_len, *e_fx, *e_fy;
+  const int32_t *off, *idx, *eoff;
+} rich_host_mesh_view;
+typedef int (*rich_tess_fn)(void* user, const double* px, const double* py,
+                            int64_t n, const double box[4], uint32_t bc,
+                            rich_host_mesh_view* out);
+typedef void (*rich_tess_release_fn)(void* user, rich_host_mesh_view* m);
+
+typedef struct rich_ctx rich_ctx;  /* device buffers of one run's step driver */
+int rich_ctx_create(rich_ctx** ctx);
+void rich_ctx_destroy(rich_ctx* ctx);
+/* Upload a host mesh as the run's current mesh. */
+int rich_ctx_set_mesh(rich_ctx* ctx, const rich_host_mesh_view* hm,
+                      const double box[4], uint32_t bc, void* stream);
+/* Device view of the run's current mesh. */
+int rich_ctx_mesh(rich_ctx* ctx, rich_mesh* out);
+int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
+              rich_tess_fn tess, rich_tess_release_fn release, void* tess_user,
+              void* stream);
+
+/* Human-readable name of a status code. */
+const char* rich_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RICH_H */

@@ -1,0 +1,500 @@
+// Device-side building blocks of one stage of RICH's moving-mesh Godunov
+// scheme (Yalinewich, Steinberg & Sari) for gfx950: primitive recovery, point
+// velocity (section 6), Green-Gauss gradient (section 2.2, eq. slope), the
+// global/local limiter switch (section 2.2), extrapolation to the edge centre
+// (section 2.2), the HLLC and exact Riemann solvers (section 2.4) in the frame
+// of the moving edge (section 1, section 5), and the lab-frame flux.
+//
+// Arithmetic is FP64 throughout; divisions and square roots are the
+// correctly rounded IEEE operations (no fast-math).  Floating-point
+// contraction is per source expression (-ffp-contract=on), so every call of
+// these functions on the same inputs produces the same bits, wherever it is
+// inlined: a cell or an edge computed by two different tiles agrees bitwise.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rich {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr uint32_t kCellMask = 0x0FFFFFFFu;
+constexpr int kRecDoubles = 16;  // reconstruction record: 128 bytes per cell
+
+// Everything one stage of one run needs (device pointers).  Passed by value
+// as a kernel argument for a single run, stored in device memory for a batch.
+struct RunDesc {
+  // mesh
+  const double *px, *py, *sx, *sy, *area;
+  const int32_t *e_i, *e_j;
+  const double *e_len, *e_fx, *e_fy;
+  const int32_t *off, *idx, *eoff;
+  // state
+  const double *sM, *sPx, *sPy, *sE;              // primitives come from here
+  const double *bM, *bPx, *bPy, *bE, *bx, *by;    // base of the update
+  double *oM, *oPx, *oPy, *oE, *ox, *oy;          // result
+  // workspace of this run
+  double* rec;       // [n][16] records
+  int32_t* flag;     // status word
+  unsigned long long* cfl_min;  // bit pattern of the smallest R/(c+|v-w|)
+  // geometry and parameters
+  double x0, y0, x1, y1, Lx, Ly;
+  double h, gamma, theta, delta_v, delta_p, chi, eta;
+  int32_t n, n_edges, n_csr, bc;
+  int32_t riemann, motion, limiter, pad;
+};
+
+// Record layout (doubles): 0..3 rho, vx, vy, p; 4..11 limited gradients
+// (d/dx, d/dy of rho, vx, vy, p); 12..13 point velocity; 14..15 centroid.
+enum { R_RHO = 0, R_VX, R_VY, R_P, R_G = 4, R_WX = 12, R_WY, R_SX, R_SY };
+
+// ---------------------------------------------------------------------------
+// mesh access
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void shift_of(const RunDesc& d, int code, double& shx,
+                                         double& shy) {
+  shx = 0.0;
+  shy = 0.0;
+  if (code >= 1 && code <= 8) {
+    int k = code <= 4 ? code - 1 : code;
+    shx = (double)(k / 3 - 1) * d.Lx;
+    shy = (double)(k % 3 - 1) * d.Ly;
+  }
+}
+
+__device__ __forceinline__ void mirror_point(const RunDesc& d, int code, double x,
+                                             double y, double& mx, double& my) {
+  mx = x;
+  my = y;
+  if (code == 9) mx = 2.0 * d.x0 - x;
+  if (code == 10) mx = 2.0 * d.x1 - x;
+  if (code == 11) my = 2.0 * d.y0 - y;
+  if (code == 12) my = 2.0 * d.y1 - y;
+}
+
+__device__ __forceinline__ void mirror_vec(int code, double vx, double vy, double& mx,
+                                           double& my) {
+  mx = (code == 9 || code == 10) ? -vx : vx;
+  my = (code == 11 || code == 12) ? -vy : vy;
+}
+
+// The neighbour across one CSR entry of cell i, in i's frame.  Indices read
+// from the mesh are range-checked; a bad index sets *bad and points at i.
+struct Nb {
+  int j, wall;
+  double rx, ry, fx, fy, L;
+};
+
+__device__ __forceinline__ Nb nb_view(const RunDesc& d, int i, double rix, double riy,
+                                      int entry, bool& bad) {
+  Nb v;
+  int e = entry >> 1;
+  int side = entry & 1;
+  if (e < 0 || e >= d.n_edges) {
+    bad = true;
+    e = 0;
+  }
+  uint32_t ej = (uint32_t)d.e_j[e];
+  int code = (int)(ej >> 28);
+  v.L = d.e_len[e];
+  v.fx = d.e_fx[e];
+  v.fy = d.e_fy[e];
+  double shx, shy;
+  shift_of(d, code, shx, shy);
+  v.wall = 0;
+  if (side == 0) {
+    if (code >= 9) {
+      v.wall = code;
+      v.j = i;
+      mirror_point(d, code, rix, riy, v.rx, v.ry);
+      return v;
+    }
+    v.j = (int)(ej & kCellMask);
+  } else {
+    v.j = d.e_i[e];
+    shx = -shx;
+    shy = -shy;
+    v.fx += shx;
+    v.fy += shy;
+  }
+  if (v.j < 0 || v.j >= d.n) {
+    bad = true;
+    v.j = i;
+  }
+  v.rx = d.px[v.j] + shx;
+  v.ry = d.py[v.j] + shy;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// A1: primitives of cell j from the extensive totals (ideal gas)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void prim_of(const RunDesc& d, int j, double& rho, double& vx,
+                                        double& vy, double& p) {
+  double A = d.area[j], M = d.sM[j];
+  rho = M / A;
+  vx = d.sPx[j] / M;
+  vy = d.sPy[j] / M;
+  p = (d.gamma - 1.0) * (d.sE[j] / A - 0.5 * rho * (vx * vx + vy * vy));
+}
+
+// ---------------------------------------------------------------------------
+// A1-A4 for one cell: primitives, point velocity, gradient, limiter.
+// Writes the record (16 doubles).  Returns false on a bad mesh index.
+// ---------------------------------------------------------------------------
+__device__ inline bool cell_record(const RunDesc& d, int i, double* rec) {
+  bool bad = false;
+  double rho, vx, vy, p;
+  prim_of(d, i, rho, vx, vy, p);
+  const double c = sqrt(d.gamma * p / rho);
+  const double rix = d.px[i], riy = d.py[i];
+  const double six = d.sx[i], siy = d.sy[i];
+  const double A = d.area[i];
+  const double R = sqrt(A / kPi);
+
+  // A2 (section 6): Lagrangian motion plus the cell-rounding correction
+  double wx = 0.0, wy = 0.0;
+  if (d.motion) {
+    wx = vx;
+    wy = vy;
+    double dx = six - rix, dy = siy - riy;
+    double dd = sqrt(dx * dx + dy * dy);
+    if (dd > d.eta * R) {
+      wx += d.chi * c * dx / dd;
+      wy += d.chi * c * dy / dd;
+    }
+  }
+
+  // A3 (eq. slope) with r_ij = r_i - r_j; bounds and pressure ratios for A4
+  const double phi[4] = {rho, vx, vy, p};
+  double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double pmax[4] = {rho, vx, vy, p}, pmin[4] = {rho, vx, vy, p};
+  bool shock = false;
+  const int k0 = d.off[i], k1 = d.off[i + 1];
+  if (k0 < 0 || k1 < k0 || k1 > d.n_csr) return false;
+  for (int k = k0; k < k1; ++k) {
+    Nb v = nb_view(d, i, rix, riy, d.idx[k], bad);
+    double pj[4];
+    if (v.wall) {
+      pj[0] = rho;
+      mirror_vec(v.wall, vx, vy, pj[1], pj[2]);
+      pj[3] = p;
+    } else {
+      prim_of(d, v.j, pj[0], pj[1], pj[2], pj[3]);
+    }
+    const double rx = rix - v.rx, ry = riy - v.ry;
+    const double inv_r = 1.0 / sqrt(rx * rx + ry * ry);
+    const double cx = v.fx - 0.5 * (rix + v.rx), cy = v.fy - 0.5 * (riy + v.ry);
+    const double ux = cx * inv_r, uy = cy * inv_r, nx = rx * inv_r, ny = ry * inv_r;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double dphi = pj[q] - phi[q];
+      const double mean = 0.5 * (phi[q] + pj[q]);
+      g[2 * q] += v.L * (dphi * ux - mean * nx);
+      g[2 * q + 1] += v.L * (dphi * uy - mean * ny);
+      pmax[q] = fmax(pmax[q], pj[q]);
+      pmin[q] = fmin(pmin[q], pj[q]);
+    }
+    double ratio = 1.0;
+    if (pj[3] > p) ratio = p / pj[3];
+    if (p > pj[3]) ratio = pj[3] / p;
+    if (d.delta_p > ratio) shock = true;
+  }
+  double G[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) G[q] = g[q] / A;
+  if (-(G[2] + G[5]) > d.delta_v * c / R) shock = true;
+
+  // A4 (section 2.2): alpha per variable
+  double alpha[4] = {1.0, 1.0, 1.0, 1.0};
+  int local = -1;
+  if (d.limiter == 0) local = shock ? 1 : 0;
+  if (d.limiter == 1) local = 0;
+  if (d.limiter == 2) local = 1;
+  if (d.limiter == 4) alpha[0] = alpha[1] = alpha[2] = alpha[3] = 0.0;
+  if (local == 0) {
+    // global limiter: min_j psi_ij is attained at the largest positive and
+    // the most negative change (division is monotone in the denominator)
+    double dmax[4] = {0, 0, 0, 0}, dmin[4] = {0, 0, 0, 0};
+    for (int k = k0; k < k1; ++k) {
+      Nb v = nb_view(d, i, rix, riy, d.idx[k], bad);
+      const double dx = v.fx - six, dy = v.fy - siy;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double dphi = G[2 * q] * dx + G[2 * q + 1] * dy;
+        dmax[q] = fmax(dmax[q], dphi);
+        dmin[q] = fmin(dmin[q], dphi);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (dmax[q] > 0.0) alpha[q] = fmin(alpha[q], (pmax[q] - phi[q]) / dmax[q]);
+      if (dmin[q] < 0.0) alpha[q] = fmin(alpha[q], (pmin[q] - phi[q]) / dmin[q]);
+    }
+  } else if (local == 1) {
+    for (int k = k0; k < k1; ++k) {
+      Nb v = nb_view(d, i, rix, riy, d.idx[k], bad);
+      double pj[4];
+      if (v.wall) {
+        pj[0] = rho;
+        mirror_vec(v.wall, vx, vy, pj[1], pj[2]);
+        pj[3] = p;
+      } else {
+        prim_of(d, v.j, pj[0], pj[1], pj[2], pj[3]);
+      }
+      const double dx = v.fx - six, dy = v.fy - siy;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double dphi = G[2 * q] * dx + G[2 * q + 1] * dy;
+        const double psi = (dphi != 0.0) ? fmax(d.theta * (pj[q] - phi[q]) / dphi, 0.0) : 1.0;
+        alpha[q] = fmin(alpha[q], psi);
+      }
+    }
+  }
+  rec[R_RHO] = rho;
+  rec[R_VX] = vx;
+  rec[R_VY] = vy;
+  rec[R_P] = p;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) rec[R_G + q] = G[q] * alpha[q / 2];
+  rec[R_WX] = wx;
+  rec[R_WY] = wy;
+  rec[R_SX] = six;
+  rec[R_SY] = siy;
+  return !bad;
+}
+
+// ---------------------------------------------------------------------------
+// Riemann solvers in the edge frame (section 2.4).  W = (rho, u, vt, p).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void phys_flux(double g, const double* W, double* F) {
+  const double rho = W[0], u = W[1], vt = W[2], pr = W[3];
+  const double E = pr / (g - 1.0) + 0.5 * rho * (u * u + vt * vt);
+  F[0] = rho * u;
+  F[1] = rho * u * u + pr;
+  F[2] = rho * u * vt;
+  F[3] = u * (E + pr);
+}
+
+// HLLC with Davis wave-speed bounds; star fluxes are the physical fluxes of
+// the star states (identical to the Rankine-Hugoniot form).
+__device__ inline void hllc(double g, const double* WL, const double* WR, double* F) {
+  const double rl = WL[0], ul = WL[1], pl = WL[3];
+  const double rr = WR[0], ur = WR[1], pr = WR[3];
+  const double cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
+  const double sl = fmin(ul - cl, ur - cr);
+  const double sr = fmax(ul + cl, ur + cr);
+  const double ss = (pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur)) /
+                    (rl * (sl - ul) - rr * (sr - ur));
+  if (0.0 <= sl) {
+    phys_flux(g, WL, F);
+    return;
+  }
+  if (!(0.0 <= ss) && !(0.0 < sr)) {
+    phys_flux(g, WR, F);
+    return;
+  }
+  const bool left = (0.0 <= ss);
+  const double* W = left ? WL : WR;
+  const double sk = left ? sl : sr;
+  const double rho = W[0], u = W[1], vt = W[2], pk = W[3];
+  const double E = pk / (g - 1.0) + 0.5 * rho * (u * u + vt * vt);
+  const double rs = rho * (sk - u) / (sk - ss);
+  const double ps = pk + rho * (sk - u) * (ss - u);
+  const double Es = rs * (E / rho + (ss - u) * (ss + pk / (rho * (sk - u))));
+  F[0] = rs * ss;
+  F[1] = rs * ss * ss + ps;
+  F[2] = rs * ss * vt;
+  F[3] = (Es + ps) * ss;
+}
+
+// Exact solver: star pressure by Newton iteration on
+// f_L(p) + f_R(p) + u_R - u_L = 0 (shock branch for p > p_K, rarefaction
+// branch otherwise), primitive-variable initial guess clipped at 1e-14,
+// relative change 1e-14 or 50 iterations; the solution sampled at x/t = 0.
+__device__ __forceinline__ void pfun(double g, double ps, double rk, double pk, double ck,
+                                     double& f, double& fd) {
+  if (ps > pk) {
+    const double A = 2.0 / ((g + 1.0) * rk), B = (g - 1.0) / (g + 1.0) * pk;
+    const double q = sqrt(A / (ps + B));
+    f = (ps - pk) * q;
+    fd = q * (1.0 - 0.5 * (ps - pk) / (B + ps));
+  } else {
+    const double pr = ps / pk;
+    f = 2.0 * ck / (g - 1.0) * (pow(pr, (g - 1.0) / (2.0 * g)) - 1.0);
+    fd = 1.0 / (rk * ck) * pow(pr, -(g + 1.0) / (2.0 * g));
+  }
+}
+
+__device__ inline bool exact_flux(double g, const double* WL, const double* WR, double* F) {
+  const double rl = WL[0], ul = WL[1], pl = WL[3];
+  const double rr = WR[0], ur = WR[1], pr = WR[3];
+  const double cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
+  if (2.0 / (g - 1.0) * (cl + cr) <= ur - ul) {
+    F[0] = F[1] = F[2] = F[3] = 0.0;
+    return false;
+  }
+  const double tiny = 1e-14;
+  double ps = 0.5 * (pl + pr) - 0.125 * (ur - ul) * (rl + rr) * (cl + cr);
+  if (ps < tiny) ps = tiny;
+  for (int it = 1; it <= 50; ++it) {
+    double fl, fld, fr, frd;
+    pfun(g, ps, rl, pl, cl, fl, fld);
+    pfun(g, ps, rr, pr, cr, fr, frd);
+    double pn = ps - (fl + fr + ur - ul) / (fld + frd);
+    if (pn < tiny) pn = tiny;
+    const double change = 2.0 * fabs(pn - ps) / (pn + ps);
+    ps = pn;
+    if (change < 1e-14) break;
+  }
+  double fl, fld, fr, frd;
+  pfun(g, ps, rl, pl, cl, fl, fld);
+  pfun(g, ps, rr, pr, cr, fr, frd);
+  const double us = 0.5 * (ul + ur) + 0.5 * (fr - fl);
+  // sample at x/t = 0
+  const double g1 = (g - 1.0) / (2.0 * g), g2 = (g + 1.0) / (2.0 * g);
+  const double g3 = 2.0 * g / (g - 1.0), g4 = 2.0 / (g - 1.0), g5 = 2.0 / (g + 1.0);
+  const double g6 = (g - 1.0) / (g + 1.0), g7 = (g - 1.0) / 2.0;
+  double W[4];
+  if (0.0 <= us) {
+    W[2] = WL[2];
+    if (ps > pl) {
+      const double s = ul - cl * sqrt(g2 * ps / pl + g1);
+      if (0.0 <= s) {
+        W[0] = rl; W[1] = ul; W[3] = pl;
+      } else {
+        W[0] = rl * (ps / pl + g6) / (g6 * ps / pl + 1.0); W[1] = us; W[3] = ps;
+      }
+    } else if (0.0 <= ul - cl) {
+      W[0] = rl; W[1] = ul; W[3] = pl;
+    } else {
+      const double cml = cl * pow(ps / pl, g1);
+      if (0.0 > us - cml) {
+        W[0] = rl * pow(ps / pl, 1.0 / g); W[1] = us; W[3] = ps;
+      } else {
+        const double cc = g5 * (cl + g7 * ul);
+        W[0] = rl * pow(cc / cl, g4);
+        W[1] = g5 * (cl + g7 * ul);
+        W[3] = pl * pow(cc / cl, g3);
+      }
+    }
+  } else {
+    W[2] = WR[2];
+    if (ps > pr) {
+      const double s = ur + cr * sqrt(g2 * ps / pr + g1);
+      if (0.0 >= s) {
+        W[0] = rr; W[1] = ur; W[3] = pr;
+      } else {
+        W[0] = rr * (ps / pr + g6) / (g6 * ps / pr + 1.0); W[1] = us; W[3] = ps;
+      }
+    } else if (0.0 >= ur + cr) {
+      W[0] = rr; W[1] = ur; W[3] = pr;
+    } else {
+      const double cmr = cr * pow(ps / pr, g1);
+      if (0.0 <= us + cmr) {
+        W[0] = rr * pow(ps / pr, 1.0 / g); W[1] = us; W[3] = ps;
+      } else {
+        const double cc = g5 * (cr - g7 * ur);
+        W[0] = rr * pow(cc / cr, g4);
+        W[1] = g5 * (-cr + g7 * ur);
+        W[3] = pr * pow(cc / cr, g3);
+      }
+    }
+  }
+  phys_flux(g, W, F);
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// A5-A7 for one edge: extrapolation, frame of the moving edge, Riemann solve,
+// lab-frame flux times the edge length.  Returns false on a bad index or a
+// vacuum in the exact solver.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void load_rec(const double* __restrict__ rec, int c, double* r) {
+  const double2* p = reinterpret_cast<const double2*>(rec + (size_t)c * kRecDoubles);
+#pragma unroll
+  for (int k = 0; k < kRecDoubles / 2; ++k) {
+    double2 v = p[k];
+    r[2 * k] = v.x;
+    r[2 * k + 1] = v.y;
+  }
+}
+
+template <int RIEMANN>
+__device__ inline bool edge_flux(const RunDesc& d, int e, const double* ri, const double* rj_in,
+                                 double* LF) {
+  bool ok = true;
+  const int i = d.e_i[e];
+  const uint32_t ej = (uint32_t)d.e_j[e];
+  const int code = (int)(ej >> 28);
+  const double fx = d.e_fx[e], fy = d.e_fy[e], L = d.e_len[e];
+  const double rix = d.px[i], riy = d.py[i];
+  double phL[4], phR[4];
+  {
+    const double dx = fx - ri[R_SX], dy = fy - ri[R_SY];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) phL[q] = ri[q] + ri[R_G + 2 * q] * dx + ri[R_G + 2 * q + 1] * dy;
+  }
+  double nx, ny, wex, wey;
+  double WL[4], WR[4];
+  if (code >= 9) {
+    nx = (code == 9) ? -1.0 : (code == 10 ? 1.0 : 0.0);
+    ny = (code == 11) ? -1.0 : (code == 12 ? 1.0 : 0.0);
+    const double tx = -ny, ty = nx;
+    const double wn = ri[R_WX] * nx + ri[R_WY] * ny;
+    wex = ri[R_WX] - wn * nx;
+    wey = ri[R_WY] - wn * ny;
+    const double vx = phL[1] - wex, vy = phL[2] - wey;
+    WL[0] = phL[0]; WL[1] = vx * nx + vy * ny; WL[2] = vx * tx + vy * ty; WL[3] = phL[3];
+    WR[0] = phL[0]; WR[1] = -WL[1]; WR[2] = WL[2]; WR[3] = phL[3];
+  } else {
+    int j = (int)(ej & kCellMask);
+    if (j >= d.n) {
+      ok = false;
+      j = i;
+    }
+    const double* rj = rj_in;
+    double shx, shy;
+    shift_of(d, code, shx, shy);
+    const double rjx = d.px[j] + shx, rjy = d.py[j] + shy;
+    const double sjx = rj[R_SX] + shx, sjy = rj[R_SY] + shy;
+    {
+      const double dx = fx - sjx, dy = fy - sjy;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) phR[q] = rj[q] + rj[R_G + 2 * q] * dx + rj[R_G + 2 * q + 1] * dy;
+    }
+    const double dx = rjx - rix, dy = rjy - riy;
+    const double dist = sqrt(dx * dx + dy * dy);
+    nx = dx / dist;
+    ny = dy / dist;
+    const double tx = -ny, ty = nx;
+    const double cx = fx - 0.5 * (rix + rjx), cy = fy - 0.5 * (riy + rjy);
+    const double wix = ri[R_WX], wiy = ri[R_WY], wjx = rj[R_WX], wjy = rj[R_WY];
+    const double a = ((wix - wjx) * cx + (wiy - wjy) * cy) / dist;
+    wex = 0.5 * (wix + wjx) + a * nx;
+    wey = 0.5 * (wiy + wjy) + a * ny;
+    const double vlx = phL[1] - wex, vly = phL[2] - wey;
+    const double vrx = phR[1] - wex, vry = phR[2] - wey;
+    WL[0] = phL[0]; WL[1] = vlx * nx + vly * ny; WL[2] = vlx * tx + vly * ty; WL[3] = phL[3];
+    WR[0] = phR[0]; WR[1] = vrx * nx + vry * ny; WR[2] = vrx * tx + vry * ty; WR[3] = phR[3];
+  }
+  double F[4];
+  if (RIEMANN == 1) {
+    if (!exact_flux(d.gamma, WL, WR, F)) ok = false;
+  } else {
+    hllc(d.gamma, WL, WR, F);
+  }
+  const double tx = -ny, ty = nx;
+  const double fpx = F[1] * nx + F[2] * tx, fpy = F[1] * ny + F[2] * ty;
+  const double fm = F[0];
+  const double fmx = fpx + fm * wex;
+  const double fmy = fpy + fm * wey;
+  const double fe = F[3] + fpx * wex + fpy * wey + 0.5 * (wex * wex + wey * wey) * fm;
+  LF[0] = L * fm;
+  LF[1] = L * fmx;
+  LF[2] = L * fmy;
+  LF[3] = L * fe;
+  return ok;
+}
+
+}  // namespace rich

@@ -1,0 +1,251 @@
+"""ctypes binding of the device path (librich.so, rich.h).
+
+Argument marshalling only: every step of the stage runs in the library's HIP
+kernels.  PyTorch provides device memory and the stream.  Importing this
+module does not need a GPU; calling into the library does, and a missing
+library raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librich.so")
+
+RICH_OK, RICH_E_INVAL, RICH_E_NOMEM, RICH_E_DEVICE, RICH_E_DOMAIN, RICH_E_MESH = 0, -1, -2, -3, -4, -5
+FLAG_DOMAIN, FLAG_VACUUM = 1, 2
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_vp = C.c_void_p
+
+
+class RichMesh(C.Structure):
+    _fields_ = [
+        ("n_cells", C.c_int64), ("n_edges", C.c_int64), ("n_csr", C.c_int64),
+        ("px", _vp), ("py", _vp), ("sx", _vp), ("sy", _vp), ("area", _vp),
+        ("e_i", _vp), ("e_j", _vp), ("e_len", _vp), ("e_fx", _vp), ("e_fy", _vp),
+        ("off", _vp), ("idx", _vp), ("eoff", _vp),
+        ("box", C.c_double * 4), ("bc", C.c_uint32),
+    ]
+
+
+class RichState(C.Structure):
+    _fields_ = [("M", _vp), ("Px", _vp), ("Py", _vp), ("E", _vp), ("x", _vp), ("y", _vp),
+                ("n_cells", C.c_int64)]
+
+
+class RichParams(C.Structure):
+    _fields_ = [
+        ("gamma", C.c_double), ("cfl", C.c_double), ("theta", C.c_double),
+        ("delta_v", C.c_double), ("delta_p", C.c_double), ("chi", C.c_double),
+        ("eta", C.c_double), ("riemann", C.c_int32), ("motion", C.c_int32),
+        ("limiter", C.c_int32),
+    ]
+
+
+class HostMeshView(C.Structure):
+    _fields_ = [
+        ("n_cells", C.c_int64), ("n_edges", C.c_int64), ("n_csr", C.c_int64),
+        ("px", _dp), ("py", _dp), ("sx", _dp), ("sy", _dp), ("area", _dp),
+        ("e_i", _ip), ("e_j", _ip), ("e_len", _dp), ("e_fx", _dp), ("e_fy", _dp),
+        ("off", _ip), ("idx", _ip), ("eoff", _ip),
+    ]
+
+
+TESS_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, _dp, _dp, C.c_int64, _dp, C.c_uint32,
+                      C.POINTER(HostMeshView))
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(HostMeshView))
+
+
+@dataclass
+class Params:
+    """Scheme parameters (rich_params); defaults are the paper's."""
+    gamma: float = 5.0 / 3.0
+    cfl: float = 0.3
+    theta: float = 0.5
+    delta_v: float = 0.2
+    delta_p: float = 0.7
+    chi: float = 0.15
+    eta: float = 0.02
+    riemann: int = 0
+    motion: int = 1
+    limiter: int = 0
+
+    def c(self):
+        return RichParams(self.gamma, self.cfl, self.theta, self.delta_v, self.delta_p,
+                          self.chi, self.eta, self.riemann, self.motion, self.limiter)
+
+
+class RichError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        mp, sp, pp = C.POINTER(RichMesh), C.POINTER(RichState), C.POINTER(RichParams)
+        L.rich_params_default.argtypes = [pp, C.c_double]
+        L.rich_params_default.restype = None
+        L.rich_workspace_size.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
+        L.rich_stage.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, C.c_size_t, _vp]
+        L.rich_stage_flags.argtypes = [_vp, _vp, _ip]
+        L.rich_cfl_dt.argtypes = [mp, sp, pp, _dp, _vp, C.c_size_t, _vp]
+        L.rich_strerror.argtypes = [C.c_int]
+        L.rich_strerror.restype = C.c_char_p
+        for f in ("rich_workspace_size", "rich_stage", "rich_stage_flags", "rich_cfl_dt"):
+            getattr(L, f).restype = C.c_int
+        if hasattr(L, "rich_stage_batch"):
+            L.rich_batch_workspace_size.argtypes = [C.c_int32, C.POINTER(C.c_int64),
+                                                    C.POINTER(C.c_size_t)]
+            L.rich_stage_batch.argtypes = [C.c_int32, C.POINTER(mp), C.POINTER(sp),
+                                           C.POINTER(sp), C.POINTER(sp), _dp, C.POINTER(pp),
+                                           _vp, C.c_size_t, _vp]
+            L.rich_batch_flags.argtypes = [C.c_int32, _vp, _vp, _ip]
+            for f in ("rich_batch_workspace_size", "rich_stage_batch", "rich_batch_flags"):
+                getattr(L, f).restype = C.c_int
+        if hasattr(L, "rich_step"):
+            L.rich_ctx_create.argtypes = [C.POINTER(_vp)]
+            L.rich_ctx_destroy.argtypes = [_vp]
+            L.rich_ctx_destroy.restype = None
+            L.rich_ctx_set_mesh.argtypes = [_vp, C.POINTER(HostMeshView), _dp, C.c_uint32, _vp]
+            L.rich_ctx_mesh.argtypes = [_vp, mp]
+            L.rich_step.argtypes = [_vp, sp, C.c_double, pp, TESS_FN, RELEASE_FN, _vp, _vp]
+            for f in ("rich_ctx_create", "rich_ctx_set_mesh", "rich_ctx_mesh", "rich_step"):
+                getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def strerror(status):
+    try:
+        return lib().rich_strerror(int(status)).decode()
+    except Exception:
+        return "unknown"
+
+
+def _check(st, what):
+    if st != RICH_OK:
+        raise RichError(st, what)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# device-resident mesh and state (torch tensors)
+# ---------------------------------------------------------------------------
+@dataclass
+class DeviceMesh:
+    t: dict
+    n_cells: int
+    n_edges: int
+    n_csr: int
+    box: tuple
+    bc: int
+    _c: RichMesh = field(default=None, repr=False)
+
+    @classmethod
+    def from_host(cls, hm, device="cuda"):
+        import torch
+        t = {}
+        for k in hm.ARRAYS:
+            a = getattr(hm, k)
+            t[k] = torch.from_numpy(np.ascontiguousarray(a)).to(device, non_blocking=False)
+        return cls(t, hm.n_cells, hm.n_edges, hm.n_csr, tuple(hm.box), int(hm.bc))
+
+    def c(self):
+        if self._c is None:
+            p = {k: C.c_void_p(v.data_ptr()) for k, v in self.t.items()}
+            self._c = RichMesh(self.n_cells, self.n_edges, self.n_csr,
+                               p["px"], p["py"], p["sx"], p["sy"], p["area"],
+                               p["e_i"], p["e_j"], p["e_len"], p["e_fx"], p["e_fy"],
+                               p["off"], p["idx"], p["eoff"],
+                               (C.c_double * 4)(*self.box), self.bc)
+        return self._c
+
+    def nbytes(self):
+        return sum(v.numel() * v.element_size() for v in self.t.values())
+
+
+@dataclass
+class DeviceState:
+    """Q (4, n): M, Px, Py, E extensive totals; X (2, n): points."""
+    Q: "torch.Tensor"
+    X: "torch.Tensor"
+
+    @classmethod
+    def from_host(cls, Q, X, device="cuda"):
+        import torch
+        return cls(torch.from_numpy(np.ascontiguousarray(Q, dtype=np.float64)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(X, dtype=np.float64)).to(device))
+
+    @classmethod
+    def empty_like(cls, other):
+        import torch
+        return cls(torch.empty_like(other.Q), torch.empty_like(other.X))
+
+    @property
+    def n(self):
+        return int(self.Q.shape[1])
+
+    def c(self):
+        assert self.Q.is_contiguous() and self.X.is_contiguous()
+        q, x = self.Q, self.X
+        return RichState(q[0].data_ptr(), q[1].data_ptr(), q[2].data_ptr(), q[3].data_ptr(),
+                         x[0].data_ptr(), x[1].data_ptr(), self.n)
+
+    def numpy(self):
+        return self.Q.cpu().numpy(), self.X.cpu().numpy()
+
+
+def rich_workspace_size(n_cells):
+    b = C.c_size_t(0)
+    _check(lib().rich_workspace_size(int(n_cells), C.byref(b)), "rich_workspace_size")
+    return int(b.value)
+
+
+def workspace(n_cells, device="cuda"):
+    import torch
+    nb = rich_workspace_size(n_cells)
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def rich_stage(mesh: DeviceMesh, src: DeviceState, base: DeviceState, out: DeviceState, h,
+               params: Params, ws, stream=None):
+    """Enqueue one stage; returns immediately (see rich_stage_flags)."""
+    st = lib().rich_stage(C.byref(mesh.c()), C.byref(src.c()), C.byref(base.c()),
+                          C.byref(out.c()), float(h), C.byref(params.c()),
+                          C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
+    _check(st, "rich_stage")
+
+
+def rich_stage_flags(ws, stream=None):
+    f = C.c_int32(0)
+    _check(lib().rich_stage_flags(C.c_void_p(ws.data_ptr()), _stream_ptr(stream), C.byref(f)),
+           "rich_stage_flags")
+    return int(f.value)
+
+
+def rich_cfl_dt(mesh: DeviceMesh, state: DeviceState, params: Params, ws, stream=None):
+    dt = C.c_double(0.0)
+    st = lib().rich_cfl_dt(C.byref(mesh.c()), C.byref(state.c()), C.byref(params.c()),
+                           C.byref(dt), C.c_void_p(ws.data_ptr()), ws.numel(),
+                           _stream_ptr(stream))
+    _check(st, "rich_cfl_dt")
+    return dt.value

@@ -1,0 +1,112 @@
+"""Shared helpers of the GPU parity tests: seeded cases, running one stage on
+both sides, and the per-quantity error metric.
+
+Metric (per conserved quantity k, per stage):
+    err_k = max_i |Q_gpu[k,i] - Q_oracle[k,i]| / scale_k
+with scale = max|M| for mass, max_i M_i (c_i + |v_i|) for both momenta,
+max|E| for energy and the box size for the points.  The bar is 1e-12.
+"""
+import math
+
+import numpy as np
+
+import oracle as O
+from paper_1410_3219_amd import inputs as I
+from paper_1410_3219_amd import tess as T
+
+TOL = 1e-12
+
+
+def host_mesh(px, py, box, bc):
+    return T.rich_tess_build(px, py, box, bc)
+
+
+def case(name, k=24, riemann=0, limiter=0, motion=1, pass2=False, seed=1):
+    """(mesh, Qsrc, Qbase, Xbase, h, oracle Params)."""
+    if name == "sod":
+        P = I.sod(k=k, seed=seed)
+        m = host_mesh(P.px, P.py, P.box, P.bc)
+        Q = P.state(m.area)
+    elif name == "sod_angle":
+        P = I.sod(k=k, seed=seed, angle=0.7, gamma=1.4)
+        m = host_mesh(P.px, P.py, P.box, P.bc)
+        Q = P.state(m.area)
+    elif name == "wave":
+        P = I.advected_wave(k=k, seed=seed)
+        m = host_mesh(P.px, P.py, P.box, P.bc)
+        Q = P.state(m.area)
+    elif name == "acoustic":
+        P = I.acoustic_wave(k=k, seed=seed, amp=1e-3)
+        m = host_mesh(P.px, P.py, P.box, P.bc)
+        Q = P.state(m.area)
+    elif name == "sedov":
+        P = I.sedov(k=k, seed=seed, lloyd_iters=2)
+        m = host_mesh(P.px, P.py, P.box, P.bc)
+        Q = I.sedov_state(P, m.area)
+    elif name == "kh":
+        P = I.kelvin_helmholtz(k=k, seed=seed)
+        m = host_mesh(P.px, P.py, P.box, P.bc)
+        Q = P.state(m.area)
+    elif name == "gresho":
+        P = I.gresho(k=k, seed=seed)
+        m = host_mesh(P.px, P.py, P.box, P.bc)
+        Q = P.state(m.area)
+    else:
+        raise ValueError(name)
+    p = O.Params(gamma=P.gamma, riemann=riemann, limiter=limiter, motion=motion)
+    X = np.stack([m.px, m.py])
+    dt, st = O.cfl_dt(m, Q, p)
+    assert st == 0
+    if not pass2:
+        return m, Q, Q, X, 0.5 * dt, p
+    # second pass of a time-centred step: primitives from the half-step state
+    # on the half-step mesh, update applied to the start-of-step state
+    s1 = O.stage(m, Q, Q, X, 0.5 * dt, p)
+    assert s1.status == 0
+    mh = host_mesh(s1.X[0], s1.X[1], m.box, m.bc) if motion else m
+    return mh, s1.Q, Q, X, dt, p
+
+
+def gpu_params(p):
+    from paper_1410_3219_amd import rich as R
+    return R.Params(gamma=p.gamma, cfl=p.cfl, theta=p.theta, delta_v=p.delta_v,
+                    delta_p=p.delta_p, chi=p.chi, eta=p.eta, riemann=p.riemann,
+                    motion=p.motion, limiter=p.limiter)
+
+
+def gpu_stage(m, Qs, Qb, Xb, h, p, repeat=1):
+    import torch
+    from paper_1410_3219_amd import rich as R
+    dm = R.DeviceMesh.from_host(m)
+    src = R.DeviceState.from_host(Qs, Xb)
+    base = R.DeviceState.from_host(Qb, Xb)
+    ws = R.workspace(m.n_cells)
+    outs = []
+    for _ in range(repeat):
+        out = R.DeviceState.empty_like(base)
+        out.Q.fill_(float("nan"))
+        out.X.fill_(float("nan"))
+        R.rich_stage(dm, src, base, out, h, gpu_params(p), ws)
+        flags = R.rich_stage_flags(ws)
+        torch.cuda.synchronize()
+        Q, X = out.numpy()
+        outs.append((Q, X, flags))
+    return outs if repeat > 1 else outs[0]
+
+
+def scales(m, Q, p, box):
+    prim = O.primitives(m, Q, p)
+    c = prim[4]
+    v = np.hypot(prim[1], prim[2])
+    return np.array([np.max(np.abs(Q[0])), np.max(Q[0] * (c + v)), np.max(Q[0] * (c + v)),
+                     np.max(np.abs(Q[3]))]), max(box[2] - box[0], box[3] - box[1])
+
+
+def errors(m, Qg, Xg, Qo, Xo, Qref, p):
+    sc, L = scales(m, Qref, p, m.box)
+    eq = np.max(np.abs(Qg - Qo), axis=1) / sc
+    dx = np.abs(Xg - Xo)
+    if m.bc == 1:
+        dx = np.minimum(dx, L - dx)
+    ex = np.max(dx) / L
+    return eq, ex
