@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Benchmark: FP64 time-centred steps of the moving-mesh Godunov scheme on
+one MI355X.
+
+Workload (default): advected wave on a 2048 x 2048 jittered lattice
+(4,194,304 cells), periodic unit box, rho = 1 + 1e-3 sin(2 pi x), p = 0.6,
+v = (1, 0.5), gamma = 5/3, Lagrangian mesh motion with cell rounding, HLLC.
+
+A step is the whole hot path: stage 1 on mesh_n (half step), stage 2 on
+mesh_{n+1/2} (full step from the start-of-step state).  The Voronoi meshes
+come from the host tessellation stage, which is an input stage timed apart:
+the benchmark first runs the real chain (GPU stages, host tessellation in
+between) and keeps every mesh resident in HBM, then replays the same chain
+from the same initial state with all inputs resident and times exactly K
+steps (after W warm-up steps) with HIP events on the launch stream.  The
+replayed final state must equal the live one bit for bit.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import glob
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s per step (FP64) and HBM fraction; batched/served vs plain, p99"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1410_3219_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(m, pass2):
+    """Bytes one stage must move at least once (cells, state, edges, CSR,
+    results): 40 B geometry + 32 B source state per cell, 32 B per edge,
+    4 B per CSR offset and entry, 48 B of results per cell, and for the
+    second stage 48 B more of start-of-step state and points."""
+    n, ne, nc = m.n_cells, m.n_edges, m.n_csr
+    b = 40 * n + 32 * n + 32 * ne + 4 * (n + 1) + 4 * nc + 48 * n
+    if pass2:
+        b += 48 * n
+    return b
+
+
+def make_problem(name, k):
+    from paper_1410_3219_amd import inputs as I
+    if name == "wave":
+        P = I.advected_wave(k=k or 2048, seed=3)
+        desc = f"advected wave {P.extra.get('amp')} amp, {int(round(P.n ** 0.5))}^2 jittered lattice, periodic unit box, v=(1,0.5), p=0.6, gamma=5/3, moving mesh"
+        state = P.state
+    elif name == "sedov":
+        P = I.sedov(k=k or 512, seed=2, lloyd_iters=5)
+        desc = f"point explosion, {P.n} uniform-random points Lloyd-relaxed 5x, walls, rho=1, p=1e-6, E=1 in the centre cell, gamma=5/3, moving mesh"
+        state = lambda area: I.sedov_state(P, area)   # noqa: E731
+    elif name == "sod":
+        P = I.sod(k=k or 64, seed=1)
+        desc = f"shock tube, {P.n} jittered lattice points, walls, gamma=5/3, moving mesh"
+        state = P.state
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return P, desc, state
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="wave", choices=["wave", "sedov", "sod"])
+    ap.add_argument("--k", type=int, default=0, help="lattice side (default per workload)")
+    ap.add_argument("--riemann", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--threads", type=int, default=0, help="host tessellation threads")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        log("bench.py measures one GPU only: this build has no multi-GPU path "
+            "(each run or batch runs on one MI355X); run with --gpus 1.")
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1410_3219_amd import rich as R
+    from paper_1410_3219_amd import tess as T
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    R.lib()  # fail loudly if the HIP library is missing
+
+    t0 = time.time()
+    P, desc, make_state = make_problem(args.workload, args.k)
+    log(f"[bench] problem {args.workload}: {P.n} cells ({time.time() - t0:.1f}s)")
+    params = R.Params(gamma=P.gamma, riemann=args.riemann)
+    K, W = args.steps, args.warmup
+
+    tess_times, h2d_times = [], []
+
+    def tessellate(x, y):
+        t = time.time()
+        hm = T.rich_tess_build(x, y, P.box, P.bc, args.threads)
+        tess_times.append(time.time() - t)
+        return hm
+
+    def upload(hm):
+        torch.cuda.synchronize()
+        t = time.time()
+        dm = R.DeviceMesh.from_host(hm)
+        torch.cuda.synchronize()
+        h2d_times.append(time.time() - t)
+        return dm
+
+    # ---------------- live chain: GPU stages + host tessellation -----------
+    hm0 = tessellate(P.px, P.py)
+    n = hm0.n_cells
+    Q0 = make_state(hm0.area)
+    X0 = np.stack([hm0.px, hm0.py])
+    ws = R.workspace(n)
+    meshes, halves, dts = [upload(hm0)], [], []
+    cur = R.DeviceState.from_host(Q0, X0)
+    init = R.DeviceState(cur.Q.clone(), cur.X.clone())
+    half = R.DeviceState.empty_like(cur)
+    nxt = R.DeviceState.empty_like(cur)
+    host_half0 = None
+    bytes_step = None
+    for s in range(W + K):
+        dt = R.rich_cfl_dt(meshes[s], cur, params, ws)
+        dts.append(dt)
+        R.rich_stage(meshes[s], cur, cur, half, 0.5 * dt, params, ws)
+        f = R.rich_stage_flags(ws)
+        if f:
+            raise SystemExit(f"stage 1 of step {s} flagged {f}")
+        xh = half.X.cpu().numpy()
+        hmh = tessellate(xh[0], xh[1])
+        if s == 0:
+            host_half0 = (hmh, half.Q.cpu().numpy().copy())
+            bytes_step = algorithmic_bytes(hm0, False) + algorithmic_bytes(hmh, True)
+        halves.append(upload(hmh))
+        R.rich_stage(halves[s], half, cur, nxt, dt, params, ws)
+        f = R.rich_stage_flags(ws)
+        if f:
+            raise SystemExit(f"stage 2 of step {s} flagged {f}")
+        xn = nxt.X.cpu().numpy()
+        meshes.append(upload(tessellate(xn[0], xn[1])))
+        cur, nxt = nxt, cur
+        log(f"[bench] live step {s + 1}/{W + K}: dt={dt:.3e} tess {tess_times[-1]:.2f}s "
+            f"(mesh {meshes[-1].nbytes() / 1e6:.0f} MB)")
+    live_final = (cur.Q.clone(), cur.X.clone())
+
+    # ---------------- timed replay, all inputs resident in HBM -------------
+    stream = torch.cuda.current_stream()
+
+    def run_step(s, a, hbuf, b):
+        R.rich_stage(meshes[s], a, a, hbuf, 0.5 * dts[s], params, ws)
+        R.rich_stage(halves[s], hbuf, a, b, dts[s], params, ws)
+
+    cur = R.DeviceState(init.Q.clone(), init.X.clone())
+    nxt = R.DeviceState.empty_like(cur)
+    for s in range(W):
+        run_step(s, cur, half, nxt)
+        cur, nxt = nxt, cur
+    torch.cuda.synchronize()
+    R.rich_profile_enable(True)
+    for k_ in ("k_cell", "k_flux"):
+        R.rich_profile_read(k_)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for s in range(W, W + K):
+        run_step(s, cur, half, nxt)
+        cur, nxt = nxt, cur
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    R.rich_profile_enable(False)
+    ms_total = ev0.elapsed_time(ev1)
+    kern = {k_: R.rich_profile_read(k_) for k_ in ("k_cell", "k_flux")}
+    flags = R.rich_stage_flags(ws)
+    replay_ok = bool(torch.equal(cur.Q, live_final[0]) and torch.equal(cur.X, live_final[1]))
+    log(f"[bench] timed {K} steps: {ms_total:.3f} ms, flags={flags}, replay bitwise={replay_ok}")
+
+    ms_per_step = ms_total / K
+    value = n * K / (ms_total / 1e3)
+    # one pass of the hot path = k_cell + k_flux; report the pair as the
+    # dominant unit (two launches per stage, two stages per step)
+    stage_ms = (kern["k_cell"][0] + kern["k_flux"][0]) / max(1, kern["k_cell"][1]) * 2
+    achieved = bytes_step / (stage_ms / 1e3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
+    if os.path.exists(tfile):
+        tj = json.load(open(tfile))
+        if tj.get("source_hash") == kernel_source_hash() and tj.get("n_cells") == n:
+            traffic = tj.get("bytes_per_step")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "n_cells": n,
+            "n_edges": hm0.n_edges,
+            "riemann": "exact" if args.riemann else "hllc",
+            "scheme": "time-centred fluxes, two stages per step, switching limiter",
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_cell+k_flux (one stage; two stages per step)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_step": bytes_step,
+            "kernel_ms_per_step": {k_: v[0] / K for k_, v in kern.items()},
+            "launches": {k_: v[1] for k_, v in kern.items()},
+        },
+        "replay_bitwise_equal_to_live": replay_ok,
+        "host_input_stage": {
+            "tessellation_s_mean": float(np.mean(tess_times)),
+            "tessellations": len(tess_times),
+            "h2d_s_mean": float(np.mean(h2d_times)),
+            "end_to_end_ms_per_step_estimate": ms_per_step + 2e3 * (
+                float(np.mean(tess_times)) + float(np.mean(h2d_times))),
+        },
+    }
+
+    # ---------------- CPU baseline: the oracle on one step -----------------
+    if not args.no_cpu_baseline:
+        sys.path.insert(0, os.path.join(ROOT, "oracle"))
+        import oracle as O
+        op = O.Params(gamma=params.gamma, cfl=params.cfl, theta=params.theta,
+                      delta_v=params.delta_v, delta_p=params.delta_p, chi=params.chi,
+                      eta=params.eta, riemann=params.riemann, motion=params.motion,
+                      limiter=params.limiter)
+        hmh, Qh_gpu = host_half0
+        t = time.perf_counter()
+        r1 = O.stage(hm0, Q0, Q0, X0, 0.5 * dts[0], op)
+        r2 = O.stage(hmh, Qh_gpu, Q0, X0, dts[0], op)
+        t_cpu = time.perf_counter() - t
+        err = float(np.max(np.abs(r1.Q - Qh_gpu), axis=1).max() / np.abs(Q0).max())
+        log(f"[bench] oracle step {t_cpu:.1f}s (stage-1 max |diff| / max|Q| = {err:.2e})")
+        out["cpu_baseline"] = {
+            "value": n / t_cpu,
+            "unit": "cell-updates/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"one full time-centred step (both stages) of the same {n}-cell workload, serial C oracle, step 0 meshes",
+        }
+        out["full_size_stage1_max_rel_diff_vs_oracle"] = err
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -170,6 +170,17 @@ int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
               rich_tess_fn tess, rich_tess_release_fn release, void* tess_user,
               void* stream);
 
+/*
+ * Kernel timing for benchmarks.  While enabled, every stage records HIP
+ * events on its launch stream around each of its kernels ("k_cell",
+ * "k_flux", or "k_stage" for the fused variant); rich_profile_read
+ * synchronises those events, returns the summed duration in milliseconds
+ * and the number of launches of the named kernel since the last read, and
+ * forgets them.  Not thread-safe; off by default.
+ */
+int rich_profile_enable(int on);
+int rich_profile_read(const char* kernel, double* total_ms, int64_t* launches);
+
 /* Human-readable name of a status code. */
 const char* rich_strerror(int status);
 

@@ -90,6 +90,8 @@ typedef struct rich_mesh_host {
   double band;        /* ghost band width finally used          */
   int32_t n_rebuilds; /* band widenings                         */
   int64_t n_exact;    /* predicate calls decided exactly        */
+  double t_triangulate; /* seconds: ghosts + Delaunay + checks  */
+  double t_voronoi;     /* seconds: cells, edges, CSR           */
 } rich_mesh_host;
 
 /*
@@ -138,6 +140,27 @@ int rich_tess_hilbert_order(const double* px, const double* py, int64_t n,
  * (periodic: wrapped back into the box).  Points are updated in place. */
 int rich_tess_lloyd(double* px, double* py, int64_t n, const double box[4],
                     uint32_t bc, int32_t iters, int32_t n_threads);
+
+/*
+ * Adapter for the time-centred step of the device path: rich_tess_callback
+ * and rich_tess_release have the signatures of rich_tess_fn and
+ * rich_tess_release_fn in rich.h, and rich_tess_view has the field layout of
+ * rich_host_mesh_view there.  `user` must be a rich_tess_ctx; each mesh the
+ * callback hands out stays valid until released.
+ */
+typedef struct rich_tess_view {
+  int64_t n_cells, n_edges, n_csr;
+  const double *px, *py, *sx, *sy, *area;
+  const int32_t *e_i, *e_j;
+  const double *e_len, *e_fx, *e_fy;
+  const int32_t *off, *idx, *eoff;
+} rich_tess_view;
+typedef struct rich_tess_ctx rich_tess_ctx;
+rich_tess_ctx* rich_tess_ctx_create(int32_t n_threads);
+void rich_tess_ctx_destroy(rich_tess_ctx* ctx);
+int rich_tess_callback(void* user, const double* px, const double* py, int64_t n,
+                       const double box[4], uint32_t bc, rich_tess_view* out);
+void rich_tess_release(void* user, rich_tess_view* v);
 
 #ifdef __cplusplus
 }

@@ -40,6 +40,7 @@ struct RunDesc {
   // geometry and parameters
   double x0, y0, x1, y1, Lx, Ly;
   double h, gamma, theta, delta_v, delta_p, chi, eta;
+  double rgm1;  // 1 / (gamma - 1)
   int32_t n, n_edges, n_csr, bc;
   int32_t riemann, motion, limiter, pad;
 };
@@ -129,13 +130,23 @@ __device__ __forceinline__ Nb nb_view(const RunDesc& d, int i, double rix, doubl
 // ---------------------------------------------------------------------------
 // A1: primitives of cell j from the extensive totals (ideal gas)
 // ---------------------------------------------------------------------------
+// Two reciprocals instead of four divisions: the results may differ from the
+// quotients in the last bit.
 __device__ __forceinline__ void prim_of(const RunDesc& d, int j, double& rho, double& vx,
                                         double& vy, double& p) {
-  double A = d.area[j], M = d.sM[j];
-  rho = M / A;
-  vx = d.sPx[j] / M;
-  vy = d.sPy[j] / M;
-  p = (d.gamma - 1.0) * (d.sE[j] / A - 0.5 * rho * (vx * vx + vy * vy));
+  const double rA = 1.0 / d.area[j];
+  const double M = d.sM[j];
+  const double rM = 1.0 / M;
+  rho = M * rA;
+  vx = d.sPx[j] * rM;
+  vy = d.sPy[j] * rM;
+  p = (d.gamma - 1.0) * (d.sE[j] * rA - 0.5 * rho * (vx * vx + vy * vy));
+}
+
+// Pressure-ratio test of the shock detector, min(pi/pj, pj/pi) < delta_p,
+// without a division (both pressures positive).
+__device__ __forceinline__ bool pressure_jump(double delta_p, double pi, double pj) {
+  return pi > pj ? (pj < delta_p * pi) : (pj > pi ? (pi < delta_p * pj) : (delta_p > 1.0));
 }
 
 // ---------------------------------------------------------------------------
@@ -190,8 +201,11 @@ __device__ inline bool cell_record(const RunDesc& d, int i, double* rec) {
     for (int q = 0; q < 4; ++q) {
       const double dphi = pj[q] - phi[q];
       const double mean = 0.5 * (phi[q] + pj[q]);
-      g[2 * q] += v.L * (dphi * ux - mean * nx);
-      g[2 * q + 1] += v.L * (dphi * uy - mean * ny);
+      // each term is rounded before it is added (as in slot_terms)
+      const double tx = v.L * (dphi * ux - mean * nx);
+      const double ty = v.L * (dphi * uy - mean * ny);
+      g[2 * q] += tx;
+      g[2 * q + 1] += ty;
       pmax[q] = fmax(pmax[q], pj[q]);
       pmin[q] = fmin(pmin[q], pj[q]);
     }
@@ -265,11 +279,54 @@ __device__ inline bool cell_record(const RunDesc& d, int i, double* rec) {
 }
 
 // ---------------------------------------------------------------------------
+// The per-neighbour part of A3/A4 for the slot-parallel cell kernel: the two
+// gradient terms of eq. (slope) for each of the four variables, the
+// neighbour's values, the offset of the edge centre from the centroid and the
+// pressure-ratio test.  Same arithmetic as the loop bodies of cell_record.
+// ---------------------------------------------------------------------------
+struct SlotTerms {
+  double g[8];
+  double pj[4];
+  double fdx, fdy;
+  bool pflag;
+};
+
+__device__ __forceinline__ void slot_terms(const RunDesc& d, int i, const double* phi,
+                                           double rix, double riy, double six, double siy,
+                                           int entry, SlotTerms& o, bool& bad) {
+  Nb v = nb_view(d, i, rix, riy, entry, bad);
+  if (v.wall) {
+    o.pj[0] = phi[0];
+    mirror_vec(v.wall, phi[1], phi[2], o.pj[1], o.pj[2]);
+    o.pj[3] = phi[3];
+  } else {
+    prim_of(d, v.j, o.pj[0], o.pj[1], o.pj[2], o.pj[3]);
+  }
+  const double rx = rix - v.rx, ry = riy - v.ry;
+  const double inv_r = 1.0 / sqrt(rx * rx + ry * ry);
+  const double cx = v.fx - 0.5 * (rix + v.rx), cy = v.fy - 0.5 * (riy + v.ry);
+  const double ux = cx * inv_r, uy = cy * inv_r, nx = rx * inv_r, ny = ry * inv_r;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double dphi = o.pj[q] - phi[q];
+    const double mean = 0.5 * (phi[q] + o.pj[q]);
+    o.g[2 * q] = v.L * (dphi * ux - mean * nx);
+    o.g[2 * q + 1] = v.L * (dphi * uy - mean * ny);
+  }
+  double ratio = 1.0;
+  if (o.pj[3] > phi[3]) ratio = phi[3] / o.pj[3];
+  if (phi[3] > o.pj[3]) ratio = o.pj[3] / phi[3];
+  o.pflag = d.delta_p > ratio;
+  o.fdx = v.fx - six;
+  o.fdy = v.fy - siy;
+}
+
+// ---------------------------------------------------------------------------
 // Riemann solvers in the edge frame (section 2.4).  W = (rho, u, vt, p).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void phys_flux(double g, const double* W, double* F) {
+__device__ __forceinline__ void phys_flux(double g, double rgm1, const double* W, double* F) {
   const double rho = W[0], u = W[1], vt = W[2], pr = W[3];
-  const double E = pr / (g - 1.0) + 0.5 * rho * (u * u + vt * vt);
+  const double E = pr * rgm1 + 0.5 * rho * (u * u + vt * vt);
   F[0] = rho * u;
   F[1] = rho * u * u + pr;
   F[2] = rho * u * vt;
@@ -278,7 +335,8 @@ __device__ __forceinline__ void phys_flux(double g, const double* W, double* F) 
 
 // HLLC with Davis wave-speed bounds; star fluxes are the physical fluxes of
 // the star states (identical to the Rankine-Hugoniot form).
-__device__ inline void hllc(double g, const double* WL, const double* WR, double* F) {
+__device__ inline void hllc(double g, double rgm1, const double* WL, const double* WR,
+                            double* F) {
   const double rl = WL[0], ul = WL[1], pl = WL[3];
   const double rr = WR[0], ur = WR[1], pr = WR[3];
   const double cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
@@ -287,18 +345,18 @@ __device__ inline void hllc(double g, const double* WL, const double* WR, double
   const double ss = (pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur)) /
                     (rl * (sl - ul) - rr * (sr - ur));
   if (0.0 <= sl) {
-    phys_flux(g, WL, F);
+    phys_flux(g, rgm1, WL, F);
     return;
   }
   if (!(0.0 <= ss) && !(0.0 < sr)) {
-    phys_flux(g, WR, F);
+    phys_flux(g, rgm1, WR, F);
     return;
   }
   const bool left = (0.0 <= ss);
   const double* W = left ? WL : WR;
   const double sk = left ? sl : sr;
   const double rho = W[0], u = W[1], vt = W[2], pk = W[3];
-  const double E = pk / (g - 1.0) + 0.5 * rho * (u * u + vt * vt);
+  const double E = pk * rgm1 + 0.5 * rho * (u * u + vt * vt);
   const double rs = rho * (sk - u) / (sk - ss);
   const double ps = pk + rho * (sk - u) * (ss - u);
   const double Es = rs * (E / rho + (ss - u) * (ss + pk / (rho * (sk - u))));
@@ -326,7 +384,8 @@ __device__ __forceinline__ void pfun(double g, double ps, double rk, double pk, 
   }
 }
 
-__device__ inline bool exact_flux(double g, const double* WL, const double* WR, double* F) {
+__device__ inline bool exact_flux(double g, double rgm1, const double* WL, const double* WR,
+                                  double* F) {
   const double rl = WL[0], ul = WL[1], pl = WL[3];
   const double rr = WR[0], ur = WR[1], pr = WR[3];
   const double cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
@@ -401,7 +460,7 @@ __device__ inline bool exact_flux(double g, const double* WL, const double* WR, 
       }
     }
   }
-  phys_flux(g, W, F);
+  phys_flux(g, rgm1, W, F);
   return true;
 }
 
@@ -464,13 +523,13 @@ __device__ inline bool edge_flux(const RunDesc& d, int e, const double* ri, cons
       for (int q = 0; q < 4; ++q) phR[q] = rj[q] + rj[R_G + 2 * q] * dx + rj[R_G + 2 * q + 1] * dy;
     }
     const double dx = rjx - rix, dy = rjy - riy;
-    const double dist = sqrt(dx * dx + dy * dy);
-    nx = dx / dist;
-    ny = dy / dist;
+    const double inv_dist = rsqrt(dx * dx + dy * dy);
+    nx = dx * inv_dist;
+    ny = dy * inv_dist;
     const double tx = -ny, ty = nx;
     const double cx = fx - 0.5 * (rix + rjx), cy = fy - 0.5 * (riy + rjy);
     const double wix = ri[R_WX], wiy = ri[R_WY], wjx = rj[R_WX], wjy = rj[R_WY];
-    const double a = ((wix - wjx) * cx + (wiy - wjy) * cy) / dist;
+    const double a = ((wix - wjx) * cx + (wiy - wjy) * cy) * inv_dist;
     wex = 0.5 * (wix + wjx) + a * nx;
     wey = 0.5 * (wiy + wjy) + a * ny;
     const double vlx = phL[1] - wex, vly = phL[2] - wey;
@@ -480,9 +539,9 @@ __device__ inline bool edge_flux(const RunDesc& d, int e, const double* ri, cons
   }
   double F[4];
   if (RIEMANN == 1) {
-    if (!exact_flux(d.gamma, WL, WR, F)) ok = false;
+    if (!exact_flux(d.gamma, d.rgm1, WL, WR, F)) ok = false;
   } else {
-    hllc(d.gamma, WL, WR, F);
+    hllc(d.gamma, d.rgm1, WL, WR, F);
   }
   const double tx = -ny, ty = nx;
   const double fpx = F[1] * nx + F[2] * tx, fpy = F[1] * ny + F[2] * ty;

@@ -27,6 +27,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "rich.h"
@@ -34,8 +35,15 @@
 
 namespace rich {
 
-constexpr int kTile = 256;      // cells per tile = threads per block
-constexpr int kEdgeCap = 1024;  // owned-edge fluxes kept in LDS per tile
+#ifndef RICH_LPC
+#define RICH_LPC 2
+#endif
+constexpr int kTile = 256;        // k_flux: cells per tile = threads per block
+constexpr int kEdgeCap = 896;     // k_flux: owned-edge fluxes kept in LDS
+constexpr int kForCap = 256;      // k_flux: other edges kept in LDS
+constexpr int kMapCap = 2304;     // k_flux: CSR entries classified in LDS
+constexpr int kCellThreads = 256;   // k_cell: threads per block
+constexpr int kLpc = RICH_LPC;      // k_cell: lanes per cell
 constexpr int kNumXcd = 8;
 constexpr size_t kHeader = 256;  // per-run workspace header
 
@@ -46,7 +54,9 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return x * q + min(x, rem) + k;
 }
 
-// run owning global tile t (tile_start is an exclusive prefix, n_runs + 1)
+// Batched launches take a plan: tile_start[0..n_runs] is the exclusive prefix
+// of the tiles of the runs in this launch, tile_start[n_runs + 1 + k] the
+// descriptor index of the k-th of them.  find_run returns k for tile t.
 __device__ __forceinline__ int find_run(const int32_t* __restrict__ tile_start, int n_runs,
                                         int t) {
   int lo = 0, hi = n_runs - 1;
@@ -77,30 +87,237 @@ __global__ void k_clear_batch(const RunDesc* __restrict__ descs, int n_runs) {
 }
 
 // ---------------------------------------------------------------------------
-// A1-A4: one thread per cell
+// A1-A4: LPC lanes per cell.  Lane l of a cell's group walks the CSR entries
+// l, l+LPC, ... (neighbour gathers, gradient terms of eq. slope, neighbour
+// bounds, pressure-ratio test), the partial results are combined with a fixed
+// xor-shuffle tree (so every lane of the group holds the same bits), then the
+// limiter pass is split the same way and each lane writes 16/LPC doubles of
+// the cell's 128-byte record.  More lanes per cell shorten each lane's chain
+// of dependent gathers and put more loads in flight.
 // ---------------------------------------------------------------------------
-template <bool BATCH>
-__global__ __launch_bounds__(kTile) void k_cell(RunDesc one, const RunDesc* __restrict__ descs,
-                                                const int32_t* __restrict__ tile_start,
-                                                int n_runs, int n_tiles) {
-  for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
-    const int t = BATCH ? b : xcd_tile(b, n_tiles);
-    const int r = BATCH ? find_run(tile_start, n_runs, t) : 0;
-    const RunDesc& d = BATCH ? descs[r] : one;
-    const int c0 = (t - (BATCH ? tile_start[r] : 0)) * kTile;
-    const int i = c0 + (int)threadIdx.x;
-    if (i < d.n) {
-      double rec[kRecDoubles];
-      if (!cell_record(d, i, rec)) atomicOr(d.flag, RICH_FLAG_DOMAIN);
-      double2* dst = reinterpret_cast<double2*>(d.rec + (size_t)i * kRecDoubles);
+template <int LPC>
+__device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
-      for (int k = 0; k < kRecDoubles / 2; ++k) dst[k] = make_double2(rec[2 * k], rec[2 * k + 1]);
+  for (int o = 1; o < LPC; o <<= 1) v += __shfl_xor(v, o, LPC);
+  return v;
+}
+template <int LPC>
+__device__ __forceinline__ double group_max(double v) {
+#pragma unroll
+  for (int o = 1; o < LPC; o <<= 1) v = fmax(v, __shfl_xor(v, o, LPC));
+  return v;
+}
+template <int LPC>
+__device__ __forceinline__ double group_min(double v) {
+#pragma unroll
+  for (int o = 1; o < LPC; o <<= 1) v = fmin(v, __shfl_xor(v, o, LPC));
+  return v;
+}
+template <int LPC>
+__device__ __forceinline__ int group_or(int v) {
+#pragma unroll
+  for (int o = 1; o < LPC; o <<= 1) v |= __shfl_xor(v, o, LPC);
+  return v;
+}
+
+template <int LPC, bool BATCH>
+__global__ __launch_bounds__(kCellThreads) void k_cell(RunDesc one,
+                                                       const RunDesc* __restrict__ descs,
+                                                       const int32_t* __restrict__ tile_start,
+                                                       int n_runs, int n_tiles) {
+  constexpr int CPB = kCellThreads / LPC;  // cells per block
+  constexpr int MAXE = 8 / LPC;            // entries per lane whose edge offsets stay in registers
+  const int lane = (int)threadIdx.x % LPC;
+  const int cl = (int)threadIdx.x / LPC;
+  for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
+    const int tt = BATCH ? b : xcd_tile(b, n_tiles);
+    const int pos = BATCH ? find_run(tile_start, n_runs, tt) : 0;
+    const RunDesc& d = BATCH ? descs[tile_start[n_runs + 1 + pos]] : one;
+    const int i0 = (tt - (BATCH ? tile_start[pos] : 0)) * CPB + cl;
+    const bool active = i0 < d.n;
+    const int i = active ? i0 : 0;
+    bool bad = false;
+
+    double rho, vx, vy, p;
+    prim_of(d, i, rho, vx, vy, p);
+    const double c = sqrt(d.gamma * p / rho);
+    const double rix = d.px[i], riy = d.py[i], six = d.sx[i], siy = d.sy[i];
+    const double A = d.area[i];
+    const double R = sqrt(A / kPi);
+    double wx = 0.0, wy = 0.0;
+    if (d.motion) {
+      // A2 (section 6): Lagrangian motion plus the cell-rounding correction
+      wx = vx;
+      wy = vy;
+      const double dx = six - rix, dy = siy - riy;
+      const double dd = sqrt(dx * dx + dy * dy);
+      if (dd > d.eta * R) {
+        wx += d.chi * c * dx / dd;
+        wy += d.chi * c * dy / dd;
+      }
+    }
+    const double phi[4] = {rho, vx, vy, p};
+    int k0 = d.off[i], k1 = d.off[i + 1];
+    if (!active || k0 < 0 || k1 < k0 || k1 > d.n_csr) {
+      if (active) bad = true;
+      k1 = k0;
+    }
+
+    // A3: eq. (slope), r_ij = r_i - r_j; each term rounded before it is added
+    double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double pmax[4] = {rho, vx, vy, p}, pmin[4] = {rho, vx, vy, p};
+    int pflag = 0;
+    double fdx[MAXE], fdy[MAXE];
+    auto entry_terms = [&](int k, double& ex, double& ey) {
+      Nb v = nb_view(d, i, rix, riy, d.idx[k], bad);
+      double pj[4];
+      if (v.wall) {
+        pj[0] = rho;
+        mirror_vec(v.wall, vx, vy, pj[1], pj[2]);
+        pj[3] = p;
+      } else {
+        prim_of(d, v.j, pj[0], pj[1], pj[2], pj[3]);
+      }
+      const double rx = rix - v.rx, ry = riy - v.ry;
+      const double inv_r = rsqrt(rx * rx + ry * ry);
+      const double cx = v.fx - 0.5 * (rix + v.rx), cy = v.fy - 0.5 * (riy + v.ry);
+      const double ux = cx * inv_r, uy = cy * inv_r, nx = rx * inv_r, ny = ry * inv_r;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double dphi = pj[q] - phi[q];
+        const double mean = 0.5 * (phi[q] + pj[q]);
+        const double tx = v.L * (dphi * ux - mean * nx);
+        const double ty = v.L * (dphi * uy - mean * ny);
+        g[2 * q] += tx;
+        g[2 * q + 1] += ty;
+        pmax[q] = fmax(pmax[q], pj[q]);
+        pmin[q] = fmin(pmin[q], pj[q]);
+      }
+      if (pressure_jump(d.delta_p, p, pj[3])) pflag = 1;
+      ex = v.fx - six;
+      ey = v.fy - siy;
+    };
+#pragma unroll
+    for (int m = 0; m < MAXE; ++m) {
+      const int k = k0 + lane + m * LPC;
+      fdx[m] = 0.0;
+      fdy[m] = 0.0;
+      if (k < k1) entry_terms(k, fdx[m], fdy[m]);
+    }
+    for (int k = k0 + lane + MAXE * LPC; k < k1; k += LPC) {
+      double ex, ey;
+      entry_terms(k, ex, ey);
+    }
+    double G[8];
+    const double rA = 1.0 / A;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) G[q] = group_sum<LPC>(g[q]) * rA;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      pmax[q] = group_max<LPC>(pmax[q]);
+      pmin[q] = group_min<LPC>(pmin[q]);
+    }
+    bool shock = group_or<LPC>(pflag) != 0;
+    if (-(G[2] + G[5]) > d.delta_v * c / R) shock = true;
+
+    // A4: limiter
+    double alpha[4] = {1.0, 1.0, 1.0, 1.0};
+    int local = -1;
+    if (d.limiter == 0) local = shock ? 1 : 0;
+    if (d.limiter == 1) local = 0;
+    if (d.limiter == 2) local = 1;
+    if (d.limiter == 4) alpha[0] = alpha[1] = alpha[2] = alpha[3] = 0.0;
+    if (local == 0) {
+      // global limiter: min_j psi_ij is attained at the largest positive and
+      // the most negative change (division is monotone in the denominator)
+      double dmax[4] = {0, 0, 0, 0}, dmin[4] = {0, 0, 0, 0};
+      auto bound = [&](double dx, double dy) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double dphi = G[2 * q] * dx + G[2 * q + 1] * dy;
+          dmax[q] = fmax(dmax[q], dphi);
+          dmin[q] = fmin(dmin[q], dphi);
+        }
+      };
+#pragma unroll
+      for (int m = 0; m < MAXE; ++m)
+        if (k0 + lane + m * LPC < k1) bound(fdx[m], fdy[m]);
+      for (int k = k0 + lane + MAXE * LPC; k < k1; k += LPC) {
+        Nb v = nb_view(d, i, rix, riy, d.idx[k], bad);
+        bound(v.fx - six, v.fy - siy);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        dmax[q] = group_max<LPC>(dmax[q]);
+        dmin[q] = group_min<LPC>(dmin[q]);
+        if (dmax[q] > 0.0) alpha[q] = fmin(alpha[q], (pmax[q] - phi[q]) / dmax[q]);
+        if (dmin[q] < 0.0) alpha[q] = fmin(alpha[q], (pmin[q] - phi[q]) / dmin[q]);
+      }
+    } else if (local == 1) {
+      for (int k = k0 + lane; k < k1; k += LPC) {
+        Nb v = nb_view(d, i, rix, riy, d.idx[k], bad);
+        double pj[4];
+        if (v.wall) {
+          pj[0] = rho;
+          mirror_vec(v.wall, vx, vy, pj[1], pj[2]);
+          pj[3] = p;
+        } else {
+          prim_of(d, v.j, pj[0], pj[1], pj[2], pj[3]);
+        }
+        const double dx = v.fx - six, dy = v.fy - siy;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double dphi = G[2 * q] * dx + G[2 * q + 1] * dy;
+          const double psi =
+              (dphi != 0.0) ? fmax(d.theta * (pj[q] - phi[q]) / dphi, 0.0) : 1.0;
+          alpha[q] = fmin(alpha[q], psi);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) alpha[q] = group_min<LPC>(alpha[q]);
+    }
+    const int bad_any = group_or<LPC>(bad ? 1 : 0);
+    if (active) {
+      double rec[kRecDoubles];
+      rec[R_RHO] = rho;
+      rec[R_VX] = vx;
+      rec[R_VY] = vy;
+      rec[R_P] = p;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) rec[R_G + q] = G[q] * alpha[q / 2];
+      rec[R_WX] = wx;
+      rec[R_WY] = wy;
+      rec[R_SX] = six;
+      rec[R_SY] = siy;
+      constexpr int PER = kRecDoubles / LPC;  // doubles written by each lane
+      double2* dst = reinterpret_cast<double2*>(d.rec + (size_t)i * kRecDoubles + lane * PER);
+#pragma unroll
+      for (int k = 0; k < PER / 2; ++k) {
+        // select this lane's slice with compile-time indices only
+        double a0 = rec[2 * k], a1 = rec[2 * k + 1];
+#pragma unroll
+        for (int l = 1; l < LPC; ++l)
+          if (lane == l) {
+            a0 = rec[l * PER + 2 * k];
+            a1 = rec[l * PER + 2 * k + 1];
+          }
+        dst[k] = make_double2(a0, a1);
+      }
+      if (bad_any && lane == 0) atomicOr(d.flag, RICH_FLAG_DOMAIN);
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// A5-A8: one block per tile
+// A5-A8: one block per tile of kTile cells.
+//   phase 0  classify the tile's CSR entries: an edge the tile owns (first
+//            cell inside the tile, within the LDS capacity) is found at its
+//            position in the owned range; any other edge goes on a list
+//   phase 1  all lanes compute the owned edges and the listed edges, once
+//            each, into LDS
+//   phase 2  one lane per cell sums its entries in CSR order
+// Fluxes of edges whose first cell lies in another tile are computed by both
+// tiles, with the same code on the same inputs, hence the same bits.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wrap_once(double v, double lo, double hi) {
   const double L = hi - lo;
@@ -135,43 +352,68 @@ template <int RIEMANN, bool BATCH>
 __global__ __launch_bounds__(kTile) void k_flux(RunDesc one, const RunDesc* __restrict__ descs,
                                                 const int32_t* __restrict__ tile_start,
                                                 int n_runs, int n_tiles) {
-  __shared__ double sF[4][kEdgeCap];
+  __shared__ double sF[4][kEdgeCap + kForCap];
+  __shared__ int s_forE[kForCap];
+  __shared__ short s_map[kMapCap];
+  __shared__ int s_nfor;
+  const int tid = (int)threadIdx.x;
   for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
     const int t = BATCH ? b : xcd_tile(b, n_tiles);
-    const int r = BATCH ? find_run(tile_start, n_runs, t) : 0;
-    const RunDesc& d = BATCH ? descs[r] : one;
-    const int c0 = (t - (BATCH ? tile_start[r] : 0)) * kTile;
+    const int pos = BATCH ? find_run(tile_start, n_runs, t) : 0;
+    const RunDesc& d = BATCH ? descs[tile_start[n_runs + 1 + pos]] : one;
+    const int c0 = (t - (BATCH ? tile_start[pos] : 0)) * kTile;
     const int c1 = min(c0 + kTile, d.n);
     const int e0 = d.eoff[c0];
-    const int ne = min(d.eoff[c1] - e0, kEdgeCap);
+    const int ne = max(0, min(d.eoff[c1] - e0, kEdgeCap));
+    const int kb = d.off[c0];
+    const int S = max(0, min(d.off[c1], d.n_csr) - kb);
+    const int Sm = min(S, kMapCap);
     bool ok = true;
-    for (int k = (int)threadIdx.x; k < ne; k += kTile) {
-      double LF[4];
-      if (!flux_of_edge<RIEMANN>(d, e0 + k, LF)) ok = false;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) sF[q][k] = LF[q];
+    if (tid == 0) s_nfor = 0;
+    __syncthreads();
+    for (int s = tid; s < Sm; s += kTile) {
+      const int e = d.idx[kb + s] >> 1;
+      int m = -1;
+      if (e >= e0 && e < e0 + ne) {
+        m = e - e0;
+      } else if (e >= 0 && e < d.n_edges) {
+        const int f = atomicAdd(&s_nfor, 1);
+        if (f < kForCap) {
+          s_forE[f] = e;
+          m = kEdgeCap + f;
+        }
+      }
+      s_map[s] = (short)m;
     }
     __syncthreads();
-    const int i = c0 + (int)threadIdx.x;
+    const int nfor = min(s_nfor, kForCap);
+    for (int w = tid; w < ne + nfor; w += kTile) {
+      const int e = w < ne ? e0 + w : s_forE[w - ne];
+      const int pos = w < ne ? w : kEdgeCap + (w - ne);
+      double LF[4];
+      if (!flux_of_edge<RIEMANN>(d, e, LF)) ok = false;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sF[q][pos] = LF[q];
+    }
+    __syncthreads();
+    const int i = c0 + tid;
     if (i < c1) {
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
       int k0 = d.off[i], k1 = d.off[i + 1];
-      if (k0 < 0 || k1 < k0 || k1 > d.n_csr) {
+      if (k0 < kb || k1 < k0 || k1 > kb + S) {
         ok = false;
         k1 = k0;
       }
       for (int k = k0; k < k1; ++k) {
         const int entry = d.idx[k];
-        const int e = entry >> 1;
+        const int s = k - kb;
+        const int m = s < Sm ? (int)s_map[s] : -1;
         double LF[4];
-        if (e >= e0 && e < e0 + ne) {
+        if (m >= 0) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) LF[q] = sF[q][e - e0];
-        } else if (e >= 0 && e < d.n_edges) {
-          if (!flux_of_edge<RIEMANN>(d, e, LF)) ok = false;
+          for (int q = 0; q < 4; ++q) LF[q] = sF[q][m];
         } else {
-          ok = false;
-          LF[0] = LF[1] = LF[2] = LF[3] = 0.0;
+          if (!flux_of_edge<RIEMANN>(d, entry >> 1, LF)) ok = false;
         }
         if (entry & 1) {
 #pragma unroll
@@ -213,9 +455,9 @@ __global__ __launch_bounds__(kTile) void k_flux(RunDesc one, const RunDesc* __re
 // ---------------------------------------------------------------------------
 // A0: Courant step, min over cells of R/(c + |v - w|)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kTile) void k_cfl(RunDesc d) {
-  __shared__ double smin[kTile / 64];
-  const int i = blockIdx.x * kTile + threadIdx.x;
+__global__ __launch_bounds__(256) void k_cfl(RunDesc d) {
+  __shared__ double smin[256 / 64];
+  const int i = blockIdx.x * 256 + threadIdx.x;
   double t = INFINITY;
   if (i < d.n) {
     double rho, vx, vy, p;
@@ -243,7 +485,7 @@ __global__ __launch_bounds__(kTile) void k_cfl(RunDesc d) {
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = smin[0];
-    for (int w = 1; w < kTile / 64; ++w) m = fmin(m, smin[w]);
+    for (int w = 1; w < 256 / 64; ++w) m = fmin(m, smin[w]);
     unsigned long long bits = (unsigned long long)__double_as_longlong(m);
     atomicMin(d.cfl_min, bits);
   }
@@ -310,6 +552,7 @@ RunDesc make_desc(const rich_mesh* m, const rich_state* src, const rich_state* b
   d.h = h;
   d.gamma = p->gamma; d.theta = p->theta; d.delta_v = p->delta_v; d.delta_p = p->delta_p;
   d.chi = p->chi; d.eta = p->eta;
+  d.rgm1 = 1.0 / (p->gamma - 1.0);
   d.n = (int32_t)m->n_cells;
   d.n_edges = (int32_t)m->n_edges;
   d.n_csr = (int32_t)m->n_csr;
@@ -318,18 +561,257 @@ RunDesc make_desc(const rich_mesh* m, const rich_state* src, const rich_state* b
   return d;
 }
 
+// ---------------------------------------------------------------------------
+// kernel timing: event pairs recorded around launches while enabled
+// ---------------------------------------------------------------------------
+struct ProfEntry {
+  std::string name;
+  hipEvent_t a, b;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<ProfEntry> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Profiler& profiler() {
+  static Profiler p;
+  return p;
+}
+
+// Records the start event of a kernel; returns the index to close, or -1.
+int prof_begin(const char* name, hipStream_t st) {
+  Profiler& P = profiler();
+  if (!P.on) return -1;
+  ProfEntry e{name, P.get(), P.get()};
+  if (!e.a || !e.b) return -1;
+  (void)hipEventRecord(e.a, st);
+  P.pending.push_back(e);
+  return (int)P.pending.size() - 1;
+}
+void prof_end(int k, hipStream_t st) {
+  if (k >= 0) (void)hipEventRecord(profiler().pending[k].b, st);
+}
+
 int launch_stage(const RunDesc& d, int riemann, hipStream_t st) {
-  const int n_tiles = (d.n + rich::kTile - 1) / rich::kTile;
+  constexpr int T = rich::kTile;
+  const int n_tiles = (d.n + T - 1) / T;
+  constexpr int CPB = rich::kCellThreads / rich::kLpc;
+  const int n_ctiles = (d.n + CPB - 1) / CPB;
   hipLaunchKernelGGL(rich::k_clear, dim3(1), dim3(64), 0, st, d.flag, d.cfl_min);
-  hipLaunchKernelGGL(rich::k_cell<false>, dim3(n_tiles), dim3(rich::kTile), 0, st, d,
-                     (const RunDesc*)nullptr, (const int32_t*)nullptr, 1, n_tiles);
+  int pc = prof_begin("k_cell", st);
+  hipLaunchKernelGGL((rich::k_cell<rich::kLpc, false>), dim3(n_ctiles), dim3(rich::kCellThreads),
+                     0, st, d, (const RunDesc*)nullptr, (const int32_t*)nullptr, 1, n_ctiles);
+  prof_end(pc, st);
+  int pf = prof_begin("k_flux", st);
   if (riemann == 1)
-    hipLaunchKernelGGL((rich::k_flux<1, false>), dim3(n_tiles), dim3(rich::kTile), 0, st, d,
+    hipLaunchKernelGGL((rich::k_flux<1, false>), dim3(n_tiles), dim3(T), 0, st, d,
                        (const RunDesc*)nullptr, (const int32_t*)nullptr, 1, n_tiles);
   else
-    hipLaunchKernelGGL((rich::k_flux<0, false>), dim3(n_tiles), dim3(rich::kTile), 0, st, d,
+    hipLaunchKernelGGL((rich::k_flux<0, false>), dim3(n_tiles), dim3(T), 0, st, d,
                        (const RunDesc*)nullptr, (const int32_t*)nullptr, 1, n_tiles);
+  prof_end(pf, st);
   return hip_status(hipGetLastError());
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// batch workspace:  [descriptors][plans][flags][Courant minima][records...]
+// ---------------------------------------------------------------------------
+struct BatchLayout {
+  size_t desc, plan, flags, cfl, rec, total;
+  std::vector<size_t> rec_off;
+};
+
+BatchLayout batch_layout(int32_t n, const int64_t* n_cells) {
+  BatchLayout L;
+  size_t o = 0;
+  L.desc = o;
+  o += align_up((size_t)n * sizeof(RunDesc), 256);
+  L.plan = o;
+  o += align_up((size_t)3 * (2 * (size_t)n + 1) * sizeof(int32_t), 256);
+  L.flags = o;
+  o += align_up((size_t)n * sizeof(int32_t), 256);
+  L.cfl = o;
+  o += align_up((size_t)n * sizeof(unsigned long long), 256);
+  L.rec = o;
+  L.rec_off.resize(n);
+  for (int32_t r = 0; r < n; ++r) {
+    L.rec_off[r] = o;
+    o += align_up((size_t)n_cells[r] * rich::kRecDoubles * sizeof(double), 256);
+  }
+  L.total = o;
+  return L;
+}
+
+// Pinned host staging for the descriptor uploads: a ring of buffers, each
+// reused only after the copy that last read it has completed.
+struct Staging {
+  struct Buf {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+  };
+  Buf bufs[4];
+  int next = 0;
+  void* get(size_t bytes, hipEvent_t* ev) {
+    Buf& b = bufs[next];
+    next = (next + 1) % 4;
+    if (b.done) (void)hipEventSynchronize(b.done);
+    if (b.cap < bytes) {
+      if (b.p) (void)hipHostFree(b.p);
+      b.p = nullptr;
+      b.cap = 0;
+      if (hipHostMalloc(&b.p, bytes, 0) != hipSuccess) return nullptr;
+      b.cap = bytes;
+    }
+    if (!b.done && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
+      return nullptr;
+    *ev = b.done;
+    return b.p;
+  }
+};
+Staging& staging() {
+  static Staging s;
+  return s;
+}
+
+int resident_blocks(const void* kernel, int threads) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 1024;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess ||
+      per < 1)
+    per = 1;
+  return cus * per;
+}
+
+// ---------------------------------------------------------------------------
+// step driver: device buffers owned by a rich_ctx
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  bool ensure(size_t bytes) {
+    if (bytes <= cap) return true;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return false;
+    cap = std::max<size_t>(bytes, 256);
+    return true;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+struct DevMesh {
+  DevBuf b[13];  // px py sx sy area e_i e_j e_len e_fx e_fy off idx eoff
+  int64_t n = 0, ne = 0, nc = 0;
+  double box[4] = {0, 0, 1, 1};
+  uint32_t bc = 0;
+  bool set = false;
+
+  int upload(const rich_host_mesh_view* hm, const double* bx, uint32_t bcv, hipStream_t st) {
+    const int64_t n_ = hm->n_cells, ne_ = hm->n_edges, nc_ = hm->n_csr;
+    const void* src[13] = {hm->px, hm->py, hm->sx, hm->sy, hm->area, hm->e_i, hm->e_j,
+                           hm->e_len, hm->e_fx, hm->e_fy, hm->off, hm->idx, hm->eoff};
+    const size_t bytes[13] = {8 * (size_t)n_, 8 * (size_t)n_, 8 * (size_t)n_, 8 * (size_t)n_,
+                              8 * (size_t)n_, 4 * (size_t)ne_, 4 * (size_t)ne_,
+                              8 * (size_t)ne_, 8 * (size_t)ne_, 8 * (size_t)ne_,
+                              4 * (size_t)(n_ + 1), 4 * (size_t)nc_, 4 * (size_t)(n_ + 1)};
+    for (int k = 0; k < 13; ++k) {
+      if (bytes[k] && !src[k]) return RICH_E_INVAL;
+      if (!b[k].ensure(bytes[k])) return RICH_E_NOMEM;
+      if (bytes[k] &&
+          hipMemcpyAsync(b[k].p, src[k], bytes[k], hipMemcpyHostToDevice, st) != hipSuccess)
+        return RICH_E_DEVICE;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return RICH_E_DEVICE;
+    n = n_;
+    ne = ne_;
+    nc = nc_;
+    std::memcpy(box, bx, sizeof(box));
+    bc = bcv;
+    set = true;
+    return RICH_OK;
+  }
+  void view(rich_mesh* m) const {
+    m->n_cells = n;
+    m->n_edges = ne;
+    m->n_csr = nc;
+    m->px = (const double*)b[0].p; m->py = (const double*)b[1].p;
+    m->sx = (const double*)b[2].p; m->sy = (const double*)b[3].p;
+    m->area = (const double*)b[4].p;
+    m->e_i = (const int32_t*)b[5].p; m->e_j = (const int32_t*)b[6].p;
+    m->e_len = (const double*)b[7].p; m->e_fx = (const double*)b[8].p;
+    m->e_fy = (const double*)b[9].p;
+    m->off = (const int32_t*)b[10].p; m->idx = (const int32_t*)b[11].p;
+    m->eoff = (const int32_t*)b[12].p;
+    std::memcpy(m->box, box, sizeof(box));
+    m->bc = bc;
+  }
+  void release() {
+    for (auto& x : b) x.release();
+    set = false;
+  }
+};
+
+struct rich_ctx {
+  DevMesh cur, spare;
+  DevBuf Qh, Xh, Qn, Xn, ws;
+  void* hostX = nullptr;
+  size_t hostX_cap = 0;
+};
+
+namespace {
+
+rich_state state_view(DevBuf& Q, DevBuf& X, int64_t n) {
+  rich_state s;
+  double* q = (double*)Q.p;
+  double* x = (double*)X.p;
+  s.M = q; s.Px = q + n; s.Py = q + 2 * n; s.E = q + 3 * n;
+  s.x = x; s.y = x + n;
+  s.n_cells = n;
+  return s;
+}
+
+int tessellate_into(rich_ctx* c, DevMesh& dst, const double* dx, int64_t n, const double* box,
+                    uint32_t bc, rich_tess_fn tess, rich_tess_release_fn release, void* user,
+                    hipStream_t st) {
+  const size_t bytes = 2 * (size_t)n * sizeof(double);
+  if (c->hostX_cap < bytes) {
+    if (c->hostX) (void)hipHostFree(c->hostX);
+    c->hostX = nullptr;
+    c->hostX_cap = 0;
+    if (hipHostMalloc(&c->hostX, bytes, 0) != hipSuccess) return RICH_E_NOMEM;
+    c->hostX_cap = bytes;
+  }
+  if (hipMemcpyAsync(c->hostX, dx, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return RICH_E_DEVICE;
+  const double* hx = (const double*)c->hostX;
+  rich_host_mesh_view hv;
+  std::memset(&hv, 0, sizeof(hv));
+  if (tess(user, hx, hx + n, n, box, bc, &hv) != 0) return RICH_E_MESH;
+  int rc = RICH_E_MESH;
+  if (hv.n_cells == n) rc = dst.upload(&hv, box, bc, st);
+  release(user, &hv);
+  return rc;
 }
 
 }  // namespace
@@ -386,9 +868,9 @@ int rich_cfl_dt(const rich_mesh* m, const rich_state* s, const rich_params* p, d
   if (ws_bytes < run_ws_bytes(m->n_cells)) return RICH_E_NOMEM;
   hipStream_t st = static_cast<hipStream_t>(stream);
   RunDesc d = make_desc(m, s, nullptr, nullptr, 0.0, p, static_cast<char*>(ws));
-  const int nb = (d.n + rich::kTile - 1) / rich::kTile;
+  const int nb = (d.n + 255) / 256;
   hipLaunchKernelGGL(rich::k_clear, dim3(1), dim3(64), 0, st, d.flag, d.cfl_min);
-  hipLaunchKernelGGL(rich::k_cfl, dim3(nb), dim3(rich::kTile), 0, st, d);
+  hipLaunchKernelGGL(rich::k_cfl, dim3(nb), dim3(256), 0, st, d);
   if (hipGetLastError() != hipSuccess) return RICH_E_DEVICE;
   unsigned long long bits = 0;
   if (hipStreamSynchronize(st) != hipSuccess) return RICH_E_DEVICE;
@@ -398,6 +880,241 @@ int rich_cfl_dt(const rich_mesh* m, const rich_state* s, const rich_params* p, d
   std::memcpy(&mn, &bits, sizeof(mn));
   *dt = p->cfl * mn;
   return (std::isfinite(*dt) && *dt > 0.0) ? RICH_OK : RICH_E_DOMAIN;
+}
+
+
+int rich_batch_workspace_size(int32_t n, const int64_t* n_cells, size_t* bytes) {
+  if (n <= 0 || !n_cells || !bytes) return RICH_E_INVAL;
+  for (int32_t r = 0; r < n; ++r)
+    if (n_cells[r] <= 0 || n_cells[r] > (int64_t)rich::kCellMask) return RICH_E_INVAL;
+  *bytes = batch_layout(n, n_cells).total;
+  return RICH_OK;
+}
+
+int rich_stage_batch(int32_t n, const rich_mesh* const* meshes, const rich_state* const* src,
+                     const rich_state* const* base, rich_state* const* out, const double* h,
+                     const rich_params* const* params, void* ws, size_t ws_bytes,
+                     void* stream) {
+  if (n <= 0 || !meshes || !src || !base || !out || !h || !params || !ws) return RICH_E_INVAL;
+  std::vector<int64_t> nc(n);
+  for (int32_t r = 0; r < n; ++r) {
+    const rich_mesh* m = meshes[r];
+    if (!valid_mesh(m) || !valid_params(params[r])) return RICH_E_INVAL;
+    const int64_t cnt = m->n_cells;
+    if (!valid_state(src[r], cnt, false) || !valid_state(base[r], cnt, true) ||
+        !valid_state(out[r], cnt, true))
+      return RICH_E_INVAL;
+    if (!std::isfinite(h[r]) || h[r] < 0.0) return RICH_E_INVAL;
+    if (out[r]->M == src[r]->M || out[r]->M == base[r]->M || out[r]->x == base[r]->x)
+      return RICH_E_INVAL;
+    nc[r] = cnt;
+  }
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return RICH_E_NOMEM;
+  BatchLayout L = batch_layout(n, nc.data());
+  if (ws_bytes < L.total) return RICH_E_NOMEM;
+  char* w = static_cast<char*>(ws);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  // descriptors and the three launch plans (cells; fluxes HLLC; fluxes exact)
+  constexpr int CPB = rich::kCellThreads / rich::kLpc;
+  std::vector<RunDesc> descs(n);
+  std::vector<int32_t> plans(3 * (2 * (size_t)n + 1), 0);
+  int32_t* pc = plans.data();
+  int32_t* pf0 = pc + (2 * n + 1);
+  int32_t* pf1 = pf0 + (2 * n + 1);
+  std::vector<int32_t> g0, g1;
+  for (int32_t r = 0; r < n; ++r) (params[r]->riemann == 1 ? g1 : g0).push_back(r);
+  int64_t tc = 0;
+  for (int32_t r = 0; r < n; ++r) {
+    RunDesc d = make_desc(meshes[r], src[r], base[r], out[r], h[r], params[r], w);
+    d.flag = reinterpret_cast<int32_t*>(w + L.flags) + r;
+    d.cfl_min = reinterpret_cast<unsigned long long*>(w + L.cfl) + r;
+    d.rec = reinterpret_cast<double*>(w + L.rec_off[r]);
+    descs[r] = d;
+    pc[r] = (int32_t)tc;
+    pc[n + 1 + r] = r;
+    tc += (nc[r] + CPB - 1) / CPB;
+  }
+  pc[n] = (int32_t)tc;
+  int64_t tf[2] = {0, 0};
+  int32_t* pf[2] = {pf0, pf1};
+  std::vector<int32_t>* grp[2] = {&g0, &g1};
+  for (int k = 0; k < 2; ++k) {
+    const int ng = (int)grp[k]->size();
+    for (int q = 0; q < ng; ++q) {
+      const int32_t r = (*grp[k])[q];
+      pf[k][q] = (int32_t)tf[k];
+      pf[k][ng + 1 + q] = r;
+      tf[k] += (nc[r] + rich::kTile - 1) / rich::kTile;
+    }
+    pf[k][ng] = (int32_t)tf[k];
+  }
+  if (tc > INT32_MAX / 2 || tf[0] > INT32_MAX / 2 || tf[1] > INT32_MAX / 2) return RICH_E_INVAL;
+
+  const size_t db = (size_t)n * sizeof(RunDesc), pb = plans.size() * sizeof(int32_t);
+  hipEvent_t ev = nullptr;
+  char* host = static_cast<char*>(staging().get(db + pb, &ev));
+  if (!host) return RICH_E_NOMEM;
+  std::memcpy(host, descs.data(), db);
+  std::memcpy(host + db, plans.data(), pb);
+  if (hipMemcpyAsync(w + L.desc, host, db, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(w + L.plan, host + db, pb, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipEventRecord(ev, st) != hipSuccess)
+    return RICH_E_DEVICE;
+
+  const RunDesc* dd = reinterpret_cast<const RunDesc*>(w + L.desc);
+  const int32_t* dplan = reinterpret_cast<const int32_t*>(w + L.plan);
+  const int32_t* dpc = dplan;
+  const int32_t* dpf0 = dplan + (2 * n + 1);
+  const int32_t* dpf1 = dpf0 + (2 * n + 1);
+  RunDesc dummy;
+  std::memset(&dummy, 0, sizeof(dummy));
+  hipLaunchKernelGGL(rich::k_clear_batch, dim3((n + 255) / 256), dim3(256), 0, st, dd, n);
+  static int cell_grid = resident_blocks(
+      reinterpret_cast<const void*>(&rich::k_cell<rich::kLpc, true>), rich::kCellThreads);
+  static int flux0_grid = resident_blocks(
+      reinterpret_cast<const void*>(&rich::k_flux<0, true>), rich::kTile);
+  static int flux1_grid = resident_blocks(
+      reinterpret_cast<const void*>(&rich::k_flux<1, true>), rich::kTile);
+  int pcl = prof_begin("k_cell", st);
+  hipLaunchKernelGGL((rich::k_cell<rich::kLpc, true>), dim3((int)std::min<int64_t>(tc, cell_grid)),
+                     dim3(rich::kCellThreads), 0, st, dummy, dd, dpc, n, (int)tc);
+  prof_end(pcl, st);
+  int pfl = prof_begin("k_flux", st);
+  if (!g0.empty())
+    hipLaunchKernelGGL((rich::k_flux<0, true>), dim3((int)std::min<int64_t>(tf[0], flux0_grid)),
+                       dim3(rich::kTile), 0, st, dummy, dd, dpf0, (int)g0.size(), (int)tf[0]);
+  if (!g1.empty())
+    hipLaunchKernelGGL((rich::k_flux<1, true>), dim3((int)std::min<int64_t>(tf[1], flux1_grid)),
+                       dim3(rich::kTile), 0, st, dummy, dd, dpf1, (int)g1.size(), (int)tf[1]);
+  prof_end(pfl, st);
+  return hip_status(hipGetLastError());
+}
+
+int rich_batch_flags(int32_t n, void* ws, void* stream, int32_t* flags) {
+  if (n <= 0 || !ws || !flags) return RICH_E_INVAL;
+  std::vector<int64_t> one(n, 1);
+  BatchLayout L = batch_layout(n, one.data());
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return RICH_E_DEVICE;
+  if (hipMemcpy(flags, static_cast<char*>(ws) + L.flags, (size_t)n * sizeof(int32_t),
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return RICH_E_DEVICE;
+  return RICH_OK;
+}
+
+
+int rich_ctx_create(rich_ctx** ctx) {
+  if (!ctx) return RICH_E_INVAL;
+  try {
+    *ctx = new rich_ctx;
+  } catch (...) {
+    return RICH_E_NOMEM;
+  }
+  return RICH_OK;
+}
+
+void rich_ctx_destroy(rich_ctx* ctx) {
+  if (!ctx) return;
+  ctx->cur.release();
+  ctx->spare.release();
+  ctx->Qh.release(); ctx->Xh.release(); ctx->Qn.release(); ctx->Xn.release();
+  ctx->ws.release();
+  if (ctx->hostX) (void)hipHostFree(ctx->hostX);
+  delete ctx;
+}
+
+int rich_ctx_set_mesh(rich_ctx* ctx, const rich_host_mesh_view* hm, const double box[4],
+                      uint32_t bc, void* stream) {
+  if (!ctx || !hm || !box || hm->n_cells <= 0 || hm->n_cells > (int64_t)rich::kCellMask ||
+      hm->n_edges < 0 || hm->n_csr < 0)
+    return RICH_E_INVAL;
+  return ctx->cur.upload(hm, box, bc, static_cast<hipStream_t>(stream));
+}
+
+int rich_ctx_mesh(rich_ctx* ctx, rich_mesh* out) {
+  if (!ctx || !out || !ctx->cur.set) return RICH_E_INVAL;
+  ctx->cur.view(out);
+  return RICH_OK;
+}
+
+int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
+              rich_tess_fn tess, rich_tess_release_fn release, void* tess_user, void* stream) {
+  if (!ctx || !state || !valid_params(p) || !ctx->cur.set) return RICH_E_INVAL;
+  if (!std::isfinite(dt) || !(dt > 0.0)) return RICH_E_INVAL;
+  if (p->motion && (!tess || !release)) return RICH_E_INVAL;
+  const int64_t n = ctx->cur.n;
+  if (!valid_state(state, n, true)) return RICH_E_INVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  size_t wsb = run_ws_bytes(n);
+  if (!ctx->Qh.ensure(32 * (size_t)n) || !ctx->Xh.ensure(16 * (size_t)n) ||
+      !ctx->Qn.ensure(32 * (size_t)n) || !ctx->Xn.ensure(16 * (size_t)n) ||
+      !ctx->ws.ensure(wsb))
+    return RICH_E_NOMEM;
+  rich_state half = state_view(ctx->Qh, ctx->Xh, n);
+  rich_state next = state_view(ctx->Qn, ctx->Xn, n);
+  rich_mesh m;
+  ctx->cur.view(&m);
+  int rc = rich_stage(&m, state, state, &half, 0.5 * dt, p, ctx->ws.p, ctx->ws.cap, stream);
+  if (rc) return rc;
+  int32_t flags = 0;
+  if ((rc = rich_stage_flags(ctx->ws.p, stream, &flags))) return rc;
+  if (flags) return RICH_E_DOMAIN;
+  rich_mesh mh = m;
+  if (p->motion) {
+    rc = tessellate_into(ctx, ctx->spare, half.x, n, ctx->cur.box, ctx->cur.bc, tess, release,
+                         tess_user, st);
+    if (rc) return rc;
+    ctx->spare.view(&mh);
+  }
+  rc = rich_stage(&mh, &half, state, &next, dt, p, ctx->ws.p, ctx->ws.cap, stream);
+  if (rc) return rc;
+  if ((rc = rich_stage_flags(ctx->ws.p, stream, &flags))) return rc;
+  if (flags) return RICH_E_DOMAIN;
+  if (p->motion) {
+    // the new mesh goes into the spare buffers, which then become current
+    rc = tessellate_into(ctx, ctx->spare, next.x, n, ctx->cur.box, ctx->cur.bc, tess, release,
+                         tess_user, st);
+    if (rc) return rc;
+    std::swap(ctx->cur, ctx->spare);
+  }
+  // commit
+  const double* sq[6] = {next.M, next.Px, next.Py, next.E, next.x, next.y};
+  double* dq[6] = {state->M, state->Px, state->Py, state->E, state->x, state->y};
+  for (int k = 0; k < 6; ++k)
+    if (hipMemcpyAsync(dq[k], sq[k], 8 * (size_t)n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return RICH_E_DEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return RICH_E_DEVICE;
+  return RICH_OK;
+}
+
+int rich_profile_enable(int on) {
+  profiler().on = on != 0;
+  return RICH_OK;
+}
+
+int rich_profile_read(const char* kernel, double* total_ms, int64_t* launches) {
+  if (!kernel || !total_ms || !launches) return RICH_E_INVAL;
+  Profiler& P = profiler();
+  double sum = 0.0;
+  int64_t cnt = 0;
+  std::vector<ProfEntry> keep;
+  for (auto& e : P.pending) {
+    if (e.name != kernel) {
+      keep.push_back(e);
+      continue;
+    }
+    if (hipEventSynchronize(e.b) != hipSuccess) return RICH_E_DEVICE;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) return RICH_E_DEVICE;
+    sum += ms;
+    ++cnt;
+    P.pool.push_back(e.a);
+    P.pool.push_back(e.b);
+  }
+  P.pending.swap(keep);
+  *total_ms = sum;
+  *launches = cnt;
+  return RICH_OK;
 }
 
 const char* rich_strerror(int status) {

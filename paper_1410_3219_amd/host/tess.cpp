@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -680,8 +681,10 @@ int build_mesh(const double* pxin, const double* pyin, int64_t n,
   Triangulation T;
   std::vector<double> ccx, ccy;
   std::vector<int32_t> vtri;
+  auto clock0 = std::chrono::steady_clock::now();
   st = triangulate(px.data(), py.data(), n, box, bc, nthreads, T, ccx, ccy, vtri);
   if (st) return st;
+  auto clock1 = std::chrono::steady_clock::now();
   const Delaunay& D = T.dt;
 
   // 1. fan sizes
@@ -864,6 +867,9 @@ int build_mesh(const double* pxin, const double* pyin, int64_t n,
   out->band = T.band;
   out->n_rebuilds = T.rebuilds;
   out->n_exact = D.n_exact;
+  auto clock2 = std::chrono::steady_clock::now();
+  out->t_triangulate = std::chrono::duration<double>(clock1 - clock0).count();
+  out->t_voronoi = std::chrono::duration<double>(clock2 - clock1).count();
   if (!out->px || !out->py || !out->sx || !out->sy || !out->area || !out->e_i ||
       !out->e_j || !out->e_len || !out->e_fx || !out->e_fy || !out->off ||
       !out->idx || !out->eoff) {
@@ -1007,6 +1013,71 @@ int rich_tess_lloyd(double* px, double* py, int64_t n, const double box[4],
     rich_tess_free(&m);
   }
   return RICH_TESS_OK;
+}
+
+struct rich_tess_ctx {
+  int32_t n_threads = 0;
+  std::vector<rich_mesh_host*> out;
+};
+
+rich_tess_ctx* rich_tess_ctx_create(int32_t n_threads) {
+  try {
+    rich_tess_ctx* c = new rich_tess_ctx;
+    c->n_threads = n_threads;
+    return c;
+  } catch (...) {
+    return nullptr;
+  }
+}
+
+void rich_tess_ctx_destroy(rich_tess_ctx* ctx) {
+  if (!ctx) return;
+  for (rich_mesh_host* m : ctx->out) {
+    rich_tess_free(m);
+    delete m;
+  }
+  delete ctx;
+}
+
+int rich_tess_callback(void* user, const double* px, const double* py, int64_t n,
+                       const double box[4], uint32_t bc, rich_tess_view* v) {
+  rich_tess_ctx* ctx = static_cast<rich_tess_ctx*>(user);
+  if (!ctx || !v) return RICH_TESS_E_INVAL;
+  rich_mesh_host* m = nullptr;
+  try {
+    m = new rich_mesh_host;
+    ctx->out.push_back(m);
+  } catch (...) {
+    delete m;
+    return RICH_TESS_E_NOMEM;
+  }
+  int st = rich_tess_build(px, py, n, box, bc, ctx->n_threads, m);
+  if (st) {
+    ctx->out.pop_back();
+    delete m;
+    return st;
+  }
+  v->n_cells = m->n_cells;
+  v->n_edges = m->n_edges;
+  v->n_csr = m->n_csr;
+  v->px = m->px; v->py = m->py; v->sx = m->sx; v->sy = m->sy; v->area = m->area;
+  v->e_i = m->e_i; v->e_j = m->e_j;
+  v->e_len = m->e_len; v->e_fx = m->e_fx; v->e_fy = m->e_fy;
+  v->off = m->off; v->idx = m->idx; v->eoff = m->eoff;
+  return RICH_TESS_OK;
+}
+
+void rich_tess_release(void* user, rich_tess_view* v) {
+  rich_tess_ctx* ctx = static_cast<rich_tess_ctx*>(user);
+  if (!ctx || !v) return;
+  for (size_t k = 0; k < ctx->out.size(); ++k)
+    if (ctx->out[k]->px == v->px) {
+      rich_tess_free(ctx->out[k]);
+      delete ctx->out[k];
+      ctx->out.erase(ctx->out.begin() + k);
+      break;
+    }
+  std::memset(v, 0, sizeof(*v));
 }
 
 }  // extern "C"

@@ -105,7 +105,10 @@ def lib():
         L.rich_cfl_dt.argtypes = [mp, sp, pp, _dp, _vp, C.c_size_t, _vp]
         L.rich_strerror.argtypes = [C.c_int]
         L.rich_strerror.restype = C.c_char_p
-        for f in ("rich_workspace_size", "rich_stage", "rich_stage_flags", "rich_cfl_dt"):
+        L.rich_profile_enable.argtypes = [C.c_int]
+        L.rich_profile_read.argtypes = [C.c_char_p, _dp, C.POINTER(C.c_int64)]
+        for f in ("rich_workspace_size", "rich_stage", "rich_stage_flags", "rich_cfl_dt",
+                  "rich_profile_enable", "rich_profile_read"):
             getattr(L, f).restype = C.c_int
         if hasattr(L, "rich_stage_batch"):
             L.rich_batch_workspace_size.argtypes = [C.c_int32, C.POINTER(C.c_int64),
@@ -122,7 +125,7 @@ def lib():
             L.rich_ctx_destroy.restype = None
             L.rich_ctx_set_mesh.argtypes = [_vp, C.POINTER(HostMeshView), _dp, C.c_uint32, _vp]
             L.rich_ctx_mesh.argtypes = [_vp, mp]
-            L.rich_step.argtypes = [_vp, sp, C.c_double, pp, TESS_FN, RELEASE_FN, _vp, _vp]
+            L.rich_step.argtypes = [_vp, sp, C.c_double, pp, _vp, _vp, _vp, _vp]
             for f in ("rich_ctx_create", "rich_ctx_set_mesh", "rich_ctx_mesh", "rich_step"):
                 getattr(L, f).restype = C.c_int
         _lib = L
@@ -249,3 +252,132 @@ def rich_cfl_dt(mesh: DeviceMesh, state: DeviceState, params: Params, ws, stream
                            _stream_ptr(stream))
     _check(st, "rich_cfl_dt")
     return dt.value
+
+
+def rich_profile_enable(on=True):
+    _check(lib().rich_profile_enable(1 if on else 0), "rich_profile_enable")
+
+
+def rich_profile_read(kernel):
+    """(total milliseconds, launches) of `kernel` since the last read."""
+    ms, n = C.c_double(0.0), C.c_int64(0)
+    _check(lib().rich_profile_read(kernel.encode(), C.byref(ms), C.byref(n)),
+           "rich_profile_read")
+    return ms.value, n.value
+
+
+# ---------------------------------------------------------------------------
+# batched stage
+# ---------------------------------------------------------------------------
+def rich_batch_workspace_size(n_cells):
+    arr = (C.c_int64 * len(n_cells))(*[int(x) for x in n_cells])
+    b = C.c_size_t(0)
+    _check(lib().rich_batch_workspace_size(len(n_cells), arr, C.byref(b)),
+           "rich_batch_workspace_size")
+    return int(b.value)
+
+
+def batch_workspace(n_cells, device="cuda"):
+    import torch
+    return torch.empty(rich_batch_workspace_size(n_cells), dtype=torch.uint8, device=device)
+
+
+def rich_stage_batch(meshes, srcs, bases, outs, hs, params, ws, stream=None):
+    """One stage of len(meshes) independent runs, one launch per kernel phase."""
+    n = len(meshes)
+    mc = [m.c() for m in meshes]
+    sc, bc_, oc = [x.c() for x in srcs], [x.c() for x in bases], [x.c() for x in outs]
+    pc = [p.c() for p in params]
+    mp = (C.POINTER(RichMesh) * n)(*[C.pointer(x) for x in mc])
+    spp = (C.POINTER(RichState) * n)(*[C.pointer(x) for x in sc])
+    bpp = (C.POINTER(RichState) * n)(*[C.pointer(x) for x in bc_])
+    opp = (C.POINTER(RichState) * n)(*[C.pointer(x) for x in oc])
+    hh = (C.c_double * n)(*[float(h) for h in hs])
+    ppp = (C.POINTER(RichParams) * n)(*[C.pointer(x) for x in pc])
+    st = lib().rich_stage_batch(n, mp, spp, bpp, opp, hh, ppp, C.c_void_p(ws.data_ptr()),
+                                ws.numel(), _stream_ptr(stream))
+    _check(st, "rich_stage_batch")
+
+
+def rich_batch_flags(n, ws, stream=None):
+    f = (C.c_int32 * n)()
+    _check(lib().rich_batch_flags(n, C.c_void_p(ws.data_ptr()), _stream_ptr(stream), f),
+           "rich_batch_flags")
+    return list(f)
+
+
+# ---------------------------------------------------------------------------
+# time-centred step driver
+# ---------------------------------------------------------------------------
+def _host_view(hm):
+    keep = {k: np.ascontiguousarray(getattr(hm, k)) for k in hm.ARRAYS}
+    dp = lambda a: a.ctypes.data_as(_dp)   # noqa: E731
+    ip = lambda a: a.ctypes.data_as(_ip)   # noqa: E731
+    v = HostMeshView(hm.n_cells, hm.n_edges, hm.n_csr,
+                     dp(keep["px"]), dp(keep["py"]), dp(keep["sx"]), dp(keep["sy"]),
+                     dp(keep["area"]), ip(keep["e_i"]), ip(keep["e_j"]), dp(keep["e_len"]),
+                     dp(keep["e_fx"]), dp(keep["e_fy"]), ip(keep["off"]), ip(keep["idx"]),
+                     ip(keep["eoff"]))
+    return v, keep
+
+
+class CtxMesh:
+    """Device view of a step driver's current mesh (borrowed)."""
+
+    def __init__(self, cm: RichMesh):
+        self._c = cm
+        self.n_cells, self.n_edges, self.n_csr = cm.n_cells, cm.n_edges, cm.n_csr
+
+    def c(self):
+        return self._c
+
+
+class RichCtx:
+    """rich_ctx: device buffers of one run's time-centred step driver.  The
+    host tessellation stage is called through its C adapter, with no Python
+    in between."""
+
+    def __init__(self, n_threads=0):
+        from . import tess
+        self.h = C.c_void_p()
+        _check(lib().rich_ctx_create(C.byref(self.h)), "rich_ctx_create")
+        TL = tess.lib()
+        TL.rich_tess_ctx_create.argtypes = [C.c_int32]
+        TL.rich_tess_ctx_create.restype = C.c_void_p
+        TL.rich_tess_ctx_destroy.argtypes = [C.c_void_p]
+        TL.rich_tess_ctx_destroy.restype = None
+        self._tl = TL
+        self.tess_user = C.c_void_p(TL.rich_tess_ctx_create(int(n_threads)))
+        self.tess_fn = C.cast(TL.rich_tess_callback, C.c_void_p)
+        self.release_fn = C.cast(TL.rich_tess_release, C.c_void_p)
+
+    def close(self):
+        if self.h:
+            lib().rich_ctx_destroy(self.h)
+            self.h = C.c_void_p()
+        if self.tess_user:
+            self._tl.rich_tess_ctx_destroy(self.tess_user)
+            self.tess_user = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_mesh(self, hm, stream=None):
+        v, keep = _host_view(hm)
+        box = (C.c_double * 4)(*hm.box)
+        _check(lib().rich_ctx_set_mesh(self.h, C.byref(v), box, int(hm.bc),
+                                       _stream_ptr(stream)), "rich_ctx_set_mesh")
+        del keep
+
+    def mesh(self):
+        cm = RichMesh()
+        _check(lib().rich_ctx_mesh(self.h, C.byref(cm)), "rich_ctx_mesh")
+        return CtxMesh(cm)
+
+    def step(self, state: DeviceState, dt, params: Params, stream=None):
+        st = lib().rich_step(self.h, C.byref(state.c()), float(dt), C.byref(params.c()),
+                             self.tess_fn, self.release_fn, self.tess_user, _stream_ptr(stream))
+        _check(st, "rich_step")

@@ -35,6 +35,7 @@ class MeshHostC(C.Structure):
         ("box", C.c_double * 4), ("bc", C.c_uint32),
         ("n_ghosts", C.c_int64), ("n_dropped", C.c_int64),
         ("band", C.c_double), ("n_rebuilds", C.c_int32), ("n_exact", C.c_int64),
+        ("t_triangulate", C.c_double), ("t_voronoi", C.c_double),
     ]
 
 
@@ -155,7 +156,8 @@ def mesh_from_c(m: MeshHostC) -> HostMesh:
         eoff=_copy(m.eoff, n + 1, i4),
         box=tuple(m.box), bc=int(m.bc),
         diag=dict(n_ghosts=m.n_ghosts, n_dropped=m.n_dropped, band=m.band,
-                  n_rebuilds=m.n_rebuilds, n_exact=m.n_exact))
+                  n_rebuilds=m.n_rebuilds, n_exact=m.n_exact,
+                  t_triangulate=m.t_triangulate, t_voronoi=m.t_voronoi))
 
 
 def rich_tess_build(px, py, box, bc, n_threads=0) -> HostMesh:
