@@ -58,6 +58,165 @@ def algorithmic_bytes(m, pass2):
     return b
 
 
+def _pmc_per_kernel(d):
+    """Mean counter value per dispatch, by kernel name (rocprofv3 csv)."""
+    import csv
+    f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    acc = {}
+    for row in csv.DictReader(open(f[0])):
+        name = row["Kernel_Name"]
+        key = ("k_cell" if "k_cell" in name else "k_flux" if "k_flux" in name else
+               "copy" if "copyBuffer" in name else None)
+        if key is None:
+            continue
+        a = acc.setdefault((key, row["Counter_Name"]), {})
+        a[row["Dispatch_Id"]] = a.get(row["Dispatch_Id"], 0.0) + float(row["Counter_Value"])
+    # the calibration copy is the largest copy dispatch
+    return {k: max(v.values()) if k[0] == "copy" else sum(v.values()) / len(v)
+            for k, v in acc.items()}
+
+
+TRAFFIC_HEADER = """\
+# HBM traffic per launch of k_cell and k_flux, workload '{w}', from two counter runs
+# on one MI355X (program directly after --, from /tmp with TMPDIR=/tmp):
+#   timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/{fd} -o p \\
+#     -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --copy-probe-mib {mib}
+#   timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <repo>/{wd} -o p \\
+#     -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --copy-probe-mib {mib}
+# summarised with:
+#   python bench.py --summarize-pmc {fd} {wd} --copy-probe-mib {mib}
+# Each counter (KiB per dispatch) is scaled by the factor that makes it read the known
+# size of a {mib} MiB device-to-device copy (copyBuffer) run after a 1 GiB cache flush.
+# source_hash is a hash of the kernel sources the counters were taken on.
+"""
+
+
+def read_traffic(workload):
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    lines = [ln for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    return json.loads(lines[-1]) if lines else None
+
+
+def summarize_pmc(args):
+    """HBM bytes per launch of k_cell and k_flux from FETCH_SIZE / WRITE_SIZE
+    (KiB per dispatch), each scaled by the factor that makes the same counter
+    read the known size of the calibration copy."""
+    fd, wd = args.summarize_pmc
+    fetch, write = _pmc_per_kernel(fd), _pmc_per_kernel(wd)
+    nbytes = args.copy_probe_mib << 20
+    cf = nbytes / (fetch[("copy", "FETCH_SIZE")] * 1024.0)
+    cw = nbytes / (write[("copy", "WRITE_SIZE")] * 1024.0)
+    out = {"source_hash": kernel_source_hash(), "copy_bytes": nbytes,
+           "fetch_scale": cf, "write_scale": cw, "kernels": {}}
+    tot = 0.0
+    for k in ("k_cell", "k_flux"):
+        fb = fetch[(k, "FETCH_SIZE")] * 1024.0 * cf
+        wb = write[(k, "WRITE_SIZE")] * 1024.0 * cw
+        out["kernels"][k] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb}
+        tot += fb + wb
+    out["bytes_per_stage"] = tot
+    out["bytes_per_step"] = 2 * tot
+    P, _, make_state = make_problem(args.workload, args.k)
+    out["n_cells"] = P.n
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.txt")
+    with open(path, "w") as f:
+        f.write(TRAFFIC_HEADER.format(w=args.workload, mib=args.copy_probe_mib,
+                                      fd=fd, wd=wd))
+        f.write(json.dumps(out) + "\n")
+    print(json.dumps(out))
+
+
+def bench_batch(args, R, T, log):
+    """Many independent shock-tube runs of uneven sizes (N log-uniform in
+    [1024, 65536], interface angle, gamma and rounding strength drawn per
+    run): one time-centred step of every run, either as batched launches
+    (rich_stage_batch: one launch per kernel phase for all runs) or as
+    separate per-run launches.  Meshes of step 0 come from the host stage
+    (timed apart); the timed step is repeated from the same start."""
+    import numpy as np
+    import torch
+    from paper_1410_3219_amd import inputs as I
+    specs = I.batch_runs(args.batch_runs)
+    runs = []
+    t0 = time.time()
+    for sp in specs:
+        P = I.sod(k=sp["side"], seed=sp["seed"], angle=sp["angle"], gamma=sp["gamma"])
+        hm = T.rich_tess_build(P.px, P.py, P.box, P.bc, args.threads)
+        prm = R.Params(gamma=sp["gamma"], chi=sp["chi"])
+        dm = R.DeviceMesh.from_host(hm)
+        s0 = R.DeviceState.from_host(P.state(hm.area), np.stack([hm.px, hm.py]))
+        runs.append(dict(hm=hm, dm=dm, s0=s0, half=R.DeviceState.empty_like(s0),
+                         out=R.DeviceState.empty_like(s0), p=prm))
+    total = sum(r["hm"].n_cells for r in runs)
+    # stage 1 of every run once (per-run calls) to get the half-step points
+    ws1 = R.workspace(max(r["hm"].n_cells for r in runs))
+    for r in runs:
+        r["dt"] = R.rich_cfl_dt(r["dm"], r["s0"], r["p"], ws1)
+        R.rich_stage(r["dm"], r["s0"], r["s0"], r["half"], 0.5 * r["dt"], r["p"], ws1)
+        xh = r["half"].X.cpu().numpy()
+        r["dmh"] = R.DeviceMesh.from_host(T.rich_tess_build(xh[0], xh[1], r["hm"].box,
+                                                            r["hm"].bc, args.threads))
+    log(f"[bench] batch setup: {len(runs)} runs, {total} cells ({time.time() - t0:.1f}s)")
+    wsb = R.batch_workspace([r["hm"].n_cells for r in runs])
+
+    def batched():
+        R.rich_stage_batch([r["dm"] for r in runs], [r["s0"] for r in runs],
+                           [r["s0"] for r in runs], [r["half"] for r in runs],
+                           [0.5 * r["dt"] for r in runs], [r["p"] for r in runs], wsb)
+        R.rich_stage_batch([r["dmh"] for r in runs], [r["half"] for r in runs],
+                           [r["s0"] for r in runs], [r["out"] for r in runs],
+                           [r["dt"] for r in runs], [r["p"] for r in runs], wsb)
+
+    def separate():
+        for r in runs:
+            R.rich_stage(r["dm"], r["s0"], r["s0"], r["half"], 0.5 * r["dt"], r["p"], ws1)
+        for r in runs:
+            R.rich_stage(r["dmh"], r["half"], r["s0"], r["out"], r["dt"], r["p"], ws1)
+
+    res = {}
+    for name, fn in (("batched", batched), ("per_run_launches", separate)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"ms_per_step": ms, "cell_updates_per_s": total / (ms / 1e3)}
+    flags = R.rich_batch_flags(len(runs), wsb)
+    return {"runs": len(runs), "cells": total, "flags_ok": not any(flags),
+            "batched": res["batched"], "per_run_launches": res["per_run_launches"],
+            "batched_over_per_run": res["batched"]["cell_updates_per_s"] /
+            res["per_run_launches"]["cell_updates_per_s"]}
+
+
+def bench_serve(args, R, log):
+    """Continuous-batching serving loop (paper_1410_3219_amd.serve): Poisson
+    step requests, sessions of 8 steps on meshes of 4k-1M cells (log-uniform,
+    shock tube / point explosion), static mesh, HBM-budget admission."""
+    import math
+    from paper_1410_3219_amd import inputs as I
+    from paper_1410_3219_amd import serve as S
+    s = I.Stream(21)
+    u = s.uniform(8)
+    sizes = [int(round(math.exp(math.log(4096) + x * (math.log(1 << 20) - math.log(4096)))))
+             for x in u]
+    kinds = ["sod" if k % 2 == 0 else "sedov" for k in range(len(sizes))]
+    t0 = time.time()
+    tpl = S.build_templates(sizes, kinds, n_threads=args.threads)
+    log(f"[bench] serving templates {[t.n for t in tpl]} ({time.time() - t0:.1f}s)")
+    res, srv = S.run(tpl, rate=args.serve_rate, duration=args.serve_seconds, log=log)
+    return res
+
+
 def make_problem(name, k):
     from paper_1410_3219_amd import inputs as I
     if name == "wave":
@@ -86,8 +245,21 @@ def main():
     ap.add_argument("--k", type=int, default=0, help="lattice side (default per workload)")
     ap.add_argument("--riemann", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and served measurements")
+    ap.add_argument("--batch-runs", type=int, default=256)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--threads", type=int, default=0, help="host tessellation threads")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run a device-to-device copy of this size first (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
+                         "script with --copy-probe-mib into profiles/traffic_<workload>.json")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -126,6 +298,18 @@ def main():
         torch.cuda.synchronize()
         h2d_times.append(time.time() - t)
         return dm
+
+    if args.copy_probe_mib:
+        # calibration copy of a known size; the source is evicted from the
+        # last-level cache first by streaming through another buffer
+        nbytes = args.copy_probe_mib << 20
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        flush = torch.empty((1 << 30) // 8, dtype=torch.float64, device=dev).fill_(2.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b, flush
 
     # ---------------- live chain: GPU stages + host tessellation -----------
     hm0 = tessellate(P.px, P.py)
@@ -167,9 +351,15 @@ def main():
     # ---------------- timed replay, all inputs resident in HBM -------------
     stream = torch.cuda.current_stream()
 
+    dt_mismatch = []
+
     def run_step(s, a, hbuf, b):
-        R.rich_stage(meshes[s], a, a, hbuf, 0.5 * dts[s], params, ws)
-        R.rich_stage(halves[s], hbuf, a, b, dts[s], params, ws)
+        # A0 (Courant step, synchronises for the host-side dt), stage 1, stage 2
+        dt = R.rich_cfl_dt(meshes[s], a, params, ws)
+        if dt != dts[s]:
+            dt_mismatch.append((s, dt, dts[s]))
+        R.rich_stage(meshes[s], a, a, hbuf, 0.5 * dt, params, ws)
+        R.rich_stage(halves[s], hbuf, a, b, dt, params, ws)
 
     cur = R.DeviceState(init.Q.clone(), init.X.clone())
     nxt = R.DeviceState.empty_like(cur)
@@ -193,7 +383,8 @@ def main():
     ms_total = ev0.elapsed_time(ev1)
     kern = {k_: R.rich_profile_read(k_) for k_ in ("k_cell", "k_flux")}
     flags = R.rich_stage_flags(ws)
-    replay_ok = bool(torch.equal(cur.Q, live_final[0]) and torch.equal(cur.X, live_final[1]))
+    replay_ok = bool(torch.equal(cur.Q, live_final[0]) and torch.equal(cur.X, live_final[1])
+                     and not dt_mismatch)
     log(f"[bench] timed {K} steps: {ms_total:.3f} ms, flags={flags}, replay bitwise={replay_ok}")
 
     ms_per_step = ms_total / K
@@ -203,11 +394,9 @@ def main():
     stage_ms = (kern["k_cell"][0] + kern["k_flux"][0]) / max(1, kern["k_cell"][1]) * 2
     achieved = bytes_step / (stage_ms / 1e3) / 1e9
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
-    if os.path.exists(tfile):
-        tj = json.load(open(tfile))
-        if tj.get("source_hash") == kernel_source_hash() and tj.get("n_cells") == n:
-            traffic = tj.get("bytes_per_step")
+    tj = read_traffic(args.workload)
+    if tj and tj.get("source_hash") == kernel_source_hash() and tj.get("n_cells") == n:
+        traffic = tj.get("bytes_per_step")
 
     out = {
         "metric": METRIC,
@@ -251,6 +440,10 @@ def main():
                 float(np.mean(tess_times)) + float(np.mean(h2d_times))),
         },
     }
+
+    if not args.no_extras:
+        out["batched"] = bench_batch(args, R, T, log)
+        out["served"] = bench_serve(args, R, log)
 
     # ---------------- CPU baseline: the oracle on one step -----------------
     if not args.no_cpu_baseline:

@@ -74,7 +74,9 @@ extern "C" {
  *                      polygon counter-clockwise.  Wall edges appear once.
  *   eoff  [n_cells+1]  eoff[c] = first edge with e_i >= c
  * Edges shorter than 1e-12 * (R_i + R_j)/2 (R = sqrt(area/pi)), which come
- * from co-circular point sets, are dropped.
+ * from co-circular point sets, are dropped, and so is every edge between a
+ * cell and the mirror image of another cell (two points and their mirrors
+ * across one wall are co-circular, so such an edge has zero length exactly).
  */
 typedef struct rich_mesh_host {
   int64_t n_cells, n_edges, n_csr;

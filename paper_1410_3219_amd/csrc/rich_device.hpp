@@ -79,51 +79,47 @@ __device__ __forceinline__ void mirror_vec(int code, double vx, double vy, doubl
   my = (code == 11 || code == 12) ? -vy : vy;
 }
 
-// The neighbour across one CSR entry of cell i, in i's frame.  Indices read
-// from the mesh are range-checked; a bad index sets *bad and points at i.
-struct Nb {
+// The neighbour across one CSR entry of cell i: the edge's data and the
+// neighbour's index and image shift.  Indices read from the mesh are
+// range-checked.
+struct NbE {
   int j, wall;
-  double rx, ry, fx, fy, L;
+  double shx, shy, fx, fy, L;
 };
 
-__device__ __forceinline__ Nb nb_view(const RunDesc& d, int i, double rix, double riy,
-                                      int entry, bool& bad) {
-  Nb v;
+__device__ __forceinline__ NbE nb_edge(const RunDesc& d, int i, int entry, bool& bad) {
+  NbE v;
   int e = entry >> 1;
-  int side = entry & 1;
+  const int side = entry & 1;
   if (e < 0 || e >= d.n_edges) {
     bad = true;
     e = 0;
   }
-  uint32_t ej = (uint32_t)d.e_j[e];
-  int code = (int)(ej >> 28);
+  const uint32_t ej = (uint32_t)d.e_j[e];
+  const int code = (int)(ej >> 28);
   v.L = d.e_len[e];
   v.fx = d.e_fx[e];
   v.fy = d.e_fy[e];
-  double shx, shy;
-  shift_of(d, code, shx, shy);
+  shift_of(d, code, v.shx, v.shy);
   v.wall = 0;
   if (side == 0) {
     if (code >= 9) {
       v.wall = code;
       v.j = i;
-      mirror_point(d, code, rix, riy, v.rx, v.ry);
       return v;
     }
     v.j = (int)(ej & kCellMask);
   } else {
     v.j = d.e_i[e];
-    shx = -shx;
-    shy = -shy;
-    v.fx += shx;
-    v.fy += shy;
+    v.shx = -v.shx;
+    v.shy = -v.shy;
+    v.fx += v.shx;
+    v.fy += v.shy;
   }
   if (v.j < 0 || v.j >= d.n) {
     bad = true;
     v.j = i;
   }
-  v.rx = d.px[v.j] + shx;
-  v.ry = d.py[v.j] + shy;
   return v;
 }
 
@@ -147,178 +143,6 @@ __device__ __forceinline__ void prim_of(const RunDesc& d, int j, double& rho, do
 // without a division (both pressures positive).
 __device__ __forceinline__ bool pressure_jump(double delta_p, double pi, double pj) {
   return pi > pj ? (pj < delta_p * pi) : (pj > pi ? (pi < delta_p * pj) : (delta_p > 1.0));
-}
-
-// ---------------------------------------------------------------------------
-// A1-A4 for one cell: primitives, point velocity, gradient, limiter.
-// Writes the record (16 doubles).  Returns false on a bad mesh index.
-// ---------------------------------------------------------------------------
-__device__ inline bool cell_record(const RunDesc& d, int i, double* rec) {
-  bool bad = false;
-  double rho, vx, vy, p;
-  prim_of(d, i, rho, vx, vy, p);
-  const double c = sqrt(d.gamma * p / rho);
-  const double rix = d.px[i], riy = d.py[i];
-  const double six = d.sx[i], siy = d.sy[i];
-  const double A = d.area[i];
-  const double R = sqrt(A / kPi);
-
-  // A2 (section 6): Lagrangian motion plus the cell-rounding correction
-  double wx = 0.0, wy = 0.0;
-  if (d.motion) {
-    wx = vx;
-    wy = vy;
-    double dx = six - rix, dy = siy - riy;
-    double dd = sqrt(dx * dx + dy * dy);
-    if (dd > d.eta * R) {
-      wx += d.chi * c * dx / dd;
-      wy += d.chi * c * dy / dd;
-    }
-  }
-
-  // A3 (eq. slope) with r_ij = r_i - r_j; bounds and pressure ratios for A4
-  const double phi[4] = {rho, vx, vy, p};
-  double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  double pmax[4] = {rho, vx, vy, p}, pmin[4] = {rho, vx, vy, p};
-  bool shock = false;
-  const int k0 = d.off[i], k1 = d.off[i + 1];
-  if (k0 < 0 || k1 < k0 || k1 > d.n_csr) return false;
-  for (int k = k0; k < k1; ++k) {
-    Nb v = nb_view(d, i, rix, riy, d.idx[k], bad);
-    double pj[4];
-    if (v.wall) {
-      pj[0] = rho;
-      mirror_vec(v.wall, vx, vy, pj[1], pj[2]);
-      pj[3] = p;
-    } else {
-      prim_of(d, v.j, pj[0], pj[1], pj[2], pj[3]);
-    }
-    const double rx = rix - v.rx, ry = riy - v.ry;
-    const double inv_r = 1.0 / sqrt(rx * rx + ry * ry);
-    const double cx = v.fx - 0.5 * (rix + v.rx), cy = v.fy - 0.5 * (riy + v.ry);
-    const double ux = cx * inv_r, uy = cy * inv_r, nx = rx * inv_r, ny = ry * inv_r;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double dphi = pj[q] - phi[q];
-      const double mean = 0.5 * (phi[q] + pj[q]);
-      // each term is rounded before it is added (as in slot_terms)
-      const double tx = v.L * (dphi * ux - mean * nx);
-      const double ty = v.L * (dphi * uy - mean * ny);
-      g[2 * q] += tx;
-      g[2 * q + 1] += ty;
-      pmax[q] = fmax(pmax[q], pj[q]);
-      pmin[q] = fmin(pmin[q], pj[q]);
-    }
-    double ratio = 1.0;
-    if (pj[3] > p) ratio = p / pj[3];
-    if (p > pj[3]) ratio = pj[3] / p;
-    if (d.delta_p > ratio) shock = true;
-  }
-  double G[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) G[q] = g[q] / A;
-  if (-(G[2] + G[5]) > d.delta_v * c / R) shock = true;
-
-  // A4 (section 2.2): alpha per variable
-  double alpha[4] = {1.0, 1.0, 1.0, 1.0};
-  int local = -1;
-  if (d.limiter == 0) local = shock ? 1 : 0;
-  if (d.limiter == 1) local = 0;
-  if (d.limiter == 2) local = 1;
-  if (d.limiter == 4) alpha[0] = alpha[1] = alpha[2] = alpha[3] = 0.0;
-  if (local == 0) {
-    // global limiter: min_j psi_ij is attained at the largest positive and
-    // the most negative change (division is monotone in the denominator)
-    double dmax[4] = {0, 0, 0, 0}, dmin[4] = {0, 0, 0, 0};
-    for (int k = k0; k < k1; ++k) {
-      Nb v = nb_view(d, i, rix, riy, d.idx[k], bad);
-      const double dx = v.fx - six, dy = v.fy - siy;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double dphi = G[2 * q] * dx + G[2 * q + 1] * dy;
-        dmax[q] = fmax(dmax[q], dphi);
-        dmin[q] = fmin(dmin[q], dphi);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (dmax[q] > 0.0) alpha[q] = fmin(alpha[q], (pmax[q] - phi[q]) / dmax[q]);
-      if (dmin[q] < 0.0) alpha[q] = fmin(alpha[q], (pmin[q] - phi[q]) / dmin[q]);
-    }
-  } else if (local == 1) {
-    for (int k = k0; k < k1; ++k) {
-      Nb v = nb_view(d, i, rix, riy, d.idx[k], bad);
-      double pj[4];
-      if (v.wall) {
-        pj[0] = rho;
-        mirror_vec(v.wall, vx, vy, pj[1], pj[2]);
-        pj[3] = p;
-      } else {
-        prim_of(d, v.j, pj[0], pj[1], pj[2], pj[3]);
-      }
-      const double dx = v.fx - six, dy = v.fy - siy;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double dphi = G[2 * q] * dx + G[2 * q + 1] * dy;
-        const double psi = (dphi != 0.0) ? fmax(d.theta * (pj[q] - phi[q]) / dphi, 0.0) : 1.0;
-        alpha[q] = fmin(alpha[q], psi);
-      }
-    }
-  }
-  rec[R_RHO] = rho;
-  rec[R_VX] = vx;
-  rec[R_VY] = vy;
-  rec[R_P] = p;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) rec[R_G + q] = G[q] * alpha[q / 2];
-  rec[R_WX] = wx;
-  rec[R_WY] = wy;
-  rec[R_SX] = six;
-  rec[R_SY] = siy;
-  return !bad;
-}
-
-// ---------------------------------------------------------------------------
-// The per-neighbour part of A3/A4 for the slot-parallel cell kernel: the two
-// gradient terms of eq. (slope) for each of the four variables, the
-// neighbour's values, the offset of the edge centre from the centroid and the
-// pressure-ratio test.  Same arithmetic as the loop bodies of cell_record.
-// ---------------------------------------------------------------------------
-struct SlotTerms {
-  double g[8];
-  double pj[4];
-  double fdx, fdy;
-  bool pflag;
-};
-
-__device__ __forceinline__ void slot_terms(const RunDesc& d, int i, const double* phi,
-                                           double rix, double riy, double six, double siy,
-                                           int entry, SlotTerms& o, bool& bad) {
-  Nb v = nb_view(d, i, rix, riy, entry, bad);
-  if (v.wall) {
-    o.pj[0] = phi[0];
-    mirror_vec(v.wall, phi[1], phi[2], o.pj[1], o.pj[2]);
-    o.pj[3] = phi[3];
-  } else {
-    prim_of(d, v.j, o.pj[0], o.pj[1], o.pj[2], o.pj[3]);
-  }
-  const double rx = rix - v.rx, ry = riy - v.ry;
-  const double inv_r = 1.0 / sqrt(rx * rx + ry * ry);
-  const double cx = v.fx - 0.5 * (rix + v.rx), cy = v.fy - 0.5 * (riy + v.ry);
-  const double ux = cx * inv_r, uy = cy * inv_r, nx = rx * inv_r, ny = ry * inv_r;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const double dphi = o.pj[q] - phi[q];
-    const double mean = 0.5 * (phi[q] + o.pj[q]);
-    o.g[2 * q] = v.L * (dphi * ux - mean * nx);
-    o.g[2 * q + 1] = v.L * (dphi * uy - mean * ny);
-  }
-  double ratio = 1.0;
-  if (o.pj[3] > phi[3]) ratio = phi[3] / o.pj[3];
-  if (phi[3] > o.pj[3]) ratio = o.pj[3] / phi[3];
-  o.pflag = d.delta_p > ratio;
-  o.fdx = v.fx - six;
-  o.fdy = v.fy - siy;
 }
 
 // ---------------------------------------------------------------------------

@@ -38,9 +38,15 @@ namespace rich {
 #ifndef RICH_LPC
 #define RICH_LPC 2
 #endif
+#ifndef RICH_CELL_WAVES
+#define RICH_CELL_WAVES 1  // minimum waves per SIMD the register budget must allow
+#endif
+#ifndef RICH_FLUX_WAVES
+#define RICH_FLUX_WAVES 1
+#endif
 constexpr int kTile = 256;        // k_flux: cells per tile = threads per block
-constexpr int kEdgeCap = 896;     // k_flux: owned-edge fluxes kept in LDS
-constexpr int kForCap = 256;      // k_flux: other edges kept in LDS
+constexpr int kEdgeCap = 800;     // k_flux: owned-edge fluxes kept in LDS
+constexpr int kForCap = 192;      // k_flux: other edges kept in LDS
 constexpr int kMapCap = 2304;     // k_flux: CSR entries classified in LDS
 constexpr int kCellThreads = 256;   // k_cell: threads per block
 constexpr int kLpc = RICH_LPC;      // k_cell: lanes per cell
@@ -121,7 +127,7 @@ __device__ __forceinline__ int group_or(int v) {
 }
 
 template <int LPC, bool BATCH>
-__global__ __launch_bounds__(kCellThreads) void k_cell(RunDesc one,
+__global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc one,
                                                        const RunDesc* __restrict__ descs,
                                                        const int32_t* __restrict__ tile_start,
                                                        int n_runs, int n_tiles) {
@@ -162,25 +168,29 @@ __global__ __launch_bounds__(kCellThreads) void k_cell(RunDesc one,
       if (active) bad = true;
       k1 = k0;
     }
+    // neighbour values and point across one CSR entry (mirror for a wall)
+    auto nb_values = [&](const NbE& v, double* pj, double& rjx, double& rjy) {
+      if (v.wall) {
+        pj[0] = rho;
+        mirror_vec(v.wall, vx, vy, pj[1], pj[2]);
+        pj[3] = p;
+        mirror_point(d, v.wall, rix, riy, rjx, rjy);
+      } else {
+        prim_of(d, v.j, pj[0], pj[1], pj[2], pj[3]);
+        rjx = d.px[v.j] + v.shx;
+        rjy = d.py[v.j] + v.shy;
+      }
+    };
 
     // A3: eq. (slope), r_ij = r_i - r_j; each term rounded before it is added
     double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double pmax[4] = {rho, vx, vy, p}, pmin[4] = {rho, vx, vy, p};
     int pflag = 0;
     double fdx[MAXE], fdy[MAXE];
-    auto entry_terms = [&](int k, double& ex, double& ey) {
-      Nb v = nb_view(d, i, rix, riy, d.idx[k], bad);
-      double pj[4];
-      if (v.wall) {
-        pj[0] = rho;
-        mirror_vec(v.wall, vx, vy, pj[1], pj[2]);
-        pj[3] = p;
-      } else {
-        prim_of(d, v.j, pj[0], pj[1], pj[2], pj[3]);
-      }
-      const double rx = rix - v.rx, ry = riy - v.ry;
+    auto accumulate = [&](const NbE& v, const double* pj, double vrx, double vry) {
+      const double rx = rix - vrx, ry = riy - vry;
       const double inv_r = rsqrt(rx * rx + ry * ry);
-      const double cx = v.fx - 0.5 * (rix + v.rx), cy = v.fy - 0.5 * (riy + v.ry);
+      const double cx = v.fx - 0.5 * (rix + vrx), cy = v.fy - 0.5 * (riy + vry);
       const double ux = cx * inv_r, uy = cy * inv_r, nx = rx * inv_r, ny = ry * inv_r;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -194,19 +204,26 @@ __global__ __launch_bounds__(kCellThreads) void k_cell(RunDesc one,
         pmin[q] = fmin(pmin[q], pj[q]);
       }
       if (pressure_jump(d.delta_p, p, pj[3])) pflag = 1;
-      ex = v.fx - six;
-      ey = v.fy - siy;
     };
 #pragma unroll
     for (int m = 0; m < MAXE; ++m) {
       const int k = k0 + lane + m * LPC;
       fdx[m] = 0.0;
       fdy[m] = 0.0;
-      if (k < k1) entry_terms(k, fdx[m], fdy[m]);
+      if (k < k1) {
+        const NbE v = nb_edge(d, i, d.idx[k], bad);
+        double pj[4], vrx, vry;
+        nb_values(v, pj, vrx, vry);
+        accumulate(v, pj, vrx, vry);
+        fdx[m] = v.fx - six;
+        fdy[m] = v.fy - siy;
+      }
     }
     for (int k = k0 + lane + MAXE * LPC; k < k1; k += LPC) {
-      double ex, ey;
-      entry_terms(k, ex, ey);
+      const NbE v = nb_edge(d, i, d.idx[k], bad);
+      double pj[4], vrx, vry;
+      nb_values(v, pj, vrx, vry);
+      accumulate(v, pj, vrx, vry);
     }
     double G[8];
     const double rA = 1.0 / A;
@@ -243,7 +260,7 @@ __global__ __launch_bounds__(kCellThreads) void k_cell(RunDesc one,
       for (int m = 0; m < MAXE; ++m)
         if (k0 + lane + m * LPC < k1) bound(fdx[m], fdy[m]);
       for (int k = k0 + lane + MAXE * LPC; k < k1; k += LPC) {
-        Nb v = nb_view(d, i, rix, riy, d.idx[k], bad);
+        const NbE v = nb_edge(d, i, d.idx[k], bad);
         bound(v.fx - six, v.fy - siy);
       }
 #pragma unroll
@@ -255,15 +272,9 @@ __global__ __launch_bounds__(kCellThreads) void k_cell(RunDesc one,
       }
     } else if (local == 1) {
       for (int k = k0 + lane; k < k1; k += LPC) {
-        Nb v = nb_view(d, i, rix, riy, d.idx[k], bad);
-        double pj[4];
-        if (v.wall) {
-          pj[0] = rho;
-          mirror_vec(v.wall, vx, vy, pj[1], pj[2]);
-          pj[3] = p;
-        } else {
-          prim_of(d, v.j, pj[0], pj[1], pj[2], pj[3]);
-        }
+        const NbE v = nb_edge(d, i, d.idx[k], bad);
+        double pj[4], vrx, vry;
+        nb_values(v, pj, vrx, vry);
         const double dx = v.fx - six, dy = v.fy - siy;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -349,7 +360,7 @@ __device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF
 }
 
 template <int RIEMANN, bool BATCH>
-__global__ __launch_bounds__(kTile) void k_flux(RunDesc one, const RunDesc* __restrict__ descs,
+__global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, const RunDesc* __restrict__ descs,
                                                 const int32_t* __restrict__ tile_start,
                                                 int n_runs, int n_tiles) {
   __shared__ double sF[4][kEdgeCap + kForCap];
@@ -453,13 +464,28 @@ __global__ __launch_bounds__(kTile) void k_flux(RunDesc one, const RunDesc* __re
 }
 
 // ---------------------------------------------------------------------------
-// A0: Courant step, min over cells of R/(c + |v - w|)
+// A0: Courant step, min over cells of R/(c + |v - w|).  Two levels: each
+// block of a bounded grid reduces its cells to one value in scratch, then a
+// single block reduces those (min is order-free, so the result is
+// deterministic).  A cell whose ratio is not a positive number makes the
+// minimum 0, which the host reports as a domain error.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_cfl(RunDesc d) {
-  __shared__ double smin[256 / 64];
-  const int i = blockIdx.x * 256 + threadIdx.x;
+constexpr int kCflThreads = 256;
+constexpr int kCflMaxBlocks = 2048;
+
+__device__ __forceinline__ double block_min(double t, double* smin) {
+  for (int o = 32; o > 0; o >>= 1) t = fmin(t, __shfl_xor(t, o));
+  if ((threadIdx.x & 63) == 0) smin[threadIdx.x >> 6] = t;
+  __syncthreads();
+  double m = smin[0];
+  for (int w = 1; w < kCflThreads / 64; ++w) m = fmin(m, smin[w]);
+  return m;
+}
+
+__global__ __launch_bounds__(kCflThreads) void k_cfl(RunDesc d, double* block_out) {
+  __shared__ double smin[kCflThreads / 64];
   double t = INFINITY;
-  if (i < d.n) {
+  for (int i = blockIdx.x * kCflThreads + threadIdx.x; i < d.n; i += gridDim.x * kCflThreads) {
     double rho, vx, vy, p;
     prim_of(d, i, rho, vx, vy, p);
     const double c = sqrt(d.gamma * p / rho);
@@ -477,18 +503,21 @@ __global__ __launch_bounds__(256) void k_cfl(RunDesc d) {
     }
     const double ux = vx - wx, uy = vy - wy;
     const double s = c + sqrt(ux * ux + uy * uy);
-    t = R / s;
-    if (!(t > 0.0)) t = INFINITY;  // NaN or non-positive: reported by the host check
+    double ti = R / s;
+    if (!(ti > 0.0) || !isfinite(ti)) ti = 0.0;
+    t = fmin(t, ti);
   }
-  for (int o = 32; o > 0; o >>= 1) t = fmin(t, __shfl_xor(t, o));
-  if ((threadIdx.x & 63) == 0) smin[threadIdx.x >> 6] = t;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = smin[0];
-    for (int w = 1; w < 256 / 64; ++w) m = fmin(m, smin[w]);
-    unsigned long long bits = (unsigned long long)__double_as_longlong(m);
-    atomicMin(d.cfl_min, bits);
-  }
+  const double m = block_min(t, smin);
+  if (threadIdx.x == 0) block_out[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(kCflThreads) void k_cfl_final(const double* block_in, int nb,
+                                                           unsigned long long* out) {
+  __shared__ double smin[kCflThreads / 64];
+  double t = INFINITY;
+  for (int b = threadIdx.x; b < nb; b += kCflThreads) t = fmin(t, block_in[b]);
+  const double m = block_min(t, smin);
+  if (threadIdx.x == 0) *out = (unsigned long long)__double_as_longlong(m);
 }
 
 }  // namespace rich
@@ -868,9 +897,12 @@ int rich_cfl_dt(const rich_mesh* m, const rich_state* s, const rich_params* p, d
   if (ws_bytes < run_ws_bytes(m->n_cells)) return RICH_E_NOMEM;
   hipStream_t st = static_cast<hipStream_t>(stream);
   RunDesc d = make_desc(m, s, nullptr, nullptr, 0.0, p, static_cast<char*>(ws));
-  const int nb = (d.n + 255) / 256;
-  hipLaunchKernelGGL(rich::k_clear, dim3(1), dim3(64), 0, st, d.flag, d.cfl_min);
-  hipLaunchKernelGGL(rich::k_cfl, dim3(nb), dim3(256), 0, st, d);
+  const int nb = std::min<int>((d.n + rich::kCflThreads - 1) / rich::kCflThreads,
+                               rich::kCflMaxBlocks);
+  // per-block minima go to the (otherwise idle) record area of the workspace
+  hipLaunchKernelGGL(rich::k_cfl, dim3(nb), dim3(rich::kCflThreads), 0, st, d, d.rec);
+  hipLaunchKernelGGL(rich::k_cfl_final, dim3(1), dim3(rich::kCflThreads), 0, st,
+                     (const double*)d.rec, nb, d.cfl_min);
   if (hipGetLastError() != hipSuccess) return RICH_E_DEVICE;
   unsigned long long bits = 0;
   if (hipStreamSynchronize(st) != hipSuccess) return RICH_E_DEVICE;

@@ -769,8 +769,14 @@ int build_mesh(const double* pxin, const double* pyin, int64_t n,
         }
         double Rj = std::sqrt(area[cell] / kPi);
         bool keep = s_len[s] >= 1e-12 * 0.5 * (Ri + Rj);
+        // A point, another point and their mirror images across one wall
+        // are concyclic (isosceles trapezoid), so the triangulation may join
+        // a cell to the mirror image of another cell.  The Voronoi edge of
+        // that pair has length zero exactly; rounding in the circumcentres
+        // of such thin triangles can leave it above the threshold, so it is
+        // dropped whatever its computed length.
+        if (code >= RICH_CODE_WALL_X0 && cell != i) keep = false;
         if (!keep) ++drop_local;
-        if (keep && code >= RICH_CODE_WALL_X0 && cell != i) bad = 1;
         bool own;
         if (code >= RICH_CODE_WALL_X0) own = true;
         else if (cell != i) own = i < cell;

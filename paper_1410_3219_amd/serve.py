@@ -55,6 +55,7 @@ class Session:
     nxt: "R.DeviceState" = None
     admitted: bool = False
     bytes: int = 0
+    final: tuple = None     # (Q, X) on the host at close, when kept
 
 
 @dataclass
@@ -90,12 +91,14 @@ def build_templates(sizes, kinds, seed=11, n_threads=0):
 
 
 class Server:
-    def __init__(self, templates, hbm_budget_bytes=16 << 30, device="cuda"):
+    def __init__(self, templates, hbm_budget_bytes=16 << 30, keep_final=False):
         import torch
         self.torch = torch
         self.templates = templates
         self.budget = hbm_budget_bytes
+        self.keep_final = keep_final
         self.used = 0
+        self.max_used = 0
         self.sessions = {}
         self.waiting = []          # sessions not yet admitted (FIFO)
         self.queue = []            # requests not yet started
@@ -127,8 +130,11 @@ class Server:
             s.nxt = R.DeviceState.empty_like(s.cur)
             s.admitted = True
             self.used += s.bytes
+            self.max_used = max(self.max_used, self.used)
 
     def _close(self, s):
+        if self.keep_final:
+            s.final = s.cur.numpy()
         s.cur = s.half = s.nxt = None
         s.admitted = False
         self.used -= s.bytes
@@ -210,7 +216,7 @@ class Server:
 
 
 def run(templates, rate=2000.0, duration=2.0, steps_per_session=8, seed=9,
-        hbm_budget_bytes=16 << 30, tpl_choice=None, log=None):
+        hbm_budget_bytes=16 << 30, tpl_choice=None, keep_final=False, log=None):
     """Poisson arrivals of step requests; each session issues its requests in
     order (a session's next request arrives after the previous one).  Returns
     latency percentiles and throughput."""
@@ -218,12 +224,16 @@ def run(templates, rate=2000.0, duration=2.0, steps_per_session=8, seed=9,
     arrivals = I.poisson_arrivals(rate, duration, seed)
     n_req = len(arrivals)
     n_sess = max(1, n_req // steps_per_session)
+    # request k belongs to session k % n_sess, so a session's step count is
+    # the number of requests that map to it
+    counts = np.bincount(np.arange(n_req) % n_sess, minlength=n_sess)
     s = I.Stream(seed + 1)
     pick = s.uniform(n_sess)
-    srv = Server(templates, hbm_budget_bytes)
+    srv = Server(templates, hbm_budget_bytes, keep_final)
     for sid in range(n_sess):
         ti = tpl_choice[sid] if tpl_choice is not None else int(pick[sid] * len(templates))
-        srv.open_session(sid, ti, steps_per_session)
+        if counts[sid]:
+            srv.open_session(sid, ti, int(counts[sid]))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0   # noqa: E731
@@ -241,7 +251,8 @@ def run(templates, rate=2000.0, duration=2.0, steps_per_session=8, seed=9,
     res = dict(requests=len(srv.done), sessions=n_sess, launches=srv.launches,
                mean_batch=float(np.mean(srv.batch_sizes)) if srv.batch_sizes else 0.0,
                p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
-               cell_updates_per_s=srv.cells_done / wall, wall_s=wall, offered_rate=rate)
+               cell_updates_per_s=srv.cells_done / wall, wall_s=wall, offered_rate=rate,
+               hbm_budget_bytes=hbm_budget_bytes, max_admitted_bytes=srv.max_used)
     if log:
         log(f"[serve] {res}")
     return res, srv

@@ -78,6 +78,20 @@ def test_cfl_dt():
         assert abs(dt - dt_ref) <= 1e-13 * dt_ref, (name, dt, dt_ref)
 
 
+@pytest.mark.parametrize("k", [1, 800])
+def test_cfl_dt_grid_sizes(k):
+    """A single cell, and 640 000 cells: more cells than one pass of the
+    bounded reduction grid covers, so blocks stride over the cells."""
+    from paper_1410_3219_amd import rich as R
+    m, Qs, Qb, Xb, h, p = U.case("wave", k=k)
+    dt_ref, st = O.cfl_dt(m, Qs, p)
+    assert st == 0
+    dm = R.DeviceMesh.from_host(m)
+    s = R.DeviceState.from_host(Qs, Xb)
+    dt = R.rich_cfl_dt(dm, s, U.gpu_params(p), R.workspace(m.n_cells))
+    assert abs(dt - dt_ref) <= 1e-13 * dt_ref, (k, dt, dt_ref)
+
+
 def test_domain_error_flag():
     # negative mass in one cell: the stage reports it and still writes
     from paper_1410_3219_amd import rich as R

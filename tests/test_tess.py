@@ -106,6 +106,39 @@ def test_mesh_identities_random(tess_mod, bc):
         assert m.n_edges == 3 * n
 
 
+def test_points_near_walls_large_random(tess_mod):
+    """151 321 uniform-random points with walls: many points lie within
+    1e-5 of a wall, so the triangulation joins cells to the mirror images of
+    other cells across co-circular trapezoids.  Those zero-length edges are
+    dropped; the mesh closes (every cell's sum of L n over its CSR entries
+    vanishes, areas tile the box) and every wall edge is a cell's own
+    mirror."""
+    px, py = I.uniform_points(389 * 389, seed=14, box=BOX)
+    m = tess_mod.rich_tess_build(px, py, BOX, 0)
+    n = px.shape[0]
+    assert abs(m.area.sum() - 1.0) < 1e-12
+    code = (m.e_j.view(np.uint32) >> 28).astype(np.int64)
+    cell = (m.e_j & 0x0FFFFFFF).astype(np.int64)
+    wall = code >= 9
+    assert (cell[wall] == m.e_i[wall]).all()
+    # outward unit normals from e_i towards its neighbour (mirror for walls)
+    rjx, rjy = m.px[cell].copy(), m.py[cell].copy()
+    rjx[code == 9] = -m.px[m.e_i[code == 9]]
+    rjx[code == 10] = 2.0 - m.px[m.e_i[code == 10]]
+    rjy[code == 11] = -m.py[m.e_i[code == 11]]
+    rjy[code == 12] = 2.0 - m.py[m.e_i[code == 12]]
+    dx, dy = rjx - m.px[m.e_i], rjy - m.py[m.e_i]
+    d = np.hypot(dx, dy)
+    e = m.idx >> 1
+    sgn = np.where(m.idx & 1, -1.0, 1.0)
+    owner = np.repeat(np.arange(n), np.diff(m.off))
+    ax = np.zeros(n)
+    ay = np.zeros(n)
+    np.add.at(ax, owner, sgn * m.e_len[e] * dx[e] / d[e])
+    np.add.at(ay, owner, sgn * m.e_len[e] * dy[e] / d[e])
+    assert np.max(np.hypot(ax, ay) / np.sqrt(m.area)) < 1e-9
+
+
 @pytest.mark.parametrize("bc", [0, 1])
 def test_mesh_identities_jittered_rect_box(tess_mod, bc):
     box = (-0.5, -1.0, 1.5, 0.25)
