@@ -113,8 +113,9 @@ def lib():
         if hasattr(L, "rich_stage_batch"):
             L.rich_batch_workspace_size.argtypes = [C.c_int32, C.POINTER(C.c_int64),
                                                     C.POINTER(C.c_size_t)]
-            L.rich_stage_batch.argtypes = [C.c_int32, C.POINTER(mp), C.POINTER(sp),
-                                           C.POINTER(sp), C.POINTER(sp), _dp, C.POINTER(pp),
+            # arrays of struct addresses (const T* const*), passed as void**
+            L.rich_stage_batch.argtypes = [C.c_int32, C.POINTER(_vp), C.POINTER(_vp),
+                                           C.POINTER(_vp), C.POINTER(_vp), _dp, C.POINTER(_vp),
                                            _vp, C.c_size_t, _vp]
             L.rich_batch_flags.argtypes = [C.c_int32, _vp, _vp, _ip]
             for f in ("rich_batch_workspace_size", "rich_stage_batch", "rich_batch_flags"):
@@ -191,6 +192,7 @@ class DeviceState:
     """Q (4, n): M, Px, Py, E extensive totals; X (2, n): points."""
     Q: "torch.Tensor"
     X: "torch.Tensor"
+    _c: RichState = field(default=None, repr=False, compare=False)
 
     @classmethod
     def from_host(cls, Q, X, device="cuda"):
@@ -207,11 +209,23 @@ class DeviceState:
     def n(self):
         return int(self.Q.shape[1])
 
+    def __setattr__(self, name, value):
+        if name in ("Q", "X"):
+            object.__setattr__(self, "_c", None)   # a new tensor: rebuild the view
+        object.__setattr__(self, name, value)
+
     def c(self):
-        assert self.Q.is_contiguous() and self.X.is_contiguous()
-        q, x = self.Q, self.X
-        return RichState(q[0].data_ptr(), q[1].data_ptr(), q[2].data_ptr(), q[3].data_ptr(),
-                         x[0].data_ptr(), x[1].data_ptr(), self.n)
+        """The C view (rows of Q and X are contiguous), built once per pair
+        of tensors (in-place updates keep the storage)."""
+        if self._c is None:
+            q, x = self.Q, self.X
+            assert q.is_contiguous() and x.is_contiguous()
+            assert q.dtype == x.dtype and q.element_size() == 8
+            n = int(q.shape[1])
+            qb, xb = q.data_ptr(), x.data_ptr()
+            object.__setattr__(self, "_c", RichState(qb, qb + 8 * n, qb + 16 * n, qb + 24 * n,
+                                                     xb, xb + 8 * n, n))
+        return self._c
 
     def numpy(self):
         return self.Q.cpu().numpy(), self.X.cpu().numpy()
@@ -285,15 +299,15 @@ def batch_workspace(n_cells, device="cuda"):
 def rich_stage_batch(meshes, srcs, bases, outs, hs, params, ws, stream=None):
     """One stage of len(meshes) independent runs, one launch per kernel phase."""
     n = len(meshes)
-    mc = [m.c() for m in meshes]
-    sc, bc_, oc = [x.c() for x in srcs], [x.c() for x in bases], [x.c() for x in outs]
-    pc = [p.c() for p in params]
-    mp = (C.POINTER(RichMesh) * n)(*[C.pointer(x) for x in mc])
-    spp = (C.POINTER(RichState) * n)(*[C.pointer(x) for x in sc])
-    bpp = (C.POINTER(RichState) * n)(*[C.pointer(x) for x in bc_])
-    opp = (C.POINTER(RichState) * n)(*[C.pointer(x) for x in oc])
+    ad = C.addressof
+    # the structs stay referenced by the objects that cache them for the call
+    mp = (_vp * n)(*[ad(m.c()) for m in meshes])
+    spp = (_vp * n)(*[ad(x.c()) for x in srcs])
+    bpp = (_vp * n)(*[ad(x.c()) for x in bases])
+    opp = (_vp * n)(*[ad(x.c()) for x in outs])
     hh = (C.c_double * n)(*[float(h) for h in hs])
-    ppp = (C.POINTER(RichParams) * n)(*[C.pointer(x) for x in pc])
+    pc = [p.c() for p in params]
+    ppp = (_vp * n)(*[ad(x) for x in pc])
     st = lib().rich_stage_batch(n, mp, spp, bpp, opp, hh, ppp, C.c_void_p(ws.data_ptr()),
                                 ws.numel(), _stream_ptr(stream))
     _check(st, "rich_stage_batch")
