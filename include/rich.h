@@ -82,6 +82,10 @@ typedef struct rich_params {
   int32_t motion;  /* 0 static mesh, 1 Lagrangian with cell rounding (section 6) */
   int32_t limiter; /* 0 global/local switch on the shock detector (section 2.2),
                       1 global only, 2 local only, 3 unlimited, 4 first order */
+  double gx, gy;   /* uniform external acceleration; each stage adds h times
+                      (0, M g, P.g) of its source totals (section 2.3: the
+                      time-centred scheme makes a first-order source second
+                      order); 0 for pure hydrodynamics */
 } rich_params;
 
 /* Fill p with the paper's defaults for adiabatic index gamma. */
@@ -132,6 +136,11 @@ int rich_stage_batch(int32_t n, const rich_mesh* const* meshes,
                      void* stream);
 /* Synchronise and read the n per-run flag words of the last batched stage. */
 int rich_batch_flags(int32_t n, void* ws, void* stream, int32_t* flags);
+/* Enqueue on stream a copy of the same n flag words into host_flags and
+ * return without waiting: the words are there once the stream has passed
+ * the copy (an event recorded after it).  host_flags should be pinned host
+ * memory (hipHostMalloc); other memory makes the copy synchronous. */
+int rich_batch_flags_async(int32_t n, void* ws, void* stream, int32_t* host_flags);
 
 /*
  * Time-centred step (section 2.3) of one run with a moving mesh:
@@ -169,6 +178,39 @@ int rich_ctx_mesh(rich_ctx* ctx, rich_mesh* out);
 int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
               rich_tess_fn tess, rich_tess_release_fn release, void* tess_user,
               void* stream);
+
+/*
+ * Time-centred step (section 2.3) of n independent runs at once: the same
+ * chain as rich_step for every run, with each of the two stages issued as
+ * one batched stage over all runs (rich_stage_batch) and the host
+ * tessellations of the runs spread over n_threads host threads in between.
+ *   ctxs[r]       run r's driver (current mesh set with rich_ctx_set_mesh);
+ *                 its device buffers are grown as needed
+ *   states[r]     host struct of device pointers: Q^n, x^n in, Q^{n+1},
+ *                 x^{n+1} out (committed only when status[r] == RICH_OK)
+ *   dt[r], params[r]
+ *   tess, release as for rich_step; tess is called with tess_users[r] for
+ *                 run r, from up to n_threads threads at once (calls for
+ *                 different runs must be safe to run concurrently, which
+ *                 holds for rich_tess_callback with one rich_tess_ctx per
+ *                 run); both may be NULL when no run moves its mesh
+ *   status[r]     out: RICH_OK, or this run's error (E_INVAL, E_NOMEM,
+ *                 E_DOMAIN, E_MESH); a failing run leaves its state and
+ *                 current mesh unchanged and never alters another run
+ *   ws            one device workspace of rich_batch_workspace_size bytes
+ *                 for the runs' cell counts
+ * Returns RICH_OK when every run succeeded, else the status of the first
+ * failing run.  When the call as a whole fails (workspace too small, a HIP
+ * error), that status is returned and written to every run not yet failed:
+ * status[r] == RICH_OK always means run r was committed.  Synchronises
+ * stream.
+ * The results are bitwise identical to n separate rich_step calls.
+ */
+int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
+                    const double* dt, const rich_params* const* params,
+                    rich_tess_fn tess, rich_tess_release_fn release,
+                    void* const* tess_users, int32_t n_threads, int32_t* status,
+                    void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Kernel timing for benchmarks.  While enabled, every stage records HIP

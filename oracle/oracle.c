@@ -663,6 +663,16 @@ int or_stage(const or_mesh* m, const double* Qsrc, const double* Qbase,
       for (int q = 0; q < 4; ++q) acc[q] += sgn * m->e_len[e] * flux[(int64_t)q * ne + e];
     }
     for (int q = 0; q < 4; ++q) Qout[(int64_t)q * n + i] = Qbase[(int64_t)q * n + i] - h * acc[q];
+    /* External acceleration (section 2.3): the source only needs first-order
+     * accuracy in time, because the time-centred composition makes it second
+     * order.  Reading: each stage adds h * S(Q_src), with S = (0, M g, P.g)
+     * from the stage's source totals (the force on the cell and its work). */
+    if (p->gx != 0.0 || p->gy != 0.0) {
+      double sm = Qsrc[i], spx = Qsrc[n + i], spy = Qsrc[2 * n + i];
+      Qout[n + i] += h * (sm * p->gx);
+      Qout[2 * n + i] += h * (sm * p->gy);
+      Qout[3 * n + i] += h * (spx * p->gx + spy * p->gy);
+    }
     double x = Xbase[i] + h * w[i], y = Xbase[n + i] + h * w[n + i];
     if (m->bc == 1) {
       x = wrap(x, m->box[0], m->box[2]);

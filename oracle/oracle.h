@@ -48,6 +48,7 @@ typedef struct or_params {
   int32_t motion;  /* 0 static (Eulerian), 1 Lagrangian + cell rounding */
   int32_t limiter; /* 0 switching (paper default), 1 global only, 2 local
                       only, 3 unlimited, 4 first order                  */
+  double gx, gy;   /* uniform external acceleration (0 for pure hydro)  */
 } or_params;
 
 /* status codes */

@@ -54,7 +54,7 @@ class OrParams(C.Structure):
         ("gamma", C.c_double), ("cfl", C.c_double), ("theta", C.c_double),
         ("delta_v", C.c_double), ("delta_p", C.c_double), ("chi", C.c_double),
         ("eta", C.c_double), ("riemann", C.c_int32), ("motion", C.c_int32),
-        ("limiter", C.c_int32),
+        ("limiter", C.c_int32), ("gx", C.c_double), ("gy", C.c_double),
     ]
 
 
@@ -71,10 +71,13 @@ class Params:
     riemann: int = 0   # 0 HLLC, 1 exact
     motion: int = 1    # 0 static, 1 Lagrangian + cell rounding
     limiter: int = 0   # 0 switching, 1 global, 2 local, 3 unlimited, 4 first order
+    gx: float = 0.0    # uniform external acceleration
+    gy: float = 0.0
 
     def c(self):
         return OrParams(self.gamma, self.cfl, self.theta, self.delta_v, self.delta_p,
-                        self.chi, self.eta, self.riemann, self.motion, self.limiter)
+                        self.chi, self.eta, self.riemann, self.motion, self.limiter,
+                        self.gx, self.gy)
 
 
 _lib = None

@@ -41,6 +41,7 @@ struct RunDesc {
   double x0, y0, x1, y1, Lx, Ly;
   double h, gamma, theta, delta_v, delta_p, chi, eta;
   double rgm1;  // 1 / (gamma - 1)
+  double gx, gy;  // uniform external acceleration
   int32_t n, n_edges, n_csr, bc;
   int32_t riemann, motion, limiter, pad;
 };
@@ -63,14 +64,15 @@ __device__ __forceinline__ void shift_of(const RunDesc& d, int code, double& shx
   }
 }
 
+// Both coordinates are always computed and selected, so that the compiler
+// keeps them in registers (conditional stores to one of two outputs are
+// otherwise merged into a dynamically indexed stack slot).
 __device__ __forceinline__ void mirror_point(const RunDesc& d, int code, double x,
                                              double y, double& mx, double& my) {
-  mx = x;
-  my = y;
-  if (code == 9) mx = 2.0 * d.x0 - x;
-  if (code == 10) mx = 2.0 * d.x1 - x;
-  if (code == 11) my = 2.0 * d.y0 - y;
-  if (code == 12) my = 2.0 * d.y1 - y;
+  const double ax = 2.0 * (code == 9 ? d.x0 : d.x1) - x;
+  const double ay = 2.0 * (code == 11 ? d.y0 : d.y1) - y;
+  mx = (code == 9 || code == 10) ? ax : x;
+  my = (code == 11 || code == 12) ? ay : y;
 }
 
 __device__ __forceinline__ void mirror_vec(int code, double vx, double vy, double& mx,

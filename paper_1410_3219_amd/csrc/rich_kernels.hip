@@ -23,11 +23,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "rich.h"
@@ -37,6 +39,9 @@ namespace rich {
 
 #ifndef RICH_LPC
 #define RICH_LPC 2
+#endif
+#ifndef RICH_CELL_MAXE
+#define RICH_CELL_MAXE 8  // CSR entries per cell whose edge offsets stay in registers
 #endif
 #ifndef RICH_CELL_WAVES
 #define RICH_CELL_WAVES 1  // minimum waves per SIMD the register budget must allow
@@ -132,7 +137,7 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
                                                        const int32_t* __restrict__ tile_start,
                                                        int n_runs, int n_tiles) {
   constexpr int CPB = kCellThreads / LPC;  // cells per block
-  constexpr int MAXE = 8 / LPC;            // entries per lane whose edge offsets stay in registers
+  constexpr int MAXE = RICH_CELL_MAXE / LPC;  // entries per lane whose edge offsets stay in registers
   const int lane = (int)threadIdx.x % LPC;
   const int cl = (int)threadIdx.x / LPC;
   for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
@@ -436,9 +441,16 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
       }
       const double h = d.h;
       const double M = d.bM[i] - h * acc[0];
-      const double Px = d.bPx[i] - h * acc[1];
-      const double Py = d.bPy[i] - h * acc[2];
-      const double E = d.bE[i] - h * acc[3];
+      double Px = d.bPx[i] - h * acc[1];
+      double Py = d.bPy[i] - h * acc[2];
+      double E = d.bE[i] - h * acc[3];
+      if (d.gx != 0.0 || d.gy != 0.0) {
+        // external acceleration: h (0, M g, P.g) of the stage's source totals
+        const double sm = d.sM[i], spx = d.sPx[i], spy = d.sPy[i];
+        Px += h * (sm * d.gx);
+        Py += h * (sm * d.gy);
+        E += h * (spx * d.gx + spy * d.gy);
+      }
       const double* rec = d.rec + (size_t)i * kRecDoubles;
       double x = d.bx[i] + h * rec[R_WX];
       double y = d.by[i] + h * rec[R_WY];
@@ -553,7 +565,8 @@ bool valid_state(const rich_state* s, int64_t n, bool need_points) {
 
 bool valid_params(const rich_params* p) {
   return p && p->gamma > 1.0 && std::isfinite(p->gamma) && p->riemann >= 0 && p->riemann <= 1 &&
-         p->motion >= 0 && p->motion <= 1 && p->limiter >= 0 && p->limiter <= 4;
+         p->motion >= 0 && p->motion <= 1 && p->limiter >= 0 && p->limiter <= 4 &&
+         std::isfinite(p->gx) && std::isfinite(p->gy);
 }
 
 RunDesc make_desc(const rich_mesh* m, const rich_state* src, const rich_state* base,
@@ -582,6 +595,8 @@ RunDesc make_desc(const rich_mesh* m, const rich_state* src, const rich_state* b
   d.gamma = p->gamma; d.theta = p->theta; d.delta_v = p->delta_v; d.delta_p = p->delta_p;
   d.chi = p->chi; d.eta = p->eta;
   d.rgm1 = 1.0 / (p->gamma - 1.0);
+  d.gx = p->gx;
+  d.gy = p->gy;
   d.n = (int32_t)m->n_cells;
   d.n_edges = (int32_t)m->n_edges;
   d.n_csr = (int32_t)m->n_csr;
@@ -756,6 +771,14 @@ struct DevMesh {
   bool set = false;
 
   int upload(const rich_host_mesh_view* hm, const double* bx, uint32_t bcv, hipStream_t st) {
+    int rc = upload_async(hm, bx, bcv, st);
+    if (rc) return rc;
+    return hipStreamSynchronize(st) == hipSuccess ? RICH_OK : RICH_E_DEVICE;
+  }
+  // Enqueues the copies; the host arrays must stay valid until the stream
+  // has passed them.
+  int upload_async(const rich_host_mesh_view* hm, const double* bx, uint32_t bcv,
+                   hipStream_t st) {
     const int64_t n_ = hm->n_cells, ne_ = hm->n_edges, nc_ = hm->n_csr;
     const void* src[13] = {hm->px, hm->py, hm->sx, hm->sy, hm->area, hm->e_i, hm->e_j,
                            hm->e_len, hm->e_fx, hm->e_fy, hm->off, hm->idx, hm->eoff};
@@ -770,7 +793,6 @@ struct DevMesh {
           hipMemcpyAsync(b[k].p, src[k], bytes[k], hipMemcpyHostToDevice, st) != hipSuccess)
         return RICH_E_DEVICE;
     }
-    if (hipStreamSynchronize(st) != hipSuccess) return RICH_E_DEVICE;
     n = n_;
     ne = ne_;
     nc = nc_;
@@ -859,6 +881,8 @@ void rich_params_default(rich_params* p, double gamma) {
   p->riemann = 0;
   p->motion = 1;
   p->limiter = 0;
+  p->gx = 0.0;
+  p->gy = 0.0;
 }
 
 int rich_workspace_size(int64_t n_cells, size_t* bytes) {
@@ -1035,6 +1059,16 @@ int rich_batch_flags(int32_t n, void* ws, void* stream, int32_t* flags) {
 }
 
 
+int rich_batch_flags_async(int32_t n, void* ws, void* stream, int32_t* host_flags) {
+  if (n <= 0 || !ws || !host_flags) return RICH_E_INVAL;
+  std::vector<int64_t> one(n, 1);
+  BatchLayout L = batch_layout(n, one.data());
+  if (hipMemcpyAsync(host_flags, static_cast<char*>(ws) + L.flags, (size_t)n * sizeof(int32_t),
+                     hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return RICH_E_DEVICE;
+  return RICH_OK;
+}
+
 int rich_ctx_create(rich_ctx** ctx) {
   if (!ctx) return RICH_E_INVAL;
   try {
@@ -1116,6 +1150,186 @@ int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
     if (hipMemcpyAsync(dq[k], sq[k], 8 * (size_t)n, hipMemcpyDeviceToDevice, st) != hipSuccess)
       return RICH_E_DEVICE;
   if (hipStreamSynchronize(st) != hipSuccess) return RICH_E_DEVICE;
+  return RICH_OK;
+}
+
+int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
+                    const double* dt, const rich_params* const* params, rich_tess_fn tess,
+                    rich_tess_release_fn release, void* const* tess_users, int32_t n_threads,
+                    int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  if (n <= 0 || !ctxs || !states || !dt || !params || !status || !ws) return RICH_E_INVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<int64_t> nc(n, 1);
+  bool any_motion = false;
+  for (int32_t r = 0; r < n; ++r) {
+    status[r] = RICH_OK;
+    rich_ctx* c = ctxs[r];
+    if (!c || !c->cur.set || !valid_params(params[r]) || !std::isfinite(dt[r]) ||
+        !(dt[r] > 0.0) || !valid_state(states[r], c->cur.n, true)) {
+      status[r] = RICH_E_INVAL;
+      continue;
+    }
+    if (params[r]->motion) {
+      if (!tess || !release || !tess_users) {
+        status[r] = RICH_E_INVAL;
+        continue;
+      }
+      any_motion = true;
+    }
+    nc[r] = c->cur.n;
+    const size_t cn = (size_t)nc[r];
+    if (!c->Qh.ensure(32 * cn) || !c->Xh.ensure(16 * cn) || !c->Qn.ensure(32 * cn) ||
+        !c->Xn.ensure(16 * cn))
+      status[r] = RICH_E_NOMEM;
+  }
+  // a failure of the call as a whole: no run still pending is committed
+  auto fail_all = [&](int e) {
+    for (int32_t r = 0; r < n; ++r)
+      if (!status[r]) status[r] = e;
+    return e;
+  };
+  size_t need = 0;
+  int rc = rich_batch_workspace_size(n, nc.data(), &need);
+  if (rc) return fail_all(rc);
+  if (ws_bytes < need) return fail_all(RICH_E_NOMEM);
+
+  std::vector<rich_state> half(n), next(n);
+  std::vector<rich_mesh> mesh(n);
+  for (int32_t r = 0; r < n; ++r) {
+    if (status[r]) continue;
+    half[r] = state_view(ctxs[r]->Qh, ctxs[r]->Xh, nc[r]);
+    next[r] = state_view(ctxs[r]->Qn, ctxs[r]->Xn, nc[r]);
+    ctxs[r]->cur.view(&mesh[r]);
+  }
+
+  // One batched stage over the runs still alive; flagged runs drop out.
+  auto stage = [&](bool second) -> int {
+    std::vector<int32_t> live;
+    for (int32_t r = 0; r < n; ++r)
+      if (!status[r]) live.push_back(r);
+    if (live.empty()) return RICH_OK;
+    const size_t m = live.size();
+    std::vector<const rich_mesh*> mp(m);
+    std::vector<const rich_state*> sp(m), bp(m);
+    std::vector<rich_state*> op(m);
+    std::vector<double> h(m);
+    std::vector<const rich_params*> pp(m);
+    for (size_t k = 0; k < m; ++k) {
+      const int32_t r = live[k];
+      mp[k] = &mesh[r];
+      sp[k] = second ? &half[r] : states[r];
+      bp[k] = states[r];
+      op[k] = second ? &next[r] : &half[r];
+      h[k] = second ? dt[r] : 0.5 * dt[r];
+      pp[k] = params[r];
+    }
+    int e = rich_stage_batch((int32_t)m, mp.data(), sp.data(), bp.data(), op.data(), h.data(),
+                             pp.data(), ws, ws_bytes, stream);
+    if (e) return e;
+    std::vector<int32_t> fl(m, 0);
+    if ((e = rich_batch_flags((int32_t)m, ws, stream, fl.data()))) return e;
+    for (size_t k = 0; k < m; ++k)
+      if (fl[k]) status[live[k]] = RICH_E_DOMAIN;
+    return RICH_OK;
+  };
+
+  // Host tessellation of the points xs[r] of every live moving run into its
+  // spare mesh: device->host copies, then the runs spread over n_threads
+  // host threads (each call with its own run's tess_users[r]), then the
+  // uploads, one synchronisation, and the host arrays released.
+  std::vector<rich_host_mesh_view> hv(n);
+  auto retessellate = [&](const std::vector<rich_state>& xs) -> int {
+    std::vector<int32_t> todo;
+    for (int32_t r = 0; r < n; ++r)
+      if (!status[r] && params[r]->motion) todo.push_back(r);
+    if (todo.empty()) return RICH_OK;
+    for (int32_t r : todo) {
+      rich_ctx* c = ctxs[r];
+      const size_t bytes = 2 * (size_t)nc[r] * sizeof(double);
+      if (c->hostX_cap < bytes) {
+        if (c->hostX) (void)hipHostFree(c->hostX);
+        c->hostX = nullptr;
+        c->hostX_cap = 0;
+        if (hipHostMalloc(&c->hostX, bytes, 0) != hipSuccess) {
+          status[r] = RICH_E_NOMEM;
+          continue;
+        }
+        c->hostX_cap = bytes;
+      }
+      if (hipMemcpyAsync(c->hostX, xs[r].x, bytes, hipMemcpyDeviceToHost, st) != hipSuccess)
+        return RICH_E_DEVICE;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return RICH_E_DEVICE;
+    std::atomic<size_t> next_job{0};
+    auto worker = [&]() {
+      for (;;) {
+        const size_t k = next_job.fetch_add(1);
+        if (k >= todo.size()) return;
+        const int32_t r = todo[k];
+        if (status[r]) continue;
+        const double* hx = static_cast<const double*>(ctxs[r]->hostX);
+        std::memset(&hv[r], 0, sizeof(hv[r]));
+        const int t = tess(tess_users[r], hx, hx + nc[r], nc[r], ctxs[r]->cur.box,
+                           ctxs[r]->cur.bc, &hv[r]);
+        if (t != 0) {
+          status[r] = RICH_E_MESH;
+        } else if (hv[r].n_cells != nc[r]) {
+          release(tess_users[r], &hv[r]);
+          status[r] = RICH_E_MESH;
+        }
+      }
+    };
+    const int nt = std::max(1, std::min<int>(n_threads > 0 ? n_threads : 1, (int)todo.size()));
+    std::vector<std::thread> pool;
+    try {
+      for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+    } catch (...) {
+      // fewer threads: the calling thread still drains the queue
+    }
+    worker();
+    for (auto& t : pool) t.join();
+    int err = RICH_OK;
+    std::vector<int32_t> uploaded;
+    for (int32_t r : todo) {
+      if (status[r]) continue;
+      const int u = ctxs[r]->spare.upload_async(&hv[r], ctxs[r]->cur.box, ctxs[r]->cur.bc, st);
+      if (u) {
+        status[r] = u;
+        if (u == RICH_E_DEVICE) err = u;
+      }
+      uploaded.push_back(r);   // released after the synchronisation below
+    }
+    const bool synced = hipStreamSynchronize(st) == hipSuccess;
+    for (int32_t r : uploaded) release(tess_users[r], &hv[r]);
+    if (!synced) return RICH_E_DEVICE;
+    return err;
+  };
+
+  if ((rc = stage(false))) return fail_all(rc);
+  if (any_motion) {
+    if ((rc = retessellate(half))) return fail_all(rc);
+    for (int32_t r = 0; r < n; ++r)
+      if (!status[r] && params[r]->motion) ctxs[r]->spare.view(&mesh[r]);
+  }
+  if ((rc = stage(true))) return fail_all(rc);
+  // the final meshes go into the spare buffers; a run's current mesh is
+  // replaced only once its whole step has succeeded
+  if (any_motion && (rc = retessellate(next))) return fail_all(rc);
+  for (int32_t r = 0; r < n; ++r) {
+    if (status[r]) continue;
+    const size_t b = 8 * (size_t)nc[r];
+    const double* sq[6] = {next[r].M, next[r].Px, next[r].Py, next[r].E, next[r].x, next[r].y};
+    double* dq[6] = {states[r]->M, states[r]->Px, states[r]->Py, states[r]->E, states[r]->x,
+                     states[r]->y};
+    for (int k = 0; k < 6; ++k)
+      if (hipMemcpyAsync(dq[k], sq[k], b, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return fail_all(RICH_E_DEVICE);
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) return fail_all(RICH_E_DEVICE);
+  for (int32_t r = 0; r < n; ++r)
+    if (!status[r] && params[r]->motion) std::swap(ctxs[r]->cur, ctxs[r]->spare);
+  for (int32_t r = 0; r < n; ++r)
+    if (status[r]) return status[r];
   return RICH_OK;
 }
 

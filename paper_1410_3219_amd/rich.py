@@ -44,7 +44,7 @@ class RichParams(C.Structure):
         ("gamma", C.c_double), ("cfl", C.c_double), ("theta", C.c_double),
         ("delta_v", C.c_double), ("delta_p", C.c_double), ("chi", C.c_double),
         ("eta", C.c_double), ("riemann", C.c_int32), ("motion", C.c_int32),
-        ("limiter", C.c_int32),
+        ("limiter", C.c_int32), ("gx", C.c_double), ("gy", C.c_double),
     ]
 
 
@@ -75,10 +75,13 @@ class Params:
     riemann: int = 0
     motion: int = 1
     limiter: int = 0
+    gx: float = 0.0     # uniform external acceleration
+    gy: float = 0.0
 
     def c(self):
         return RichParams(self.gamma, self.cfl, self.theta, self.delta_v, self.delta_p,
-                          self.chi, self.eta, self.riemann, self.motion, self.limiter)
+                          self.chi, self.eta, self.riemann, self.motion, self.limiter,
+                          self.gx, self.gy)
 
 
 class RichError(RuntimeError):
@@ -118,7 +121,9 @@ def lib():
                                            C.POINTER(_vp), C.POINTER(_vp), _dp, C.POINTER(_vp),
                                            _vp, C.c_size_t, _vp]
             L.rich_batch_flags.argtypes = [C.c_int32, _vp, _vp, _ip]
-            for f in ("rich_batch_workspace_size", "rich_stage_batch", "rich_batch_flags"):
+            L.rich_batch_flags_async.argtypes = [C.c_int32, _vp, _vp, _vp]
+            for f in ("rich_batch_workspace_size", "rich_stage_batch", "rich_batch_flags",
+                      "rich_batch_flags_async"):
                 getattr(L, f).restype = C.c_int
         if hasattr(L, "rich_step"):
             L.rich_ctx_create.argtypes = [C.POINTER(_vp)]
@@ -127,7 +132,11 @@ def lib():
             L.rich_ctx_set_mesh.argtypes = [_vp, C.POINTER(HostMeshView), _dp, C.c_uint32, _vp]
             L.rich_ctx_mesh.argtypes = [_vp, mp]
             L.rich_step.argtypes = [_vp, sp, C.c_double, pp, _vp, _vp, _vp, _vp]
-            for f in ("rich_ctx_create", "rich_ctx_set_mesh", "rich_ctx_mesh", "rich_step"):
+            L.rich_step_batch.argtypes = [C.c_int32, C.POINTER(_vp), C.POINTER(_vp), _dp,
+                                          C.POINTER(_vp), _vp, _vp, C.POINTER(_vp), C.c_int32,
+                                          _ip, _vp, C.c_size_t, _vp]
+            for f in ("rich_ctx_create", "rich_ctx_set_mesh", "rich_ctx_mesh", "rich_step",
+                      "rich_step_batch"):
                 getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -320,6 +329,15 @@ def rich_batch_flags(n, ws, stream=None):
     return list(f)
 
 
+def rich_batch_flags_async(n, ws, host_flags, stream=None):
+    """Enqueue the copy of the n flag words into host_flags (a pinned int32
+    CPU tensor of at least n elements); valid once the stream passes it."""
+    assert host_flags.dtype.itemsize == 4 and host_flags.numel() >= n
+    _check(lib().rich_batch_flags_async(n, C.c_void_p(ws.data_ptr()), _stream_ptr(stream),
+                                        C.c_void_p(host_flags.data_ptr())),
+           "rich_batch_flags_async")
+
+
 # ---------------------------------------------------------------------------
 # time-centred step driver
 # ---------------------------------------------------------------------------
@@ -395,3 +413,27 @@ class RichCtx:
         st = lib().rich_step(self.h, C.byref(state.c()), float(dt), C.byref(params.c()),
                              self.tess_fn, self.release_fn, self.tess_user, _stream_ptr(stream))
         _check(st, "rich_step")
+
+
+def rich_step_batch(ctxs, states, dts, params, ws, n_threads=0, stream=None):
+    """Time-centred step of len(ctxs) runs (RichCtx each) with batched stage
+    launches; returns the per-run status list (0: committed).  Raises only
+    when the call as a whole failed."""
+    n = len(ctxs)
+    ad = C.addressof
+    cp = (_vp * n)(*[c.h.value for c in ctxs])
+    spp = (_vp * n)(*[ad(s.c()) for s in states])
+    dd = (C.c_double * n)(*[float(x) for x in dts])
+    pc = [p.c() for p in params]
+    ppp = (_vp * n)(*[ad(x) for x in pc])
+    users = (_vp * n)(*[c.tess_user.value for c in ctxs])
+    status = (C.c_int32 * n)()
+    t0 = ctxs[0]
+    nt = int(n_threads) if n_threads > 0 else (os.cpu_count() or 1)
+    rc = lib().rich_step_batch(n, cp, spp, dd, ppp, t0.tess_fn, t0.release_fn, users, nt,
+                               status, C.c_void_p(ws.data_ptr()), ws.numel(),
+                               _stream_ptr(stream))
+    st = list(status)
+    if rc != RICH_OK and not any(st):   # rejected before any run was looked at
+        _check(rc, "rich_step_batch")
+    return st   # st[r] == 0: run r was committed

@@ -6,12 +6,13 @@ scheduler:
 
   * admits a session when the device memory it needs (state buffers, the
     workspace share) fits the HBM budget, otherwise the session waits;
-  * on every tick gathers the next stage of every admitted request (stage 1
-    of new requests, stage 2 of those whose stage 1 finished) into ONE
-    batched launch (rich_stage_batch), so requests that arrive while others
-    are on the GPU join the next launch as slots free up;
-  * completes a request when its stage 2 finishes and records its latency
-    (arrival -> completion event).
+  * on every tick gathers every ready request (admitted session, none of
+    its requests on the device) into one launch pair: stage 1 of all of them
+    as one batched launch, then stage 2 as another, back to back on the
+    stream; requests that arrive while launches are on the device join the
+    next pair, and up to two pairs are in flight at once;
+  * completes the requests of a pair when its event has passed, checks the
+    per-run flags and records each latency (arrival -> completion).
 
 Meshes are served from a pool of templates tessellated once by the host
 stage and shared read-only by the sessions built on them (static mesh: the
@@ -43,6 +44,7 @@ class Template:
     X0: np.ndarray
     params: "R.Params"
     dt: float
+    state0: "R.DeviceState" = None   # initial state on the device (copied per session)
 
 
 @dataclass
@@ -63,7 +65,7 @@ class Request:
     rid: int
     sid: int
     arrival: float
-    phase: int = 0          # 0 waiting, 1 stage 1 in flight, 2 stage 2 in flight
+    phase: int = 0          # 0 waiting, 1 on the device
     done: float = -1.0
 
 
@@ -86,23 +88,37 @@ def build_templates(sizes, kinds, seed=11, n_threads=0):
         s = R.DeviceState.from_host(Q, X)
         ws = R.workspace(m.n_cells)
         dt = R.rich_cfl_dt(dm, s, params, ws)
-        out.append(Template(f"{kind}{m.n_cells}", m.n_cells, dm, Q, X, params, 0.5 * dt))
+        out.append(Template(f"{kind}{m.n_cells}", m.n_cells, dm, Q, X, params, 0.5 * dt, s))
     return out
 
 
 class Server:
-    def __init__(self, templates, hbm_budget_bytes=16 << 30, keep_final=False):
+    """Continuous batching of step requests over device-resident sessions.
+
+    A launch takes every request that is ready (session admitted, no other
+    request of the same session on the device) and issues both stages of its
+    step back to back as two batched launches on one stream, so stage 2 needs
+    no host round trip; up to `max_inflight` such launch pairs are on the
+    device at once, each with its own workspaces, while the host gathers the
+    next.  Sessions are admitted in arrival order while their device memory
+    fits the budget and released when their last request completes."""
+
+    def __init__(self, templates, hbm_budget_bytes=16 << 30, keep_final=False,
+                 max_inflight=2):
         import torch
         self.torch = torch
         self.templates = templates
         self.budget = hbm_budget_bytes
         self.keep_final = keep_final
+        self.max_inflight = max_inflight
         self.used = 0
         self.max_used = 0
         self.sessions = {}
         self.waiting = []          # sessions not yet admitted (FIFO)
-        self.queue = []            # requests not yet started
-        self.inflight = None       # (event, [(req, stage)], ws)
+        self.queue = []            # requests not yet completed, in arrival order
+        self.inflight = []         # [(event, [req], ws1, ws2, host flags)]
+        self.ws_pool = []          # idle batch workspaces
+        self.busy = set()          # sessions with a request on the device
         self.done = []
         self.launches = 0
         self.batch_sizes = []
@@ -112,8 +128,20 @@ class Server:
     # -- sessions ---------------------------------------------------------
     @staticmethod
     def session_bytes(n):
-        # three state buffers (Q: 32 B, X: 16 B per cell) + workspace share
-        return 3 * 48 * n + R.rich_workspace_size(n)
+        # three state buffers (Q: 32 B, X: 16 B per cell) and the session's
+        # share of the two workspaces of its launch pair
+        return 3 * 48 * n + 2 * R.rich_workspace_size(n)
+
+    def _ws(self, n_cells):
+        """A batch workspace for these runs from the pool of idle ones (the
+        smallest that fits), else a new one with 25 % headroom."""
+        need = R.rich_batch_workspace_size(n_cells)
+        fit = [k for k, w in enumerate(self.ws_pool) if w.numel() >= need]
+        if fit:
+            k = min(fit, key=lambda j: self.ws_pool[j].numel())
+            return self.ws_pool.pop(k)
+        import torch
+        return torch.empty(need + need // 4, dtype=torch.uint8, device="cuda")
 
     def open_session(self, sid, tpl_index, steps):
         tpl = self.templates[tpl_index]
@@ -125,7 +153,11 @@ class Server:
     def _admit(self):
         while self.waiting and self.used + self.waiting[0].bytes <= self.budget:
             s = self.waiting.pop(0)
-            s.cur = R.DeviceState.from_host(s.tpl.Q0, s.tpl.X0)
+            t0 = s.tpl.state0
+            if t0 is not None:   # device-to-device copy of the template's state
+                s.cur = R.DeviceState(t0.Q.clone(), t0.X.clone())
+            else:
+                s.cur = R.DeviceState.from_host(s.tpl.Q0, s.tpl.X0)
             s.half = R.DeviceState.empty_like(s.cur)
             s.nxt = R.DeviceState.empty_like(s.cur)
             s.admitted = True
@@ -144,104 +176,109 @@ class Server:
         self.queue.append(Request(rid, sid, arrival))
 
     def _launch(self):
-        """Gather the ready stages of admitted sessions into one launch."""
         items = []
-        busy = set()
+        seen = set()
         for req in self.queue:
             s = self.sessions[req.sid]
-            if not s.admitted or req.sid in busy:
+            if req.phase or not s.admitted or req.sid in self.busy or req.sid in seen:
                 continue
-            busy.add(req.sid)     # one request per session per launch
+            seen.add(req.sid)     # a session's requests run in order
             items.append(req)
         if not items:
             return False
-        meshes, srcs, bases, outs, hs, ps, work = [], [], [], [], [], [], []
-        for req in items:
-            s = self.sessions[req.sid]
-            meshes.append(s.tpl.mesh)
-            ps.append(s.tpl.params)
-            if req.phase == 0:        # stage 1: (Q^n, Q^n, x^n, dt/2)
-                srcs.append(s.cur); bases.append(s.cur); outs.append(s.half)
-                hs.append(0.5 * s.tpl.dt)
-                work.append((req, 1))
-            else:                     # stage 2: (Q^{n+1/2}, Q^n, x^n, dt)
-                srcs.append(s.half); bases.append(s.cur); outs.append(s.nxt)
-                hs.append(s.tpl.dt)
-                work.append((req, 2))
-        ws = R.batch_workspace([m.n_cells for m in meshes])
-        R.rich_stage_batch(meshes, srcs, bases, outs, hs, ps, ws, self.stream)
+        ss = [self.sessions[r.sid] for r in items]
+        meshes = [s.tpl.mesh for s in ss]
+        ps = [s.tpl.params for s in ss]
+        ns = [m.n_cells for m in meshes]
+        ws1, ws2 = self._ws(ns), self._ws(ns)
+        # stage 1: (Q^n, Q^n, x^n, dt/2) -> half; stage 2: (half, Q^n, x^n, dt) -> nxt
+        R.rich_stage_batch(meshes, [s.cur for s in ss], [s.cur for s in ss],
+                           [s.half for s in ss], [0.5 * s.tpl.dt for s in ss], ps, ws1,
+                           self.stream)
+        R.rich_stage_batch(meshes, [s.half for s in ss], [s.cur for s in ss],
+                           [s.nxt for s in ss], [s.tpl.dt for s in ss], ps, ws2, self.stream)
+        # both stages' flag words come back with the launch (no stream sync)
+        flags = self.torch.empty((2, len(items)), dtype=self.torch.int32, pin_memory=True)
+        R.rich_batch_flags_async(len(items), ws1, flags[0], self.stream)
+        R.rich_batch_flags_async(len(items), ws2, flags[1], self.stream)
         ev = self.torch.cuda.Event()
         ev.record(self.stream)
-        for req, stage in work:
-            req.phase = stage
-        self.inflight = (ev, work, ws)
+        for r in items:
+            r.phase = 1
+            self.busy.add(r.sid)
+        self.inflight.append((ev, items, ws1, ws2, flags))
         self.launches += 1
-        self.batch_sizes.append(len(work))
+        self.batch_sizes.append(len(items))
         return True
 
     def _complete(self, now_fn):
-        ev, work, ws = self.inflight
-        if not ev.query():
-            return False
-        flags = R.rich_batch_flags(len(work), ws, self.stream)
-        t = now_fn()
-        for (req, stage), f in zip(work, flags):
-            s = self.sessions[req.sid]
-            if f:
-                raise RuntimeError(f"session {req.sid} stage {stage} flagged {f}")
-            if stage == 2:
+        progressed = False
+        while self.inflight and self.inflight[0][0].query():
+            ev, items, ws1, ws2, flags = self.inflight.pop(0)
+            f1, f2 = flags[0].tolist(), flags[1].tolist()
+            self.ws_pool += [ws1, ws2]
+            if len(self.ws_pool) > 4 * self.max_inflight:   # keep the largest idle ones
+                self.ws_pool.sort(key=lambda t: t.numel())
+                del self.ws_pool[:len(self.ws_pool) - 4 * self.max_inflight]
+            t = now_fn()
+            for req, a, b in zip(items, f1, f2):
+                s = self.sessions[req.sid]
+                if a or b:
+                    raise RuntimeError(f"session {req.sid} flagged {a}/{b}")
                 s.cur, s.nxt = s.nxt, s.cur
                 req.done = t
                 self.done.append(req)
-                self.queue.remove(req)
+                self.busy.discard(req.sid)
                 self.cells_done += s.tpl.n
                 s.steps_left -= 1
                 if s.steps_left == 0:
                     self._close(s)
-        self.inflight = None
-        return True
+            progressed = True
+        if progressed:   # one pass over the queue per completion, not per request
+            self.queue = [r for r in self.queue if r.done < 0]
+        return progressed
 
     def tick(self, now_fn):
-        if self.inflight is not None and not self._complete(now_fn):
-            return
+        self._complete(now_fn)
         self._admit()
-        self._launch()
+        if len(self.inflight) < self.max_inflight:
+            self._launch()
 
     def drain(self, now_fn, timeout_s=600.0):
         t0 = time.perf_counter()
-        while self.queue or self.inflight is not None:
+        while self.queue or self.inflight:
             self.tick(now_fn)
             if time.perf_counter() - t0 > timeout_s:
                 raise RuntimeError("serving loop did not drain")
 
 
 def run(templates, rate=2000.0, duration=2.0, steps_per_session=8, seed=9,
-        hbm_budget_bytes=16 << 30, tpl_choice=None, keep_final=False, log=None):
-    """Poisson arrivals of step requests; each session issues its requests in
-    order (a session's next request arrives after the previous one).  Returns
-    latency percentiles and throughput."""
+        hbm_budget_bytes=16 << 30, tpl_choice=None, keep_final=False, max_inflight=2,
+        log=None):
+    """Poisson arrivals of step requests; requests k*S .. k*S+S-1 (S =
+    steps_per_session) are the steps of session k, which opens when its
+    first request arrives.  Returns latency percentiles (arrival ->
+    completion seen by the host) and throughput."""
     import torch
     arrivals = I.poisson_arrivals(rate, duration, seed)
     n_req = len(arrivals)
-    n_sess = max(1, n_req // steps_per_session)
-    # request k belongs to session k % n_sess, so a session's step count is
-    # the number of requests that map to it
-    counts = np.bincount(np.arange(n_req) % n_sess, minlength=n_sess)
+    n_sess = max(1, (n_req + steps_per_session - 1) // steps_per_session)
     s = I.Stream(seed + 1)
     pick = s.uniform(n_sess)
-    srv = Server(templates, hbm_budget_bytes, keep_final)
-    for sid in range(n_sess):
-        ti = tpl_choice[sid] if tpl_choice is not None else int(pick[sid] * len(templates))
-        if counts[sid]:
-            srv.open_session(sid, ti, int(counts[sid]))
+    srv = Server(templates, hbm_budget_bytes, keep_final, max_inflight)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0   # noqa: E731
     k = 0
-    while k < n_req or srv.queue or srv.inflight is not None:
+    while k < n_req or srv.queue or srv.inflight:
         t = now()
         while k < n_req and arrivals[k] <= t:
-            srv.submit(k, k % n_sess, arrivals[k])
+            sid = k // steps_per_session
+            if k % steps_per_session == 0:
+                ti = (tpl_choice[sid] if tpl_choice is not None
+                      else int(pick[sid] * len(templates)))
+                srv.open_session(sid, ti, min(steps_per_session, n_req - k))
+            srv.submit(k, sid, arrivals[k])
             k += 1
         srv.tick(now)
         if now() > duration * 50 + 120:
@@ -252,6 +289,7 @@ def run(templates, rate=2000.0, duration=2.0, steps_per_session=8, seed=9,
                mean_batch=float(np.mean(srv.batch_sizes)) if srv.batch_sizes else 0.0,
                p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
                cell_updates_per_s=srv.cells_done / wall, wall_s=wall, offered_rate=rate,
+               offered_cell_updates_per_s=rate * float(np.mean([t.n for t in templates])),
                hbm_budget_bytes=hbm_budget_bytes, max_admitted_bytes=srv.max_used)
     if log:
         log(f"[serve] {res}")

@@ -21,7 +21,7 @@ def host_mesh(px, py, box, bc):
     return T.rich_tess_build(px, py, box, bc)
 
 
-def case(name, k=24, riemann=0, limiter=0, motion=1, pass2=False, seed=1):
+def case(name, k=24, riemann=0, limiter=0, motion=1, pass2=False, seed=1, g=(0.0, 0.0)):
     """(mesh, Qsrc, Qbase, Xbase, h, oracle Params)."""
     if name == "sod":
         P = I.sod(k=k, seed=seed)
@@ -53,7 +53,8 @@ def case(name, k=24, riemann=0, limiter=0, motion=1, pass2=False, seed=1):
         Q = P.state(m.area)
     else:
         raise ValueError(name)
-    p = O.Params(gamma=P.gamma, riemann=riemann, limiter=limiter, motion=motion)
+    p = O.Params(gamma=P.gamma, riemann=riemann, limiter=limiter, motion=motion,
+                 gx=g[0], gy=g[1])
     X = np.stack([m.px, m.py])
     dt, st = O.cfl_dt(m, Q, p)
     assert st == 0
@@ -71,7 +72,7 @@ def gpu_params(p):
     from paper_1410_3219_amd import rich as R
     return R.Params(gamma=p.gamma, cfl=p.cfl, theta=p.theta, delta_v=p.delta_v,
                     delta_p=p.delta_p, chi=p.chi, eta=p.eta, riemann=p.riemann,
-                    motion=p.motion, limiter=p.limiter)
+                    motion=p.motion, limiter=p.limiter, gx=p.gx, gy=p.gy)
 
 
 def gpu_stage(m, Qs, Qb, Xb, h, p, repeat=1):

@@ -99,6 +99,34 @@ def _gpu_chain(P, m, Q, X, dts, p):
     return out
 
 
+def test_step_free_fall_and_gravity_chain():
+    """rich_step under a uniform acceleration: the oracle's chain on a
+    Kelvin-Helmholtz setup with gravity, and exact free fall of a uniform
+    gas (the closed form the oracle is pinned to)."""
+    P = I.kelvin_helmholtz(k=18)
+    m = T.rich_tess_build(P.px, P.py, P.box, P.bc)
+    Q = P.state(m.area)
+    X = np.stack([m.px, m.py])
+    p = O.Params(gamma=P.gamma, gx=0.2, gy=-0.9)
+    dt, _ = O.cfl_dt(m, Q, p)
+    Qo, Xo, mo = _oracle_chain(P, m, Q, X, [dt] * 3, p)
+    Qg, Xg = _gpu_chain(P, m, Q, X, [dt] * 3, p)
+    eq, ex = U.errors(mo, Qg, Xg, Qo, Xo, Qo, p)
+    assert (eq < 1e-11).all() and ex < 1e-12, (eq, ex)
+    v0, g, gam = (0.3, -0.2), (0.7, -1.3), 5.0 / 3.0
+    P = I.uniform_flow(k=16, v=v0, jitter=0.2, bc=1, gamma=gam)
+    m = T.rich_tess_build(P.px, P.py, P.box, P.bc)
+    Q = P.state(m.area)
+    X0 = np.stack([m.px, m.py])
+    p = O.Params(gamma=gam, chi=0.0, gx=g[0], gy=g[1])
+    Qg, Xg = _gpu_chain(P, m, Q, X0, [0.02] * 4, p)
+    t = 0.08
+    for q in range(2):
+        assert np.max(np.abs(Qg[1 + q] / Qg[0] - (v0[q] + g[q] * t))) < 1e-13
+        want = (X0[q] + v0[q] * t + 0.5 * g[q] * t * t) % 1.0
+        assert np.max(np.abs((Xg[q] - want + 0.5) % 1.0 - 0.5)) < 1e-13
+
+
 @pytest.mark.parametrize("name,motion", [("sod", 1), ("wave", 1), ("kh", 0)])
 def test_step_follows_oracle_chain(name, motion):
     if name == "sod":
@@ -158,3 +186,84 @@ def test_shock_tube_100_steps_drift_report():
     eq, ex = U.errors(mo, Qg, Xg, Qo, Xo, Qo, p)
     print(f"\nshock tube 64^2, 100 steps: drift per quantity {eq}, points {ex}")
     assert (eq < 1e-6).all()
+
+
+def _step_batch_runs():
+    """(problem, Params) of runs of uneven sizes: moving and static meshes,
+    walls and periodic boxes, both Riemann solvers."""
+    specs = [(I.sod(k=17, seed=3), dict(motion=1)),
+             (I.advected_wave(k=23, seed=4), dict(motion=1)),
+             (I.kelvin_helmholtz(k=14, seed=5), dict(motion=0)),
+             (I.sod(k=9, seed=6, angle=0.4, gamma=1.4), dict(motion=1, riemann=1)),
+             (I.gresho(k=20, seed=7), dict(motion=1, chi=0.5, eta=0.05))]
+    out = []
+    for P, kw in specs:
+        m = T.rich_tess_build(P.px, P.py, P.box, P.bc)
+        Q = P.state(m.area)
+        X = np.stack([m.px, m.py])
+        p = O.Params(gamma=P.gamma, **kw)
+        dt, st = O.cfl_dt(m, Q, p)
+        assert st == 0
+        out.append((m, Q, X, p, dt))
+    return out
+
+
+def _batch_chain(runs, steps, bad_run=None):
+    import torch
+    from paper_1410_3219_amd import rich as R
+    ctxs, states = [], []
+    for r, (m, Q, X, p, dt) in enumerate(runs):
+        c = R.RichCtx(n_threads=1)
+        c.set_mesh(m)
+        Qr = Q.copy()
+        if r == bad_run:
+            Qr[3, 3] = -1.0
+        ctxs.append(c)
+        states.append(R.DeviceState.from_host(Qr, X))
+    ws = R.batch_workspace([m.n_cells for m, *_ in runs])
+    all_status = []
+    for _ in range(steps):
+        st = R.rich_step_batch(ctxs, states, [r[4] for r in runs],
+                               [U.gpu_params(r[3]) for r in runs], ws, n_threads=4)
+        all_status.append(st)
+    torch.cuda.synchronize()
+    out = [s.numpy() for s in states]
+    meshes = [c.mesh().n_edges for c in ctxs]
+    for c in ctxs:
+        c.close()
+    return out, all_status, meshes
+
+
+def test_step_batch_equals_separate_steps_bitwise():
+    runs = _step_batch_runs()
+    res, status, _ = _batch_chain(runs, 3)
+    assert all(s == [0] * len(runs) for s in status), status
+    for (m, Q, X, p, dt), (Qb, Xb) in zip(runs, res):
+        Qs, Xs = _gpu_chain(None, m, Q, X, [dt] * 3, p)
+        assert np.array_equal(Qb, Qs) and np.array_equal(Xb, Xs)
+
+
+def test_step_batch_follows_oracle_chain():
+    runs = _step_batch_runs()
+    res, _, _ = _batch_chain(runs, 2)
+    for (m, Q, X, p, dt), (Qb, Xb) in list(zip(runs, res))[:2]:
+        Qo, Xo, mo = _oracle_chain(None, m, Q, X, [dt] * 2, p)
+        eq, ex = U.errors(mo, Qb, Xb, Qo, Xo, Qo, p)
+        assert (eq < 1e-11).all() and ex < 1e-12, (eq, ex)
+
+
+def test_step_batch_failure_is_isolated():
+    from paper_1410_3219_amd import rich as R
+    runs = _step_batch_runs()
+    good, _, _ = _batch_chain(runs, 1)
+    res, status, _ = _batch_chain(runs, 1, bad_run=1)
+    assert status[0][1] == R.RICH_E_DOMAIN
+    for r in range(len(runs)):
+        if r == 1:
+            # not committed: the state is the (bad) initial one
+            Q = runs[1][1].copy()
+            Q[3, 3] = -1.0
+            assert np.array_equal(res[1][0], Q) and np.array_equal(res[1][1], runs[1][2])
+            continue
+        assert status[0][r] == 0
+        assert np.array_equal(res[r][0], good[r][0]) and np.array_equal(res[r][1], good[r][1])

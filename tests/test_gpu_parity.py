@@ -33,6 +33,12 @@ def test_stage_hllc(name, k, pass2):
     _run(name, k=k, pass2=pass2)
 
 
+@pytest.mark.parametrize("name,pass2", [("sod", False), ("sod", True), ("kh", True),
+                                        ("sedov", False)])
+def test_stage_external_acceleration(name, pass2):
+    _run(name, k=29, pass2=pass2, g=(0.4, -1.1))
+
+
 @pytest.mark.parametrize("name", ["sod", "wave", "sedov"])
 def test_stage_exact_riemann(name):
     _run(name, k=27, riemann=1)

@@ -87,6 +87,14 @@ MUTATIONS = [
      "if (p->delta_p > ratio) shock = 1;",
      "if (p->delta_p < ratio) shock = 1;",
      [pins.shock_detector]),
+    ("acceleration source taken from the base state",
+     "double sm = Qsrc[i], spx = Qsrc[n + i], spy = Qsrc[2 * n + i];",
+     "double sm = Qbase[i], spx = Qbase[n + i], spy = Qbase[2 * n + i];",
+     [pins.free_fall]),
+    ("work of the external acceleration dropped",
+     "Qout[3 * n + i] += h * (spx * p->gx + spy * p->gy);",
+     "Qout[3 * n + i] += 0.0 * h * (spx * p->gx + spy * p->gy);",
+     [pins.free_fall]),
     ("primitive pressure misses the kinetic energy",
      "double pr = (p->gamma - 1.0) * (E / A - 0.5 * rho * (vx * vx + vy * vy));",
      "double pr = (p->gamma - 1.0) * (E / A);",
