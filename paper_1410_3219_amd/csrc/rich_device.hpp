@@ -130,15 +130,19 @@ __device__ __forceinline__ NbE nb_edge(const RunDesc& d, int i, int entry, bool&
 // ---------------------------------------------------------------------------
 // Two reciprocals instead of four divisions: the results may differ from the
 // quotients in the last bit.
-__device__ __forceinline__ void prim_of(const RunDesc& d, int j, double& rho, double& vx,
-                                        double& vy, double& p) {
-  const double rA = 1.0 / d.area[j];
-  const double M = d.sM[j];
+__device__ __forceinline__ void prim_from(const RunDesc& d, double A, double M, double Px,
+                                          double Py, double E, double& rho, double& vx,
+                                          double& vy, double& p) {
+  const double rA = 1.0 / A;
   const double rM = 1.0 / M;
   rho = M * rA;
-  vx = d.sPx[j] * rM;
-  vy = d.sPy[j] * rM;
-  p = (d.gamma - 1.0) * (d.sE[j] * rA - 0.5 * rho * (vx * vx + vy * vy));
+  vx = Px * rM;
+  vy = Py * rM;
+  p = (d.gamma - 1.0) * (E * rA - 0.5 * rho * (vx * vx + vy * vy));
+}
+__device__ __forceinline__ void prim_of(const RunDesc& d, int j, double& rho, double& vx,
+                                        double& vy, double& p) {
+  prim_from(d, d.area[j], d.sM[j], d.sPx[j], d.sPy[j], d.sE[j], rho, vx, vy, p);
 }
 
 // Pressure-ratio test of the shock detector, min(pi/pj, pj/pi) < delta_p,
@@ -305,15 +309,14 @@ __device__ __forceinline__ void load_rec(const double* __restrict__ rec, int c, 
   }
 }
 
+// The flux of edge e = (i, ej) with midpoint (fx, fy), length L; point r_i
+// and the records of both sides given (rj unused for a wall).
 template <int RIEMANN>
-__device__ inline bool edge_flux(const RunDesc& d, int e, const double* ri, const double* rj_in,
-                                 double* LF) {
+__device__ inline bool edge_flux_at(const RunDesc& d, int i, uint32_t ej, double fx, double fy,
+                                    double L, double rix, double riy, const double* ri,
+                                    const double* rj_in, double* LF) {
   bool ok = true;
-  const int i = d.e_i[e];
-  const uint32_t ej = (uint32_t)d.e_j[e];
   const int code = (int)(ej >> 28);
-  const double fx = d.e_fx[e], fy = d.e_fy[e], L = d.e_len[e];
-  const double rix = d.px[i], riy = d.py[i];
   double phL[4], phR[4];
   {
     const double dx = fx - ri[R_SX], dy = fy - ri[R_SY];
@@ -380,6 +383,14 @@ __device__ inline bool edge_flux(const RunDesc& d, int e, const double* ri, cons
   LF[2] = L * fmy;
   LF[3] = L * fe;
   return ok;
+}
+
+template <int RIEMANN>
+__device__ inline bool edge_flux(const RunDesc& d, int e, const double* ri, const double* rj_in,
+                                 double* LF) {
+  const int i = d.e_i[e];
+  return edge_flux_at<RIEMANN>(d, i, (uint32_t)d.e_j[e], d.e_fx[e], d.e_fy[e], d.e_len[e],
+                               d.px[i], d.py[i], ri, rj_in, LF);
 }
 
 }  // namespace rich

@@ -41,7 +41,10 @@ namespace rich {
 #define RICH_LPC 2
 #endif
 #ifndef RICH_CELL_MAXE
-#define RICH_CELL_MAXE 8  // CSR entries per cell whose edge offsets stay in registers
+#define RICH_CELL_MAXE 6  // CSR entries per cell loaded level by level (the rest in a loop)
+#endif
+#ifndef RICH_FLUX_REC_LDS
+#define RICH_FLUX_REC_LDS 0  // k_flux: keep the tile's cell records in LDS
 #endif
 #ifndef RICH_CELL_WAVES
 #define RICH_CELL_WAVES 1  // minimum waves per SIMD the register budget must allow
@@ -49,10 +52,13 @@ namespace rich {
 #ifndef RICH_FLUX_WAVES
 #define RICH_FLUX_WAVES 1
 #endif
-constexpr int kTile = 256;        // k_flux: cells per tile = threads per block
-constexpr int kEdgeCap = 800;     // k_flux: owned-edge fluxes kept in LDS
-constexpr int kForCap = 192;      // k_flux: other edges kept in LDS
-constexpr int kMapCap = 2304;     // k_flux: CSR entries classified in LDS
+#ifndef RICH_FLUX_TILE
+#define RICH_FLUX_TILE 256
+#endif
+constexpr int kTile = RICH_FLUX_TILE;          // k_flux: cells per tile = threads per block
+constexpr int kEdgeCap = kTile * 25 / 8;       // k_flux: owned-edge fluxes kept in LDS
+constexpr int kForCap = kTile * 3 / 4;         // k_flux: other edges kept in LDS
+constexpr int kMapCap = kTile * 9;             // k_flux: CSR entries classified in LDS
 constexpr int kCellThreads = 256;   // k_cell: threads per block
 constexpr int kLpc = RICH_LPC;      // k_cell: lanes per cell
 constexpr int kNumXcd = 8;
@@ -210,18 +216,98 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
       }
       if (pressure_jump(d.delta_p, p, pj[3])) pflag = 1;
     };
+    // The first MAXE/LPC entries of each lane go level by level: all CSR
+    // entries, then all edges, then all neighbours, each level's loads issued
+    // together with in-range indices and no branch between them (an entry
+    // past the cell's end reads entry k0 and is ignored), so that a lane waits
+    // for three memory round trips instead of three per entry.
+    {
+      const int kc = max(0, min(k0, d.n_csr - 1));
+      bool val[MAXE];
+      int ent[MAXE];
 #pragma unroll
-    for (int m = 0; m < MAXE; ++m) {
-      const int k = k0 + lane + m * LPC;
-      fdx[m] = 0.0;
-      fdy[m] = 0.0;
-      if (k < k1) {
-        const NbE v = nb_edge(d, i, d.idx[k], bad);
-        double pj[4], vrx, vry;
-        nb_values(v, pj, vrx, vry);
-        accumulate(v, pj, vrx, vry);
-        fdx[m] = v.fx - six;
-        fdy[m] = v.fy - siy;
+      for (int m = 0; m < MAXE; ++m) {
+        const int k = k0 + lane + m * LPC;
+        val[m] = k < k1;
+        ent[m] = d.idx[val[m] ? k : kc];
+      }
+      int ee[MAXE];
+#pragma unroll
+      for (int m = 0; m < MAXE; ++m) {
+        int e = ent[m] >> 1;
+        if (val[m] && (e < 0 || e >= d.n_edges)) {
+          bad = true;
+          val[m] = false;
+        }
+        ee[m] = val[m] ? e : 0;
+      }
+      uint32_t ej[MAXE];
+      int ei[MAXE];
+      double eL[MAXE], efx[MAXE], efy[MAXE];
+#pragma unroll
+      for (int m = 0; m < MAXE; ++m) {
+        ej[m] = (uint32_t)d.e_j[ee[m]];
+        ei[m] = d.e_i[ee[m]];
+        eL[m] = d.e_len[ee[m]];
+        efx[m] = d.e_fx[ee[m]];
+        efy[m] = d.e_fy[ee[m]];
+      }
+      NbE v[MAXE];
+#pragma unroll
+      for (int m = 0; m < MAXE; ++m) {
+        const int side = ent[m] & 1;
+        const int code = (int)(ej[m] >> 28);
+        v[m].L = eL[m];
+        v[m].fx = efx[m];
+        v[m].fy = efy[m];
+        shift_of(d, code, v[m].shx, v[m].shy);
+        v[m].wall = (side == 0 && code >= 9) ? code : 0;
+        int j = side == 0 ? (int)(ej[m] & kCellMask) : ei[m];
+        if (side) {
+          v[m].shx = -v[m].shx;
+          v[m].shy = -v[m].shy;
+          v[m].fx += v[m].shx;
+          v[m].fy += v[m].shy;
+        }
+        if (v[m].wall) j = i;
+        if (val[m] && (j < 0 || j >= d.n)) {
+          bad = true;
+          j = i;
+        }
+        v[m].j = val[m] ? j : i;
+      }
+      double nA[MAXE], nM[MAXE], nPx[MAXE], nPy[MAXE], nE[MAXE], nx_[MAXE], ny_[MAXE];
+#pragma unroll
+      for (int m = 0; m < MAXE; ++m) {
+        const int j = v[m].j;
+        nA[m] = d.area[j];
+        nM[m] = d.sM[j];
+        nPx[m] = d.sPx[j];
+        nPy[m] = d.sPy[j];
+        nE[m] = d.sE[j];
+        nx_[m] = d.px[j];
+        ny_[m] = d.py[j];
+      }
+#pragma unroll
+      for (int m = 0; m < MAXE; ++m) {
+        fdx[m] = 0.0;
+        fdy[m] = 0.0;
+        if (val[m]) {
+          double pj[4], vrx, vry;
+          if (v[m].wall) {
+            pj[0] = rho;
+            mirror_vec(v[m].wall, vx, vy, pj[1], pj[2]);
+            pj[3] = p;
+            mirror_point(d, v[m].wall, rix, riy, vrx, vry);
+          } else {
+            prim_from(d, nA[m], nM[m], nPx[m], nPy[m], nE[m], pj[0], pj[1], pj[2], pj[3]);
+            vrx = nx_[m] + v[m].shx;
+            vry = ny_[m] + v[m].shy;
+          }
+          accumulate(v[m], pj, vrx, vry);
+          fdx[m] = v[m].fx - six;
+          fdy[m] = v[m].fy - siy;
+        }
       }
     }
     for (int k = k0 + lane + MAXE * LPC; k < k1; k += LPC) {
@@ -342,8 +428,24 @@ __device__ __forceinline__ double wrap_once(double v, double lo, double hi) {
   return v;
 }
 
+// Record of cell c: from the tile's copy in LDS when c lies in the tile
+// (srec != nullptr, rows of kRecPad doubles), else from the workspace.
+constexpr int kRecPad = kRecDoubles + 1;  // odd row stride: no LDS bank conflicts
+__device__ __forceinline__ void fetch_rec(const RunDesc& d, const double* srec, int c0, int nt,
+                                          int c, double* r) {
+  const int l = c - c0;
+  if (srec != nullptr && l >= 0 && l < nt) {
+#pragma unroll
+    for (int k = 0; k < kRecDoubles; ++k) r[k] = srec[l * kRecPad + k];
+  } else {
+    load_rec(d.rec, c, r);
+  }
+}
+
 template <int RIEMANN>
-__device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF) {
+__device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF,
+                                             const double* srec = nullptr, int c0 = 0,
+                                             int nt = 0) {
   double ri[kRecDoubles], rj[kRecDoubles];
   if (e < 0 || e >= d.n_edges) {
     LF[0] = LF[1] = LF[2] = LF[3] = 0.0;
@@ -355,11 +457,11 @@ __device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF
     LF[0] = LF[1] = LF[2] = LF[3] = 0.0;
     return false;
   }
-  load_rec(d.rec, i, ri);
+  fetch_rec(d, srec, c0, nt, i, ri);
   if ((ej >> 28) < 9) {
     int j = (int)(ej & kCellMask);
     if (j >= d.n) j = i;
-    load_rec(d.rec, j, rj);
+    fetch_rec(d, srec, c0, nt, j, rj);
   }
   return edge_flux<RIEMANN>(d, e, ri, rj, LF);
 }
@@ -370,8 +472,15 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
                                                 int n_runs, int n_tiles) {
   __shared__ double sF[4][kEdgeCap + kForCap];
   __shared__ int s_forE[kForCap];
-  __shared__ short s_map[kMapCap];
+  __shared__ short s_map[kMapCap];  // (flux slot << 1) | side, or -1
+  __shared__ int s_off[kTile + 1];  // the tile's CSR offsets
   __shared__ int s_nfor;
+#if RICH_FLUX_REC_LDS
+  __shared__ double s_rec[kTile * kRecPad];  // the tile's cell records
+  const double* srec = s_rec;
+#else
+  const double* srec = nullptr;
+#endif
   const int tid = (int)threadIdx.x;
   for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
     const int t = BATCH ? b : xcd_tile(b, n_tiles);
@@ -386,9 +495,19 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
     const int Sm = min(S, kMapCap);
     bool ok = true;
     if (tid == 0) s_nfor = 0;
+    for (int c = tid; c <= c1 - c0; c += kTile) s_off[c] = d.off[c0 + c];
+#if RICH_FLUX_REC_LDS
+    if (tid < c1 - c0) {
+      double r[kRecDoubles];
+      load_rec(d.rec, c0 + tid, r);
+#pragma unroll
+      for (int k = 0; k < kRecDoubles; ++k) s_rec[tid * kRecPad + k] = r[k];
+    }
+#endif
     __syncthreads();
     for (int s = tid; s < Sm; s += kTile) {
-      const int e = d.idx[kb + s] >> 1;
+      const int entry = d.idx[kb + s];
+      const int e = entry >> 1;
       int m = -1;
       if (e >= e0 && e < e0 + ne) {
         m = e - e0;
@@ -399,7 +518,7 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
           m = kEdgeCap + f;
         }
       }
-      s_map[s] = (short)m;
+      s_map[s] = (short)(m < 0 ? -1 : (m << 1) | (entry & 1));
     }
     __syncthreads();
     const int nfor = min(s_nfor, kForCap);
@@ -407,7 +526,7 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
       const int e = w < ne ? e0 + w : s_forE[w - ne];
       const int pos = w < ne ? w : kEdgeCap + (w - ne);
       double LF[4];
-      if (!flux_of_edge<RIEMANN>(d, e, LF)) ok = false;
+      if (!flux_of_edge<RIEMANN>(d, e, LF, srec, c0, c1 - c0)) ok = false;
 #pragma unroll
       for (int q = 0; q < 4; ++q) sF[q][pos] = LF[q];
     }
@@ -415,23 +534,27 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
     const int i = c0 + tid;
     if (i < c1) {
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      int k0 = d.off[i], k1 = d.off[i + 1];
+      int k0 = s_off[tid], k1 = s_off[tid + 1];
       if (k0 < kb || k1 < k0 || k1 > kb + S) {
         ok = false;
         k1 = k0;
       }
       for (int k = k0; k < k1; ++k) {
-        const int entry = d.idx[k];
         const int s = k - kb;
-        const int m = s < Sm ? (int)s_map[s] : -1;
+        const int ms = s < Sm ? (int)s_map[s] : -1;
         double LF[4];
-        if (m >= 0) {
+        int side;
+        if (ms >= 0) {
+          const int m = ms >> 1;
+          side = ms & 1;
 #pragma unroll
           for (int q = 0; q < 4; ++q) LF[q] = sF[q][m];
         } else {
-          if (!flux_of_edge<RIEMANN>(d, entry >> 1, LF)) ok = false;
+          const int entry = d.idx[k];
+          side = entry & 1;
+          if (!flux_of_edge<RIEMANN>(d, entry >> 1, LF, srec, c0, c1 - c0)) ok = false;
         }
-        if (entry & 1) {
+        if (side) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) acc[q] -= LF[q];
         } else {
@@ -451,9 +574,14 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
         Py += h * (sm * d.gy);
         E += h * (spx * d.gx + spy * d.gy);
       }
+#if RICH_FLUX_REC_LDS
+      const double wxi = s_rec[tid * kRecPad + R_WX], wyi = s_rec[tid * kRecPad + R_WY];
+#else
       const double* rec = d.rec + (size_t)i * kRecDoubles;
-      double x = d.bx[i] + h * rec[R_WX];
-      double y = d.by[i] + h * rec[R_WY];
+      const double wxi = rec[R_WX], wyi = rec[R_WY];
+#endif
+      double x = d.bx[i] + h * wxi;
+      double y = d.by[i] + h * wyi;
       if (d.bc == RICH_BOUNDARY_PERIODIC) {
         x = wrap_once(x, d.x0, d.x1);
         y = wrap_once(y, d.y0, d.y1);
