@@ -49,12 +49,36 @@ extern "C" {
 #define RICH_BOUNDARY_WALLS    0u
 #define RICH_BOUNDARY_PERIODIC 1u
 
-/* Mesh of one run (device pointers, borrowed). */
+/*
+ * Device layout of a mesh: one record per cell and one per edge, so that a
+ * gather of a neighbour's geometry or of an edge takes two 16-byte loads.
+ * The values are those of the host stage's arrays (rich_tess.h), rearranged
+ * bit for bit by rich_mesh_pack.
+ *   rich_cell  px, py  mesh-generating point
+ *              area    cell area
+ *              sx, sy  centroid (in the frame of the point)
+ *   rich_edge  fx, fy  Voronoi edge midpoint (in the frame of cell i)
+ *              len     edge length
+ *              i       first cell (edges sorted by i)
+ *              j       neighbour cell (low 28 bits) and ghost code (top 4
+ *                      bits), as e_j of the host stage
+ * Both arrays must be 16-byte aligned.
+ */
+typedef struct rich_cell {
+  double px, py, area, sx, sy, pad;
+} rich_cell;
+typedef struct rich_edge {
+  double fx, fy, len;
+  int32_t i, j;
+} rich_edge;
+
+/* Mesh of one run (device pointers, borrowed).  off[n_cells+1], idx[n_csr]
+ * (2*edge + side, each cell's entries counter-clockwise) and eoff[n_cells+1]
+ * (first edge of each cell) as in the host stage. */
 typedef struct rich_mesh {
   int64_t n_cells, n_edges, n_csr;
-  const double *px, *py, *sx, *sy, *area;
-  const int32_t *e_i, *e_j;
-  const double *e_len, *e_fx, *e_fy;
+  const rich_cell* cells;
+  const rich_edge* edges;
   const int32_t *off, *idx, *eoff;
   double box[4];  /* x0, y0, x1, y1 */
   uint32_t bc;    /* RICH_BOUNDARY_* */
@@ -162,6 +186,9 @@ typedef struct rich_host_mesh_view {
   const double *e_len, *e_fx, *e_fy;
   const int32_t *off, *idx, *eoff;
 } rich_host_mesh_view;
+/* Host helper: rearrange a host mesh's cell and edge arrays into the device
+ * records (host memory: cells[n_cells], edges[n_edges], caller-owned). */
+int rich_mesh_pack(const rich_host_mesh_view* hm, rich_cell* cells, rich_edge* edges);
 typedef int (*rich_tess_fn)(void* user, const double* px, const double* py,
                             int64_t n, const double box[4], uint32_t bc,
                             rich_host_mesh_view* out);

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rich.h"
+
 namespace rich {
 
 constexpr double kPi = 3.14159265358979323846;
@@ -25,9 +27,8 @@ constexpr int kRecDoubles = 16;  // reconstruction record: 128 bytes per cell
 // as a kernel argument for a single run, stored in device memory for a batch.
 struct RunDesc {
   // mesh
-  const double *px, *py, *sx, *sy, *area;
-  const int32_t *e_i, *e_j;
-  const double *e_len, *e_fx, *e_fy;
+  const rich_cell* cells;
+  const rich_edge* edges;
   const int32_t *off, *idx, *eoff;
   // state
   const double *sM, *sPx, *sPy, *sE;              // primitives come from here
@@ -49,6 +50,50 @@ struct RunDesc {
 // Record layout (doubles): 0..3 rho, vx, vy, p; 4..11 limited gradients
 // (d/dx, d/dy of rho, vx, vy, p); 12..13 point velocity; 14..15 centroid.
 enum { R_RHO = 0, R_VX, R_VY, R_P, R_G = 4, R_WX = 12, R_WY, R_SX, R_SY };
+
+// ---------------------------------------------------------------------------
+// mesh records: 16-byte loads
+// ---------------------------------------------------------------------------
+struct EdgeRec {
+  double fx, fy, L;
+  int i;
+  uint32_t j;
+};
+__device__ __forceinline__ EdgeRec load_edge(const RunDesc& d, int e) {
+  const double2 a = reinterpret_cast<const double2*>(d.edges + e)[0];
+  const int4 b = reinterpret_cast<const int4*>(d.edges + e)[1];
+  EdgeRec r;
+  r.fx = a.x;
+  r.fy = a.y;
+  r.L = __hiloint2double(b.y, b.x);
+  r.i = b.z;
+  r.j = (uint32_t)b.w;
+  return r;
+}
+// point of cell c (one load); point and area (two); all (three)
+__device__ __forceinline__ void load_point(const RunDesc& d, int c, double& px, double& py) {
+  const double2 a = reinterpret_cast<const double2*>(d.cells + c)[0];
+  px = a.x;
+  py = a.y;
+}
+__device__ __forceinline__ void load_point_area(const RunDesc& d, int c, double& px, double& py,
+                                                double& area) {
+  const double2* p = reinterpret_cast<const double2*>(d.cells + c);
+  const double2 a = p[0], b = p[1];
+  px = a.x;
+  py = a.y;
+  area = b.x;
+}
+__device__ __forceinline__ void load_cell(const RunDesc& d, int c, double& px, double& py,
+                                          double& area, double& sx, double& sy) {
+  const double2* p = reinterpret_cast<const double2*>(d.cells + c);
+  const double2 a = p[0], b = p[1], g = p[2];
+  px = a.x;
+  py = a.y;
+  area = b.x;
+  sx = b.y;
+  sy = g.x;
+}
 
 // ---------------------------------------------------------------------------
 // mesh access
@@ -97,11 +142,12 @@ __device__ __forceinline__ NbE nb_edge(const RunDesc& d, int i, int entry, bool&
     bad = true;
     e = 0;
   }
-  const uint32_t ej = (uint32_t)d.e_j[e];
+  const EdgeRec er = load_edge(d, e);
+  const uint32_t ej = er.j;
   const int code = (int)(ej >> 28);
-  v.L = d.e_len[e];
-  v.fx = d.e_fx[e];
-  v.fy = d.e_fy[e];
+  v.L = er.L;
+  v.fx = er.fx;
+  v.fy = er.fy;
   shift_of(d, code, v.shx, v.shy);
   v.wall = 0;
   if (side == 0) {
@@ -112,7 +158,7 @@ __device__ __forceinline__ NbE nb_edge(const RunDesc& d, int i, int entry, bool&
     }
     v.j = (int)(ej & kCellMask);
   } else {
-    v.j = d.e_i[e];
+    v.j = er.i;
     v.shx = -v.shx;
     v.shy = -v.shy;
     v.fx += v.shx;
@@ -140,9 +186,9 @@ __device__ __forceinline__ void prim_from(const RunDesc& d, double A, double M, 
   vy = Py * rM;
   p = (d.gamma - 1.0) * (E * rA - 0.5 * rho * (vx * vx + vy * vy));
 }
-__device__ __forceinline__ void prim_of(const RunDesc& d, int j, double& rho, double& vx,
-                                        double& vy, double& p) {
-  prim_from(d, d.area[j], d.sM[j], d.sPx[j], d.sPy[j], d.sE[j], rho, vx, vy, p);
+__device__ __forceinline__ void prim_of(const RunDesc& d, int j, double area, double& rho,
+                                        double& vx, double& vy, double& p) {
+  prim_from(d, area, d.sM[j], d.sPx[j], d.sPy[j], d.sE[j], rho, vx, vy, p);
 }
 
 // Pressure-ratio test of the shock detector, min(pi/pj, pj/pi) < delta_p,
@@ -344,7 +390,10 @@ __device__ inline bool edge_flux_at(const RunDesc& d, int i, uint32_t ej, double
     const double* rj = rj_in;
     double shx, shy;
     shift_of(d, code, shx, shy);
-    const double rjx = d.px[j] + shx, rjy = d.py[j] + shy;
+    double rjx, rjy;
+    load_point(d, j, rjx, rjy);
+    rjx += shx;
+    rjy += shy;
     const double sjx = rj[R_SX] + shx, sjy = rj[R_SY] + shy;
     {
       const double dx = fx - sjx, dy = fy - sjy;
@@ -388,9 +437,10 @@ __device__ inline bool edge_flux_at(const RunDesc& d, int i, uint32_t ej, double
 template <int RIEMANN>
 __device__ inline bool edge_flux(const RunDesc& d, int e, const double* ri, const double* rj_in,
                                  double* LF) {
-  const int i = d.e_i[e];
-  return edge_flux_at<RIEMANN>(d, i, (uint32_t)d.e_j[e], d.e_fx[e], d.e_fy[e], d.e_len[e],
-                               d.px[i], d.py[i], ri, rj_in, LF);
+  const EdgeRec er = load_edge(d, e);
+  double rix, riy;
+  load_point(d, er.i, rix, riy);
+  return edge_flux_at<RIEMANN>(d, er.i, er.j, er.fx, er.fy, er.L, rix, riy, ri, rj_in, LF);
 }
 
 }  // namespace rich

@@ -35,6 +35,9 @@
 #include "rich.h"
 #include "rich_device.hpp"
 
+static_assert(sizeof(rich_cell) == 48, "rich_cell is three 16-byte chunks");
+static_assert(sizeof(rich_edge) == 32, "rich_edge is two 16-byte chunks");
+
 namespace rich {
 
 #ifndef RICH_LPC
@@ -155,11 +158,11 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
     const int i = active ? i0 : 0;
     bool bad = false;
 
+    double rix, riy, A, six, siy;
+    load_cell(d, i, rix, riy, A, six, siy);
     double rho, vx, vy, p;
-    prim_of(d, i, rho, vx, vy, p);
+    prim_of(d, i, A, rho, vx, vy, p);
     const double c = sqrt(d.gamma * p / rho);
-    const double rix = d.px[i], riy = d.py[i], six = d.sx[i], siy = d.sy[i];
-    const double A = d.area[i];
     const double R = sqrt(A / kPi);
     double wx = 0.0, wy = 0.0;
     if (d.motion) {
@@ -187,9 +190,11 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
         pj[3] = p;
         mirror_point(d, v.wall, rix, riy, rjx, rjy);
       } else {
-        prim_of(d, v.j, pj[0], pj[1], pj[2], pj[3]);
-        rjx = d.px[v.j] + v.shx;
-        rjy = d.py[v.j] + v.shy;
+        double Aj;
+        load_point_area(d, v.j, rjx, rjy, Aj);
+        prim_of(d, v.j, Aj, pj[0], pj[1], pj[2], pj[3]);
+        rjx += v.shx;
+        rjy += v.shy;
       }
     };
 
@@ -246,11 +251,12 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
       double eL[MAXE], efx[MAXE], efy[MAXE];
 #pragma unroll
       for (int m = 0; m < MAXE; ++m) {
-        ej[m] = (uint32_t)d.e_j[ee[m]];
-        ei[m] = d.e_i[ee[m]];
-        eL[m] = d.e_len[ee[m]];
-        efx[m] = d.e_fx[ee[m]];
-        efy[m] = d.e_fy[ee[m]];
+        const EdgeRec er = load_edge(d, ee[m]);
+        ej[m] = er.j;
+        ei[m] = er.i;
+        eL[m] = er.L;
+        efx[m] = er.fx;
+        efy[m] = er.fy;
       }
       NbE v[MAXE];
 #pragma unroll
@@ -280,13 +286,11 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
 #pragma unroll
       for (int m = 0; m < MAXE; ++m) {
         const int j = v[m].j;
-        nA[m] = d.area[j];
+        load_point_area(d, j, nx_[m], ny_[m], nA[m]);
         nM[m] = d.sM[j];
         nPx[m] = d.sPx[j];
         nPy[m] = d.sPy[j];
         nE[m] = d.sE[j];
-        nx_[m] = d.px[j];
-        ny_[m] = d.py[j];
       }
 #pragma unroll
       for (int m = 0; m < MAXE; ++m) {
@@ -451,8 +455,9 @@ __device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF
     LF[0] = LF[1] = LF[2] = LF[3] = 0.0;
     return false;
   }
-  const int i = d.e_i[e];
-  const uint32_t ej = (uint32_t)d.e_j[e];
+  const EdgeRec er = load_edge(d, e);
+  const int i = er.i;
+  const uint32_t ej = er.j;
   if (i < 0 || i >= d.n) {
     LF[0] = LF[1] = LF[2] = LF[3] = 0.0;
     return false;
@@ -463,7 +468,9 @@ __device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF
     if (j >= d.n) j = i;
     fetch_rec(d, srec, c0, nt, j, rj);
   }
-  return edge_flux<RIEMANN>(d, e, ri, rj, LF);
+  double rix, riy;
+  load_point(d, i, rix, riy);
+  return edge_flux_at<RIEMANN>(d, i, ej, er.fx, er.fy, er.L, rix, riy, ri, rj, LF);
 }
 
 template <int RIEMANN, bool BATCH>
@@ -626,15 +633,17 @@ __global__ __launch_bounds__(kCflThreads) void k_cfl(RunDesc d, double* block_ou
   __shared__ double smin[kCflThreads / 64];
   double t = INFINITY;
   for (int i = blockIdx.x * kCflThreads + threadIdx.x; i < d.n; i += gridDim.x * kCflThreads) {
+    double pxi, pyi, A, sxi, syi;
+    load_cell(d, i, pxi, pyi, A, sxi, syi);
     double rho, vx, vy, p;
-    prim_of(d, i, rho, vx, vy, p);
+    prim_of(d, i, A, rho, vx, vy, p);
     const double c = sqrt(d.gamma * p / rho);
-    const double R = sqrt(d.area[i] / kPi);
+    const double R = sqrt(A / kPi);
     double wx = 0.0, wy = 0.0;
     if (d.motion) {
       wx = vx;
       wy = vy;
-      const double dx = d.sx[i] - d.px[i], dy = d.sy[i] - d.py[i];
+      const double dx = sxi - pxi, dy = syi - pyi;
       const double dd = sqrt(dx * dx + dy * dy);
       if (dd > d.eta * R) {
         wx += d.chi * c * dx / dd;
@@ -680,8 +689,9 @@ size_t run_ws_bytes(int64_t n) {
 bool valid_mesh(const rich_mesh* m) {
   return m && m->n_cells > 0 && m->n_cells <= (int64_t)rich::kCellMask && m->n_edges >= 0 &&
          m->n_edges < (int64_t)INT32_MAX / 2 && m->n_csr >= 0 && m->n_csr < (int64_t)INT32_MAX &&
-         m->px && m->py && m->sx && m->sy && m->area && m->off && m->eoff &&
-         (m->n_edges == 0 || (m->e_i && m->e_j && m->e_len && m->e_fx && m->e_fy)) &&
+         m->cells && (reinterpret_cast<uintptr_t>(m->cells) & 15) == 0 && m->off && m->eoff &&
+         (m->n_edges == 0 ||
+          (m->edges && (reinterpret_cast<uintptr_t>(m->edges) & 15) == 0)) &&
          (m->n_csr == 0 || m->idx) && m->box[2] > m->box[0] && m->box[3] > m->box[1] &&
          (m->bc == RICH_BOUNDARY_WALLS || m->bc == RICH_BOUNDARY_PERIODIC);
 }
@@ -701,8 +711,8 @@ RunDesc make_desc(const rich_mesh* m, const rich_state* src, const rich_state* b
                   rich_state* out, double h, const rich_params* p, char* ws) {
   RunDesc d;
   std::memset(&d, 0, sizeof(d));
-  d.px = m->px; d.py = m->py; d.sx = m->sx; d.sy = m->sy; d.area = m->area;
-  d.e_i = m->e_i; d.e_j = m->e_j; d.e_len = m->e_len; d.e_fx = m->e_fx; d.e_fy = m->e_fy;
+  d.cells = m->cells;
+  d.edges = m->edges;
   d.off = m->off; d.idx = m->idx; d.eoff = m->eoff;
   d.sM = src->M; d.sPx = src->Px; d.sPy = src->Py; d.sE = src->E;
   if (base) {
@@ -892,7 +902,9 @@ struct DevBuf {
 };
 
 struct DevMesh {
-  DevBuf b[13];  // px py sx sy area e_i e_j e_len e_fx e_fy off idx eoff
+  DevBuf b[5];  // cells edges off idx eoff
+  std::vector<rich_cell> hc;  // host staging of the packed records
+  std::vector<rich_edge> he;
   int64_t n = 0, ne = 0, nc = 0;
   double box[4] = {0, 0, 1, 1};
   uint32_t bc = 0;
@@ -903,18 +915,23 @@ struct DevMesh {
     if (rc) return rc;
     return hipStreamSynchronize(st) == hipSuccess ? RICH_OK : RICH_E_DEVICE;
   }
-  // Enqueues the copies; the host arrays must stay valid until the stream
-  // has passed them.
+  // Enqueues the copies; the host arrays (and this object's staging) must
+  // stay valid until the stream has passed them.
   int upload_async(const rich_host_mesh_view* hm, const double* bx, uint32_t bcv,
                    hipStream_t st) {
     const int64_t n_ = hm->n_cells, ne_ = hm->n_edges, nc_ = hm->n_csr;
-    const void* src[13] = {hm->px, hm->py, hm->sx, hm->sy, hm->area, hm->e_i, hm->e_j,
-                           hm->e_len, hm->e_fx, hm->e_fy, hm->off, hm->idx, hm->eoff};
-    const size_t bytes[13] = {8 * (size_t)n_, 8 * (size_t)n_, 8 * (size_t)n_, 8 * (size_t)n_,
-                              8 * (size_t)n_, 4 * (size_t)ne_, 4 * (size_t)ne_,
-                              8 * (size_t)ne_, 8 * (size_t)ne_, 8 * (size_t)ne_,
-                              4 * (size_t)(n_ + 1), 4 * (size_t)nc_, 4 * (size_t)(n_ + 1)};
-    for (int k = 0; k < 13; ++k) {
+    try {
+      hc.resize((size_t)n_);
+      he.resize((size_t)std::max<int64_t>(ne_, 0));
+    } catch (...) {
+      return RICH_E_NOMEM;
+    }
+    int rc = rich_mesh_pack(hm, hc.data(), he.data());
+    if (rc) return rc;
+    const void* src[5] = {hc.data(), he.data(), hm->off, hm->idx, hm->eoff};
+    const size_t bytes[5] = {sizeof(rich_cell) * (size_t)n_, sizeof(rich_edge) * (size_t)ne_,
+                             4 * (size_t)(n_ + 1), 4 * (size_t)nc_, 4 * (size_t)(n_ + 1)};
+    for (int k = 0; k < 5; ++k) {
       if (bytes[k] && !src[k]) return RICH_E_INVAL;
       if (!b[k].ensure(bytes[k])) return RICH_E_NOMEM;
       if (bytes[k] &&
@@ -933,19 +950,18 @@ struct DevMesh {
     m->n_cells = n;
     m->n_edges = ne;
     m->n_csr = nc;
-    m->px = (const double*)b[0].p; m->py = (const double*)b[1].p;
-    m->sx = (const double*)b[2].p; m->sy = (const double*)b[3].p;
-    m->area = (const double*)b[4].p;
-    m->e_i = (const int32_t*)b[5].p; m->e_j = (const int32_t*)b[6].p;
-    m->e_len = (const double*)b[7].p; m->e_fx = (const double*)b[8].p;
-    m->e_fy = (const double*)b[9].p;
-    m->off = (const int32_t*)b[10].p; m->idx = (const int32_t*)b[11].p;
-    m->eoff = (const int32_t*)b[12].p;
+    m->cells = (const rich_cell*)b[0].p;
+    m->edges = (const rich_edge*)b[1].p;
+    m->off = (const int32_t*)b[2].p;
+    m->idx = (const int32_t*)b[3].p;
+    m->eoff = (const int32_t*)b[4].p;
     std::memcpy(m->box, box, sizeof(box));
     m->bc = bc;
   }
   void release() {
     for (auto& x : b) x.release();
+    std::vector<rich_cell>().swap(hc);
+    std::vector<rich_edge>().swap(he);
     set = false;
   }
 };
@@ -1194,6 +1210,33 @@ int rich_batch_flags_async(int32_t n, void* ws, void* stream, int32_t* host_flag
   if (hipMemcpyAsync(host_flags, static_cast<char*>(ws) + L.flags, (size_t)n * sizeof(int32_t),
                      hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream)) != hipSuccess)
     return RICH_E_DEVICE;
+  return RICH_OK;
+}
+
+int rich_mesh_pack(const rich_host_mesh_view* hm, rich_cell* cells, rich_edge* edges) {
+  if (!hm || hm->n_cells <= 0 || hm->n_edges < 0 || !cells || (hm->n_edges > 0 && !edges))
+    return RICH_E_INVAL;
+  if (!hm->px || !hm->py || !hm->sx || !hm->sy || !hm->area) return RICH_E_INVAL;
+  if (hm->n_edges > 0 &&
+      (!hm->e_i || !hm->e_j || !hm->e_len || !hm->e_fx || !hm->e_fy))
+    return RICH_E_INVAL;
+  for (int64_t c = 0; c < hm->n_cells; ++c) {
+    rich_cell& r = cells[c];
+    r.px = hm->px[c];
+    r.py = hm->py[c];
+    r.area = hm->area[c];
+    r.sx = hm->sx[c];
+    r.sy = hm->sy[c];
+    r.pad = 0.0;
+  }
+  for (int64_t e = 0; e < hm->n_edges; ++e) {
+    rich_edge& r = edges[e];
+    r.fx = hm->e_fx[e];
+    r.fy = hm->e_fy[e];
+    r.len = hm->e_len[e];
+    r.i = hm->e_i[e];
+    r.j = hm->e_j[e];
+  }
   return RICH_OK;
 }
 

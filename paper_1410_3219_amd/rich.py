@@ -27,11 +27,13 @@ _vp = C.c_void_p
 class RichMesh(C.Structure):
     _fields_ = [
         ("n_cells", C.c_int64), ("n_edges", C.c_int64), ("n_csr", C.c_int64),
-        ("px", _vp), ("py", _vp), ("sx", _vp), ("sy", _vp), ("area", _vp),
-        ("e_i", _vp), ("e_j", _vp), ("e_len", _vp), ("e_fx", _vp), ("e_fy", _vp),
+        ("cells", _vp), ("edges", _vp),
         ("off", _vp), ("idx", _vp), ("eoff", _vp),
         ("box", C.c_double * 4), ("bc", C.c_uint32),
     ]
+
+
+CELL_BYTES, EDGE_BYTES = 48, 32   # sizeof(rich_cell), sizeof(rich_edge)
 
 
 class RichState(C.Structure):
@@ -106,6 +108,8 @@ def lib():
         L.rich_stage.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, C.c_size_t, _vp]
         L.rich_stage_flags.argtypes = [_vp, _vp, _ip]
         L.rich_cfl_dt.argtypes = [mp, sp, pp, _dp, _vp, C.c_size_t, _vp]
+        L.rich_mesh_pack.argtypes = [C.POINTER(HostMeshView), _vp, _vp]
+        L.rich_mesh_pack.restype = C.c_int
         L.rich_strerror.argtypes = [C.c_int]
         L.rich_strerror.restype = C.c_char_p
         L.rich_profile_enable.argtypes = [C.c_int]
@@ -175,20 +179,21 @@ class DeviceMesh:
 
     @classmethod
     def from_host(cls, hm, device="cuda"):
+        """Pack the host stage's arrays into the device records (rich_mesh_pack)
+        and upload them with the CSR arrays."""
         import torch
-        t = {}
-        for k in hm.ARRAYS:
-            a = getattr(hm, k)
-            t[k] = torch.from_numpy(np.ascontiguousarray(a)).to(device, non_blocking=False)
+        cells, edges = pack_mesh(hm)
+        t = {"cells": torch.from_numpy(cells).to(device),
+             "edges": torch.from_numpy(edges).to(device)}
+        for k in ("off", "idx", "eoff"):
+            t[k] = torch.from_numpy(np.ascontiguousarray(getattr(hm, k))).to(device)
         return cls(t, hm.n_cells, hm.n_edges, hm.n_csr, tuple(hm.box), int(hm.bc))
 
     def c(self):
         if self._c is None:
             p = {k: C.c_void_p(v.data_ptr()) for k, v in self.t.items()}
             self._c = RichMesh(self.n_cells, self.n_edges, self.n_csr,
-                               p["px"], p["py"], p["sx"], p["sy"], p["area"],
-                               p["e_i"], p["e_j"], p["e_len"], p["e_fx"], p["e_fy"],
-                               p["off"], p["idx"], p["eoff"],
+                               p["cells"], p["edges"], p["off"], p["idx"], p["eoff"],
                                (C.c_double * 4)(*self.box), self.bc)
         return self._c
 
@@ -341,6 +346,17 @@ def rich_batch_flags_async(n, ws, host_flags, stream=None):
 # ---------------------------------------------------------------------------
 # time-centred step driver
 # ---------------------------------------------------------------------------
+def pack_mesh(hm):
+    """Host mesh -> (cells, edges) byte arrays in the device record layout."""
+    v, keep = _host_view(hm)
+    cells = np.empty(CELL_BYTES * hm.n_cells, dtype=np.uint8)
+    edges = np.empty(EDGE_BYTES * max(hm.n_edges, 1), dtype=np.uint8)
+    _check(lib().rich_mesh_pack(C.byref(v), cells.ctypes.data_as(_vp),
+                                edges.ctypes.data_as(_vp)), "rich_mesh_pack")
+    del keep
+    return cells, edges[:EDGE_BYTES * hm.n_edges]
+
+
 def _host_view(hm):
     keep = {k: np.ascontiguousarray(getattr(hm, k)) for k in hm.ARRAYS}
     dp = lambda a: a.ctypes.data_as(_dp)   # noqa: E731

@@ -43,3 +43,32 @@ def test_strerror_without_gpu():
     L.rich_strerror.restype = ctypes.c_char_p
     assert L.rich_strerror(0) == b"ok"
     assert b"mesh" in L.rich_strerror(-5)
+
+
+def test_mesh_pack_is_a_bitwise_rearrangement():
+    """rich_mesh_pack (host code, no GPU): the device records hold exactly the
+    host stage's values, in the documented field order."""
+    import numpy as np
+    from paper_1410_3219_amd import inputs as I
+    from paper_1410_3219_amd import rich as R
+    from paper_1410_3219_amd import tess as T
+    for bc in (0, 1):
+        px, py = I.uniform_points(300, seed=3 + bc)
+        m = T.rich_tess_build(px, py, (0.0, 0.0, 1.0, 1.0), bc)
+        cells, edges = R.pack_mesh(m)
+        cdt = np.dtype({"names": ["px", "py", "area", "sx", "sy", "pad"],
+                        "formats": ["<f8"] * 6})
+        edt = np.dtype({"names": ["fx", "fy", "len", "i", "j"],
+                        "formats": ["<f8", "<f8", "<f8", "<i4", "<i4"]})
+        assert cdt.itemsize == R.CELL_BYTES and edt.itemsize == R.EDGE_BYTES
+        c = cells.view(cdt)
+        e = edges.view(edt)
+        assert c.shape[0] == m.n_cells and e.shape[0] == m.n_edges
+        for f in ("px", "py", "area", "sx", "sy"):
+            assert np.array_equal(c[f].view(np.uint64), getattr(m, f).view(np.uint64)), f
+        assert (c["pad"] == 0).all()
+        for f, g in (("fx", "e_fx"), ("fy", "e_fy"), ("len", "e_len"), ("i", "e_i"), ("j", "e_j")):
+            a = e[f]
+            b = getattr(m, g)
+            assert np.array_equal(a.view(np.uint64) if a.dtype.itemsize == 8 else a,
+                                  b.view(np.uint64) if b.dtype.itemsize == 8 else b), f
