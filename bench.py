@@ -224,6 +224,53 @@ def bench_serve(args, R, log):
     return res
 
 
+def bench_extrapolated(args, R, T, P, make_state, hm0, dm0, log, steps=3):
+    """The same workload advanced with the extrapolated-fluxes integrator
+    (section 2.3, AREPO's scheme: one stage and one tessellation per step).
+    A live chain builds the meshes, then the steps are replayed with all
+    inputs in HBM: Courant step, one stage."""
+    import numpy as np
+    import torch
+    prm = R.Params(gamma=P.gamma, riemann=args.riemann, integrator=1)
+    n = hm0.n_cells
+    ws = R.workspace(n)
+    cur = R.DeviceState.from_host(make_state(hm0.area), np.stack([hm0.px, hm0.py]))
+    init = R.DeviceState(cur.Q.clone(), cur.X.clone())
+    nxt = R.DeviceState.empty_like(cur)
+    meshes, dts = [dm0], []
+    for s in range(steps):
+        dt = R.rich_cfl_dt(meshes[s], cur, prm, ws)
+        dts.append(dt)
+        R.rich_stage(meshes[s], cur, cur, nxt, dt, prm, ws)
+        if R.rich_stage_flags(ws):
+            raise SystemExit(f"extrapolated-fluxes step {s} flagged")
+        if s + 1 < steps:
+            xn = nxt.X.cpu().numpy()
+            meshes.append(R.DeviceMesh.from_host(
+                T.rich_tess_build(xn[0], xn[1], P.box, P.bc, args.threads)))
+        cur, nxt = nxt, cur
+    live = (cur.Q.clone(), cur.X.clone())
+    cur.Q.copy_(init.Q)
+    cur.X.copy_(init.X)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ok = True
+    e0.record()
+    for s in range(steps):
+        dt = R.rich_cfl_dt(meshes[s], cur, prm, ws)
+        ok = ok and dt == dts[s]
+        R.rich_stage(meshes[s], cur, cur, nxt, dt, prm, ws)
+        cur, nxt = nxt, cur
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ok = ok and bool(torch.equal(cur.Q, live[0]) and torch.equal(cur.X, live[1]))
+    out = {"steps": steps, "ms_per_step": ms, "cell_updates_per_s": n / (ms / 1e3),
+           "replay_bitwise_equal_to_live": ok}
+    log(f"[bench] extrapolated fluxes {out}")
+    return out
+
+
 def bench_sweep(args, log):
     """Section 6 cell-rounding sweep (Gresho vortex, 30x30 cells, a 6x6
     (chi, eta) grid) advanced by the batched time-centred step for a fixed
@@ -479,6 +526,8 @@ def main():
         out["batched"] = bench_batch(args, R, T, log)
         out["served"] = bench_serve(args, R, log)
         out["sweep_section6"] = bench_sweep(args, log)
+        out["extrapolated_fluxes"] = bench_extrapolated(args, R, T, P, make_state, hm0,
+                                                        meshes[0], log)
         out["batched_over_plain"] = out["batched"]["batched"]["cell_updates_per_s"] / value
         out["served_saturated_over_plain"] = (
             out["served"]["saturated"]["cell_updates_per_s"] / value)

@@ -110,6 +110,13 @@ typedef struct rich_params {
                       (0, M g, P.g) of its source totals (section 2.3: the
                       time-centred scheme makes a first-order source second
                       order); 0 for pure hydrodynamics */
+  int32_t integrator; /* 0 time-centred fluxes (the paper's scheme: two
+                      stages per step); 1 extrapolated fluxes (AREPO's,
+                      section 2.3: one stage per step, whose face states are
+                      advanced half a step with the time derivatives the
+                      limited gradients give in the primitive Euler
+                      equations, following each cell's point; the source
+                      term is then first order in time) */
 } rich_params;
 
 /* Fill p with the paper's defaults for adiabatic index gamma. */
@@ -167,7 +174,8 @@ int rich_batch_flags(int32_t n, void* ws, void* stream, int32_t* flags);
 int rich_batch_flags_async(int32_t n, void* ws, void* stream, int32_t* host_flags);
 
 /*
- * Time-centred step (section 2.3) of one run with a moving mesh:
+ * One step (section 2.3) of one run.  Time-centred fluxes (integrator 0),
+ * with a moving mesh:
  *   1. stage(mesh_n, Q^n, Q^n, x^n, dt/2)        -> Q^{n+1/2}, x^{n+1/2}
  *   2. tessellate x^{n+1/2}                       -> mesh_{n+1/2}
  *   3. stage(mesh_{n+1/2}, Q^{n+1/2}, Q^n, x^n, dt) -> Q^{n+1}, x^{n+1}
@@ -176,7 +184,9 @@ int rich_batch_flags_async(int32_t n, void* ws, void* stream, int32_t* host_flag
  * stage); it receives host point arrays and must fill *out with host mesh
  * arrays that stay valid until `release` is called on it.  The library
  * uploads them into its own device buffers (owned by ctx).  With a static
- * mesh (params->motion == 0) no tessellation happens.
+ * mesh (params->motion == 0) no tessellation happens.  Extrapolated fluxes
+ * (integrator 1): stage(mesh_n, Q^n, Q^n, x^n, dt) -> Q^{n+1}, x^{n+1}, then
+ * one tessellation.
  * The state is committed only on success; on RICH_E_DOMAIN it is unchanged.
  */
 typedef struct rich_host_mesh_view {
@@ -207,10 +217,11 @@ int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
               void* stream);
 
 /*
- * Time-centred step (section 2.3) of n independent runs at once: the same
- * chain as rich_step for every run, with each of the two stages issued as
- * one batched stage over all runs (rich_stage_batch) and the host
- * tessellations of the runs spread over n_threads host threads in between.
+ * One step (section 2.3) of n independent runs at once: the same chain as
+ * rich_step for every run (each with its own integrator), with each stage
+ * issued as one batched stage over the runs that take it (rich_stage_batch)
+ * and the host tessellations of the runs spread over n_threads host threads
+ * in between.
  *   ctxs[r]       run r's driver (current mesh set with rich_ctx_set_mesh);
  *                 its device buffers are grown as needed
  *   states[r]     host struct of device pointers: Q^n, x^n in, Q^{n+1},

@@ -631,6 +631,41 @@ static double wrap(double v, double lo, double hi) {
   return v;
 }
 
+/* ---------------------------------------------------------------------- */
+/* Extrapolated fluxes (section 2.3): the spatial derivatives are put into  */
+/* the hydrodynamic equations to get the time derivatives of the            */
+/* primitives, and the values are advanced by half a step before they are   */
+/* extrapolated to the edges.  Reading: the primitive Euler equations with  */
+/* the limited gradients, the time derivative taken along the motion of the */
+/* cell's point w (so the advection uses v - w):                            */
+/*   d rho/dt = -(v - w).grad rho - rho div v                               */
+/*   d v/dt   = -((v - w).grad) v - grad p / rho                            */
+/*   d p/dt   = -(v - w).grad p - gamma p div v                             */
+/* ---------------------------------------------------------------------- */
+static void half_step_primitives(const or_mesh* m, const double* prim, const double* lgrad,
+                                 const double* w, double gamma, double half_h,
+                                 double* out) {
+  int64_t n = m->n_cells;
+  memcpy(out, prim, sizeof(double) * 5 * (size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    double rho = prim[i], vx = prim[n + i], vy = prim[2 * n + i], pr = prim[3 * n + i];
+    double ux = vx - w[i], uy = vy - w[n + i];
+    double drx = lgrad[i], dry = lgrad[n + i];
+    double dvxx = lgrad[2 * n + i], dvxy = lgrad[3 * n + i];
+    double dvyx = lgrad[4 * n + i], dvyy = lgrad[5 * n + i];
+    double dpx = lgrad[6 * n + i], dpy = lgrad[7 * n + i];
+    double div = dvxx + dvyy;
+    double rho_t = -(ux * drx + uy * dry) - rho * div;
+    double vx_t = -(ux * dvxx + uy * dvxy) - dpx / rho;
+    double vy_t = -(ux * dvyx + uy * dvyy) - dpy / rho;
+    double p_t = -(ux * dpx + uy * dpy) - gamma * pr * div;
+    out[i] = rho + half_h * rho_t;
+    out[n + i] = vx + half_h * vx_t;
+    out[2 * n + i] = vy + half_h * vy_t;
+    out[3 * n + i] = pr + half_h * p_t;
+  }
+}
+
 int or_stage(const or_mesh* m, const double* Qsrc, const double* Qbase,
              const double* Xbase, double h, const or_params* p, double* Qout,
              double* Xout, double* d_prim, double* d_w, double* d_alpha,
@@ -653,7 +688,19 @@ int or_stage(const or_mesh* m, const double* Qsrc, const double* Qbase,
   or_limiter(m, prim, grad, p, alpha, flag);
   for (int q = 0; q < 8; ++q)
     for (int64_t i = 0; i < n; ++i) grad[(int64_t)q * n + i] *= alpha[(int64_t)(q / 2) * n + i];
-  int st = or_edge_fluxes(m, prim, grad, w, p, flux);
+  const double* fprim = prim;
+  double* prim_h = NULL;
+  if (p->integrator == 1) {
+    prim_h = malloc(sizeof(double) * 5 * (size_t)n);
+    if (!prim_h) {
+      free(prim); free(w); free(grad); free(alpha); free(flag); free(flux);
+      return OR_E_INVAL;
+    }
+    half_step_primitives(m, prim, grad, w, p->gamma, 0.5 * h, prim_h);
+    fprim = prim_h;
+  }
+  int st = or_edge_fluxes(m, fprim, grad, w, p, flux);
+  free(prim_h);
 
   for (int64_t i = 0; i < n; ++i) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};

@@ -49,6 +49,8 @@ typedef struct or_params {
   int32_t limiter; /* 0 switching (paper default), 1 global only, 2 local
                       only, 3 unlimited, 4 first order                  */
   double gx, gy;   /* uniform external acceleration (0 for pure hydro)  */
+  int32_t integrator; /* 0 time-centred fluxes (the paper's), 1 extrapolated
+                         fluxes (AREPO's, section 2.3)                     */
 } or_params;
 
 /* status codes */

@@ -55,6 +55,7 @@ class OrParams(C.Structure):
         ("delta_v", C.c_double), ("delta_p", C.c_double), ("chi", C.c_double),
         ("eta", C.c_double), ("riemann", C.c_int32), ("motion", C.c_int32),
         ("limiter", C.c_int32), ("gx", C.c_double), ("gy", C.c_double),
+        ("integrator", C.c_int32),
     ]
 
 
@@ -73,11 +74,12 @@ class Params:
     limiter: int = 0   # 0 switching, 1 global, 2 local, 3 unlimited, 4 first order
     gx: float = 0.0    # uniform external acceleration
     gy: float = 0.0
+    integrator: int = 0   # 0 time-centred fluxes, 1 extrapolated fluxes
 
     def c(self):
         return OrParams(self.gamma, self.cfl, self.theta, self.delta_v, self.delta_p,
                         self.chi, self.eta, self.riemann, self.motion, self.limiter,
-                        self.gx, self.gy)
+                        self.gx, self.gy, self.integrator)
 
 
 _lib = None
@@ -262,8 +264,19 @@ def exact_sample(gamma, WL, WR, xi):
 
 
 def step(mesh, Q, X, dt, p: Params, tess, diag=False):
-    """Time-centred step.  `tess(px, py, box, bc)` returns the mesh of the
-    given points.  Returns (Q_new, X_new, mesh_new, mesh_half, status)."""
+    """One step (section 2.3).  `tess(px, py, box, bc)` returns the mesh of
+    the given points.  Returns (Q_new, X_new, mesh_new, mesh_half, status).
+
+    Time-centred fluxes (integrator 0): a half stage, the mesh rebuilt, then
+    the full stage from the start-of-step state with the half-step fluxes.
+    Extrapolated fluxes (integrator 1): one full stage on the start-of-step
+    mesh with half-step face states, the points moved by dt w^n."""
+    if p.integrator == 1:
+        s = stage(mesh, Q, Q, X, dt, p)
+        if s.status != 0:
+            return None, None, None, None, s.status
+        mesh_n = tess(s.X[0], s.X[1], mesh.box, mesh.bc) if p.motion else mesh
+        return s.Q, s.X, mesh_n, None, 0
     s1 = stage(mesh, Q, Q, X, 0.5 * dt, p)
     if s1.status != 0:
         return None, None, None, None, s1.status

@@ -44,7 +44,7 @@ struct RunDesc {
   double rgm1;  // 1 / (gamma - 1)
   double gx, gy;  // uniform external acceleration
   int32_t n, n_edges, n_csr, bc;
-  int32_t riemann, motion, limiter, pad;
+  int32_t riemann, motion, limiter, integrator;
 };
 
 // Record layout (doubles): 0..3 rho, vx, vy, p; 4..11 limited gradients

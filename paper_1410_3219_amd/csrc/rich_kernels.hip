@@ -391,6 +391,23 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
       rec[R_P] = p;
 #pragma unroll
       for (int q = 0; q < 8; ++q) rec[R_G + q] = G[q] * alpha[q / 2];
+      if (d.integrator == 1) {
+        // extrapolated fluxes (section 2.3): the primitives advanced half a
+        // step with the time derivatives the limited gradients give in the
+        // primitive Euler equations, following the cell's point (v - w)
+        const double* g = rec + R_G;
+        const double ux = vx - wx, uy = vy - wy;
+        const double div = g[2] + g[5];
+        const double rho_t = -(ux * g[0] + uy * g[1]) - rho * div;
+        const double vx_t = -(ux * g[2] + uy * g[3]) - g[6] / rho;
+        const double vy_t = -(ux * g[4] + uy * g[5]) - g[7] / rho;
+        const double p_t = -(ux * g[6] + uy * g[7]) - d.gamma * p * div;
+        const double hh = 0.5 * d.h;
+        rec[R_RHO] = rho + hh * rho_t;
+        rec[R_VX] = vx + hh * vx_t;
+        rec[R_VY] = vy + hh * vy_t;
+        rec[R_P] = p + hh * p_t;
+      }
       rec[R_WX] = wx;
       rec[R_WY] = wy;
       rec[R_SX] = six;
@@ -704,7 +721,8 @@ bool valid_state(const rich_state* s, int64_t n, bool need_points) {
 bool valid_params(const rich_params* p) {
   return p && p->gamma > 1.0 && std::isfinite(p->gamma) && p->riemann >= 0 && p->riemann <= 1 &&
          p->motion >= 0 && p->motion <= 1 && p->limiter >= 0 && p->limiter <= 4 &&
-         std::isfinite(p->gx) && std::isfinite(p->gy);
+         std::isfinite(p->gx) && std::isfinite(p->gy) && p->integrator >= 0 &&
+         p->integrator <= 1;
 }
 
 RunDesc make_desc(const rich_mesh* m, const rich_state* src, const rich_state* base,
@@ -740,6 +758,7 @@ RunDesc make_desc(const rich_mesh* m, const rich_state* src, const rich_state* b
   d.n_csr = (int32_t)m->n_csr;
   d.bc = (int32_t)m->bc;
   d.riemann = p->riemann; d.motion = p->motion; d.limiter = p->limiter;
+  d.integrator = p->integrator;
   return d;
 }
 
@@ -1027,6 +1046,7 @@ void rich_params_default(rich_params* p, double gamma) {
   p->limiter = 0;
   p->gx = 0.0;
   p->gy = 0.0;
+  p->integrator = 0;
 }
 
 int rich_workspace_size(int64_t n_cells, size_t* bytes) {
@@ -1291,20 +1311,27 @@ int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
   rich_state next = state_view(ctx->Qn, ctx->Xn, n);
   rich_mesh m;
   ctx->cur.view(&m);
-  int rc = rich_stage(&m, state, state, &half, 0.5 * dt, p, ctx->ws.p, ctx->ws.cap, stream);
-  if (rc) return rc;
+  int rc;
   int32_t flags = 0;
-  if ((rc = rich_stage_flags(ctx->ws.p, stream, &flags))) return rc;
-  if (flags) return RICH_E_DOMAIN;
-  rich_mesh mh = m;
-  if (p->motion) {
-    rc = tessellate_into(ctx, ctx->spare, half.x, n, ctx->cur.box, ctx->cur.bc, tess, release,
-                         tess_user, st);
+  if (p->integrator == 1) {
+    // extrapolated fluxes: one stage on the start-of-step mesh
+    rc = rich_stage(&m, state, state, &next, dt, p, ctx->ws.p, ctx->ws.cap, stream);
     if (rc) return rc;
-    ctx->spare.view(&mh);
+  } else {
+    rc = rich_stage(&m, state, state, &half, 0.5 * dt, p, ctx->ws.p, ctx->ws.cap, stream);
+    if (rc) return rc;
+    if ((rc = rich_stage_flags(ctx->ws.p, stream, &flags))) return rc;
+    if (flags) return RICH_E_DOMAIN;
+    rich_mesh mh = m;
+    if (p->motion) {
+      rc = tessellate_into(ctx, ctx->spare, half.x, n, ctx->cur.box, ctx->cur.bc, tess, release,
+                           tess_user, st);
+      if (rc) return rc;
+      ctx->spare.view(&mh);
+    }
+    rc = rich_stage(&mh, &half, state, &next, dt, p, ctx->ws.p, ctx->ws.cap, stream);
+    if (rc) return rc;
   }
-  rc = rich_stage(&mh, &half, state, &next, dt, p, ctx->ws.p, ctx->ws.cap, stream);
-  if (rc) return rc;
   if ((rc = rich_stage_flags(ctx->ws.p, stream, &flags))) return rc;
   if (flags) return RICH_E_DOMAIN;
   if (p->motion) {
@@ -1377,7 +1404,7 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
   auto stage = [&](bool second) -> int {
     std::vector<int32_t> live;
     for (int32_t r = 0; r < n; ++r)
-      if (!status[r]) live.push_back(r);
+      if (!status[r] && !(second && params[r]->integrator == 1)) live.push_back(r);
     if (live.empty()) return RICH_OK;
     const size_t m = live.size();
     std::vector<const rich_mesh*> mp(m);
@@ -1387,11 +1414,12 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
     std::vector<const rich_params*> pp(m);
     for (size_t k = 0; k < m; ++k) {
       const int32_t r = live[k];
+      const bool one = params[r]->integrator == 1;  // extrapolated fluxes: one stage
       mp[k] = &mesh[r];
       sp[k] = second ? &half[r] : states[r];
       bp[k] = states[r];
-      op[k] = second ? &next[r] : &half[r];
-      h[k] = second ? dt[r] : 0.5 * dt[r];
+      op[k] = (second || one) ? &next[r] : &half[r];
+      h[k] = (second || one) ? dt[r] : 0.5 * dt[r];
       pp[k] = params[r];
     }
     int e = rich_stage_batch((int32_t)m, mp.data(), sp.data(), bp.data(), op.data(), h.data(),
@@ -1409,10 +1437,11 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
   // host threads (each call with its own run's tess_users[r]), then the
   // uploads, one synchronisation, and the host arrays released.
   std::vector<rich_host_mesh_view> hv(n);
-  auto retessellate = [&](const std::vector<rich_state>& xs) -> int {
+  auto retessellate = [&](const std::vector<rich_state>& xs, bool half_step) -> int {
     std::vector<int32_t> todo;
     for (int32_t r = 0; r < n; ++r)
-      if (!status[r] && params[r]->motion) todo.push_back(r);
+      if (!status[r] && params[r]->motion && !(half_step && params[r]->integrator == 1))
+        todo.push_back(r);
     if (todo.empty()) return RICH_OK;
     for (int32_t r : todo) {
       rich_ctx* c = ctxs[r];
@@ -1477,15 +1506,19 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
   };
 
   if ((rc = stage(false))) return fail_all(rc);
-  if (any_motion) {
-    if ((rc = retessellate(half))) return fail_all(rc);
+  bool any_two = false;   // runs with a second stage (time-centred fluxes)
+  for (int32_t r = 0; r < n; ++r)
+    if (!status[r] && params[r]->integrator == 0) any_two = true;
+  if (any_motion && any_two) {
+    if ((rc = retessellate(half, true))) return fail_all(rc);
     for (int32_t r = 0; r < n; ++r)
-      if (!status[r] && params[r]->motion) ctxs[r]->spare.view(&mesh[r]);
+      if (!status[r] && params[r]->motion && params[r]->integrator == 0)
+        ctxs[r]->spare.view(&mesh[r]);
   }
   if ((rc = stage(true))) return fail_all(rc);
   // the final meshes go into the spare buffers; a run's current mesh is
   // replaced only once its whole step has succeeded
-  if (any_motion && (rc = retessellate(next))) return fail_all(rc);
+  if (any_motion && (rc = retessellate(next, false))) return fail_all(rc);
   for (int32_t r = 0; r < n; ++r) {
     if (status[r]) continue;
     const size_t b = 8 * (size_t)nc[r];

@@ -47,6 +47,7 @@ class RichParams(C.Structure):
         ("delta_v", C.c_double), ("delta_p", C.c_double), ("chi", C.c_double),
         ("eta", C.c_double), ("riemann", C.c_int32), ("motion", C.c_int32),
         ("limiter", C.c_int32), ("gx", C.c_double), ("gy", C.c_double),
+        ("integrator", C.c_int32),
     ]
 
 
@@ -79,11 +80,12 @@ class Params:
     limiter: int = 0
     gx: float = 0.0     # uniform external acceleration
     gy: float = 0.0
+    integrator: int = 0   # 0 time-centred fluxes (two stages), 1 extrapolated fluxes
 
     def c(self):
         return RichParams(self.gamma, self.cfl, self.theta, self.delta_v, self.delta_p,
                           self.chi, self.eta, self.riemann, self.motion, self.limiter,
-                          self.gx, self.gy)
+                          self.gx, self.gy, self.integrator)
 
 
 class RichError(RuntimeError):

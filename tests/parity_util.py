@@ -21,7 +21,8 @@ def host_mesh(px, py, box, bc):
     return T.rich_tess_build(px, py, box, bc)
 
 
-def case(name, k=24, riemann=0, limiter=0, motion=1, pass2=False, seed=1, g=(0.0, 0.0)):
+def case(name, k=24, riemann=0, limiter=0, motion=1, pass2=False, seed=1, g=(0.0, 0.0),
+         integrator=0):
     """(mesh, Qsrc, Qbase, Xbase, h, oracle Params)."""
     if name == "sod":
         P = I.sod(k=k, seed=seed)
@@ -54,10 +55,12 @@ def case(name, k=24, riemann=0, limiter=0, motion=1, pass2=False, seed=1, g=(0.0
     else:
         raise ValueError(name)
     p = O.Params(gamma=P.gamma, riemann=riemann, limiter=limiter, motion=motion,
-                 gx=g[0], gy=g[1])
+                 gx=g[0], gy=g[1], integrator=integrator)
     X = np.stack([m.px, m.py])
     dt, st = O.cfl_dt(m, Q, p)
     assert st == 0
+    if integrator == 1:   # extrapolated fluxes: one full-step stage
+        return m, Q, Q, X, dt, p
     if not pass2:
         return m, Q, Q, X, 0.5 * dt, p
     # second pass of a time-centred step: primitives from the half-step state
@@ -72,7 +75,8 @@ def gpu_params(p):
     from paper_1410_3219_amd import rich as R
     return R.Params(gamma=p.gamma, cfl=p.cfl, theta=p.theta, delta_v=p.delta_v,
                     delta_p=p.delta_p, chi=p.chi, eta=p.eta, riemann=p.riemann,
-                    motion=p.motion, limiter=p.limiter, gx=p.gx, gy=p.gy)
+                    motion=p.motion, limiter=p.limiter, gx=p.gx, gy=p.gy,
+                    integrator=p.integrator)
 
 
 def gpu_stage(m, Qs, Qb, Xb, h, p, repeat=1):

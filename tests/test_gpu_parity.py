@@ -39,6 +39,13 @@ def test_stage_external_acceleration(name, pass2):
     _run(name, k=29, pass2=pass2, g=(0.4, -1.1))
 
 
+@pytest.mark.parametrize("name,riemann", [("sod", 0), ("wave", 0), ("sedov", 0), ("kh", 0),
+                                          ("gresho", 0), ("sod", 1)])
+def test_stage_extrapolated_fluxes(name, riemann):
+    """The extrapolated-fluxes stage (face states advanced half a step)."""
+    _run(name, k=27, riemann=riemann, integrator=1)
+
+
 @pytest.mark.parametrize("name", ["sod", "wave", "sedov"])
 def test_stage_exact_riemann(name):
     _run(name, k=27, riemann=1)

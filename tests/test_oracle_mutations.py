@@ -95,6 +95,30 @@ MUTATIONS = [
      "Qout[3 * n + i] += h * (spx * p->gx + spy * p->gy);",
      "Qout[3 * n + i] += 0.0 * h * (spx * p->gx + spy * p->gy);",
      [pins.free_fall]),
+    ("extrapolated fluxes: advection of the density reversed",
+     "double rho_t = -(ux * drx + uy * dry) - rho * div;",
+     "double rho_t = +(ux * drx + uy * dry) - rho * div;",
+     [pins.extrapolated_second_order]),
+    ("extrapolated fluxes: compression term of the density dropped",
+     "double rho_t = -(ux * drx + uy * dry) - rho * div;",
+     "double rho_t = -(ux * drx + uy * dry);",
+     [pins.extrapolated_second_order]),
+    ("extrapolated fluxes: pressure gradient missing from the velocity",
+     "double vx_t = -(ux * dvxx + uy * dvxy) - dpx / rho;",
+     "double vx_t = -(ux * dvxx + uy * dvxy);",
+     [pins.extrapolated_second_order]),
+    ("extrapolated fluxes: transposed velocity gradient",
+     "double vx_t = -(ux * dvxx + uy * dvxy) - dpx / rho;",
+     "double vx_t = -(ux * dvxx + uy * dvyx) - dpx / rho;",
+     [pins.extrapolated_second_order]),
+    ("extrapolated fluxes: gamma missing from the pressure equation",
+     "double p_t = -(ux * dpx + uy * dpy) - gamma * pr * div;",
+     "double p_t = -(ux * dpx + uy * dpy) - pr * div;",
+     [pins.extrapolated_second_order]),
+    ("extrapolated fluxes: advanced a full step instead of half",
+     "half_step_primitives(m, prim, grad, w, p->gamma, 0.5 * h, prim_h);",
+     "half_step_primitives(m, prim, grad, w, p->gamma, h, prim_h);",
+     [pins.extrapolated_second_order]),
     ("primitive pressure misses the kinetic energy",
      "double pr = (p->gamma - 1.0) * (E / A - 0.5 * rho * (vx * vx + vy * vy));",
      "double pr = (p->gamma - 1.0) * (E / A);",
