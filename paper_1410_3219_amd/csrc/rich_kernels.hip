@@ -68,6 +68,9 @@ constexpr int kNumXcd = 8;
 constexpr size_t kHeader = 256;  // per-run workspace header
 
 // block -> tile, so that XCD x (blocks x, x+8, ...) gets one contiguous range
+// of tiles.  A bijection on [0, nb) for any nb; persistent grids pass the
+// virtual block index of each grid-stride round (their size is a multiple of
+// the CU count, so that index keeps the hardware block's XCD).
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int q = nb / kNumXcd, rem = nb % kNumXcd;
   const int x = b % kNumXcd, k = b / kNumXcd;
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
   const int lane = (int)threadIdx.x % LPC;
   const int cl = (int)threadIdx.x / LPC;
   for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
-    const int tt = BATCH ? b : xcd_tile(b, n_tiles);
+    const int tt = xcd_tile(b, n_tiles);
     const int pos = BATCH ? find_run(tile_start, n_runs, tt) : 0;
     const RunDesc& d = BATCH ? descs[tile_start[n_runs + 1 + pos]] : one;
     const int i0 = (tt - (BATCH ? tile_start[pos] : 0)) * CPB + cl;
@@ -507,7 +510,7 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
 #endif
   const int tid = (int)threadIdx.x;
   for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
-    const int t = BATCH ? b : xcd_tile(b, n_tiles);
+    const int t = xcd_tile(b, n_tiles);
     const int pos = BATCH ? find_run(tile_start, n_runs, t) : 0;
     const RunDesc& d = BATCH ? descs[tile_start[n_runs + 1 + pos]] : one;
     const int c0 = (t - (BATCH ? tile_start[pos] : 0)) * kTile;
@@ -635,7 +638,7 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
 // minimum 0, which the host reports as a domain error.
 // ---------------------------------------------------------------------------
 constexpr int kCflThreads = 256;
-constexpr int kCflMaxBlocks = 2048;
+constexpr int kCflMaxBlocks = 16384;  // one cell per thread up to 4.19M cells, then strides
 
 __device__ __forceinline__ double block_min(double t, double* smin) {
   for (int o = 32; o > 0; o >>= 1) t = fmin(t, __shfl_xor(t, o));
@@ -677,13 +680,29 @@ __global__ __launch_bounds__(kCflThreads) void k_cfl(RunDesc d, double* block_ou
   if (threadIdx.x == 0) block_out[blockIdx.x] = m;
 }
 
-__global__ __launch_bounds__(kCflThreads) void k_cfl_final(const double* block_in, int nb,
-                                                           unsigned long long* out) {
-  __shared__ double smin[kCflThreads / 64];
-  double t = INFINITY;
-  for (int b = threadIdx.x; b < nb; b += kCflThreads) t = fmin(t, block_in[b]);
-  const double m = block_min(t, smin);
-  if (threadIdx.x == 0) *out = (unsigned long long)__double_as_longlong(m);
+constexpr int kCflFinalThreads = 1024;
+__global__ __launch_bounds__(kCflFinalThreads) void k_cfl_final(const double* block_in, int nb,
+                                                                unsigned long long* out) {
+  __shared__ double smin[kCflFinalThreads / 64];
+  // four independent minima per thread, so the loads of a thread overlap
+  double t0 = INFINITY, t1 = INFINITY, t2 = INFINITY, t3 = INFINITY;
+  int b = threadIdx.x;
+  for (; b + 3 * kCflFinalThreads < nb; b += 4 * kCflFinalThreads) {
+    t0 = fmin(t0, block_in[b]);
+    t1 = fmin(t1, block_in[b + kCflFinalThreads]);
+    t2 = fmin(t2, block_in[b + 2 * kCflFinalThreads]);
+    t3 = fmin(t3, block_in[b + 3 * kCflFinalThreads]);
+  }
+  for (; b < nb; b += kCflFinalThreads) t0 = fmin(t0, block_in[b]);
+  double t = fmin(fmin(t0, t1), fmin(t2, t3));
+  for (int o = 32; o > 0; o >>= 1) t = fmin(t, __shfl_xor(t, o));
+  if ((threadIdx.x & 63) == 0) smin[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = smin[0];
+    for (int w = 1; w < kCflFinalThreads / 64; ++w) m = fmin(m, smin[w]);
+    *out = (unsigned long long)__double_as_longlong(m);
+  }
 }
 
 }  // namespace rich
@@ -1089,7 +1108,7 @@ int rich_cfl_dt(const rich_mesh* m, const rich_state* s, const rich_params* p, d
                                rich::kCflMaxBlocks);
   // per-block minima go to the (otherwise idle) record area of the workspace
   hipLaunchKernelGGL(rich::k_cfl, dim3(nb), dim3(rich::kCflThreads), 0, st, d, d.rec);
-  hipLaunchKernelGGL(rich::k_cfl_final, dim3(1), dim3(rich::kCflThreads), 0, st,
+  hipLaunchKernelGGL(rich::k_cfl_final, dim3(1), dim3(rich::kCflFinalThreads), 0, st,
                      (const double*)d.rec, nb, d.cfl_min);
   if (hipGetLastError() != hipSuccess) return RICH_E_DEVICE;
   unsigned long long bits = 0;

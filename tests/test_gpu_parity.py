@@ -91,10 +91,11 @@ def test_cfl_dt():
         assert abs(dt - dt_ref) <= 1e-13 * dt_ref, (name, dt, dt_ref)
 
 
-@pytest.mark.parametrize("k", [1, 800])
+@pytest.mark.parametrize("k", [1, 2100])
 def test_cfl_dt_grid_sizes(k):
-    """A single cell, and 640 000 cells: more cells than one pass of the
-    bounded reduction grid covers, so blocks stride over the cells."""
+    """A single cell, and 4 410 000 cells: more cells than one pass of the
+    bounded reduction grid (16 384 blocks of 256) covers, so blocks stride
+    over the cells."""
     from paper_1410_3219_amd import rich as R
     m, Qs, Qb, Xb, h, p = U.case("wave", k=k)
     dt_ref, st = O.cfl_dt(m, Qs, p)
