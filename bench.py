@@ -271,6 +271,71 @@ def bench_extrapolated(args, R, T, P, make_state, hm0, dm0, log, steps=3):
     return out
 
 
+def bench_config(args, R, T, name, riemann, steps, log):
+    """Another configuration of the same path (time-centred steps): a live
+    chain builds the meshes, then the steps are replayed with all inputs in
+    HBM (Courant step, stage 1, stage 2), timed with events; kernel times and
+    the HBM roofline fraction as for the main line."""
+    import numpy as np
+    import torch
+    P, desc, make_state = make_problem(name, 0)
+    prm = R.Params(gamma=P.gamma, riemann=riemann)
+    hm0 = T.rich_tess_build(P.px, P.py, P.box, P.bc, args.threads)
+    n = hm0.n_cells
+    ws = R.workspace(n)
+    cur = R.DeviceState.from_host(make_state(hm0.area), np.stack([hm0.px, hm0.py]))
+    init = R.DeviceState(cur.Q.clone(), cur.X.clone())
+    half = R.DeviceState.empty_like(cur)
+    nxt = R.DeviceState.empty_like(cur)
+    meshes, halves, dts, nbytes = [R.DeviceMesh.from_host(hm0)], [], [], 0
+    hm = hm0
+    for s in range(steps):
+        dt = R.rich_cfl_dt(meshes[s], cur, prm, ws)
+        dts.append(dt)
+        R.rich_stage(meshes[s], cur, cur, half, 0.5 * dt, prm, ws)
+        xh = half.X.cpu().numpy()
+        hmh = T.rich_tess_build(xh[0], xh[1], P.box, P.bc, args.threads)
+        nbytes += algorithmic_bytes(hm, False) + algorithmic_bytes(hmh, True)
+        halves.append(R.DeviceMesh.from_host(hmh))
+        R.rich_stage(halves[s], half, cur, nxt, dt, prm, ws)
+        if R.rich_stage_flags(ws):
+            raise SystemExit(f"{name}: step {s} flagged")
+        xn = nxt.X.cpu().numpy()
+        hm = T.rich_tess_build(xn[0], xn[1], P.box, P.bc, args.threads)
+        meshes.append(R.DeviceMesh.from_host(hm))
+        cur, nxt = nxt, cur
+    live = (cur.Q.clone(), cur.X.clone())
+    cur.Q.copy_(init.Q)
+    cur.X.copy_(init.X)
+    torch.cuda.synchronize()
+    R.rich_profile_enable(True)
+    for k in ("k_cell", "k_flux"):
+        R.rich_profile_read(k)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ok = True
+    e0.record()
+    for s in range(steps):
+        dt = R.rich_cfl_dt(meshes[s], cur, prm, ws)
+        ok = ok and dt == dts[s]
+        R.rich_stage(meshes[s], cur, cur, half, 0.5 * dt, prm, ws)
+        R.rich_stage(halves[s], half, cur, nxt, dt, prm, ws)
+        cur, nxt = nxt, cur
+    e1.record()
+    torch.cuda.synchronize()
+    kc, kf = R.rich_profile_read("k_cell"), R.rich_profile_read("k_flux")
+    R.rich_profile_enable(False)
+    ms = e0.elapsed_time(e1) / steps
+    kern_ms = (kc[0] + kf[0]) / steps
+    ok = ok and bool(torch.equal(cur.Q, live[0]) and torch.equal(cur.X, live[1]))
+    out = {"workload": desc, "riemann": "exact" if riemann else "hllc", "n_cells": n,
+           "steps": steps, "ms_per_step": ms, "cell_updates_per_s": n / (ms / 1e3),
+           "kernel_ms_per_step": kern_ms,
+           "roofline_frac": (nbytes / steps) / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+           "replay_bitwise_equal_to_live": ok}
+    log(f"[bench] {name} {out}")
+    return out
+
+
 def bench_sweep(args, log):
     """Section 6 cell-rounding sweep (Gresho vortex, 30x30 cells, a 6x6
     (chi, eta) grid) advanced by the batched time-centred step for a fixed
@@ -528,6 +593,8 @@ def main():
         out["sweep_section6"] = bench_sweep(args, log)
         out["extrapolated_fluxes"] = bench_extrapolated(args, R, T, P, make_state, hm0,
                                                         meshes[0], log)
+        out["sedov_512sq"] = bench_config(args, R, T, "sedov", 0, 5, log)
+        out["sod_64sq_exact_100_steps"] = bench_config(args, R, T, "sod", 1, 100, log)
         out["batched_over_plain"] = out["batched"]["batched"]["cell_updates_per_s"] / value
         out["served_saturated_over_plain"] = (
             out["served"]["saturated"]["cell_updates_per_s"] / value)

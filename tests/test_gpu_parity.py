@@ -8,6 +8,8 @@ import pytest
 
 import oracle as O
 import parity_util as U
+from paper_1410_3219_amd import inputs as I
+from paper_1410_3219_amd import tess as T
 
 pytestmark = pytest.mark.gpu
 
@@ -69,6 +71,38 @@ def test_stage_limiters_and_motion(limiter, motion):
 def test_stage_tiny_and_exact_tile(name, k):
     # one cell, a few cells, and exactly one full 256-cell tile
     _run(name, k=k)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_stage_cells_in_random_order(bc):
+    """20 000 uniform-random points in random (not Hilbert) order: most of a
+    tile's neighbours lie in other tiles, so tiles own more edges than the
+    LDS slots hold and touch more foreign edges than the LDS list holds;
+    those fluxes are recomputed in the gather.  Both stages, walls and a
+    periodic box."""
+    px, py = I.uniform_points(20000, seed=5 + bc, sort=False)
+    box = (0.0, 0.0, 1.0, 1.0)
+    m = T.rich_tess_build(px, py, box, bc)
+    rho = np.where(px < 0.5, 1.0, 0.125)
+    pr = np.where(px < 0.5, 1.0, 0.1)
+    Q = I.conserved(rho, 0.2, -0.1, pr, m.area, 5.0 / 3.0)
+    X = np.stack([m.px, m.py])
+    p = O.Params(gamma=5.0 / 3.0)
+    dt, st = O.cfl_dt(m, Q, p)
+    assert st == 0
+    ref = O.stage(m, Q, Q, X, 0.5 * dt, p)
+    assert ref.status == 0
+    Qg, Xg, flags = U.gpu_stage(m, Q, Q, X, 0.5 * dt, p)
+    assert flags == 0
+    eq, ex = U.errors(m, Qg, Xg, ref.Q, ref.X, Q, p)
+    assert (eq < U.TOL).all() and ex < U.TOL, (eq, ex)
+    mh = T.rich_tess_build(ref.X[0], ref.X[1], box, bc)
+    ref2 = O.stage(mh, ref.Q, Q, X, dt, p)
+    assert ref2.status == 0
+    Qg2, Xg2, flags = U.gpu_stage(mh, ref.Q, Q, X, dt, p)
+    assert flags == 0
+    eq, ex = U.errors(mh, Qg2, Xg2, ref2.Q, ref2.X, Q, p)
+    assert (eq < U.TOL).all() and ex < U.TOL, (eq, ex)
 
 
 def test_deterministic_repeat():
