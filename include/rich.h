@@ -9,19 +9,21 @@
  * an opaque `void*` (a hipStream_t; NULL is the null stream).  The caller owns
  * all memory it passes in; the library never frees or keeps it.
  *
- * Data layout (device memory, structure of arrays, FP64 values, int32 indices)
- * is the one the host tessellation stage produces (rich_tess.h):
- *   cells    px, py, sx, sy, area                      [n_cells]
- *   edges    e_i, e_j (neighbour | ghost code << 28), e_len, e_fx, e_fy
- *                                                      [n_edges], sorted by e_i
- *   CSR      off [n_cells+1], idx [n_csr] = 2*edge+side, eoff [n_cells+1]
- * The state of a run is the extensive cell totals M, Px, Py, E (mass,
- * momentum, total energy integrated over each cell) and the mesh-generating
- * points x, y.
+ * Data layout (device memory, FP64 values, int32 indices): the mesh is the
+ * host tessellation stage's (rich_tess.h) with its cells and edges as
+ * records (rich_cell, rich_edge below; rich_mesh_pack builds them) and its
+ * CSR arrays as they are; the state of a run is the extensive cell totals M,
+ * Px, Py, E (mass, momentum, total energy integrated over each cell) and the
+ * mesh-generating points x, y, each a row of n_cells doubles.
  *
  * Status codes: every function returns RICH_OK (0) or a negative code; no
- * C++ exception crosses the ABI.  Functions named *_async only enqueue work;
- * their domain checks are read back with rich_stage_flags.
+ * C++ exception crosses the ABI.  rich_stage and rich_stage_batch only
+ * enqueue work on the stream; their domain checks are read back with
+ * rich_stage_flags / rich_batch_flags(_async).
+ *
+ * Threads: calls from several host threads may run concurrently as long as
+ * each uses its own workspace, rich_ctx and stream; the kernel timing
+ * switch (rich_profile_*) is process-wide and not thread-safe.
  */
 #ifndef RICH_H
 #define RICH_H

@@ -29,6 +29,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -905,6 +906,29 @@ Staging& staging() {
   static Staging s;
   return s;
 }
+std::mutex& staging_lock() {
+  static std::mutex m;
+  return m;
+}
+
+// Copy two host blocks into device memory through the pinned ring, on
+// stream st.  The whole sequence (pick a buffer, fill it, enqueue the
+// copies, record the buffer's event) holds one lock, so host threads that
+// launch batches concurrently never share a buffer in flight.
+int upload_staged(void* dst1, const void* src1, size_t b1, void* dst2, const void* src2,
+                  size_t b2, hipStream_t st) {
+  std::lock_guard<std::mutex> g(staging_lock());
+  hipEvent_t ev = nullptr;
+  char* host = static_cast<char*>(staging().get(b1 + b2, &ev));
+  if (!host) return RICH_E_NOMEM;
+  std::memcpy(host, src1, b1);
+  std::memcpy(host + b1, src2, b2);
+  if (hipMemcpyAsync(dst1, host, b1, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(dst2, host + b1, b2, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipEventRecord(ev, st) != hipSuccess)
+    return RICH_E_DEVICE;
+  return RICH_OK;
+}
 
 int resident_blocks(const void* kernel, int threads) {
   int dev = 0, cus = 0, per = 0;
@@ -1101,7 +1125,8 @@ int rich_cfl_dt(const rich_mesh* m, const rich_state* s, const rich_params* p, d
                 void* ws, size_t ws_bytes, void* stream) {
   if (!valid_mesh(m) || !valid_params(p) || !dt || !ws) return RICH_E_INVAL;
   if (!valid_state(s, m->n_cells, false)) return RICH_E_INVAL;
-  if (ws_bytes < run_ws_bytes(m->n_cells)) return RICH_E_NOMEM;
+  if (ws_bytes < run_ws_bytes(m->n_cells) || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return RICH_E_NOMEM;
   hipStream_t st = static_cast<hipStream_t>(stream);
   RunDesc d = make_desc(m, s, nullptr, nullptr, 0.0, p, static_cast<char*>(ws));
   const int nb = std::min<int>((d.n + rich::kCflThreads - 1) / rich::kCflThreads,
@@ -1191,15 +1216,8 @@ int rich_stage_batch(int32_t n, const rich_mesh* const* meshes, const rich_state
   if (tc > INT32_MAX / 2 || tf[0] > INT32_MAX / 2 || tf[1] > INT32_MAX / 2) return RICH_E_INVAL;
 
   const size_t db = (size_t)n * sizeof(RunDesc), pb = plans.size() * sizeof(int32_t);
-  hipEvent_t ev = nullptr;
-  char* host = static_cast<char*>(staging().get(db + pb, &ev));
-  if (!host) return RICH_E_NOMEM;
-  std::memcpy(host, descs.data(), db);
-  std::memcpy(host + db, plans.data(), pb);
-  if (hipMemcpyAsync(w + L.desc, host, db, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(w + L.plan, host + db, pb, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipEventRecord(ev, st) != hipSuccess)
-    return RICH_E_DEVICE;
+  const int up = upload_staged(w + L.desc, descs.data(), db, w + L.plan, plans.data(), pb, st);
+  if (up) return up;
 
   const RunDesc* dd = reinterpret_cast<const RunDesc*>(w + L.desc);
   const int32_t* dplan = reinterpret_cast<const int32_t*>(w + L.plan);
