@@ -72,3 +72,59 @@ def test_mesh_pack_is_a_bitwise_rearrangement():
             b = getattr(m, g)
             assert np.array_equal(a.view(np.uint64) if a.dtype.itemsize == 8 else a,
                                   b.view(np.uint64) if b.dtype.itemsize == 8 else b), f
+
+
+def test_argument_validation_without_gpu():
+    """Host-side validation of the C-ABI, on a machine without a GPU: every
+    call below is invalid in one way and must be rejected with its status
+    before any device work (pointers are dummies that are never touched).
+    Skipped where a GPU is present, so that a validation bug can never
+    launch a kernel on them."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("host-only check: never pass dummy pointers where a GPU could run them")
+    from paper_1410_3219_amd import rich as R
+    C = ctypes
+    L = R.lib()
+    fake = 1 << 20   # 256-byte aligned, never dereferenced
+
+    def mesh(n=100, ne=300, nc=600, box=(0.0, 0.0, 1.0, 1.0), bc=0, cells=fake):
+        return R.RichMesh(n, ne, nc, cells, fake, fake, fake, fake,
+                          (C.c_double * 4)(*box), bc)
+
+    def state(n=100, base=fake):
+        return R.RichState(base, base + 8 * n, base + 16 * n, base + 24 * n,
+                           base + 32 * n, base + 40 * n, n)
+
+    src, base, out = state(), state(base=fake * 2), state(base=fake * 4)
+    p = R.Params()
+    wsz = C.c_size_t(0)
+    assert L.rich_workspace_size(100, C.byref(wsz)) == R.RICH_OK and wsz.value > 0
+    big = wsz.value
+
+    def stage(m=None, s=src, b=base, o=out, h=0.01, prm=None, ws=fake, nbytes=big):
+        return L.rich_stage(C.byref(m or mesh()), C.byref(s), C.byref(b), C.byref(o),
+                            h, C.byref((prm or p).c()), C.c_void_p(ws), nbytes, None)
+
+    assert stage(m=mesh(n=0)) == R.RICH_E_INVAL                    # empty mesh
+    assert stage(m=mesh(ne=-1)) == R.RICH_E_INVAL                  # negative edge count
+    assert stage(m=mesh(nc=-1)) == R.RICH_E_INVAL
+    assert stage(m=mesh(box=(0.0, 0.0, 0.0, 1.0))) == R.RICH_E_INVAL
+    assert stage(m=mesh(bc=7)) == R.RICH_E_INVAL
+    assert stage(m=mesh(cells=fake + 8)) == R.RICH_E_INVAL         # records not 16-byte aligned
+    assert stage(s=state(n=99)) == R.RICH_E_INVAL                  # size mismatch
+    assert stage(o=src) == R.RICH_E_INVAL                          # out aliases src
+    assert stage(h=float("nan")) == R.RICH_E_INVAL
+    assert stage(h=-1.0) == R.RICH_E_INVAL
+    for bad in (R.Params(gamma=1.0), R.Params(riemann=2), R.Params(motion=3),
+                R.Params(limiter=5), R.Params(integrator=2), R.Params(gx=float("inf"))):
+        assert stage(prm=bad) == R.RICH_E_INVAL
+    assert stage(nbytes=big - 1) == R.RICH_E_NOMEM                 # workspace too small
+    assert stage(ws=fake + 8) == R.RICH_E_NOMEM                    # workspace not aligned
+    dt = C.c_double(0.0)
+    assert L.rich_cfl_dt(C.byref(mesh()), C.byref(src), C.byref(p.c()), C.byref(dt),
+                         C.c_void_p(fake + 8), big, None) == R.RICH_E_NOMEM
+    assert L.rich_workspace_size(0, C.byref(wsz)) == R.RICH_E_INVAL
+    arr = (C.c_int64 * 2)(100, 0)
+    assert L.rich_batch_workspace_size(2, arr, C.byref(wsz)) == R.RICH_E_INVAL
+    assert L.rich_stage_batch(0, None, None, None, None, None, None, None, 0, None) == R.RICH_E_INVAL

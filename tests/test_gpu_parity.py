@@ -169,3 +169,25 @@ def test_invalid_arguments_rejected():
     with pytest.raises(R.RichError) as e:
         R.rich_stage(dm, src, src, out, h, U.gpu_params(p), small)
     assert e.value.status == R.RICH_E_NOMEM
+
+
+def test_full_size_wave_stage():
+    """The benchmark workload at full size (2048^2 = 4 194 304 cells,
+    12 582 912 edges, periodic, moving mesh, HLLC), stage 1 in the launch
+    configuration the benchmark times, compared with the oracle on every
+    cell."""
+    P = I.advected_wave(k=2048, seed=3)
+    m = T.rich_tess_build(P.px, P.py, P.box, P.bc)
+    assert m.n_cells == 2048 * 2048 and m.n_edges == 3 * m.n_cells
+    Q = P.state(m.area)
+    X = np.stack([m.px, m.py])
+    p = O.Params(gamma=P.gamma)
+    dt, st = O.cfl_dt(m, Q, p)
+    assert st == 0
+    ref = O.stage(m, Q, Q, X, 0.5 * dt, p)
+    assert ref.status == 0
+    Qg, Xg, flags = U.gpu_stage(m, Q, Q, X, 0.5 * dt, p)
+    assert flags == 0
+    eq, ex = U.errors(m, Qg, Xg, ref.Q, ref.X, Q, p)
+    print(f"\nfull size: err M,Px,Py,E={eq} x={ex}", flush=True)
+    assert (eq < U.TOL).all() and ex < U.TOL, (eq, ex)
