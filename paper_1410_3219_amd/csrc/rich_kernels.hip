@@ -533,8 +533,20 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
     }
 #endif
     __syncthreads();
-    for (int s = tid; s < Sm; s += kTile) {
-      const int entry = d.idx[kb + s];
+    // all of a lane's CSR entries are loaded first (independent loads in
+    // flight together), then classified
+    constexpr int MPT = kMapCap / kTile;
+    int ent[MPT];
+#pragma unroll
+    for (int r = 0; r < MPT; ++r) {
+      const int s = tid + r * kTile;
+      ent[r] = s < Sm ? d.idx[kb + s] : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < MPT; ++r) {
+      const int s = tid + r * kTile;
+      if (s >= Sm) break;
+      const int entry = ent[r];
       const int e = entry >> 1;
       int m = -1;
       if (e >= e0 && e < e0 + ne) {
