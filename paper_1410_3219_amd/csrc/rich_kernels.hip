@@ -47,9 +47,6 @@ namespace rich {
 #ifndef RICH_CELL_MAXE
 #define RICH_CELL_MAXE 6  // CSR entries per cell loaded level by level (the rest in a loop)
 #endif
-#ifndef RICH_FLUX_REC_LDS
-#define RICH_FLUX_REC_LDS 0  // k_flux: keep the tile's cell records in LDS
-#endif
 #ifndef RICH_CELL_WAVES
 #define RICH_CELL_WAVES 1  // minimum waves per SIMD the register budget must allow
 #endif
@@ -453,24 +450,9 @@ __device__ __forceinline__ double wrap_once(double v, double lo, double hi) {
   return v;
 }
 
-// Record of cell c: from the tile's copy in LDS when c lies in the tile
-// (srec != nullptr, rows of kRecPad doubles), else from the workspace.
-constexpr int kRecPad = kRecDoubles + 1;  // odd row stride: no LDS bank conflicts
-__device__ __forceinline__ void fetch_rec(const RunDesc& d, const double* srec, int c0, int nt,
-                                          int c, double* r) {
-  const int l = c - c0;
-  if (srec != nullptr && l >= 0 && l < nt) {
-#pragma unroll
-    for (int k = 0; k < kRecDoubles; ++k) r[k] = srec[l * kRecPad + k];
-  } else {
-    load_rec(d.rec, c, r);
-  }
-}
-
+// A5-A7 for edge e from the records of its two cells in the workspace.
 template <int RIEMANN>
-__device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF,
-                                             const double* srec = nullptr, int c0 = 0,
-                                             int nt = 0) {
+__device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF) {
   double ri[kRecDoubles], rj[kRecDoubles];
   if (e < 0 || e >= d.n_edges) {
     LF[0] = LF[1] = LF[2] = LF[3] = 0.0;
@@ -483,11 +465,11 @@ __device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF
     LF[0] = LF[1] = LF[2] = LF[3] = 0.0;
     return false;
   }
-  fetch_rec(d, srec, c0, nt, i, ri);
+  load_rec(d.rec, i, ri);
   if ((ej >> 28) < 9) {
     int j = (int)(ej & kCellMask);
     if (j >= d.n) j = i;
-    fetch_rec(d, srec, c0, nt, j, rj);
+    load_rec(d.rec, j, rj);
   }
   double rix, riy;
   load_point(d, i, rix, riy);
@@ -503,12 +485,6 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
   __shared__ short s_map[kMapCap];  // (flux slot << 1) | side, or -1
   __shared__ int s_off[kTile + 1];  // the tile's CSR offsets
   __shared__ int s_nfor;
-#if RICH_FLUX_REC_LDS
-  __shared__ double s_rec[kTile * kRecPad];  // the tile's cell records
-  const double* srec = s_rec;
-#else
-  const double* srec = nullptr;
-#endif
   const int tid = (int)threadIdx.x;
   for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
     const int t = xcd_tile(b, n_tiles);
@@ -524,14 +500,6 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
     bool ok = true;
     if (tid == 0) s_nfor = 0;
     for (int c = tid; c <= c1 - c0; c += kTile) s_off[c] = d.off[c0 + c];
-#if RICH_FLUX_REC_LDS
-    if (tid < c1 - c0) {
-      double r[kRecDoubles];
-      load_rec(d.rec, c0 + tid, r);
-#pragma unroll
-      for (int k = 0; k < kRecDoubles; ++k) s_rec[tid * kRecPad + k] = r[k];
-    }
-#endif
     __syncthreads();
     // all of a lane's CSR entries are loaded first (independent loads in
     // flight together), then classified
@@ -566,7 +534,7 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
       const int e = w < ne ? e0 + w : s_forE[w - ne];
       const int pos = w < ne ? w : kEdgeCap + (w - ne);
       double LF[4];
-      if (!flux_of_edge<RIEMANN>(d, e, LF, srec, c0, c1 - c0)) ok = false;
+      if (!flux_of_edge<RIEMANN>(d, e, LF)) ok = false;
 #pragma unroll
       for (int q = 0; q < 4; ++q) sF[q][pos] = LF[q];
     }
@@ -592,7 +560,7 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
         } else {
           const int entry = d.idx[k];
           side = entry & 1;
-          if (!flux_of_edge<RIEMANN>(d, entry >> 1, LF, srec, c0, c1 - c0)) ok = false;
+          if (!flux_of_edge<RIEMANN>(d, entry >> 1, LF)) ok = false;
         }
         if (side) {
 #pragma unroll
@@ -614,12 +582,8 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
         Py += h * (sm * d.gy);
         E += h * (spx * d.gx + spy * d.gy);
       }
-#if RICH_FLUX_REC_LDS
-      const double wxi = s_rec[tid * kRecPad + R_WX], wyi = s_rec[tid * kRecPad + R_WY];
-#else
       const double* rec = d.rec + (size_t)i * kRecDoubles;
       const double wxi = rec[R_WX], wyi = rec[R_WY];
-#endif
       double x = d.bx[i] + h * wxi;
       double y = d.by[i] + h * wyi;
       if (d.bc == RICH_BOUNDARY_PERIODIC) {
