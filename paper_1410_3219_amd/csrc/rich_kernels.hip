@@ -116,28 +116,46 @@ __global__ void k_clear_batch(const RunDesc* __restrict__ descs, int n_runs) {
 // the cell's 128-byte record.  More lanes per cell shorten each lane's chain
 // of dependent gathers and put more loads in flight.
 // ---------------------------------------------------------------------------
-template <int LPC>
+// The value of lane (lane ^ O).  Within a quad of lanes (O = 1, 2) this is
+// a DPP quad permutation on the vector ALU (no LDS round trip); further
+// apart it is a shuffle.  Moves bits exactly.
+template <int O>
+__device__ __forceinline__ int lane_xor(int v) {
+  if constexpr (O == 1) {
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (O == 2) {
+    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else {
+    return __shfl_xor(v, O);
+  }
+}
+template <int O>
+__device__ __forceinline__ double lane_xor(double v) {
+  const int lo = lane_xor<O>(__double2loint(v));
+  const int hi = lane_xor<O>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Reductions over the LPC lanes of a cell (a fixed xor tree: every lane of
+// the group ends with the same bits).
+template <int LPC, int O = 1>
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int o = 1; o < LPC; o <<= 1) v += __shfl_xor(v, o, LPC);
+  if constexpr (O < LPC) return group_sum<LPC, 2 * O>(v + lane_xor<O>(v));
   return v;
 }
-template <int LPC>
+template <int LPC, int O = 1>
 __device__ __forceinline__ double group_max(double v) {
-#pragma unroll
-  for (int o = 1; o < LPC; o <<= 1) v = fmax(v, __shfl_xor(v, o, LPC));
+  if constexpr (O < LPC) return group_max<LPC, 2 * O>(fmax(v, lane_xor<O>(v)));
   return v;
 }
-template <int LPC>
+template <int LPC, int O = 1>
 __device__ __forceinline__ double group_min(double v) {
-#pragma unroll
-  for (int o = 1; o < LPC; o <<= 1) v = fmin(v, __shfl_xor(v, o, LPC));
+  if constexpr (O < LPC) return group_min<LPC, 2 * O>(fmin(v, lane_xor<O>(v)));
   return v;
 }
-template <int LPC>
+template <int LPC, int O = 1>
 __device__ __forceinline__ int group_or(int v) {
-#pragma unroll
-  for (int o = 1; o < LPC; o <<= 1) v |= __shfl_xor(v, o, LPC);
+  if constexpr (O < LPC) return group_or<LPC, 2 * O>(v | lane_xor<O>(v));
   return v;
 }
 
