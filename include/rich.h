@@ -167,6 +167,36 @@ int rich_stage_batch(int32_t n, const rich_mesh* const* meshes,
                      rich_state* const* out, const double* h,
                      const rich_params* const* params, void* ws, size_t ws_bytes,
                      void* stream);
+/*
+ * The same batched stage in two calls, so that its launches can be replayed
+ * (for example captured once in a HIP graph and launched many times):
+ *   rich_stage_batch_prepare  validates the runs exactly as rich_stage_batch,
+ *                             enqueues on `stream` the upload of the run
+ *                             descriptors and launch plans into ws, and fills
+ *                             *plan (host struct, no pointers) with the launch
+ *                             sizes; ws then holds everything the launch reads;
+ *   rich_stage_batch_launch   enqueues the kernels of the stage (no copies, no
+ *                             memsets, no allocation, no host synchronisation).
+ * A launch reads the device and host memory named when the plan was made, so
+ * every replay runs the stage again on whatever those buffers then hold.
+ * rich_stage_batch is prepare followed by launch.  Kernel timing must be off
+ * while a launch is captured.
+ */
+typedef struct rich_batch_plan {
+  int32_t n_runs;
+  int32_t n_cell_tiles;     /* tiles of the cell kernel over all runs          */
+  int32_t n_flux_tiles[2];  /* flux tiles of the HLLC runs, of the exact runs  */
+  int32_t n_group[2];       /* number of HLLC runs, of exact-solver runs        */
+  int32_t grid_cell;        /* persistent grid of the cell kernel              */
+  int32_t grid_flux[2];     /* persistent grids of the two flux kernels        */
+} rich_batch_plan;
+int rich_stage_batch_prepare(int32_t n, const rich_mesh* const* meshes,
+                             const rich_state* const* src, const rich_state* const* base,
+                             rich_state* const* out, const double* h,
+                             const rich_params* const* params, void* ws, size_t ws_bytes,
+                             void* stream, rich_batch_plan* plan);
+int rich_stage_batch_launch(const rich_batch_plan* plan, void* ws, void* stream);
+
 /* Synchronise and read the n per-run flag words of the last batched stage. */
 int rich_batch_flags(int32_t n, void* ws, void* stream, int32_t* flags);
 /* Enqueue on stream a copy of the same n flag words into host_flags and

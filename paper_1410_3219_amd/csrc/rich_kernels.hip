@@ -1149,11 +1149,14 @@ int rich_batch_workspace_size(int32_t n, const int64_t* n_cells, size_t* bytes) 
   return RICH_OK;
 }
 
-int rich_stage_batch(int32_t n, const rich_mesh* const* meshes, const rich_state* const* src,
-                     const rich_state* const* base, rich_state* const* out, const double* h,
-                     const rich_params* const* params, void* ws, size_t ws_bytes,
-                     void* stream) {
-  if (n <= 0 || !meshes || !src || !base || !out || !h || !params || !ws) return RICH_E_INVAL;
+int rich_stage_batch_prepare(int32_t n, const rich_mesh* const* meshes,
+                             const rich_state* const* src, const rich_state* const* base,
+                             rich_state* const* out, const double* h,
+                             const rich_params* const* params, void* ws, size_t ws_bytes,
+                             void* stream, rich_batch_plan* plan) {
+  if (n <= 0 || !meshes || !src || !base || !out || !h || !params || !ws || !plan)
+    return RICH_E_INVAL;
+  std::memset(plan, 0, sizeof(*plan));
   std::vector<int64_t> nc(n);
   for (int32_t r = 0; r < n; ++r) {
     const rich_mesh* m = meshes[r];
@@ -1213,6 +1216,33 @@ int rich_stage_batch(int32_t n, const rich_mesh* const* meshes, const rich_state
   const int up = upload_staged(w + L.desc, descs.data(), db, w + L.plan, plans.data(), pb, st);
   if (up) return up;
 
+  static const int cell_grid = resident_blocks(
+      reinterpret_cast<const void*>(&rich::k_cell<rich::kLpc, true>), rich::kCellThreads);
+  static const int flux0_grid = resident_blocks(
+      reinterpret_cast<const void*>(&rich::k_flux<0, true>), rich::kTile);
+  static const int flux1_grid = resident_blocks(
+      reinterpret_cast<const void*>(&rich::k_flux<1, true>), rich::kTile);
+  plan->n_runs = n;
+  plan->n_cell_tiles = (int32_t)tc;
+  plan->n_flux_tiles[0] = (int32_t)tf[0];
+  plan->n_flux_tiles[1] = (int32_t)tf[1];
+  plan->n_group[0] = (int32_t)g0.size();
+  plan->n_group[1] = (int32_t)g1.size();
+  plan->grid_cell = (int32_t)std::min<int64_t>(tc, cell_grid);
+  plan->grid_flux[0] = (int32_t)std::min<int64_t>(tf[0], flux0_grid);
+  plan->grid_flux[1] = (int32_t)std::min<int64_t>(tf[1], flux1_grid);
+  return RICH_OK;
+}
+
+int rich_stage_batch_launch(const rich_batch_plan* plan, void* ws, void* stream) {
+  if (!plan || !ws || plan->n_runs <= 0 || plan->n_cell_tiles <= 0 || plan->grid_cell <= 0)
+    return RICH_E_INVAL;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return RICH_E_NOMEM;
+  const int32_t n = plan->n_runs;
+  std::vector<int64_t> one(n, 1);
+  const BatchLayout L = batch_layout(n, one.data());   // descriptor and plan offsets
+  char* w = static_cast<char*>(ws);
+  hipStream_t st = static_cast<hipStream_t>(stream);
   const RunDesc* dd = reinterpret_cast<const RunDesc*>(w + L.desc);
   const int32_t* dplan = reinterpret_cast<const int32_t*>(w + L.plan);
   const int32_t* dpc = dplan;
@@ -1221,25 +1251,30 @@ int rich_stage_batch(int32_t n, const rich_mesh* const* meshes, const rich_state
   RunDesc dummy;
   std::memset(&dummy, 0, sizeof(dummy));
   hipLaunchKernelGGL(rich::k_clear_batch, dim3((n + 255) / 256), dim3(256), 0, st, dd, n);
-  static int cell_grid = resident_blocks(
-      reinterpret_cast<const void*>(&rich::k_cell<rich::kLpc, true>), rich::kCellThreads);
-  static int flux0_grid = resident_blocks(
-      reinterpret_cast<const void*>(&rich::k_flux<0, true>), rich::kTile);
-  static int flux1_grid = resident_blocks(
-      reinterpret_cast<const void*>(&rich::k_flux<1, true>), rich::kTile);
   int pcl = prof_begin("k_cell", st);
-  hipLaunchKernelGGL((rich::k_cell<rich::kLpc, true>), dim3((int)std::min<int64_t>(tc, cell_grid)),
-                     dim3(rich::kCellThreads), 0, st, dummy, dd, dpc, n, (int)tc);
+  hipLaunchKernelGGL((rich::k_cell<rich::kLpc, true>), dim3(plan->grid_cell),
+                     dim3(rich::kCellThreads), 0, st, dummy, dd, dpc, n, plan->n_cell_tiles);
   prof_end(pcl, st);
   int pfl = prof_begin("k_flux", st);
-  if (!g0.empty())
-    hipLaunchKernelGGL((rich::k_flux<0, true>), dim3((int)std::min<int64_t>(tf[0], flux0_grid)),
-                       dim3(rich::kTile), 0, st, dummy, dd, dpf0, (int)g0.size(), (int)tf[0]);
-  if (!g1.empty())
-    hipLaunchKernelGGL((rich::k_flux<1, true>), dim3((int)std::min<int64_t>(tf[1], flux1_grid)),
-                       dim3(rich::kTile), 0, st, dummy, dd, dpf1, (int)g1.size(), (int)tf[1]);
+  if (plan->n_group[0] > 0 && plan->grid_flux[0] > 0)
+    hipLaunchKernelGGL((rich::k_flux<0, true>), dim3(plan->grid_flux[0]), dim3(rich::kTile), 0,
+                       st, dummy, dd, dpf0, plan->n_group[0], plan->n_flux_tiles[0]);
+  if (plan->n_group[1] > 0 && plan->grid_flux[1] > 0)
+    hipLaunchKernelGGL((rich::k_flux<1, true>), dim3(plan->grid_flux[1]), dim3(rich::kTile), 0,
+                       st, dummy, dd, dpf1, plan->n_group[1], plan->n_flux_tiles[1]);
   prof_end(pfl, st);
   return hip_status(hipGetLastError());
+}
+
+int rich_stage_batch(int32_t n, const rich_mesh* const* meshes, const rich_state* const* src,
+                     const rich_state* const* base, rich_state* const* out, const double* h,
+                     const rich_params* const* params, void* ws, size_t ws_bytes,
+                     void* stream) {
+  rich_batch_plan plan;
+  const int rc = rich_stage_batch_prepare(n, meshes, src, base, out, h, params, ws, ws_bytes,
+                                          stream, &plan);
+  if (rc) return rc;
+  return rich_stage_batch_launch(&plan, ws, stream);
 }
 
 int rich_batch_flags(int32_t n, void* ws, void* stream, int32_t* flags) {

@@ -36,6 +36,12 @@ class RichMesh(C.Structure):
 CELL_BYTES, EDGE_BYTES = 48, 32   # sizeof(rich_cell), sizeof(rich_edge)
 
 
+class RichBatchPlan(C.Structure):
+    _fields_ = [("n_runs", C.c_int32), ("n_cell_tiles", C.c_int32),
+                ("n_flux_tiles", C.c_int32 * 2), ("n_group", C.c_int32 * 2),
+                ("grid_cell", C.c_int32), ("grid_flux", C.c_int32 * 2)]
+
+
 class RichState(C.Structure):
     _fields_ = [("M", _vp), ("Px", _vp), ("Py", _vp), ("E", _vp), ("x", _vp), ("y", _vp),
                 ("n_cells", C.c_int64)]
@@ -128,8 +134,14 @@ def lib():
                                            _vp, C.c_size_t, _vp]
             L.rich_batch_flags.argtypes = [C.c_int32, _vp, _vp, _ip]
             L.rich_batch_flags_async.argtypes = [C.c_int32, _vp, _vp, _vp]
+            L.rich_stage_batch_prepare.argtypes = [C.c_int32, C.POINTER(_vp), C.POINTER(_vp),
+                                                   C.POINTER(_vp), C.POINTER(_vp), _dp,
+                                                   C.POINTER(_vp), _vp, C.c_size_t, _vp,
+                                                   C.POINTER(RichBatchPlan)]
+            L.rich_stage_batch_launch.argtypes = [C.POINTER(RichBatchPlan), _vp, _vp]
             for f in ("rich_batch_workspace_size", "rich_stage_batch", "rich_batch_flags",
-                      "rich_batch_flags_async"):
+                      "rich_batch_flags_async", "rich_stage_batch_prepare",
+                      "rich_stage_batch_launch"):
                 getattr(L, f).restype = C.c_int
         if hasattr(L, "rich_step"):
             L.rich_ctx_create.argtypes = [C.POINTER(_vp)]
@@ -312,8 +324,7 @@ def batch_workspace(n_cells, device="cuda"):
     return torch.empty(rich_batch_workspace_size(n_cells), dtype=torch.uint8, device=device)
 
 
-def rich_stage_batch(meshes, srcs, bases, outs, hs, params, ws, stream=None):
-    """One stage of len(meshes) independent runs, one launch per kernel phase."""
+def _batch_args(meshes, srcs, bases, outs, hs, params):
     n = len(meshes)
     ad = C.addressof
     # the structs stay referenced by the objects that cache them for the call
@@ -324,9 +335,34 @@ def rich_stage_batch(meshes, srcs, bases, outs, hs, params, ws, stream=None):
     hh = (C.c_double * n)(*[float(h) for h in hs])
     pc = [p.c() for p in params]
     ppp = (_vp * n)(*[ad(x) for x in pc])
+    return n, mp, spp, bpp, opp, hh, ppp, pc
+
+
+def rich_stage_batch(meshes, srcs, bases, outs, hs, params, ws, stream=None):
+    """One stage of len(meshes) independent runs, one launch per kernel phase."""
+    n, mp, spp, bpp, opp, hh, ppp, _pc = _batch_args(meshes, srcs, bases, outs, hs, params)
     st = lib().rich_stage_batch(n, mp, spp, bpp, opp, hh, ppp, C.c_void_p(ws.data_ptr()),
                                 ws.numel(), _stream_ptr(stream))
     _check(st, "rich_stage_batch")
+
+
+def rich_stage_batch_prepare(meshes, srcs, bases, outs, hs, params, ws, stream=None):
+    """Upload the descriptors of a batched stage into ws; returns the plan
+    that rich_stage_batch_launch replays (the buffers named here must stay
+    alive while the plan is used)."""
+    n, mp, spp, bpp, opp, hh, ppp, _pc = _batch_args(meshes, srcs, bases, outs, hs, params)
+    plan = RichBatchPlan()
+    st = lib().rich_stage_batch_prepare(n, mp, spp, bpp, opp, hh, ppp,
+                                        C.c_void_p(ws.data_ptr()), ws.numel(),
+                                        _stream_ptr(stream), C.byref(plan))
+    _check(st, "rich_stage_batch_prepare")
+    return plan
+
+
+def rich_stage_batch_launch(plan, ws, stream=None):
+    """Enqueue the kernels of a prepared batched stage (capturable)."""
+    _check(lib().rich_stage_batch_launch(C.byref(plan), C.c_void_p(ws.data_ptr()),
+                                         _stream_ptr(stream)), "rich_stage_batch_launch")
 
 
 def rich_batch_flags(n, ws, stream=None):
