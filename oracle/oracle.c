@@ -762,6 +762,9 @@ int or_cfl_dt(const or_mesh* m, const double* Q, const or_params* p, double* dt)
     double ux = prim[n + i] - w[i], uy = prim[2 * n + i] - w[n + i];
     double s = prim[4 * n + i] + sqrt(ux * ux + uy * uy);
     double t = R / s;
+    /* a cell with no positive finite Courant time (no real sound speed, or
+       a gas at rest with zero pressure) leaves the step undefined */
+    if (!(t > 0.0) || !isfinite(t)) t = 0.0;
     if (t < best) best = t;
   }
   *dt = p->cfl * best;

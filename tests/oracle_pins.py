@@ -623,6 +623,15 @@ def cfl_uniform(O):
     assert st == 0 and abs(dt - 0.3 * R / c) < 1e-15
     dt, st = O.cfl_dt(m, Q, O.Params(gamma=g, motion=0))
     assert abs(dt - 0.3 * R / (c + math.hypot(0.3, -0.1))) < 1e-15
+    # one cell without a real sound speed: no Courant step (domain error)
+    Qb = Q.copy()
+    Qb[3, 17] = -Qb[3, 17]
+    dt, st = O.cfl_dt(m, Qb, O.Params(gamma=g))
+    assert st == -4 and dt == 0.0          # OR_E_DOMAIN
+    # a gas at rest with zero pressure has zero signal speed: no step either
+    Q0 = I.conserved(1.0, 0.0, 0.0, 0.0, m.area, g)
+    dt, st = O.cfl_dt(m, Q0, O.Params(gamma=g, motion=0))
+    assert st == -4
 
 
 def sod_L(O, k, limiter=0, riemann=0, steps=None, t_end=0.1):

@@ -123,6 +123,10 @@ MUTATIONS = [
      "double pr = (p->gamma - 1.0) * (E / A - 0.5 * rho * (vx * vx + vy * vy));",
      "double pr = (p->gamma - 1.0) * (E / A);",
      [pins.uniform_flow, pins.cfl_uniform]),
+    ("Courant minimum skips a cell without a sound speed",
+     "    if (!(t > 0.0) || !isfinite(t)) t = 0.0;\n",
+     "\n",
+     [pins.cfl_uniform]),
 ]
 
 
