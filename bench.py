@@ -312,7 +312,8 @@ def bench_extrapolated(args, R, T, P, make_state, hm0, dm0, log, steps=3):
 def bench_config(args, R, T, name, riemann, steps, log):
     """Another configuration of the same path (time-centred steps): a live
     chain builds the meshes, then the steps are replayed with all inputs in
-    HBM (Courant step, stage 1, stage 2), timed with events; kernel times and
+    HBM (stage 1 with the Courant step fused, stage 2, no synchronisation
+    inside a step), timed with events; kernel times and
     the HBM roofline fraction as for the main line."""
     import numpy as np
     import torch
@@ -353,13 +354,12 @@ def bench_config(args, R, T, name, riemann, steps, log):
     ok = True
     e0.record()
     for s in range(steps):
-        dt = R.rich_cfl_dt(meshes[s], cur, prm, ws)
-        ok = ok and dt == dts[s]
-        R.rich_stage(meshes[s], cur, cur, half, 0.5 * dt, prm, ws)
-        R.rich_stage(halves[s], half, cur, nxt, dt, prm, ws)
+        R.rich_stage_courant(meshes[s], cur, cur, half, 0.5, prm, ws)
+        R.rich_stage_dt_of(halves[s], half, cur, nxt, 1.0, ws, prm, ws)
         cur, nxt = nxt, cur
     e1.record()
     torch.cuda.synchronize()
+    ok = R.rich_stage_dt(ws) == dts[-1]
     kc, kf = R.rich_profile_read("k_cell"), R.rich_profile_read("k_flux")
     R.rich_profile_enable(False)
     ms = e0.elapsed_time(e1) / steps
@@ -538,12 +538,11 @@ def main():
     dt_mismatch = []
 
     def run_step(s, a, hbuf, b):
-        # A0 (Courant step, synchronises for the host-side dt), stage 1, stage 2
-        dt = R.rich_cfl_dt(meshes[s], a, params, ws)
-        if dt != dts[s]:
-            dt_mismatch.append((s, dt, dts[s]))
-        R.rich_stage(meshes[s], a, a, hbuf, 0.5 * dt, params, ws)
-        R.rich_stage(halves[s], hbuf, a, b, dt, params, ws)
+        # A0 fused into stage 1's cell pass: dt = cfl * min R/(c+|v-w|) is
+        # reduced and kept on the device, stage 1 steps dt/2 and stage 2 dt
+        # from it; nothing synchronises inside the step
+        R.rich_stage_courant(meshes[s], a, a, hbuf, 0.5, params, ws)
+        R.rich_stage_dt_of(halves[s], hbuf, a, b, 1.0, ws, params, ws)
 
     cur = R.DeviceState(init.Q.clone(), init.X.clone())
     nxt = R.DeviceState.empty_like(cur)
@@ -567,6 +566,9 @@ def main():
     ms_total = ev0.elapsed_time(ev1)
     kern = {k_: R.rich_profile_read(k_) for k_ in ("k_cell", "k_flux")}
     flags = R.rich_stage_flags(ws)
+    dt_last = R.rich_stage_dt(ws)
+    if dt_last != dts[W + K - 1]:
+        dt_mismatch.append((W + K - 1, dt_last, dts[W + K - 1]))
     replay_ok = bool(torch.equal(cur.Q, live_final[0]) and torch.equal(cur.X, live_final[1])
                      and not dt_mismatch)
     log(f"[bench] timed {K} steps: {ms_total:.3f} ms, flags={flags}, replay bitwise={replay_ok}")

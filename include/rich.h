@@ -155,6 +155,41 @@ int rich_cfl_dt(const rich_mesh* m, const rich_state* s, const rich_params* p,
                 double* dt, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Courant step fused into a stage, with no host round trip (sections 2.3 and
+ * 2.2): the cell pass of this stage also takes the Courant minimum of src
+ * (the same quantity rich_cfl_dt reduces), a one-block reduction writes
+ * dt = cfl * minimum into workspace ws, and the stage is then rich_stage with
+ * h = h_factor * dt read from device memory.  A time-centred step is
+ *   rich_stage_courant(m, s, s, half, 0.5, p, ws, ...)
+ *   (tessellate the half-step points)
+ *   rich_stage_dt_of(m', half, s, out, 1.0, ws, p, ws, ...)
+ * with results bitwise equal to rich_cfl_dt followed by rich_stage with
+ * h = dt / 2 and h = dt.  Enqueued on `stream`; nothing synchronises.
+ * Arguments are those of rich_stage; h_factor must be finite and >= 0, and
+ * p->cfl positive.  Returns RICH_E_INVAL, without enqueuing, for integrator 1
+ * (its cell pass needs the step before the minimum exists).  A dt that is
+ * not positive and finite sets RICH_FLAG_DOMAIN in this stage's flag word.
+ */
+int rich_stage_courant(const rich_mesh* m, const rich_state* src, const rich_state* base,
+                       rich_state* out, double h_factor, const rich_params* p, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/*
+ * rich_stage with h = h_factor * dt, where dt is the value the last
+ * rich_stage_courant on workspace dt_ws wrote (read on the device when the
+ * kernels run, so the call may be enqueued before that value exists).
+ * dt_ws may be ws itself: a stage leaves the dt slot of its workspace alone.
+ */
+int rich_stage_dt_of(const rich_mesh* m, const rich_state* src, const rich_state* base,
+                     rich_state* out, double h_factor, const void* dt_ws,
+                     const rich_params* p, void* ws, size_t ws_bytes, void* stream);
+
+/* Synchronise `stream` and copy the dt the last rich_stage_courant on ws
+ * wrote to the host double *dt; RICH_E_DOMAIN if it is not positive and
+ * finite. */
+int rich_stage_dt(void* ws, void* stream, double* dt);
+
+/*
  * Batched stage over n independent runs of any sizes, in one launch per
  * kernel phase: meshes[r], src[r], base[r], out[r], h[r], params[r] as for
  * rich_stage (host arrays of pointers to host structs holding device

@@ -36,11 +36,14 @@ struct RunDesc {
   double *oM, *oPx, *oPy, *oE, *ox, *oy;          // result
   // workspace of this run
   double* rec;       // [n][16] records
+  double* cfl_blocks;   // Courant minimum of each cell-kernel block, or null
+  const double* h_dev;  // if set, the step is h_factor * (*h_dev) (device dt)
+  double h_factor;
   int32_t* flag;     // status word
   unsigned long long* cfl_min;  // bit pattern of the smallest R/(c+|v-w|)
   // geometry and parameters
   double x0, y0, x1, y1, Lx, Ly;
-  double h, gamma, theta, delta_v, delta_p, chi, eta;
+  double h, gamma, theta, delta_v, delta_p, chi, eta, cfl;
   double rgm1;  // 1 / (gamma - 1)
   double gx, gy;  // uniform external acceleration
   int32_t n, n_edges, n_csr, bc;

@@ -159,6 +159,19 @@ __device__ __forceinline__ int group_or(int v) {
   return v;
 }
 
+// Minimum over the block of the cell kernel (kCellThreads lanes).
+__device__ __forceinline__ double block_min_cells(double t) {
+  __shared__ double sm[kCellThreads / 64];
+  for (int o = 32; o > 0; o >>= 1) t = fmin(t, __shfl_xor(t, o));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = t;
+  __syncthreads();
+  double m = sm[0];
+#pragma unroll
+  for (int w = 1; w < kCellThreads / 64; ++w) m = fmin(m, sm[w]);
+  __syncthreads();
+  return m;
+}
+
 template <int LPC, bool BATCH>
 __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc one,
                                                        const RunDesc* __restrict__ descs,
@@ -194,6 +207,17 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
         wx += d.chi * c * dx / dd;
         wy += d.chi * c * dy / dd;
       }
+    }
+    if (d.cfl_blocks != nullptr) {
+      // A0 fused into the cell pass: the Courant ratio of this cell, as in
+      // k_cfl, reduced to the block's minimum (each cell's lanes agree)
+      const double ux = vx - wx, uy = vy - wy;
+      const double cs = c + sqrt(ux * ux + uy * uy);
+      double ti = R / cs;
+      if (!(ti > 0.0) || !isfinite(ti)) ti = 0.0;
+      if (!active) ti = INFINITY;
+      const double bm = block_min_cells(ti);
+      if (threadIdx.x == 0) d.cfl_blocks[tt] = bm;
     }
     const double phi[4] = {rho, vx, vy, p};
     int k0 = d.off[i], k1 = d.off[i + 1];
@@ -421,7 +445,7 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
         const double vx_t = -(ux * g[2] + uy * g[3]) - g[6] / rho;
         const double vy_t = -(ux * g[4] + uy * g[5]) - g[7] / rho;
         const double p_t = -(ux * g[6] + uy * g[7]) - d.gamma * p * div;
-        const double hh = 0.5 * d.h;
+        const double hh = 0.5 * (d.h_dev != nullptr ? d.h_factor * (*d.h_dev) : d.h);
         rec[R_RHO] = rho + hh * rho_t;
         rec[R_VX] = vx + hh * vx_t;
         rec[R_VY] = vy + hh * vy_t;
@@ -588,7 +612,7 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
           for (int q = 0; q < 4; ++q) acc[q] += LF[q];
         }
       }
-      const double h = d.h;
+      const double h = d.h_dev != nullptr ? d.h_factor * (*d.h_dev) : d.h;
       const double M = d.bM[i] - h * acc[0];
       double Px = d.bPx[i] - h * acc[1];
       double Py = d.bPy[i] - h * acc[2];
@@ -676,8 +700,13 @@ __global__ __launch_bounds__(kCflThreads) void k_cfl(RunDesc d, double* block_ou
 }
 
 constexpr int kCflFinalThreads = 1024;
+// The minimum of the block minima, as a bit pattern in *out; with dt_out
+// also dt = cfl * minimum in *dt_out, and the domain flag when that is not
+// a positive number.
 __global__ __launch_bounds__(kCflFinalThreads) void k_cfl_final(const double* block_in, int nb,
-                                                                unsigned long long* out) {
+                                                                unsigned long long* out,
+                                                                double cfl, double* dt_out,
+                                                                int32_t* flag) {
   __shared__ double smin[kCflFinalThreads / 64];
   // four independent minima per thread, so the loads of a thread overlap
   double t0 = INFINITY, t1 = INFINITY, t2 = INFINITY, t3 = INFINITY;
@@ -697,6 +726,11 @@ __global__ __launch_bounds__(kCflFinalThreads) void k_cfl_final(const double* bl
     double m = smin[0];
     for (int w = 1; w < kCflFinalThreads / 64; ++w) m = fmin(m, smin[w]);
     *out = (unsigned long long)__double_as_longlong(m);
+    if (dt_out != nullptr) {
+      const double dt = cfl * m;
+      *dt_out = dt;
+      if (!(dt > 0.0) || !isfinite(dt)) atomicOr(flag, RICH_FLAG_DOMAIN);
+    }
   }
 }
 
@@ -713,8 +747,12 @@ int hip_status(hipError_t e) { return e == hipSuccess ? RICH_OK : RICH_E_DEVICE;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+constexpr int64_t kCellsPerBlock = rich::kCellThreads / rich::kLpc;
+constexpr size_t kDtOffset = 16;  // header: flag @0, Courant minimum @8, dt @16
+
 size_t run_ws_bytes(int64_t n) {
-  return rich::kHeader + align_up((size_t)n * rich::kRecDoubles * sizeof(double), 256);
+  return rich::kHeader + align_up((size_t)n * rich::kRecDoubles * sizeof(double), 256) +
+         align_up((size_t)((n + kCellsPerBlock - 1) / kCellsPerBlock) * sizeof(double), 256);
 }
 
 bool valid_mesh(const rich_mesh* m) {
@@ -763,7 +801,7 @@ RunDesc make_desc(const rich_mesh* m, const rich_state* src, const rich_state* b
   d.Ly = m->box[3] - m->box[1];
   d.h = h;
   d.gamma = p->gamma; d.theta = p->theta; d.delta_v = p->delta_v; d.delta_p = p->delta_p;
-  d.chi = p->chi; d.eta = p->eta;
+  d.chi = p->chi; d.eta = p->eta; d.cfl = p->cfl;
   d.rgm1 = 1.0 / (p->gamma - 1.0);
   d.gx = p->gx;
   d.gy = p->gy;
@@ -827,6 +865,10 @@ int launch_stage(const RunDesc& d, int riemann, hipStream_t st) {
   hipLaunchKernelGGL((rich::k_cell<rich::kLpc, false>), dim3(n_ctiles), dim3(rich::kCellThreads),
                      0, st, d, (const RunDesc*)nullptr, (const int32_t*)nullptr, 1, n_ctiles);
   prof_end(pc, st);
+  if (d.cfl_blocks != nullptr)   // dt from the cell kernel's Courant minima
+    hipLaunchKernelGGL(rich::k_cfl_final, dim3(1), dim3(rich::kCflFinalThreads), 0, st,
+                       (const double*)d.cfl_blocks, n_ctiles, d.cfl_min, d.cfl,
+                       const_cast<double*>(d.h_dev), d.flag);
   int pf = prof_begin("k_flux", st);
   if (riemann == 1)
     hipLaunchKernelGGL((rich::k_flux<1, false>), dim3(n_tiles), dim3(T), 0, st, d,
@@ -1106,6 +1148,58 @@ int rich_stage(const rich_mesh* m, const rich_state* src, const rich_state* base
   return launch_stage(d, p->riemann, static_cast<hipStream_t>(stream));
 }
 
+namespace {
+int stage_with_device_dt(const rich_mesh* m, const rich_state* src, const rich_state* base,
+                         rich_state* out, double h_factor, const void* dt_ws, bool courant,
+                         const rich_params* p, void* ws, size_t ws_bytes, void* stream) {
+  if (!valid_mesh(m) || !valid_params(p) || !ws || (!courant && !dt_ws)) return RICH_E_INVAL;
+  const int64_t n = m->n_cells;
+  if (!valid_state(src, n, false) || !valid_state(base, n, true) || !valid_state(out, n, true))
+    return RICH_E_INVAL;
+  if (!std::isfinite(h_factor) || h_factor < 0.0) return RICH_E_INVAL;
+  if (!(p->cfl > 0.0) || !std::isfinite(p->cfl)) return RICH_E_INVAL;
+  // extrapolated fluxes need the step inside the cell pass, before its minimum exists
+  if (courant && p->integrator == 1) return RICH_E_INVAL;
+  if (out->M == src->M || out->M == base->M || out->x == base->x) return RICH_E_INVAL;
+  if (ws_bytes < run_ws_bytes(n) || (reinterpret_cast<uintptr_t>(ws) & 255)) return RICH_E_NOMEM;
+  if (dt_ws && (reinterpret_cast<uintptr_t>(dt_ws) & 255)) return RICH_E_INVAL;
+  char* w = static_cast<char*>(ws);
+  RunDesc d = make_desc(m, src, base, out, 0.0, p, w);
+  d.h_factor = h_factor;
+  if (courant) {
+    d.cfl_blocks = reinterpret_cast<double*>(
+        w + rich::kHeader + align_up((size_t)n * rich::kRecDoubles * sizeof(double), 256));
+    d.h_dev = reinterpret_cast<const double*>(w + kDtOffset);
+  } else {
+    d.h_dev = reinterpret_cast<const double*>(static_cast<const char*>(dt_ws) + kDtOffset);
+  }
+  return launch_stage(d, p->riemann, static_cast<hipStream_t>(stream));
+}
+}  // namespace
+
+int rich_stage_courant(const rich_mesh* m, const rich_state* src, const rich_state* base,
+                       rich_state* out, double h_factor, const rich_params* p, void* ws,
+                       size_t ws_bytes, void* stream) {
+  return stage_with_device_dt(m, src, base, out, h_factor, nullptr, true, p, ws, ws_bytes,
+                              stream);
+}
+
+int rich_stage_dt_of(const rich_mesh* m, const rich_state* src, const rich_state* base,
+                     rich_state* out, double h_factor, const void* dt_ws, const rich_params* p,
+                     void* ws, size_t ws_bytes, void* stream) {
+  return stage_with_device_dt(m, src, base, out, h_factor, dt_ws, false, p, ws, ws_bytes,
+                              stream);
+}
+
+int rich_stage_dt(void* ws, void* stream, double* dt) {
+  if (!ws || !dt) return RICH_E_INVAL;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return RICH_E_DEVICE;
+  if (hipMemcpy(dt, static_cast<char*>(ws) + kDtOffset, sizeof(double), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return RICH_E_DEVICE;
+  return (std::isfinite(*dt) && *dt > 0.0) ? RICH_OK : RICH_E_DOMAIN;
+}
+
 int rich_stage_flags(void* ws, void* stream, int32_t* flags) {
   if (!ws || !flags) return RICH_E_INVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1128,7 +1222,8 @@ int rich_cfl_dt(const rich_mesh* m, const rich_state* s, const rich_params* p, d
   // per-block minima go to the (otherwise idle) record area of the workspace
   hipLaunchKernelGGL(rich::k_cfl, dim3(nb), dim3(rich::kCflThreads), 0, st, d, d.rec);
   hipLaunchKernelGGL(rich::k_cfl_final, dim3(1), dim3(rich::kCflFinalThreads), 0, st,
-                     (const double*)d.rec, nb, d.cfl_min);
+                     (const double*)d.rec, nb, d.cfl_min, 0.0, (double*)nullptr,
+                     (int32_t*)nullptr);
   if (hipGetLastError() != hipSuccess) return RICH_E_DEVICE;
   unsigned long long bits = 0;
   if (hipStreamSynchronize(st) != hipSuccess) return RICH_E_DEVICE;

@@ -116,6 +116,10 @@ def lib():
         L.rich_stage.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, C.c_size_t, _vp]
         L.rich_stage_flags.argtypes = [_vp, _vp, _ip]
         L.rich_cfl_dt.argtypes = [mp, sp, pp, _dp, _vp, C.c_size_t, _vp]
+        L.rich_stage_courant.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, C.c_size_t, _vp]
+        L.rich_stage_dt_of.argtypes = [mp, sp, sp, sp, C.c_double, _vp, pp, _vp, C.c_size_t,
+                                       _vp]
+        L.rich_stage_dt.argtypes = [_vp, _vp, _dp]
         L.rich_mesh_pack.argtypes = [C.POINTER(HostMeshView), _vp, _vp]
         L.rich_mesh_pack.restype = C.c_int
         L.rich_strerror.argtypes = [C.c_int]
@@ -123,6 +127,7 @@ def lib():
         L.rich_profile_enable.argtypes = [C.c_int]
         L.rich_profile_read.argtypes = [C.c_char_p, _dp, C.POINTER(C.c_int64)]
         for f in ("rich_workspace_size", "rich_stage", "rich_stage_flags", "rich_cfl_dt",
+                  "rich_stage_courant", "rich_stage_dt_of", "rich_stage_dt",
                   "rich_profile_enable", "rich_profile_read"):
             getattr(L, f).restype = C.c_int
         if hasattr(L, "rich_stage_batch"):
@@ -293,6 +298,34 @@ def rich_cfl_dt(mesh: DeviceMesh, state: DeviceState, params: Params, ws, stream
                            C.byref(dt), C.c_void_p(ws.data_ptr()), ws.numel(),
                            _stream_ptr(stream))
     _check(st, "rich_cfl_dt")
+    return dt.value
+
+
+def rich_stage_courant(mesh: DeviceMesh, src: DeviceState, base: DeviceState,
+                       out: DeviceState, h_factor, params: Params, ws, stream=None):
+    """Enqueue a stage whose step is h_factor * the Courant dt of src, both
+    taken on the device (dt stays in ws; see rich_stage_dt)."""
+    st = lib().rich_stage_courant(C.byref(mesh.c()), C.byref(src.c()), C.byref(base.c()),
+                                  C.byref(out.c()), float(h_factor), C.byref(params.c()),
+                                  C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
+    _check(st, "rich_stage_courant")
+
+
+def rich_stage_dt_of(mesh: DeviceMesh, src: DeviceState, base: DeviceState, out: DeviceState,
+                     h_factor, dt_ws, params: Params, ws, stream=None):
+    """Enqueue a stage whose step is h_factor * the dt held in workspace dt_ws."""
+    st = lib().rich_stage_dt_of(C.byref(mesh.c()), C.byref(src.c()), C.byref(base.c()),
+                                C.byref(out.c()), float(h_factor),
+                                C.c_void_p(dt_ws.data_ptr()), C.byref(params.c()),
+                                C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
+    _check(st, "rich_stage_dt_of")
+
+
+def rich_stage_dt(ws, stream=None):
+    """Synchronise and return the dt the last rich_stage_courant on ws wrote."""
+    dt = C.c_double(0.0)
+    _check(lib().rich_stage_dt(C.c_void_p(ws.data_ptr()), _stream_ptr(stream), C.byref(dt)),
+           "rich_stage_dt")
     return dt.value
 
 

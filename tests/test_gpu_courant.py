@@ -1,0 +1,152 @@
+"""Courant step fused into the stages (rich_stage_courant / rich_stage_dt_of /
+rich_stage_dt) against the separate path rich_cfl_dt + rich_stage, through
+the C-ABI.
+
+The fused path takes the same minimum over the same cells (section 2.3) and
+multiplies by the same factors, so the time-centred step it makes is bitwise
+equal to the separate one; its dt also agrees with the oracle's."""
+import numpy as np
+import pytest
+
+import oracle as O
+import parity_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+def _both_paths(name, k, **kw):
+    from paper_1410_3219_amd import rich as R
+    m, Qs, Qb, Xb, h, p = U.case(name, k=k, **kw)
+    gp = U.gpu_params(p)
+    dm = R.DeviceMesh.from_host(m)
+    s = R.DeviceState.from_host(Qs, Xb)
+    n = m.n_cells
+
+    # separate: host dt, then two stages with host steps
+    ws = R.workspace(n)
+    dt = R.rich_cfl_dt(dm, s, gp, ws)
+    half = R.DeviceState.empty_like(s)
+    R.rich_stage(dm, s, s, half, 0.5 * dt, gp, ws)
+    assert R.rich_stage_flags(ws) == 0
+    Qh, Xh = half.numpy()
+    mh = U.host_mesh(Xh[0], Xh[1], m.box, m.bc) if p.motion else m
+    dmh = R.DeviceMesh.from_host(mh)
+    out = R.DeviceState.empty_like(s)
+    R.rich_stage(dmh, half, s, out, dt, gp, ws)
+    assert R.rich_stage_flags(ws) == 0
+
+    # fused: dt stays on the device between the stages
+    wf = R.workspace(n)
+    half_f = R.DeviceState.empty_like(s)
+    R.rich_stage_courant(dm, s, s, half_f, 0.5, gp, wf)
+    assert R.rich_stage_flags(wf) == 0
+    dt_f = R.rich_stage_dt(wf)
+    Qhf, Xhf = half_f.numpy()
+    out_f = R.DeviceState.empty_like(s)
+    R.rich_stage_dt_of(dmh, half_f, s, out_f, 1.0, wf, gp, wf)
+    assert R.rich_stage_flags(wf) == 0
+    assert R.rich_stage_dt(wf) == dt_f     # the second stage left the slot alone
+    return m, Qs, p, dt, dt_f, (Qh, Xh, Qhf, Xhf), (out.numpy(), out_f.numpy())
+
+
+@pytest.mark.parametrize("name,k,kw", [
+    ("sod", 30, {}),
+    ("sedov", 33, {}),
+    ("kh", 26, {"riemann": 1}),
+    ("gresho", 30, {"motion": 0}),
+    ("wave", 37, {"g": (0.3, -0.7)}),
+    ("acoustic", 5, {}),          # 25 cells: one partial block
+])
+def test_fused_step_bitwise_equal(name, k, kw):
+    m, Qs, p, dt, dt_f, halves, outs = _both_paths(name, k, **kw)
+    dt_ref, st = O.cfl_dt(m, Qs, p)
+    assert st == 0
+    assert dt_f == dt, (dt_f, dt)
+    assert abs(dt_f - dt_ref) <= 1e-13 * dt_ref, (dt_f, dt_ref)
+    Qh, Xh, Qhf, Xhf = halves
+    assert np.array_equal(Qh, Qhf) and np.array_equal(Xh, Xhf)
+    (Q, X), (Qf, Xf) = outs
+    assert np.array_equal(Q, Qf) and np.array_equal(X, Xf)
+
+
+def test_fused_step_many_blocks():
+    """4 410 000 cells: 34 454 cell-kernel blocks, more than the one-block
+    final reduction covers in one pass of its four-way strided loop."""
+    m, Qs, p, dt, dt_f, halves, outs = _both_paths("wave", 2100, motion=0)
+    dt_ref, st = O.cfl_dt(m, Qs, p)
+    assert dt_f == dt and abs(dt_f - dt_ref) <= 1e-13 * dt_ref
+    (Q, X), (Qf, Xf) = outs
+    assert np.array_equal(Q, Qf) and np.array_equal(X, Xf)
+
+
+def test_device_step_with_extrapolated_fluxes():
+    """integrator 1 reads the step in its cell pass: rich_stage_dt_of with a
+    dt made on the device equals rich_stage with the host dt; the fused
+    Courant stage itself is rejected for it."""
+    from paper_1410_3219_amd import rich as R
+    m, Qs, Qb, Xb, h, p = U.case("sedov", k=30, integrator=1)
+    gp = U.gpu_params(p)
+    gp0 = U.gpu_params(p)
+    gp0.integrator = 0
+    dm = R.DeviceMesh.from_host(m)
+    s = R.DeviceState.from_host(Qs, Xb)
+    scratch = R.DeviceState.empty_like(s)
+    wdt = R.workspace(m.n_cells)
+    R.rich_stage_courant(dm, s, s, scratch, 1.0, gp0, wdt)
+    dt = R.rich_stage_dt(wdt)
+    assert dt == R.rich_cfl_dt(dm, s, gp, R.workspace(m.n_cells))
+
+    ws = R.workspace(m.n_cells)
+    a = R.DeviceState.empty_like(s)
+    R.rich_stage(dm, s, s, a, dt, gp, ws)
+    b = R.DeviceState.empty_like(s)
+    R.rich_stage_dt_of(dm, s, s, b, 1.0, wdt, gp, ws)
+    (Qa, Xa), (Qb2, Xb2) = a.numpy(), b.numpy()
+    assert np.array_equal(Qa, Qb2) and np.array_equal(Xa, Xb2)
+    ref = O.stage(m, Qs, Qs, Xb, dt, p)
+    eq, ex = U.errors(m, Qb2, Xb2, ref.Q, ref.X, Qs, p)
+    assert (eq < U.TOL).all() and ex < U.TOL, (eq, ex)
+
+    with pytest.raises(R.RichError) as e:
+        R.rich_stage_courant(dm, s, s, b, 1.0, gp, ws)
+    assert e.value.status == R.RICH_E_INVAL
+
+
+def test_invalid_dt_reported():
+    """A cell with negative pressure has no sound speed: the Courant minimum
+    is 0, the stage flags the domain error and rich_stage_dt says so."""
+    from paper_1410_3219_amd import rich as R
+    m, Qs, Qb, Xb, h, p = U.case("sod", k=20)
+    Qs = Qs.copy()
+    Qs[3, 7] = -1.0          # negative energy: negative pressure
+    dt_ref, st = O.cfl_dt(m, Qs, p)
+    assert st != 0
+    dm = R.DeviceMesh.from_host(m)
+    s = R.DeviceState.from_host(Qs, Xb)
+    out = R.DeviceState.empty_like(s)
+    ws = R.workspace(m.n_cells)
+    R.rich_stage_courant(dm, s, s, out, 0.5, U.gpu_params(p), ws)
+    assert R.rich_stage_flags(ws) & R.FLAG_DOMAIN
+    with pytest.raises(R.RichError) as e:
+        R.rich_stage_dt(ws)
+    assert e.value.status == R.RICH_E_DOMAIN
+
+
+def test_fused_arguments_rejected():
+    from paper_1410_3219_amd import rich as R
+    m, Qs, Qb, Xb, h, p = U.case("sod", k=8)
+    gp = U.gpu_params(p)
+    dm = R.DeviceMesh.from_host(m)
+    s = R.DeviceState.from_host(Qs, Xb)
+    out = R.DeviceState.empty_like(s)
+    ws = R.workspace(m.n_cells)
+    for bad in (float("nan"), -0.5, float("inf")):
+        with pytest.raises(R.RichError) as e:
+            R.rich_stage_courant(dm, s, s, out, bad, gp, ws)
+        assert e.value.status == R.RICH_E_INVAL
+    with pytest.raises(R.RichError) as e:
+        R.rich_stage_dt_of(dm, s, s, out, 1.0, ws[1:], gp, ws)   # misaligned dt workspace
+    assert e.value.status == R.RICH_E_INVAL
+    with pytest.raises(R.RichError) as e:
+        R.rich_stage_courant(dm, s, s, out, 0.5, gp, ws[: ws.numel() // 2])
+    assert e.value.status == R.RICH_E_NOMEM
