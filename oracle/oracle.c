@@ -18,6 +18,8 @@
  *   or_area_rate       section 5, eq. (areachange)
  *   or_stage           one conservative update (section 2.3)
  *   or_cfl_dt          section 2.3 (Courant condition, number 0.3)
+ *   or_voronoi         section 2.1: the Voronoi cells of the mesh points, by
+ *                      clipping against every other point (input stage)
  *
  * Readings of points the paper leaves open are listed where they are used.
  * Build: gcc -O2 -std=c99 -ffp-contract=off (no fast-math).
@@ -771,4 +773,156 @@ int or_cfl_dt(const or_mesh* m, const double* Q, const or_params* p, double* dt)
   free(prim);
   free(w);
   return isfinite(*dt) && *dt > 0.0 ? OR_OK : OR_E_DOMAIN;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Voronoi mesh by definition (section 2.1)                                 */
+/* ---------------------------------------------------------------------- */
+
+/* A convex polygon around the point, in coordinates relative to it, and the
+   neighbour label of the edge from vertex k to vertex k+1. */
+#define OR_VMAX 256
+typedef struct {
+  int nv;
+  double x[OR_VMAX], y[OR_VMAX];
+  int32_t lab[OR_VMAX];
+} or_poly;
+
+/* Keeps the part of the polygon where (x, y) . (ax, ay) <= b, labelling the
+   new edge `lab`.  Sutherland-Hodgman for one half-plane. */
+static int or_clip(or_poly* P, double ax, double ay, double b, int32_t lab) {
+  or_poly Q;
+  Q.nv = 0;
+  int any_out = 0;
+  for (int k = 0; k < P->nv; ++k)
+    if (P->x[k] * ax + P->y[k] * ay - b > 0.0) any_out = 1;
+  if (!any_out) return 0;
+  for (int k = 0; k < P->nv; ++k) {
+    int k1 = (k + 1) % P->nv;
+    double s0 = P->x[k] * ax + P->y[k] * ay - b;
+    double s1 = P->x[k1] * ax + P->y[k1] * ay - b;
+    if (s0 <= 0.0) {
+      if (Q.nv >= OR_VMAX) return -1;
+      Q.x[Q.nv] = P->x[k]; Q.y[Q.nv] = P->y[k]; Q.lab[Q.nv] = P->lab[k]; ++Q.nv;
+    }
+    if ((s0 <= 0.0) != (s1 <= 0.0)) {
+      /* the edge k -> k1 crosses the line: new vertex there */
+      double t = s0 / (s0 - s1);
+      if (Q.nv >= OR_VMAX) return -1;
+      Q.x[Q.nv] = P->x[k] + t * (P->x[k1] - P->x[k]);
+      Q.y[Q.nv] = P->y[k] + t * (P->y[k1] - P->y[k]);
+      /* leaving the kept side: the new edge follows this vertex;
+         entering it: the old edge's label continues */
+      Q.lab[Q.nv] = s0 <= 0.0 ? lab : P->lab[k];
+      ++Q.nv;
+    }
+  }
+  *P = Q;
+  return 0;
+}
+
+int or_voronoi(int64_t n, const double* px, const double* py, const double* box,
+               uint32_t bc, int32_t max_fan, double* area, double* sx, double* sy,
+               int32_t* deg, int32_t* nb, double* len, double* fx, double* fy) {
+  if (n < 1 || !px || !py || !box || max_fan < 1 || !area || !sx || !sy || !deg || !nb ||
+      !len || !fx || !fy)
+    return OR_E_INVAL;
+  const double Lx = box[2] - box[0], Ly = box[3] - box[1];
+  if (!(Lx > 0.0) || !(Ly > 0.0) || (bc != 0 && bc != 1)) return OR_E_INVAL;
+  or_poly* P = malloc(sizeof(or_poly));
+  int32_t* fan = malloc(sizeof(int32_t) * (size_t)n * OR_VMAX);
+  double* vx = malloc(sizeof(double) * (size_t)n * OR_VMAX);
+  double* vy = malloc(sizeof(double) * (size_t)n * OR_VMAX);
+  int32_t* nv = malloc(sizeof(int32_t) * (size_t)n);
+  if (!P || !fan || !vx || !vy || !nv) {
+    free(P); free(fan); free(vx); free(vy); free(nv);
+    return OR_E_INVAL;
+  }
+  int st = OR_OK;
+  for (int64_t i = 0; i < n && st == OR_OK; ++i) {
+    const double xi = px[i], yi = py[i];
+    /* the region the cell cannot leave, counter-clockwise from its lower
+       left corner: the box (walls), or the bisectors with the point's own
+       nearest images (periodic) */
+    double hx0, hx1, hy0, hy1;
+    int32_t lb, lr, lt, ll;
+    if (bc == 0) {
+      hx0 = box[0] - xi; hx1 = box[2] - xi; hy0 = box[1] - yi; hy1 = box[3] - yi;
+      lb = (int32_t)((uint32_t)i | (11u << 28));   /* y0 wall */
+      lr = (int32_t)((uint32_t)i | (10u << 28));   /* x1 wall */
+      lt = (int32_t)((uint32_t)i | (12u << 28));   /* y1 wall */
+      ll = (int32_t)((uint32_t)i | (9u << 28));    /* x0 wall */
+    } else {
+      hx0 = -0.5 * Lx; hx1 = 0.5 * Lx; hy0 = -0.5 * Ly; hy1 = 0.5 * Ly;
+      /* image code of shift (sx, sy): k = 3 (sx + 1) + (sy + 1), skipping 4 */
+      lb = (int32_t)((uint32_t)i | (4u << 28));    /* shift (0, -1) */
+      lr = (int32_t)((uint32_t)i | (7u << 28));    /* shift (1, 0) */
+      lt = (int32_t)((uint32_t)i | (5u << 28));    /* shift (0, 1) */
+      ll = (int32_t)((uint32_t)i | (2u << 28));    /* shift (-1, 0) */
+    }
+    P->nv = 4;
+    P->x[0] = hx0; P->y[0] = hy0; P->lab[0] = lb;
+    P->x[1] = hx1; P->y[1] = hy0; P->lab[1] = lr;
+    P->x[2] = hx1; P->y[2] = hy1; P->lab[2] = lt;
+    P->x[3] = hx0; P->y[3] = hy1; P->lab[3] = ll;
+    for (int64_t j = 0; j < n && st == OR_OK; ++j) {
+      for (int sxs = -1; sxs <= 1; ++sxs)
+        for (int sys = -1; sys <= 1; ++sys) {
+          if (bc == 0 && (sxs != 0 || sys != 0)) continue;
+          if (j == i && sxs == 0 && sys == 0) continue;
+          /* image of point j, relative to point i */
+          double dx = px[j] + sxs * Lx - xi, dy = py[j] + sys * Ly - yi;
+          int k = 3 * (sxs + 1) + (sys + 1);
+          uint32_t code = bc == 0 ? 0u : (uint32_t)(k < 4 ? k + 1 : (k == 4 ? 0 : k));
+          int32_t lab = (int32_t)((uint32_t)j | (code << 28));
+          /* nearer to i than to the image: x . d <= |d|^2 / 2 */
+          if (or_clip(P, dx, dy, 0.5 * (dx * dx + dy * dy), lab) != 0) st = OR_E_INVAL;
+        }
+    }
+    if (st != OR_OK) break;
+    if (P->nv < 3 || P->nv > OR_VMAX) { st = OR_E_INVAL; break; }
+    /* area and centroid by the shoelace sums over the triangles fanned
+       from the point */
+    double A2 = 0.0, cx = 0.0, cy = 0.0;
+    for (int k = 0; k < P->nv; ++k) {
+      int k1 = (k + 1) % P->nv;
+      double cr = P->x[k] * P->y[k1] - P->y[k] * P->x[k1];
+      A2 += cr;
+      cx += (P->x[k] + P->x[k1]) * cr;
+      cy += (P->y[k] + P->y[k1]) * cr;
+    }
+    area[i] = 0.5 * A2;
+    sx[i] = xi + cx / (3.0 * A2);
+    sy[i] = yi + cy / (3.0 * A2);
+    nv[i] = P->nv;
+    for (int k = 0; k < P->nv; ++k) {
+      fan[i * OR_VMAX + k] = P->lab[k];
+      vx[i * OR_VMAX + k] = xi + P->x[k];
+      vy[i * OR_VMAX + k] = yi + P->y[k];
+    }
+  }
+  /* edges, without the degenerate ones */
+  for (int64_t i = 0; i < n && st == OR_OK; ++i) {
+    const double Ri = sqrt(area[i] / OR_PI);
+    int32_t d = 0;
+    for (int k = 0; k < nv[i]; ++k) {
+      int k1 = (k + 1) % nv[i];
+      double ax = vx[i * OR_VMAX + k], ay = vy[i * OR_VMAX + k];
+      double bx = vx[i * OR_VMAX + k1], by = vy[i * OR_VMAX + k1];
+      double L = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
+      int32_t lab = fan[i * OR_VMAX + k];
+      int64_t j = (int64_t)((uint32_t)lab & 0x0FFFFFFFu);
+      double Rj = sqrt(area[j] / OR_PI);
+      if (!(L >= 1e-12 * 0.5 * (Ri + Rj))) continue;
+      if (d >= max_fan) { st = OR_E_INVAL; break; }
+      nb[i * max_fan + d] = lab;
+      len[i * max_fan + d] = L;
+      fx[i * max_fan + d] = 0.5 * (ax + bx);
+      fy[i * max_fan + d] = 0.5 * (ay + by);
+      ++d;
+    }
+    deg[i] = d;
+  }
+  free(P); free(fan); free(vx); free(vy); free(nv);
+  return st;
 }

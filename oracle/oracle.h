@@ -94,6 +94,21 @@ int or_stage(const or_mesh* m, const double* Qsrc, const double* Qbase,
 /* Courant time step of the state Q on mesh m (A0). */
 int or_cfl_dt(const or_mesh* m, const double* Q, const or_params* p, double* dt);
 
+/* Voronoi mesh of the points by its definition (section 2.1): cell i is the
+ * set of points of the box nearer to (px_i, py_i) than to any other point
+ * (walls: the box bounds the cell, which is what the mirror images of the
+ * point across the walls give; periodic box: every periodic image of every
+ * point counts).  O(n^2) half-plane clipping, for small n.
+ * Outputs: area[n], centroid sx[n], sy[n], deg[n] and, for cell i, slots
+ * i*max_fan .. i*max_fan+deg[i]-1, counter-clockwise: nb (neighbour cell |
+ * code << 28: 0 interior, 1..8 periodic image, 9..12 wall x0 x1 y0 y1), len,
+ * fx, fy (edge midpoint).  Edges shorter than 1e-12 (R_i + R_j) / 2 with
+ * R = sqrt(area / pi) are left out.  Returns OR_E_INVAL for bad arguments or
+ * a cell with more than max_fan edges. */
+int or_voronoi(int64_t n, const double* px, const double* py, const double* box,
+               uint32_t bc, int32_t max_fan, double* area, double* sx, double* sy,
+               int32_t* deg, int32_t* nb, double* len, double* fx, double* fy);
+
 /* One-dimensional Riemann problem in the frame of an edge.  States are
  * (rho, u, vt, p): density, normal velocity, tangential velocity, pressure.
  * Flux out: (mass, normal momentum, tangential momentum, energy). */

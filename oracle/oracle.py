@@ -101,13 +101,15 @@ def lib():
         L.or_stage.argtypes = [mp, _dp, _dp, _dp, C.c_double, pp, _dp, _dp, _dp, _dp,
                                _dp, _ip, _dp]
         L.or_cfl_dt.argtypes = [mp, _dp, pp, _dp]
+        L.or_voronoi.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_uint32, C.c_int32, _dp, _dp,
+                                 _dp, _ip, _ip, _dp, _dp, _dp]
         L.or_hllc.argtypes = [C.c_double, _dp, _dp, _dp]
         L.or_hllc.restype = None
         L.or_exact.argtypes = [C.c_double, _dp, _dp, _dp, _dp]
         L.or_exact_sample.argtypes = [C.c_double, _dp, _dp, C.c_double, _dp]
         for f in ("or_primitives", "or_point_velocity", "or_gradients", "or_limiter",
                   "or_edge_fluxes", "or_area_rate", "or_stage", "or_cfl_dt", "or_exact",
-                  "or_exact_sample"):
+                  "or_exact_sample", "or_voronoi"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -321,3 +323,92 @@ def build_variant(src_text, out_path):
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC",
                            "-shared", "-I", _HERE, src, "-o", out_path, "-lm"])
     return out_path
+
+
+# ---------------------------------------------------------------------------
+# Voronoi mesh by definition (input stage, section 2.1)
+# ---------------------------------------------------------------------------
+CELL_MASK = 0x0FFFFFFF
+CODE_SHIFT = 28
+
+
+class Voronoi:
+    """Cells of or_voronoi: area, centroid (sx, sy) and, per cell, the
+    counter-clockwise list of (neighbour cell, code, length, midpoint)."""
+
+
+def voronoi(px, py, box, bc, max_fan=32):
+    px = np.ascontiguousarray(px, dtype=np.float64)
+    py = np.ascontiguousarray(py, dtype=np.float64)
+    n = px.shape[0]
+    bx = np.ascontiguousarray(box, dtype=np.float64)
+    V = Voronoi()
+    V.px, V.py, V.box, V.bc, V.max_fan = px, py, tuple(box), int(bc), max_fan
+    V.area, V.sx, V.sy = np.empty(n), np.empty(n), np.empty(n)
+    V.deg = np.zeros(n, dtype=np.int32)
+    V.nb = np.zeros(n * max_fan, dtype=np.int32)
+    V.len, V.fx, V.fy = (np.zeros(n * max_fan) for _ in range(3))
+    st = lib().or_voronoi(n, _d(px), _d(py), _d(bx), int(bc), max_fan, _d(V.area), _d(V.sx),
+                          _d(V.sy), _i(V.deg), _i(V.nb), _d(V.len), _d(V.fx), _d(V.fy))
+    if st != 0:
+        raise ValueError(f"or_voronoi failed ({st})")
+    return V
+
+
+def fan(V, i):
+    """[(cell, code, length, fx, fy)] of cell i, counter-clockwise."""
+    out = []
+    for q in range(V.deg[i]):
+        s = i * V.max_fan + q
+        u = int(V.nb[s]) & 0xFFFFFFFF
+        out.append((u & CELL_MASK, u >> CODE_SHIFT, V.len[s], V.fx[s], V.fy[s]))
+    return out
+
+
+def voronoi_mesh(V):
+    """The mesh arrays of the input stage (px, py, sx, sy, area, e_i, e_j,
+    e_len, e_fx, e_fy, off, idx, box, bc) assembled from the cells: an edge
+    belongs to the lower-numbered cell (a wall edge to its cell, an edge
+    between a cell and its own periodic image to the side with code >= 5);
+    each cell's CSR lists its edges counter-clockwise as 2 * edge + side."""
+    n = V.px.shape[0]
+
+    def owns(i, cell, code):
+        if code >= 9:
+            return True
+        if cell != i:
+            return i < cell
+        return code >= 5
+
+    e_i, e_j, e_len, e_fx, e_fy, where = [], [], [], [], [], {}
+    for i in range(n):
+        for (cell, code, L, fx_, fy_) in fan(V, i):
+            if owns(i, cell, code):
+                where[(i, cell, code)] = len(e_i)
+                e_i.append(i)
+                e_j.append(np.int32(np.uint32(cell | (code << CODE_SHIFT)).view(np.int32)))
+                e_len.append(L)
+                e_fx.append(fx_)
+                e_fy.append(fy_)
+    off, idx = [0], []
+    for i in range(n):
+        for (cell, code, L, fx_, fy_) in fan(V, i):
+            if owns(i, cell, code):
+                idx.append(2 * where[(i, cell, code)])
+            else:
+                back = 0 if code == 0 else 9 - code
+                idx.append(2 * where[(cell, i, back)] + 1)
+        off.append(len(idx))
+
+    class M:
+        pass
+    m = M()
+    m.n_cells, m.n_edges, m.n_csr = n, len(e_i), len(idx)
+    m.px, m.py, m.sx, m.sy, m.area = V.px, V.py, V.sx, V.sy, V.area
+    m.e_i = np.array(e_i, dtype=np.int32)
+    m.e_j = np.array(e_j, dtype=np.int32)
+    m.e_len, m.e_fx, m.e_fy = (np.array(a, dtype=np.float64) for a in (e_len, e_fx, e_fy))
+    m.off = np.array(off, dtype=np.int32)
+    m.idx = np.array(idx, dtype=np.int32)
+    m.box, m.bc = V.box, V.bc
+    return m

@@ -40,6 +40,14 @@ AssertionError when the oracle disagrees.  What each pin fixes:
                        time-centred steps make the source second order)
   extrapolated_second_order  the extrapolated-fluxes integrator (section
                        2.3) converges at second order on a sound wave
+  voronoi_lattices     Voronoi cells of square and hexagonal lattices in
+                       closed form (areas, centroids, edge lengths,
+                       midpoints, neighbour codes), walls and periodic
+  voronoi_identities   random points: areas tile the box, first moments
+                       integrate the box, wall edges make its perimeter,
+                       every edge is seen alike from both sides
+  voronoi_host_agreement  the same cells as the Delaunay construction with
+                       exact predicates of the input stage
 """
 import json
 import math
@@ -671,8 +679,129 @@ def sod_accuracy(O):
     assert max(abs(a - b) for a, b in zip(L64, L64_exact)) < 0.05
 
 
+def _fan_map(O, V, i):
+    return {(c, k): (L, fx, fy) for (c, k, L, fx, fy) in O.fan(V, i)}
+
+
+def _shift_of(code):
+    k = code - 1 if code <= 4 else code
+    return k // 3 - 1, k % 3 - 1
+
+
+def voronoi_lattices(O):
+    k = 12
+    h = 1.0 / k
+    g = (np.arange(k) + 0.5) * h
+    px, py = [a.ravel() for a in np.meshgrid(g, g, indexing="ij")]
+    for bc in (0, 1):
+        V = O.voronoi(px, py, BOX, bc)
+        assert np.allclose(V.area, h * h, rtol=1e-13, atol=0)
+        assert np.allclose(V.sx, px, rtol=0, atol=1e-15)
+        assert np.allclose(V.sy, py, rtol=0, atol=1e-15)
+        for i in range(k * k):
+            F = O.fan(V, i)
+            assert len(F) == 4, (bc, i, F)
+            for (c, code, L, fx, fy) in F:
+                assert abs(L - h) < 1e-15
+                # the midpoint is half way to the neighbour (or its image / mirror)
+                if code >= 9:
+                    assert c == i
+                    mx, my = {9: (0.0, py[i]), 10: (1.0, py[i]), 11: (px[i], 0.0),
+                              12: (px[i], 1.0)}[code]
+                else:
+                    sx_, sy_ = _shift_of(code) if code else (0, 0)
+                    mx = 0.5 * (px[i] + px[c] + sx_)
+                    my = 0.5 * (py[i] + py[c] + sy_)
+                assert abs(fx - mx) < 1e-15 and abs(fy - my) < 1e-15, (bc, i, code)
+            codes = sorted(code for (_, code, _, _, _) in F)
+            if bc == 0 and 0 < i % k < k - 1 and 0 < i // k < k - 1:
+                assert codes == [0, 0, 0, 0]
+        if bc == 1:   # corner cell: two neighbours across the periodic seams
+            F = O.fan(V, 0)
+            got = sorted((c, code) for (c, code, _, _, _) in F)
+            assert got == sorted([(1, 0), (k, 0), (k - 1, 4), ((k - 1) * k, 2)]), got
+    # one point in a periodic box: its cell is the box, bounded by its own
+    # images across the four sides
+    V = O.voronoi(np.array([0.3]), np.array([0.6]), BOX, 1)
+    F = O.fan(V, 0)
+    assert abs(V.area[0] - 1.0) < 1e-15
+    assert sorted((c, code) for (c, code, _, _, _) in F) == [(0, 2), (0, 4), (0, 5), (0, 7)]
+    for (_, code, L, fx, fy) in F:
+        sx_, sy_ = _shift_of(code)
+        assert abs(L - 1.0) < 1e-15
+        assert abs(fx - (0.3 + 0.5 * sx_)) < 1e-15 and abs(fy - (0.6 + 0.5 * sy_)) < 1e-15
+    # hexagonal lattice, spacing a, periodic box of 8 x 8 rows
+    m = 8
+    a = 1.0 / m
+    Ly = m * a * math.sqrt(3.0) / 2.0
+    xs, ys = [], []
+    for r in range(m):
+        for c in range(m):
+            xs.append((c + 0.5 * (r % 2) + 0.25) * a)
+            ys.append((r + 0.5) * a * math.sqrt(3.0) / 2.0)
+    box = (0.0, 0.0, 1.0, Ly)
+    V = O.voronoi(np.array(xs), np.array(ys), box, 1)
+    assert np.allclose(V.area, math.sqrt(3.0) / 2.0 * a * a, rtol=1e-13, atol=0)
+    assert np.allclose(V.sx, xs, atol=1e-15) and np.allclose(V.sy, ys, atol=1e-15)
+    for i in range(m * m):
+        F = O.fan(V, i)
+        assert len(F) == 6
+        for (_, _, L, _, _) in F:
+            assert abs(L - a / math.sqrt(3.0)) < 1e-15
+
+
+def voronoi_identities(O):
+    r = np.random.default_rng(11)
+    n = 300
+    px, py = r.uniform(0.02, 0.98, n), r.uniform(0.02, 0.98, n)
+    box = (0.0, 0.0, 1.0, 0.9)
+    py = py * 0.9
+    for bc in (0, 1):
+        V = O.voronoi(px, py, box, bc)
+        assert (V.area > 0).all()
+        assert abs(V.area.sum() - 0.9) < 1e-13
+        if bc == 0:
+            # first moments of the cells integrate x and y over the box
+            assert abs((V.area * V.sx).sum() - 0.5 * 0.9) < 1e-13
+            assert abs((V.area * V.sy).sum() - 0.5 * 0.9 * 0.9) < 1e-13
+            wall = sum(L for i in range(n) for (_, code, L, _, _) in O.fan(V, i) if code >= 9)
+            assert abs(wall - 2 * (1.0 + 0.9)) < 1e-13
+        for i in range(n):
+            Fi = _fan_map(O, V, i)
+            for (c, code), (L, fx, fy) in Fi.items():
+                if code >= 9:
+                    continue
+                back = 0 if code == 0 else 9 - code
+                Lj, fxj, fyj = _fan_map(O, V, c)[(i, back)]
+                sx_, sy_ = _shift_of(code) if code else (0, 0)
+                assert abs(L - Lj) < 1e-14
+                assert abs(fx - (fxj + sx_ * 1.0)) < 1e-14 and abs(fy - (fyj + sy_ * 0.9)) < 1e-14
+
+
+def voronoi_host_agreement(O):
+    for bc, P in ((0, I.sod(k=20, seed=5)), (1, I.advected_wave(k=20, seed=6)),
+                  (0, I.sedov(k=18, seed=2, lloyd_iters=1))):
+        m = T.rich_tess_build(P.px, P.py, P.box, P.bc)
+        V = O.voronoi(m.px, m.py, P.box, P.bc)
+        assert np.abs(V.area - m.area).max() < 1e-14 * m.area.max()
+        assert np.abs(V.sx - m.sx).max() < 1e-14 and np.abs(V.sy - m.sy).max() < 1e-14
+        for i in range(m.n_cells):
+            host = {}
+            for kk in range(m.off[i], m.off[i + 1]):
+                e, side = m.idx[kk] >> 1, m.idx[kk] & 1
+                u = int(m.e_j[e]) & 0xFFFFFFFF
+                c, code = u & 0x0FFFFFFF, u >> 28
+                key = (c, code) if side == 0 else (int(m.e_i[e]), 0 if code == 0 else 9 - code)
+                host[key] = m.e_len[e]
+            mine = _fan_map(O, V, i)
+            assert set(host) == set(mine), (bc, i, sorted(host), sorted(mine))
+            for key, L in host.items():
+                assert abs(mine[key][0] - L) < 1e-14
+
+
 ALL = [gradient_linear, gradient_periodic, tvd_example, limiter_bounds, hllc_cases,
        hllc_weak_waves, exact_shock_tube, exact_two_shocks, area_rate_fd,
        uniform_state_moving, uniform_flow, advection, conservation, galilean,
        mirror_symmetry, shock_detector, point_velocity, cfl_uniform, sod_accuracy,
-       free_fall, extrapolated_second_order]
+       free_fall, extrapolated_second_order, voronoi_lattices, voronoi_identities,
+       voronoi_host_agreement]

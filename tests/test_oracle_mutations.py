@@ -127,6 +127,22 @@ MUTATIONS = [
      "    if (!(t > 0.0) || !isfinite(t)) t = 0.0;\n",
      "\n",
      [pins.cfl_uniform]),
+    ("Voronoi centroid without the factor 1/3",
+     "sx[i] = xi + cx / (3.0 * A2);",
+     "sx[i] = xi + cx / A2;",
+     [pins.voronoi_identities]),
+    ("Voronoi edge midpoint taken at one end",
+     "fx[i * max_fan + d] = 0.5 * (ax + bx);",
+     "fx[i * max_fan + d] = ax;",
+     [pins.voronoi_lattices, pins.voronoi_identities]),
+    ("Voronoi clip labels the new edge with the old neighbour",
+     "Q.lab[Q.nv] = s0 <= 0.0 ? lab : P->lab[k];",
+     "Q.lab[Q.nv] = s0 <= 0.0 ? P->lab[k] : lab;",
+     [pins.voronoi_host_agreement]),
+    ("Voronoi periodic image code of the lower side",
+     "(4u << 28));    /* shift (0, -1) */",
+     "(3u << 28));    /* shift (0, -1) */",
+     [pins.voronoi_lattices]),
 ]
 
 
