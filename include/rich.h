@@ -318,6 +318,84 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
                     void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Device re-tessellation (section 2.1: the mesh is the Voronoi tessellation
+ * of the mesh points, rebuilt after every move).  The Voronoi cell of each
+ * new point is found by clipping, on the device, the box (walls) or the
+ * square bounded by the point's own periodic images against the bisectors
+ * with candidate points: the neighbours and neighbours' neighbours of the
+ * cell in a previous mesh `prev` of the same points (periodic: the nearest
+ * image of each candidate).  The result has the input stage's layout and
+ * rules: the same neighbour codes, edges shorter than 1e-12 (R_i + R_j)/2
+ * dropped, an edge owned by the lower-numbered cell (a wall edge by its
+ * cell; an edge with the cell's own periodic image by the side with code
+ * >= 5), each cell's edges and CSR entries counter-clockwise.  The order of
+ * a cell's entries may start elsewhere than the host stage's, so stage
+ * results on the two meshes agree to rounding, not bitwise.
+ *
+ * The tessellation is certified on the device: every kept edge must be seen
+ * by both of its cells with the same length, and the cell areas must sum to
+ * the box area.  Each clipped cell contains the true cell, so together these
+ * fail when a true neighbour was missing from the candidates (points moved
+ * further than the previous mesh's second ring).  Then a RICH_RETESS_*
+ * bit is set, the output mesh is left with no edges (a stage on it reads no
+ * edge), and the caller rebuilds the mesh on the host (rich_tess_build).
+ */
+#define RICH_RETESS_POINT    1   /* a point outside the box or not finite       */
+#define RICH_RETESS_FAN      2   /* a cell with more than 20 edges              */
+#define RICH_RETESS_CLIP     4   /* a clip left nothing, or parallel bisectors  */
+#define RICH_RETESS_ASYM     8   /* an edge not seen alike from both cells      */
+#define RICH_RETESS_AREA    16   /* cell areas do not sum to the box area       */
+#define RICH_RETESS_CAP     32   /* more edges than the output capacity         */
+
+/* Device buffers of a re-tessellated mesh (caller-allocated, sizes from
+ * rich_retess_capacity). */
+typedef struct rich_mesh_bufs {
+  int64_t n_cells;
+  int64_t cap_edges;     /* entries of edges[]                        */
+  int64_t cap_csr;       /* entries of idx[]                          */
+  rich_cell* cells;      /* [n_cells], 16-byte aligned                */
+  rich_edge* edges;      /* [cap_edges], 16-byte aligned              */
+  int32_t* off;          /* [n_cells + 1]                             */
+  int32_t* idx;          /* [cap_csr]                                 */
+  int32_t* eoff;         /* [n_cells + 1]                             */
+} rich_mesh_bufs;
+
+/* Edge and CSR capacities that hold any mesh of n_cells cells (at most
+ * 3 n interior edges plus the wall edges). */
+int rich_retess_capacity(int64_t n_cells, int64_t* cap_edges, int64_t* cap_csr);
+
+/* Workspace bytes of rich_retess for n_cells cells (256-byte aligned device
+ * memory).  Its first 64 bytes are the result header (rich_retess_result);
+ * the caller zeroes them once when allocating it. */
+int rich_retess_workspace_size(int64_t n_cells, size_t* bytes);
+
+/* Re-tessellate: new points (x, y) (device arrays of prev->n_cells; walls:
+ * strictly inside the box, periodic: inside [x0, x1) x [y0, y1), as a stage
+ * leaves them) with candidates from mesh `prev`, into `out`.  prev and out
+ * must not share memory.  Enqueued on `stream`; RICH_E_INVAL without
+ * enqueuing for bad arguments (a periodic box needs at least 16 cells). */
+int rich_retess(const rich_mesh* prev, const double* x, const double* y,
+                const rich_mesh_bufs* out, void* ws, size_t ws_bytes, void* stream);
+
+/* The stage's view of `out` after rich_retess: n_edges and n_csr are the
+ * capacities (the kernels use them as bounds only), box and bc as given. */
+int rich_retess_view(const rich_mesh_bufs* out, const double box[4], uint32_t bc,
+                     rich_mesh* m);
+
+typedef struct rich_retess_info {
+  int32_t flags;      /* RICH_RETESS_* bits of the last rich_retess on ws   */
+  int32_t sticky;     /* OR of the flags of every call since ws was zeroed  */
+  int64_t n_edges;    /* edges and CSR entries of the last mesh             */
+  int64_t n_csr;
+  int64_t n_dropped;  /* degenerate edges left out                          */
+  double area_sum;    /* sum of the cell areas                              */
+} rich_retess_info;
+
+/* Synchronise `stream` and read the header of ws.  Returns RICH_E_MESH when
+ * the last call's flags are set, else RICH_OK. */
+int rich_retess_result(void* ws, void* stream, rich_retess_info* info);
+
+/*
  * Kernel timing for benchmarks.  While enabled, every stage records HIP
  * events on its launch stream around each of its kernels ("k_cell",
  * "k_flux", or "k_stage" for the fused variant); rich_profile_read

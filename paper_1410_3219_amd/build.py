@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 TESS_SRC = os.path.join(HERE, "host", "tess.cpp")
 TESS_LIB = os.path.join(HERE, "librichtess.so")
-HIP_SRCS = [os.path.join(HERE, "csrc", f) for f in ("rich_kernels.hip",)]
+HIP_SRCS = [os.path.join(HERE, "csrc", f) for f in ("rich_kernels.hip", "rich_retess.hip")]
 HIP_LIB = os.path.join(HERE, "librich.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 

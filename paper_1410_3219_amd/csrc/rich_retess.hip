@@ -1,0 +1,708 @@
+// Device re-tessellation of moved mesh points (section 2.1: the mesh is the
+// Voronoi tessellation of its points, rebuilt after every move).
+//
+// Cell i of the new mesh is the polygon left after clipping a bounding
+// region against the bisector of the new point r_i with each candidate point:
+// the region is the box for walls (its sides are the bisectors with the
+// point's mirror images) and, for a periodic box, the square bounded by the
+// bisectors with the point's own images one box length away.  The candidates
+// are the neighbours and the neighbours' neighbours of the cell in a previous
+// mesh of the same points, each at its nearest periodic image.  A clipped
+// polygon always contains the true Voronoi cell; it equals it when every true
+// neighbour was a candidate.  The kernels certify that (every kept edge seen
+// alike by both cells; the areas summing to the box area) instead of
+// assuming it, and report failure so that the caller rebuilds on the host.
+//
+// The polygon is held as the counter-clockwise list of the displacements d
+// from r_i to its edge-generating points (neighbours, images, mirrors):
+// vertex q is the intersection of the bisectors of entries q-1 and q, i.e.
+// the point p with p.d = |d|^2 / 2 for both, so vertices come from the
+// generating points alone and not from the order of the clips.
+//
+// Pipeline (one launch each, all on the caller's stream):
+//   k_rt_begin    clear the result header
+//   k_rt_clip     one thread per cell: clip, area, centroid, edge slots
+//   k_rt_classify keep / own each slot by the input stage's rules, check
+//                 each kept edge against the neighbour's slot, count
+//   k_rt_scan_*   prefix sums of the counts into off[] and eoff[]
+//   k_rt_emit     edge records and CSR entries
+//   k_rt_end      fold the flags into the sticky word
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "rich.h"
+
+namespace retess {
+
+constexpr uint32_t kMask = 0x0FFFFFFFu;
+constexpr int kShift = 28;
+constexpr int kMaxFan = 20;    // edges of a finished cell (RICH_RETESS_FAN beyond)
+constexpr int kMaxPoly = 24;   // edges of a polygon while it is being clipped
+constexpr int kRingMax = 64;   // CSR entries read per cell of the previous mesh
+constexpr int kThreads = 128;
+constexpr int kScanThreads = 1024;
+constexpr double kPi = 3.14159265358979323846;
+// neighbour codes of the reflecting walls x = x0, x = x1, y = y0, y = y1 in
+// the top bits of rich_edge.j (the neighbour is the cell's own mirror image)
+constexpr int kWallX0 = 9, kWallX1 = 10, kWallY0 = 11, kWallY1 = 12;
+
+struct Hdr {  // first 64 bytes of the workspace
+  int32_t flags, sticky;
+  int64_t n_edges, n_csr, n_dropped;
+  double area_sum;
+  int64_t pad[3];
+};
+static_assert(sizeof(Hdr) == 64, "result header");
+
+struct Args {
+  // previous mesh (candidates)
+  const int32_t* p_off;
+  const int32_t* p_idx;
+  const rich_edge* p_edges;
+  int64_t p_n_csr, p_n_edges;
+  // new points and output
+  const double *x, *y;
+  rich_cell* cells;
+  rich_edge* edges;
+  int32_t *off, *idx, *eoff;
+  int64_t cap_edges, cap_csr;
+  // workspace
+  Hdr* hdr;
+  int32_t* deg;        // [n]
+  int32_t* s_nb;       // [n][kMaxFan] generating point: cell | code << 28
+  double *s_len, *s_fx, *s_fy;  // [n][kMaxFan]
+  uint8_t* s_flag;     // [n][kMaxFan] bit 0 kept, bit 1 owned
+  int64_t* bsum;       // [2][n_scan_blocks] block totals of kept / owned
+  // geometry
+  double x0, y0, x1, y1, Lx, Ly;
+  int32_t n, bc, n_scan_blocks;
+};
+
+__device__ __forceinline__ int32_t pack(int cell, int code) {
+  return (int32_t)((uint32_t)cell | ((uint32_t)code << kShift));
+}
+// periodic image shift (sx, sy) in box lengths <-> code 1..8 (0 is no shift)
+__device__ __forceinline__ int shift_code(int sx, int sy) {
+  const int k = (sx + 1) * 3 + (sy + 1);
+  return k < 4 ? k + 1 : k;
+}
+__device__ __forceinline__ void code_shift(int code, int& sx, int& sy) {
+  const int k = code <= 4 ? code - 1 : code;
+  sx = k / 3 - 1;
+  sy = k % 3 - 1;
+}
+__device__ __forceinline__ int back_code(int code) { return code == 0 ? 0 : 9 - code; }
+
+// The point p with p.a = |a|^2/2 and p.b = |b|^2/2 (the Voronoi vertex of the
+// origin and the points a and b); false unless b is counter-clockwise of a.
+__device__ __forceinline__ bool bisector_meet(double ax, double ay, double bx, double by,
+                                              double& px, double& py) {
+  const double det = ax * by - ay * bx;
+  const double ha = 0.5 * (ax * ax + ay * ay), hb = 0.5 * (bx * bx + by * by);
+  px = (ha * by - hb * ay) / det;
+  py = (ax * hb - ha * bx) / det;
+  return det > 0.0;
+}
+
+// Neighbour cell of CSR entry k of the previous mesh (-1 if out of range).
+__device__ __forceinline__ int prev_neighbour(const Args& a, int k) {
+  const int ent = a.p_idx[k];
+  const int e = ent >> 1;
+  if (ent < 0 || e >= a.p_n_edges) return -1;
+  if (ent & 1) return a.p_edges[e].i;
+  return (int)((uint32_t)a.p_edges[e].j & kMask);
+}
+
+__global__ void k_rt_begin(Hdr* h) {
+  if (threadIdx.x == 0) {
+    h->flags = 0;
+    h->n_edges = 0;
+    h->n_csr = 0;
+    h->n_dropped = 0;
+    h->area_sum = 0.0;
+  }
+}
+
+__global__ void k_rt_end(Hdr* h) {
+  if (threadIdx.x == 0) h->sticky |= h->flags;
+}
+
+// ---------------------------------------------------------------------------
+// clipping
+// ---------------------------------------------------------------------------
+struct Poly {
+  double dx[kMaxPoly], dy[kMaxPoly];
+  int32_t id[kMaxPoly];
+  int nv;
+};
+
+// Clip P by the half-plane p.d <= |d|^2/2 of candidate `cid` at displacement
+// d.  Returns a RICH_RETESS_* bit on failure, else 0.
+__device__ int clip(Poly& P, double dx, double dy, int32_t cid) {
+  for (int q = 0; q < P.nv; ++q)
+    if (P.id[q] == cid) return 0;  // already an edge of the polygon
+  const double h = 0.5 * (dx * dx + dy * dy);
+  // a vertex is cut off when it is further than 1e-14 |d| beyond the
+  // bisector: a shallower cut would make an edge far below the
+  // degenerate-edge threshold of the input stage
+  const double tol = 2e-14 * h;
+  uint32_t out = 0;
+  for (int q = 0; q < P.nv; ++q) {
+    const int qm = q == 0 ? P.nv - 1 : q - 1;
+    double vx, vy;
+    if (!bisector_meet(P.dx[qm], P.dy[qm], P.dx[q], P.dy[q], vx, vy)) return RICH_RETESS_CLIP;
+    if (vx * dx + vy * dy - h > tol) out |= 1u << q;
+  }
+  if (out == 0) return 0;
+  const uint32_t full = P.nv == 32 ? 0xFFFFFFFFu : ((1u << P.nv) - 1u);
+  if (out == full) return RICH_RETESS_CLIP;
+  // the cut vertices form one cyclic run a .. a+m-1 (the polygon is convex)
+  int a = -1, starts = 0;
+  for (int q = 0; q < P.nv; ++q) {
+    const int qm = q == 0 ? P.nv - 1 : q - 1;
+    if (((out >> q) & 1u) && !((out >> qm) & 1u)) {
+      a = q;
+      ++starts;
+    }
+  }
+  if (starts != 1) return RICH_RETESS_CLIP;
+  const int m = __popc(out);
+  const int r = m - 1;  // edges a .. a+r-1 lie wholly beyond the bisector
+  if (a + r <= P.nv) {
+    if (r == 0) {  // one vertex cut: the new edge is inserted at a
+      if (P.nv + 1 > kMaxPoly) return RICH_RETESS_FAN;
+      for (int t = P.nv; t > a; --t) {
+        P.dx[t] = P.dx[t - 1]; P.dy[t] = P.dy[t - 1]; P.id[t] = P.id[t - 1];
+      }
+      P.dx[a] = dx; P.dy[a] = dy; P.id[a] = cid;
+      ++P.nv;
+    } else {
+      P.dx[a] = dx; P.dy[a] = dy; P.id[a] = cid;
+      for (int t = a + r; t < P.nv; ++t) {
+        P.dx[t - r + 1] = P.dx[t]; P.dy[t - r + 1] = P.dy[t]; P.id[t - r + 1] = P.id[t];
+      }
+      P.nv = P.nv - r + 1;
+    }
+  } else {  // the removed edges wrap past the end: keep w .. a-1, then the new one
+    const int w = a + r - P.nv;
+    for (int t = w; t < a; ++t) {
+      P.dx[t - w] = P.dx[t]; P.dy[t - w] = P.dy[t]; P.id[t - w] = P.id[t];
+    }
+    P.dx[a - w] = dx; P.dy[a - w] = dy; P.id[a - w] = cid;
+    P.nv = a - w + 1;
+  }
+  return 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_rt_clip(Args a) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= a.n) return;
+  const double xi = a.x[i], yi = a.y[i];
+  int bad = 0;
+  Poly P;
+  const bool periodic = a.bc == (int)RICH_BOUNDARY_PERIODIC;
+  if (periodic) {
+    if (!(xi >= a.x0 && xi < a.x1 && yi >= a.y0 && yi < a.y1)) bad |= RICH_RETESS_POINT;
+    // the point's own images below, right, above and left
+    P.dx[0] = 0.0;   P.dy[0] = -a.Ly; P.id[0] = pack(i, shift_code(0, -1));
+    P.dx[1] = a.Lx;  P.dy[1] = 0.0;   P.id[1] = pack(i, shift_code(1, 0));
+    P.dx[2] = 0.0;   P.dy[2] = a.Ly;  P.id[2] = pack(i, shift_code(0, 1));
+    P.dx[3] = -a.Lx; P.dy[3] = 0.0;   P.id[3] = pack(i, shift_code(-1, 0));
+  } else {
+    if (!(xi > a.x0 && xi < a.x1 && yi > a.y0 && yi < a.y1)) bad |= RICH_RETESS_POINT;
+    // mirror images across the walls y0, x1, y1, x0
+    P.dx[0] = 0.0;                 P.dy[0] = 2.0 * (a.y0 - yi); P.id[0] = pack(i, kWallY0);
+    P.dx[1] = 2.0 * (a.x1 - xi);   P.dy[1] = 0.0;               P.id[1] = pack(i, kWallX1);
+    P.dx[2] = 0.0;                 P.dy[2] = 2.0 * (a.y1 - yi); P.id[2] = pack(i, kWallY1);
+    P.dx[3] = 2.0 * (a.x0 - xi);   P.dy[3] = 0.0;               P.id[3] = pack(i, kWallX0);
+  }
+  P.nv = 4;
+
+  auto candidate = [&](int c) {
+    if (c < 0 || c >= a.n) return;
+    double dx = a.x[c] - xi, dy = a.y[c] - yi;
+    int code = 0;
+    if (periodic) {
+      int sx = 0, sy = 0;
+      if (dx > 0.5 * a.Lx) { dx -= a.Lx; sx = -1; } else if (dx < -0.5 * a.Lx) { dx += a.Lx; sx = 1; }
+      if (dy > 0.5 * a.Ly) { dy -= a.Ly; sy = -1; } else if (dy < -0.5 * a.Ly) { dy += a.Ly; sy = 1; }
+      if (sx != 0 || sy != 0) code = shift_code(sx, sy);
+    }
+    bad |= clip(P, dx, dy, pack(c, code));
+  };
+
+  int k0 = 0, k1 = 0;
+  if (!bad) {
+    k0 = a.p_off[i];
+    k1 = a.p_off[i + 1];
+    if (k0 < 0 || k1 < k0 || k1 > a.p_n_csr || k1 - k0 > kRingMax) {
+      bad |= RICH_RETESS_CLIP;
+      k1 = k0;
+    }
+  }
+  // first ring, then the second: the polygon is near its final shape before
+  // the many second-ring candidates, most of which then cut nothing
+  for (int k = k0; k < k1 && !bad; ++k) {
+    const int j = prev_neighbour(a, k);
+    if (j != i) candidate(j);
+  }
+  for (int k = k0; k < k1 && !bad; ++k) {
+    const int j = prev_neighbour(a, k);
+    if (j < 0 || j == i || j >= a.n) continue;
+    int l0 = a.p_off[j], l1 = a.p_off[j + 1];
+    if (l0 < 0 || l1 < l0 || l1 > a.p_n_csr || l1 - l0 > kRingMax) {
+      bad |= RICH_RETESS_CLIP;
+      break;
+    }
+    for (int l = l0; l < l1 && !bad; ++l) {
+      const int c = prev_neighbour(a, l);
+      if (c != i) candidate(c);
+    }
+  }
+  if (!bad && P.nv > kMaxFan) bad |= RICH_RETESS_FAN;
+
+  rich_cell cr;
+  cr.px = xi; cr.py = yi; cr.pad = 0.0;
+  if (bad) {
+    atomicOr(&a.hdr->flags, bad);
+    a.deg[i] = 0;
+    cr.area = 0.0; cr.sx = xi; cr.sy = yi;
+    a.cells[i] = cr;
+    return;
+  }
+  // vertices, area and centroid (shoelace over the triangles fanned from the
+  // point), edges with their midpoints
+  double vx0, vy0;
+  bisector_meet(P.dx[P.nv - 1], P.dy[P.nv - 1], P.dx[0], P.dy[0], vx0, vy0);
+  double A2 = 0.0, cx = 0.0, cy = 0.0;
+  double ux = vx0, uy = vy0;
+  const size_t s0 = (size_t)i * kMaxFan;
+  for (int q = 0; q < P.nv; ++q) {
+    double wx, wy;  // vertex q+1: end of edge q
+    if (q + 1 < P.nv)
+      bisector_meet(P.dx[q], P.dy[q], P.dx[q + 1], P.dy[q + 1], wx, wy);
+    else {
+      wx = vx0;
+      wy = vy0;
+    }
+    const double c = ux * wy - uy * wx;
+    A2 += c;
+    cx += (ux + wx) * c;
+    cy += (uy + wy) * c;
+    const double ex = wx - ux, ey = wy - uy;
+    a.s_nb[s0 + q] = P.id[q];
+    a.s_len[s0 + q] = sqrt(ex * ex + ey * ey);
+    a.s_fx[s0 + q] = xi + 0.5 * (ux + wx);
+    a.s_fy[s0 + q] = yi + 0.5 * (uy + wy);
+    ux = wx;
+    uy = wy;
+  }
+  a.deg[i] = P.nv;
+  cr.area = 0.5 * A2;
+  cr.sx = xi + cx / (3.0 * A2);
+  cr.sy = yi + cy / (3.0 * A2);
+  a.cells[i] = cr;
+}
+
+// ---------------------------------------------------------------------------
+// keep / own, certification, counts
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_rt_classify(Args a) {
+  __shared__ double s_area[kThreads / 64];
+  __shared__ long long s_drop[kThreads / 64];
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  double area = 0.0;
+  long long drop = 0;
+  if (i < a.n) {
+    const int d = a.deg[i];
+    area = a.cells[i].area;
+    const double Ri = sqrt(area / kPi);
+    const size_t s0 = (size_t)i * kMaxFan;
+    int n_keep = 0, n_own = 0, bad = 0;
+    for (int q = 0; q < d; ++q) {
+      const int32_t id = a.s_nb[s0 + q];
+      const int j = (int)((uint32_t)id & kMask);
+      const int code = (int)((uint32_t)id >> kShift);
+      const double Rj = sqrt(a.cells[j].area / kPi);
+      const double L = a.s_len[s0 + q];
+      const bool keep = L >= 1e-12 * 0.5 * (Ri + Rj);
+      bool own;
+      if (code >= kWallX0) own = true;
+      else if (j != i) own = i < j;
+      else own = code >= 5;
+      a.s_flag[s0 + q] = (uint8_t)((keep ? 1 : 0) | (keep && own ? 2 : 0));
+      if (!keep) {
+        ++drop;
+        continue;
+      }
+      ++n_keep;
+      if (own) ++n_own;
+      if (code >= kWallX0) continue;
+      // the same edge from the neighbour's side
+      const int32_t want = pack(i, back_code(code));
+      const int dj = a.deg[j];
+      const size_t t0 = (size_t)j * kMaxFan;
+      int found = -1;
+      for (int t = 0; t < dj; ++t)
+        if (a.s_nb[t0 + t] == want) { found = t; break; }
+      if (found < 0) { bad |= RICH_RETESS_ASYM; continue; }
+      const double Lj = a.s_len[t0 + found];
+      double fxj = a.s_fx[t0 + found], fyj = a.s_fy[t0 + found];
+      if (code != 0) {  // the neighbour sees the edge one image away
+        int sx, sy;
+        code_shift(code, sx, sy);
+        fxj += sx * a.Lx;
+        fyj += sy * a.Ly;
+      }
+      const double tol = 1e-9 * (Ri + Rj);
+      if (!(Lj >= 1e-12 * 0.5 * (Ri + Rj)) || fabs(L - Lj) > tol ||
+          fabs(a.s_fx[s0 + q] - fxj) > tol || fabs(a.s_fy[s0 + q] - fyj) > tol)
+        bad |= RICH_RETESS_ASYM;
+    }
+    if (d == 0 || !(area > 0.0)) bad |= RICH_RETESS_CLIP;
+    if (bad) atomicOr(&a.hdr->flags, bad);
+    a.off[i + 1] = n_keep;  // counts; the scan makes them offsets
+    a.eoff[i + 1] = n_own;
+  }
+  // block sums of the areas and of the dropped edges
+  for (int o = 32; o > 0; o >>= 1) {
+    area += __shfl_xor(area, o);
+    drop += __shfl_xor(drop, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_area[threadIdx.x >> 6] = area;
+    s_drop[threadIdx.x >> 6] = drop;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    long long u = 0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+      t += s_area[w];
+      u += s_drop[w];
+    }
+    atomicAdd(&a.hdr->area_sum, t);
+    atomicAdd((unsigned long long*)&a.hdr->n_dropped, (unsigned long long)u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// prefix sums of the kept / owned counts (in place in off[1..n], eoff[1..n])
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void block_scan2(int& v0, int& v1, int* s0, int* s1, int& tot0,
+                                            int& tot1) {
+  // inclusive scan over the block of two values per thread
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u0 = __shfl_up(v0, o), u1 = __shfl_up(v1, o);
+    if (lane >= o) { v0 += u0; v1 += u1; }
+  }
+  if (lane == 63) { s0[wv] = v0; s1[wv] = v1; }
+  __syncthreads();
+  if (wv == 0) {
+    constexpr int NW = kScanThreads / 64;
+    int w0 = lane < NW ? s0[lane] : 0, w1 = lane < NW ? s1[lane] : 0;
+    for (int o = 1; o < NW; o <<= 1) {
+      const int u0 = __shfl_up(w0, o), u1 = __shfl_up(w1, o);
+      if (lane >= o) { w0 += u0; w1 += u1; }
+    }
+    if (lane < NW) { s0[lane] = w0; s1[lane] = w1; }
+  }
+  __syncthreads();
+  if (wv > 0) { v0 += s0[wv - 1]; v1 += s1[wv - 1]; }
+  tot0 = s0[kScanThreads / 64 - 1];
+  tot1 = s1[kScanThreads / 64 - 1];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_rt_scan_local(Args a) {
+  __shared__ int s0[kScanThreads / 64], s1[kScanThreads / 64];
+  const int i = blockIdx.x * kScanThreads + threadIdx.x;
+  int v0 = i < a.n ? a.off[i + 1] : 0;
+  int v1 = i < a.n ? a.eoff[i + 1] : 0;
+  int t0, t1;
+  block_scan2(v0, v1, s0, s1, t0, t1);
+  if (i < a.n) {
+    a.off[i + 1] = v0;
+    a.eoff[i + 1] = v1;
+  }
+  if (threadIdx.x == 0) {
+    a.bsum[blockIdx.x] = t0;
+    a.bsum[a.n_scan_blocks + blockIdx.x] = t1;
+  }
+}
+
+// one block: exclusive scan of the block totals, totals and the checks that
+// need every cell (areas, capacities)
+__global__ __launch_bounds__(kScanThreads) void k_rt_scan_blocks(Args a) {
+  __shared__ long long s0[kScanThreads], s1[kScanThreads];
+  const int nb = a.n_scan_blocks;
+  const int per = (nb + kScanThreads - 1) / kScanThreads;
+  const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
+  long long c0 = 0, c1 = 0;
+  for (int b = b0; b < b1; ++b) {
+    c0 += a.bsum[b];
+    c1 += a.bsum[nb + b];
+  }
+  s0[threadIdx.x] = c0;
+  s1[threadIdx.x] = c1;
+  __syncthreads();
+  // serial over the 1024 chunk sums by one thread: 1024 additions
+  if (threadIdx.x == 0) {
+    long long r0 = 0, r1 = 0;
+    for (int t = 0; t < kScanThreads; ++t) {
+      const long long u0 = s0[t], u1 = s1[t];
+      s0[t] = r0;
+      s1[t] = r1;
+      r0 += u0;
+      r1 += u1;
+    }
+    Hdr* h = a.hdr;
+    h->n_csr = r0;
+    h->n_edges = r1;
+    int f = 0;
+    if (r0 > a.cap_csr || r1 > a.cap_edges) f |= RICH_RETESS_CAP;
+    const double box = a.Lx * a.Ly;
+    if (!(fabs(h->area_sum - box) <= 1e-10 * box)) f |= RICH_RETESS_AREA;
+    if (f) h->flags |= f;
+  }
+  __syncthreads();
+  long long r0 = s0[threadIdx.x], r1 = s1[threadIdx.x];
+  for (int b = b0; b < b1; ++b) {
+    const long long u0 = a.bsum[b], u1 = a.bsum[nb + b];
+    a.bsum[b] = r0;
+    a.bsum[nb + b] = r1;
+    r0 += u0;
+    r1 += u1;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_rt_scan_add(Args a) {
+  const int i = blockIdx.x * kScanThreads + threadIdx.x;
+  if (i == 0) {
+    a.off[0] = 0;
+    a.eoff[0] = 0;
+  }
+  if (i < a.n) {
+    a.off[i + 1] += (int32_t)a.bsum[blockIdx.x];
+    a.eoff[i + 1] += (int32_t)a.bsum[a.n_scan_blocks + blockIdx.x];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// edge records and CSR entries
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_rt_emit(Args a) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= a.n) return;
+  if (a.hdr->flags != 0) {  // failed: leave a mesh without edges
+    a.off[i + 1] = 0;
+    a.eoff[i + 1] = 0;
+    if (i == 0) {
+      a.off[0] = 0;
+      a.eoff[0] = 0;
+    }
+    return;
+  }
+  const int d = a.deg[i];
+  const size_t s0 = (size_t)i * kMaxFan;
+  int k = a.off[i], e = a.eoff[i];
+  int bad = 0;
+  for (int q = 0; q < d; ++q) {
+    const uint8_t f = a.s_flag[s0 + q];
+    if (!(f & 1)) continue;
+    const int32_t id = a.s_nb[s0 + q];
+    if (f & 2) {
+      rich_edge r;
+      r.fx = a.s_fx[s0 + q];
+      r.fy = a.s_fy[s0 + q];
+      r.len = a.s_len[s0 + q];
+      r.i = i;
+      r.j = id;
+      a.edges[e] = r;
+      a.idx[k] = 2 * e;
+      ++e;
+    } else {
+      // owned by the neighbour: its edge index is its first edge plus the
+      // owned slots before the matching one
+      const int j = (int)((uint32_t)id & kMask);
+      const int32_t want = pack(i, back_code((int)((uint32_t)id >> kShift)));
+      const size_t t0 = (size_t)j * kMaxFan;
+      const int dj = a.deg[j];
+      int rank = 0, found = -1;
+      for (int t = 0; t < dj; ++t) {
+        const int32_t u = a.s_nb[t0 + t];
+        if (u == want) { found = t; break; }
+        if (a.s_flag[t0 + t] & 2) ++rank;
+      }
+      if (found < 0 || !(a.s_flag[t0 + found] & 2)) {
+        bad = RICH_RETESS_ASYM;
+        a.idx[k] = 0;
+      } else {
+        a.idx[k] = 2 * (a.eoff[j] + rank) + 1;
+      }
+    }
+    ++k;
+  }
+  if (bad) atomicOr(&a.hdr->flags, bad);
+}
+
+}  // namespace retess
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+namespace {
+
+size_t rt_align(size_t v) { return (v + 255) / 256 * 256; }
+
+struct RtLayout {
+  size_t deg, s_nb, s_len, s_fx, s_fy, s_flag, bsum, total;
+  int nb;
+};
+
+RtLayout rt_layout(int64_t n) {
+  RtLayout L;
+  const size_t slots = (size_t)n * retess::kMaxFan;
+  L.nb = (int)((n + retess::kScanThreads - 1) / retess::kScanThreads);
+  size_t o = 256;  // result header
+  L.deg = o;    o += rt_align(4 * (size_t)n);
+  L.s_nb = o;   o += rt_align(4 * slots);
+  L.s_len = o;  o += rt_align(8 * slots);
+  L.s_fx = o;   o += rt_align(8 * slots);
+  L.s_fy = o;   o += rt_align(8 * slots);
+  L.s_flag = o; o += rt_align(slots);
+  L.bsum = o;   o += rt_align(16 * (size_t)L.nb);
+  L.total = o;
+  return L;
+}
+
+void rt_capacity(int64_t n, int64_t* ce, int64_t* cc) {
+  const int64_t r = (int64_t)std::ceil(std::sqrt((double)n));
+  *ce = 3 * n + 8 * r + 64;
+  *cc = 2 * *ce;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rich_retess_capacity(int64_t n_cells, int64_t* cap_edges, int64_t* cap_csr) {
+  if (n_cells <= 0 || n_cells > (int64_t)retess::kMask || !cap_edges || !cap_csr)
+    return RICH_E_INVAL;
+  rt_capacity(n_cells, cap_edges, cap_csr);
+  if (*cap_csr >= (int64_t)INT32_MAX) return RICH_E_INVAL;
+  return RICH_OK;
+}
+
+int rich_retess_workspace_size(int64_t n_cells, size_t* bytes) {
+  if (n_cells <= 0 || n_cells > (int64_t)retess::kMask || !bytes) return RICH_E_INVAL;
+  *bytes = rt_layout(n_cells).total;
+  return RICH_OK;
+}
+
+int rich_retess(const rich_mesh* prev, const double* x, const double* y,
+                const rich_mesh_bufs* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!prev || !x || !y || !out || !ws) return RICH_E_INVAL;
+  const int64_t n = prev->n_cells;
+  if (n <= 0 || n > (int64_t)retess::kMask || out->n_cells != n) return RICH_E_INVAL;
+  if (!prev->off || !prev->eoff || (prev->n_csr > 0 && !prev->idx) ||
+      (prev->n_edges > 0 && !prev->edges) || prev->n_csr < 0 || prev->n_edges < 0 ||
+      prev->n_csr >= (int64_t)INT32_MAX || prev->n_edges >= (int64_t)INT32_MAX)
+    return RICH_E_INVAL;
+  if (!out->cells || !out->edges || !out->off || !out->idx || !out->eoff ||
+      (reinterpret_cast<uintptr_t>(out->cells) & 15) ||
+      (reinterpret_cast<uintptr_t>(out->edges) & 15) || out->cap_edges <= 0 ||
+      out->cap_csr <= 0 || out->cap_csr >= (int64_t)INT32_MAX)
+    return RICH_E_INVAL;
+  if (!(prev->box[2] > prev->box[0]) || !(prev->box[3] > prev->box[1]) ||
+      !std::isfinite(prev->box[0]) || !std::isfinite(prev->box[1]) ||
+      !std::isfinite(prev->box[2]) || !std::isfinite(prev->box[3]))
+    return RICH_E_INVAL;
+  if (prev->bc != RICH_BOUNDARY_WALLS && prev->bc != RICH_BOUNDARY_PERIODIC) return RICH_E_INVAL;
+  if (prev->bc == RICH_BOUNDARY_PERIODIC && n < 16) return RICH_E_INVAL;
+  const RtLayout L = rt_layout(n);
+  if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return RICH_E_NOMEM;
+
+  char* w = static_cast<char*>(ws);
+  retess::Args a;
+  std::memset(&a, 0, sizeof(a));
+  a.p_off = prev->off;
+  a.p_idx = prev->idx;
+  a.p_edges = prev->edges;
+  a.p_n_csr = prev->n_csr;
+  a.p_n_edges = prev->n_edges;
+  a.x = x;
+  a.y = y;
+  a.cells = out->cells;
+  a.edges = out->edges;
+  a.off = out->off;
+  a.idx = out->idx;
+  a.eoff = out->eoff;
+  a.cap_edges = out->cap_edges;
+  a.cap_csr = out->cap_csr;
+  a.hdr = reinterpret_cast<retess::Hdr*>(w);
+  a.deg = reinterpret_cast<int32_t*>(w + L.deg);
+  a.s_nb = reinterpret_cast<int32_t*>(w + L.s_nb);
+  a.s_len = reinterpret_cast<double*>(w + L.s_len);
+  a.s_fx = reinterpret_cast<double*>(w + L.s_fx);
+  a.s_fy = reinterpret_cast<double*>(w + L.s_fy);
+  a.s_flag = reinterpret_cast<uint8_t*>(w + L.s_flag);
+  a.bsum = reinterpret_cast<int64_t*>(w + L.bsum);
+  a.x0 = prev->box[0];
+  a.y0 = prev->box[1];
+  a.x1 = prev->box[2];
+  a.y1 = prev->box[3];
+  a.Lx = a.x1 - a.x0;
+  a.Ly = a.y1 - a.y0;
+  a.n = (int32_t)n;
+  a.bc = (int32_t)prev->bc;
+  a.n_scan_blocks = L.nb;
+
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int gc = (int)((n + retess::kThreads - 1) / retess::kThreads);
+  hipLaunchKernelGGL(retess::k_rt_begin, dim3(1), dim3(64), 0, st, a.hdr);
+  hipLaunchKernelGGL(retess::k_rt_clip, dim3(gc), dim3(retess::kThreads), 0, st, a);
+  hipLaunchKernelGGL(retess::k_rt_classify, dim3(gc), dim3(retess::kThreads), 0, st, a);
+  hipLaunchKernelGGL(retess::k_rt_scan_local, dim3(L.nb), dim3(retess::kScanThreads), 0, st, a);
+  hipLaunchKernelGGL(retess::k_rt_scan_blocks, dim3(1), dim3(retess::kScanThreads), 0, st, a);
+  hipLaunchKernelGGL(retess::k_rt_scan_add, dim3(L.nb), dim3(retess::kScanThreads), 0, st, a);
+  hipLaunchKernelGGL(retess::k_rt_emit, dim3(gc), dim3(retess::kThreads), 0, st, a);
+  hipLaunchKernelGGL(retess::k_rt_end, dim3(1), dim3(64), 0, st, a.hdr);
+  return hipGetLastError() == hipSuccess ? RICH_OK : RICH_E_DEVICE;
+}
+
+int rich_retess_view(const rich_mesh_bufs* out, const double box[4], uint32_t bc,
+                     rich_mesh* m) {
+  if (!out || !box || !m || out->n_cells <= 0) return RICH_E_INVAL;
+  m->n_cells = out->n_cells;
+  m->n_edges = out->cap_edges;
+  m->n_csr = out->cap_csr;
+  m->cells = out->cells;
+  m->edges = out->edges;
+  m->off = out->off;
+  m->idx = out->idx;
+  m->eoff = out->eoff;
+  for (int k = 0; k < 4; ++k) m->box[k] = box[k];
+  m->bc = bc;
+  return RICH_OK;
+}
+
+int rich_retess_result(void* ws, void* stream, rich_retess_info* info) {
+  if (!ws || !info) return RICH_E_INVAL;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return RICH_E_DEVICE;
+  retess::Hdr h;
+  if (hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return RICH_E_DEVICE;
+  info->flags = h.flags;
+  info->sticky = h.sticky;
+  info->n_edges = h.n_edges;
+  info->n_csr = h.n_csr;
+  info->n_dropped = h.n_dropped;
+  info->area_sum = h.area_sum;
+  return h.flags ? RICH_E_MESH : RICH_OK;
+}
+
+}  // extern "C"

@@ -36,6 +36,19 @@ class RichMesh(C.Structure):
 CELL_BYTES, EDGE_BYTES = 48, 32   # sizeof(rich_cell), sizeof(rich_edge)
 
 
+class RichMeshBufs(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("cap_edges", C.c_int64), ("cap_csr", C.c_int64),
+                ("cells", _vp), ("edges", _vp), ("off", _vp), ("idx", _vp), ("eoff", _vp)]
+
+
+class RichRetessInfo(C.Structure):
+    _fields_ = [("flags", C.c_int32), ("sticky", C.c_int32), ("n_edges", C.c_int64),
+                ("n_csr", C.c_int64), ("n_dropped", C.c_int64), ("area_sum", C.c_double)]
+
+
+RETESS_POINT, RETESS_FAN, RETESS_CLIP, RETESS_ASYM, RETESS_AREA, RETESS_CAP = 1, 2, 4, 8, 16, 32
+
+
 class RichBatchPlan(C.Structure):
     _fields_ = [("n_runs", C.c_int32), ("n_cell_tiles", C.c_int32),
                 ("n_flux_tiles", C.c_int32 * 2), ("n_group", C.c_int32 * 2),
@@ -120,6 +133,12 @@ def lib():
         L.rich_stage_dt_of.argtypes = [mp, sp, sp, sp, C.c_double, _vp, pp, _vp, C.c_size_t,
                                        _vp]
         L.rich_stage_dt.argtypes = [_vp, _vp, _dp]
+        L.rich_retess_capacity.argtypes = [C.c_int64, C.POINTER(C.c_int64),
+                                           C.POINTER(C.c_int64)]
+        L.rich_retess_workspace_size.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
+        L.rich_retess.argtypes = [mp, _vp, _vp, C.POINTER(RichMeshBufs), _vp, C.c_size_t, _vp]
+        L.rich_retess_view.argtypes = [C.POINTER(RichMeshBufs), _dp, C.c_uint32, mp]
+        L.rich_retess_result.argtypes = [_vp, _vp, C.POINTER(RichRetessInfo)]
         L.rich_mesh_pack.argtypes = [C.POINTER(HostMeshView), _vp, _vp]
         L.rich_mesh_pack.restype = C.c_int
         L.rich_strerror.argtypes = [C.c_int]
@@ -128,6 +147,8 @@ def lib():
         L.rich_profile_read.argtypes = [C.c_char_p, _dp, C.POINTER(C.c_int64)]
         for f in ("rich_workspace_size", "rich_stage", "rich_stage_flags", "rich_cfl_dt",
                   "rich_stage_courant", "rich_stage_dt_of", "rich_stage_dt",
+                  "rich_retess_capacity", "rich_retess_workspace_size", "rich_retess",
+                  "rich_retess_view", "rich_retess_result",
                   "rich_profile_enable", "rich_profile_read"):
             getattr(L, f).restype = C.c_int
         if hasattr(L, "rich_stage_batch"):
@@ -327,6 +348,98 @@ def rich_stage_dt(ws, stream=None):
     _check(lib().rich_stage_dt(C.c_void_p(ws.data_ptr()), _stream_ptr(stream), C.byref(dt)),
            "rich_stage_dt")
     return dt.value
+
+
+# ---------------------------------------------------------------------------
+# device re-tessellation
+# ---------------------------------------------------------------------------
+def rich_retess_capacity(n_cells):
+    ce, cc = C.c_int64(0), C.c_int64(0)
+    _check(lib().rich_retess_capacity(int(n_cells), C.byref(ce), C.byref(cc)),
+           "rich_retess_capacity")
+    return int(ce.value), int(cc.value)
+
+
+def retess_workspace(n_cells, device="cuda"):
+    """Workspace of rich_retess, zeroed (its result header starts cleared)."""
+    import torch
+    b = C.c_size_t(0)
+    _check(lib().rich_retess_workspace_size(int(n_cells), C.byref(b)),
+           "rich_retess_workspace_size")
+    return torch.zeros(int(b.value), dtype=torch.uint8, device=device)
+
+
+class DeviceMeshBufs:
+    """Output buffers of rich_retess for n_cells cells, at full capacity."""
+
+    def __init__(self, n_cells, box, bc, device="cuda"):
+        import torch
+        ce, cc = rich_retess_capacity(n_cells)
+        self.n_cells, self.cap_edges, self.cap_csr = int(n_cells), ce, cc
+        self.box, self.bc = tuple(float(v) for v in box), int(bc)
+        u8, i32 = torch.uint8, torch.int32
+        self.t = {"cells": torch.empty(CELL_BYTES * n_cells, dtype=u8, device=device),
+                  "edges": torch.empty(EDGE_BYTES * ce, dtype=u8, device=device),
+                  "off": torch.zeros(n_cells + 1, dtype=i32, device=device),
+                  "idx": torch.zeros(cc, dtype=i32, device=device),
+                  "eoff": torch.zeros(n_cells + 1, dtype=i32, device=device)}
+        p = {k: C.c_void_p(v.data_ptr()) for k, v in self.t.items()}
+        self._c = RichMeshBufs(self.n_cells, ce, cc, p["cells"], p["edges"], p["off"],
+                               p["idx"], p["eoff"])
+
+    def c(self):
+        return self._c
+
+    def mesh(self):
+        """The stage's view (edge and CSR counts are the capacities)."""
+        return DeviceMesh(self.t, self.n_cells, self.cap_edges, self.cap_csr, self.box,
+                          self.bc)
+
+
+def rich_retess(prev: DeviceMesh, X, bufs: DeviceMeshBufs, ws, stream=None):
+    """Enqueue the re-tessellation of points X (2, n) (device) with candidates
+    from `prev` into `bufs`; read the outcome with rich_retess_result."""
+    X = X if X.is_contiguous() else X.contiguous()
+    n = prev.n_cells
+    xp = C.c_void_p(X.data_ptr())
+    yp = C.c_void_p(X.data_ptr() + 8 * n)
+    st = lib().rich_retess(C.byref(prev.c()), xp, yp, C.byref(bufs.c()),
+                           C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
+    _check(st, "rich_retess")
+
+
+def rich_retess_result(ws, stream=None):
+    """(status, info): status RICH_E_MESH when the last call failed."""
+    info = RichRetessInfo()
+    st = lib().rich_retess_result(C.c_void_p(ws.data_ptr()), _stream_ptr(stream),
+                                  C.byref(info))
+    if st not in (RICH_OK, RICH_E_MESH):
+        _check(st, "rich_retess_result")
+    return st, {"flags": info.flags, "sticky": info.sticky, "n_edges": info.n_edges,
+                "n_csr": info.n_csr, "n_dropped": info.n_dropped, "area_sum": info.area_sum}
+
+
+def mesh_to_host(dm: DeviceMesh, n_edges=None, n_csr=None):
+    """Device mesh records back as host-stage arrays (for checks)."""
+    cells = dm.t["cells"].cpu().numpy().view(np.float64).reshape(-1, 6)
+    ne = dm.n_edges if n_edges is None else n_edges
+    nc = dm.n_csr if n_csr is None else n_csr
+    er = dm.t["edges"][:EDGE_BYTES * ne].cpu().numpy()
+    ed = er.view(np.dtype([("fx", "<f8"), ("fy", "<f8"), ("len", "<f8"), ("i", "<i4"),
+                           ("j", "<i4")]))
+
+    class H:
+        pass
+    h = H()
+    h.n_cells, h.n_edges, h.n_csr = dm.n_cells, ne, nc
+    h.px, h.py, h.area, h.sx, h.sy = (np.ascontiguousarray(cells[:, k]) for k in range(5))
+    h.e_fx, h.e_fy, h.e_len = (np.ascontiguousarray(ed[k]) for k in ("fx", "fy", "len"))
+    h.e_i, h.e_j = np.ascontiguousarray(ed["i"]), np.ascontiguousarray(ed["j"])
+    h.off = dm.t["off"].cpu().numpy()
+    h.idx = dm.t["idx"][:nc].cpu().numpy()
+    h.eoff = dm.t["eoff"].cpu().numpy()
+    h.box, h.bc = dm.box, dm.bc
+    return h
 
 
 def rich_profile_enable(on=True):

@@ -1,0 +1,343 @@
+"""Device re-tessellation (rich_retess) through the C-ABI.
+
+The reference for the cells is the oracle's Voronoi tessellation by
+definition (or_voronoi, clipping against every point) on small meshes, and
+the exact-predicate Delaunay construction of the input stage at full size.
+Topology (each cell's kept neighbours with their image / wall codes) must be
+identical; areas, centroids, edge lengths and midpoints agree to 1e-12 of the
+cell size.  Stages and time-centred chains on device-built meshes follow the
+oracle on oracle-built meshes to the stage bar."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import parity_util as U
+from paper_1410_3219_amd import inputs as I
+from paper_1410_3219_amd import tess as T
+
+pytestmark = pytest.mark.gpu
+
+MASK = 0x0FFFFFFF
+
+
+def csr_keys(h):
+    """Per CSR entry: (cell, neighbour, code seen from the cell) as one int64,
+    sorted, and the edge length in the same order."""
+    n = h.n_cells
+    off = np.asarray(h.off, dtype=np.int64)
+    cell = np.repeat(np.arange(n, dtype=np.int64), np.diff(off))
+    ent = np.asarray(h.idx[: off[-1]], dtype=np.int64)
+    e, side = ent >> 1, ent & 1
+    u = np.asarray(h.e_j, dtype=np.int64)[e] & 0xFFFFFFFF
+    jc, code = u & MASK, u >> 28
+    nb = np.where(side == 0, jc, np.asarray(h.e_i, dtype=np.int64)[e])
+    cd = np.where(side == 0, code, np.where(code == 0, 0, 9 - code))
+    key = (cell << 36) | (nb << 4) | cd
+    o = np.argsort(key, kind="stable")
+    return key[o], np.asarray(h.e_len)[e][o]
+
+
+def edge_keys(h):
+    """Per edge (owner side): key, length, midpoint, sorted by key."""
+    ne = h.n_edges
+    ei = np.asarray(h.e_i[:ne], dtype=np.int64)
+    u = np.asarray(h.e_j[:ne], dtype=np.int64) & 0xFFFFFFFF
+    key = (ei << 36) | ((u & MASK) << 4) | (u >> 28)
+    o = np.argsort(key, kind="stable")
+    return key[o], np.asarray(h.e_len[:ne])[o], np.asarray(h.e_fx[:ne])[o], \
+        np.asarray(h.e_fy[:ne])[o]
+
+
+def check_structure(h):
+    """CSR and edge arrays are well formed: offsets monotone, edges sorted by
+    owner with eoff, every CSR entry names an edge of its cell."""
+    n = h.n_cells
+    off, eoff = np.asarray(h.off), np.asarray(h.eoff)
+    assert off[0] == 0 and eoff[0] == 0
+    assert (np.diff(off) >= 0).all() and (np.diff(eoff) >= 0).all()
+    assert off[-1] == h.n_csr and eoff[-1] == h.n_edges
+    ei = np.asarray(h.e_i[: h.n_edges])
+    assert (ei == np.repeat(np.arange(n), np.diff(eoff))).all()
+    cell = np.repeat(np.arange(n), np.diff(off))
+    ent = np.asarray(h.idx[: h.n_csr])
+    e, side = ent >> 1, ent & 1
+    assert (e >= 0).all() and (e < h.n_edges).all()
+    u = np.asarray(h.e_j, dtype=np.int64)[e] & 0xFFFFFFFF
+    other = np.where(side == 0, ei[e], u & MASK)
+    assert (other == cell).all()
+    assert (2 * h.n_edges - np.count_nonzero(
+        (np.asarray(h.e_j[: h.n_edges], dtype=np.int64) & 0xFFFFFFFF) >> 28 >= 9)
+        == h.n_csr)
+
+
+def compare_meshes(dev, ref, h_cell, tol=1e-12):
+    """Same topology, geometry within tol * cell size."""
+    assert dev.n_edges == ref.n_edges and dev.n_csr == ref.n_csr
+    kd, ld = csr_keys(dev)
+    kr, lr = csr_keys(ref)
+    assert np.array_equal(kd, kr)
+    assert np.abs(ld - lr).max() <= tol * h_cell
+    ed, edl, edx, edy = edge_keys(dev)
+    er, erl, erx, ery = edge_keys(ref)
+    assert np.array_equal(ed, er)
+    assert np.abs(edl - erl).max() <= tol * h_cell
+    assert np.abs(edx - erx).max() <= tol * h_cell and np.abs(edy - ery).max() <= tol * h_cell
+    assert np.abs(dev.area - ref.area).max() <= tol * h_cell * h_cell
+    assert np.abs(dev.sx - ref.sx).max() <= tol * h_cell
+    assert np.abs(dev.sy - ref.sy).max() <= tol * h_cell
+    assert np.array_equal(dev.px, ref.px) and np.array_equal(dev.py, ref.py)
+
+
+def _problem(name, k, seed=1):
+    if name == "sod":
+        return I.sod(k=k, seed=seed)
+    if name == "wave":
+        return I.advected_wave(k=k, seed=seed)
+    if name == "sedov":
+        return I.sedov(k=k, seed=seed, lloyd_iters=2)
+    if name == "kh":
+        return I.kelvin_helmholtz(k=k, seed=seed)
+    if name == "gresho":
+        return I.gresho(k=k, seed=seed)
+    raise ValueError(name)
+
+
+def _initial(name, k, seed=1):
+    P = _problem(name, k, seed)
+    m = T.rich_tess_build(P.px, P.py, P.box, P.bc)
+    Q = I.sedov_state(P, m.area) if name == "sedov" else P.state(m.area)
+    return P, m, Q, np.stack([m.px, m.py])
+
+
+def _half_step_points(R, dm, Q, X, p):
+    """Points after a real stage-1 move (device)."""
+    s = R.DeviceState.from_host(Q, X)
+    half = R.DeviceState.empty_like(s)
+    ws = R.workspace(dm.n_cells)
+    R.rich_stage_courant(dm, s, s, half, 0.5, p, ws)
+    assert R.rich_stage_flags(ws) == 0
+    return s, half
+
+
+@pytest.mark.parametrize("name,k", [("sod", 24), ("wave", 27), ("sedov", 26), ("kh", 22),
+                                    ("gresho", 20)])
+def test_retess_matches_oracle_voronoi(name, k):
+    from paper_1410_3219_amd import rich as R
+    P, m, Q, X = _initial(name, k)
+    dm = R.DeviceMesh.from_host(m)
+    p = R.Params(gamma=P.gamma, motion=1)
+    s, half = _half_step_points(R, dm, Q, X, p)
+    bufs = R.DeviceMeshBufs(m.n_cells, m.box, m.bc)
+    tws = R.retess_workspace(m.n_cells)
+    R.rich_retess(dm, half.X, bufs, tws)
+    st, info = R.rich_retess_result(tws)
+    assert st == 0 and info["flags"] == 0 and info["sticky"] == 0, info
+    dev = R.mesh_to_host(bufs.mesh(), info["n_edges"], info["n_csr"])
+    check_structure(dev)
+    Xh = half.X.cpu().numpy()
+    ref = O.voronoi_mesh(O.voronoi(Xh[0], Xh[1], m.box, m.bc))
+    h_cell = math.sqrt((m.box[2] - m.box[0]) * (m.box[3] - m.box[1]) / m.n_cells)
+    compare_meshes(dev, ref, h_cell)
+    assert abs(info["area_sum"] - (m.box[2] - m.box[0]) * (m.box[3] - m.box[1])) < 1e-12
+
+
+def test_retess_repeat_is_bitwise_deterministic():
+    from paper_1410_3219_amd import rich as R
+    P, m, Q, X = _initial("sedov", 30)
+    dm = R.DeviceMesh.from_host(m)
+    p = R.Params(gamma=P.gamma)
+    s, half = _half_step_points(R, dm, Q, X, p)
+    outs = []
+    for _ in range(2):
+        bufs = R.DeviceMeshBufs(m.n_cells, m.box, m.bc)
+        tws = R.retess_workspace(m.n_cells)
+        R.rich_retess(dm, half.X, bufs, tws)
+        assert R.rich_retess_result(tws)[0] == 0
+        outs.append({k: v.cpu() for k, v in bufs.t.items()})
+    for k in outs[0]:
+        if k in ("edges", "idx"):
+            continue
+        assert np.array_equal(outs[0][k].numpy(), outs[1][k].numpy()), k
+    st, info = R.rich_retess_result(tws)
+    ne, nc = info["n_edges"], info["n_csr"]
+    assert np.array_equal(outs[0]["edges"][: 32 * ne].numpy(), outs[1]["edges"][: 32 * ne].numpy())
+    assert np.array_equal(outs[0]["idx"][:nc].numpy(), outs[1]["idx"][:nc].numpy())
+
+
+@pytest.mark.parametrize("name", ["sod", "wave", "sedov"])
+def test_stage_on_device_mesh_matches_oracle(name):
+    """Stage 2 of a time-centred step on the device-built half-step mesh
+    against the oracle's stage on its own Voronoi mesh of the same points."""
+    from paper_1410_3219_amd import rich as R
+    P, m, Q, X = _initial(name, 26)
+    dm = R.DeviceMesh.from_host(m)
+    op = O.Params(gamma=P.gamma)
+    p = U.gpu_params(op)
+    ws = R.workspace(m.n_cells)
+    s = R.DeviceState.from_host(Q, X)
+    half = R.DeviceState.empty_like(s)
+    R.rich_stage_courant(dm, s, s, half, 0.5, p, ws)
+    dt = R.rich_stage_dt(ws)
+    bufs = R.DeviceMeshBufs(m.n_cells, m.box, m.bc)
+    tws = R.retess_workspace(m.n_cells)
+    R.rich_retess(dm, half.X, bufs, tws)
+    assert R.rich_retess_result(tws)[0] == 0
+    out = R.DeviceState.empty_like(s)
+    R.rich_stage_dt_of(bufs.mesh(), half, s, out, 1.0, ws, p, ws)
+    assert R.rich_stage_flags(ws) == 0
+    Qh, Xh = half.numpy()
+    mo = O.voronoi_mesh(O.voronoi(Xh[0], Xh[1], m.box, m.bc))
+    ref = O.stage(mo, Qh, Q, X, dt, op)
+    assert ref.status == 0
+    Qg, Xg = out.numpy()
+    eq, ex = U.errors(mo, Qg, Xg, ref.Q, ref.X, Q, op)
+    print(f"\n{name} stage 2 on device mesh: err {eq} x {ex}")
+    assert (eq < U.TOL).all() and ex < U.TOL, (eq, ex)
+
+
+@pytest.mark.parametrize("name", ["sod", "wave", "kh"])
+def test_device_chain_follows_oracle_chain(name):
+    """Four time-centred steps with every mesh after the first built on the
+    device (Courant step on the device too) against the oracle's chain whose
+    meshes are its own Voronoi tessellations."""
+    from paper_1410_3219_amd import rich as R
+    P, m, Q, X = _initial(name, 22)
+    op = O.Params(gamma=P.gamma)
+    p = U.gpu_params(op)
+    n = m.n_cells
+
+    def tess(px, py, box, bc):
+        return O.voronoi_mesh(O.voronoi(px, py, box, bc))
+
+    Qo, Xo, mo = Q, X, tess(m.px, m.py, m.box, m.bc)
+    dts = []
+    mesh = R.DeviceMesh.from_host(m)
+    ws = R.workspace(n)
+    s = R.DeviceState.from_host(Q, X)
+    half = R.DeviceState.empty_like(s)
+    nxt = R.DeviceState.empty_like(s)
+    bufs = [R.DeviceMeshBufs(n, m.box, m.bc) for _ in range(3)]
+    tws = R.retess_workspace(n)
+    b = 0
+    for step in range(4):
+        R.rich_stage_courant(mesh, s, s, half, 0.5, p, ws)
+        mh = bufs[b % 3]
+        b += 1
+        R.rich_retess(mesh, half.X, mh, tws)
+        R.rich_stage_dt_of(mh.mesh(), half, s, nxt, 1.0, ws, p, ws)
+        mn = bufs[b % 3]
+        b += 1
+        R.rich_retess(mh.mesh(), nxt.X, mn, tws)
+        dts.append(R.rich_stage_dt(ws))
+        mesh = mn.mesh()
+        s, nxt = nxt, s
+    st, info = R.rich_retess_result(tws)
+    assert st == 0 and info["sticky"] == 0, info
+    for dt in dts:
+        Qo, Xo, mo, _, sto = O.step(mo, Qo, Xo, dt, op, tess)
+        assert sto == 0
+    Qg, Xg = s.numpy()
+    eq, ex = U.errors(mo, Qg, Xg, Qo, Xo, Qo, op)
+    print(f"\n{name} 4-step device chain err {eq} x {ex}")
+    assert (eq < 1e-11).all() and ex < 1e-12
+
+
+def test_retess_full_size_matches_host_stage():
+    """The benchmark mesh (2048^2 = 4 194 304 cells, periodic) after a real
+    half step: every cell, edge and CSR entry against the input stage's exact
+    construction on the same points."""
+    from paper_1410_3219_amd import rich as R
+    P = I.advected_wave(k=2048, seed=1)
+    m = T.rich_tess_build(P.px, P.py, P.box, P.bc)
+    Q = P.state(m.area)
+    X = np.stack([m.px, m.py])
+    dm = R.DeviceMesh.from_host(m)
+    p = R.Params(gamma=P.gamma)
+    s, half = _half_step_points(R, dm, Q, X, p)
+    bufs = R.DeviceMeshBufs(m.n_cells, m.box, m.bc)
+    tws = R.retess_workspace(m.n_cells)
+    R.rich_retess(dm, half.X, bufs, tws)
+    st, info = R.rich_retess_result(tws)
+    assert st == 0, info
+    dev = R.mesh_to_host(bufs.mesh(), info["n_edges"], info["n_csr"])
+    del bufs
+    Xh = half.X.cpu().numpy()
+    ref = T.rich_tess_build(Xh[0], Xh[1], P.box, P.bc)
+    check_structure(dev)
+    compare_meshes(dev, ref, 1.0 / 2048)
+
+
+def test_retess_failure_is_reported_and_safe():
+    """Candidates from a mesh of other points (every point moved by three
+    cell sizes in a random direction): the certification fails, the output
+    mesh has no edges, and a stage on it reads none."""
+    from paper_1410_3219_amd import rich as R
+    import torch
+    P, m, Q, X = _initial("sod", 24)
+    r = np.random.default_rng(3)
+    h = 1.0 / 24
+    ang = r.uniform(0, 2 * np.pi, m.n_cells)
+    Xm = X + 3 * h * np.stack([np.cos(ang), np.sin(ang)])
+    Xm = np.clip(Xm, 1e-3, 1 - 1e-3)
+    dm = R.DeviceMesh.from_host(m)
+    bufs = R.DeviceMeshBufs(m.n_cells, m.box, m.bc)
+    tws = R.retess_workspace(m.n_cells)
+    Xd = torch.from_numpy(Xm).cuda()
+    R.rich_retess(dm, Xd, bufs, tws)
+    st, info = R.rich_retess_result(tws)
+    assert st == R.RICH_E_MESH and info["flags"] != 0, info
+    assert info["sticky"] == info["flags"]
+    assert (bufs.t["off"].cpu().numpy() == 0).all()
+    assert (bufs.t["eoff"].cpu().numpy() == 0).all()
+    # a stage on the failed mesh touches no edge and stays bounded
+    s = R.DeviceState.from_host(Q, Xm)
+    out = R.DeviceState.empty_like(s)
+    ws = R.workspace(m.n_cells)
+    R.rich_stage(bufs.mesh(), s, s, out, 1e-4, R.Params(gamma=P.gamma), ws)
+    R.rich_stage_flags(ws)
+    # the next good call clears the flags but not the sticky word
+    R.rich_retess(dm, torch.from_numpy(X).cuda(), bufs, tws)
+    st, info2 = R.rich_retess_result(tws)
+    assert st == 0 and info2["flags"] == 0 and info2["sticky"] == info["flags"]
+
+
+def test_retess_points_outside_reported():
+    from paper_1410_3219_amd import rich as R
+    import torch
+    P, m, Q, X = _initial("wave", 20)
+    Xb = X.copy()
+    Xb[0, 5] = 1.5     # outside the periodic box
+    dm = R.DeviceMesh.from_host(m)
+    bufs = R.DeviceMeshBufs(m.n_cells, m.box, m.bc)
+    tws = R.retess_workspace(m.n_cells)
+    R.rich_retess(dm, torch.from_numpy(Xb).cuda(), bufs, tws)
+    st, info = R.rich_retess_result(tws)
+    assert st == R.RICH_E_MESH and info["flags"] & R.RETESS_POINT
+
+
+def test_retess_invalid_arguments():
+    from paper_1410_3219_amd import rich as R
+    import torch
+    P = I.advected_wave(k=3, seed=1)   # 9 cells in a periodic box: too few
+    m = T.rich_tess_build(P.px, P.py, P.box, P.bc)
+    dm = R.DeviceMesh.from_host(m)
+    bufs = R.DeviceMeshBufs(m.n_cells, m.box, m.bc)
+    tws = R.retess_workspace(m.n_cells)
+    X = torch.from_numpy(np.stack([m.px, m.py])).cuda()
+    with pytest.raises(R.RichError) as e:
+        R.rich_retess(dm, X, bufs, tws)
+    assert e.value.status == R.RICH_E_INVAL
+    P, m, Q, Xh = _initial("sod", 10)
+    dm = R.DeviceMesh.from_host(m)
+    X = torch.from_numpy(Xh).cuda()
+    small = R.retess_workspace(m.n_cells)[:1024]
+    bufs = R.DeviceMeshBufs(m.n_cells, m.box, m.bc)
+    with pytest.raises(R.RichError) as e:
+        R.rich_retess(dm, X, bufs, small)
+    assert e.value.status == R.RICH_E_NOMEM
+    other = R.DeviceMeshBufs(m.n_cells + 1, m.box, m.bc)
+    with pytest.raises(R.RichError) as e:
+        R.rich_retess(dm, X, other, R.retess_workspace(m.n_cells + 1))
+    assert e.value.status == R.RICH_E_INVAL
