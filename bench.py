@@ -309,6 +309,69 @@ def bench_extrapolated(args, R, T, P, make_state, hm0, dm0, log, steps=3):
     return out
 
 
+def bench_device_chain(args, R, P, make_state, hm0, dm0, live_final, n_steps, log, K=5):
+    """The time-centred step with both meshes rebuilt on the device
+    (rich_retess, candidates from the previous mesh) instead of by the host
+    stage: stage 1 with the Courant step, re-tessellation of the half-step
+    points, stage 2, re-tessellation of the new points; nothing leaves the
+    device.  The chain runs n_steps steps from the initial state (the last K
+    timed) and is compared with the live chain built on host meshes."""
+    import numpy as np
+    import torch
+    n = hm0.n_cells
+    prm = R.Params(gamma=P.gamma, riemann=args.riemann)
+    ws = R.workspace(n)
+    tws = R.retess_workspace(n)
+    bufs = [R.DeviceMeshBufs(n, hm0.box, hm0.bc) for _ in range(3)]
+    s = R.DeviceState.from_host(make_state(hm0.area), np.stack([hm0.px, hm0.py]))
+    half = R.DeviceState.empty_like(s)
+    nxt = R.DeviceState.empty_like(s)
+    state = {"mesh": dm0, "b": 0, "s": s, "nxt": nxt}
+
+    def step():
+        mesh, b = state["mesh"], state["b"]
+        mh, mn = bufs[b % 3], bufs[(b + 1) % 3]
+        R.rich_stage_courant(mesh, state["s"], state["s"], half, 0.5, prm, ws)
+        R.rich_retess(mesh, half.X, mh, tws)
+        R.rich_stage_dt_of(mh.mesh(), half, state["s"], state["nxt"], 1.0, ws, prm, ws)
+        R.rich_retess(mh.mesh(), state["nxt"].X, mn, tws)
+        state["mesh"], state["b"] = mn.mesh(), b + 2
+        state["s"], state["nxt"] = state["nxt"], state["s"]
+
+    for _ in range(n_steps - K):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / K
+    st, info = R.rich_retess_result(tws)
+    flags = R.rich_stage_flags(ws)
+    # re-tessellation alone, repeated on the last mesh pair
+    mh = bufs[state["b"] % 3]
+    e0.record()
+    for _ in range(K):
+        R.rich_retess(state["mesh"], state["s"].X, mh, tws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_rt = e0.elapsed_time(e1) / K
+    st2, info2 = R.rich_retess_result(tws)
+    Q = state["s"].Q
+    scale = Q.abs().amax(dim=1)
+    diff = ((Q - live_final[0]).abs().amax(dim=1) / scale).max().item()
+    out = {"steps": n_steps, "timed_steps": K, "ms_per_step": ms,
+           "cell_updates_per_s": n / (ms / 1e3), "retess_ms": ms_rt,
+           "retess_cells_per_s": n / (ms_rt / 1e3),
+           "all_certified": st == 0 and st2 == 0 and info["sticky"] == 0 and flags == 0,
+           "n_edges": info2["n_edges"],
+           "max_rel_diff_vs_host_mesh_chain": diff}
+    log(f"[bench] device chain {out}")
+    return out
+
+
 def bench_config(args, R, T, name, riemann, steps, log):
     """Another configuration of the same path (time-centred steps): a live
     chain builds the meshes, then the steps are replayed with all inputs in
@@ -430,6 +493,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and served measurements")
+    ap.add_argument("--legs", default="",
+                    help="comma-separated subset of the extra legs to run (default: all)")
     ap.add_argument("--batch-runs", type=int, default=256)
     ap.add_argument("--sweep-steps", type=int, default=20)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -628,16 +693,25 @@ def main():
     }
 
     if not args.no_extras:
-        out["batched"] = bench_batch(args, R, T, log)
-        out["served"] = bench_serve(args, R, log)
-        out["sweep_section6"] = bench_sweep(args, log)
-        out["extrapolated_fluxes"] = bench_extrapolated(args, R, T, P, make_state, hm0,
-                                                        meshes[0], log)
-        out["sedov_512sq"] = bench_config(args, R, T, "sedov", 0, 5, log)
-        out["sod_64sq_exact_100_steps"] = bench_config(args, R, T, "sod", 1, 100, log)
-        out["batched_over_plain"] = out["batched"]["batched"]["cell_updates_per_s"] / value
-        out["served_saturated_over_plain"] = (
-            out["served"]["saturated"]["cell_updates_per_s"] / value)
+        legs = {
+            "batched": lambda: bench_batch(args, R, T, log),
+            "served": lambda: bench_serve(args, R, log),
+            "sweep_section6": lambda: bench_sweep(args, log),
+            "extrapolated_fluxes": lambda: bench_extrapolated(args, R, T, P, make_state, hm0,
+                                                              meshes[0], log),
+            "device_retess_chain": lambda: bench_device_chain(args, R, P, make_state, hm0,
+                                                              meshes[0], live_final, W + K, log),
+            "sedov_512sq": lambda: bench_config(args, R, T, "sedov", 0, 5, log),
+            "sod_64sq_exact_100_steps": lambda: bench_config(args, R, T, "sod", 1, 100, log),
+        }
+        want = [x for x in args.legs.split(",") if x] or list(legs)
+        for name in want:
+            out[name] = legs[name]()
+        if "batched" in out:
+            out["batched_over_plain"] = out["batched"]["batched"]["cell_updates_per_s"] / value
+        if "served" in out:
+            out["served_saturated_over_plain"] = (
+                out["served"]["saturated"]["cell_updates_per_s"] / value)
 
     # ---------------- CPU baseline: the oracle on one step -----------------
     if not args.no_cpu_baseline:

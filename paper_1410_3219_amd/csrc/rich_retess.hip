@@ -14,10 +14,12 @@
 // assuming it, and report failure so that the caller rebuilds on the host.
 //
 // The polygon is held as the counter-clockwise list of the displacements d
-// from r_i to its edge-generating points (neighbours, images, mirrors):
-// vertex q is the intersection of the bisectors of entries q-1 and q, i.e.
-// the point p with p.d = |d|^2 / 2 for both, so vertices come from the
-// generating points alone and not from the order of the clips.
+// from r_i to its edge-generating points (neighbours, images, mirrors) and
+// its vertices: vertex q is the intersection of the bisectors of entries q-1
+// and q, i.e. the point p with p.d = |d|^2 / 2 for both, computed once when
+// those two edges become adjacent, so vertices come from the generating
+// points alone and not from the order of the clips.  A candidate further
+// than twice the largest vertex distance cannot cut and is skipped at once.
 //
 // Pipeline (one launch each, all on the caller's stream):
 //   k_rt_begin    clear the result header
@@ -134,30 +136,49 @@ __global__ void k_rt_end(Hdr* h) {
 // clipping
 // ---------------------------------------------------------------------------
 struct Poly {
-  double dx[kMaxPoly], dy[kMaxPoly];
+  double dx[kMaxPoly], dy[kMaxPoly];  // generating point of edge q, relative to r_i
+  double vx[kMaxPoly], vy[kMaxPoly];  // vertex q: start of edge q
   int32_t id[kMaxPoly];
   int nv;
+  double r2;  // largest squared vertex distance from r_i
 };
+
+__device__ __forceinline__ void update_radius(Poly& P) {
+  double r2 = 0.0;
+  for (int q = 0; q < P.nv; ++q) r2 = fmax(r2, P.vx[q] * P.vx[q] + P.vy[q] * P.vy[q]);
+  P.r2 = r2;
+}
+
+// Vertices of the starting polygon from its four generators.
+__device__ int init_vertices(Poly& P) {
+  for (int q = 0; q < P.nv; ++q) {
+    const int qm = q == 0 ? P.nv - 1 : q - 1;
+    if (!bisector_meet(P.dx[qm], P.dy[qm], P.dx[q], P.dy[q], P.vx[q], P.vy[q]))
+      return RICH_RETESS_CLIP;
+  }
+  update_radius(P);
+  return 0;
+}
 
 // Clip P by the half-plane p.d <= |d|^2/2 of candidate `cid` at displacement
 // d.  Returns a RICH_RETESS_* bit on failure, else 0.
 __device__ int clip(Poly& P, double dx, double dy, int32_t cid) {
+  const double d2 = dx * dx + dy * dy;
+  // no vertex is further than sqrt(r2) from r_i, so none can lie beyond a
+  // bisector at distance |d|/2 >= sqrt(r2): the candidate cannot cut
+  if (4.0 * P.r2 <= d2) return 0;
   for (int q = 0; q < P.nv; ++q)
     if (P.id[q] == cid) return 0;  // already an edge of the polygon
-  const double h = 0.5 * (dx * dx + dy * dy);
+  const double h = 0.5 * d2;
   // a vertex is cut off when it is further than 1e-14 |d| beyond the
   // bisector: a shallower cut would make an edge far below the
   // degenerate-edge threshold of the input stage
   const double tol = 2e-14 * h;
   uint32_t out = 0;
-  for (int q = 0; q < P.nv; ++q) {
-    const int qm = q == 0 ? P.nv - 1 : q - 1;
-    double vx, vy;
-    if (!bisector_meet(P.dx[qm], P.dy[qm], P.dx[q], P.dy[q], vx, vy)) return RICH_RETESS_CLIP;
-    if (vx * dx + vy * dy - h > tol) out |= 1u << q;
-  }
+  for (int q = 0; q < P.nv; ++q)
+    if (P.vx[q] * dx + P.vy[q] * dy - h > tol) out |= 1u << q;
   if (out == 0) return 0;
-  const uint32_t full = P.nv == 32 ? 0xFFFFFFFFu : ((1u << P.nv) - 1u);
+  const uint32_t full = (1u << P.nv) - 1u;
   if (out == full) return RICH_RETESS_CLIP;
   // the cut vertices form one cyclic run a .. a+m-1 (the polygon is convex)
   int a = -1, starts = 0;
@@ -171,29 +192,46 @@ __device__ int clip(Poly& P, double dx, double dy, int32_t cid) {
   if (starts != 1) return RICH_RETESS_CLIP;
   const int m = __popc(out);
   const int r = m - 1;  // edges a .. a+r-1 lie wholly beyond the bisector
+  const int am = a == 0 ? P.nv - 1 : a - 1;
+  const int b = a + r < P.nv ? a + r : a + r - P.nv;
+  // the two new vertices: where the new edge meets the kept edges am and b
+  double px, py, qx, qy;
+  if (!bisector_meet(P.dx[am], P.dy[am], dx, dy, px, py) ||
+      !bisector_meet(dx, dy, P.dx[b], P.dy[b], qx, qy))
+    return RICH_RETESS_CLIP;
+  int at_c, at_b;  // new positions of the new edge and of edge b
   if (a + r <= P.nv) {
     if (r == 0) {  // one vertex cut: the new edge is inserted at a
       if (P.nv + 1 > kMaxPoly) return RICH_RETESS_FAN;
       for (int t = P.nv; t > a; --t) {
         P.dx[t] = P.dx[t - 1]; P.dy[t] = P.dy[t - 1]; P.id[t] = P.id[t - 1];
+        P.vx[t] = P.vx[t - 1]; P.vy[t] = P.vy[t - 1];
       }
-      P.dx[a] = dx; P.dy[a] = dy; P.id[a] = cid;
       ++P.nv;
     } else {
-      P.dx[a] = dx; P.dy[a] = dy; P.id[a] = cid;
       for (int t = a + r; t < P.nv; ++t) {
-        P.dx[t - r + 1] = P.dx[t]; P.dy[t - r + 1] = P.dy[t]; P.id[t - r + 1] = P.id[t];
+        const int u = t - r + 1;
+        P.dx[u] = P.dx[t]; P.dy[u] = P.dy[t]; P.id[u] = P.id[t];
+        P.vx[u] = P.vx[t]; P.vy[u] = P.vy[t];
       }
       P.nv = P.nv - r + 1;
     }
+    at_c = a;
+    at_b = a + 1 < P.nv ? a + 1 : 0;
   } else {  // the removed edges wrap past the end: keep w .. a-1, then the new one
     const int w = a + r - P.nv;
     for (int t = w; t < a; ++t) {
       P.dx[t - w] = P.dx[t]; P.dy[t - w] = P.dy[t]; P.id[t - w] = P.id[t];
+      P.vx[t - w] = P.vx[t]; P.vy[t - w] = P.vy[t];
     }
-    P.dx[a - w] = dx; P.dy[a - w] = dy; P.id[a - w] = cid;
     P.nv = a - w + 1;
+    at_c = a - w;
+    at_b = 0;
   }
+  P.dx[at_c] = dx; P.dy[at_c] = dy; P.id[at_c] = cid;
+  P.vx[at_c] = px; P.vy[at_c] = py;
+  P.vx[at_b] = qx; P.vy[at_b] = qy;
+  update_radius(P);
   return 0;
 }
 
@@ -220,6 +258,7 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args a) {
     P.dx[3] = 2.0 * (a.x0 - xi);   P.dy[3] = 0.0;               P.id[3] = pack(i, kWallX0);
   }
   P.nv = 4;
+  bad |= init_vertices(P);
 
   auto candidate = [&](int c) {
     if (c < 0 || c >= a.n) return;
@@ -275,19 +314,12 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args a) {
   }
   // vertices, area and centroid (shoelace over the triangles fanned from the
   // point), edges with their midpoints
-  double vx0, vy0;
-  bisector_meet(P.dx[P.nv - 1], P.dy[P.nv - 1], P.dx[0], P.dy[0], vx0, vy0);
   double A2 = 0.0, cx = 0.0, cy = 0.0;
-  double ux = vx0, uy = vy0;
+  double ux = P.vx[0], uy = P.vy[0];
   const size_t s0 = (size_t)i * kMaxFan;
   for (int q = 0; q < P.nv; ++q) {
-    double wx, wy;  // vertex q+1: end of edge q
-    if (q + 1 < P.nv)
-      bisector_meet(P.dx[q], P.dy[q], P.dx[q + 1], P.dy[q + 1], wx, wy);
-    else {
-      wx = vx0;
-      wy = vy0;
-    }
+    const int q1 = q + 1 < P.nv ? q + 1 : 0;
+    const double wx = P.vx[q1], wy = P.vy[q1];  // vertex q+1: end of edge q
     const double c = ux * wy - uy * wx;
     A2 += c;
     cx += (ux + wx) * c;
