@@ -279,6 +279,13 @@ int rich_ctx_set_mesh(rich_ctx* ctx, const rich_host_mesh_view* hm,
                       const double box[4], uint32_t bc, void* stream);
 /* Device view of the run's current mesh. */
 int rich_ctx_mesh(rich_ctx* ctx, rich_mesh* out);
+/* With on = 1, rich_step rebuilds each mesh on the device (rich_retess, with
+ * the previous mesh as the candidate source) and calls the host stage `tess`
+ * only for a mesh the device does not certify; on = 0 (the default) always
+ * uses the host stage.  rich_ctx_tess_counts reports how many meshes were
+ * built each way since the context was created. */
+int rich_ctx_set_device_tess(rich_ctx* ctx, int32_t on);
+int rich_ctx_tess_counts(rich_ctx* ctx, int64_t* device, int64_t* host_fallback);
 int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
               rich_tess_fn tess, rich_tess_release_fn release, void* tess_user,
               void* stream);

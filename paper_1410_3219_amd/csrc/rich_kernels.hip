@@ -1065,10 +1065,14 @@ struct DevMesh {
 };
 
 struct rich_ctx {
-  DevMesh cur, spare;
+  DevMesh cur, spare, third;
   DevBuf Qh, Xh, Qn, Xn, ws;
   void* hostX = nullptr;
   size_t hostX_cap = 0;
+  // device re-tessellation with the host stage as fallback
+  bool device_tess = false;
+  DevBuf rws;                 // rich_retess workspace (header zeroed at allocation)
+  int64_t n_device = 0, n_fallback = 0;
 };
 
 namespace {
@@ -1081,6 +1085,47 @@ rich_state state_view(DevBuf& Q, DevBuf& X, int64_t n) {
   s.x = x; s.y = x + n;
   s.n_cells = n;
   return s;
+}
+
+// The mesh of points (x, y) (device) into dst, rebuilt on the device with
+// candidates from prev.  RICH_E_MESH when the result is not certified.
+int retess_into(rich_ctx* c, const rich_mesh& prev, const double* x, const double* y,
+                DevMesh& dst, hipStream_t st) {
+  const int64_t n = prev.n_cells;
+  int64_t ce = 0, cc = 0;
+  size_t wsb = 0;
+  if (rich_retess_capacity(n, &ce, &cc) || rich_retess_workspace_size(n, &wsb))
+    return RICH_E_INVAL;
+  const size_t bytes[5] = {sizeof(rich_cell) * (size_t)n, sizeof(rich_edge) * (size_t)ce,
+                           4 * (size_t)(n + 1), 4 * (size_t)cc, 4 * (size_t)(n + 1)};
+  for (int k = 0; k < 5; ++k)
+    if (!dst.b[k].ensure(bytes[k])) return RICH_E_NOMEM;
+  if (c->rws.cap < wsb) {
+    if (!c->rws.ensure(wsb)) return RICH_E_NOMEM;
+    if (hipMemsetAsync(c->rws.p, 0, 256, st) != hipSuccess) return RICH_E_DEVICE;
+  }
+  rich_mesh_bufs out;
+  out.n_cells = n;
+  out.cap_edges = (int64_t)(dst.b[1].cap / sizeof(rich_edge));
+  out.cap_csr = std::min<int64_t>((int64_t)(dst.b[3].cap / 4), (int64_t)INT32_MAX - 1);
+  out.cells = (rich_cell*)dst.b[0].p;
+  out.edges = (rich_edge*)dst.b[1].p;
+  out.off = (int32_t*)dst.b[2].p;
+  out.idx = (int32_t*)dst.b[3].p;
+  out.eoff = (int32_t*)dst.b[4].p;
+  dst.set = false;
+  int rc = rich_retess(&prev, x, y, &out, c->rws.p, c->rws.cap, st);
+  if (rc) return rc;
+  rich_retess_info info;
+  rc = rich_retess_result(c->rws.p, st, &info);
+  if (rc) return rc;
+  dst.n = n;
+  dst.ne = info.n_edges;
+  dst.nc = info.n_csr;
+  std::memcpy(dst.box, prev.box, sizeof(dst.box));
+  dst.bc = prev.bc;
+  dst.set = true;
+  return RICH_OK;
 }
 
 int tessellate_into(rich_ctx* c, DevMesh& dst, const double* dx, int64_t n, const double* box,
@@ -1435,6 +1480,8 @@ void rich_ctx_destroy(rich_ctx* ctx) {
   if (!ctx) return;
   ctx->cur.release();
   ctx->spare.release();
+  ctx->third.release();
+  ctx->rws.release();
   ctx->Qh.release(); ctx->Xh.release(); ctx->Qn.release(); ctx->Xn.release();
   ctx->ws.release();
   if (ctx->hostX) (void)hipHostFree(ctx->hostX);
@@ -1455,6 +1502,39 @@ int rich_ctx_mesh(rich_ctx* ctx, rich_mesh* out) {
   return RICH_OK;
 }
 
+namespace {
+// The mesh of state s's points into dst: on the device from `prev` when the
+// context asks for it, with the host stage when that is off or the device
+// result is not certified.
+int mesh_of(rich_ctx* ctx, const rich_mesh& prev, const rich_state& s, DevMesh& dst,
+            rich_tess_fn tess, rich_tess_release_fn release, void* tess_user, hipStream_t st) {
+  if (ctx->device_tess) {
+    const int rc = retess_into(ctx, prev, s.x, s.y, dst, st);
+    if (rc == RICH_OK) {
+      ++ctx->n_device;
+      return RICH_OK;
+    }
+    if (rc != RICH_E_MESH) return rc;
+    ++ctx->n_fallback;
+  }
+  return tessellate_into(ctx, dst, s.x, prev.n_cells, ctx->cur.box, ctx->cur.bc, tess, release,
+                         tess_user, st);
+}
+}  // namespace
+
+int rich_ctx_set_device_tess(rich_ctx* ctx, int32_t on) {
+  if (!ctx || (on != 0 && on != 1)) return RICH_E_INVAL;
+  ctx->device_tess = on == 1;
+  return RICH_OK;
+}
+
+int rich_ctx_tess_counts(rich_ctx* ctx, int64_t* device, int64_t* host_fallback) {
+  if (!ctx || !device || !host_fallback) return RICH_E_INVAL;
+  *device = ctx->n_device;
+  *host_fallback = ctx->n_fallback;
+  return RICH_OK;
+}
+
 int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
               rich_tess_fn tess, rich_tess_release_fn release, void* tess_user, void* stream) {
   if (!ctx || !state || !valid_params(p) || !ctx->cur.set) return RICH_E_INVAL;
@@ -1472,6 +1552,7 @@ int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
   rich_state next = state_view(ctx->Qn, ctx->Xn, n);
   rich_mesh m;
   ctx->cur.view(&m);
+  rich_mesh mh = m;
   int rc;
   int32_t flags = 0;
   if (p->integrator == 1) {
@@ -1483,10 +1564,8 @@ int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
     if (rc) return rc;
     if ((rc = rich_stage_flags(ctx->ws.p, stream, &flags))) return rc;
     if (flags) return RICH_E_DOMAIN;
-    rich_mesh mh = m;
     if (p->motion) {
-      rc = tessellate_into(ctx, ctx->spare, half.x, n, ctx->cur.box, ctx->cur.bc, tess, release,
-                           tess_user, st);
+      rc = mesh_of(ctx, m, half, ctx->spare, tess, release, tess_user, st);
       if (rc) return rc;
       ctx->spare.view(&mh);
     }
@@ -1496,11 +1575,12 @@ int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
   if ((rc = rich_stage_flags(ctx->ws.p, stream, &flags))) return rc;
   if (flags) return RICH_E_DOMAIN;
   if (p->motion) {
-    // the new mesh goes into the spare buffers, which then become current
-    rc = tessellate_into(ctx, ctx->spare, next.x, n, ctx->cur.box, ctx->cur.bc, tess, release,
-                         tess_user, st);
+    // the new mesh goes into the third buffers (the device rebuild reads the
+    // half-step mesh from the spare ones), which then become current
+    rc = mesh_of(ctx, p->integrator == 1 ? m : mh, next, ctx->third, tess, release, tess_user,
+                 st);
     if (rc) return rc;
-    std::swap(ctx->cur, ctx->spare);
+    std::swap(ctx->cur, ctx->third);
   }
   // commit
   const double* sq[6] = {next.M, next.Px, next.Py, next.E, next.x, next.y};

@@ -175,12 +175,14 @@ def lib():
             L.rich_ctx_destroy.restype = None
             L.rich_ctx_set_mesh.argtypes = [_vp, C.POINTER(HostMeshView), _dp, C.c_uint32, _vp]
             L.rich_ctx_mesh.argtypes = [_vp, mp]
+            L.rich_ctx_set_device_tess.argtypes = [_vp, C.c_int32]
+            L.rich_ctx_tess_counts.argtypes = [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
             L.rich_step.argtypes = [_vp, sp, C.c_double, pp, _vp, _vp, _vp, _vp]
             L.rich_step_batch.argtypes = [C.c_int32, C.POINTER(_vp), C.POINTER(_vp), _dp,
                                           C.POINTER(_vp), _vp, _vp, C.POINTER(_vp), C.c_int32,
                                           _ip, _vp, C.c_size_t, _vp]
             for f in ("rich_ctx_create", "rich_ctx_set_mesh", "rich_ctx_mesh", "rich_step",
-                      "rich_step_batch"):
+                      "rich_step_batch", "rich_ctx_set_device_tess", "rich_ctx_tess_counts"):
                 getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -569,10 +571,12 @@ class RichCtx:
     host tessellation stage is called through its C adapter, with no Python
     in between."""
 
-    def __init__(self, n_threads=0):
+    def __init__(self, n_threads=0, device_tess=False):
         from . import tess
         self.h = C.c_void_p()
         _check(lib().rich_ctx_create(C.byref(self.h)), "rich_ctx_create")
+        if device_tess:
+            _check(lib().rich_ctx_set_device_tess(self.h, 1), "rich_ctx_set_device_tess")
         TL = tess.lib()
         TL.rich_tess_ctx_create.argtypes = [C.c_int32]
         TL.rich_tess_ctx_create.restype = C.c_void_p
@@ -596,6 +600,13 @@ class RichCtx:
             self.close()
         except Exception:
             pass
+
+    def tess_counts(self):
+        """(meshes built on the device, meshes the host stage built instead)."""
+        d, f = C.c_int64(0), C.c_int64(0)
+        _check(lib().rich_ctx_tess_counts(self.h, C.byref(d), C.byref(f)),
+               "rich_ctx_tess_counts")
+        return int(d.value), int(f.value)
 
     def set_mesh(self, hm, stream=None):
         v, keep = _host_view(hm)

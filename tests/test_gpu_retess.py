@@ -341,3 +341,57 @@ def test_retess_invalid_arguments():
     with pytest.raises(R.RichError) as e:
         R.rich_retess(dm, X, other, R.retess_workspace(m.n_cells + 1))
     assert e.value.status == R.RICH_E_INVAL
+
+
+@pytest.mark.parametrize("name", ["sod", "wave"])
+def test_step_driver_with_device_tess_follows_oracle_chain(name):
+    """rich_step with device re-tessellation: four steps, every mesh after
+    the first built on the device, against the oracle chain on its own
+    Voronoi meshes."""
+    from paper_1410_3219_amd import rich as R
+    P, m, Q, X = _initial(name, 22)
+    op = O.Params(gamma=P.gamma)
+
+    def tess(px, py, box, bc):
+        return O.voronoi_mesh(O.voronoi(px, py, box, bc))
+
+    dt, _ = O.cfl_dt(m, Q, op)
+    ctx = R.RichCtx(device_tess=True)
+    ctx.set_mesh(m)
+    s = R.DeviceState.from_host(Q, X)
+    Qo, Xo, mo = Q, X, tess(m.px, m.py, m.box, m.bc)
+    for _ in range(4):
+        ctx.step(s, dt, U.gpu_params(op))
+        Qo, Xo, mo, _, sto = O.step(mo, Qo, Xo, dt, op, tess)
+        assert sto == 0
+    assert ctx.tess_counts() == (8, 0)
+    Qg, Xg = s.numpy()
+    eq, ex = U.errors(mo, Qg, Xg, Qo, Xo, Qo, op)
+    print(f"\n{name} step driver, device meshes: err {eq} x {ex}")
+    assert (eq < 1e-11).all() and ex < 1e-12
+    ctx.close()
+
+
+def test_step_driver_falls_back_to_host_stage():
+    """A current mesh whose cells are other points (a permutation) gives the
+    device re-tessellation wrong candidates: it is not certified, the host
+    stage builds that mesh instead, and the step equals the host-only
+    driver's bit for bit."""
+    from paper_1410_3219_amd import rich as R
+    P, m, Q, X = _initial("sod", 16)
+    perm = np.random.default_rng(7).permutation(m.n_cells)
+    mp = T.rich_tess_build(m.px[perm], m.py[perm], m.box, m.bc)
+    Qu = I.conserved(1.0, 0.0, 0.0, 1.0, m.area, P.gamma)
+    p = R.Params(gamma=P.gamma)
+    out = []
+    for dev in (True, False):
+        ctx = R.RichCtx(device_tess=dev)
+        ctx.set_mesh(mp)
+        s = R.DeviceState.from_host(Qu, X)
+        ctx.step(s, 1e-3, p)
+        out.append((s.numpy(), ctx.tess_counts()))
+        ctx.close()
+    (Qd, Xd), counts = out[0]
+    (Qh, Xh), counts_h = out[1]
+    assert counts[1] >= 1 and counts_h == (0, 0), counts
+    assert np.array_equal(Qd, Qh) and np.array_equal(Xd, Xh)
