@@ -133,6 +133,37 @@ def summarize_pmc(args):
     print(json.dumps(out))
 
 
+def summarize_counters(d, name, command):
+    """Per kernel of the HIP path, the mean per dispatch of every counter of a
+    rocprofv3 --pmc run (counters summed over the dispatch's instances)."""
+    import csv
+    import re
+    f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    acc = {}
+    for row in csv.DictReader(open(f[0])):
+        kname = re.sub(r"\(.*$", "", row["Kernel_Name"]).replace("void ", "")
+        if not kname.startswith(("rich::", "retess::")):
+            continue
+        a = acc.setdefault(kname, {}).setdefault(row["Counter_Name"], {})
+        a[row["Dispatch_Id"]] = a.get(row["Dispatch_Id"], 0.0) + float(row["Counter_Value"])
+    counters = sorted({c for k in acc.values() for c in k})
+    path = os.path.join(ROOT, "profiles", f"{name}.txt")
+    with open(path, "w") as out:
+        out.write(f"# rocprofv3 counters, mean per dispatch, per kernel\n#\n# command (on one "
+                  f"MI355X, from /tmp with TMPDIR=/tmp):\n#   {command}\n# summarised with:\n"
+                  f"#   python bench.py --summarize-counters <dir> {name} '<command>'\n#\n")
+        out.write(f"{'kernel':40s} {'dispatches':>10s} " +
+                  " ".join(f"{c:>22s}" for c in counters) + "\n")
+        for k in sorted(acc):
+            n = max(len(v) for v in acc[k].values())
+            vals = [sum(acc[k][c].values()) / len(acc[k][c]) if c in acc[k] else float("nan")
+                    for c in counters]
+            out.write(f"{k[:40]:40s} {n:10d} " + " ".join(f"{v:22.4g}" for v in vals) + "\n")
+    print(open(path).read())
+
+
 def bench_batch(args, R, T, log):
     """Many independent shock-tube runs of uneven sizes (N log-uniform in
     [1024, 65536], interface angle, gamma and rounding strength drawn per
@@ -504,12 +535,18 @@ def main():
     ap.add_argument("--threads", type=int, default=0, help="host tessellation threads")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a device-to-device copy of this size first (counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("PMC_DIR", "NAME", "COMMAND"),
+                    help="average each counter per kernel over a rocprofv3 --pmc run into "
+                         "profiles/NAME.txt, recording COMMAND as the run that made it")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
                          "script with --copy-probe-mib into profiles/traffic_<workload>.json")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(args)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -395,3 +395,50 @@ def test_step_driver_falls_back_to_host_stage():
     (Qh, Xh), counts_h = out[1]
     assert counts[1] >= 1 and counts_h == (0, 0), counts
     assert np.array_equal(Qd, Qh) and np.array_equal(Xd, Xh)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_retess_exact_lattices(bc):
+    """Degenerate inputs: an exact square lattice (four points on every
+    Voronoi vertex's circle, so the diagonal edges have zero length and are
+    dropped) and an exact hexagonal one, re-tessellated from a mesh of
+    jittered points: the same cells as the oracle's Voronoi tessellation."""
+    from paper_1410_3219_amd import rich as R
+    import torch
+    k = 24
+    g = (np.arange(k) + 0.5) / k
+    px, py = [a.ravel().copy() for a in np.meshgrid(g, g, indexing="ij")]
+    box = (0.0, 0.0, 1.0, 1.0)
+    r = np.random.default_rng(5)
+    jx = px + 0.05 / k * r.uniform(-1, 1, px.size)
+    jy = py + 0.05 / k * r.uniform(-1, 1, py.size)
+    m = T.rich_tess_build(jx, jy, box, bc)
+    dm = R.DeviceMesh.from_host(m)
+    for (qx, qy, bx) in ((px, py, box), _hex(k, bc)):
+        if bx != box:
+            m2 = T.rich_tess_build(qx + 0.01 / k, qy, bx, bc)
+            dprev = R.DeviceMesh.from_host(m2)
+        else:
+            dprev = dm
+        bufs = R.DeviceMeshBufs(qx.size, bx, bc)
+        tws = R.retess_workspace(qx.size)
+        Xd = torch.from_numpy(np.stack([qx, qy])).cuda()
+        R.rich_retess(dprev, Xd, bufs, tws)
+        st, info = R.rich_retess_result(tws)
+        assert st == 0, info
+        dev = R.mesh_to_host(bufs.mesh(), info["n_edges"], info["n_csr"])
+        check_structure(dev)
+        ref = O.voronoi_mesh(O.voronoi(qx, qy, bx, bc))
+        compare_meshes(dev, ref, 1.0 / k)
+
+
+def _hex(k, bc):
+    """k x k hexagonal lattice (rows offset by half a spacing) in a box of
+    height k * sqrt(3)/2 spacings; with walls, shifted off the walls."""
+    a = 1.0 / k
+    xs, ys = [], []
+    for rr in range(k):
+        for c in range(k):
+            xs.append((c + 0.5 * (rr % 2) + 0.25) * a)
+            ys.append((rr + 0.5) * a * math.sqrt(3.0) / 2.0)
+    return np.array(xs), np.array(ys), (0.0, 0.0, 1.0, k * a * math.sqrt(3.0) / 2.0)
