@@ -1087,10 +1087,10 @@ rich_state state_view(DevBuf& Q, DevBuf& X, int64_t n) {
   return s;
 }
 
-// The mesh of points (x, y) (device) into dst, rebuilt on the device with
-// candidates from prev.  RICH_E_MESH when the result is not certified.
-int retess_into(rich_ctx* c, const rich_mesh& prev, const double* x, const double* y,
-                DevMesh& dst, hipStream_t st) {
+// Enqueue the device rebuild of the mesh of points (x, y) into dst, with
+// candidates from prev (retess_finish reads the outcome).
+int retess_enqueue(rich_ctx* c, const rich_mesh& prev, const double* x, const double* y,
+                   DevMesh& dst, hipStream_t st) {
   const int64_t n = prev.n_cells;
   int64_t ce = 0, cc = 0;
   size_t wsb = 0;
@@ -1114,18 +1114,28 @@ int retess_into(rich_ctx* c, const rich_mesh& prev, const double* x, const doubl
   out.idx = (int32_t*)dst.b[3].p;
   out.eoff = (int32_t*)dst.b[4].p;
   dst.set = false;
-  int rc = rich_retess(&prev, x, y, &out, c->rws.p, c->rws.cap, st);
-  if (rc) return rc;
+  return rich_retess(&prev, x, y, &out, c->rws.p, c->rws.cap, st);
+}
+
+// Synchronise and take the rebuilt mesh into dst; RICH_E_MESH when the
+// device did not certify it.
+int retess_finish(rich_ctx* c, const rich_mesh& prev, DevMesh& dst, hipStream_t st) {
   rich_retess_info info;
-  rc = rich_retess_result(c->rws.p, st, &info);
+  const int rc = rich_retess_result(c->rws.p, st, &info);
   if (rc) return rc;
-  dst.n = n;
+  dst.n = prev.n_cells;
   dst.ne = info.n_edges;
   dst.nc = info.n_csr;
   std::memcpy(dst.box, prev.box, sizeof(dst.box));
   dst.bc = prev.bc;
   dst.set = true;
   return RICH_OK;
+}
+
+int retess_into(rich_ctx* c, const rich_mesh& prev, const double* x, const double* y,
+                DevMesh& dst, hipStream_t st) {
+  const int rc = retess_enqueue(c, prev, x, y, dst, st);
+  return rc ? rc : retess_finish(c, prev, dst, st);
 }
 
 int tessellate_into(rich_ctx* c, DevMesh& dst, const double* dx, int64_t n, const double* box,
@@ -1677,12 +1687,36 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
   // spare mesh: device->host copies, then the runs spread over n_threads
   // host threads (each call with its own run's tess_users[r]), then the
   // uploads, one synchronisation, and the host arrays released.
+  // Runs whose context asks for it are rebuilt on the device first (all
+  // enqueued, then one synchronisation); a mesh the device does not certify
+  // joins the host tessellations.
   std::vector<rich_host_mesh_view> hv(n);
   auto retessellate = [&](const std::vector<rich_state>& xs, bool half_step) -> int {
-    std::vector<int32_t> todo;
+    std::vector<int32_t> todo, dev;
     for (int32_t r = 0; r < n; ++r)
       if (!status[r] && params[r]->motion && !(half_step && params[r]->integrator == 1))
+        (ctxs[r]->device_tess ? dev : todo).push_back(r);
+    auto dst_of = [&](int32_t r) -> DevMesh& {
+      return half_step ? ctxs[r]->spare : ctxs[r]->third;
+    };
+    std::vector<int32_t> enq;
+    for (int32_t r : dev) {
+      const int e = retess_enqueue(ctxs[r], mesh[r], xs[r].x, xs[r].y, dst_of(r), st);
+      if (e == RICH_E_DEVICE) return e;
+      if (e) status[r] = e;
+      else enq.push_back(r);
+    }
+    for (int32_t r : enq) {
+      const int e = retess_finish(ctxs[r], mesh[r], dst_of(r), st);
+      if (e == RICH_OK) {
+        ++ctxs[r]->n_device;
+      } else if (e == RICH_E_MESH) {
+        ++ctxs[r]->n_fallback;
         todo.push_back(r);
+      } else {
+        return e;
+      }
+    }
     if (todo.empty()) return RICH_OK;
     for (int32_t r : todo) {
       rich_ctx* c = ctxs[r];
@@ -1733,7 +1767,7 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
     std::vector<int32_t> uploaded;
     for (int32_t r : todo) {
       if (status[r]) continue;
-      const int u = ctxs[r]->spare.upload_async(&hv[r], ctxs[r]->cur.box, ctxs[r]->cur.bc, st);
+      const int u = dst_of(r).upload_async(&hv[r], ctxs[r]->cur.box, ctxs[r]->cur.bc, st);
       if (u) {
         status[r] = u;
         if (u == RICH_E_DEVICE) err = u;
@@ -1757,8 +1791,9 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
         ctxs[r]->spare.view(&mesh[r]);
   }
   if ((rc = stage(true))) return fail_all(rc);
-  // the final meshes go into the spare buffers; a run's current mesh is
-  // replaced only once its whole step has succeeded
+  // the final meshes go into the third buffers (a device rebuild reads the
+  // half-step mesh from the spare ones); a run's current mesh is replaced
+  // only once its whole step has succeeded
   if (any_motion && (rc = retessellate(next, false))) return fail_all(rc);
   for (int32_t r = 0; r < n; ++r) {
     if (status[r]) continue;
@@ -1772,7 +1807,7 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
   }
   if (hipStreamSynchronize(st) != hipSuccess) return fail_all(RICH_E_DEVICE);
   for (int32_t r = 0; r < n; ++r)
-    if (!status[r] && params[r]->motion) std::swap(ctxs[r]->cur, ctxs[r]->spare);
+    if (!status[r] && params[r]->motion) std::swap(ctxs[r]->cur, ctxs[r]->third);
   for (int32_t r = 0; r < n; ++r)
     if (status[r]) return status[r];
   return RICH_OK;

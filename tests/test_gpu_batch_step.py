@@ -85,10 +85,10 @@ def _oracle_chain(P, m, Q, X, dts, p):
     return Q, X, m
 
 
-def _gpu_chain(P, m, Q, X, dts, p):
+def _gpu_chain(P, m, Q, X, dts, p, device_tess=False):
     import torch
     from paper_1410_3219_amd import rich as R
-    ctx = R.RichCtx()
+    ctx = R.RichCtx(device_tess=device_tess)
     ctx.set_mesh(m)
     s = R.DeviceState.from_host(Q, X)
     for dt in dts:
@@ -229,12 +229,12 @@ def _step_batch_runs():
     return out
 
 
-def _batch_chain(runs, steps, bad_run=None):
+def _batch_chain(runs, steps, bad_run=None, device_tess=lambda r: False, counts=None):
     import torch
     from paper_1410_3219_amd import rich as R
     ctxs, states = [], []
     for r, (m, Q, X, p, dt) in enumerate(runs):
-        c = R.RichCtx(n_threads=1)
+        c = R.RichCtx(n_threads=1, device_tess=device_tess(r))
         c.set_mesh(m)
         Qr = Q.copy()
         if r == bad_run:
@@ -250,6 +250,8 @@ def _batch_chain(runs, steps, bad_run=None):
     torch.cuda.synchronize()
     out = [s.numpy() for s in states]
     meshes = [c.mesh().n_edges for c in ctxs]
+    if counts is not None:
+        counts.extend(c.tess_counts() for c in ctxs)
     for c in ctxs:
         c.close()
     return out, all_status, meshes
@@ -262,6 +264,22 @@ def test_step_batch_equals_separate_steps_bitwise():
     for (m, Q, X, p, dt), (Qb, Xb) in zip(runs, res):
         Qs, Xs = _gpu_chain(None, m, Q, X, [dt] * 3, p)
         assert np.array_equal(Qb, Qs) and np.array_equal(Xb, Xs)
+
+
+def test_step_batch_with_device_tess_equals_separate_steps_bitwise():
+    """Half of the runs rebuild their meshes on the device: the batched step
+    equals each run's own rich_step (with the same choice) bit for bit."""
+    runs = _step_batch_runs()
+    dev = lambda r: r % 2 == 0   # noqa: E731
+    counts = []
+    res, status, _ = _batch_chain(runs, 3, device_tess=dev, counts=counts)
+    assert all(s == [0] * len(runs) for s in status), status
+    for r, ((m, Q, X, p, dt), (Qb, Xb)) in enumerate(zip(runs, res)):
+        Qs, Xs = _gpu_chain(None, m, Q, X, [dt] * 3, p, device_tess=dev(r))
+        assert np.array_equal(Qb, Qs) and np.array_equal(Xb, Xs), r
+        moving = p.motion == 1
+        per_step = (1 if p.integrator == 1 else 2) if moving else 0
+        assert counts[r] == ((3 * per_step, 0) if dev(r) else (0, 0)), (r, counts[r])
 
 
 def test_step_batch_follows_oracle_chain():
