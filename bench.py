@@ -473,26 +473,32 @@ def bench_config(args, R, T, name, riemann, steps, log):
 def bench_sweep(args, log):
     """Section 6 cell-rounding sweep (Gresho vortex, 30x30 cells, a 6x6
     (chi, eta) grid) advanced by the batched time-centred step for a fixed
-    number of steps: end-to-end rate, host tessellation included."""
+    number of steps: end-to-end rate, tessellation included, with the meshes
+    built by the host stage and with them rebuilt on the device."""
     import numpy as np
     import torch
     from paper_1410_3219_amd import sweep as SW
-    sw = SW.Sweep(SW.chi_eta_grid(6, 6), k=30, n_threads=args.threads or 0)
-    sw.step()            # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.sweep_steps):
-        sw.step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    n = sw.mesh0.n_cells
-    L = sw.density_L()
-    out = {"runs": len(sw.grid), "cells_per_run": n, "steps": args.sweep_steps,
-           "s": dt, "cell_updates_per_s_end_to_end": len(sw.grid) * n * args.sweep_steps / dt,
-           "all_ok": all(s == 0 for s in sw.status),
-           "density_L_min": float(np.nanmin(L)), "density_L_max": float(np.nanmax(L))}
-    sw.close()
-    log(f"[bench] sweep {out}")
+    out = {}
+    for mode, dev in (("host_meshes", False), ("device_meshes", True)):
+        sw = SW.Sweep(SW.chi_eta_grid(6, 6), k=30, n_threads=args.threads or 0,
+                      device_tess=dev)
+        sw.step()            # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.sweep_steps):
+            sw.step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        n = sw.mesh0.n_cells
+        L = sw.density_L()
+        out[mode] = {"runs": len(sw.grid), "cells_per_run": n, "steps": args.sweep_steps,
+                     "s": dt,
+                     "cell_updates_per_s_end_to_end": len(sw.grid) * n * args.sweep_steps / dt,
+                     "all_ok": all(s == 0 for s in sw.status),
+                     "meshes_device_host": sw.tess_counts(),
+                     "density_L_min": float(np.nanmin(L)), "density_L_max": float(np.nanmax(L))}
+        sw.close()
+        log(f"[bench] sweep {mode} {out[mode]}")
     return out
 
 

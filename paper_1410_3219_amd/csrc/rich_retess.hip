@@ -75,7 +75,7 @@ struct Args {
   Hdr* hdr;
   int32_t* deg;        // [n]
   int32_t* s_nb;       // [n][kMaxFan] generating point: cell | code << 28
-  double *s_len, *s_fx, *s_fy;  // [n][kMaxFan]
+  double* s_geo;       // [n][kMaxFan][3] edge length, midpoint x, midpoint y
   uint8_t* s_flag;     // [n][kMaxFan] bit 0 kept, bit 1 owned
   int64_t* bsum;       // [2][n_scan_blocks] block totals of kept / owned
   // geometry
@@ -326,9 +326,10 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args a) {
     cy += (uy + wy) * c;
     const double ex = wx - ux, ey = wy - uy;
     a.s_nb[s0 + q] = P.id[q];
-    a.s_len[s0 + q] = sqrt(ex * ex + ey * ey);
-    a.s_fx[s0 + q] = xi + 0.5 * (ux + wx);
-    a.s_fy[s0 + q] = yi + 0.5 * (uy + wy);
+    double* g = a.s_geo + 3 * (s0 + q);
+    g[0] = sqrt(ex * ex + ey * ey);
+    g[1] = xi + 0.5 * (ux + wx);
+    g[2] = yi + 0.5 * (uy + wy);
     ux = wx;
     uy = wy;
   }
@@ -359,7 +360,8 @@ __global__ __launch_bounds__(kThreads) void k_rt_classify(Args a) {
       const int j = (int)((uint32_t)id & kMask);
       const int code = (int)((uint32_t)id >> kShift);
       const double Rj = sqrt(a.cells[j].area / kPi);
-      const double L = a.s_len[s0 + q];
+      const double* g = a.s_geo + 3 * (s0 + q);
+      const double L = g[0];
       const bool keep = L >= 1e-12 * 0.5 * (Ri + Rj);
       bool own;
       if (code >= kWallX0) own = true;
@@ -381,8 +383,9 @@ __global__ __launch_bounds__(kThreads) void k_rt_classify(Args a) {
       for (int t = 0; t < dj; ++t)
         if (a.s_nb[t0 + t] == want) { found = t; break; }
       if (found < 0) { bad |= RICH_RETESS_ASYM; continue; }
-      const double Lj = a.s_len[t0 + found];
-      double fxj = a.s_fx[t0 + found], fyj = a.s_fy[t0 + found];
+      const double* gj = a.s_geo + 3 * (t0 + found);
+      const double Lj = gj[0];
+      double fxj = gj[1], fyj = gj[2];
       if (code != 0) {  // the neighbour sees the edge one image away
         int sx, sy;
         code_shift(code, sx, sy);
@@ -391,7 +394,7 @@ __global__ __launch_bounds__(kThreads) void k_rt_classify(Args a) {
       }
       const double tol = 1e-9 * (Ri + Rj);
       if (!(Lj >= 1e-12 * 0.5 * (Ri + Rj)) || fabs(L - Lj) > tol ||
-          fabs(a.s_fx[s0 + q] - fxj) > tol || fabs(a.s_fy[s0 + q] - fyj) > tol)
+          fabs(g[1] - fxj) > tol || fabs(g[2] - fyj) > tol)
         bad |= RICH_RETESS_ASYM;
     }
     if (d == 0 || !(area > 0.0)) bad |= RICH_RETESS_CLIP;
@@ -548,10 +551,11 @@ __global__ __launch_bounds__(kThreads) void k_rt_emit(Args a) {
     if (!(f & 1)) continue;
     const int32_t id = a.s_nb[s0 + q];
     if (f & 2) {
+      const double* g = a.s_geo + 3 * (s0 + q);
       rich_edge r;
-      r.fx = a.s_fx[s0 + q];
-      r.fy = a.s_fy[s0 + q];
-      r.len = a.s_len[s0 + q];
+      r.fx = g[1];
+      r.fy = g[2];
+      r.len = g[0];
       r.i = i;
       r.j = id;
       a.edges[e] = r;
@@ -592,7 +596,7 @@ namespace {
 size_t rt_align(size_t v) { return (v + 255) / 256 * 256; }
 
 struct RtLayout {
-  size_t deg, s_nb, s_len, s_fx, s_fy, s_flag, bsum, total;
+  size_t deg, s_nb, s_geo, s_flag, bsum, total;
   int nb;
 };
 
@@ -603,9 +607,7 @@ RtLayout rt_layout(int64_t n) {
   size_t o = 256;  // result header
   L.deg = o;    o += rt_align(4 * (size_t)n);
   L.s_nb = o;   o += rt_align(4 * slots);
-  L.s_len = o;  o += rt_align(8 * slots);
-  L.s_fx = o;   o += rt_align(8 * slots);
-  L.s_fy = o;   o += rt_align(8 * slots);
+  L.s_geo = o;  o += rt_align(24 * slots);
   L.s_flag = o; o += rt_align(slots);
   L.bsum = o;   o += rt_align(16 * (size_t)L.nb);
   L.total = o;
@@ -679,9 +681,7 @@ int rich_retess(const rich_mesh* prev, const double* x, const double* y,
   a.hdr = reinterpret_cast<retess::Hdr*>(w);
   a.deg = reinterpret_cast<int32_t*>(w + L.deg);
   a.s_nb = reinterpret_cast<int32_t*>(w + L.s_nb);
-  a.s_len = reinterpret_cast<double*>(w + L.s_len);
-  a.s_fx = reinterpret_cast<double*>(w + L.s_fx);
-  a.s_fy = reinterpret_cast<double*>(w + L.s_fy);
+  a.s_geo = reinterpret_cast<double*>(w + L.s_geo);
   a.s_flag = reinterpret_cast<uint8_t*>(w + L.s_flag);
   a.bsum = reinterpret_cast<int64_t*>(w + L.bsum);
   a.x0 = prev->box[0];

@@ -31,7 +31,10 @@ def chi_eta_grid(n_chi=6, n_eta=6, chi=(0.01, 1.0), eta=(0.001, 0.5)):
 
 
 class Sweep:
-    def __init__(self, grid, k=30, seed=4, n_threads=0):
+    """device_tess: each run rebuilds its meshes on the device (rich_retess),
+    with the host stage only as the fallback for an uncertified mesh."""
+
+    def __init__(self, grid, k=30, seed=4, n_threads=0, device_tess=False):
         P = I.gresho(k=k, seed=seed)
         m = T.rich_tess_build(P.px, P.py, P.box, P.bc)
         self.problem, self.mesh0 = P, m
@@ -41,7 +44,7 @@ class Sweep:
         self.n_threads = n_threads
         self.ctxs, self.states, self.params = [], [], []
         for chi, eta in self.grid:
-            c = R.RichCtx(n_threads=1)
+            c = R.RichCtx(n_threads=1, device_tess=device_tess)
             c.set_mesh(m)
             self.ctxs.append(c)
             self.states.append(R.DeviceState.from_host(self.Q0, self.X0))
@@ -107,6 +110,11 @@ class Sweep:
             rho = Q[0] / m.area
             out.append(float(np.mean(np.abs(rho - 1.0))))
         return out
+
+    def tess_counts(self):
+        """(meshes built on the device, meshes the host stage built) over all runs."""
+        c = [x.tess_counts() for x in self.ctxs]
+        return sum(a for a, _ in c), sum(b for _, b in c)
 
     def close(self):
         for c in self.ctxs:

@@ -11,10 +11,11 @@ from paper_1410_3219_amd import tess as T
 pytestmark = pytest.mark.gpu
 
 
-def test_sweep_runs_follow_oracle_chains():
+@pytest.mark.parametrize("device_tess", [False, True])
+def test_sweep_runs_follow_oracle_chains(device_tess):
     from paper_1410_3219_amd import sweep as SW
     grid = [(0.01, 0.001), (0.15, 0.02), (1.0, 0.5), (0.5, 0.005)]
-    sw = SW.Sweep(grid, k=16, n_threads=4)
+    sw = SW.Sweep(grid, k=16, n_threads=4, device_tess=device_tess)
     P, m = sw.problem, sw.mesh0
     # per-run dt from the oracle's Courant step, fixed for the 3 steps
     dts = []
@@ -41,6 +42,7 @@ def test_sweep_runs_follow_oracle_chains():
         assert abs(L_gpu[r] - L_o) <= 1e-9 * max(L_o, 1e-12) + 1e-15, (r, L_gpu[r], L_o)
     # different rounding strengths move the points differently
     assert len({round(x, 15) for x in L_gpu}) > 1
+    assert sw.tess_counts() == ((2 * 3 * len(grid), 0) if device_tess else (0, 0))
     sw.close()
 
 
