@@ -155,6 +155,17 @@ int rich_cfl_dt(const rich_mesh* m, const rich_state* s, const rich_params* p,
                 double* dt, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Area change rate of every cell that the moving edges imply (section 5, eq.
+ * areachange): adot[i] = dA_i/dt with the point velocities w of state s on
+ * mesh m (section 6).  The actual change of a cell's area over a step differs
+ * from h * adot at second order: that difference is the paper's area
+ * inconsistency.  adot is a device array of m->n_cells doubles.  Enqueued on
+ * `stream`; a bad CSR entry sets RICH_FLAG_DOMAIN (rich_stage_flags).
+ */
+int rich_area_rate(const rich_mesh* m, const rich_state* s, const rich_params* p,
+                   double* adot, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Courant step fused into a stage, with no host round trip (sections 2.3 and
  * 2.2): the cell pass of this stage also takes the Courant minimum of src
  * (the same quantity rich_cfl_dt reduces), a one-block reduction writes

@@ -668,6 +668,51 @@ __device__ __forceinline__ double block_min(double t, double* smin) {
   return m;
 }
 
+// Area change rate of every cell implied by its edges' velocities (section 5,
+// eq. areachange): each edge moves along its normal with the edge velocity of
+// the moving frame, so dA_i/dt = -sum_j L_ij ((w_j - w_i).c_ij - (w_i + w_j)/2 .
+// r_ij) / |r_ij| with r_ij from point i to the neighbour (image or mirror) and
+// c_ij from their midpoint to the edge centre.  The point velocities come
+// from the records that k_cell wrote.
+__global__ __launch_bounds__(kCflThreads) void k_adot(RunDesc d, double* adot) {
+  const int i = blockIdx.x * kCflThreads + threadIdx.x;
+  if (i >= d.n) return;
+  double rix, riy;
+  load_point(d, i, rix, riy);
+  const double* ri = d.rec + (size_t)i * kRecDoubles;
+  const double wix = ri[R_WX], wiy = ri[R_WY];
+  int k0 = d.off[i], k1 = d.off[i + 1];
+  bool bad = false;
+  if (k0 < 0 || k1 < k0 || k1 > d.n_csr) {
+    bad = true;
+    k1 = k0;
+  }
+  double s = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const NbE v = nb_edge(d, i, d.idx[k], bad);
+    double rjx, rjy, wjx, wjy;
+    if (v.wall) {
+      mirror_point(d, v.wall, rix, riy, rjx, rjy);
+      mirror_vec(v.wall, wix, wiy, wjx, wjy);
+    } else {
+      load_point(d, v.j, rjx, rjy);
+      rjx += v.shx;
+      rjy += v.shy;
+      const double* rj = d.rec + (size_t)v.j * kRecDoubles;
+      wjx = rj[R_WX];
+      wjy = rj[R_WY];
+    }
+    const double rx = rjx - rix, ry = rjy - riy;
+    const double r = sqrt(rx * rx + ry * ry);
+    const double cx = v.fx - 0.5 * (rix + rjx), cy = v.fy - 0.5 * (riy + rjy);
+    const double t1 = ((wjx - wix) * cx + (wjy - wiy) * cy) / r;
+    const double t2 = (0.5 * (wix + wjx) * rx + 0.5 * (wiy + wjy) * ry) / r;
+    s -= v.L * (t1 - t2);
+  }
+  adot[i] = s;
+  if (bad) atomicOr(d.flag, RICH_FLAG_DOMAIN);
+}
+
 __global__ __launch_bounds__(kCflThreads) void k_cfl(RunDesc d, double* block_out) {
   __shared__ double smin[kCflThreads / 64];
   double t = INFINITY;
@@ -1262,6 +1307,25 @@ int rich_stage_flags(void* ws, void* stream, int32_t* flags) {
   if (hipMemcpy(flags, ws, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
     return RICH_E_DEVICE;
   return RICH_OK;
+}
+
+int rich_area_rate(const rich_mesh* m, const rich_state* s, const rich_params* p, double* adot,
+                   void* ws, size_t ws_bytes, void* stream) {
+  if (!valid_mesh(m) || !valid_params(p) || !adot || !ws) return RICH_E_INVAL;
+  if (!valid_state(s, m->n_cells, false)) return RICH_E_INVAL;
+  if (ws_bytes < run_ws_bytes(m->n_cells) || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return RICH_E_NOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  RunDesc d = make_desc(m, s, nullptr, nullptr, 0.0, p, static_cast<char*>(ws));
+  constexpr int CPB = rich::kCellThreads / rich::kLpc;
+  const int n_ctiles = (d.n + CPB - 1) / CPB;
+  // the cell pass writes the point velocities into the records
+  hipLaunchKernelGGL(rich::k_clear, dim3(1), dim3(64), 0, st, d.flag, d.cfl_min);
+  hipLaunchKernelGGL((rich::k_cell<rich::kLpc, false>), dim3(n_ctiles), dim3(rich::kCellThreads),
+                     0, st, d, (const RunDesc*)nullptr, (const int32_t*)nullptr, 1, n_ctiles);
+  hipLaunchKernelGGL(rich::k_adot, dim3((d.n + rich::kCflThreads - 1) / rich::kCflThreads),
+                     dim3(rich::kCflThreads), 0, st, d, adot);
+  return hip_status(hipGetLastError());
 }
 
 int rich_cfl_dt(const rich_mesh* m, const rich_state* s, const rich_params* p, double* dt,

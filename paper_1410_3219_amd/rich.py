@@ -129,6 +129,7 @@ def lib():
         L.rich_stage.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, C.c_size_t, _vp]
         L.rich_stage_flags.argtypes = [_vp, _vp, _ip]
         L.rich_cfl_dt.argtypes = [mp, sp, pp, _dp, _vp, C.c_size_t, _vp]
+        L.rich_area_rate.argtypes = [mp, sp, pp, _vp, _vp, C.c_size_t, _vp]
         L.rich_stage_courant.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, C.c_size_t, _vp]
         L.rich_stage_dt_of.argtypes = [mp, sp, sp, sp, C.c_double, _vp, pp, _vp, C.c_size_t,
                                        _vp]
@@ -146,7 +147,7 @@ def lib():
         L.rich_profile_enable.argtypes = [C.c_int]
         L.rich_profile_read.argtypes = [C.c_char_p, _dp, C.POINTER(C.c_int64)]
         for f in ("rich_workspace_size", "rich_stage", "rich_stage_flags", "rich_cfl_dt",
-                  "rich_stage_courant", "rich_stage_dt_of", "rich_stage_dt",
+                  "rich_stage_courant", "rich_stage_dt_of", "rich_stage_dt", "rich_area_rate",
                   "rich_retess_capacity", "rich_retess_workspace_size", "rich_retess",
                   "rich_retess_view", "rich_retess_result",
                   "rich_profile_enable", "rich_profile_read"):
@@ -322,6 +323,17 @@ def rich_cfl_dt(mesh: DeviceMesh, state: DeviceState, params: Params, ws, stream
                            _stream_ptr(stream))
     _check(st, "rich_cfl_dt")
     return dt.value
+
+
+def rich_area_rate(mesh: DeviceMesh, state: DeviceState, params: Params, ws, stream=None):
+    """dA/dt of every cell implied by the moving edges (device tensor)."""
+    import torch
+    adot = torch.empty(mesh.n_cells, dtype=torch.float64, device=state.Q.device)
+    st = lib().rich_area_rate(C.byref(mesh.c()), C.byref(state.c()), C.byref(params.c()),
+                              C.c_void_p(adot.data_ptr()), C.c_void_p(ws.data_ptr()),
+                              ws.numel(), _stream_ptr(stream))
+    _check(st, "rich_area_rate")
+    return adot
 
 
 def rich_stage_courant(mesh: DeviceMesh, src: DeviceState, base: DeviceState,
