@@ -400,18 +400,38 @@ int rich_retess(const rich_mesh* prev, const double* x, const double* y,
 int rich_retess_view(const rich_mesh_bufs* out, const double box[4], uint32_t bc,
                      rich_mesh* m);
 
+/* Many re-tessellations at once, one launch per kernel for all n runs: run
+ * r as rich_retess(prev[r], x[r], y[r], out[r], ws[r], ws_bytes[r]), each
+ * run with its own workspace and output buffers.  bws is device memory of
+ * rich_retess_batch_workspace_size bytes, 256-byte aligned; the call
+ * synchronises `stream` once, to upload the runs' descriptors into it, and
+ * then enqueues the kernels.  Any run's bad arguments fail the whole call
+ * with that run's status, before anything is enqueued.  The results are
+ * read with rich_retess_batch_result (or per run with rich_retess_result). */
+int rich_retess_batch_workspace_size(int32_t n, size_t* bytes);
+int rich_retess_batch(int32_t n, const rich_mesh* const* prev, const double* const* x,
+                      const double* const* y, const rich_mesh_bufs* const* out,
+                      void* const* ws, const size_t* ws_bytes, void* bws, size_t bws_bytes,
+                      void* stream);
+
 typedef struct rich_retess_info {
   int32_t flags;      /* RICH_RETESS_* bits of the last rich_retess on ws   */
   int32_t sticky;     /* OR of the flags of every call since ws was zeroed  */
   int64_t n_edges;    /* edges and CSR entries of the last mesh             */
   int64_t n_csr;
   int64_t n_dropped;  /* degenerate edges left out                          */
-  double area_sum;    /* sum of the cell areas                              */
+  double area_sum;    /* sum of the cell areas (a check value, summed with
+                         atomics: its last bits vary from call to call)    */
 } rich_retess_info;
 
 /* Synchronise `stream` and read the header of ws.  Returns RICH_E_MESH when
  * the last call's flags are set, else RICH_OK. */
 int rich_retess_result(void* ws, void* stream, rich_retess_info* info);
+/* Synchronise `stream` and read the results of the last rich_retess_batch on
+ * bws: info[r] and status[r] (RICH_E_MESH when run r's flags are set) for
+ * its n runs. */
+int rich_retess_batch_result(int32_t n, void* bws, void* stream, rich_retess_info* info,
+                             int32_t* status);
 
 /*
  * Kernel timing for benchmarks.  While enabled, every stage records HIP

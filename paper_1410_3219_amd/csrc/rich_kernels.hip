@@ -1117,6 +1117,7 @@ struct rich_ctx {
   // device re-tessellation with the host stage as fallback
   bool device_tess = false;
   DevBuf rws;                 // rich_retess workspace (header zeroed at allocation)
+  DevBuf bws;                 // descriptors of a batched rebuild this context leads
   int64_t n_device = 0, n_fallback = 0;
 };
 
@@ -1132,11 +1133,8 @@ rich_state state_view(DevBuf& Q, DevBuf& X, int64_t n) {
   return s;
 }
 
-// Enqueue the device rebuild of the mesh of points (x, y) into dst, with
-// candidates from prev (retess_finish reads the outcome).
-int retess_enqueue(rich_ctx* c, const rich_mesh& prev, const double* x, const double* y,
-                   DevMesh& dst, hipStream_t st) {
-  const int64_t n = prev.n_cells;
+// Buffers of a device rebuild of run c's n-cell mesh into dst, described in out.
+int retess_prepare(rich_ctx* c, int64_t n, DevMesh& dst, hipStream_t st, rich_mesh_bufs& out) {
   int64_t ce = 0, cc = 0;
   size_t wsb = 0;
   if (rich_retess_capacity(n, &ce, &cc) || rich_retess_workspace_size(n, &wsb))
@@ -1149,7 +1147,6 @@ int retess_enqueue(rich_ctx* c, const rich_mesh& prev, const double* x, const do
     if (!c->rws.ensure(wsb)) return RICH_E_NOMEM;
     if (hipMemsetAsync(c->rws.p, 0, 256, st) != hipSuccess) return RICH_E_DEVICE;
   }
-  rich_mesh_bufs out;
   out.n_cells = n;
   out.cap_edges = (int64_t)(dst.b[1].cap / sizeof(rich_edge));
   out.cap_csr = std::min<int64_t>((int64_t)(dst.b[3].cap / 4), (int64_t)INT32_MAX - 1);
@@ -1159,28 +1156,31 @@ int retess_enqueue(rich_ctx* c, const rich_mesh& prev, const double* x, const do
   out.idx = (int32_t*)dst.b[3].p;
   out.eoff = (int32_t*)dst.b[4].p;
   dst.set = false;
-  return rich_retess(&prev, x, y, &out, c->rws.p, c->rws.cap, st);
+  return RICH_OK;
 }
 
-// Synchronise and take the rebuilt mesh into dst; RICH_E_MESH when the
-// device did not certify it.
-int retess_finish(rich_ctx* c, const rich_mesh& prev, DevMesh& dst, hipStream_t st) {
-  rich_retess_info info;
-  const int rc = rich_retess_result(c->rws.p, st, &info);
-  if (rc) return rc;
+// Take a certified rebuilt mesh (counts in info) into dst.
+void retess_adopt(const rich_mesh& prev, const rich_retess_info& info, DevMesh& dst) {
   dst.n = prev.n_cells;
   dst.ne = info.n_edges;
   dst.nc = info.n_csr;
   std::memcpy(dst.box, prev.box, sizeof(dst.box));
   dst.bc = prev.bc;
   dst.set = true;
-  return RICH_OK;
 }
 
+// The mesh of points (x, y) (device) into dst, rebuilt on the device with
+// candidates from prev.  RICH_E_MESH when the result is not certified.
 int retess_into(rich_ctx* c, const rich_mesh& prev, const double* x, const double* y,
                 DevMesh& dst, hipStream_t st) {
-  const int rc = retess_enqueue(c, prev, x, y, dst, st);
-  return rc ? rc : retess_finish(c, prev, dst, st);
+  rich_mesh_bufs out;
+  int rc = retess_prepare(c, prev.n_cells, dst, st, out);
+  if (rc) return rc;
+  if ((rc = rich_retess(&prev, x, y, &out, c->rws.p, c->rws.cap, st))) return rc;
+  rich_retess_info info;
+  if ((rc = rich_retess_result(c->rws.p, st, &info))) return rc;
+  retess_adopt(prev, info, dst);
+  return RICH_OK;
 }
 
 int tessellate_into(rich_ctx* c, DevMesh& dst, const double* dx, int64_t n, const double* box,
@@ -1556,6 +1556,7 @@ void rich_ctx_destroy(rich_ctx* ctx) {
   ctx->spare.release();
   ctx->third.release();
   ctx->rws.release();
+  ctx->bws.release();
   ctx->Qh.release(); ctx->Xh.release(); ctx->Qn.release(); ctx->Xn.release();
   ctx->ws.release();
   if (ctx->hostX) (void)hipHostFree(ctx->hostX);
@@ -1763,22 +1764,52 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
     auto dst_of = [&](int32_t r) -> DevMesh& {
       return half_step ? ctxs[r]->spare : ctxs[r]->third;
     };
-    std::vector<int32_t> enq;
-    for (int32_t r : dev) {
-      const int e = retess_enqueue(ctxs[r], mesh[r], xs[r].x, xs[r].y, dst_of(r), st);
-      if (e == RICH_E_DEVICE) return e;
-      if (e) status[r] = e;
-      else enq.push_back(r);
-    }
-    for (int32_t r : enq) {
-      const int e = retess_finish(ctxs[r], mesh[r], dst_of(r), st);
+    if (!dev.empty()) {
+      // one batched rebuild of every device run; runs whose arguments the
+      // device path does not take (a periodic box of under 16 cells) and
+      // uncertified meshes go to the host stage
+      const size_t m = dev.size();
+      std::vector<rich_mesh_bufs> ob(m);
+      std::vector<const rich_mesh*> pp(m);
+      std::vector<const rich_mesh_bufs*> op(m);
+      std::vector<const double*> xp(m), yp(m);
+      std::vector<void*> wp(m);
+      std::vector<size_t> wb(m);
+      for (size_t k = 0; k < m; ++k) {
+        const int32_t r = dev[k];
+        const int e = retess_prepare(ctxs[r], nc[r], dst_of(r), st, ob[k]);
+        if (e) return e;
+        pp[k] = &mesh[r];
+        op[k] = &ob[k];
+        xp[k] = xs[r].x;
+        yp[k] = xs[r].y;
+        wp[k] = ctxs[r]->rws.p;
+        wb[k] = ctxs[r]->rws.cap;
+      }
+      size_t bb = 0;
+      rich_ctx* owner = ctxs[dev[0]];   // holds the batch descriptors for this call
+      int e = rich_retess_batch_workspace_size((int32_t)m, &bb);
+      if (e) return e;
+      if (!owner->bws.ensure(bb)) return RICH_E_NOMEM;
+      e = rich_retess_batch((int32_t)m, pp.data(), xp.data(), yp.data(), op.data(), wp.data(),
+                            wb.data(), owner->bws.p, owner->bws.cap, st);
+      std::vector<rich_retess_info> info(m);
+      std::vector<int32_t> rs(m, RICH_E_MESH);
       if (e == RICH_OK) {
-        ++ctxs[r]->n_device;
-      } else if (e == RICH_E_MESH) {
-        ++ctxs[r]->n_fallback;
-        todo.push_back(r);
-      } else {
+        if ((e = rich_retess_batch_result((int32_t)m, owner->bws.p, st, info.data(), rs.data())))
+          return e;
+      } else if (e != RICH_E_INVAL) {
         return e;
+      }
+      for (size_t k = 0; k < m; ++k) {
+        const int32_t r = dev[k];
+        if (rs[k] == RICH_OK) {
+          retess_adopt(mesh[r], info[k], dst_of(r));
+          ++ctxs[r]->n_device;
+        } else {
+          ++ctxs[r]->n_fallback;
+          todo.push_back(r);
+        }
       }
     }
     if (todo.empty()) return RICH_OK;

@@ -34,6 +34,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "rich.h"
 
@@ -83,6 +84,42 @@ struct Args {
   int32_t n, bc, n_scan_blocks;
 };
 
+// Many runs in one launch: run r's descriptor is descs[r]; its blocks of
+// kThreads cells are cstart[r] .. cstart[r+1]-1 and its scan blocks of
+// kScanThreads cells sstart[r] .. sstart[r+1]-1; hdr_out[r] receives its
+// result header at the end.
+struct Batch {
+  const Args* descs;
+  const int32_t* cstart;
+  const int32_t* sstart;
+  Hdr* hdr_out;
+  int32_t n_runs;
+};
+
+// Run of block b in a start table of n_runs + 1 entries.
+__device__ __forceinline__ int run_of_block(const int32_t* __restrict__ start, int n_runs, int b) {
+  int lo = 0, hi = n_runs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The descriptor of this block's run and the block's index within the run.
+template <bool B>
+__device__ __forceinline__ const Args& block_run(const Args& one, const int32_t* start,
+                                                 const Batch& bt, int& blk) {
+  if (!B) {
+    blk = blockIdx.x;
+    return one;
+  }
+  const int r = run_of_block(start, bt.n_runs, blockIdx.x);
+  blk = blockIdx.x - start[r];
+  return bt.descs[r];
+}
+
 __device__ __forceinline__ int32_t pack(int cell, int code) {
   return (int32_t)((uint32_t)cell | ((uint32_t)code << kShift));
 }
@@ -118,7 +155,9 @@ __device__ __forceinline__ int prev_neighbour(const Args& a, int k) {
   return (int)((uint32_t)a.p_edges[e].j & kMask);
 }
 
-__global__ void k_rt_begin(Hdr* h) {
+template <bool B>
+__global__ void k_rt_begin(Hdr* one, Batch bt) {
+  Hdr* h = B ? bt.descs[blockIdx.x].hdr : one;
   if (threadIdx.x == 0) {
     h->flags = 0;
     h->n_edges = 0;
@@ -128,8 +167,13 @@ __global__ void k_rt_begin(Hdr* h) {
   }
 }
 
-__global__ void k_rt_end(Hdr* h) {
-  if (threadIdx.x == 0) h->sticky |= h->flags;
+template <bool B>
+__global__ void k_rt_end(Hdr* one, Batch bt) {
+  Hdr* h = B ? bt.descs[blockIdx.x].hdr : one;
+  if (threadIdx.x == 0) {
+    h->sticky |= h->flags;
+    if (B) bt.hdr_out[blockIdx.x] = *h;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -235,8 +279,11 @@ __device__ int clip(Poly& P, double dx, double dy, int32_t cid) {
   return 0;
 }
 
-__global__ __launch_bounds__(kThreads) void k_rt_clip(Args a) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
+template <bool B>
+__global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
+  int blk;
+  const Args& a = block_run<B>(one, bt.cstart, bt, blk);
+  const int i = blk * kThreads + threadIdx.x;
   if (i >= a.n) return;
   const double xi = a.x[i], yi = a.y[i];
   int bad = 0;
@@ -343,10 +390,13 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args a) {
 // ---------------------------------------------------------------------------
 // keep / own, certification, counts
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_rt_classify(Args a) {
+template <bool B>
+__global__ __launch_bounds__(kThreads) void k_rt_classify(Args one, Batch bt) {
+  int blk;
+  const Args& a = block_run<B>(one, bt.cstart, bt, blk);
   __shared__ double s_area[kThreads / 64];
   __shared__ long long s_drop[kThreads / 64];
-  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const int i = blk * kThreads + threadIdx.x;
   double area = 0.0;
   long long drop = 0;
   if (i < a.n) {
@@ -453,9 +503,12 @@ __device__ __forceinline__ void block_scan2(int& v0, int& v1, int* s0, int* s1, 
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_rt_scan_local(Args a) {
+template <bool B>
+__global__ __launch_bounds__(kScanThreads) void k_rt_scan_local(Args one, Batch bt) {
+  int blk;
+  const Args& a = block_run<B>(one, bt.sstart, bt, blk);
   __shared__ int s0[kScanThreads / 64], s1[kScanThreads / 64];
-  const int i = blockIdx.x * kScanThreads + threadIdx.x;
+  const int i = blk * kScanThreads + threadIdx.x;
   int v0 = i < a.n ? a.off[i + 1] : 0;
   int v1 = i < a.n ? a.eoff[i + 1] : 0;
   int t0, t1;
@@ -465,14 +518,16 @@ __global__ __launch_bounds__(kScanThreads) void k_rt_scan_local(Args a) {
     a.eoff[i + 1] = v1;
   }
   if (threadIdx.x == 0) {
-    a.bsum[blockIdx.x] = t0;
-    a.bsum[a.n_scan_blocks + blockIdx.x] = t1;
+    a.bsum[blk] = t0;
+    a.bsum[a.n_scan_blocks + blk] = t1;
   }
 }
 
 // one block: exclusive scan of the block totals, totals and the checks that
 // need every cell (areas, capacities)
-__global__ __launch_bounds__(kScanThreads) void k_rt_scan_blocks(Args a) {
+template <bool B>
+__global__ __launch_bounds__(kScanThreads) void k_rt_scan_blocks(Args one, Batch bt) {
+  const Args& a = B ? bt.descs[blockIdx.x] : one;
   __shared__ long long s0[kScanThreads], s1[kScanThreads];
   const int nb = a.n_scan_blocks;
   const int per = (nb + kScanThreads - 1) / kScanThreads;
@@ -515,23 +570,29 @@ __global__ __launch_bounds__(kScanThreads) void k_rt_scan_blocks(Args a) {
   }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_rt_scan_add(Args a) {
-  const int i = blockIdx.x * kScanThreads + threadIdx.x;
+template <bool B>
+__global__ __launch_bounds__(kScanThreads) void k_rt_scan_add(Args one, Batch bt) {
+  int blk;
+  const Args& a = block_run<B>(one, bt.sstart, bt, blk);
+  const int i = blk * kScanThreads + threadIdx.x;
   if (i == 0) {
     a.off[0] = 0;
     a.eoff[0] = 0;
   }
   if (i < a.n) {
-    a.off[i + 1] += (int32_t)a.bsum[blockIdx.x];
-    a.eoff[i + 1] += (int32_t)a.bsum[a.n_scan_blocks + blockIdx.x];
+    a.off[i + 1] += (int32_t)a.bsum[blk];
+    a.eoff[i + 1] += (int32_t)a.bsum[a.n_scan_blocks + blk];
   }
 }
 
 // ---------------------------------------------------------------------------
 // edge records and CSR entries
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_rt_emit(Args a) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
+template <bool B>
+__global__ __launch_bounds__(kThreads) void k_rt_emit(Args one, Batch bt) {
+  int blk;
+  const Args& a = block_run<B>(one, bt.cstart, bt, blk);
+  const int i = blk * kThreads + threadIdx.x;
   if (i >= a.n) return;
   if (a.hdr->flags != 0) {  // failed: leave a mesh without edges
     a.off[i + 1] = 0;
@@ -620,26 +681,10 @@ void rt_capacity(int64_t n, int64_t* ce, int64_t* cc) {
   *cc = 2 * *ce;
 }
 
-}  // namespace
-
-extern "C" {
-
-int rich_retess_capacity(int64_t n_cells, int64_t* cap_edges, int64_t* cap_csr) {
-  if (n_cells <= 0 || n_cells > (int64_t)retess::kMask || !cap_edges || !cap_csr)
-    return RICH_E_INVAL;
-  rt_capacity(n_cells, cap_edges, cap_csr);
-  if (*cap_csr >= (int64_t)INT32_MAX) return RICH_E_INVAL;
-  return RICH_OK;
-}
-
-int rich_retess_workspace_size(int64_t n_cells, size_t* bytes) {
-  if (n_cells <= 0 || n_cells > (int64_t)retess::kMask || !bytes) return RICH_E_INVAL;
-  *bytes = rt_layout(n_cells).total;
-  return RICH_OK;
-}
-
-int rich_retess(const rich_mesh* prev, const double* x, const double* y,
-                const rich_mesh_bufs* out, void* ws, size_t ws_bytes, void* stream) {
+// Checks one run's arguments and fills its descriptor; RICH_OK or the status.
+int make_args(const rich_mesh* prev, const double* x, const double* y,
+              const rich_mesh_bufs* out, void* ws, size_t ws_bytes, retess::Args& a,
+              RtLayout& L) {
   if (!prev || !x || !y || !out || !ws) return RICH_E_INVAL;
   const int64_t n = prev->n_cells;
   if (n <= 0 || n > (int64_t)retess::kMask || out->n_cells != n) return RICH_E_INVAL;
@@ -658,11 +703,10 @@ int rich_retess(const rich_mesh* prev, const double* x, const double* y,
     return RICH_E_INVAL;
   if (prev->bc != RICH_BOUNDARY_WALLS && prev->bc != RICH_BOUNDARY_PERIODIC) return RICH_E_INVAL;
   if (prev->bc == RICH_BOUNDARY_PERIODIC && n < 16) return RICH_E_INVAL;
-  const RtLayout L = rt_layout(n);
+  L = rt_layout(n);
   if (ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return RICH_E_NOMEM;
 
   char* w = static_cast<char*>(ws);
-  retess::Args a;
   std::memset(&a, 0, sizeof(a));
   a.p_off = prev->off;
   a.p_idx = prev->idx;
@@ -693,17 +737,58 @@ int rich_retess(const rich_mesh* prev, const double* x, const double* y,
   a.n = (int32_t)n;
   a.bc = (int32_t)prev->bc;
   a.n_scan_blocks = L.nb;
+  return RICH_OK;
+}
 
+// The eight launches of one re-tessellation (B: of n_runs runs at once, with
+// gc cell blocks and gs scan blocks in all).
+template <bool B>
+void launch_all(const retess::Args& a, const retess::Batch& bt, int gc, int gs, int n_runs,
+                hipStream_t st) {
+  using namespace retess;
+  hipLaunchKernelGGL(k_rt_begin<B>, dim3(n_runs), dim3(64), 0, st, a.hdr, bt);
+  hipLaunchKernelGGL(k_rt_clip<B>, dim3(gc), dim3(kThreads), 0, st, a, bt);
+  hipLaunchKernelGGL(k_rt_classify<B>, dim3(gc), dim3(kThreads), 0, st, a, bt);
+  hipLaunchKernelGGL(k_rt_scan_local<B>, dim3(gs), dim3(kScanThreads), 0, st, a, bt);
+  hipLaunchKernelGGL(k_rt_scan_blocks<B>, dim3(n_runs), dim3(kScanThreads), 0, st, a, bt);
+  hipLaunchKernelGGL(k_rt_scan_add<B>, dim3(gs), dim3(kScanThreads), 0, st, a, bt);
+  hipLaunchKernelGGL(k_rt_emit<B>, dim3(gc), dim3(kThreads), 0, st, a, bt);
+  hipLaunchKernelGGL(k_rt_end<B>, dim3(n_runs), dim3(64), 0, st, a.hdr, bt);
+}
+
+size_t batch_bytes(int32_t n) {
+  return rt_align(sizeof(retess::Args) * (size_t)n) + rt_align(8 * ((size_t)n + 1)) +
+         rt_align(sizeof(retess::Hdr) * (size_t)n);
+}
+
+}  // namespace
+
+extern "C" {
+
+int rich_retess_capacity(int64_t n_cells, int64_t* cap_edges, int64_t* cap_csr) {
+  if (n_cells <= 0 || n_cells > (int64_t)retess::kMask || !cap_edges || !cap_csr)
+    return RICH_E_INVAL;
+  rt_capacity(n_cells, cap_edges, cap_csr);
+  if (*cap_csr >= (int64_t)INT32_MAX) return RICH_E_INVAL;
+  return RICH_OK;
+}
+
+int rich_retess_workspace_size(int64_t n_cells, size_t* bytes) {
+  if (n_cells <= 0 || n_cells > (int64_t)retess::kMask || !bytes) return RICH_E_INVAL;
+  *bytes = rt_layout(n_cells).total;
+  return RICH_OK;
+}
+
+int rich_retess(const rich_mesh* prev, const double* x, const double* y,
+                const rich_mesh_bufs* out, void* ws, size_t ws_bytes, void* stream) {
+  retess::Args a;
+  RtLayout L;
+  const int rc = make_args(prev, x, y, out, ws, ws_bytes, a, L);
+  if (rc) return rc;
+  const int64_t n = prev->n_cells;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int gc = (int)((n + retess::kThreads - 1) / retess::kThreads);
-  hipLaunchKernelGGL(retess::k_rt_begin, dim3(1), dim3(64), 0, st, a.hdr);
-  hipLaunchKernelGGL(retess::k_rt_clip, dim3(gc), dim3(retess::kThreads), 0, st, a);
-  hipLaunchKernelGGL(retess::k_rt_classify, dim3(gc), dim3(retess::kThreads), 0, st, a);
-  hipLaunchKernelGGL(retess::k_rt_scan_local, dim3(L.nb), dim3(retess::kScanThreads), 0, st, a);
-  hipLaunchKernelGGL(retess::k_rt_scan_blocks, dim3(1), dim3(retess::kScanThreads), 0, st, a);
-  hipLaunchKernelGGL(retess::k_rt_scan_add, dim3(L.nb), dim3(retess::kScanThreads), 0, st, a);
-  hipLaunchKernelGGL(retess::k_rt_emit, dim3(gc), dim3(retess::kThreads), 0, st, a);
-  hipLaunchKernelGGL(retess::k_rt_end, dim3(1), dim3(64), 0, st, a.hdr);
+  launch_all<false>(a, retess::Batch{}, gc, L.nb, 1, st);
   return hipGetLastError() == hipSuccess ? RICH_OK : RICH_E_DEVICE;
 }
 
@@ -720,6 +805,77 @@ int rich_retess_view(const rich_mesh_bufs* out, const double box[4], uint32_t bc
   m->eoff = out->eoff;
   for (int k = 0; k < 4; ++k) m->box[k] = box[k];
   m->bc = bc;
+  return RICH_OK;
+}
+
+int rich_retess_batch_workspace_size(int32_t n, size_t* bytes) {
+  if (n <= 0 || !bytes) return RICH_E_INVAL;
+  *bytes = batch_bytes(n);
+  return RICH_OK;
+}
+
+int rich_retess_batch(int32_t n, const rich_mesh* const* prev, const double* const* x,
+                      const double* const* y, const rich_mesh_bufs* const* out,
+                      void* const* ws, const size_t* ws_bytes, void* bws, size_t bws_bytes,
+                      void* stream) {
+  if (n <= 0 || !prev || !x || !y || !out || !ws || !ws_bytes || !bws) return RICH_E_INVAL;
+  if (bws_bytes < batch_bytes(n) || (reinterpret_cast<uintptr_t>(bws) & 255)) return RICH_E_NOMEM;
+  std::vector<retess::Args> args((size_t)n);
+  std::vector<int32_t> starts(2 * ((size_t)n + 1));
+  int64_t gc = 0, gs = 0;
+  for (int32_t r = 0; r < n; ++r) {
+    RtLayout L;
+    const int rc = make_args(prev[r], x[r], y[r], out[r], ws[r], ws_bytes[r], args[r], L);
+    if (rc) return rc;
+    for (int32_t q = 0; q < r; ++q)
+      if (ws[q] == ws[r]) return RICH_E_INVAL;   // runs need workspaces of their own
+    starts[r] = (int32_t)gc;
+    starts[n + 1 + r] = (int32_t)gs;
+    gc += (prev[r]->n_cells + retess::kThreads - 1) / retess::kThreads;
+    gs += L.nb;
+    if (gc >= INT32_MAX / 2 || gs >= INT32_MAX / 2) return RICH_E_INVAL;
+  }
+  starts[n] = (int32_t)gc;
+  starts[2 * (size_t)n + 1] = (int32_t)gs;
+  char* b = static_cast<char*>(bws);
+  const size_t o_start = rt_align(sizeof(retess::Args) * (size_t)n);
+  const size_t o_hdr = o_start + rt_align(8 * ((size_t)n + 1));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // the host arrays die with this call: upload, then wait for the copies
+  if (hipMemcpyAsync(b, args.data(), sizeof(retess::Args) * (size_t)n, hipMemcpyHostToDevice,
+                     st) != hipSuccess ||
+      hipMemcpyAsync(b + o_start, starts.data(), starts.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return RICH_E_DEVICE;
+  retess::Batch bt;
+  bt.descs = reinterpret_cast<const retess::Args*>(b);
+  bt.cstart = reinterpret_cast<const int32_t*>(b + o_start);
+  bt.sstart = bt.cstart + n + 1;
+  bt.hdr_out = reinterpret_cast<retess::Hdr*>(b + o_hdr);
+  bt.n_runs = n;
+  launch_all<true>(args[0], bt, (int)gc, (int)gs, n, st);
+  return hipGetLastError() == hipSuccess ? RICH_OK : RICH_E_DEVICE;
+}
+
+int rich_retess_batch_result(int32_t n, void* bws, void* stream, rich_retess_info* info,
+                             int32_t* status) {
+  if (n <= 0 || !bws || !info || !status) return RICH_E_INVAL;
+  const size_t o_hdr = rt_align(sizeof(retess::Args) * (size_t)n) + rt_align(8 * ((size_t)n + 1));
+  std::vector<retess::Hdr> h((size_t)n);
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess ||
+      hipMemcpy(h.data(), static_cast<char*>(bws) + o_hdr, sizeof(retess::Hdr) * (size_t)n,
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return RICH_E_DEVICE;
+  for (int32_t r = 0; r < n; ++r) {
+    info[r].flags = h[r].flags;
+    info[r].sticky = h[r].sticky;
+    info[r].n_edges = h[r].n_edges;
+    info[r].n_csr = h[r].n_csr;
+    info[r].n_dropped = h[r].n_dropped;
+    info[r].area_sum = h[r].area_sum;
+    status[r] = h[r].flags ? RICH_E_MESH : RICH_OK;
+  }
   return RICH_OK;
 }
 

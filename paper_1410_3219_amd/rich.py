@@ -140,6 +140,12 @@ def lib():
         L.rich_retess.argtypes = [mp, _vp, _vp, C.POINTER(RichMeshBufs), _vp, C.c_size_t, _vp]
         L.rich_retess_view.argtypes = [C.POINTER(RichMeshBufs), _dp, C.c_uint32, mp]
         L.rich_retess_result.argtypes = [_vp, _vp, C.POINTER(RichRetessInfo)]
+        L.rich_retess_batch_workspace_size.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
+        L.rich_retess_batch.argtypes = [C.c_int32, C.POINTER(_vp), C.POINTER(_vp),
+                                        C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),
+                                        C.POINTER(C.c_size_t), _vp, C.c_size_t, _vp]
+        L.rich_retess_batch_result.argtypes = [C.c_int32, _vp, _vp, C.POINTER(RichRetessInfo),
+                                               _ip]
         L.rich_mesh_pack.argtypes = [C.POINTER(HostMeshView), _vp, _vp]
         L.rich_mesh_pack.restype = C.c_int
         L.rich_strerror.argtypes = [C.c_int]
@@ -149,7 +155,8 @@ def lib():
         for f in ("rich_workspace_size", "rich_stage", "rich_stage_flags", "rich_cfl_dt",
                   "rich_stage_courant", "rich_stage_dt_of", "rich_stage_dt", "rich_area_rate",
                   "rich_retess_capacity", "rich_retess_workspace_size", "rich_retess",
-                  "rich_retess_view", "rich_retess_result",
+                  "rich_retess_view", "rich_retess_result", "rich_retess_batch_workspace_size",
+                  "rich_retess_batch", "rich_retess_batch_result",
                   "rich_profile_enable", "rich_profile_read"):
             getattr(L, f).restype = C.c_int
         if hasattr(L, "rich_stage_batch"):
@@ -431,6 +438,41 @@ def rich_retess_result(ws, stream=None):
         _check(st, "rich_retess_result")
     return st, {"flags": info.flags, "sticky": info.sticky, "n_edges": info.n_edges,
                 "n_csr": info.n_csr, "n_dropped": info.n_dropped, "area_sum": info.area_sum}
+
+
+def rich_retess_batch(prevs, Xs, bufs, wss, bws=None, stream=None):
+    """Re-tessellate several runs in one launch per kernel; returns the batch
+    workspace to pass to rich_retess_batch_result."""
+    import torch
+    n = len(prevs)
+    if bws is None:
+        b = C.c_size_t(0)
+        _check(lib().rich_retess_batch_workspace_size(n, C.byref(b)),
+               "rich_retess_batch_workspace_size")
+        bws = torch.empty(int(b.value), dtype=torch.uint8, device=Xs[0].device)
+    Xs = [X if X.is_contiguous() else X.contiguous() for X in Xs]
+    ad = C.addressof
+    pm = (_vp * n)(*[ad(m.c()) for m in prevs])
+    xp = (_vp * n)(*[X.data_ptr() for X in Xs])
+    yp = (_vp * n)(*[X.data_ptr() + 8 * m.n_cells for X, m in zip(Xs, prevs)])
+    op = (_vp * n)(*[ad(b_.c()) for b_ in bufs])
+    wp = (_vp * n)(*[w.data_ptr() for w in wss])
+    wb = (C.c_size_t * n)(*[w.numel() for w in wss])
+    _check(lib().rich_retess_batch(n, pm, xp, yp, op, wp, wb, C.c_void_p(bws.data_ptr()),
+                                   bws.numel(), _stream_ptr(stream)), "rich_retess_batch")
+    return bws
+
+
+def rich_retess_batch_result(n, bws, stream=None):
+    """[(status, info dict)] of the runs of the last rich_retess_batch on bws."""
+    info = (RichRetessInfo * n)()
+    st = (C.c_int32 * n)()
+    _check(lib().rich_retess_batch_result(n, C.c_void_p(bws.data_ptr()), _stream_ptr(stream),
+                                          info, st), "rich_retess_batch_result")
+    return [(int(st[r]), {"flags": info[r].flags, "sticky": info[r].sticky,
+                          "n_edges": info[r].n_edges, "n_csr": info[r].n_csr,
+                          "n_dropped": info[r].n_dropped, "area_sum": info[r].area_sum})
+            for r in range(n)]
 
 
 def mesh_to_host(dm: DeviceMesh, n_edges=None, n_csr=None):

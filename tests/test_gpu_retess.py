@@ -442,3 +442,55 @@ def _hex(k, bc):
             xs.append((c + 0.5 * (rr % 2) + 0.25) * a)
             ys.append((rr + 0.5) * a * math.sqrt(3.0) / 2.0)
     return np.array(xs), np.array(ys), (0.0, 0.0, 1.0, k * a * math.sqrt(3.0) / 2.0)
+
+
+def test_retess_batch_equals_single_runs_bitwise():
+    """rich_retess_batch over runs of different sizes and boundaries: every
+    run's mesh and result equal its own rich_retess bit for bit; a run whose
+    candidates are wrong fails alone."""
+    from paper_1410_3219_amd import rich as R
+    import torch
+    cases = [("sod", 13), ("wave", 21), ("sedov", 17), ("kh", 9), ("gresho", 25)]
+    prevs, Xs, ns = [], [], []
+    for r, (name, k) in enumerate(cases):
+        P, m, Q, X = _initial(name, k, seed=r + 2)
+        dm = R.DeviceMesh.from_host(m)
+        p = R.Params(gamma=P.gamma)
+        _, half = _half_step_points(R, dm, Q, X, p)
+        if r == 3:   # candidates from a mesh of permuted points: not certified
+            perm = np.random.default_rng(1).permutation(m.n_cells)
+            dm = R.DeviceMesh.from_host(T.rich_tess_build(m.px[perm], m.py[perm], m.box, m.bc))
+        prevs.append(dm)
+        Xs.append(half.X)
+        ns.append(m.n_cells)
+    single = []
+    for dm, X, n in zip(prevs, Xs, ns):
+        b = R.DeviceMeshBufs(n, dm.box, dm.bc)
+        w = R.retess_workspace(n)
+        R.rich_retess(dm, X, b, w)
+        single.append((R.rich_retess_result(w), {k: v.cpu() for k, v in b.t.items()}))
+    bufs = [R.DeviceMeshBufs(n, dm.box, dm.bc) for dm, n in zip(prevs, ns)]
+    wss = [R.retess_workspace(n) for n in ns]
+    bws = R.rich_retess_batch(prevs, Xs, bufs, wss)
+    res = R.rich_retess_batch_result(len(prevs), bws)
+    def same(i1, i2):   # the area sum is a check value summed with atomics
+        a1, a2 = dict(i1), dict(i2)
+        return abs(a1.pop("area_sum") - a2.pop("area_sum")) < 1e-13 and a1 == a2
+
+    for r, ((st1, info1), t1) in enumerate(single):
+        st2, info2 = res[r]
+        assert st1 == st2 and same(info1, info2), (r, info1, info2)
+        st3, info3 = R.rich_retess_result(wss[r])
+        assert st3 == st2 and same(info3, info2)
+        if r == 3:
+            assert st2 == R.RICH_E_MESH
+            continue
+        assert st2 == 0
+        ne, nc = info2["n_edges"], info2["n_csr"]
+        t2 = {k: v.cpu() for k, v in bufs[r].t.items()}
+        for key, lim in (("cells", None), ("off", None), ("eoff", None), ("edges", 32 * ne),
+                         ("idx", nc)):
+            a, b = t1[key].numpy(), t2[key].numpy()
+            if lim is not None:
+                a, b = a[:lim], b[:lim]
+            assert np.array_equal(a, b), (r, key)
