@@ -224,15 +224,20 @@ def bench_batch(args, R, T, log):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         res[name] = {"ms_per_step": ms, "cell_updates_per_s": total / (ms / 1e3)}
-    # the same step as prepared plans whose launches are captured once in a
-    # HIP graph and replayed (no host marshalling, no descriptor upload)
+    # edge-tile shape autotuned on these runs (each stage of the step on its
+    # own mesh), then the step as prepared plans with the tuned tiles whose
+    # launches are captured once in a HIP graph and replayed (no host
+    # marshalling, no descriptor upload)
     wsg = R.batch_workspace([r["hm"].n_cells for r in runs])
-    p1 = R.rich_stage_batch_prepare([r["dm"] for r in runs], [r["s0"] for r in runs],
-                                    [r["s0"] for r in runs], [r["half"] for r in runs],
-                                    [0.5 * r["dt"] for r in runs], [r["p"] for r in runs], wsb)
-    p2 = R.rich_stage_batch_prepare([r["dmh"] for r in runs], [r["half"] for r in runs],
-                                    [r["s0"] for r in runs], [r["out"] for r in runs],
-                                    [r["dt"] for r in runs], [r["p"] for r in runs], wsg)
+    a1 = ([r["dm"] for r in runs], [r["s0"] for r in runs], [r["s0"] for r in runs],
+          [r["half"] for r in runs], [0.5 * r["dt"] for r in runs], [r["p"] for r in runs])
+    a2 = ([r["dmh"] for r in runs], [r["half"] for r in runs], [r["s0"] for r in runs],
+          [r["out"] for r in runs], [r["dt"] for r in runs], [r["p"] for r in runs])
+    tile1, ms1 = R.rich_stage_batch_autotune(*a1, wsb, reps=3)
+    tile2, ms2 = R.rich_stage_batch_autotune(*a2, wsg, reps=3)
+    log(f"[bench] batch tile autotune: stage 1 {ms1} -> {tile1}, stage 2 {ms2} -> {tile2}")
+    p1 = R.rich_stage_batch_prepare_tile(*a1, tile1, wsb)
+    p2 = R.rich_stage_batch_prepare_tile(*a2, tile2, wsg)
     torch.cuda.synchronize()
     gs = torch.cuda.Stream()
     gs.wait_stream(torch.cuda.current_stream())
@@ -259,7 +264,9 @@ def bench_batch(args, R, T, log):
     gms = e0.elapsed_time(e1) / reps
     res["graph_replay"] = {"ms_per_step": gms, "cell_updates_per_s": total / (gms / 1e3),
                            "bitwise_equal_to_eager": all(torch.equal(r["out"].Q, w)
-                                                         for r, w in zip(runs, want))}
+                                                         for r, w in zip(runs, want)),
+                           "flux_tiles": [tile1, tile2],
+                           "autotune_ms_per_stage": {"stage1": ms1, "stage2": ms2}}
     del graph
     flags = R.rich_batch_flags(len(runs), wsb)
     return {"runs": len(runs), "cells": total, "flags_ok": not any(flags),

@@ -235,6 +235,7 @@ typedef struct rich_batch_plan {
   int32_t n_group[2];       /* number of HLLC runs, of exact-solver runs        */
   int32_t grid_cell;        /* persistent grid of the cell kernel              */
   int32_t grid_flux[2];     /* persistent grids of the two flux kernels        */
+  int32_t flux_tile;        /* cells per flux tile (edge-tile shape)           */
 } rich_batch_plan;
 int rich_stage_batch_prepare(int32_t n, const rich_mesh* const* meshes,
                              const rich_state* const* src, const rich_state* const* base,
@@ -242,6 +243,28 @@ int rich_stage_batch_prepare(int32_t n, const rich_mesh* const* meshes,
                              const rich_params* const* params, void* ws, size_t ws_bytes,
                              void* stream, rich_batch_plan* plan);
 int rich_stage_batch_launch(const rich_batch_plan* plan, void* ws, void* stream);
+/* As rich_stage_batch_prepare, with flux tiles of `tile` cells (128, 256 or
+ * 512; rich_stage_batch_prepare takes 256).  A tile is a group of
+ * consecutive cells whose owned edges one workgroup solves; the results do
+ * not depend on it, bit for bit (each edge's flux is computed with the same
+ * arithmetic wherever it is computed, and each cell sums its edges in CSR
+ * order). */
+int rich_stage_batch_prepare_tile(int32_t n, const rich_mesh* const* meshes,
+                                  const rich_state* const* src, const rich_state* const* base,
+                                  rich_state* const* out, const double* h,
+                                  const rich_params* const* params, int32_t tile, void* ws,
+                                  size_t ws_bytes, void* stream, rich_batch_plan* plan);
+/* Autotune the edge-tile shape of a batched stage: prepares and times (HIP
+ * events, `reps` launches after one warm-up) the stage with each tile of
+ * 128, 256 and 512 cells on these runs, writing the mean milliseconds per
+ * launch into ms[3] and the fastest tile into *best_tile.  Runs the stage
+ * 3 * (reps + 1) times (out is written each time; src and base are only
+ * read) and synchronises `stream`. */
+int rich_stage_batch_autotune(int32_t n, const rich_mesh* const* meshes,
+                              const rich_state* const* src, const rich_state* const* base,
+                              rich_state* const* out, const double* h,
+                              const rich_params* const* params, int32_t reps, void* ws,
+                              size_t ws_bytes, void* stream, int32_t* best_tile, double* ms);
 
 /* Synchronise and read the n per-run flag words of the last batched stage. */
 int rich_batch_flags(int32_t n, void* ws, void* stream, int32_t* flags);

@@ -56,10 +56,7 @@ namespace rich {
 #ifndef RICH_FLUX_TILE
 #define RICH_FLUX_TILE 256
 #endif
-constexpr int kTile = RICH_FLUX_TILE;          // k_flux: cells per tile = threads per block
-constexpr int kEdgeCap = kTile * 25 / 8;       // k_flux: owned-edge fluxes kept in LDS
-constexpr int kForCap = kTile * 3 / 4;         // k_flux: other edges kept in LDS
-constexpr int kMapCap = kTile * 9;             // k_flux: CSR entries classified in LDS
+constexpr int kTile = RICH_FLUX_TILE;          // k_flux: default cells per tile = threads per block
 constexpr int kCellThreads = 256;   // k_cell: threads per block
 constexpr int kLpc = RICH_LPC;      // k_cell: lanes per cell
 constexpr int kNumXcd = 8;
@@ -518,22 +515,26 @@ __device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF
   return edge_flux_at<RIEMANN>(d, i, ej, er.fx, er.fy, er.L, rix, riy, ri, rj, LF);
 }
 
-template <int RIEMANN, bool BATCH>
-__global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, const RunDesc* __restrict__ descs,
+template <int RIEMANN, bool BATCH, int TILE = kTile>
+__global__ __launch_bounds__(TILE, RICH_FLUX_WAVES) void k_flux(RunDesc one, const RunDesc* __restrict__ descs,
                                                 const int32_t* __restrict__ tile_start,
                                                 int n_runs, int n_tiles) {
+  // LDS capacities in proportion to the tile: fluxes of the owned edges
+  // (about 3 per cell), of other edges the tile's cells need (its border),
+  // and the classification of the tile's CSR entries (about 6 per cell)
+  constexpr int kEdgeCap = TILE * 25 / 8, kForCap = TILE * 3 / 4, kMapCap = TILE * 9;
   __shared__ double sF[4][kEdgeCap + kForCap];
   __shared__ int s_forE[kForCap];
   __shared__ short s_map[kMapCap];  // (flux slot << 1) | side, or -1
-  __shared__ int s_off[kTile + 1];  // the tile's CSR offsets
+  __shared__ int s_off[TILE + 1];  // the tile's CSR offsets
   __shared__ int s_nfor;
   const int tid = (int)threadIdx.x;
   for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
     const int t = xcd_tile(b, n_tiles);
     const int pos = BATCH ? find_run(tile_start, n_runs, t) : 0;
     const RunDesc& d = BATCH ? descs[tile_start[n_runs + 1 + pos]] : one;
-    const int c0 = (t - (BATCH ? tile_start[pos] : 0)) * kTile;
-    const int c1 = min(c0 + kTile, d.n);
+    const int c0 = (t - (BATCH ? tile_start[pos] : 0)) * TILE;
+    const int c1 = min(c0 + TILE, d.n);
     const int e0 = d.eoff[c0];
     const int ne = max(0, min(d.eoff[c1] - e0, kEdgeCap));
     const int kb = d.off[c0];
@@ -541,20 +542,20 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
     const int Sm = min(S, kMapCap);
     bool ok = true;
     if (tid == 0) s_nfor = 0;
-    for (int c = tid; c <= c1 - c0; c += kTile) s_off[c] = d.off[c0 + c];
+    for (int c = tid; c <= c1 - c0; c += TILE) s_off[c] = d.off[c0 + c];
     __syncthreads();
     // all of a lane's CSR entries are loaded first (independent loads in
     // flight together), then classified
-    constexpr int MPT = kMapCap / kTile;
+    constexpr int MPT = kMapCap / TILE;
     int ent[MPT];
 #pragma unroll
     for (int r = 0; r < MPT; ++r) {
-      const int s = tid + r * kTile;
+      const int s = tid + r * TILE;
       ent[r] = s < Sm ? d.idx[kb + s] : -1;
     }
 #pragma unroll
     for (int r = 0; r < MPT; ++r) {
-      const int s = tid + r * kTile;
+      const int s = tid + r * TILE;
       if (s >= Sm) break;
       const int entry = ent[r];
       const int e = entry >> 1;
@@ -572,7 +573,7 @@ __global__ __launch_bounds__(kTile, RICH_FLUX_WAVES) void k_flux(RunDesc one, co
     }
     __syncthreads();
     const int nfor = min(s_nfor, kForCap);
-    for (int w = tid; w < ne + nfor; w += kTile) {
+    for (int w = tid; w < ne + nfor; w += TILE) {
       const int e = w < ne ? e0 + w : s_forE[w - ne];
       const int pos = w < ne ? w : kEdgeCap + (w - ne);
       double LF[4];
@@ -1011,6 +1012,19 @@ int upload_staged(void* dst1, const void* src1, size_t b1, void* dst2, const voi
   return RICH_OK;
 }
 
+// The batched flux kernel of solver k (0 HLLC, 1 exact) with tiles of `tile` cells.
+void launch_flux_batch(int k, int tile, int grid, hipStream_t st, const RunDesc& dummy,
+                       const RunDesc* dd, const int32_t* dpf, int n_group, int n_tiles) {
+  switch (k * 4 + (tile == 128 ? 0 : tile == 256 ? 1 : 2)) {
+    case 0: hipLaunchKernelGGL((rich::k_flux<0, true, 128>), dim3(grid), dim3(128), 0, st, dummy, dd, dpf, n_group, n_tiles); break;
+    case 1: hipLaunchKernelGGL((rich::k_flux<0, true, 256>), dim3(grid), dim3(256), 0, st, dummy, dd, dpf, n_group, n_tiles); break;
+    case 2: hipLaunchKernelGGL((rich::k_flux<0, true, 512>), dim3(grid), dim3(512), 0, st, dummy, dd, dpf, n_group, n_tiles); break;
+    case 4: hipLaunchKernelGGL((rich::k_flux<1, true, 128>), dim3(grid), dim3(128), 0, st, dummy, dd, dpf, n_group, n_tiles); break;
+    case 5: hipLaunchKernelGGL((rich::k_flux<1, true, 256>), dim3(grid), dim3(256), 0, st, dummy, dd, dpf, n_group, n_tiles); break;
+    default: hipLaunchKernelGGL((rich::k_flux<1, true, 512>), dim3(grid), dim3(512), 0, st, dummy, dd, dpf, n_group, n_tiles); break;
+  }
+}
+
 int resident_blocks(const void* kernel, int threads) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1024;
@@ -1368,8 +1382,18 @@ int rich_stage_batch_prepare(int32_t n, const rich_mesh* const* meshes,
                              rich_state* const* out, const double* h,
                              const rich_params* const* params, void* ws, size_t ws_bytes,
                              void* stream, rich_batch_plan* plan) {
+  return rich_stage_batch_prepare_tile(n, meshes, src, base, out, h, params, rich::kTile, ws,
+                                       ws_bytes, stream, plan);
+}
+
+int rich_stage_batch_prepare_tile(int32_t n, const rich_mesh* const* meshes,
+                                  const rich_state* const* src, const rich_state* const* base,
+                                  rich_state* const* out, const double* h,
+                                  const rich_params* const* params, int32_t tile, void* ws,
+                                  size_t ws_bytes, void* stream, rich_batch_plan* plan) {
   if (n <= 0 || !meshes || !src || !base || !out || !h || !params || !ws || !plan)
     return RICH_E_INVAL;
+  if (tile != 128 && tile != 256 && tile != 512) return RICH_E_INVAL;
   std::memset(plan, 0, sizeof(*plan));
   std::vector<int64_t> nc(n);
   for (int32_t r = 0; r < n; ++r) {
@@ -1420,7 +1444,7 @@ int rich_stage_batch_prepare(int32_t n, const rich_mesh* const* meshes,
       const int32_t r = (*grp[k])[q];
       pf[k][q] = (int32_t)tf[k];
       pf[k][ng + 1 + q] = r;
-      tf[k] += (nc[r] + rich::kTile - 1) / rich::kTile;
+      tf[k] += (nc[r] + tile - 1) / tile;
     }
     pf[k][ng] = (int32_t)tf[k];
   }
@@ -1432,10 +1456,16 @@ int rich_stage_batch_prepare(int32_t n, const rich_mesh* const* meshes,
 
   static const int cell_grid = resident_blocks(
       reinterpret_cast<const void*>(&rich::k_cell<rich::kLpc, true>), rich::kCellThreads);
-  static const int flux0_grid = resident_blocks(
-      reinterpret_cast<const void*>(&rich::k_flux<0, true>), rich::kTile);
-  static const int flux1_grid = resident_blocks(
-      reinterpret_cast<const void*>(&rich::k_flux<1, true>), rich::kTile);
+  static const int flux_grid[3][2] = {
+      {resident_blocks(reinterpret_cast<const void*>(&rich::k_flux<0, true, 128>), 128),
+       resident_blocks(reinterpret_cast<const void*>(&rich::k_flux<1, true, 128>), 128)},
+      {resident_blocks(reinterpret_cast<const void*>(&rich::k_flux<0, true, 256>), 256),
+       resident_blocks(reinterpret_cast<const void*>(&rich::k_flux<1, true, 256>), 256)},
+      {resident_blocks(reinterpret_cast<const void*>(&rich::k_flux<0, true, 512>), 512),
+       resident_blocks(reinterpret_cast<const void*>(&rich::k_flux<1, true, 512>), 512)}};
+  const int ti = tile == 128 ? 0 : (tile == 256 ? 1 : 2);
+  const int flux0_grid = flux_grid[ti][0], flux1_grid = flux_grid[ti][1];
+  plan->flux_tile = tile;
   plan->n_runs = n;
   plan->n_cell_tiles = (int32_t)tc;
   plan->n_flux_tiles[0] = (int32_t)tf[0];
@@ -1470,14 +1500,56 @@ int rich_stage_batch_launch(const rich_batch_plan* plan, void* ws, void* stream)
                      dim3(rich::kCellThreads), 0, st, dummy, dd, dpc, n, plan->n_cell_tiles);
   prof_end(pcl, st);
   int pfl = prof_begin("k_flux", st);
-  if (plan->n_group[0] > 0 && plan->grid_flux[0] > 0)
-    hipLaunchKernelGGL((rich::k_flux<0, true>), dim3(plan->grid_flux[0]), dim3(rich::kTile), 0,
-                       st, dummy, dd, dpf0, plan->n_group[0], plan->n_flux_tiles[0]);
-  if (plan->n_group[1] > 0 && plan->grid_flux[1] > 0)
-    hipLaunchKernelGGL((rich::k_flux<1, true>), dim3(plan->grid_flux[1]), dim3(rich::kTile), 0,
-                       st, dummy, dd, dpf1, plan->n_group[1], plan->n_flux_tiles[1]);
+  for (int k = 0; k < 2; ++k) {
+    if (plan->n_group[k] <= 0 || plan->grid_flux[k] <= 0) continue;
+    const int32_t* dpf = k == 0 ? dpf0 : dpf1;
+    launch_flux_batch(k, plan->flux_tile, plan->grid_flux[k], st, dummy, dd, dpf,
+                      plan->n_group[k], plan->n_flux_tiles[k]);
+  }
   prof_end(pfl, st);
   return hip_status(hipGetLastError());
+}
+
+int rich_stage_batch_autotune(int32_t n, const rich_mesh* const* meshes,
+                              const rich_state* const* src, const rich_state* const* base,
+                              rich_state* const* out, const double* h,
+                              const rich_params* const* params, int32_t reps, void* ws,
+                              size_t ws_bytes, void* stream, int32_t* best_tile, double* ms) {
+  if (!best_tile || !ms || reps <= 0) return RICH_E_INVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  static const int32_t tiles[3] = {128, 256, 512};
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    return RICH_E_DEVICE;
+  }
+  int rc = RICH_OK;
+  double best = 0.0;
+  *best_tile = 0;
+  for (int k = 0; k < 3 && rc == RICH_OK; ++k) {
+    rich_batch_plan plan;
+    rc = rich_stage_batch_prepare_tile(n, meshes, src, base, out, h, params, tiles[k], ws,
+                                       ws_bytes, stream, &plan);
+    if (rc) break;
+    if ((rc = rich_stage_batch_launch(&plan, ws, stream))) break;   // warm-up
+    if (hipEventRecord(a, st) != hipSuccess) { rc = RICH_E_DEVICE; break; }
+    for (int r = 0; r < reps && rc == RICH_OK; ++r) rc = rich_stage_batch_launch(&plan, ws, stream);
+    if (rc) break;
+    float t = 0.0f;
+    if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&t, a, b) != hipSuccess) {
+      rc = RICH_E_DEVICE;
+      break;
+    }
+    ms[k] = (double)t / reps;
+    if (*best_tile == 0 || ms[k] < best) {
+      best = ms[k];
+      *best_tile = tiles[k];
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
 }
 
 int rich_stage_batch(int32_t n, const rich_mesh* const* meshes, const rich_state* const* src,

@@ -52,7 +52,8 @@ RETESS_POINT, RETESS_FAN, RETESS_CLIP, RETESS_ASYM, RETESS_AREA, RETESS_CAP = 1,
 class RichBatchPlan(C.Structure):
     _fields_ = [("n_runs", C.c_int32), ("n_cell_tiles", C.c_int32),
                 ("n_flux_tiles", C.c_int32 * 2), ("n_group", C.c_int32 * 2),
-                ("grid_cell", C.c_int32), ("grid_flux", C.c_int32 * 2)]
+                ("grid_cell", C.c_int32), ("grid_flux", C.c_int32 * 2),
+                ("flux_tile", C.c_int32)]
 
 
 class RichState(C.Structure):
@@ -173,9 +174,18 @@ def lib():
                                                    C.POINTER(_vp), _vp, C.c_size_t, _vp,
                                                    C.POINTER(RichBatchPlan)]
             L.rich_stage_batch_launch.argtypes = [C.POINTER(RichBatchPlan), _vp, _vp]
+            L.rich_stage_batch_prepare_tile.argtypes = [C.c_int32, C.POINTER(_vp), C.POINTER(_vp),
+                                                        C.POINTER(_vp), C.POINTER(_vp), _dp,
+                                                        C.POINTER(_vp), C.c_int32, _vp,
+                                                        C.c_size_t, _vp, C.POINTER(RichBatchPlan)]
+            L.rich_stage_batch_autotune.argtypes = [C.c_int32, C.POINTER(_vp), C.POINTER(_vp),
+                                                    C.POINTER(_vp), C.POINTER(_vp), _dp,
+                                                    C.POINTER(_vp), C.c_int32, _vp, C.c_size_t,
+                                                    _vp, _ip, _dp]
             for f in ("rich_batch_workspace_size", "rich_stage_batch", "rich_batch_flags",
                       "rich_batch_flags_async", "rich_stage_batch_prepare",
-                      "rich_stage_batch_launch"):
+                      "rich_stage_batch_launch", "rich_stage_batch_prepare_tile",
+                      "rich_stage_batch_autotune"):
                 getattr(L, f).restype = C.c_int
         if hasattr(L, "rich_step"):
             L.rich_ctx_create.argtypes = [C.POINTER(_vp)]
@@ -559,6 +569,30 @@ def rich_stage_batch_prepare(meshes, srcs, bases, outs, hs, params, ws, stream=N
                                         _stream_ptr(stream), C.byref(plan))
     _check(st, "rich_stage_batch_prepare")
     return plan
+
+
+def rich_stage_batch_prepare_tile(meshes, srcs, bases, outs, hs, params, tile, ws,
+                                  stream=None):
+    """rich_stage_batch_prepare with flux tiles of `tile` cells (128, 256, 512)."""
+    n, mp, spp, bpp, opp, hh, ppp, _pc = _batch_args(meshes, srcs, bases, outs, hs, params)
+    plan = RichBatchPlan()
+    st = lib().rich_stage_batch_prepare_tile(n, mp, spp, bpp, opp, hh, ppp, int(tile),
+                                             C.c_void_p(ws.data_ptr()), ws.numel(),
+                                             _stream_ptr(stream), C.byref(plan))
+    _check(st, "rich_stage_batch_prepare_tile")
+    return plan
+
+
+def rich_stage_batch_autotune(meshes, srcs, bases, outs, hs, params, ws, reps=3, stream=None):
+    """(best tile, {tile: ms per launch}) of a batched stage on these runs."""
+    n, mp, spp, bpp, opp, hh, ppp, _pc = _batch_args(meshes, srcs, bases, outs, hs, params)
+    best = C.c_int32(0)
+    ms = (C.c_double * 3)()
+    st = lib().rich_stage_batch_autotune(n, mp, spp, bpp, opp, hh, ppp, int(reps),
+                                         C.c_void_p(ws.data_ptr()), ws.numel(),
+                                         _stream_ptr(stream), C.byref(best), ms)
+    _check(st, "rich_stage_batch_autotune")
+    return int(best.value), {128: ms[0], 256: ms[1], 512: ms[2]}
 
 
 def rich_stage_batch_launch(plan, ws, stream=None):

@@ -65,6 +65,42 @@ def test_batch_equals_single_runs_bitwise_and_oracle():
         assert (eq < U.TOL).all() and ex < U.TOL, (eq, ex)
 
 
+def test_batch_tile_shapes_bitwise_equal_and_autotune():
+    """Every edge-tile shape (128, 256, 512 cells) gives the same results bit
+    for bit; the autotuner times each and picks one of them."""
+    import torch
+    from paper_1410_3219_amd import rich as R
+    cases = _runs()
+    ref, _ = _run_batch(cases)
+    meshes = [R.DeviceMesh.from_host(m) for m, *_ in cases]
+    srcs = [R.DeviceState.from_host(Qs, Xb) for m, Qs, Qb, Xb, h, p in cases]
+    bases = [R.DeviceState.from_host(Qb, Xb) for m, Qs, Qb, Xb, h, p in cases]
+    hs = [c[4] for c in cases]
+    ps = [U.gpu_params(c[5]) for c in cases]
+    ws = R.batch_workspace([m.n_cells for m, *_ in cases])
+    for tile in (128, 256, 512):
+        outs = [R.DeviceState.empty_like(b) for b in bases]
+        for o in outs:
+            o.Q.fill_(float("nan"))
+        plan = R.rich_stage_batch_prepare_tile(meshes, srcs, bases, outs, hs, ps, tile, ws)
+        assert plan.flux_tile == tile
+        R.rich_stage_batch_launch(plan, ws)
+        assert R.rich_batch_flags(len(cases), ws) == [0] * len(cases)
+        torch.cuda.synchronize()
+        for (Qr, Xr), o in zip(ref, outs):
+            Qo, Xo = o.numpy()
+            assert np.array_equal(Qo, Qr) and np.array_equal(Xo, Xr), tile
+    outs = [R.DeviceState.empty_like(b) for b in bases]
+    best, ms = R.rich_stage_batch_autotune(meshes, srcs, bases, outs, hs, ps, ws, reps=2)
+    assert best in (128, 256, 512) and all(v > 0 for v in ms.values())
+    assert ms[best] == min(ms.values())
+    for (Qr, Xr), o in zip(ref, outs):
+        assert np.array_equal(o.numpy()[0], Qr)
+    with pytest.raises(R.RichError) as e:
+        R.rich_stage_batch_prepare_tile(meshes, srcs, bases, outs, hs, ps, 64, ws)
+    assert e.value.status == R.RICH_E_INVAL
+
+
 def test_batch_failure_is_isolated():
     cases = _runs()
     good, _ = _run_batch(cases)
