@@ -2,7 +2,8 @@
  * rich.h -- C-ABI of the device path (librich.so): one stage and one
  * time-centred step of the moving-mesh Godunov scheme of RICH (Yalinewich,
  * Steinberg & Sari) on an MI355X (gfx950), for one run or a batch of
- * independent runs.
+ * independent runs; the Courant step, the area change rate of the cells, and
+ * the rebuild of the Voronoi mesh of moved points on the device.
  *
  * Every step of the stage runs in HIP kernels; this header carries no HIP or
  * torch types: device pointers are plain pointers and the stream is passed as
@@ -12,7 +13,7 @@
  * Data layout (device memory, FP64 values, int32 indices): the mesh is the
  * host tessellation stage's (rich_tess.h) with its cells and edges as
  * records (rich_cell, rich_edge below; rich_mesh_pack builds them) and its
- * CSR arrays as they are; the state of a run is the extensive cell totals M,
+ * CSR arrays as they are, or the same layout written by rich_retess; the state of a run is the extensive cell totals M,
  * Px, Py, E (mass, momentum, total energy integrated over each cell) and the
  * mesh-generating points x, y, each a row of n_cells doubles.
  *
