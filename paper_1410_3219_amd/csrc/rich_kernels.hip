@@ -1656,12 +1656,14 @@ namespace {
 int mesh_of(rich_ctx* ctx, const rich_mesh& prev, const rich_state& s, DevMesh& dst,
             rich_tess_fn tess, rich_tess_release_fn release, void* tess_user, hipStream_t st) {
   if (ctx->device_tess) {
+    // RICH_E_INVAL: a run the device rebuild does not take (a periodic box
+    // of under 16 cells); RICH_E_MESH: a mesh it did not certify
     const int rc = retess_into(ctx, prev, s.x, s.y, dst, st);
     if (rc == RICH_OK) {
       ++ctx->n_device;
       return RICH_OK;
     }
-    if (rc != RICH_E_MESH) return rc;
+    if (rc != RICH_E_MESH && rc != RICH_E_INVAL) return rc;
     ++ctx->n_fallback;
   }
   return tessellate_into(ctx, dst, s.x, prev.n_cells, ctx->cur.box, ctx->cur.bc, tess, release,

@@ -494,3 +494,25 @@ def test_retess_batch_equals_single_runs_bitwise():
             if lim is not None:
                 a, b = a[:lim], b[:lim]
             assert np.array_equal(a, b), (r, key)
+
+
+def test_step_driver_small_periodic_box_uses_host_stage():
+    """A periodic box of 9 cells is below what the device rebuild takes: the
+    driver builds those meshes with the host stage and the step equals the
+    host-only driver's bit for bit."""
+    from paper_1410_3219_amd import rich as R
+    P = I.advected_wave(k=3, seed=2)
+    m = T.rich_tess_build(P.px, P.py, P.box, P.bc)
+    Q = P.state(m.area)
+    X = np.stack([m.px, m.py])
+    p = R.Params(gamma=P.gamma)
+    out = []
+    for dev in (True, False):
+        ctx = R.RichCtx(device_tess=dev)
+        ctx.set_mesh(m)
+        s = R.DeviceState.from_host(Q, X)
+        ctx.step(s, 1e-3, p)
+        out.append((s.numpy(), ctx.tess_counts()))
+        ctx.close()
+    assert out[0][1] == (0, 2) and out[1][1] == (0, 0)
+    assert np.array_equal(out[0][0][0], out[1][0][0]) and np.array_equal(out[0][0][1], out[1][0][1])
