@@ -1,29 +1,29 @@
 // Device re-tessellation of moved mesh points (section 2.1: the mesh is the
 // Voronoi tessellation of its points, rebuilt after every move).
 //
-// Cell i of the new mesh is the polygon left after clipping a bounding
-// region against the bisector of the new point r_i with each candidate point:
-// the region is the box for walls (its sides are the bisectors with the
-// point's mirror images) and, for a periodic box, the square bounded by the
-// bisectors with the point's own images one box length away.  The candidates
-// are the neighbours and the neighbours' neighbours of the cell in a previous
-// mesh of the same points, each at its nearest periodic image.  A clipped
-// polygon always contains the true Voronoi cell; it equals it when every true
+// Cell i of the new mesh is the set of points nearer to the new point r_i
+// than to each candidate point, within the box for walls (its sides are the
+// bisectors with the point's mirror images).  The candidates are the
+// neighbours and the neighbours' neighbours of the cell in a previous mesh of
+// the same points, each at its nearest periodic image (a periodic box of at
+// least 16 cells, whose neighbours enclose each point).  The cell so found
+// always contains the true Voronoi cell; it equals it when every true
 // neighbour was a candidate.  The kernels certify that (every kept edge seen
 // alike by both cells; the areas summing to the box area) instead of
 // assuming it, and report failure so that the caller rebuilds on the host.
 //
-// The polygon is held as the counter-clockwise list of the displacements d
-// from r_i to its edge-generating points (neighbours, images, mirrors) and
-// its vertices: vertex q is the intersection of the bisectors of entries q-1
-// and q, i.e. the point p with p.d = |d|^2 / 2 for both, computed once when
-// those two edges become adjacent, so vertices come from the generating
-// points alone and not from the order of the clips.  A candidate further
-// than twice the largest vertex distance cannot cut and is skipped at once.
+// No polygon is edited: each candidate's bisector is cut down to the part
+// that every other candidate allows (two bounds kept as fractions), and the
+// candidates with a non-empty part are the cell's edges; their parts' ends
+// are the vertices.  The candidates (at most 16, in LDS) are the wall
+// mirrors and the previous neighbours; a neighbour's neighbour enters only
+// when its bisector crosses the cell those give (one further than twice the
+// largest vertex distance cannot, and is skipped at once).  The loops over
+// candidates have straight-line bodies, so the lanes of a wave stay together.
 //
 // Pipeline (one launch each, all on the caller's stream):
 //   k_rt_begin    clear the result header
-//   k_rt_clip     one thread per cell: clip, area, centroid, edge slots
+//   k_rt_clip     one thread per cell: the cell's edges, area, centroid
 //   k_rt_classify keep / own each slot by the input stage's rules, check
 //                 each kept edge against the neighbour's slot, count
 //   k_rt_scan_*   prefix sums of the counts into off[] and eoff[]
@@ -43,9 +43,9 @@ namespace retess {
 constexpr uint32_t kMask = 0x0FFFFFFFu;
 constexpr int kShift = 28;
 constexpr int kMaxFan = 20;    // edges of a finished cell (RICH_RETESS_FAN beyond)
-constexpr int kMaxPoly = 24;   // edges of a polygon while it is being clipped
+constexpr int kSlots = 16;     // candidate slots of a cell: 4 bounds, neighbours, entrants
 constexpr int kRingMax = 64;   // CSR entries read per cell of the previous mesh
-constexpr int kThreads = 128;
+constexpr int kThreads = 64;
 constexpr int kScanThreads = 1024;
 constexpr double kPi = 3.14159265358979323846;
 // neighbour codes of the reflecting walls x = x0, x = x1, y = y0, y = y1 in
@@ -177,139 +177,115 @@ __global__ void k_rt_end(Hdr* one, Batch bt) {
 }
 
 // ---------------------------------------------------------------------------
-// clipping
+// the cell of one point
 // ---------------------------------------------------------------------------
-struct Poly {
-  double dx[kMaxPoly], dy[kMaxPoly];  // generating point of edge q, relative to r_i
-  double vx[kMaxPoly], vy[kMaxPoly];  // vertex q: start of edge q
-  int32_t id[kMaxPoly];
-  int nv;
-  double r2;  // largest squared vertex distance from r_i
+// A lane's candidate slots in LDS: slot u of the lane holds the displacement d
+// from r_i to a generating point and its id (cell | code << 28); slot u of
+// lane t lives at [u * kThreads + t], so a wave's accesses to one slot are
+// consecutive.
+struct Slots {
+  double* dx;
+  double* dy;
+  int32_t* id;
+  __device__ double& x(int u) const { return dx[u * kThreads]; }
+  __device__ double& y(int u) const { return dy[u * kThreads]; }
+  __device__ int32_t& n(int u) const { return id[u * kThreads]; }
 };
 
-__device__ __forceinline__ void update_radius(Poly& P) {
-  double r2 = 0.0;
-  for (int q = 0; q < P.nv; ++q) r2 = fmax(r2, P.vx[q] * P.vx[q] + P.vy[q] * P.vy[q]);
-  P.r2 = r2;
+// The part of the bisector of displacement (dux, duy) (the line
+// p.d = |d|^2/2, parametrised p(t) = d/2 + t (-duy, dux), t increasing
+// counter-clockwise about r_i) that satisfies p.d_v <= |d_v|^2/2 for every
+// slot v of mask vm except `self`: [t_lo, t_hi].  The bounds are kept as
+// fractions and compared by cross-multiplication, so the loop divides
+// nothing.  Returns false when that part is empty, or when a slot of the
+// same id comes before `self` (a duplicate); *bounded is false when one end
+// is open (the slots do not enclose the point).
+__device__ bool bisector_part(const Slots& S, uint32_t vm, int nv, int self, double dux,
+                              double duy, int32_t idu, double& tlo, double& thi, bool& bounded) {
+  const double mux = 0.5 * dux, muy = 0.5 * duy;
+  const double eux = -duy, euy = dux;
+  double ln = 0.0, ld = 1.0, hn = 0.0, hd = 1.0;
+  bool has_lo = false, has_hi = false, empty = false;
+  // straight-line body (selects, no branches) over the lane's nv slots
+#pragma unroll 4
+  for (int v = 0; v < nv; ++v) {
+    const double dvx = S.x(v), dvy = S.y(v);
+    const bool use = ((vm >> v) & 1u) && v != self;
+    const bool same = use && S.n(v) == idu;
+    empty = empty || (same && v < self);
+    const bool act = use && !same;
+    const double a0 = eux * dvx + euy * dvy;
+    const double b0 = 0.5 * (dvx * dvx + dvy * dvy) - (mux * dvx + muy * dvy);
+    const double a = act ? a0 : 0.0;
+    const double b = act ? b0 : 1.0;
+    // a > 0: t <= b / a;  a < 0: t >= (-b) / (-a);  a = 0, b < 0: no t
+    const bool up = a > 0.0 && (!has_hi || b * hd < hn * a);
+    hn = up ? b : hn;
+    hd = up ? a : hd;
+    has_hi = has_hi || up;
+    const bool dn = a < 0.0 && (!has_lo || -b * ld > ln * -a);
+    ln = dn ? -b : ln;
+    ld = dn ? -a : ld;
+    has_lo = has_lo || dn;
+    empty = empty || (a == 0.0 && b < 0.0);
+  }
+  bounded = has_lo && has_hi;
+  if (empty || !bounded || !(ln * hd < hn * ld)) return false;
+  tlo = ln / ld;
+  thi = hn / hd;
+  return true;
 }
 
-// Vertices of the starting polygon from its four generators.
-__device__ int init_vertices(Poly& P) {
-  for (int q = 0; q < P.nv; ++q) {
-    const int qm = q == 0 ? P.nv - 1 : q - 1;
-    if (!bisector_meet(P.dx[qm], P.dy[qm], P.dx[q], P.dy[q], P.vx[q], P.vy[q]))
-      return RICH_RETESS_CLIP;
-  }
-  update_radius(P);
-  return 0;
+// Counter-clockwise order of directions: the upper half-plane (from angle 0
+// inclusive) before the lower one, then by the sign of the cross product.
+__device__ __forceinline__ bool ccw_before(double ax, double ay, double bx, double by) {
+  const int ha = (ay < 0.0 || (ay == 0.0 && ax < 0.0)) ? 1 : 0;
+  const int hb = (by < 0.0 || (by == 0.0 && bx < 0.0)) ? 1 : 0;
+  if (ha != hb) return ha < hb;
+  return ax * by - ay * bx > 0.0;
 }
 
-// Clip P by the half-plane p.d <= |d|^2/2 of candidate `cid` at displacement
-// d.  Returns a RICH_RETESS_* bit on failure, else 0.
-__device__ int clip(Poly& P, double dx, double dy, int32_t cid) {
-  const double d2 = dx * dx + dy * dy;
-  // no vertex is further than sqrt(r2) from r_i, so none can lie beyond a
-  // bisector at distance |d|/2 >= sqrt(r2): the candidate cannot cut
-  if (4.0 * P.r2 <= d2) return 0;
-  for (int q = 0; q < P.nv; ++q)
-    if (P.id[q] == cid) return 0;  // already an edge of the polygon
-  const double h = 0.5 * d2;
-  // a vertex is cut off when it is further than 1e-14 |d| beyond the
-  // bisector: a shallower cut would make an edge far below the
-  // degenerate-edge threshold of the input stage
-  const double tol = 2e-14 * h;
-  uint32_t out = 0;
-  for (int q = 0; q < P.nv; ++q)
-    if (P.vx[q] * dx + P.vy[q] * dy - h > tol) out |= 1u << q;
-  if (out == 0) return 0;
-  const uint32_t full = (1u << P.nv) - 1u;
-  if (out == full) return RICH_RETESS_CLIP;
-  // the cut vertices form one cyclic run a .. a+m-1 (the polygon is convex)
-  int a = -1, starts = 0;
-  for (int q = 0; q < P.nv; ++q) {
-    const int qm = q == 0 ? P.nv - 1 : q - 1;
-    if (((out >> q) & 1u) && !((out >> qm) & 1u)) {
-      a = q;
-      ++starts;
-    }
-  }
-  if (starts != 1) return RICH_RETESS_CLIP;
-  const int m = __popc(out);
-  const int r = m - 1;  // edges a .. a+r-1 lie wholly beyond the bisector
-  const int am = a == 0 ? P.nv - 1 : a - 1;
-  const int b = a + r < P.nv ? a + r : a + r - P.nv;
-  // the two new vertices: where the new edge meets the kept edges am and b
-  double px, py, qx, qy;
-  if (!bisector_meet(P.dx[am], P.dy[am], dx, dy, px, py) ||
-      !bisector_meet(dx, dy, P.dx[b], P.dy[b], qx, qy))
-    return RICH_RETESS_CLIP;
-  int at_c, at_b;  // new positions of the new edge and of edge b
-  if (a + r <= P.nv) {
-    if (r == 0) {  // one vertex cut: the new edge is inserted at a
-      if (P.nv + 1 > kMaxPoly) return RICH_RETESS_FAN;
-      for (int t = P.nv; t > a; --t) {
-        P.dx[t] = P.dx[t - 1]; P.dy[t] = P.dy[t - 1]; P.id[t] = P.id[t - 1];
-        P.vx[t] = P.vx[t - 1]; P.vy[t] = P.vy[t - 1];
-      }
-      ++P.nv;
-    } else {
-      for (int t = a + r; t < P.nv; ++t) {
-        const int u = t - r + 1;
-        P.dx[u] = P.dx[t]; P.dy[u] = P.dy[t]; P.id[u] = P.id[t];
-        P.vx[u] = P.vx[t]; P.vy[u] = P.vy[t];
-      }
-      P.nv = P.nv - r + 1;
-    }
-    at_c = a;
-    at_b = a + 1 < P.nv ? a + 1 : 0;
-  } else {  // the removed edges wrap past the end: keep w .. a-1, then the new one
-    const int w = a + r - P.nv;
-    for (int t = w; t < a; ++t) {
-      P.dx[t - w] = P.dx[t]; P.dy[t - w] = P.dy[t]; P.id[t - w] = P.id[t];
-      P.vx[t - w] = P.vx[t]; P.vy[t - w] = P.vy[t];
-    }
-    P.nv = a - w + 1;
-    at_c = a - w;
-    at_b = 0;
-  }
-  P.dx[at_c] = dx; P.dy[at_c] = dy; P.id[at_c] = cid;
-  P.vx[at_c] = px; P.vy[at_c] = py;
-  P.vx[at_b] = qx; P.vy[at_b] = qy;
-  update_radius(P);
-  return 0;
-}
-
+// One thread per cell.  With walls, slots 0-3 hold the point's mirrors
+// (they bound it); then come the cell's neighbours in the previous mesh; the
+// first pass finds the polygon those allow.  The neighbours' neighbours then enter only when their
+// bisector crosses that polygon, into slots that bound nothing; the second
+// pass gives the cell, its area, centroid and edges in counter-clockwise
+// order.  Every slot v is tried against every slot u (a fixed loop with no
+// polygon to edit), so lanes of a wave stay together.
 template <bool B>
 __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
+  __shared__ double s_dx[kSlots * kThreads], s_dy[kSlots * kThreads];
+  __shared__ int32_t s_id[kSlots * kThreads];
   int blk;
   const Args& a = block_run<B>(one, bt.cstart, bt, blk);
   const int i = blk * kThreads + threadIdx.x;
   if (i >= a.n) return;
+  const Slots S{s_dx + threadIdx.x, s_dy + threadIdx.x, s_id + threadIdx.x};
   const double xi = a.x[i], yi = a.y[i];
   int bad = 0;
-  Poly P;
   const bool periodic = a.bc == (int)RICH_BOUNDARY_PERIODIC;
+  // live slots are 0 .. nv-1; vm marks those that hold a candidate
+  int nv = 0;
+  uint32_t vm = 0u;
   if (periodic) {
+    // no bounds: the neighbours enclose the point (a cell they leave open
+    // is reported, and rebuilt on the host)
     if (!(xi >= a.x0 && xi < a.x1 && yi >= a.y0 && yi < a.y1)) bad |= RICH_RETESS_POINT;
-    // the point's own images below, right, above and left
-    P.dx[0] = 0.0;   P.dy[0] = -a.Ly; P.id[0] = pack(i, shift_code(0, -1));
-    P.dx[1] = a.Lx;  P.dy[1] = 0.0;   P.id[1] = pack(i, shift_code(1, 0));
-    P.dx[2] = 0.0;   P.dy[2] = a.Ly;  P.id[2] = pack(i, shift_code(0, 1));
-    P.dx[3] = -a.Lx; P.dy[3] = 0.0;   P.id[3] = pack(i, shift_code(-1, 0));
   } else {
     if (!(xi > a.x0 && xi < a.x1 && yi > a.y0 && yi < a.y1)) bad |= RICH_RETESS_POINT;
-    // mirror images across the walls y0, x1, y1, x0
-    P.dx[0] = 0.0;                 P.dy[0] = 2.0 * (a.y0 - yi); P.id[0] = pack(i, kWallY0);
-    P.dx[1] = 2.0 * (a.x1 - xi);   P.dy[1] = 0.0;               P.id[1] = pack(i, kWallX1);
-    P.dx[2] = 0.0;                 P.dy[2] = 2.0 * (a.y1 - yi); P.id[2] = pack(i, kWallY1);
-    P.dx[3] = 2.0 * (a.x0 - xi);   P.dy[3] = 0.0;               P.id[3] = pack(i, kWallX0);
+    // the point's mirrors across the walls y0, x1, y1, x0
+    S.x(0) = 0.0;                S.y(0) = 2.0 * (a.y0 - yi); S.n(0) = pack(i, kWallY0);
+    S.x(1) = 2.0 * (a.x1 - xi);  S.y(1) = 0.0;               S.n(1) = pack(i, kWallX1);
+    S.x(2) = 0.0;                S.y(2) = 2.0 * (a.y1 - yi); S.n(2) = pack(i, kWallY1);
+    S.x(3) = 2.0 * (a.x0 - xi);  S.y(3) = 0.0;               S.n(3) = pack(i, kWallX0);
+    nv = 4;
+    vm = 0xFu;
   }
-  P.nv = 4;
-  bad |= init_vertices(P);
 
-  auto candidate = [&](int c) {
-    if (c < 0 || c >= a.n) return;
-    double dx = a.x[c] - xi, dy = a.y[c] - yi;
+  // displacement of cell c from r_i (nearest periodic image) and its id
+  auto displacement = [&](int c, double& dx, double& dy) -> int32_t {
+    dx = a.x[c] - xi;
+    dy = a.y[c] - yi;
     int code = 0;
     if (periodic) {
       int sx = 0, sy = 0;
@@ -317,70 +293,154 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
       if (dy > 0.5 * a.Ly) { dy -= a.Ly; sy = -1; } else if (dy < -0.5 * a.Ly) { dy += a.Ly; sy = 1; }
       if (sx != 0 || sy != 0) code = shift_code(sx, sy);
     }
-    bad |= clip(P, dx, dy, pack(c, code));
+    return pack(c, code);
   };
 
   int k0 = 0, k1 = 0;
   if (!bad) {
     k0 = a.p_off[i];
     k1 = a.p_off[i + 1];
-    if (k0 < 0 || k1 < k0 || k1 > a.p_n_csr || k1 - k0 > kRingMax) {
+    if (k0 < 0 || k1 < k0 || k1 > a.p_n_csr) {
       bad |= RICH_RETESS_CLIP;
+      k1 = k0;
+    } else if (k1 - k0 > kSlots - nv) {
+      bad |= RICH_RETESS_FAN;
       k1 = k0;
     }
   }
-  // first ring, then the second: the polygon is near its final shape before
-  // the many second-ring candidates, most of which then cut nothing
-  for (int k = k0; k < k1 && !bad; ++k) {
+  for (int k = k0; k < k1; ++k) {
     const int j = prev_neighbour(a, k);
-    if (j != i) candidate(j);
+    if (j < 0 || j >= a.n || j == i) continue;
+    double dx, dy;
+    S.n(nv) = displacement(j, dx, dy);
+    S.x(nv) = dx;
+    S.y(nv) = dy;
+    vm |= 1u << nv;
+    ++nv;
   }
+
+  // first pass: the polygon of the bounds and the first ring, and the
+  // largest distance of its vertices
+  uint32_t em = 0;
+  double r2 = 0.0;
+  if (!bad) {
+    for (int u = 0; u < nv; ++u) {
+      if (!((vm >> u) & 1u)) continue;
+      double tlo, thi;
+      bool bounded;
+      const double dux = S.x(u), duy = S.y(u);
+      if (bisector_part(S, vm, nv, u, dux, duy, S.n(u), tlo, thi, bounded)) {
+        em |= 1u << u;
+        const double px = 0.5 * dux - thi * duy, py = 0.5 * duy + thi * dux;
+        r2 = fmax(r2, px * px + py * py);
+      } else if (!bounded) {
+        bad |= RICH_RETESS_CLIP;
+      }
+    }
+  }
+
+  // second ring: a candidate enters when its bisector crosses the polygon
+  // (a candidate further than twice the largest vertex distance cannot)
   for (int k = k0; k < k1 && !bad; ++k) {
     const int j = prev_neighbour(a, k);
-    if (j < 0 || j == i || j >= a.n) continue;
-    int l0 = a.p_off[j], l1 = a.p_off[j + 1];
+    if (j < 0 || j >= a.n || j == i) continue;
+    const int l0 = a.p_off[j], l1 = a.p_off[j + 1];
     if (l0 < 0 || l1 < l0 || l1 > a.p_n_csr || l1 - l0 > kRingMax) {
       bad |= RICH_RETESS_CLIP;
       break;
     }
-    for (int l = l0; l < l1 && !bad; ++l) {
+    for (int l = l0; l < l1; ++l) {
       const int c = prev_neighbour(a, l);
-      if (c != i) candidate(c);
+      if (c < 0 || c >= a.n || c == i) continue;
+      double dx, dy;
+      const int32_t id = displacement(c, dx, dy);
+      if (4.0 * r2 <= dx * dx + dy * dy) continue;
+      bool known = false;
+      for (int v = 0; v < nv; ++v) known = known || (((vm >> v) & 1u) && S.n(v) == id);
+      if (known) continue;
+      double tlo, thi;
+      bool bounded;
+      if (!bisector_part(S, vm, nv, -1, dx, dy, id, tlo, thi, bounded)) continue;
+      // a new slot, else one whose bisector bounds nothing (it stays
+      // redundant as candidates are added)
+      int u = nv;
+      if (nv < kSlots) {
+        ++nv;
+      } else {
+        const uint32_t usable = ~em & ((1u << kSlots) - 1u);
+        if (usable == 0u) {
+          bad |= RICH_RETESS_FAN;
+          break;
+        }
+        u = __ffs(usable) - 1;
+      }
+      S.x(u) = dx;
+      S.y(u) = dy;
+      S.n(u) = id;
+      vm |= 1u << u;
+      em |= 1u << u;   // holds a cutting candidate now: not reusable
     }
   }
-  if (!bad && P.nv > kMaxFan) bad |= RICH_RETESS_FAN;
 
   rich_cell cr;
-  cr.px = xi; cr.py = yi; cr.pad = 0.0;
+  cr.px = xi;
+  cr.py = yi;
+  cr.pad = 0.0;
   if (bad) {
     atomicOr(&a.hdr->flags, bad);
     a.deg[i] = 0;
-    cr.area = 0.0; cr.sx = xi; cr.sy = yi;
+    cr.area = 0.0;
+    cr.sx = xi;
+    cr.sy = yi;
     a.cells[i] = cr;
     return;
   }
-  // vertices, area and centroid (shoelace over the triangles fanned from the
-  // point), edges with their midpoints
+  // second pass: the cell's edges, written in counter-clockwise order, and
+  // the shoelace sums of the triangles they make with the point
+  uint32_t fm = 0;
+  for (int u = 0; u < nv; ++u) {
+    if (!((vm >> u) & 1u)) continue;
+    double tlo, thi;
+    bool bounded;
+    if (bisector_part(S, vm, nv, u, S.x(u), S.y(u), S.n(u), tlo, thi, bounded)) fm |= 1u << u;
+    else if (!bounded) bad |= RICH_RETESS_CLIP;
+  }
+  const int deg = __popc(fm);
+  if (deg < 3 || deg > kMaxFan) bad |= deg > kMaxFan ? RICH_RETESS_FAN : RICH_RETESS_CLIP;
   double A2 = 0.0, cx = 0.0, cy = 0.0;
-  double ux = P.vx[0], uy = P.vy[0];
   const size_t s0 = (size_t)i * kMaxFan;
-  for (int q = 0; q < P.nv; ++q) {
-    const int q1 = q + 1 < P.nv ? q + 1 : 0;
-    const double wx = P.vx[q1], wy = P.vy[q1];  // vertex q+1: end of edge q
+  for (int u = 0; u < nv && !bad; ++u) {
+    if (!((fm >> u) & 1u)) continue;
+    const double dux = S.x(u), duy = S.y(u);
+    double tlo, thi;
+    bool bounded;
+    bisector_part(S, vm, nv, u, dux, duy, S.n(u), tlo, thi, bounded);
+    const double ux = 0.5 * dux - tlo * duy, uy = 0.5 * duy + tlo * dux;
+    const double wx = 0.5 * dux - thi * duy, wy = 0.5 * duy + thi * dux;
     const double c = ux * wy - uy * wx;
     A2 += c;
     cx += (ux + wx) * c;
     cy += (uy + wy) * c;
+    int rank = 0;
+    for (int v = 0; v < nv; ++v)
+      rank += (((fm >> v) & 1u) && v != u && ccw_before(S.x(v), S.y(v), dux, duy)) ? 1 : 0;
     const double ex = wx - ux, ey = wy - uy;
-    a.s_nb[s0 + q] = P.id[q];
-    double* g = a.s_geo + 3 * (s0 + q);
+    a.s_nb[s0 + rank] = S.n(u);
+    double* g = a.s_geo + 3 * (s0 + rank);
     g[0] = sqrt(ex * ex + ey * ey);
     g[1] = xi + 0.5 * (ux + wx);
     g[2] = yi + 0.5 * (uy + wy);
-    ux = wx;
-    uy = wy;
   }
-  a.deg[i] = P.nv;
+  if (bad) {
+    atomicOr(&a.hdr->flags, bad);
+    a.deg[i] = 0;
+    cr.area = 0.0;
+    cr.sx = xi;
+    cr.sy = yi;
+    a.cells[i] = cr;
+    return;
+  }
+  a.deg[i] = deg;
   cr.area = 0.5 * A2;
   cr.sx = xi + cx / (3.0 * A2);
   cr.sy = yi + cy / (3.0 * A2);
