@@ -27,7 +27,8 @@
 //   k_rt_classify keep / own each slot by the input stage's rules, check
 //                 each kept edge against the neighbour's slot, count
 //   k_rt_scan_*   prefix sums of the counts into off[] and eoff[]
-//   k_rt_emit     edge records and CSR entries
+//   k_rt_emit     edge records (each also told to the neighbour's slot)
+//   k_rt_emit_csr CSR entries
 //   k_rt_end      fold the flags into the sticky word
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -56,7 +57,8 @@ struct Hdr {  // first 64 bytes of the workspace
   int32_t flags, sticky;
   int64_t n_edges, n_csr, n_dropped;
   double area_sum;
-  int64_t pad[3];
+  int64_t n_wall;   // kept wall edges (each one CSR entry)
+  int64_t pad[2];
 };
 static_assert(sizeof(Hdr) == 64, "result header");
 
@@ -78,6 +80,8 @@ struct Args {
   int32_t* s_nb;       // [n][kMaxFan] generating point: cell | code << 28
   double* s_geo;       // [n][kMaxFan][3] edge length, midpoint x, midpoint y
   uint8_t* s_flag;     // [n][kMaxFan] bit 0 kept, bit 1 owned
+  uint8_t* s_back;     // [n][kMaxFan] owned edge: its slot in the neighbour's row
+  int32_t* s_edge;     // [n][kMaxFan] kept, not owned: the owner's edge index
   int64_t* bsum;       // [2][n_scan_blocks] block totals of kept / owned
   // geometry
   double x0, y0, x1, y1, Lx, Ly;
@@ -164,6 +168,7 @@ __global__ void k_rt_begin(Hdr* one, Batch bt) {
     h->n_csr = 0;
     h->n_dropped = 0;
     h->area_sum = 0.0;
+    h->n_wall = 0;
   }
 }
 
@@ -455,10 +460,10 @@ __global__ __launch_bounds__(kThreads) void k_rt_classify(Args one, Batch bt) {
   int blk;
   const Args& a = block_run<B>(one, bt.cstart, bt, blk);
   __shared__ double s_area[kThreads / 64];
-  __shared__ long long s_drop[kThreads / 64];
+  __shared__ long long s_drop[kThreads / 64], s_wall[kThreads / 64];
   const int i = blk * kThreads + threadIdx.x;
   double area = 0.0;
-  long long drop = 0;
+  long long drop = 0, walls = 0;
   if (i < a.n) {
     const int d = a.deg[i];
     area = a.cells[i].area;
@@ -484,8 +489,14 @@ __global__ __launch_bounds__(kThreads) void k_rt_classify(Args one, Batch bt) {
       }
       ++n_keep;
       if (own) ++n_own;
-      if (code >= kWallX0) continue;
-      // the same edge from the neighbour's side
+      if (code >= kWallX0) {
+        ++walls;
+        continue;
+      }
+      // the owner finds the same edge in the neighbour's slots; that every
+      // other kept slot is such a match follows from the counts (checked
+      // once they are summed: kept = 2 owned - walls)
+      if (!own) continue;
       const int32_t want = pack(i, back_code(code));
       const int dj = a.deg[j];
       const size_t t0 = (size_t)j * kMaxFan;
@@ -493,6 +504,7 @@ __global__ __launch_bounds__(kThreads) void k_rt_classify(Args one, Batch bt) {
       for (int t = 0; t < dj; ++t)
         if (a.s_nb[t0 + t] == want) { found = t; break; }
       if (found < 0) { bad |= RICH_RETESS_ASYM; continue; }
+      a.s_back[s0 + q] = (uint8_t)found;
       const double* gj = a.s_geo + 3 * (t0 + found);
       const double Lj = gj[0];
       double fxj = gj[1], fyj = gj[2];
@@ -516,21 +528,25 @@ __global__ __launch_bounds__(kThreads) void k_rt_classify(Args one, Batch bt) {
   for (int o = 32; o > 0; o >>= 1) {
     area += __shfl_xor(area, o);
     drop += __shfl_xor(drop, o);
+    walls += __shfl_xor(walls, o);
   }
   if ((threadIdx.x & 63) == 0) {
     s_area[threadIdx.x >> 6] = area;
     s_drop[threadIdx.x >> 6] = drop;
+    s_wall[threadIdx.x >> 6] = walls;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
-    long long u = 0;
+    long long u = 0, v = 0;
     for (int w = 0; w < kThreads / 64; ++w) {
       t += s_area[w];
       u += s_drop[w];
+      v += s_wall[w];
     }
     atomicAdd(&a.hdr->area_sum, t);
     atomicAdd((unsigned long long*)&a.hdr->n_dropped, (unsigned long long)u);
+    if (v) atomicAdd((unsigned long long*)&a.hdr->n_wall, (unsigned long long)v);
   }
 }
 
@@ -615,6 +631,7 @@ __global__ __launch_bounds__(kScanThreads) void k_rt_scan_blocks(Args one, Batch
     h->n_edges = r1;
     int f = 0;
     if (r0 > a.cap_csr || r1 > a.cap_edges) f |= RICH_RETESS_CAP;
+    if (r0 != 2 * r1 - h->n_wall) f |= RICH_RETESS_ASYM;   // an unmatched kept slot
     const double box = a.Lx * a.Ly;
     if (!(fabs(h->area_sum - box) <= 1e-10 * box)) f |= RICH_RETESS_AREA;
     if (f) h->flags |= f;
@@ -653,6 +670,36 @@ __global__ __launch_bounds__(kThreads) void k_rt_emit(Args one, Batch bt) {
   int blk;
   const Args& a = block_run<B>(one, bt.cstart, bt, blk);
   const int i = blk * kThreads + threadIdx.x;
+  if (i >= a.n || a.hdr->flags != 0) return;
+  // the cell's owned edges, and each one's index into the slot that sees it
+  // from the neighbour's side
+  const int d = a.deg[i];
+  const size_t s0 = (size_t)i * kMaxFan;
+  int e = a.eoff[i];
+  for (int q = 0; q < d; ++q) {
+    if ((a.s_flag[s0 + q] & 3) != 3) continue;
+    const int32_t id = a.s_nb[s0 + q];
+    const double* g = a.s_geo + 3 * (s0 + q);
+    rich_edge r;
+    r.fx = g[1];
+    r.fy = g[2];
+    r.len = g[0];
+    r.i = i;
+    r.j = id;
+    a.edges[e] = r;
+    if ((int)((uint32_t)id >> kShift) < kWallX0) {
+      const int j = (int)((uint32_t)id & kMask);
+      a.s_edge[(size_t)j * kMaxFan + a.s_back[s0 + q]] = e;
+    }
+    ++e;
+  }
+}
+
+template <bool B>
+__global__ __launch_bounds__(kThreads) void k_rt_emit_csr(Args one, Batch bt) {
+  int blk;
+  const Args& a = block_run<B>(one, bt.cstart, bt, blk);
+  const int i = blk * kThreads + threadIdx.x;
   if (i >= a.n) return;
   if (a.hdr->flags != 0) {  // failed: leave a mesh without edges
     a.off[i + 1] = 0;
@@ -663,48 +710,16 @@ __global__ __launch_bounds__(kThreads) void k_rt_emit(Args one, Batch bt) {
     }
     return;
   }
+  // the cell's CSR entries, counter-clockwise: 2 * edge for its own edges,
+  // 2 * edge + 1 for its neighbours'
   const int d = a.deg[i];
   const size_t s0 = (size_t)i * kMaxFan;
   int k = a.off[i], e = a.eoff[i];
-  int bad = 0;
   for (int q = 0; q < d; ++q) {
     const uint8_t f = a.s_flag[s0 + q];
     if (!(f & 1)) continue;
-    const int32_t id = a.s_nb[s0 + q];
-    if (f & 2) {
-      const double* g = a.s_geo + 3 * (s0 + q);
-      rich_edge r;
-      r.fx = g[1];
-      r.fy = g[2];
-      r.len = g[0];
-      r.i = i;
-      r.j = id;
-      a.edges[e] = r;
-      a.idx[k] = 2 * e;
-      ++e;
-    } else {
-      // owned by the neighbour: its edge index is its first edge plus the
-      // owned slots before the matching one
-      const int j = (int)((uint32_t)id & kMask);
-      const int32_t want = pack(i, back_code((int)((uint32_t)id >> kShift)));
-      const size_t t0 = (size_t)j * kMaxFan;
-      const int dj = a.deg[j];
-      int rank = 0, found = -1;
-      for (int t = 0; t < dj; ++t) {
-        const int32_t u = a.s_nb[t0 + t];
-        if (u == want) { found = t; break; }
-        if (a.s_flag[t0 + t] & 2) ++rank;
-      }
-      if (found < 0 || !(a.s_flag[t0 + found] & 2)) {
-        bad = RICH_RETESS_ASYM;
-        a.idx[k] = 0;
-      } else {
-        a.idx[k] = 2 * (a.eoff[j] + rank) + 1;
-      }
-    }
-    ++k;
+    a.idx[k++] = (f & 2) ? 2 * (e++) : 2 * a.s_edge[s0 + q] + 1;
   }
-  if (bad) atomicOr(&a.hdr->flags, bad);
 }
 
 }  // namespace retess
@@ -717,7 +732,7 @@ namespace {
 size_t rt_align(size_t v) { return (v + 255) / 256 * 256; }
 
 struct RtLayout {
-  size_t deg, s_nb, s_geo, s_flag, bsum, total;
+  size_t deg, s_nb, s_geo, s_flag, s_back, s_edge, bsum, total;
   int nb;
 };
 
@@ -730,6 +745,8 @@ RtLayout rt_layout(int64_t n) {
   L.s_nb = o;   o += rt_align(4 * slots);
   L.s_geo = o;  o += rt_align(24 * slots);
   L.s_flag = o; o += rt_align(slots);
+  L.s_back = o; o += rt_align(slots);
+  L.s_edge = o; o += rt_align(4 * slots);
   L.bsum = o;   o += rt_align(16 * (size_t)L.nb);
   L.total = o;
   return L;
@@ -787,6 +804,8 @@ int make_args(const rich_mesh* prev, const double* x, const double* y,
   a.s_nb = reinterpret_cast<int32_t*>(w + L.s_nb);
   a.s_geo = reinterpret_cast<double*>(w + L.s_geo);
   a.s_flag = reinterpret_cast<uint8_t*>(w + L.s_flag);
+  a.s_back = reinterpret_cast<uint8_t*>(w + L.s_back);
+  a.s_edge = reinterpret_cast<int32_t*>(w + L.s_edge);
   a.bsum = reinterpret_cast<int64_t*>(w + L.bsum);
   a.x0 = prev->box[0];
   a.y0 = prev->box[1];
@@ -800,7 +819,7 @@ int make_args(const rich_mesh* prev, const double* x, const double* y,
   return RICH_OK;
 }
 
-// The eight launches of one re-tessellation (B: of n_runs runs at once, with
+// The nine launches of one re-tessellation (B: of n_runs runs at once, with
 // gc cell blocks and gs scan blocks in all).
 template <bool B>
 void launch_all(const retess::Args& a, const retess::Batch& bt, int gc, int gs, int n_runs,
@@ -813,6 +832,7 @@ void launch_all(const retess::Args& a, const retess::Batch& bt, int gc, int gs, 
   hipLaunchKernelGGL(k_rt_scan_blocks<B>, dim3(n_runs), dim3(kScanThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_scan_add<B>, dim3(gs), dim3(kScanThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_emit<B>, dim3(gc), dim3(kThreads), 0, st, a, bt);
+  hipLaunchKernelGGL(k_rt_emit_csr<B>, dim3(gc), dim3(kThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_end<B>, dim3(n_runs), dim3(64), 0, st, a.hdr, bt);
 }
 
