@@ -375,8 +375,9 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
  * results on the two meshes agree to rounding, not bitwise.
  *
  * The tessellation is certified on the device: every kept edge must be seen
- * by both of its cells with the same length, and the cell areas must sum to
- * the box area.  Each clipped cell contains the true cell, so together these
+ * by both of its cells with the same length and midpoint (each edge's owner
+ * checks it, and the counts of kept and owned edges must agree), and the
+ * cell areas must sum to the box area.  Each clipped cell contains the true cell, so together these
  * fail when a true neighbour was missing from the candidates (points moved
  * further than the previous mesh's second ring).  Then a RICH_RETESS_*
  * bit is set, the output mesh is left with no edges (a stage on it reads no
