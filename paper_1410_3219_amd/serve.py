@@ -12,7 +12,12 @@ scheduler:
     stream; requests that arrive while launches are on the device join the
     next pair, and up to two pairs are in flight at once;
   * completes the requests of a pair when its event has passed, checks the
-    per-run flags and records each latency (arrival -> completion).
+    per-run flags and records each latency (arrival -> completion);
+  * evicts a session whose step is flagged (negative density or pressure,
+    a point outside the domain): the failed step is not committed, the
+    session's device memory is released, its request and every later one
+    of that session complete as failed, and the other sessions of the same
+    launch, which the batched stage keeps independent, go on unaffected.
 
 Meshes are served from a pool of templates tessellated once by the host
 stage and shared read-only by the sessions built on them (static mesh: the
@@ -58,6 +63,7 @@ class Session:
     admitted: bool = False
     bytes: int = 0
     final: tuple = None     # (Q, X) on the host at close, when kept
+    error: int = 0          # stage flags (stage 1 | stage 2 << 8) of an evicted session
 
 
 @dataclass
@@ -67,6 +73,7 @@ class Request:
     arrival: float
     phase: int = 0          # 0 waiting, 1 on the device
     done: float = -1.0
+    failed: bool = False
 
 
 def build_templates(sizes, kinds, seed=11, n_threads=0):
@@ -120,6 +127,7 @@ class Server:
         self.ws_pool = []          # idle batch workspaces
         self.busy = set()          # sessions with a request on the device
         self.done = []
+        self.failed = []           # requests of evicted sessions
         self.launches = 0
         self.batch_sizes = []
         self.cells_done = 0
@@ -171,9 +179,25 @@ class Server:
         s.admitted = False
         self.used -= s.bytes
 
+    def _evict(self, s, flags, t):
+        """Close a session whose step was flagged; its committed state (the
+        one before the failed step) is what keep_final records."""
+        s.error = flags
+        self.busy.discard(s.sid)
+        self._close(s)
+        for req in self.queue:
+            if req.sid == s.sid and req.done < 0:
+                req.done, req.failed = t, True
+                self.failed.append(req)
+
     # -- requests ---------------------------------------------------------
     def submit(self, rid, sid, arrival):
-        self.queue.append(Request(rid, sid, arrival))
+        req = Request(rid, sid, arrival)
+        if self.sessions[sid].error:   # evicted: fails at once
+            req.done, req.failed = arrival, True
+            self.failed.append(req)
+            return
+        self.queue.append(req)
 
     def _launch(self):
         items = []
@@ -224,7 +248,8 @@ class Server:
             for req, a, b in zip(items, f1, f2):
                 s = self.sessions[req.sid]
                 if a or b:
-                    raise RuntimeError(f"session {req.sid} flagged {a}/{b}")
+                    self._evict(s, (a & 0xff) | ((b & 0xff) << 8), t)
+                    continue
                 s.cur, s.nxt = s.nxt, s.cur
                 req.done = t
                 self.done.append(req)
@@ -284,8 +309,10 @@ def run(templates, rate=2000.0, duration=2.0, steps_per_session=8, seed=9,
         if now() > duration * 50 + 120:
             raise RuntimeError("serving run did not finish")
     wall = now()
-    lat = np.array([r.done - r.arrival for r in srv.done])
-    res = dict(requests=len(srv.done), sessions=n_sess, launches=srv.launches,
+    lat = np.array([r.done - r.arrival for r in srv.done]) if srv.done else np.zeros(1)
+    res = dict(requests=len(srv.done), failed_requests=len(srv.failed),
+               evicted_sessions=sum(1 for x in srv.sessions.values() if x.error),
+               sessions=n_sess, launches=srv.launches,
                mean_batch=float(np.mean(srv.batch_sizes)) if srv.batch_sizes else 0.0,
                p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
                cell_updates_per_s=srv.cells_done / wall, wall_s=wall, offered_rate=rate,
