@@ -144,6 +144,26 @@ int rich_stage(const rich_mesh* m, const rich_state* src, const rich_state* base
                rich_state* out, double h, const rich_params* p, void* ws,
                size_t ws_bytes, void* stream);
 
+/*
+ * rich_stage with a record of the decisions the scheme takes (for comparing
+ * branches with an independent implementation; its outputs equal rich_stage's
+ * bit for bit).  Device arrays, caller-owned:
+ *   cell_bits[n_cells]  bit 0  shock flag of the switching limiter (section
+ *                              2.2: compression or pressure jump)
+ *                       bit 1  cell-rounding correction applied (section 6:
+ *                              centroid offset above eta R)
+ *                       bits 2-5  alpha < 1 for rho, vx, vy, p (section 2.2)
+ *   edge_bits[n_edges]  HLLC (section 2.4): bit 0 = (0 <= S_L),
+ *                       bit 1 = (0 <= S*), bit 2 = (0 < S_R); exact solver:
+ *                       bit 1 = (0 <= u*), the side of the contact sampled;
+ *                       bit 3 = no flux could be formed (vacuum, bad index)
+ * The edge record is taken by a separate launch after the cell pass; the
+ * arithmetic is the stage's own.  RICH_E_INVAL for null record pointers.
+ */
+int rich_stage_debug(const rich_mesh* m, const rich_state* src, const rich_state* base,
+                     rich_state* out, double h, const rich_params* p, void* ws,
+                     size_t ws_bytes, uint8_t* cell_bits, uint8_t* edge_bits, void* stream);
+
 /* Synchronise `stream` and return the flag word of the last stage that used
  * workspace ws (RICH_FLAG_* bits; 0 when all produced cells are valid). */
 int rich_stage_flags(void* ws, void* stream, int32_t* flags);

@@ -324,14 +324,20 @@ static void phys_flux(double g, const double* W, double* F) {
  * both outer waves; the star-region flux is the flux of the star state with
  * pressure p*_K = p_K + rho_K (S_K - u_K)(S* - u_K), which equals the
  * Rankine-Hugoniot form F_K + S_K (U*_K - U_K). */
-void or_hllc(double g, const double* WL, const double* WR, double* F) {
+static void hllc_speeds(double g, const double* WL, const double* WR, double* sl,
+                        double* ss, double* sr) {
   double rl = WL[0], ul = WL[1], pl = WL[3];
   double rr = WR[0], ur = WR[1], pr = WR[3];
   double cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
-  double sl = fmin(ul - cl, ur - cr);
-  double sr = fmax(ul + cl, ur + cr);
-  double ss = (pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur)) /
-              (rl * (sl - ul) - rr * (sr - ur));
+  *sl = fmin(ul - cl, ur - cr);
+  *sr = fmax(ul + cl, ur + cr);
+  *ss = (pr - pl + rl * ul * (*sl - ul) - rr * ur * (*sr - ur)) /
+        (rl * (*sl - ul) - rr * (*sr - ur));
+}
+
+void or_hllc(double g, const double* WL, const double* WR, double* F) {
+  double sl, ss, sr;
+  hllc_speeds(g, WL, WR, &sl, &ss, &sr);
   /* branch order: 0 <= S_L -> F_L; 0 <= S* -> F*_L; 0 < S_R -> F*_R; F_R */
   if (0.0 <= sl) {
     phys_flux(g, WL, F);
@@ -520,56 +526,69 @@ static void face_state(const double* prim, const double* lgrad, int64_t n, int64
              lgrad[(int64_t)(2 * q + 1) * n + i] * dy;
 }
 
+/* The Riemann states of edge e in its own frame (WL on e_i's side), the
+ * edge normal (nx, ny) and the edge velocity (wex, wey). */
+static void edge_frame(const or_mesh* m, const double* prim, const double* lgrad,
+                       const double* w, int64_t e, double* WL, double* WR, double* nx_out,
+                       double* ny_out, double* wex_out, double* wey_out) {
+  int64_t n = m->n_cells;
+  double Lx = m->box[2] - m->box[0], Ly = m->box[3] - m->box[1];
+  int64_t i = m->e_i[e];
+  int code = nb_code(m->e_j[e]);
+  double fx = m->e_fx[e], fy = m->e_fy[e];
+  double phiL[4], phiR[4];
+  face_state(prim, lgrad, n, i, fx - m->sx[i], fy - m->sy[i], phiL);
+  double nx, ny, wex, wey;
+  if (is_wall(code)) {
+    nx = (code == 9) ? -1.0 : (code == 10 ? 1.0 : 0.0);
+    ny = (code == 11) ? -1.0 : (code == 12 ? 1.0 : 0.0);
+    double tx = -ny, ty = nx;
+    double wn = w[i] * nx + w[n + i] * ny;
+    wex = w[i] - wn * nx;
+    wey = w[n + i] - wn * ny;
+    double vx = phiL[1] - wex, vy = phiL[2] - wey;
+    WL[0] = phiL[0]; WL[1] = vx * nx + vy * ny; WL[2] = vx * tx + vy * ty; WL[3] = phiL[3];
+    WR[0] = phiL[0]; WR[1] = -WL[1]; WR[2] = WL[2]; WR[3] = phiL[3];
+  } else {
+    int64_t j = nb_cell(m->e_j[e]);
+    double shx = 0.0, shy = 0.0;
+    if (code >= 1 && code <= 8) {
+      double a, b;
+      code_shift(code, &a, &b);
+      shx = a * Lx;
+      shy = b * Ly;
+    }
+    double rjx = m->px[j] + shx, rjy = m->py[j] + shy;
+    double sjx = m->sx[j] + shx, sjy = m->sy[j] + shy;
+    face_state(prim, lgrad, n, j, fx - sjx, fy - sjy, phiR);
+    double dx = rjx - m->px[i], dy = rjy - m->py[i];
+    double d = sqrt(dx * dx + dy * dy);
+    nx = dx / d;
+    ny = dy / d;
+    double tx = -ny, ty = nx;
+    double cx = fx - 0.5 * (m->px[i] + rjx), cy = fy - 0.5 * (m->py[i] + rjy);
+    double wix = w[i], wiy = w[n + i], wjx = w[j], wjy = w[n + j];
+    double a = ((wix - wjx) * cx + (wiy - wjy) * cy) / d;
+    wex = 0.5 * (wix + wjx) + a * nx;
+    wey = 0.5 * (wiy + wjy) + a * ny;
+    double vlx = phiL[1] - wex, vly = phiL[2] - wey;
+    double vrx = phiR[1] - wex, vry = phiR[2] - wey;
+    WL[0] = phiL[0]; WL[1] = vlx * nx + vly * ny; WL[2] = vlx * tx + vly * ty; WL[3] = phiL[3];
+    WR[0] = phiR[0]; WR[1] = vrx * nx + vry * ny; WR[2] = vrx * tx + vry * ty; WR[3] = phiR[3];
+  }
+  *nx_out = nx;
+  *ny_out = ny;
+  *wex_out = wex;
+  *wey_out = wey;
+}
+
 int or_edge_fluxes(const or_mesh* m, const double* prim, const double* lgrad,
                    const double* w, const or_params* p, double* flux) {
-  int64_t n = m->n_cells, ne = m->n_edges;
-  double Lx = m->box[2] - m->box[0], Ly = m->box[3] - m->box[1];
+  int64_t ne = m->n_edges;
   int bad = 0;
   for (int64_t e = 0; e < ne; ++e) {
-    int64_t i = m->e_i[e];
-    int code = nb_code(m->e_j[e]);
-    double fx = m->e_fx[e], fy = m->e_fy[e];
-    double phiL[4], phiR[4];
-    face_state(prim, lgrad, n, i, fx - m->sx[i], fy - m->sy[i], phiL);
-    double nx, ny, wex, wey;
-    double WL[4], WR[4];
-    if (is_wall(code)) {
-      nx = (code == 9) ? -1.0 : (code == 10 ? 1.0 : 0.0);
-      ny = (code == 11) ? -1.0 : (code == 12 ? 1.0 : 0.0);
-      double tx = -ny, ty = nx;
-      double wn = w[i] * nx + w[n + i] * ny;
-      wex = w[i] - wn * nx;
-      wey = w[n + i] - wn * ny;
-      double vx = phiL[1] - wex, vy = phiL[2] - wey;
-      WL[0] = phiL[0]; WL[1] = vx * nx + vy * ny; WL[2] = vx * tx + vy * ty; WL[3] = phiL[3];
-      WR[0] = phiL[0]; WR[1] = -WL[1]; WR[2] = WL[2]; WR[3] = phiL[3];
-    } else {
-      int64_t j = nb_cell(m->e_j[e]);
-      double shx = 0.0, shy = 0.0;
-      if (code >= 1 && code <= 8) {
-        double a, b;
-        code_shift(code, &a, &b);
-        shx = a * Lx;
-        shy = b * Ly;
-      }
-      double rjx = m->px[j] + shx, rjy = m->py[j] + shy;
-      double sjx = m->sx[j] + shx, sjy = m->sy[j] + shy;
-      face_state(prim, lgrad, n, j, fx - sjx, fy - sjy, phiR);
-      double dx = rjx - m->px[i], dy = rjy - m->py[i];
-      double d = sqrt(dx * dx + dy * dy);
-      nx = dx / d;
-      ny = dy / d;
-      double tx = -ny, ty = nx;
-      double cx = fx - 0.5 * (m->px[i] + rjx), cy = fy - 0.5 * (m->py[i] + rjy);
-      double wix = w[i], wiy = w[n + i], wjx = w[j], wjy = w[n + j];
-      double a = ((wix - wjx) * cx + (wiy - wjy) * cy) / d;
-      wex = 0.5 * (wix + wjx) + a * nx;
-      wey = 0.5 * (wiy + wjy) + a * ny;
-      double vlx = phiL[1] - wex, vly = phiL[2] - wey;
-      double vrx = phiR[1] - wex, vry = phiR[2] - wey;
-      WL[0] = phiL[0]; WL[1] = vlx * nx + vly * ny; WL[2] = vlx * tx + vly * ty; WL[3] = phiL[3];
-      WR[0] = phiR[0]; WR[1] = vrx * nx + vry * ny; WR[2] = vrx * tx + vry * ty; WR[3] = phiR[3];
-    }
+    double WL[4], WR[4], nx, ny, wex, wey;
+    edge_frame(m, prim, lgrad, w, e, WL, WR, &nx, &ny, &wex, &wey);
     double F[4];
     if (p->riemann == 1) {
       if (or_exact(p->gamma, WL, WR, F, NULL) < 0) bad = 1;
@@ -582,6 +601,34 @@ int or_edge_fluxes(const or_mesh* m, const double* prim, const double* lgrad,
     flux[ne + e] = fpx + F[0] * wex;
     flux[2 * ne + e] = fpy + F[0] * wey;
     flux[3 * ne + e] = F[3] + fpx * wex + fpy * wey + 0.5 * (wex * wex + wey * wey) * F[0];
+  }
+  return bad ? OR_E_DOMAIN : OR_OK;
+}
+
+/* The quantities whose signs pick the Riemann solver's branch on every edge
+ * (section 2.4), for comparing branch records: HLLC S_L, S*, S_R; exact
+ * solver NaN, u*, NaN; and a velocity scale |u_L| + c_L + |u_R| + c_R of the
+ * edge's two states. */
+int or_edge_waves(const or_mesh* m, const double* prim, const double* lgrad,
+                  const double* w, const or_params* p, double* waves) {
+  int64_t ne = m->n_edges;
+  int bad = 0;
+  for (int64_t e = 0; e < ne; ++e) {
+    double WL[4], WR[4], nx, ny, wex, wey;
+    edge_frame(m, prim, lgrad, w, e, WL, WR, &nx, &ny, &wex, &wey);
+    double sl = NAN, ss = NAN, sr = NAN;
+    if (p->riemann == 1) {
+      double F[4], star[2] = {NAN, NAN};
+      if (or_exact(p->gamma, WL, WR, F, star) < 0) bad = 1;
+      ss = star[1];
+    } else {
+      hllc_speeds(p->gamma, WL, WR, &sl, &ss, &sr);
+    }
+    waves[e] = sl;
+    waves[ne + e] = ss;
+    waves[2 * ne + e] = sr;
+    waves[3 * ne + e] = fabs(WL[1]) + sqrt(p->gamma * WL[3] / WL[0]) + fabs(WR[1]) +
+                        sqrt(p->gamma * WR[3] / WR[0]);
   }
   return bad ? OR_E_DOMAIN : OR_OK;
 }

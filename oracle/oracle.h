@@ -79,6 +79,12 @@ int or_limiter(const or_mesh* m, const double* prim, const double* grad,
 int or_edge_fluxes(const or_mesh* m, const double* prim, const double* lgrad,
                    const double* w, const or_params* p, double* flux);
 
+/* Branch quantities of the Riemann solver on every edge (section 2.4), for
+ * comparing branch records, waves[4E] planar: HLLC S_L | S* | S_R | scale;
+ * exact solver NaN | u* | NaN | scale; scale = |u_L| + c_L + |u_R| + c_R. */
+int or_edge_waves(const or_mesh* m, const double* prim, const double* lgrad,
+                  const double* w, const or_params* p, double* waves);
+
 /* Area change rate of every cell implied by the edge velocities (eq. areachange) */
 int or_area_rate(const or_mesh* m, const double* w, double* adot);
 

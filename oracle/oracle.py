@@ -97,6 +97,7 @@ def lib():
         L.or_gradients.argtypes = [mp, _dp, _dp]
         L.or_limiter.argtypes = [mp, _dp, _dp, pp, _dp, _ip]
         L.or_edge_fluxes.argtypes = [mp, _dp, _dp, _dp, pp, _dp]
+        L.or_edge_waves.argtypes = [mp, _dp, _dp, _dp, pp, _dp]
         L.or_area_rate.argtypes = [mp, _dp, _dp]
         L.or_stage.argtypes = [mp, _dp, _dp, _dp, C.c_double, pp, _dp, _dp, _dp, _dp,
                                _dp, _ip, _dp]
@@ -108,7 +109,7 @@ def lib():
         L.or_exact.argtypes = [C.c_double, _dp, _dp, _dp, _dp]
         L.or_exact_sample.argtypes = [C.c_double, _dp, _dp, C.c_double, _dp]
         for f in ("or_primitives", "or_point_velocity", "or_gradients", "or_limiter",
-                  "or_edge_fluxes", "or_area_rate", "or_stage", "or_cfl_dt", "or_exact",
+                  "or_edge_fluxes", "or_edge_waves", "or_area_rate", "or_stage", "or_cfl_dt", "or_exact",
                   "or_exact_sample", "or_voronoi"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -191,6 +192,18 @@ def edge_fluxes(mesh, prim, lgrad, w, p: Params):
     st = lib().or_edge_fluxes(C.byref(m.s), _d(prim), _d(lgrad), _d(w), C.byref(p.c()),
                               _d(F))
     return F, st
+
+
+def edge_waves(mesh, prim, lgrad, w, p: Params):
+    """(4, E): the quantities whose signs pick the Riemann solver's branch
+    on each edge (HLLC: S_L, S*, S_R; exact: NaN, u*, NaN) and a velocity
+    scale of the edge's two states."""
+    m = _MeshRef(mesh)
+    prim, lgrad, w = _f64(prim, (5, m.n)), _f64(lgrad, (8, m.n)), _f64(w, (2, m.n))
+    out = np.empty((4, m.ne))
+    st = lib().or_edge_waves(C.byref(m.s), _d(prim), _d(lgrad), _d(w), C.byref(p.c()),
+                             _d(out))
+    return out, st
 
 
 def area_rate(mesh, w):

@@ -214,8 +214,10 @@ __device__ __forceinline__ void phys_flux(double g, double rgm1, const double* W
 
 // HLLC with Davis wave-speed bounds; star fluxes are the physical fluxes of
 // the star states (identical to the Rankine-Hugoniot form).
+// br (debug record, may be null): bit 0 = (0 <= S_L), bit 1 = (0 <= S*),
+// bit 2 = (0 < S_R), the three comparisons that pick the flux.
 __device__ inline void hllc(double g, double rgm1, const double* WL, const double* WR,
-                            double* F) {
+                            double* F, uint8_t* br = nullptr) {
   const double rl = WL[0], ul = WL[1], pl = WL[3];
   const double rr = WR[0], ur = WR[1], pr = WR[3];
   const double cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
@@ -223,6 +225,8 @@ __device__ inline void hllc(double g, double rgm1, const double* WL, const doubl
   const double sr = fmax(ul + cl, ur + cr);
   const double ss = (pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur)) /
                     (rl * (sl - ul) - rr * (sr - ur));
+  if (br != nullptr)
+    *br = (uint8_t)((0.0 <= sl ? 1 : 0) | (0.0 <= ss ? 2 : 0) | (0.0 < sr ? 4 : 0));
   if (0.0 <= sl) {
     phys_flux(g, rgm1, WL, F);
     return;
@@ -263,13 +267,16 @@ __device__ __forceinline__ void pfun(double g, double ps, double rk, double pk, 
   }
 }
 
+// br (debug record, may be null): bit 1 = (0 <= u*), the side of the contact
+// sampled at x/t = 0; bit 3 = the states would create a vacuum.
 __device__ inline bool exact_flux(double g, double rgm1, const double* WL, const double* WR,
-                                  double* F) {
+                                  double* F, uint8_t* br = nullptr) {
   const double rl = WL[0], ul = WL[1], pl = WL[3];
   const double rr = WR[0], ur = WR[1], pr = WR[3];
   const double cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
   if (2.0 / (g - 1.0) * (cl + cr) <= ur - ul) {
     F[0] = F[1] = F[2] = F[3] = 0.0;
+    if (br != nullptr) *br = 8;
     return false;
   }
   const double tiny = 1e-14;
@@ -289,6 +296,7 @@ __device__ inline bool exact_flux(double g, double rgm1, const double* WL, const
   pfun(g, ps, rl, pl, cl, fl, fld);
   pfun(g, ps, rr, pr, cr, fr, frd);
   const double us = 0.5 * (ul + ur) + 0.5 * (fr - fl);
+  if (br != nullptr) *br = (uint8_t)(0.0 <= us ? 2 : 0);
   // sample at x/t = 0
   const double g1 = (g - 1.0) / (2.0 * g), g2 = (g + 1.0) / (2.0 * g);
   const double g3 = 2.0 * g / (g - 1.0), g4 = 2.0 / (g - 1.0), g5 = 2.0 / (g + 1.0);
@@ -359,11 +367,12 @@ __device__ __forceinline__ void load_rec(const double* __restrict__ rec, int c, 
 }
 
 // The flux of edge e = (i, ej) with midpoint (fx, fy), length L; point r_i
-// and the records of both sides given (rj unused for a wall).
+// and the records of both sides given (rj unused for a wall).  br, when not
+// null, receives the Riemann solver's branch record.
 template <int RIEMANN>
 __device__ inline bool edge_flux_at(const RunDesc& d, int i, uint32_t ej, double fx, double fy,
                                     double L, double rix, double riy, const double* ri,
-                                    const double* rj_in, double* LF) {
+                                    const double* rj_in, double* LF, uint8_t* br = nullptr) {
   bool ok = true;
   const int code = (int)(ej >> 28);
   double phL[4], phR[4];
@@ -420,9 +429,9 @@ __device__ inline bool edge_flux_at(const RunDesc& d, int i, uint32_t ej, double
   }
   double F[4];
   if (RIEMANN == 1) {
-    if (!exact_flux(d.gamma, d.rgm1, WL, WR, F)) ok = false;
+    if (!exact_flux(d.gamma, d.rgm1, WL, WR, F, br)) ok = false;
   } else {
-    hllc(d.gamma, d.rgm1, WL, WR, F);
+    hllc(d.gamma, d.rgm1, WL, WR, F, br);
   }
   const double tx = -ny, ty = nx;
   const double fpx = F[1] * nx + F[2] * tx, fpy = F[1] * ny + F[2] * ty;

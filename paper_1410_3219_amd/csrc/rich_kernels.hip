@@ -169,11 +169,15 @@ __device__ __forceinline__ double block_min_cells(double t) {
   return m;
 }
 
-template <int LPC, bool BATCH>
+// DBG: also write each cell's branch record to dbg[i]: bit 0 the shock
+// flag, bit 1 the cell-rounding correction applied, bits 2..5 alpha < 1 for
+// rho, vx, vy, p.  The production instantiations have DBG = false.
+template <int LPC, bool BATCH, bool DBG = false>
 __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc one,
                                                        const RunDesc* __restrict__ descs,
                                                        const int32_t* __restrict__ tile_start,
-                                                       int n_runs, int n_tiles) {
+                                                       int n_runs, int n_tiles,
+                                                       uint8_t* __restrict__ dbg) {
   constexpr int CPB = kCellThreads / LPC;  // cells per block
   constexpr int MAXE = RICH_CELL_MAXE / LPC;  // entries per lane whose edge offsets stay in registers
   const int lane = (int)threadIdx.x % LPC;
@@ -194,6 +198,7 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
     const double c = sqrt(d.gamma * p / rho);
     const double R = sqrt(A / kPi);
     double wx = 0.0, wy = 0.0;
+    bool rounded = false;
     if (d.motion) {
       // A2 (section 6): Lagrangian motion plus the cell-rounding correction
       wx = vx;
@@ -203,6 +208,7 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
       if (dd > d.eta * R) {
         wx += d.chi * c * dx / dd;
         wy += d.chi * c * dy / dd;
+        rounded = true;
       }
     }
     if (d.cfl_blocks != nullptr) {
@@ -467,6 +473,14 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
         dst[k] = make_double2(a0, a1);
       }
       if (bad_any && lane == 0) atomicOr(d.flag, RICH_FLAG_DOMAIN);
+      if constexpr (DBG) {
+        if (lane == 0) {
+          int bits = (shock ? 1 : 0) | (rounded ? 2 : 0);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bits |= (alpha[q] < 1.0 ? 4 << q : 0);
+          dbg[i] = (uint8_t)bits;
+        }
+      }
     }
   }
 }
@@ -491,7 +505,8 @@ __device__ __forceinline__ double wrap_once(double v, double lo, double hi) {
 
 // A5-A7 for edge e from the records of its two cells in the workspace.
 template <int RIEMANN>
-__device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF) {
+__device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF,
+                                             uint8_t* br = nullptr) {
   double ri[kRecDoubles], rj[kRecDoubles];
   if (e < 0 || e >= d.n_edges) {
     LF[0] = LF[1] = LF[2] = LF[3] = 0.0;
@@ -512,7 +527,19 @@ __device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF
   }
   double rix, riy;
   load_point(d, i, rix, riy);
-  return edge_flux_at<RIEMANN>(d, i, ej, er.fx, er.fy, er.L, rix, riy, ri, rj, LF);
+  return edge_flux_at<RIEMANN>(d, i, ej, er.fx, er.fy, er.L, rix, riy, ri, rj, LF, br);
+}
+
+// Debug record of the Riemann solver's branch on every edge (one thread per
+// edge), from the cell records of the stage; arithmetic identical to k_flux.
+template <int RIEMANN>
+__global__ __launch_bounds__(256) void k_edge_bits(RunDesc d, uint8_t* bits) {
+  const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (e >= d.n_edges) return;
+  double LF[4];
+  uint8_t b = 0;
+  if (!flux_of_edge<RIEMANN>(d, e, LF, &b)) b |= 8;
+  bits[e] = b;
 }
 
 template <int RIEMANN, bool BATCH, int TILE = kTile>
@@ -901,16 +928,30 @@ void prof_end(int k, hipStream_t st) {
   if (k >= 0) (void)hipEventRecord(profiler().pending[k].b, st);
 }
 
-int launch_stage(const RunDesc& d, int riemann, hipStream_t st) {
+int launch_stage(const RunDesc& d, int riemann, hipStream_t st, uint8_t* dbg_cell = nullptr,
+                 uint8_t* dbg_edge = nullptr) {
   constexpr int T = rich::kTile;
   const int n_tiles = (d.n + T - 1) / T;
   constexpr int CPB = rich::kCellThreads / rich::kLpc;
   const int n_ctiles = (d.n + CPB - 1) / CPB;
   hipLaunchKernelGGL(rich::k_clear, dim3(1), dim3(64), 0, st, d.flag, d.cfl_min);
   int pc = prof_begin("k_cell", st);
-  hipLaunchKernelGGL((rich::k_cell<rich::kLpc, false>), dim3(n_ctiles), dim3(rich::kCellThreads),
-                     0, st, d, (const RunDesc*)nullptr, (const int32_t*)nullptr, 1, n_ctiles);
+  if (dbg_cell != nullptr)
+    hipLaunchKernelGGL((rich::k_cell<rich::kLpc, false, true>), dim3(n_ctiles),
+                       dim3(rich::kCellThreads), 0, st, d, (const RunDesc*)nullptr,
+                       (const int32_t*)nullptr, 1, n_ctiles, dbg_cell);
+  else
+    hipLaunchKernelGGL((rich::k_cell<rich::kLpc, false>), dim3(n_ctiles),
+                       dim3(rich::kCellThreads), 0, st, d, (const RunDesc*)nullptr,
+                       (const int32_t*)nullptr, 1, n_ctiles, (uint8_t*)nullptr);
   prof_end(pc, st);
+  if (dbg_edge != nullptr && d.n_edges > 0) {
+    const int eb = (int)((d.n_edges + 255) / 256);
+    if (riemann == 1)
+      hipLaunchKernelGGL(rich::k_edge_bits<1>, dim3(eb), dim3(256), 0, st, d, dbg_edge);
+    else
+      hipLaunchKernelGGL(rich::k_edge_bits<0>, dim3(eb), dim3(256), 0, st, d, dbg_edge);
+  }
   if (d.cfl_blocks != nullptr)   // dt from the cell kernel's Courant minima
     hipLaunchKernelGGL(rich::k_cfl_final, dim3(1), dim3(rich::kCflFinalThreads), 0, st,
                        (const double*)d.cfl_blocks, n_ctiles, d.cfl_min, d.cfl,
@@ -1262,6 +1303,20 @@ int rich_stage(const rich_mesh* m, const rich_state* src, const rich_state* base
   return launch_stage(d, p->riemann, static_cast<hipStream_t>(stream));
 }
 
+int rich_stage_debug(const rich_mesh* m, const rich_state* src, const rich_state* base,
+                     rich_state* out, double h, const rich_params* p, void* ws,
+                     size_t ws_bytes, uint8_t* cell_bits, uint8_t* edge_bits, void* stream) {
+  if (!valid_mesh(m) || !valid_params(p) || !ws || !cell_bits || !edge_bits) return RICH_E_INVAL;
+  const int64_t n = m->n_cells;
+  if (!valid_state(src, n, false) || !valid_state(base, n, true) || !valid_state(out, n, true))
+    return RICH_E_INVAL;
+  if (!std::isfinite(h) || h < 0.0) return RICH_E_INVAL;
+  if (out->M == src->M || out->M == base->M || out->x == base->x) return RICH_E_INVAL;
+  if (ws_bytes < run_ws_bytes(n) || (reinterpret_cast<uintptr_t>(ws) & 255)) return RICH_E_NOMEM;
+  RunDesc d = make_desc(m, src, base, out, h, p, static_cast<char*>(ws));
+  return launch_stage(d, p->riemann, static_cast<hipStream_t>(stream), cell_bits, edge_bits);
+}
+
 namespace {
 int stage_with_device_dt(const rich_mesh* m, const rich_state* src, const rich_state* base,
                          rich_state* out, double h_factor, const void* dt_ws, bool courant,
@@ -1336,7 +1391,8 @@ int rich_area_rate(const rich_mesh* m, const rich_state* s, const rich_params* p
   // the cell pass writes the point velocities into the records
   hipLaunchKernelGGL(rich::k_clear, dim3(1), dim3(64), 0, st, d.flag, d.cfl_min);
   hipLaunchKernelGGL((rich::k_cell<rich::kLpc, false>), dim3(n_ctiles), dim3(rich::kCellThreads),
-                     0, st, d, (const RunDesc*)nullptr, (const int32_t*)nullptr, 1, n_ctiles);
+                     0, st, d, (const RunDesc*)nullptr, (const int32_t*)nullptr, 1, n_ctiles,
+                     (uint8_t*)nullptr);
   hipLaunchKernelGGL(rich::k_adot, dim3((d.n + rich::kCflThreads - 1) / rich::kCflThreads),
                      dim3(rich::kCflThreads), 0, st, d, adot);
   return hip_status(hipGetLastError());
@@ -1497,7 +1553,8 @@ int rich_stage_batch_launch(const rich_batch_plan* plan, void* ws, void* stream)
   hipLaunchKernelGGL(rich::k_clear_batch, dim3((n + 255) / 256), dim3(256), 0, st, dd, n);
   int pcl = prof_begin("k_cell", st);
   hipLaunchKernelGGL((rich::k_cell<rich::kLpc, true>), dim3(plan->grid_cell),
-                     dim3(rich::kCellThreads), 0, st, dummy, dd, dpc, n, plan->n_cell_tiles);
+                     dim3(rich::kCellThreads), 0, st, dummy, dd, dpc, n, plan->n_cell_tiles,
+                     (uint8_t*)nullptr);
   prof_end(pcl, st);
   int pfl = prof_begin("k_flux", st);
   for (int k = 0; k < 2; ++k) {

@@ -129,6 +129,8 @@ def lib():
         L.rich_workspace_size.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
         L.rich_stage.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, C.c_size_t, _vp]
         L.rich_stage_flags.argtypes = [_vp, _vp, _ip]
+        L.rich_stage_debug.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, C.c_size_t, _vp, _vp,
+                                       _vp]
         L.rich_cfl_dt.argtypes = [mp, sp, pp, _dp, _vp, C.c_size_t, _vp]
         L.rich_area_rate.argtypes = [mp, sp, pp, _vp, _vp, C.c_size_t, _vp]
         L.rich_stage_courant.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, C.c_size_t, _vp]
@@ -324,6 +326,22 @@ def rich_stage(mesh: DeviceMesh, src: DeviceState, base: DeviceState, out: Devic
                           C.byref(out.c()), float(h), C.byref(params.c()),
                           C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
     _check(st, "rich_stage")
+
+
+def rich_stage_debug(mesh: DeviceMesh, src: DeviceState, base: DeviceState, out: DeviceState,
+                     h, params: Params, ws, stream=None):
+    """rich_stage plus the branch records; returns (cell_bits, edge_bits),
+    uint8 device tensors (bit meanings in rich.h)."""
+    import torch
+    dev = src.Q.device
+    cb = torch.zeros(mesh.n_cells, dtype=torch.uint8, device=dev)
+    eb = torch.zeros(max(mesh.n_edges, 1), dtype=torch.uint8, device=dev)
+    st = lib().rich_stage_debug(C.byref(mesh.c()), C.byref(src.c()), C.byref(base.c()),
+                                C.byref(out.c()), float(h), C.byref(params.c()),
+                                C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(cb.data_ptr()),
+                                C.c_void_p(eb.data_ptr()), _stream_ptr(stream))
+    _check(st, "rich_stage_debug")
+    return cb, eb[:mesh.n_edges]
 
 
 def rich_stage_flags(ws, stream=None):

@@ -368,6 +368,51 @@ def uniform_flow(O):
     assert np.max(np.abs(dx)) < 1e-13
 
 
+def edge_waves_uniform(O):
+    """Branch quantities of the Riemann solvers in a uniform flow on a static
+    mesh (section 2.4, edge frame of section 5): across an interior or
+    periodic edge with unit normal n both states are the flow, so HLLC gives
+    S_L = v.n - c, S* = v.n, S_R = v.n + c and the exact solver u* = v.n;
+    across a reflecting wall the mirror state reverses v.n, so S* = u* = 0
+    and S_L = -|v.n| - c, S_R = |v.n| + c."""
+    g, rho, pr, v = 5.0 / 3.0, 1.0, 0.6, (1.0, 0.5)
+    c = np.sqrt(g * pr / rho)
+    for bc in (1, 0):
+        P = I.uniform_flow(k=10, v=v, rho=rho, p=pr, jitter=0.3, bc=bc)
+        m = mesh(P.px, P.py, P.box, bc)
+        prim = prim_array(np.full(m.n_cells, rho), np.full(m.n_cells, v[0]),
+                          np.full(m.n_cells, v[1]), np.full(m.n_cells, pr), g)
+        zero_g, zero_w = np.zeros((8, m.n_cells)), np.zeros((2, m.n_cells))
+        ej = m.e_j.view(np.uint32).astype(np.int64)
+        code, j = ej >> 28, ej & ((1 << 28) - 1)
+        un = np.empty(m.n_edges)
+        wall = code >= 9
+        for e in range(m.n_edges):
+            if wall[e]:
+                nx, ny = {9: (-1, 0), 10: (1, 0), 11: (0, -1), 12: (0, 1)}[int(code[e])]
+            else:
+                sx, sy = _shift_of(int(code[e])) if code[e] else (0, 0)
+                dx = m.px[j[e]] + sx - m.px[m.e_i[e]]
+                dy = m.py[j[e]] + sy - m.py[m.e_i[e]]
+                nx, ny = dx / np.hypot(dx, dy), dy / np.hypot(dx, dy)
+            un[e] = v[0] * nx + v[1] * ny
+        if bc == 0:
+            assert wall.any()
+        want_ss = np.where(wall, 0.0, un)
+        want_sl = np.where(wall, -np.abs(un) - c, un - c)
+        want_sr = np.where(wall, np.abs(un) + c, un + c)
+        W, st = O.edge_waves(m, prim, zero_g, zero_w, O.Params(gamma=g, motion=0))
+        assert st == 0
+        assert np.abs(W[0] - want_sl).max() < 1e-13
+        assert np.abs(W[1] - want_ss).max() < 1e-13
+        assert np.abs(W[2] - want_sr).max() < 1e-13
+        assert np.abs(W[3] - 2.0 * (np.abs(un) + c)).max() < 1e-13
+        W, st = O.edge_waves(m, prim, zero_g, zero_w, O.Params(gamma=g, motion=0, riemann=1))
+        assert st == 0
+        assert np.isnan(W[0]).all() and np.isnan(W[2]).all()
+        assert np.abs(W[1] - want_ss).max() < 1e-12
+
+
 def free_fall(O):
     """Uniform gas in a uniform external acceleration g (periodic box, points
     moving with the flow, no rounding correction).  Every edge moves with the
@@ -804,4 +849,4 @@ ALL = [gradient_linear, gradient_periodic, tvd_example, limiter_bounds, hllc_cas
        uniform_state_moving, uniform_flow, advection, conservation, galilean,
        mirror_symmetry, shock_detector, point_velocity, cfl_uniform, sod_accuracy,
        free_fall, extrapolated_second_order, voronoi_lattices, voronoi_identities,
-       voronoi_host_agreement]
+       voronoi_host_agreement, edge_waves_uniform]

@@ -39,9 +39,13 @@ MUTATIONS = [
      "psi = (dphi != 0.0) ? fmax(p->theta * (phi_j[q] - phi_i[q]) / dphi, 0.0) : 1.0;",
      "psi = (dphi != 0.0) ? fmax((phi_j[q] - phi_i[q]) / dphi, 0.0) : 1.0;",
      [pins.tvd_example, pins.limiter_bounds]),
+    ("edge waves: star pressure reported for u*",
+     "      ss = star[1];",
+     "      ss = star[0];",
+     [pins.edge_waves_uniform]),
     ("HLLC contact speed: pressure difference reversed",
-     "double ss = (pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur)) /",
-     "double ss = (pl - pr + rl * ul * (sl - ul) - rr * ur * (sr - ur)) /",
+     "*ss = (pr - pl + rl * ul * (*sl - ul) - rr * ur * (*sr - ur)) /",
+     "*ss = (pl - pr + rl * ul * (*sl - ul) - rr * ur * (*sr - ur)) /",
      [pins.hllc_weak_waves]),
     ("HLLC star pressure sign",
      "double ps = pk + rho * (sk - u) * (ss - u);",
