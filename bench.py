@@ -358,6 +358,7 @@ def bench_device_chain(args, R, P, make_state, hm0, dm0, live_final, n_steps, lo
     timed) and is compared with the live chain built on host meshes."""
     import numpy as np
     import torch
+    K = max(1, min(K, n_steps))   # the chain ends at the live chain's step count
     n = hm0.n_cells
     prm = R.Params(gamma=P.gamma, riemann=args.riemann)
     ws = R.workspace(n)

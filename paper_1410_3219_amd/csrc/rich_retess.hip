@@ -15,8 +15,9 @@
 // No polygon is edited: each candidate's bisector is cut down to the part
 // that every other candidate allows (two bounds kept as fractions), and the
 // candidates with a non-empty part are the cell's edges; their parts' ends
-// are the vertices.  The candidates (at most 16, in LDS) are the wall
-// mirrors and the previous neighbours; a neighbour's neighbour enters only
+// are the vertices.  The candidates (in LDS: 12 slots per cell, and 4 more
+// for the mirrors of a walled box) are the wall mirrors and the previous
+// neighbours; a neighbour's neighbour enters only
 // when its bisector crosses the cell those give (one further than twice the
 // largest vertex distance cannot, and is skipped at once).  The loops over
 // candidates have straight-line bodies, so the lanes of a wave stay together.
@@ -44,7 +45,8 @@ namespace retess {
 constexpr uint32_t kMask = 0x0FFFFFFFu;
 constexpr int kShift = 28;
 constexpr int kMaxFan = 20;    // edges of a finished cell (RICH_RETESS_FAN beyond)
-constexpr int kSlots = 16;     // candidate slots of a cell: 4 bounds, neighbours, entrants
+constexpr int kSlots = 16;     // candidate slots of a cell: 4 wall bounds, neighbours, entrants
+constexpr int kSlotsPeriodic = 12;  // without walls: the same room for neighbours and entrants
 constexpr int kRingMax = 64;   // CSR entries read per cell of the previous mesh
 constexpr int kThreads = 64;
 constexpr int kScanThreads = 1024;
@@ -256,15 +258,21 @@ __device__ __forceinline__ bool ccw_before(double ax, double ay, double bx, doub
 // bisector crosses that polygon, into slots that bound nothing; the second
 // pass gives the cell, its area, centroid and edges in counter-clockwise
 // order.  Every slot v is tried against every slot u (a fixed loop with no
-// polygon to edit), so lanes of a wave stay together.
-template <bool B>
+// polygon to edit), so lanes of a wave stay together.  NS slots per cell: the
+// slots take the block's LDS, which sets how many waves a compute unit holds,
+// so runs without walls (no bound slots) use kSlotsPeriodic.  Each launch
+// serves one kind of run (a batch of both kinds takes two launches), so a
+// run's slots, and its results, never depend on the other runs.
+template <bool B, int NS>
 __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
-  __shared__ double s_dx[kSlots * kThreads], s_dy[kSlots * kThreads];
-  __shared__ int32_t s_id[kSlots * kThreads];
+  static_assert(NS <= 32, "slot masks are 32-bit");
+  __shared__ double s_dx[NS * kThreads], s_dy[NS * kThreads];
+  __shared__ int32_t s_id[NS * kThreads];
   int blk;
   const Args& a = block_run<B>(one, bt.cstart, bt, blk);
   const int i = blk * kThreads + threadIdx.x;
   if (i >= a.n) return;
+  if ((a.bc == (int)RICH_BOUNDARY_PERIODIC) != (NS == kSlotsPeriodic)) return;  // the other launch's
   const Slots S{s_dx + threadIdx.x, s_dy + threadIdx.x, s_id + threadIdx.x};
   const double xi = a.x[i], yi = a.y[i];
   int bad = 0;
@@ -308,7 +316,7 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
     if (k0 < 0 || k1 < k0 || k1 > a.p_n_csr) {
       bad |= RICH_RETESS_CLIP;
       k1 = k0;
-    } else if (k1 - k0 > kSlots - nv) {
+    } else if (k1 - k0 > NS - nv) {
       bad |= RICH_RETESS_FAN;
       k1 = k0;
     }
@@ -369,10 +377,10 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
       // a new slot, else one whose bisector bounds nothing (it stays
       // redundant as candidates are added)
       int u = nv;
-      if (nv < kSlots) {
+      if (nv < NS) {
         ++nv;
       } else {
-        const uint32_t usable = ~em & ((1u << kSlots) - 1u);
+        const uint32_t usable = ~em & ((1u << NS) - 1u);
         if (usable == 0u) {
           bad |= RICH_RETESS_FAN;
           break;
@@ -823,10 +831,14 @@ int make_args(const rich_mesh* prev, const double* x, const double* y,
 // gc cell blocks and gs scan blocks in all).
 template <bool B>
 void launch_all(const retess::Args& a, const retess::Batch& bt, int gc, int gs, int n_runs,
-                hipStream_t st) {
+                bool walls, bool periodic, hipStream_t st) {
   using namespace retess;
+  static_assert(kSlotsPeriodic < kSlots, "the two clip launches are told apart by NS");
   hipLaunchKernelGGL(k_rt_begin<B>, dim3(n_runs), dim3(64), 0, st, a.hdr, bt);
-  hipLaunchKernelGGL(k_rt_clip<B>, dim3(gc), dim3(kThreads), 0, st, a, bt);
+  if (walls)
+    hipLaunchKernelGGL((k_rt_clip<B, kSlots>), dim3(gc), dim3(kThreads), 0, st, a, bt);
+  if (periodic)
+    hipLaunchKernelGGL((k_rt_clip<B, kSlotsPeriodic>), dim3(gc), dim3(kThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_classify<B>, dim3(gc), dim3(kThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_scan_local<B>, dim3(gs), dim3(kScanThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_scan_blocks<B>, dim3(n_runs), dim3(kScanThreads), 0, st, a, bt);
@@ -868,7 +880,8 @@ int rich_retess(const rich_mesh* prev, const double* x, const double* y,
   const int64_t n = prev->n_cells;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int gc = (int)((n + retess::kThreads - 1) / retess::kThreads);
-  launch_all<false>(a, retess::Batch{}, gc, L.nb, 1, st);
+  const bool periodic = a.bc == (int)RICH_BOUNDARY_PERIODIC;
+  launch_all<false>(a, retess::Batch{}, gc, L.nb, 1, !periodic, periodic, st);
   return hipGetLastError() == hipSuccess ? RICH_OK : RICH_E_DEVICE;
 }
 
@@ -934,7 +947,12 @@ int rich_retess_batch(int32_t n, const rich_mesh* const* prev, const double* con
   bt.sstart = bt.cstart + n + 1;
   bt.hdr_out = reinterpret_cast<retess::Hdr*>(b + o_hdr);
   bt.n_runs = n;
-  launch_all<true>(args[0], bt, (int)gc, (int)gs, n, st);
+  bool walls = false, periodic = false;
+  for (const retess::Args& r : args) {
+    walls = walls || r.bc != (int)RICH_BOUNDARY_PERIODIC;
+    periodic = periodic || r.bc == (int)RICH_BOUNDARY_PERIODIC;
+  }
+  launch_all<true>(args[0], bt, (int)gc, (int)gs, n, walls, periodic, st);
   return hipGetLastError() == hipSuccess ? RICH_OK : RICH_E_DEVICE;
 }
 
