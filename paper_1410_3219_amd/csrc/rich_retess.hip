@@ -461,24 +461,44 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
 }
 
 // ---------------------------------------------------------------------------
-// keep / own, certification, counts
+// keep / own, certification, counts.  This kernel and the two emit kernels
+// give each cell a group of kGroup lanes, one per slot (a cell's slots are
+// contiguous, so a group's loads and stores are too, and the lanes of a
+// wave do like work); a block still covers kThreads cells.
 // ---------------------------------------------------------------------------
+constexpr int kGroup = 8;
+constexpr int kGroupThreads = kThreads * kGroup;
+static_assert(64 % kGroup == 0, "groups do not straddle waves");
+
+// The group's bits of a wave-wide ballot.
+__device__ __forceinline__ uint32_t group_bits(bool v) {
+  const unsigned long long m = __ballot(v);
+  const int first = (int)(threadIdx.x & 63) & ~(kGroup - 1);
+  return (uint32_t)(m >> first) & ((1u << kGroup) - 1u);
+}
+
 template <bool B>
-__global__ __launch_bounds__(kThreads) void k_rt_classify(Args one, Batch bt) {
+__global__ __launch_bounds__(kGroupThreads) void k_rt_classify(Args one, Batch bt) {
   int blk;
   const Args& a = block_run<B>(one, bt.cstart, bt, blk);
-  __shared__ double s_area[kThreads / 64];
-  __shared__ long long s_drop[kThreads / 64], s_wall[kThreads / 64];
-  const int i = blk * kThreads + threadIdx.x;
+  constexpr int NW = kGroupThreads / 64;
+  __shared__ double s_area[NW];
+  __shared__ long long s_drop[NW], s_wall[NW];
+  const int l = (int)threadIdx.x % kGroup;
+  const int i = blk * kThreads + (int)threadIdx.x / kGroup;
   double area = 0.0;
   long long drop = 0, walls = 0;
+  int n_keep = 0, n_own = 0, bad = 0;
   if (i < a.n) {
     const int d = a.deg[i];
-    area = a.cells[i].area;
-    const double Ri = sqrt(area / kPi);
+    const double Ai = a.cells[i].area;
+    if (l == 0) {
+      area = Ai;
+      if (d == 0 || !(Ai > 0.0)) bad |= RICH_RETESS_CLIP;
+    }
+    const double Ri = sqrt(Ai / kPi);
     const size_t s0 = (size_t)i * kMaxFan;
-    int n_keep = 0, n_own = 0, bad = 0;
-    for (int q = 0; q < d; ++q) {
+    for (int q = l; q < d; q += kGroup) {
       const int32_t id = a.s_nb[s0 + q];
       const int j = (int)((uint32_t)id & kMask);
       const int code = (int)((uint32_t)id >> kShift);
@@ -527,7 +547,14 @@ __global__ __launch_bounds__(kThreads) void k_rt_classify(Args one, Batch bt) {
           fabs(g[1] - fxj) > tol || fabs(g[2] - fyj) > tol)
         bad |= RICH_RETESS_ASYM;
     }
-    if (d == 0 || !(area > 0.0)) bad |= RICH_RETESS_CLIP;
+  }
+  // the cell's counts and flags over its group
+  for (int o = kGroup / 2; o > 0; o >>= 1) {
+    n_keep += __shfl_xor(n_keep, o);
+    n_own += __shfl_xor(n_own, o);
+    bad |= __shfl_xor(bad, o);
+  }
+  if (i < a.n && l == 0) {
     if (bad) atomicOr(&a.hdr->flags, bad);
     a.off[i + 1] = n_keep;  // counts; the scan makes them offsets
     a.eoff[i + 1] = n_own;
@@ -547,7 +574,7 @@ __global__ __launch_bounds__(kThreads) void k_rt_classify(Args one, Batch bt) {
   if (threadIdx.x == 0) {
     double t = 0.0;
     long long u = 0, v = 0;
-    for (int w = 0; w < kThreads / 64; ++w) {
+    for (int w = 0; w < NW; ++w) {
       t += s_area[w];
       u += s_drop[w];
       v += s_wall[w];
@@ -674,59 +701,75 @@ __global__ __launch_bounds__(kScanThreads) void k_rt_scan_add(Args one, Batch bt
 // edge records and CSR entries
 // ---------------------------------------------------------------------------
 template <bool B>
-__global__ __launch_bounds__(kThreads) void k_rt_emit(Args one, Batch bt) {
+__global__ __launch_bounds__(kGroupThreads) void k_rt_emit(Args one, Batch bt) {
   int blk;
   const Args& a = block_run<B>(one, bt.cstart, bt, blk);
-  const int i = blk * kThreads + threadIdx.x;
-  if (i >= a.n || a.hdr->flags != 0) return;
-  // the cell's owned edges, and each one's index into the slot that sees it
-  // from the neighbour's side
+  const int l = (int)threadIdx.x % kGroup;
+  const int i = blk * kThreads + (int)threadIdx.x / kGroup;
+  if (i >= a.n || a.hdr->flags != 0) return;  // whole groups
+  // the cell's owned edges, in slot order from eoff[i], and each one's index
+  // into the slot that sees it from the neighbour's side
   const int d = a.deg[i];
   const size_t s0 = (size_t)i * kMaxFan;
   int e = a.eoff[i];
-  for (int q = 0; q < d; ++q) {
-    if ((a.s_flag[s0 + q] & 3) != 3) continue;
-    const int32_t id = a.s_nb[s0 + q];
-    const double* g = a.s_geo + 3 * (s0 + q);
-    rich_edge r;
-    r.fx = g[1];
-    r.fy = g[2];
-    r.len = g[0];
-    r.i = i;
-    r.j = id;
-    a.edges[e] = r;
-    if ((int)((uint32_t)id >> kShift) < kWallX0) {
-      const int j = (int)((uint32_t)id & kMask);
-      a.s_edge[(size_t)j * kMaxFan + a.s_back[s0 + q]] = e;
+  for (int base = 0; base < d; base += kGroup) {
+    const int q = base + l;
+    const bool owned = q < d && (a.s_flag[s0 + q] & 3) == 3;
+    const uint32_t gm = group_bits(owned);
+    if (owned) {
+      const int ee = e + __popc(gm & ((1u << l) - 1u));
+      const int32_t id = a.s_nb[s0 + q];
+      const double* g = a.s_geo + 3 * (s0 + q);
+      rich_edge r;
+      r.fx = g[1];
+      r.fy = g[2];
+      r.len = g[0];
+      r.i = i;
+      r.j = id;
+      a.edges[ee] = r;
+      if ((int)((uint32_t)id >> kShift) < kWallX0) {
+        const int j = (int)((uint32_t)id & kMask);
+        a.s_edge[(size_t)j * kMaxFan + a.s_back[s0 + q]] = ee;
+      }
     }
-    ++e;
+    e += __popc(gm);
   }
 }
 
 template <bool B>
-__global__ __launch_bounds__(kThreads) void k_rt_emit_csr(Args one, Batch bt) {
+__global__ __launch_bounds__(kGroupThreads) void k_rt_emit_csr(Args one, Batch bt) {
   int blk;
   const Args& a = block_run<B>(one, bt.cstart, bt, blk);
-  const int i = blk * kThreads + threadIdx.x;
-  if (i >= a.n) return;
+  const int l = (int)threadIdx.x % kGroup;
+  const int i = blk * kThreads + (int)threadIdx.x / kGroup;
+  if (i >= a.n) return;  // whole groups
   if (a.hdr->flags != 0) {  // failed: leave a mesh without edges
-    a.off[i + 1] = 0;
-    a.eoff[i + 1] = 0;
-    if (i == 0) {
-      a.off[0] = 0;
-      a.eoff[0] = 0;
+    if (l == 0) {
+      a.off[i + 1] = 0;
+      a.eoff[i + 1] = 0;
+      if (i == 0) {
+        a.off[0] = 0;
+        a.eoff[0] = 0;
+      }
     }
     return;
   }
-  // the cell's CSR entries, counter-clockwise: 2 * edge for its own edges,
-  // 2 * edge + 1 for its neighbours'
+  // the cell's CSR entries, counter-clockwise (slot order): 2 * edge for its
+  // own edges, 2 * edge + 1 for its neighbours'
   const int d = a.deg[i];
   const size_t s0 = (size_t)i * kMaxFan;
   int k = a.off[i], e = a.eoff[i];
-  for (int q = 0; q < d; ++q) {
-    const uint8_t f = a.s_flag[s0 + q];
-    if (!(f & 1)) continue;
-    a.idx[k++] = (f & 2) ? 2 * (e++) : 2 * a.s_edge[s0 + q] + 1;
+  for (int base = 0; base < d; base += kGroup) {
+    const int q = base + l;
+    const uint8_t f = q < d ? a.s_flag[s0 + q] : (uint8_t)0;
+    const uint32_t mk = group_bits((f & 1) != 0);
+    const uint32_t mo = group_bits((f & 2) != 0);
+    const uint32_t below = (1u << l) - 1u;
+    if (f & 1)
+      a.idx[k + __popc(mk & below)] =
+          (f & 2) ? 2 * (e + __popc(mo & below)) : 2 * a.s_edge[s0 + q] + 1;
+    k += __popc(mk);
+    e += __popc(mo);
   }
 }
 
@@ -839,12 +882,12 @@ void launch_all(const retess::Args& a, const retess::Batch& bt, int gc, int gs, 
     hipLaunchKernelGGL((k_rt_clip<B, kSlots>), dim3(gc), dim3(kThreads), 0, st, a, bt);
   if (periodic)
     hipLaunchKernelGGL((k_rt_clip<B, kSlotsPeriodic>), dim3(gc), dim3(kThreads), 0, st, a, bt);
-  hipLaunchKernelGGL(k_rt_classify<B>, dim3(gc), dim3(kThreads), 0, st, a, bt);
+  hipLaunchKernelGGL(k_rt_classify<B>, dim3(gc), dim3(kGroupThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_scan_local<B>, dim3(gs), dim3(kScanThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_scan_blocks<B>, dim3(n_runs), dim3(kScanThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_scan_add<B>, dim3(gs), dim3(kScanThreads), 0, st, a, bt);
-  hipLaunchKernelGGL(k_rt_emit<B>, dim3(gc), dim3(kThreads), 0, st, a, bt);
-  hipLaunchKernelGGL(k_rt_emit_csr<B>, dim3(gc), dim3(kThreads), 0, st, a, bt);
+  hipLaunchKernelGGL(k_rt_emit<B>, dim3(gc), dim3(kGroupThreads), 0, st, a, bt);
+  hipLaunchKernelGGL(k_rt_emit_csr<B>, dim3(gc), dim3(kGroupThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_end<B>, dim3(n_runs), dim3(64), 0, st, a.hdr, bt);
 }
 
