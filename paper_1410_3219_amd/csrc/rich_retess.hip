@@ -243,6 +243,35 @@ __device__ bool bisector_part(const Slots& S, uint32_t vm, int nv, int self, dou
   return true;
 }
 
+// The cells and points of CSR entries k0 .. k0+CH-1 of the previous mesh
+// (those below k1), loaded level by level: entries, then their edges, then
+// the points, each level's loads in flight together.  c[m] = -1 for an entry
+// past k1, out of range, or naming cell `self` (its point load reads cell 0;
+// no edge is read for an entry out of range).
+template <int CH>
+__device__ __forceinline__ void ring_chunk(const Args& a, int k0, int k1, int self, int* c,
+                                           double* cx, double* cy) {
+#pragma unroll
+  for (int m = 0; m < CH; ++m) c[m] = k0 + m < k1 ? a.p_idx[k0 + m] : -1;
+#pragma unroll
+  for (int m = 0; m < CH; ++m) {
+    const int ent = c[m];
+    const int e = ent >> 1;
+    int cell = -1;
+    if (ent >= 0 && e < a.p_n_edges) {  // no load for an entry out of range
+      const rich_edge& pe = a.p_edges[e];
+      cell = (ent & 1) ? pe.i : (int)((uint32_t)pe.j & kMask);
+    }
+    c[m] = (cell < 0 || cell >= a.n || cell == self) ? -1 : cell;
+  }
+#pragma unroll
+  for (int m = 0; m < CH; ++m) {
+    const int cell = c[m] < 0 ? 0 : c[m];
+    cx[m] = a.x[cell];
+    cy[m] = a.y[cell];
+  }
+}
+
 // Counter-clockwise order of directions: the upper half-plane (from angle 0
 // inclusive) before the lower one, then by the sign of the cross product.
 __device__ __forceinline__ bool ccw_before(double ax, double ay, double bx, double by) {
@@ -296,9 +325,9 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
   }
 
   // displacement of cell c from r_i (nearest periodic image) and its id
-  auto displacement = [&](int c, double& dx, double& dy) -> int32_t {
-    dx = a.x[c] - xi;
-    dy = a.y[c] - yi;
+  auto displacement = [&](int c, double xc, double yc, double& dx, double& dy) -> int32_t {
+    dx = xc - xi;
+    dy = yc - yi;
     int code = 0;
     if (periodic) {
       int sx = 0, sy = 0;
@@ -321,15 +350,21 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
       k1 = k0;
     }
   }
-  for (int k = k0; k < k1; ++k) {
-    const int j = prev_neighbour(a, k);
-    if (j < 0 || j >= a.n || j == i) continue;
-    double dx, dy;
-    S.n(nv) = displacement(j, dx, dy);
-    S.x(nv) = dx;
-    S.y(nv) = dy;
-    vm |= 1u << nv;
-    ++nv;
+  constexpr int CH = 8;  // candidates loaded together
+  for (int k = k0; k < k1; k += CH) {
+    int c[CH];
+    double cx[CH], cy[CH];
+    ring_chunk<CH>(a, k, k1, i, c, cx, cy);
+#pragma unroll
+    for (int m = 0; m < CH; ++m) {
+      if (c[m] < 0) continue;
+      double dx, dy;
+      S.n(nv) = displacement(c[m], cx[m], cy[m], dx, dy);
+      S.x(nv) = dx;
+      S.y(nv) = dy;
+      vm |= 1u << nv;
+      ++nv;
+    }
   }
 
   // first pass: the polygon of the bounds and the first ring, and the
@@ -362,36 +397,40 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
       bad |= RICH_RETESS_CLIP;
       break;
     }
-    for (int l = l0; l < l1; ++l) {
-      const int c = prev_neighbour(a, l);
-      if (c < 0 || c >= a.n || c == i) continue;
-      double dx, dy;
-      const int32_t id = displacement(c, dx, dy);
-      if (4.0 * r2 <= dx * dx + dy * dy) continue;
-      bool known = false;
-      for (int v = 0; v < nv; ++v) known = known || (((vm >> v) & 1u) && S.n(v) == id);
-      if (known) continue;
-      double tlo, thi;
-      bool bounded;
-      if (!bisector_part(S, vm, nv, -1, dx, dy, id, tlo, thi, bounded)) continue;
-      // a new slot, else one whose bisector bounds nothing (it stays
-      // redundant as candidates are added)
-      int u = nv;
-      if (nv < NS) {
-        ++nv;
-      } else {
-        const uint32_t usable = ~em & ((1u << NS) - 1u);
-        if (usable == 0u) {
-          bad |= RICH_RETESS_FAN;
-          break;
+    for (int l = l0; l < l1 && !bad; l += CH) {
+      int cc[CH];
+      double ccx[CH], ccy[CH];
+      ring_chunk<CH>(a, l, l1, i, cc, ccx, ccy);
+      for (int m = 0; m < CH; ++m) {
+        if (cc[m] < 0) continue;
+        double dx, dy;
+        const int32_t id = displacement(cc[m], ccx[m], ccy[m], dx, dy);
+        if (4.0 * r2 <= dx * dx + dy * dy) continue;
+        bool known = false;
+        for (int v = 0; v < nv; ++v) known = known || (((vm >> v) & 1u) && S.n(v) == id);
+        if (known) continue;
+        double tlo, thi;
+        bool bounded;
+        if (!bisector_part(S, vm, nv, -1, dx, dy, id, tlo, thi, bounded)) continue;
+        // a new slot, else one whose bisector bounds nothing (it stays
+        // redundant as candidates are added)
+        int u = nv;
+        if (nv < NS) {
+          ++nv;
+        } else {
+          const uint32_t usable = ~em & ((1u << NS) - 1u);
+          if (usable == 0u) {
+            bad |= RICH_RETESS_FAN;
+            break;
+          }
+          u = __ffs(usable) - 1;
         }
-        u = __ffs(usable) - 1;
+        S.x(u) = dx;
+        S.y(u) = dy;
+        S.n(u) = id;
+        vm |= 1u << u;
+        em |= 1u << u;   // holds a cutting candidate now: not reusable
       }
-      S.x(u) = dx;
-      S.y(u) = dy;
-      S.n(u) = id;
-      vm |= 1u << u;
-      em |= 1u << u;   // holds a cutting candidate now: not reusable
     }
   }
 
