@@ -45,7 +45,9 @@ extern "C" {
 #define RICH_E_MESH    -5  /* invalid mesh or tessellation failure             */
 
 /* Per-run flag bits reported by rich_stage_flags. */
-#define RICH_FLAG_DOMAIN 1  /* a produced cell failed the physical checks */
+#define RICH_FLAG_DOMAIN 1  /* a produced cell failed the physical checks, or
+                               the mesh gave a cell a non-positive area or an
+                               entry out of range */
 #define RICH_FLAG_VACUUM 2  /* exact Riemann solver: states create a vacuum */
 
 /* Boundary kinds (same values as rich_tess.h). */

@@ -193,6 +193,7 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
 
     double rix, riy, A, six, siy;
     load_cell(d, i, rix, riy, A, six, siy);
+    if (active && !(A > 0.0 && A < INFINITY)) bad = true;  // a mesh cell without a volume
     double rho, vx, vy, p;
     prim_of(d, i, A, rho, vx, vy, p);
     const double c = sqrt(d.gamma * p / rho);
