@@ -48,6 +48,21 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def totals_drift(Q0, Q1, t_end, steps):
+    """Change of the domain totals of M, Px, Py, E between two states (host
+    arrays), relative to the largest |total| of the quantity's cells times the
+    cell count (so a total that starts at zero is measured against its cells);
+    reported, not a bar: walls exert forces, so only M and E are conserved
+    with walls, all four in a periodic box."""
+    import numpy as np
+    q0, q1 = np.asarray(Q0, dtype=np.float64), np.asarray(Q1, dtype=np.float64)
+    t0, t1 = q0.sum(axis=1), q1.sum(axis=1)
+    scale = np.abs(q0).max(axis=1) * q0.shape[1]
+    rel = np.abs(t1 - t0) / np.where(scale > 0, scale, 1.0)
+    return {"steps": steps, "t_end": t_end,
+            "rel_change": {k: float(v) for k, v in zip(("M", "Px", "Py", "E"), rel)}}
+
+
 def algorithmic_bytes(m, pass2):
     """Bytes one stage must move at least once (cells, state, edges, CSR,
     results): 40 B geometry + 32 B source state per cell, 32 B per edge,
@@ -473,7 +488,9 @@ def bench_config(args, R, T, name, riemann, steps, log):
            "steps": steps, "ms_per_step": ms, "cell_updates_per_s": n / (ms / 1e3),
            "kernel_ms_per_step": kern_ms,
            "roofline_frac": (nbytes / steps) / (kern_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-           "replay_bitwise_equal_to_live": ok}
+           "replay_bitwise_equal_to_live": ok,
+           "conservation": totals_drift(init.Q.cpu().numpy(), live[0].cpu().numpy(),
+                                        float(sum(dts)), steps)}
     log(f"[bench] {name} {out}")
     return out
 
@@ -754,6 +771,7 @@ def main():
             "launches": {k_: v[1] for k_, v in kern.items()},
         },
         "replay_bitwise_equal_to_live": replay_ok,
+        "conservation": totals_drift(Q0, live_final[0].cpu().numpy(), float(sum(dts)), W + K),
         "host_input_stage": {
             "tessellation_s_mean": float(np.mean(tess_times)),
             "tessellations": len(tess_times),
