@@ -317,6 +317,32 @@ def bench_serve(args, R, log):
     return res
 
 
+def bench_serve_moving(args, R, log, rate=500.0):
+    """The serving loop with sessions on moving meshes: each step rebuilds
+    both meshes of every session on the device (batched re-tessellation), so
+    the loop never waits on the host stage.  Same size mix as the static leg
+    (point-explosion templates Lloyd-relaxed), offered at a rate the device
+    sustains, then at ten times that rate for a short time (saturated)."""
+    import math
+    from paper_1410_3219_amd import inputs as I
+    from paper_1410_3219_amd import serve as S
+    s = I.Stream(21)
+    u = s.uniform(8)
+    sizes = [int(round(math.exp(math.log(4096) + x * (math.log(1 << 20) - math.log(4096)))))
+             for x in u]
+    kinds = ["sod" if k % 2 == 0 else "sedov" for k in range(len(sizes))]
+    t0 = time.time()
+    tpl = S.build_templates(sizes, kinds, n_threads=args.threads, moving=True)
+    log(f"[bench] moving serving templates {[t.n for t in tpl]} ({time.time() - t0:.1f}s)")
+    res, _ = S.run(tpl, rate=rate, duration=args.serve_seconds, log=log)
+    sat, _ = S.run(tpl, rate=10 * rate, duration=0.25 * args.serve_seconds, seed=10, log=log)
+    res["saturated"] = {k: sat[k] for k in ("requests", "failed_requests", "launches",
+                                            "mean_batch", "p50_ms", "p99_ms",
+                                            "cell_updates_per_s", "wall_s", "offered_rate",
+                                            "offered_cell_updates_per_s")}
+    return res
+
+
 def bench_extrapolated(args, R, T, P, make_state, hm0, dm0, log, steps=3):
     """The same workload advanced with the extrapolated-fluxes integrator
     (section 2.3, AREPO's scheme: one stage and one tessellation per step).
@@ -785,6 +811,7 @@ def main():
         legs = {
             "batched": lambda: bench_batch(args, R, T, log),
             "served": lambda: bench_serve(args, R, log),
+            "served_moving": lambda: bench_serve_moving(args, R, log),
             "sweep_section6": lambda: bench_sweep(args, log),
             "extrapolated_fluxes": lambda: bench_extrapolated(args, R, T, P, make_state, hm0,
                                                               meshes[0], log),

@@ -409,13 +409,17 @@ def rich_retess_capacity(n_cells):
     return int(ce.value), int(cc.value)
 
 
-def retess_workspace(n_cells, device="cuda"):
-    """Workspace of rich_retess, zeroed (its result header starts cleared)."""
-    import torch
+def rich_retess_workspace_size(n_cells):
     b = C.c_size_t(0)
     _check(lib().rich_retess_workspace_size(int(n_cells), C.byref(b)),
            "rich_retess_workspace_size")
-    return torch.zeros(int(b.value), dtype=torch.uint8, device=device)
+    return int(b.value)
+
+
+def retess_workspace(n_cells, device="cuda"):
+    """Workspace of rich_retess, zeroed (its result header starts cleared)."""
+    import torch
+    return torch.zeros(rich_retess_workspace_size(n_cells), dtype=torch.uint8, device=device)
 
 
 class DeviceMeshBufs:

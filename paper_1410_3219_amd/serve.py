@@ -20,10 +20,18 @@ scheduler:
     launch, which the batched stage keeps independent, go on unaffected.
 
 Meshes are served from a pool of templates tessellated once by the host
-stage and shared read-only by the sessions built on them (static mesh: the
-points do not move, so no tessellation happens inside the loop and the
-measured latency is the device's).  Every launch is asynchronous; the host
-polls completion events.
+stage and shared read-only by the sessions built on them.  With static
+templates the points do not move, so no tessellation happens inside the
+loop and the measured latency is the device's.  With moving templates
+(Lagrangian motion) each session's mesh is rebuilt on the device twice per
+step, batched over the launch's sessions: stage 1, re-tessellation of the
+half-step points, stage 2 on that mesh, re-tessellation of the new points;
+each session keeps three mesh buffers in rotation and a re-tessellation
+workspace.  A step whose device-built mesh is not certified is redone for
+that session with the host stage (as the step driver does), at host speed;
+the loop counts such steps.  The batched re-tessellation uploads its descriptors with a
+wait on the stream, so moving sessions keep one launch pair in flight.
+Static launches are asynchronous; the host polls completion events.
 
 All arithmetic is in the batched HIP stage; this module only schedules.
 """
@@ -50,6 +58,7 @@ class Template:
     params: "R.Params"
     dt: float
     state0: "R.DeviceState" = None   # initial state on the device (copied per session)
+    moving: bool = False             # Lagrangian motion: meshes rebuilt on the device
 
 
 @dataclass
@@ -63,7 +72,12 @@ class Session:
     admitted: bool = False
     bytes: int = 0
     final: tuple = None     # (Q, X) on the host at close, when kept
-    error: int = 0          # stage flags (stage 1 | stage 2 << 8) of an evicted session
+    error: int = 0          # stage flags (stage 1 | stage 2 << 8; 1 << 16: a mesh
+                            # not certified) of an evicted session
+    mesh: "R.DeviceMesh" = None     # moving: the current mesh
+    mbufs: list = None              # moving: three mesh buffers in rotation
+    rws: object = None              # moving: re-tessellation workspace
+    b: int = 0                      # moving: rotation index
 
 
 @dataclass
@@ -76,8 +90,10 @@ class Request:
     failed: bool = False
 
 
-def build_templates(sizes, kinds, seed=11, n_threads=0):
-    """One template per (size, kind): host tessellation once, upload once."""
+def build_templates(sizes, kinds, seed=11, n_threads=0, moving=False):
+    """One template per (size, kind): host tessellation once, upload once;
+    moving: Lagrangian motion with cell rounding (the paper's defaults),
+    else a static mesh."""
     out = []
     for k, (n, kind) in enumerate(zip(sizes, kinds)):
         side = max(2, int(round(math.sqrt(n))))
@@ -86,16 +102,18 @@ def build_templates(sizes, kinds, seed=11, n_threads=0):
             m = T.rich_tess_build(P.px, P.py, P.box, P.bc, n_threads)
             Q = P.state(m.area)
         else:
-            P = I.sedov(k=side, seed=seed + k, lloyd_iters=0)
+            # moving meshes start from Lloyd-relaxed points (regular cells)
+            P = I.sedov(k=side, seed=seed + k, lloyd_iters=5 if moving else 0)
             m = T.rich_tess_build(P.px, P.py, P.box, P.bc, n_threads)
             Q = I.sedov_state(P, m.area)
-        params = R.Params(gamma=P.gamma, motion=0)
+        params = R.Params(gamma=P.gamma, motion=1 if moving else 0)
         dm = R.DeviceMesh.from_host(m)
         X = np.stack([m.px, m.py])
         s = R.DeviceState.from_host(Q, X)
         ws = R.workspace(m.n_cells)
         dt = R.rich_cfl_dt(dm, s, params, ws)
-        out.append(Template(f"{kind}{m.n_cells}", m.n_cells, dm, Q, X, params, 0.5 * dt, s))
+        out.append(Template(f"{kind}{m.n_cells}", m.n_cells, dm, Q, X, params, 0.5 * dt, s,
+                            moving))
     return out
 
 
@@ -115,19 +133,24 @@ class Server:
         import torch
         self.torch = torch
         self.templates = templates
+        self.moving = any(t.moving for t in templates)
+        if self.moving and not all(t.moving for t in templates):
+            raise ValueError("templates are either all moving or all static")
         self.budget = hbm_budget_bytes
         self.keep_final = keep_final
-        self.max_inflight = max_inflight
+        # the batched re-tessellation waits on the stream: one pair in flight
+        self.max_inflight = 1 if self.moving else max_inflight
         self.used = 0
         self.max_used = 0
         self.sessions = {}
         self.waiting = []          # sessions not yet admitted (FIFO)
         self.queue = []            # requests not yet completed, in arrival order
-        self.inflight = []         # [(event, [req], ws1, ws2, host flags)]
+        self.inflight = []         # [(event, [req], ws1, ws2, host flags, retess workspaces)]
         self.ws_pool = []          # idle batch workspaces
         self.busy = set()          # sessions with a request on the device
         self.done = []
         self.failed = []           # requests of evicted sessions
+        self.fallbacks = 0         # moving: steps redone with host-built meshes
         self.launches = 0
         self.batch_sizes = []
         self.cells_done = 0
@@ -135,10 +158,16 @@ class Server:
 
     # -- sessions ---------------------------------------------------------
     @staticmethod
-    def session_bytes(n):
+    def session_bytes(n, moving=False):
         # three state buffers (Q: 32 B, X: 16 B per cell) and the session's
-        # share of the two workspaces of its launch pair
-        return 3 * 48 * n + 2 * R.rich_workspace_size(n)
+        # share of the two workspaces of its launch pair; moving: three mesh
+        # buffers at capacity and a re-tessellation workspace
+        b = 3 * 48 * n + 2 * R.rich_workspace_size(n)
+        if moving:
+            ce, cc = R.rich_retess_capacity(n)
+            mesh = R.CELL_BYTES * n + R.EDGE_BYTES * ce + 8 * (n + 1) + 4 * cc
+            b += 3 * mesh + R.rich_retess_workspace_size(n)
+        return b
 
     def _ws(self, n_cells):
         """A batch workspace for these runs from the pool of idle ones (the
@@ -153,7 +182,7 @@ class Server:
 
     def open_session(self, sid, tpl_index, steps):
         tpl = self.templates[tpl_index]
-        s = Session(sid, tpl, steps, bytes=self.session_bytes(tpl.n))
+        s = Session(sid, tpl, steps, bytes=self.session_bytes(tpl.n, tpl.moving))
         self.sessions[sid] = s
         self.waiting.append(s)
         return s
@@ -168,6 +197,12 @@ class Server:
                 s.cur = R.DeviceState.from_host(s.tpl.Q0, s.tpl.X0)
             s.half = R.DeviceState.empty_like(s.cur)
             s.nxt = R.DeviceState.empty_like(s.cur)
+            if s.tpl.moving:
+                m = s.tpl.mesh
+                s.mesh = m
+                s.mbufs = [R.DeviceMeshBufs(m.n_cells, m.box, m.bc) for _ in range(3)]
+                s.rws = R.retess_workspace(m.n_cells)
+                s.b = 0
             s.admitted = True
             self.used += s.bytes
             self.max_used = max(self.max_used, self.used)
@@ -176,6 +211,7 @@ class Server:
         if self.keep_final:
             s.final = s.cur.numpy()
         s.cur = s.half = s.nxt = None
+        s.mesh = s.mbufs = s.rws = None
         s.admitted = False
         self.used -= s.bytes
 
@@ -215,12 +251,28 @@ class Server:
         ps = [s.tpl.params for s in ss]
         ns = [m.n_cells for m in meshes]
         ws1, ws2 = self._ws(ns), self._ws(ns)
-        # stage 1: (Q^n, Q^n, x^n, dt/2) -> half; stage 2: (half, Q^n, x^n, dt) -> nxt
+        rt = None
+        if self.moving:
+            meshes = [s.mesh for s in ss]
+            hb = [s.mbufs[s.b % 3] for s in ss]
+            nb = [s.mbufs[(s.b + 1) % 3] for s in ss]
+            hmeshes = [b.mesh() for b in hb]
+        else:
+            hmeshes = meshes
+        # stage 1: (Q^n, Q^n, x^n, dt/2) -> half; stage 2: (half, Q^n, x^n, dt) -> nxt,
+        # on the mesh of the half-step points when the points move
         R.rich_stage_batch(meshes, [s.cur for s in ss], [s.cur for s in ss],
                            [s.half for s in ss], [0.5 * s.tpl.dt for s in ss], ps, ws1,
                            self.stream)
-        R.rich_stage_batch(meshes, [s.half for s in ss], [s.cur for s in ss],
+        if self.moving:
+            bws1 = R.rich_retess_batch(meshes, [s.half.X for s in ss], hb,
+                                       [s.rws for s in ss], stream=self.stream)
+        R.rich_stage_batch(hmeshes, [s.half for s in ss], [s.cur for s in ss],
                            [s.nxt for s in ss], [s.tpl.dt for s in ss], ps, ws2, self.stream)
+        if self.moving:
+            bws2 = R.rich_retess_batch(hmeshes, [s.nxt.X for s in ss], nb,
+                                       [s.rws for s in ss], stream=self.stream)
+            rt = (bws1, bws2)
         # both stages' flag words come back with the launch (no stream sync)
         flags = self.torch.empty((2, len(items)), dtype=self.torch.int32, pin_memory=True)
         R.rich_batch_flags_async(len(items), ws1, flags[0], self.stream)
@@ -230,7 +282,7 @@ class Server:
         for r in items:
             r.phase = 1
             self.busy.add(r.sid)
-        self.inflight.append((ev, items, ws1, ws2, flags))
+        self.inflight.append((ev, items, ws1, ws2, flags, rt))
         self.launches += 1
         self.batch_sizes.append(len(items))
         return True
@@ -238,18 +290,36 @@ class Server:
     def _complete(self, now_fn):
         progressed = False
         while self.inflight and self.inflight[0][0].query():
-            ev, items, ws1, ws2, flags = self.inflight.pop(0)
+            ev, items, ws1, ws2, flags, rt = self.inflight.pop(0)
             f1, f2 = flags[0].tolist(), flags[1].tolist()
+            half_ok = [True] * len(items)
+            new_ok = [True] * len(items)
+            if rt is not None:   # both meshes of each session's step
+                half_ok = [r[0] == 0 for r in R.rich_retess_batch_result(len(items), rt[0],
+                                                                        self.stream)]
+                new_ok = [r[0] == 0 for r in R.rich_retess_batch_result(len(items), rt[1],
+                                                                       self.stream)]
             self.ws_pool += [ws1, ws2]
             if len(self.ws_pool) > 4 * self.max_inflight:   # keep the largest idle ones
                 self.ws_pool.sort(key=lambda t: t.numel())
                 del self.ws_pool[:len(self.ws_pool) - 4 * self.max_inflight]
             t = now_fn()
-            for req, a, b in zip(items, f1, f2):
+            for req, a, b, h_ok, n_ok in zip(items, f1, f2, half_ok, new_ok):
                 s = self.sessions[req.sid]
-                if a or b:
+                # stage 2 counts only on a certified half-step mesh
+                if a or (h_ok and b):
                     self._evict(s, (a & 0xff) | ((b & 0xff) << 8), t)
                     continue
+                if self.moving:
+                    if h_ok and n_ok:
+                        s.mesh = s.mbufs[(s.b + 1) % 3].mesh()
+                    else:
+                        f = self._host_step(s, h_ok)
+                        if f:
+                            self._evict(s, (f & 0xff) << 8, t)
+                            continue
+                        self.fallbacks += 1
+                    s.b += 2
                 s.cur, s.nxt = s.nxt, s.cur
                 req.done = t
                 self.done.append(req)
@@ -262,6 +332,26 @@ class Server:
         if progressed:   # one pass over the queue per completion, not per request
             self.queue = [r for r in self.queue if r.done < 0]
         return progressed
+
+    def _host_step(self, s, half_ok):
+        """Finish session s's step with host-built meshes: stage 1 ran on its
+        certified current mesh; if the half-step mesh was not certified,
+        stage 2 is redone on the host stage's mesh of the half-step points;
+        the new mesh is the host stage's.  Returns stage 2's flags."""
+        from . import tess as T
+        m = s.mesh
+        flags = 0
+        if not half_ok:
+            xh = s.half.X.cpu().numpy()
+            hm = R.DeviceMesh.from_host(T.rich_tess_build(xh[0], xh[1], m.box, m.bc))
+            ws = R.workspace(s.tpl.n)
+            R.rich_stage(hm, s.half, s.cur, s.nxt, s.tpl.dt, s.tpl.params, ws, self.stream)
+            flags = R.rich_stage_flags(ws, self.stream)
+            if flags:
+                return flags
+        xn = s.nxt.X.cpu().numpy()
+        s.mesh = R.DeviceMesh.from_host(T.rich_tess_build(xn[0], xn[1], m.box, m.bc))
+        return flags
 
     def tick(self, now_fn):
         self._complete(now_fn)
@@ -310,7 +400,8 @@ def run(templates, rate=2000.0, duration=2.0, steps_per_session=8, seed=9,
             raise RuntimeError("serving run did not finish")
     wall = now()
     lat = np.array([r.done - r.arrival for r in srv.done]) if srv.done else np.zeros(1)
-    res = dict(requests=len(srv.done), failed_requests=len(srv.failed),
+    res = dict(moving=srv.moving, host_fallback_steps=srv.fallbacks,
+               requests=len(srv.done), failed_requests=len(srv.failed),
                evicted_sessions=sum(1 for x in srv.sessions.values() if x.error),
                sessions=n_sess, launches=srv.launches,
                mean_batch=float(np.mean(srv.batch_sizes)) if srv.batch_sizes else 0.0,

@@ -80,3 +80,110 @@ def test_flagged_session_is_evicted_and_others_go_on():
         assert s.error == 0
         ref = _alone(s.tpl, steps)
         assert np.array_equal(s.final[0], ref[0]) and np.array_equal(s.final[1], ref[1])
+
+
+def _alone_moving(tpl, steps):
+    """The same steps with single-run stages and re-tessellations."""
+    import torch
+    from paper_1410_3219_amd import rich as R
+    m = tpl.mesh
+    cur = R.DeviceState.from_host(tpl.Q0, tpl.X0)
+    half = R.DeviceState.empty_like(cur)
+    nxt = R.DeviceState.empty_like(cur)
+    ws = R.workspace(tpl.n)
+    bufs = [R.DeviceMeshBufs(m.n_cells, m.box, m.bc) for _ in range(3)]
+    rws = R.retess_workspace(tpl.n)
+    mesh, b = m, 0
+    for _ in range(steps):
+        hb, nb = bufs[b % 3], bufs[(b + 1) % 3]
+        R.rich_stage(mesh, cur, cur, half, 0.5 * tpl.dt, tpl.params, ws)
+        R.rich_retess(mesh, half.X, hb, rws)
+        assert R.rich_retess_result(rws)[0] == 0
+        R.rich_stage(hb.mesh(), half, cur, nxt, tpl.dt, tpl.params, ws)
+        R.rich_retess(hb.mesh(), nxt.X, nb, rws)
+        assert R.rich_retess_result(rws)[0] == 0
+        mesh, b = nb.mesh(), b + 2
+        cur, nxt = nxt, cur
+    torch.cuda.synchronize()
+    return cur.numpy()
+
+
+def test_served_moving_sessions_match_alone_bitwise():
+    """Sessions on moving meshes (each step: stage 1, device re-tessellation
+    of the half-step points, stage 2, re-tessellation of the new points, all
+    batched over the launch's sessions) end in exactly the state of the same
+    steps run alone; the points do move."""
+    from paper_1410_3219_amd import serve as S
+    tpl = S.build_templates([400, 900, 625], ["sod", "sedov", "sod"], moving=True)
+    res, srv = S.run(tpl, rate=3000.0, duration=0.03, steps_per_session=3, keep_final=True)
+    assert res["moving"] and res["failed_requests"] == 0
+    assert res["requests"] == len(S.I.poisson_arrivals(3000.0, 0.03, 9))
+    per_sess = {}
+    for r in srv.done:
+        per_sess[r.sid] = per_sess.get(r.sid, 0) + 1
+    assert srv.used == 0
+    moved = 0.0
+    for sid, sess in srv.sessions.items():
+        ref = _alone_moving(sess.tpl, per_sess[sid])
+        assert np.array_equal(sess.final[0], ref[0]) and np.array_equal(sess.final[1], ref[1])
+        moved = max(moved, float(np.abs(sess.final[1] - sess.tpl.X0).max()))
+    assert moved > 0.0
+    assert S.Server.session_bytes(900, True) > S.Server.session_bytes(900)
+
+
+def _flower_template():
+    """A walled box whose central cell has 14 neighbours (a point inside a
+    ring of 14), more candidates than a device-rebuilt cell holds: every
+    device mesh of it is reported, not certified."""
+    from paper_1410_3219_amd import inputs as I
+    from paper_1410_3219_amd import rich as R
+    from paper_1410_3219_amd import serve as S
+    from paper_1410_3219_amd import tess as T
+    P = I.sod(k=20, seed=4)
+    keep = np.hypot(P.px - 0.5, P.py - 0.5) > 0.1
+    a = 2 * np.pi * np.arange(14) / 14
+    px = np.concatenate([P.px[keep], [0.5], 0.5 + 0.06 * np.cos(a)])
+    py = np.concatenate([P.py[keep], [0.5], 0.5 + 0.06 * np.sin(a)])
+    m = T.rich_tess_build(px, py, P.box, P.bc)
+    deg = np.diff(m.off)
+    assert deg.max() >= 14
+    n = m.n_cells
+    rho = np.where(px < 0.5, 1.0, 0.125)
+    pr = np.where(px < 0.5, 1.0, 0.1)
+    Q = np.stack([rho * m.area, 0 * m.area, 0 * m.area, pr / (P.gamma - 1) * m.area])
+    X = np.stack([m.px, m.py])
+    params = R.Params(gamma=P.gamma, motion=1)
+    dm = R.DeviceMesh.from_host(m)
+    s = R.DeviceState.from_host(Q, X)
+    dt = 0.5 * R.rich_cfl_dt(dm, s, params, R.workspace(n))
+    return S.Template("flower", n, dm, Q, X, params, dt, s, True), m
+
+
+def test_served_moving_session_falls_back_to_host_meshes():
+    """A session whose device-built meshes are not certified finishes each
+    step on host-built meshes, ending in the state the step driver (device
+    re-tessellation with the host stage as fallback) reaches."""
+    import torch
+    from paper_1410_3219_amd import rich as R
+    from paper_1410_3219_amd import serve as S
+    tpl, m = _flower_template()
+    steps = 3
+    srv = S.Server([tpl], keep_final=True)
+    srv.open_session(0, 0, steps)
+    for k in range(steps):
+        srv.submit(k, 0, 0.0)
+    import time
+    t0 = time.perf_counter()
+    srv.drain(lambda: time.perf_counter() - t0, timeout_s=120.0)
+    assert not srv.failed and srv.fallbacks == steps
+    ctx = R.RichCtx(device_tess=True)
+    ctx.set_mesh(m)
+    st = R.DeviceState.from_host(tpl.Q0, tpl.X0)
+    for _ in range(steps):
+        ctx.step(st, tpl.dt, tpl.params)
+    torch.cuda.synchronize()
+    ref = st.numpy()
+    assert ctx.tess_counts()[1] == 2 * steps   # every mesh built by the host stage
+    ctx.close()
+    fin = srv.sessions[0].final
+    assert np.array_equal(fin[0], ref[0]) and np.array_equal(fin[1], ref[1])
