@@ -125,8 +125,11 @@ class Server:
     step back to back as two batched launches on one stream, so stage 2 needs
     no host round trip; up to `max_inflight` such launch pairs are on the
     device at once, each with its own workspaces, while the host gathers the
-    next.  Sessions are admitted in arrival order while their device memory
-    fits the budget and released when their last request completes."""
+    next.  With moving templates each stage is followed by a batched
+    re-tessellation, whose descriptor upload waits on the stream, so one
+    launch pair is in flight.  Sessions are admitted in arrival order while
+    their device memory fits the budget and released when their last request
+    completes."""
 
     def __init__(self, templates, hbm_budget_bytes=16 << 30, keep_final=False,
                  max_inflight=2):
