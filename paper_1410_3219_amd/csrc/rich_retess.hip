@@ -447,41 +447,63 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
     a.cells[i] = cr;
     return;
   }
-  // second pass: the cell's edges, written in counter-clockwise order, and
-  // the shoelace sums of the triangles they make with the point
-  uint32_t fm = 0;
-  for (int u = 0; u < nv; ++u) {
-    if (!((vm >> u) & 1u)) continue;
-    double tlo, thi;
-    bool bounded;
-    if (bisector_part(S, vm, nv, u, S.x(u), S.y(u), S.n(u), tlo, thi, bounded)) fm |= 1u << u;
-    else if (!bounded) bad |= RICH_RETESS_CLIP;
-  }
-  const int deg = __popc(fm);
-  if (deg < 3 || deg > kMaxFan) bad |= deg > kMaxFan ? RICH_RETESS_FAN : RICH_RETESS_CLIP;
+  // second pass: each candidate's part of its bisector.  A live one (an
+  // edge) is written at once, at its counter-clockwise rank among all the
+  // candidates (same direction: by slot), and its triangle with the point
+  // is added to the shoelace sums in slot order; the positions left by
+  // candidates that bound nothing are closed up afterwards, which leaves
+  // the live ones in counter-clockwise order.
+  uint32_t fm = 0, holes = 0;
   double A2 = 0.0, cx = 0.0, cy = 0.0;
   const size_t s0 = (size_t)i * kMaxFan;
-  for (int u = 0; u < nv && !bad; ++u) {
-    if (!((fm >> u) & 1u)) continue;
+  for (int u = 0; u < nv; ++u) {
+    if (!((vm >> u) & 1u)) continue;
     const double dux = S.x(u), duy = S.y(u);
+    int rank = 0;
+    for (int v = 0; v < nv; ++v) {
+      if (!((vm >> v) & 1u) || v == u) continue;
+      const double vx = S.x(v), vy = S.y(v);
+      rank += (ccw_before(vx, vy, dux, duy) || (v < u && !ccw_before(dux, duy, vx, vy))) ? 1 : 0;
+    }
     double tlo, thi;
     bool bounded;
-    bisector_part(S, vm, nv, u, dux, duy, S.n(u), tlo, thi, bounded);
+    if (!bisector_part(S, vm, nv, u, dux, duy, S.n(u), tlo, thi, bounded)) {
+      if (!bounded) bad |= RICH_RETESS_CLIP;
+      holes |= 1u << rank;
+      continue;
+    }
+    fm |= 1u << u;
     const double ux = 0.5 * dux - tlo * duy, uy = 0.5 * duy + tlo * dux;
     const double wx = 0.5 * dux - thi * duy, wy = 0.5 * duy + thi * dux;
     const double c = ux * wy - uy * wx;
     A2 += c;
     cx += (ux + wx) * c;
     cy += (uy + wy) * c;
-    int rank = 0;
-    for (int v = 0; v < nv; ++v)
-      rank += (((fm >> v) & 1u) && v != u && ccw_before(S.x(v), S.y(v), dux, duy)) ? 1 : 0;
     const double ex = wx - ux, ey = wy - uy;
-    a.s_nb[s0 + rank] = S.n(u);
+    a.s_nb[s0 + rank] = S.n(u);   // rank < number of candidates <= NS < kMaxFan
     double* g = a.s_geo + 3 * (s0 + rank);
     g[0] = sqrt(ex * ex + ey * ey);
     g[1] = xi + 0.5 * (ux + wx);
     g[2] = yi + 0.5 * (uy + wy);
+  }
+  const int deg = __popc(fm);
+  if (deg < 3 || deg > kMaxFan) bad |= deg > kMaxFan ? RICH_RETESS_FAN : RICH_RETESS_CLIP;
+  if (!bad && holes != 0u) {
+    __threadfence_block();  // this lane's row writes above are read back below
+    const int total = __popc(vm);
+    for (int p = 0, q = 0; p < total; ++p) {
+      if ((holes >> p) & 1u) continue;
+      if (q != p) {
+        a.s_nb[s0 + q] = a.s_nb[s0 + p];
+        const double* g = a.s_geo + 3 * (s0 + p);
+        double* h = a.s_geo + 3 * (s0 + q);
+        const double g0 = g[0], g1 = g[1], g2 = g[2];
+        h[0] = g0;
+        h[1] = g1;
+        h[2] = g2;
+      }
+      ++q;
+    }
   }
   if (bad) {
     atomicOr(&a.hdr->flags, bad);
