@@ -143,6 +143,41 @@ def test_retess_matches_oracle_voronoi(name, k):
     assert abs(info["area_sum"] - (m.box[2] - m.box[0]) * (m.box[3] - m.box[1])) < 1e-12
 
 
+@pytest.mark.parametrize("name", ["sod", "wave"])
+def test_retess_after_edge_flips_matches_oracle_voronoi(name):
+    """Points jostled by up to a fifth of the spacing from the previous
+    mesh's points: many previous neighbours no longer share an edge (their
+    candidates bound nothing, and the positions they took in a cell's
+    counter-clockwise order are closed up), new neighbours enter from the
+    second ring; the result is still the oracle's Voronoi mesh."""
+    from paper_1410_3219_amd import rich as R
+    import torch
+    P, m, Q, X = _initial(name, 24)
+    h = math.sqrt((m.box[2] - m.box[0]) * (m.box[3] - m.box[1]) / m.n_cells)
+    d = np.random.default_rng(5).uniform(-0.2 * h, 0.2 * h, X.shape)
+    X1 = X + d
+    if m.bc == 1:
+        X1 = np.stack([np.mod(X1[0] - m.box[0], m.box[2] - m.box[0]) + m.box[0],
+                       np.mod(X1[1] - m.box[1], m.box[3] - m.box[1]) + m.box[1]])
+    else:
+        X1 = np.stack([np.clip(X1[0], m.box[0] + 1e-3 * h, m.box[2] - 1e-3 * h),
+                       np.clip(X1[1], m.box[1] + 1e-3 * h, m.box[3] - 1e-3 * h)])
+    dm = R.DeviceMesh.from_host(m)
+    bufs = R.DeviceMeshBufs(m.n_cells, m.box, m.bc)
+    tws = R.retess_workspace(m.n_cells)
+    R.rich_retess(dm, torch.from_numpy(np.ascontiguousarray(X1)).cuda(), bufs, tws)
+    st, info = R.rich_retess_result(tws)
+    assert st == 0 and info["flags"] == 0, info
+    dev = R.mesh_to_host(bufs.mesh(), info["n_edges"], info["n_csr"])
+    check_structure(dev)
+    ref = O.voronoi_mesh(O.voronoi(X1[0], X1[1], m.box, m.bc))
+    compare_meshes(dev, ref, h)
+    lost = np.setdiff1d(csr_keys(m)[0], csr_keys(ref)[0])
+    gained = np.setdiff1d(csr_keys(ref)[0], csr_keys(m)[0])
+    print(f"\n{name}: {lost.size} CSR entries lost, {gained.size} gained")
+    assert lost.size > 20 and gained.size > 20
+
+
 def test_retess_repeat_is_bitwise_deterministic():
     from paper_1410_3219_amd import rich as R
     P, m, Q, X = _initial("sedov", 30)
