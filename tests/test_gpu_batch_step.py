@@ -342,3 +342,64 @@ def test_step_batch_failure_is_isolated():
             continue
         assert status[0][r] == 0
         assert np.array_equal(res[r][0], good[r][0]) and np.array_equal(res[r][1], good[r][1])
+
+
+def test_batch_full_size_sampled_oracle_parity():
+    """The batched workload at full size (256 shock-tube runs of 1k-65k
+    cells, 4.0M cells in all, interface angle, gamma and rounding strength
+    per run), in the configuration the benchmark replays: each stage as a
+    prepared plan with its autotuned edge-tile shape.  Every run's flags are
+    clear, and sampled runs (the smallest, the largest and six more) equal
+    the oracle's stages to 1e-12 on the same inputs."""
+    import torch
+    from paper_1410_3219_amd import rich as R
+    specs = I.batch_runs(256)
+    runs = []
+    for sp in specs:
+        P = I.sod(k=sp["side"], seed=sp["seed"], angle=sp["angle"], gamma=sp["gamma"])
+        hm = T.rich_tess_build(P.px, P.py, P.box, P.bc)
+        Q0 = P.state(hm.area)
+        X0 = np.stack([hm.px, hm.py])
+        op = O.Params(gamma=sp["gamma"], chi=sp["chi"])
+        dt, st = O.cfl_dt(hm, Q0, op)
+        assert st == 0
+        s0 = R.DeviceState.from_host(Q0, X0)
+        runs.append(dict(hm=hm, Q0=Q0, X0=X0, op=op, dt=dt, dm=R.DeviceMesh.from_host(hm),
+                         s0=s0, half=R.DeviceState.empty_like(s0),
+                         out=R.DeviceState.empty_like(s0)))
+    total = sum(r["hm"].n_cells for r in runs)
+    assert 3.5e6 < total < 4.5e6
+    ps = [U.gpu_params(r["op"]) for r in runs]
+    ws = R.batch_workspace([r["hm"].n_cells for r in runs])
+    a1 = ([r["dm"] for r in runs], [r["s0"] for r in runs], [r["s0"] for r in runs],
+          [r["half"] for r in runs], [0.5 * r["dt"] for r in runs], ps)
+    tile1, _ = R.rich_stage_batch_autotune(*a1, ws, reps=1)
+    R.rich_stage_batch_launch(R.rich_stage_batch_prepare_tile(*a1, tile1, ws), ws)
+    assert R.rich_batch_flags(len(runs), ws) == [0] * len(runs)
+    for r in runs:   # the half-step meshes of the GPU's half-step points
+        xh = r["half"].X.cpu().numpy()
+        r["hmh"] = T.rich_tess_build(xh[0], xh[1], r["hm"].box, r["hm"].bc)
+        r["dmh"] = R.DeviceMesh.from_host(r["hmh"])
+    a2 = ([r["dmh"] for r in runs], [r["half"] for r in runs], [r["s0"] for r in runs],
+          [r["out"] for r in runs], [r["dt"] for r in runs], ps)
+    tile2, _ = R.rich_stage_batch_autotune(*a2, ws, reps=1)
+    R.rich_stage_batch_launch(R.rich_stage_batch_prepare_tile(*a2, tile2, ws), ws)
+    assert R.rich_batch_flags(len(runs), ws) == [0] * len(runs)
+    torch.cuda.synchronize()
+    sizes = np.array([r["hm"].n_cells for r in runs])
+    pick = {int(sizes.argmin()), int(sizes.argmax())}
+    pick |= set(np.random.default_rng(3).choice(len(runs), 6, replace=False).tolist())
+    for k in sorted(pick):
+        r = runs[k]
+        Qh, Xh = r["half"].numpy()
+        ref1 = O.stage(r["hm"], r["Q0"], r["Q0"], r["X0"], 0.5 * r["dt"], r["op"])
+        assert ref1.status == 0
+        eq, ex = U.errors(r["hm"], Qh, Xh, ref1.Q, ref1.X, r["Q0"], r["op"])
+        assert (eq < U.TOL).all() and ex < U.TOL, (k, 1, eq, ex)
+        Qo, Xo = r["out"].numpy()
+        ref2 = O.stage(r["hmh"], Qh, r["Q0"], r["X0"], r["dt"], r["op"])
+        assert ref2.status == 0
+        eq, ex = U.errors(r["hmh"], Qo, Xo, ref2.Q, ref2.X, Qh, r["op"])
+        assert (eq < U.TOL).all() and ex < U.TOL, (k, 2, eq, ex)
+    print(f"\n{len(runs)} runs, {total} cells, tiles {tile1}/{tile2}, "
+          f"{len(pick)} runs checked against the oracle")
