@@ -194,3 +194,33 @@ def test_full_size_wave_stage(integrator):
     eq, ex = U.errors(m, Qg, Xg, ref.Q, ref.X, Q, p)
     print(f"\nfull size, integrator {integrator}: err M,Px,Py,E={eq} x={ex}", flush=True)
     assert (eq < U.TOL).all() and ex < U.TOL, (eq, ex)
+
+
+def test_full_size_point_explosion_step():
+    """The point-explosion configuration at full size (262 144 uniform-random
+    points Lloyd-relaxed 5 times, walls, E = 1 in the centre cell, exact and
+    HLLC solvers): both stages of a time-centred step, each compared with
+    the oracle on every cell from the same inputs."""
+    P = I.sedov(k=512, seed=2, lloyd_iters=5)
+    m = T.rich_tess_build(P.px, P.py, P.box, P.bc)
+    Q = I.sedov_state(P, m.area)
+    X = np.stack([m.px, m.py])
+    for riemann in (0, 1):
+        p = O.Params(gamma=P.gamma, riemann=riemann)
+        dt, st = O.cfl_dt(m, Q, p)
+        assert st == 0
+        ref1 = O.stage(m, Q, Q, X, 0.5 * dt, p)
+        assert ref1.status == 0
+        Qh, Xh, flags = U.gpu_stage(m, Q, Q, X, 0.5 * dt, p)
+        assert flags == 0
+        eq, ex = U.errors(m, Qh, Xh, ref1.Q, ref1.X, Q, p)
+        assert (eq < U.TOL).all() and ex < U.TOL, (riemann, 1, eq, ex)
+        mh = T.rich_tess_build(Xh[0], Xh[1], m.box, m.bc)
+        ref2 = O.stage(mh, Qh, Q, X, dt, p)
+        assert ref2.status == 0
+        Qn, Xn, flags = U.gpu_stage(mh, Qh, Q, X, dt, p)
+        assert flags == 0
+        eq2, ex2 = U.errors(mh, Qn, Xn, ref2.Q, ref2.X, Qh, p)
+        print(f"\nsedov 512^2 riemann={riemann}: stage 1 {eq.max():.2e}, stage 2 {eq2.max():.2e}",
+              flush=True)
+        assert (eq2 < U.TOL).all() and ex2 < U.TOL, (riemann, 2, eq2, ex2)
