@@ -45,8 +45,8 @@ namespace retess {
 constexpr uint32_t kMask = 0x0FFFFFFFu;
 constexpr int kShift = 28;
 constexpr int kMaxFan = 20;    // edges of a finished cell (RICH_RETESS_FAN beyond)
-constexpr int kSlots = 16;     // candidate slots of a cell: 4 wall bounds, neighbours, entrants
-constexpr int kSlotsPeriodic = 12;  // without walls: the same room for neighbours and entrants
+constexpr int kSlotsLds = 12;  // candidate slots of a cell in LDS: neighbours and entrants
+                               // (a walled box adds its 4 mirrors, held in registers)
 constexpr int kRingMax = 64;   // CSR entries read per cell of the previous mesh
 constexpr int kThreads = 64;
 constexpr int kScanThreads = 1024;
@@ -190,14 +190,18 @@ __global__ void k_rt_end(Hdr* one, Batch bt) {
 // from r_i to a generating point and its id (cell | code << 28); slot u of
 // lane t lives at [u * kThreads + t], so a wave's accesses to one slot are
 // consecutive.
+// Slots below BASE are not in LDS (a walled box's mirrors, held in
+// registers); slot u >= BASE lives at LDS slot u - BASE.
+template <int BASE>
 struct Slots {
   double* dx;
   double* dy;
   int32_t* id;
-  __device__ double& x(int u) const { return dx[u * kThreads]; }
-  __device__ double& y(int u) const { return dy[u * kThreads]; }
-  __device__ int32_t& n(int u) const { return id[u * kThreads]; }
+  __device__ double& x(int u) const { return dx[(u - BASE) * kThreads]; }
+  __device__ double& y(int u) const { return dy[(u - BASE) * kThreads]; }
+  __device__ int32_t& n(int u) const { return id[(u - BASE) * kThreads]; }
 };
+
 
 // The part of the bisector of displacement (dux, duy) (the line
 // p.d = |d|^2/2, parametrised p(t) = d/2 + t (-duy, dux), t increasing
@@ -207,20 +211,18 @@ struct Slots {
 // nothing.  Returns false when that part is empty, or when a slot of the
 // same id comes before `self` (a duplicate); *bounded is false when one end
 // is open (the slots do not enclose the point).
-__device__ bool bisector_part(const Slots& S, uint32_t vm, int nv, int self, double dux,
-                              double duy, int32_t idu, double& tlo, double& thi, bool& bounded) {
+template <bool WALLS>
+__device__ __forceinline__ bool bisector_part(const Slots<WALLS ? 4 : 0>& S, double wy0,
+                                              double wx1, double wy2, double wx3, uint32_t vm,
+                                              int nv, int self, double dux, double duy,
+                                              int32_t idu, double& tlo, double& thi,
+                                              bool& bounded) {
   const double mux = 0.5 * dux, muy = 0.5 * duy;
   const double eux = -duy, euy = dux;
   double ln = 0.0, ld = 1.0, hn = 0.0, hd = 1.0;
   bool has_lo = false, has_hi = false, empty = false;
-  // straight-line body (selects, no branches) over the lane's nv slots
-#pragma unroll 4
-  for (int v = 0; v < nv; ++v) {
-    const double dvx = S.x(v), dvy = S.y(v);
-    const bool use = ((vm >> v) & 1u) && v != self;
-    const bool same = use && S.n(v) == idu;
-    empty = empty || (same && v < self);
-    const bool act = use && !same;
+  // straight-line body (selects, no branches)
+  auto cut = [&](double dvx, double dvy, bool act) {
     const double a0 = eux * dvx + euy * dvy;
     const double b0 = 0.5 * (dvx * dvx + dvy * dvy) - (mux * dvx + muy * dvy);
     const double a = act ? a0 : 0.0;
@@ -235,6 +237,21 @@ __device__ bool bisector_part(const Slots& S, uint32_t vm, int nv, int self, dou
     ld = dn ? -a : ld;
     has_lo = has_lo || dn;
     empty = empty || (a == 0.0 && b < 0.0);
+  };
+  constexpr int BASE = WALLS ? 4 : 0;
+  if constexpr (WALLS) {  // the mirrors (0, wy0), (wx1, 0), (0, wy2), (wx3, 0) first
+    cut(0.0, wy0, (vm & 1u) && self != 0);
+    cut(wx1, 0.0, ((vm >> 1) & 1u) && self != 1);
+    cut(0.0, wy2, ((vm >> 2) & 1u) && self != 2);
+    cut(wx3, 0.0, ((vm >> 3) & 1u) && self != 3);
+  }
+  // then the lane's LDS slots
+#pragma unroll 4
+  for (int v = BASE; v < nv; ++v) {
+    const bool use = ((vm >> v) & 1u) && v != self;
+    const bool same = use && S.n(v) == idu;
+    empty = empty || (same && v < self);
+    cut(S.x(v), S.y(v), use && !same);
   }
   bounded = has_lo && has_hi;
   if (empty || !bounded || !(ln * hd < hn * ld)) return false;
@@ -287,25 +304,31 @@ __device__ __forceinline__ bool ccw_before(double ax, double ay, double bx, doub
 // bisector crosses that polygon, into slots that bound nothing; the second
 // pass gives the cell, its area, centroid and edges in counter-clockwise
 // order.  Every slot v is tried against every slot u (a fixed loop with no
-// polygon to edit), so lanes of a wave stay together.  NS slots per cell: the
-// slots take the block's LDS, which sets how many waves a compute unit holds,
-// so runs without walls (no bound slots) use kSlotsPeriodic.  Each launch
-// serves one kind of run (a batch of both kinds takes two launches), so a
-// run's slots, and its results, never depend on the other runs.
-template <bool B, int NS>
+// polygon to edit), so lanes of a wave stay together.  The candidate slots
+// are the block's LDS, which sets how many waves a compute unit holds: a cell
+// has kSlotsLds of them, and a walled box's four mirrors (slots 0-3) are held
+// in registers, so both kinds of run give 12 slots to neighbours and
+// entrants.  Each launch serves one kind of run (a batch of both kinds takes
+// two launches), so a run's results never depend on the other runs.
+template <bool B, bool WALLS>
 __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
+  constexpr int BASE = WALLS ? 4 : 0;   // mirror slots, held in registers
+  constexpr int NS = kSlotsLds + BASE;  // candidates per cell
   static_assert(NS <= 32, "slot masks are 32-bit");
-  __shared__ double s_dx[NS * kThreads], s_dy[NS * kThreads];
-  __shared__ int32_t s_id[NS * kThreads];
+  __shared__ double s_dx[kSlotsLds * kThreads], s_dy[kSlotsLds * kThreads];
+  __shared__ int32_t s_id[kSlotsLds * kThreads];
   int blk;
   const Args& a = block_run<B>(one, bt.cstart, bt, blk);
   const int i = blk * kThreads + threadIdx.x;
   if (i >= a.n) return;
-  if ((a.bc == (int)RICH_BOUNDARY_PERIODIC) != (NS == kSlotsPeriodic)) return;  // the other launch's
-  const Slots S{s_dx + threadIdx.x, s_dy + threadIdx.x, s_id + threadIdx.x};
+  if ((a.bc == (int)RICH_BOUNDARY_PERIODIC) == WALLS) return;  // the other launch's run
+  const Slots<BASE> S{s_dx + threadIdx.x, s_dy + threadIdx.x, s_id + threadIdx.x};
+  // a walled box: the point's mirrors across the walls y0, x1, y1, x0 (slots
+  // 0-3) are the displacements (0, wy0), (wx1, 0), (0, wy2), (wx3, 0)
+  double wy0 = 0.0, wx1 = 0.0, wy2 = 0.0, wx3 = 0.0;
   const double xi = a.x[i], yi = a.y[i];
   int bad = 0;
-  const bool periodic = a.bc == (int)RICH_BOUNDARY_PERIODIC;
+  constexpr bool periodic = !WALLS;
   // live slots are 0 .. nv-1; vm marks those that hold a candidate
   int nv = 0;
   uint32_t vm = 0u;
@@ -316,13 +339,24 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
   } else {
     if (!(xi > a.x0 && xi < a.x1 && yi > a.y0 && yi < a.y1)) bad |= RICH_RETESS_POINT;
     // the point's mirrors across the walls y0, x1, y1, x0
-    S.x(0) = 0.0;                S.y(0) = 2.0 * (a.y0 - yi); S.n(0) = pack(i, kWallY0);
-    S.x(1) = 2.0 * (a.x1 - xi);  S.y(1) = 0.0;               S.n(1) = pack(i, kWallX1);
-    S.x(2) = 0.0;                S.y(2) = 2.0 * (a.y1 - yi); S.n(2) = pack(i, kWallY1);
-    S.x(3) = 2.0 * (a.x0 - xi);  S.y(3) = 0.0;               S.n(3) = pack(i, kWallX0);
+    wy0 = 2.0 * (a.y0 - yi);
+    wx1 = 2.0 * (a.x1 - xi);
+    wy2 = 2.0 * (a.y1 - yi);
+    wx3 = 2.0 * (a.x0 - xi);
     nv = 4;
     vm = 0xFu;
   }
+  // candidate u: displacement and id (with walls, u < 4 is a mirror)
+  auto cand = [&](int u, double& dx, double& dy) -> int32_t {
+    if (WALLS && u < 4) {
+      dx = u == 1 ? wx1 : (u == 3 ? wx3 : 0.0);
+      dy = u == 0 ? wy0 : (u == 2 ? wy2 : 0.0);
+      return pack(i, u == 0 ? kWallY0 : u == 1 ? kWallX1 : u == 2 ? kWallY1 : kWallX0);
+    }
+    dx = S.x(u);
+    dy = S.y(u);
+    return S.n(u);
+  };
 
   // displacement of cell c from r_i (nearest periodic image) and its id
   auto displacement = [&](int c, double xc, double yc, double& dx, double& dy) -> int32_t {
@@ -376,8 +410,9 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
       if (!((vm >> u) & 1u)) continue;
       double tlo, thi;
       bool bounded;
-      const double dux = S.x(u), duy = S.y(u);
-      if (bisector_part(S, vm, nv, u, dux, duy, S.n(u), tlo, thi, bounded)) {
+      double dux, duy;
+      const int32_t idu = cand(u, dux, duy);
+      if (bisector_part<WALLS>(S, wy0, wx1, wy2, wx3, vm, nv, u, dux, duy, idu, tlo, thi, bounded)) {
         em |= 1u << u;
         const double px = 0.5 * dux - thi * duy, py = 0.5 * duy + thi * dux;
         r2 = fmax(r2, px * px + py * py);
@@ -407,18 +442,19 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
         const int32_t id = displacement(cc[m], ccx[m], ccy[m], dx, dy);
         if (4.0 * r2 <= dx * dx + dy * dy) continue;
         bool known = false;
-        for (int v = 0; v < nv; ++v) known = known || (((vm >> v) & 1u) && S.n(v) == id);
+        for (int v = BASE; v < nv; ++v) known = known || (((vm >> v) & 1u) && S.n(v) == id);
         if (known) continue;
         double tlo, thi;
         bool bounded;
-        if (!bisector_part(S, vm, nv, -1, dx, dy, id, tlo, thi, bounded)) continue;
+        if (!bisector_part<WALLS>(S, wy0, wx1, wy2, wx3, vm, nv, -1, dx, dy, id, tlo, thi, bounded)) continue;
         // a new slot, else one whose bisector bounds nothing (it stays
         // redundant as candidates are added)
         int u = nv;
         if (nv < NS) {
           ++nv;
         } else {
-          const uint32_t usable = ~em & ((1u << NS) - 1u);
+          // (a mirror is never reused)
+          const uint32_t usable = ~em & ((1u << NS) - 1u) & ~((1u << BASE) - 1u);
           if (usable == 0u) {
             bad |= RICH_RETESS_FAN;
             break;
@@ -458,16 +494,18 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
   const size_t s0 = (size_t)i * kMaxFan;
   for (int u = 0; u < nv; ++u) {
     if (!((vm >> u) & 1u)) continue;
-    const double dux = S.x(u), duy = S.y(u);
+    double dux, duy;
+    const int32_t idu = cand(u, dux, duy);
     int rank = 0;
     for (int v = 0; v < nv; ++v) {
       if (!((vm >> v) & 1u) || v == u) continue;
-      const double vx = S.x(v), vy = S.y(v);
+      double vx, vy;
+      cand(v, vx, vy);
       rank += (ccw_before(vx, vy, dux, duy) || (v < u && !ccw_before(dux, duy, vx, vy))) ? 1 : 0;
     }
     double tlo, thi;
     bool bounded;
-    if (!bisector_part(S, vm, nv, u, dux, duy, S.n(u), tlo, thi, bounded)) {
+    if (!bisector_part<WALLS>(S, wy0, wx1, wy2, wx3, vm, nv, u, dux, duy, idu, tlo, thi, bounded)) {
       if (!bounded) bad |= RICH_RETESS_CLIP;
       holes |= 1u << rank;
       continue;
@@ -480,7 +518,7 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
     cx += (ux + wx) * c;
     cy += (uy + wy) * c;
     const double ex = wx - ux, ey = wy - uy;
-    a.s_nb[s0 + rank] = S.n(u);   // rank < number of candidates <= NS < kMaxFan
+    a.s_nb[s0 + rank] = idu;   // rank < number of candidates <= NS < kMaxFan
     double* g = a.s_geo + 3 * (s0 + rank);
     g[0] = sqrt(ex * ex + ey * ey);
     g[1] = xi + 0.5 * (ux + wx);
@@ -937,12 +975,11 @@ template <bool B>
 void launch_all(const retess::Args& a, const retess::Batch& bt, int gc, int gs, int n_runs,
                 bool walls, bool periodic, hipStream_t st) {
   using namespace retess;
-  static_assert(kSlotsPeriodic < kSlots, "the two clip launches are told apart by NS");
   hipLaunchKernelGGL(k_rt_begin<B>, dim3(n_runs), dim3(64), 0, st, a.hdr, bt);
   if (walls)
-    hipLaunchKernelGGL((k_rt_clip<B, kSlots>), dim3(gc), dim3(kThreads), 0, st, a, bt);
+    hipLaunchKernelGGL((k_rt_clip<B, true>), dim3(gc), dim3(kThreads), 0, st, a, bt);
   if (periodic)
-    hipLaunchKernelGGL((k_rt_clip<B, kSlotsPeriodic>), dim3(gc), dim3(kThreads), 0, st, a, bt);
+    hipLaunchKernelGGL((k_rt_clip<B, false>), dim3(gc), dim3(kThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_classify<B>, dim3(gc), dim3(kGroupThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_scan_local<B>, dim3(gs), dim3(kScanThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_scan_blocks<B>, dim3(n_runs), dim3(kScanThreads), 0, st, a, bt);
