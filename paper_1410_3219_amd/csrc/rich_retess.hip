@@ -221,7 +221,7 @@ __device__ __forceinline__ bool bisector_part(const Slots<WALLS ? 4 : 0>& S, dou
   const double eux = -duy, euy = dux;
   double ln = 0.0, ld = 1.0, hn = 0.0, hd = 1.0;
   bool has_lo = false, has_hi = false, empty = false;
-  // straight-line body (selects, no branches)
+  // straight-line bodies (selects, no branches); the mirrors' constraints
   auto cut = [&](double dvx, double dvy, bool act) {
     const double a0 = eux * dvx + euy * dvy;
     const double b0 = 0.5 * (dvx * dvx + dvy * dvy) - (mux * dvx + muy * dvy);
@@ -248,10 +248,25 @@ __device__ __forceinline__ bool bisector_part(const Slots<WALLS ? 4 : 0>& S, dou
   // then the lane's LDS slots
 #pragma unroll 4
   for (int v = BASE; v < nv; ++v) {
+    const double dvx = S.x(v), dvy = S.y(v);
     const bool use = ((vm >> v) & 1u) && v != self;
     const bool same = use && S.n(v) == idu;
     empty = empty || (same && v < self);
-    cut(S.x(v), S.y(v), use && !same);
+    const bool act = use && !same;
+    const double a0 = eux * dvx + euy * dvy;
+    const double b0 = 0.5 * (dvx * dvx + dvy * dvy) - (mux * dvx + muy * dvy);
+    const double a = act ? a0 : 0.0;
+    const double b = act ? b0 : 1.0;
+    // a > 0: t <= b / a;  a < 0: t >= (-b) / (-a);  a = 0, b < 0: no t
+    const bool up = a > 0.0 && (!has_hi || b * hd < hn * a);
+    hn = up ? b : hn;
+    hd = up ? a : hd;
+    has_hi = has_hi || up;
+    const bool dn = a < 0.0 && (!has_lo || -b * ld > ln * -a);
+    ln = dn ? -b : ln;
+    ld = dn ? -a : ld;
+    has_lo = has_lo || dn;
+    empty = empty || (a == 0.0 && b < 0.0);
   }
   bounded = has_lo && has_hi;
   if (empty || !bounded || !(ln * hd < hn * ld)) return false;
