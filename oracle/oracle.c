@@ -715,11 +715,12 @@ static void half_step_primitives(const or_mesh* m, const double* prim, const dou
   }
 }
 
-int or_stage(const or_mesh* m, const double* Qsrc, const double* Qbase,
-             const double* Xbase, double h, const or_params* p, double* Qout,
-             double* Xout, double* d_prim, double* d_w, double* d_alpha,
-             int32_t* d_flag, double* d_flux) {
+static int stage(const or_mesh* m, const double* Qsrc, const double* Qbase,
+                 const double* Xbase, double h, const or_params* p, const double* ax,
+                 const double* ay, double* Qout, double* Xout, double* d_prim, double* d_w,
+                 double* d_alpha, int32_t* d_flag, double* d_flux) {
   if (!m || !Qsrc || !Qbase || !Xbase || !p || !Qout || !Xout) return OR_E_INVAL;
+  if ((ax == NULL) != (ay == NULL)) return OR_E_INVAL;
   int64_t n = m->n_cells, ne = m->n_edges;
   double* prim = malloc(sizeof(double) * 5 * (size_t)n);
   double* w = malloc(sizeof(double) * 2 * (size_t)n);
@@ -762,12 +763,18 @@ int or_stage(const or_mesh* m, const double* Qsrc, const double* Qbase,
     /* External acceleration (section 2.3): the source only needs first-order
      * accuracy in time, because the time-centred composition makes it second
      * order.  Reading: each stage adds h * S(Q_src), with S = (0, M g, P.g)
-     * from the stage's source totals (the force on the cell and its work). */
-    if (p->gx != 0.0 || p->gy != 0.0) {
+     * from the stage's source totals (the force on the cell and its work);
+     * g is the uniform acceleration plus the cell's own (ax, ay) if given. */
+    double gx = p->gx, gy = p->gy;
+    if (ax) {
+      gx += ax[i];
+      gy += ay[i];
+    }
+    if (gx != 0.0 || gy != 0.0) {
       double sm = Qsrc[i], spx = Qsrc[n + i], spy = Qsrc[2 * n + i];
-      Qout[n + i] += h * (sm * p->gx);
-      Qout[2 * n + i] += h * (sm * p->gy);
-      Qout[3 * n + i] += h * (spx * p->gx + spy * p->gy);
+      Qout[n + i] += h * (sm * gx);
+      Qout[2 * n + i] += h * (sm * gy);
+      Qout[3 * n + i] += h * (spx * gx + spy * gy);
     }
     double x = Xbase[i] + h * w[i], y = Xbase[n + i] + h * w[n + i];
     if (m->bc == 1) {
@@ -789,6 +796,21 @@ int or_stage(const or_mesh* m, const double* Qsrc, const double* Qbase,
   if (d_flux) memcpy(d_flux, flux, sizeof(double) * 4 * (size_t)ne);
   free(prim); free(w); free(grad); free(alpha); free(flag); free(flux);
   return st;
+}
+
+int or_stage(const or_mesh* m, const double* Qsrc, const double* Qbase,
+             const double* Xbase, double h, const or_params* p, double* Qout,
+             double* Xout, double* d_prim, double* d_w, double* d_alpha,
+             int32_t* d_flag, double* d_flux) {
+  return stage(m, Qsrc, Qbase, Xbase, h, p, NULL, NULL, Qout, Xout, d_prim, d_w, d_alpha,
+               d_flag, d_flux);
+}
+
+int or_stage_accel(const or_mesh* m, const double* Qsrc, const double* Qbase,
+                   const double* Xbase, double h, const or_params* p, const double* ax,
+                   const double* ay, double* Qout, double* Xout) {
+  if (!ax || !ay) return OR_E_INVAL;
+  return stage(m, Qsrc, Qbase, Xbase, h, p, ax, ay, Qout, Xout, NULL, NULL, NULL, NULL, NULL);
 }
 
 /* ---------------------------------------------------------------------- */

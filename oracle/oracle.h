@@ -97,6 +97,13 @@ int or_stage(const or_mesh* m, const double* Qsrc, const double* Qbase,
              double* Xout, double* d_prim, double* d_w, double* d_alpha,
              int32_t* d_flag, double* d_flux);
 
+/* or_stage with a per-cell external acceleration: cell i is accelerated by
+ * (p->gx + ax[i], p->gy + ay[i]) (section 2.3's source term, from the
+ * stage's source totals). */
+int or_stage_accel(const or_mesh* m, const double* Qsrc, const double* Qbase,
+                   const double* Xbase, double h, const or_params* p, const double* ax,
+                   const double* ay, double* Qout, double* Xout);
+
 /* Courant time step of the state Q on mesh m (A0). */
 int or_cfl_dt(const or_mesh* m, const double* Q, const or_params* p, double* dt);
 

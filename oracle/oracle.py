@@ -102,6 +102,7 @@ def lib():
         L.or_stage.argtypes = [mp, _dp, _dp, _dp, C.c_double, pp, _dp, _dp, _dp, _dp,
                                _dp, _ip, _dp]
         L.or_cfl_dt.argtypes = [mp, _dp, pp, _dp]
+        L.or_stage_accel.argtypes = [mp, _dp, _dp, _dp, C.c_double, pp, _dp, _dp, _dp, _dp]
         L.or_voronoi.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_uint32, C.c_int32, _dp, _dp,
                                  _dp, _ip, _ip, _dp, _dp, _dp]
         L.or_hllc.argtypes = [C.c_double, _dp, _dp, _dp]
@@ -109,7 +110,8 @@ def lib():
         L.or_exact.argtypes = [C.c_double, _dp, _dp, _dp, _dp]
         L.or_exact_sample.argtypes = [C.c_double, _dp, _dp, C.c_double, _dp]
         for f in ("or_primitives", "or_point_velocity", "or_gradients", "or_limiter",
-                  "or_edge_fluxes", "or_edge_waves", "or_area_rate", "or_stage", "or_cfl_dt", "or_exact",
+                  "or_edge_fluxes", "or_edge_waves", "or_area_rate", "or_stage", "or_stage_accel",
+                  "or_cfl_dt", "or_exact",
                   "or_exact_sample", "or_voronoi"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -246,6 +248,21 @@ def stage(mesh, Qsrc, Qbase, Xbase, h, p: Params, diag=False) -> StageResult:
     if diag:
         flux = flux[:, :m.ne]
     return StageResult(Qout, Xout, st, prim, w, alpha, flag, flux)
+
+
+def stage_accel(mesh, Qsrc, Qbase, Xbase, h, p: Params, accel) -> StageResult:
+    """One stage with a per-cell external acceleration accel (2, n) added to
+    the uniform one of p."""
+    m = _MeshRef(mesh)
+    Qsrc, Qbase = _f64(Qsrc, (4, m.n)), _f64(Qbase, (4, m.n))
+    Xbase = _f64(Xbase, (2, m.n))
+    a = _f64(accel, (2, m.n))
+    Qout = np.empty((4, m.n))
+    Xout = np.empty((2, m.n))
+    ax, ay = np.ascontiguousarray(a[0]), np.ascontiguousarray(a[1])
+    st = lib().or_stage_accel(C.byref(m.s), _d(Qsrc), _d(Qbase), _d(Xbase), float(h),
+                              C.byref(p.c()), _d(ax), _d(ay), _d(Qout), _d(Xout))
+    return StageResult(Qout, Xout, st, None, None, None, None, None)
 
 
 def cfl_dt(mesh, Q, p: Params):

@@ -413,6 +413,40 @@ def edge_waves_uniform(O):
         assert np.abs(W[1] - want_ss).max() < 1e-12
 
 
+def accel_field(O):
+    """A per-cell acceleration (section 2.3 source term) on a uniform flow
+    over a static periodic mesh: the fluxes of a uniform state cancel around
+    every closed cell, so one stage changes only by h times the source of
+    the stage's source totals, with g_i = g + a_i: M_out = M_base,
+    P_out = P_base + h M_src g_i, E_out = E_base + h P_src . g_i, and the
+    points stay.  The base differs from the source (twice the mass), so a
+    source taken from the base fails."""
+    g = 5.0 / 3.0
+    P = I.uniform_flow(k=12, v=(0.3, -0.2), rho=1.0, p=1.0, jitter=0.3, bc=1)
+    m = mesh(P.px, P.py, P.box, 1)
+    Qs = P.state(m.area)
+    Qb = Qs.copy()
+    Qb[0] *= 2.0
+    X = np.stack([m.px, m.py])
+    a = np.stack([0.7 * (m.px - 0.5), -1.3 * (m.py - 0.5) + 0.2])
+    p = O.Params(gamma=g, motion=0, gx=0.1, gy=0.0)
+    h = 1e-3
+    r = O.stage_accel(m, Qs, Qb, X, h, p, a)
+    assert r.status == 0
+    gx, gy = 0.1 + a[0], a[1]
+    want = np.stack([Qb[0], Qb[1] + h * Qs[0] * gx, Qb[2] + h * Qs[0] * gy,
+                     Qb[3] + h * (Qs[1] * gx + Qs[2] * gy)])
+    change = np.abs(want - Qb).max(axis=1)
+    err = np.abs(r.Q - want).max(axis=1)
+    assert err[0] < 1e-14 * np.abs(Qb[0]).max()
+    assert (err[1:] < 1e-9 * change[1:]).all(), (err, change)
+    assert np.array_equal(r.X, X)
+    # no field: the uniform-acceleration stage, bit for bit
+    r0 = O.stage_accel(m, Qs, Qb, X, h, p, np.zeros_like(a))
+    ref = O.stage(m, Qs, Qb, X, h, p)
+    assert np.array_equal(r0.Q, ref.Q) and np.array_equal(r0.X, ref.X)
+
+
 def free_fall(O):
     """Uniform gas in a uniform external acceleration g (periodic box, points
     moving with the flow, no rounding correction).  Every edge moves with the
@@ -849,4 +883,4 @@ ALL = [gradient_linear, gradient_periodic, tvd_example, limiter_bounds, hllc_cas
        uniform_state_moving, uniform_flow, advection, conservation, galilean,
        mirror_symmetry, shock_detector, point_velocity, cfl_uniform, sod_accuracy,
        free_fall, extrapolated_second_order, voronoi_lattices, voronoi_identities,
-       voronoi_host_agreement, edge_waves_uniform]
+       voronoi_host_agreement, edge_waves_uniform, accel_field]

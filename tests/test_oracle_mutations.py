@@ -39,6 +39,14 @@ MUTATIONS = [
      "psi = (dphi != 0.0) ? fmax(p->theta * (phi_j[q] - phi_i[q]) / dphi, 0.0) : 1.0;",
      "psi = (dphi != 0.0) ? fmax((phi_j[q] - phi_i[q]) / dphi, 0.0) : 1.0;",
      [pins.tvd_example, pins.limiter_bounds]),
+    ("per-cell acceleration: components swapped",
+     "      gx += ax[i];\n      gy += ay[i];",
+     "      gx += ay[i];\n      gy += ax[i];",
+     [pins.accel_field]),
+    ("per-cell acceleration: ignored",
+     "    if (ax) {\n      gx += ax[i];",
+     "    if (ax && 0) {\n      gx += ax[i];",
+     [pins.accel_field]),
     ("edge waves: star pressure reported for u*",
      "      ss = star[1];",
      "      ss = star[0];",
@@ -94,11 +102,11 @@ MUTATIONS = [
     ("acceleration source taken from the base state",
      "double sm = Qsrc[i], spx = Qsrc[n + i], spy = Qsrc[2 * n + i];",
      "double sm = Qbase[i], spx = Qbase[n + i], spy = Qbase[2 * n + i];",
-     [pins.free_fall]),
+     [pins.free_fall, pins.accel_field]),
     ("work of the external acceleration dropped",
-     "Qout[3 * n + i] += h * (spx * p->gx + spy * p->gy);",
-     "Qout[3 * n + i] += 0.0 * h * (spx * p->gx + spy * p->gy);",
-     [pins.free_fall]),
+     "Qout[3 * n + i] += h * (spx * gx + spy * gy);",
+     "Qout[3 * n + i] += 0.0 * h * (spx * gx + spy * gy);",
+     [pins.free_fall, pins.accel_field]),
     ("extrapolated fluxes: advection of the density reversed",
      "double rho_t = -(ux * drx + uy * dry) - rho * div;",
      "double rho_t = +(ux * drx + uy * dry) - rho * div;",
