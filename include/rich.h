@@ -147,6 +147,17 @@ int rich_stage(const rich_mesh* m, const rich_state* src, const rich_state* base
                size_t ws_bytes, void* stream);
 
 /*
+ * rich_stage with a per-cell external acceleration (section 2.3's source
+ * term): cell i is accelerated by (p->gx + ax[i], p->gy + ay[i]), and the
+ * stage adds h (0, M g_i, P.g_i) of its source totals, as for the uniform
+ * one.  ax, ay: device arrays of n_cells doubles, caller-owned, read only;
+ * RICH_E_INVAL when null.  Otherwise as rich_stage.
+ */
+int rich_stage_accel(const rich_mesh* m, const rich_state* src, const rich_state* base,
+                     rich_state* out, double h, const rich_params* p, const double* ax,
+                     const double* ay, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * rich_stage with a record of the decisions the scheme takes (for comparing
  * branches with an independent implementation; its outputs equal rich_stage's
  * bit for bit).  Device arrays, caller-owned:

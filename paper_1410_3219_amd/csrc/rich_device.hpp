@@ -46,6 +46,7 @@ struct RunDesc {
   double h, gamma, theta, delta_v, delta_p, chi, eta, cfl;
   double rgm1;  // 1 / (gamma - 1)
   double gx, gy;  // uniform external acceleration
+  const double *ax, *ay;  // per-cell acceleration added to (gx, gy), or null
   int32_t n, n_edges, n_csr, bc;
   int32_t riemann, motion, limiter, integrator;
 };

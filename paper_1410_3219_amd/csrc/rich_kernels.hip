@@ -646,12 +646,17 @@ __global__ __launch_bounds__(TILE, RICH_FLUX_WAVES) void k_flux(RunDesc one, con
       double Px = d.bPx[i] - h * acc[1];
       double Py = d.bPy[i] - h * acc[2];
       double E = d.bE[i] - h * acc[3];
-      if (d.gx != 0.0 || d.gy != 0.0) {
+      double gx = d.gx, gy = d.gy;
+      if (d.ax != nullptr) {  // the cell's own acceleration
+        gx += d.ax[i];
+        gy += d.ay[i];
+      }
+      if (gx != 0.0 || gy != 0.0) {
         // external acceleration: h (0, M g, P.g) of the stage's source totals
         const double sm = d.sM[i], spx = d.sPx[i], spy = d.sPy[i];
-        Px += h * (sm * d.gx);
-        Py += h * (sm * d.gy);
-        E += h * (spx * d.gx + spy * d.gy);
+        Px += h * (sm * gx);
+        Py += h * (sm * gy);
+        E += h * (spx * gx + spy * gy);
       }
       const double* rec = d.rec + (size_t)i * kRecDoubles;
       const double wxi = rec[R_WX], wyi = rec[R_WY];
@@ -1301,6 +1306,22 @@ int rich_stage(const rich_mesh* m, const rich_state* src, const rich_state* base
   if (out->M == src->M || out->M == base->M || out->x == base->x) return RICH_E_INVAL;
   if (ws_bytes < run_ws_bytes(n) || (reinterpret_cast<uintptr_t>(ws) & 255)) return RICH_E_NOMEM;
   RunDesc d = make_desc(m, src, base, out, h, p, static_cast<char*>(ws));
+  return launch_stage(d, p->riemann, static_cast<hipStream_t>(stream));
+}
+
+int rich_stage_accel(const rich_mesh* m, const rich_state* src, const rich_state* base,
+                     rich_state* out, double h, const rich_params* p, const double* ax,
+                     const double* ay, void* ws, size_t ws_bytes, void* stream) {
+  if (!valid_mesh(m) || !valid_params(p) || !ws || !ax || !ay) return RICH_E_INVAL;
+  const int64_t n = m->n_cells;
+  if (!valid_state(src, n, false) || !valid_state(base, n, true) || !valid_state(out, n, true))
+    return RICH_E_INVAL;
+  if (!std::isfinite(h) || h < 0.0) return RICH_E_INVAL;
+  if (out->M == src->M || out->M == base->M || out->x == base->x) return RICH_E_INVAL;
+  if (ws_bytes < run_ws_bytes(n) || (reinterpret_cast<uintptr_t>(ws) & 255)) return RICH_E_NOMEM;
+  RunDesc d = make_desc(m, src, base, out, h, p, static_cast<char*>(ws));
+  d.ax = ax;
+  d.ay = ay;
   return launch_stage(d, p->riemann, static_cast<hipStream_t>(stream));
 }
 

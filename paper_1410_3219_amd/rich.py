@@ -131,6 +131,8 @@ def lib():
         L.rich_stage_flags.argtypes = [_vp, _vp, _ip]
         L.rich_stage_debug.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, C.c_size_t, _vp, _vp,
                                        _vp]
+        L.rich_stage_accel.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, _vp, _vp, C.c_size_t,
+                                       _vp]
         L.rich_cfl_dt.argtypes = [mp, sp, pp, _dp, _vp, C.c_size_t, _vp]
         L.rich_area_rate.argtypes = [mp, sp, pp, _vp, _vp, C.c_size_t, _vp]
         L.rich_stage_courant.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, C.c_size_t, _vp]
@@ -326,6 +328,21 @@ def rich_stage(mesh: DeviceMesh, src: DeviceState, base: DeviceState, out: Devic
                           C.byref(out.c()), float(h), C.byref(params.c()),
                           C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
     _check(st, "rich_stage")
+
+
+def rich_stage_accel(mesh: DeviceMesh, src: DeviceState, base: DeviceState, out: DeviceState,
+                     h, params: Params, accel, ws, stream=None):
+    """Enqueue one stage with a per-cell acceleration accel (2, n), a float64
+    device tensor, added to the uniform one of params."""
+    a = accel if accel.is_contiguous() else accel.contiguous()
+    n = mesh.n_cells
+    if tuple(a.shape) != (2, n) or a.element_size() != 8:
+        raise RichError(RICH_E_INVAL, "rich_stage_accel: accel must be (2, n_cells) float64")
+    st = lib().rich_stage_accel(C.byref(mesh.c()), C.byref(src.c()), C.byref(base.c()),
+                                C.byref(out.c()), float(h), C.byref(params.c()),
+                                C.c_void_p(a.data_ptr()), C.c_void_p(a.data_ptr() + 8 * n),
+                                C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
+    _check(st, "rich_stage_accel")
 
 
 def rich_stage_debug(mesh: DeviceMesh, src: DeviceState, base: DeviceState, out: DeviceState,

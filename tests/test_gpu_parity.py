@@ -224,3 +224,63 @@ def test_full_size_point_explosion_step():
         print(f"\nsedov 512^2 riemann={riemann}: stage 1 {eq.max():.2e}, stage 2 {eq2.max():.2e}",
               flush=True)
         assert (eq2 < U.TOL).all() and ex2 < U.TOL, (riemann, 2, eq2, ex2)
+
+
+def _gpu_stage_accel(m, Qs, Qb, Xb, h, p, a):
+    import torch
+    from paper_1410_3219_amd import rich as R
+    dm = R.DeviceMesh.from_host(m)
+    src = R.DeviceState.from_host(Qs, Xb)
+    base = R.DeviceState.from_host(Qb, Xb)
+    out = R.DeviceState.empty_like(base)
+    ws = R.workspace(m.n_cells)
+    R.rich_stage_accel(dm, src, base, out, h, U.gpu_params(p), torch.from_numpy(a).cuda(), ws)
+    flags = R.rich_stage_flags(ws)
+    torch.cuda.synchronize()
+    return (*out.numpy(), flags)
+
+
+@pytest.mark.parametrize("name,k,pass2,riemann", [("sod", 21, False, 0), ("kh", 24, True, 0),
+                                                  ("wave", 19, False, 1), ("sedov", 23, True, 0)])
+def test_stage_acceleration_field(name, k, pass2, riemann):
+    """A per-cell external acceleration added to a uniform one (section 2.3
+    source term): rich_stage_accel against the oracle's stage with the same
+    field, walls and periodic boxes, both stages, both solvers."""
+    m, Qs, Qb, Xb, h, p = U.case(name, k=k, riemann=riemann, pass2=pass2, g=(0.05, -0.3))
+    rng = np.random.default_rng(k)
+    a = np.stack([0.8 * np.sin(2 * np.pi * m.px) + rng.uniform(-0.1, 0.1, m.n_cells),
+                  -0.5 * np.cos(2 * np.pi * m.py)])
+    ref = O.stage_accel(m, Qs, Qb, Xb, h, p, a)
+    assert ref.status == 0
+    Qg, Xg, flags = _gpu_stage_accel(m, Qs, Qb, Xb, h, p, a)
+    assert flags == 0
+    eq, ex = U.errors(m, Qg, Xg, ref.Q, ref.X, Qs, p)
+    assert (eq < U.TOL).all() and ex < U.TOL, (eq, ex)
+    # the field adds h M_src a to the momentum of the stage without it
+    Q0, _, _ = U.gpu_stage(m, Qs, Qb, Xb, h, p)
+    for q in (1, 2):
+        want = h * Qs[0] * a[q - 1]
+        tol = 1e-9 * np.abs(want).max() + 1e-14 * np.abs(Qg[q]).max()
+        assert np.abs((Qg[q] - Q0[q]) - want).max() < tol, q
+
+
+def test_stage_constant_field_equals_uniform_acceleration():
+    """A field equal to (cx, cy) everywhere gives the stage of the uniform
+    acceleration (cx, cy) bit for bit; a missing field is rejected."""
+    import ctypes as C
+    from paper_1410_3219_amd import rich as R
+    m, Qs, Qb, Xb, h, p = U.case("kh", k=20, g=(0.3, -0.7))
+    Qu, Xu, fu = U.gpu_stage(m, Qs, Qb, Xb, h, p)
+    p0 = O.Params(gamma=p.gamma, riemann=p.riemann, limiter=p.limiter, motion=p.motion)
+    a = np.stack([np.full(m.n_cells, 0.3), np.full(m.n_cells, -0.7)])
+    Qa, Xa, fa = _gpu_stage_accel(m, Qs, Qb, Xb, h, p0, a)
+    assert fu == 0 and fa == 0
+    assert np.array_equal(Qa, Qu) and np.array_equal(Xa, Xu)
+    dm = R.DeviceMesh.from_host(m)
+    src = R.DeviceState.from_host(Qs, Xb)
+    out = R.DeviceState.empty_like(src)
+    ws = R.workspace(m.n_cells)
+    st = R.lib().rich_stage_accel(C.byref(dm.c()), C.byref(src.c()), C.byref(src.c()),
+                                  C.byref(out.c()), float(h), C.byref(U.gpu_params(p).c()),
+                                  None, None, C.c_void_p(ws.data_ptr()), ws.numel(), None)
+    assert st == R.RICH_E_INVAL
