@@ -357,6 +357,13 @@ int rich_ctx_tess_counts(rich_ctx* ctx, int64_t* device, int64_t* host_fallback)
 int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
               rich_tess_fn tess, rich_tess_release_fn release, void* tess_user,
               void* stream);
+/* rich_step with a per-cell external acceleration in every stage (as
+ * rich_stage_accel): cell i, which keeps its index through the step, is
+ * accelerated by (p->gx + ax[i], p->gy + ay[i]).  ax, ay: device arrays of
+ * n_cells doubles, caller-owned; RICH_E_INVAL when null. */
+int rich_step_accel(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
+                    const double* ax, const double* ay, rich_tess_fn tess,
+                    rich_tess_release_fn release, void* tess_user, void* stream);
 
 /*
  * One step (section 2.3) of n independent runs at once: the same chain as

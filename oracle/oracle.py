@@ -295,25 +295,31 @@ def exact_sample(gamma, WL, WR, xi):
     return W, it
 
 
-def step(mesh, Q, X, dt, p: Params, tess, diag=False):
+def step(mesh, Q, X, dt, p: Params, tess, diag=False, accel=None):
     """One step (section 2.3).  `tess(px, py, box, bc)` returns the mesh of
     the given points.  Returns (Q_new, X_new, mesh_new, mesh_half, status).
+    accel (2, n): a per-cell acceleration added to p's uniform one in every
+    stage (cells keep their index through the step).
 
     Time-centred fluxes (integrator 0): a half stage, the mesh rebuilt, then
     the full stage from the start-of-step state with the half-step fluxes.
     Extrapolated fluxes (integrator 1): one full stage on the start-of-step
     mesh with half-step face states, the points moved by dt w^n."""
+    def st(m, Qs, Qb, Xb, h):
+        return stage(m, Qs, Qb, Xb, h, p) if accel is None else \
+            stage_accel(m, Qs, Qb, Xb, h, p, accel)
+
     if p.integrator == 1:
-        s = stage(mesh, Q, Q, X, dt, p)
+        s = st(mesh, Q, Q, X, dt)
         if s.status != 0:
             return None, None, None, None, s.status
         mesh_n = tess(s.X[0], s.X[1], mesh.box, mesh.bc) if p.motion else mesh
         return s.Q, s.X, mesh_n, None, 0
-    s1 = stage(mesh, Q, Q, X, 0.5 * dt, p)
+    s1 = st(mesh, Q, Q, X, 0.5 * dt)
     if s1.status != 0:
         return None, None, None, None, s1.status
     mesh_h = tess(s1.X[0], s1.X[1], mesh.box, mesh.bc) if p.motion else mesh
-    s2 = stage(mesh_h, s1.Q, Q, X, dt, p)
+    s2 = st(mesh_h, s1.Q, Q, X, dt)
     if s2.status != 0:
         return None, None, None, mesh_h, s2.status
     mesh_n = tess(s2.X[0], s2.X[1], mesh.box, mesh.bc) if p.motion else mesh

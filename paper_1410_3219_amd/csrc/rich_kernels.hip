@@ -1763,8 +1763,18 @@ int rich_ctx_tess_counts(rich_ctx* ctx, int64_t* device, int64_t* host_fallback)
   return RICH_OK;
 }
 
-int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
-              rich_tess_fn tess, rich_tess_release_fn release, void* tess_user, void* stream) {
+namespace {
+// One stage of a step, with the per-cell acceleration when given.
+int step_stage(const rich_mesh* m, const rich_state* src, const rich_state* base,
+               rich_state* out, double h, const rich_params* p, const double* ax,
+               const double* ay, void* ws, size_t ws_bytes, void* stream) {
+  return ax ? rich_stage_accel(m, src, base, out, h, p, ax, ay, ws, ws_bytes, stream)
+            : rich_stage(m, src, base, out, h, p, ws, ws_bytes, stream);
+}
+
+int step_impl(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
+              const double* ax, const double* ay, rich_tess_fn tess,
+              rich_tess_release_fn release, void* tess_user, void* stream) {
   if (!ctx || !state || !valid_params(p) || !ctx->cur.set) return RICH_E_INVAL;
   if (!std::isfinite(dt) || !(dt > 0.0)) return RICH_E_INVAL;
   if (p->motion && (!tess || !release)) return RICH_E_INVAL;
@@ -1785,10 +1795,11 @@ int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
   int32_t flags = 0;
   if (p->integrator == 1) {
     // extrapolated fluxes: one stage on the start-of-step mesh
-    rc = rich_stage(&m, state, state, &next, dt, p, ctx->ws.p, ctx->ws.cap, stream);
+    rc = step_stage(&m, state, state, &next, dt, p, ax, ay, ctx->ws.p, ctx->ws.cap, stream);
     if (rc) return rc;
   } else {
-    rc = rich_stage(&m, state, state, &half, 0.5 * dt, p, ctx->ws.p, ctx->ws.cap, stream);
+    rc = step_stage(&m, state, state, &half, 0.5 * dt, p, ax, ay, ctx->ws.p, ctx->ws.cap,
+                    stream);
     if (rc) return rc;
     if ((rc = rich_stage_flags(ctx->ws.p, stream, &flags))) return rc;
     if (flags) return RICH_E_DOMAIN;
@@ -1797,7 +1808,7 @@ int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
       if (rc) return rc;
       ctx->spare.view(&mh);
     }
-    rc = rich_stage(&mh, &half, state, &next, dt, p, ctx->ws.p, ctx->ws.cap, stream);
+    rc = step_stage(&mh, &half, state, &next, dt, p, ax, ay, ctx->ws.p, ctx->ws.cap, stream);
     if (rc) return rc;
   }
   if ((rc = rich_stage_flags(ctx->ws.p, stream, &flags))) return rc;
@@ -1818,6 +1829,19 @@ int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
       return RICH_E_DEVICE;
   if (hipStreamSynchronize(st) != hipSuccess) return RICH_E_DEVICE;
   return RICH_OK;
+}
+}  // namespace
+
+int rich_step(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
+              rich_tess_fn tess, rich_tess_release_fn release, void* tess_user, void* stream) {
+  return step_impl(ctx, state, dt, p, nullptr, nullptr, tess, release, tess_user, stream);
+}
+
+int rich_step_accel(rich_ctx* ctx, rich_state* state, double dt, const rich_params* p,
+                    const double* ax, const double* ay, rich_tess_fn tess,
+                    rich_tess_release_fn release, void* tess_user, void* stream) {
+  if (!ax || !ay) return RICH_E_INVAL;
+  return step_impl(ctx, state, dt, p, ax, ay, tess, release, tess_user, stream);
 }
 
 int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,

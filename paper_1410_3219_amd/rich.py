@@ -200,6 +200,7 @@ def lib():
             L.rich_ctx_set_device_tess.argtypes = [_vp, C.c_int32]
             L.rich_ctx_tess_counts.argtypes = [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
             L.rich_step.argtypes = [_vp, sp, C.c_double, pp, _vp, _vp, _vp, _vp]
+            L.rich_step_accel.argtypes = [_vp, sp, C.c_double, pp, _vp, _vp, _vp, _vp, _vp, _vp]
             L.rich_step_batch.argtypes = [C.c_int32, C.POINTER(_vp), C.POINTER(_vp), _dp,
                                           C.POINTER(_vp), _vp, _vp, C.POINTER(_vp), C.c_int32,
                                           _ip, _vp, C.c_size_t, _vp]
@@ -747,10 +748,24 @@ class RichCtx:
         _check(lib().rich_ctx_mesh(self.h, C.byref(cm)), "rich_ctx_mesh")
         return CtxMesh(cm)
 
-    def step(self, state: DeviceState, dt, params: Params, stream=None):
-        st = lib().rich_step(self.h, C.byref(state.c()), float(dt), C.byref(params.c()),
-                             self.tess_fn, self.release_fn, self.tess_user, _stream_ptr(stream))
-        _check(st, "rich_step")
+    def step(self, state: DeviceState, dt, params: Params, stream=None, accel=None):
+        """One time-centred step (rich_step); accel (2, n), a float64 device
+        tensor, adds a per-cell acceleration (rich_step_accel)."""
+        if accel is None:
+            st = lib().rich_step(self.h, C.byref(state.c()), float(dt), C.byref(params.c()),
+                                 self.tess_fn, self.release_fn, self.tess_user,
+                                 _stream_ptr(stream))
+            _check(st, "rich_step")
+            return
+        a = accel if accel.is_contiguous() else accel.contiguous()
+        n = state.n
+        if tuple(a.shape) != (2, n) or a.element_size() != 8:
+            raise RichError(RICH_E_INVAL, "rich_step_accel: accel must be (2, n_cells) float64")
+        st = lib().rich_step_accel(self.h, C.byref(state.c()), float(dt), C.byref(params.c()),
+                                   C.c_void_p(a.data_ptr()), C.c_void_p(a.data_ptr() + 8 * n),
+                                   self.tess_fn, self.release_fn, self.tess_user,
+                                   _stream_ptr(stream))
+        _check(st, "rich_step_accel")
 
 
 def rich_step_batch(ctxs, states, dts, params, ws, n_threads=0, stream=None):
