@@ -247,6 +247,18 @@ int rich_stage_batch(int32_t n, const rich_mesh* const* meshes,
                      rich_state* const* out, const double* h,
                      const rich_params* const* params, void* ws, size_t ws_bytes,
                      void* stream);
+/* rich_stage_batch with a per-cell external acceleration (section 2.3 source
+ * term, as rich_stage_accel): ax[r], ay[r] are device arrays of
+ * meshes[r]->n_cells doubles added to params[r]'s uniform (gx, gy), or both
+ * NULL for a run without a field (a run with one of the two NULL is
+ * RICH_E_INVAL, as are NULL ax or ay themselves).  Host arrays of n device
+ * pointers, caller-owned.  The per-run results are bitwise identical to n
+ * separate rich_stage_accel (or, for runs without a field, rich_stage) calls. */
+int rich_stage_batch_accel(int32_t n, const rich_mesh* const* meshes,
+                           const rich_state* const* src, const rich_state* const* base,
+                           rich_state* const* out, const double* h,
+                           const rich_params* const* params, const double* const* ax,
+                           const double* const* ay, void* ws, size_t ws_bytes, void* stream);
 /*
  * The same batched stage in two calls, so that its launches can be replayed
  * (for example captured once in a HIP graph and launched many times):

@@ -1464,13 +1464,21 @@ int rich_stage_batch_prepare(int32_t n, const rich_mesh* const* meshes,
                                        ws_bytes, stream, plan);
 }
 
-int rich_stage_batch_prepare_tile(int32_t n, const rich_mesh* const* meshes,
-                                  const rich_state* const* src, const rich_state* const* base,
-                                  rich_state* const* out, const double* h,
-                                  const rich_params* const* params, int32_t tile, void* ws,
-                                  size_t ws_bytes, void* stream, rich_batch_plan* plan) {
+namespace {
+
+// The batched stage's validation and upload; ax, ay (either both null or both
+// set) hold each run's per-cell acceleration, null entries meaning none.
+int batch_prepare(int32_t n, const rich_mesh* const* meshes, const rich_state* const* src,
+                  const rich_state* const* base, rich_state* const* out, const double* h,
+                  const rich_params* const* params, const double* const* ax,
+                  const double* const* ay, int32_t tile, void* ws, size_t ws_bytes,
+                  void* stream, rich_batch_plan* plan) {
   if (n <= 0 || !meshes || !src || !base || !out || !h || !params || !ws || !plan)
     return RICH_E_INVAL;
+  if ((ax == nullptr) != (ay == nullptr)) return RICH_E_INVAL;
+  if (ax)
+    for (int32_t r = 0; r < n; ++r)
+      if ((ax[r] == nullptr) != (ay[r] == nullptr)) return RICH_E_INVAL;
   if (tile != 128 && tile != 256 && tile != 512) return RICH_E_INVAL;
   std::memset(plan, 0, sizeof(*plan));
   std::vector<int64_t> nc(n);
@@ -1507,6 +1515,10 @@ int rich_stage_batch_prepare_tile(int32_t n, const rich_mesh* const* meshes,
     d.flag = reinterpret_cast<int32_t*>(w + L.flags) + r;
     d.cfl_min = reinterpret_cast<unsigned long long*>(w + L.cfl) + r;
     d.rec = reinterpret_cast<double*>(w + L.rec_off[r]);
+    if (ax) {
+      d.ax = ax[r];
+      d.ay = ay[r];
+    }
     descs[r] = d;
     pc[r] = (int32_t)tc;
     pc[n + 1 + r] = r;
@@ -1554,6 +1566,17 @@ int rich_stage_batch_prepare_tile(int32_t n, const rich_mesh* const* meshes,
   plan->grid_flux[0] = (int32_t)std::min<int64_t>(tf[0], flux0_grid);
   plan->grid_flux[1] = (int32_t)std::min<int64_t>(tf[1], flux1_grid);
   return RICH_OK;
+}
+
+}  // namespace
+
+int rich_stage_batch_prepare_tile(int32_t n, const rich_mesh* const* meshes,
+                                  const rich_state* const* src, const rich_state* const* base,
+                                  rich_state* const* out, const double* h,
+                                  const rich_params* const* params, int32_t tile, void* ws,
+                                  size_t ws_bytes, void* stream, rich_batch_plan* plan) {
+  return batch_prepare(n, meshes, src, base, out, h, params, nullptr, nullptr, tile, ws,
+                       ws_bytes, stream, plan);
 }
 
 int rich_stage_batch_launch(const rich_batch_plan* plan, void* ws, void* stream) {
@@ -1638,6 +1661,19 @@ int rich_stage_batch(int32_t n, const rich_mesh* const* meshes, const rich_state
   rich_batch_plan plan;
   const int rc = rich_stage_batch_prepare(n, meshes, src, base, out, h, params, ws, ws_bytes,
                                           stream, &plan);
+  if (rc) return rc;
+  return rich_stage_batch_launch(&plan, ws, stream);
+}
+
+int rich_stage_batch_accel(int32_t n, const rich_mesh* const* meshes,
+                           const rich_state* const* src, const rich_state* const* base,
+                           rich_state* const* out, const double* h,
+                           const rich_params* const* params, const double* const* ax,
+                           const double* const* ay, void* ws, size_t ws_bytes, void* stream) {
+  if (!ax || !ay) return RICH_E_INVAL;
+  rich_batch_plan plan;
+  const int rc = batch_prepare(n, meshes, src, base, out, h, params, ax, ay, rich::kTile, ws,
+                               ws_bytes, stream, &plan);
   if (rc) return rc;
   return rich_stage_batch_launch(&plan, ws, stream);
 }

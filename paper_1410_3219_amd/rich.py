@@ -171,6 +171,10 @@ def lib():
             L.rich_stage_batch.argtypes = [C.c_int32, C.POINTER(_vp), C.POINTER(_vp),
                                            C.POINTER(_vp), C.POINTER(_vp), _dp, C.POINTER(_vp),
                                            _vp, C.c_size_t, _vp]
+            L.rich_stage_batch_accel.argtypes = [C.c_int32, C.POINTER(_vp), C.POINTER(_vp),
+                                                 C.POINTER(_vp), C.POINTER(_vp), _dp,
+                                                 C.POINTER(_vp), C.POINTER(_vp),
+                                                 C.POINTER(_vp), _vp, C.c_size_t, _vp]
             L.rich_batch_flags.argtypes = [C.c_int32, _vp, _vp, _ip]
             L.rich_batch_flags_async.argtypes = [C.c_int32, _vp, _vp, _vp]
             L.rich_stage_batch_prepare.argtypes = [C.c_int32, C.POINTER(_vp), C.POINTER(_vp),
@@ -596,6 +600,26 @@ def rich_stage_batch(meshes, srcs, bases, outs, hs, params, ws, stream=None):
     st = lib().rich_stage_batch(n, mp, spp, bpp, opp, hh, ppp, C.c_void_p(ws.data_ptr()),
                                 ws.numel(), _stream_ptr(stream))
     _check(st, "rich_stage_batch")
+
+
+def rich_stage_batch_accel(meshes, srcs, bases, outs, hs, params, accels, ws, stream=None):
+    """rich_stage_batch with per-run per-cell accelerations: accels[r] is a
+    contiguous (2, n_r) float64 device tensor, or None for a run without one."""
+    n, mp, spp, bpp, opp, hh, ppp, _pc = _batch_args(meshes, srcs, bases, outs, hs, params)
+    if len(accels) != n:
+        raise RichError(RICH_E_INVAL, "rich_stage_batch_accel: one field (or None) per run")
+    ax, ay = (_vp * n)(), (_vp * n)()
+    for r, a in enumerate(accels):
+        if a is None:
+            continue
+        nc = meshes[r].n_cells
+        if tuple(a.shape) != (2, nc) or a.element_size() != 8 or not a.is_contiguous():
+            raise RichError(RICH_E_INVAL,
+                            "rich_stage_batch_accel: accels[r] must be contiguous (2, n_r) float64")
+        ax[r], ay[r] = a.data_ptr(), a.data_ptr() + 8 * nc
+    st = lib().rich_stage_batch_accel(n, mp, spp, bpp, opp, hh, ppp, ax, ay,
+                                      C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
+    _check(st, "rich_stage_batch_accel")
 
 
 def rich_stage_batch_prepare(meshes, srcs, bases, outs, hs, params, ws, stream=None):

@@ -65,6 +65,66 @@ def test_batch_equals_single_runs_bitwise_and_oracle():
         assert (eq < U.TOL).all() and ex < U.TOL, (eq, ex)
 
 
+def test_batch_with_acceleration_fields_equals_single_runs_and_oracle():
+    """rich_stage_batch_accel over runs with and without a per-cell field
+    (section 2.3 source term) equals separate rich_stage_accel / rich_stage
+    calls bit for bit and the oracle's stage_accel / stage to 1e-12."""
+    import torch
+    from paper_1410_3219_amd import rich as R
+    specs = [("sod", 17, 0, True), ("wave", 23, 1, True), ("sedov", 20, 0, False),
+             ("kh", 31, 0, True), ("sod", 1, 1, True)]
+    cases, fields = [], []
+    for name, k, riemann, with_field in specs:
+        c = U.case(name, k=k, riemann=riemann, pass2=(k % 2 == 1), g=(0.05, -0.3))
+        m = c[0]
+        rng = np.random.default_rng(k)
+        a = np.stack([0.8 * np.sin(2 * np.pi * m.px) + rng.uniform(-0.1, 0.1, m.n_cells),
+                      -0.5 * np.cos(2 * np.pi * m.py)]) if with_field else None
+        cases.append(c)
+        fields.append(a)
+    meshes, srcs, bases, outs, hs, ps, accels = [], [], [], [], [], [], []
+    for (m, Qs, Qb, Xb, h, p), a in zip(cases, fields):
+        meshes.append(R.DeviceMesh.from_host(m))
+        srcs.append(R.DeviceState.from_host(Qs, Xb))
+        bases.append(R.DeviceState.from_host(Qb, Xb))
+        o = R.DeviceState.empty_like(bases[-1])
+        o.Q.fill_(float("nan"))
+        outs.append(o)
+        hs.append(h)
+        ps.append(U.gpu_params(p))
+        accels.append(None if a is None else torch.from_numpy(a).cuda())
+    ws = R.batch_workspace([c[0].n_cells for c in cases])
+    R.rich_stage_batch_accel(meshes, srcs, bases, outs, hs, ps, accels, ws)
+    flags = R.rich_batch_flags(len(cases), ws)
+    torch.cuda.synchronize()
+    assert flags == [0] * len(cases)
+    for r, ((m, Qs, Qb, Xb, h, p), a) in enumerate(zip(cases, fields)):
+        Qbat, Xbat = outs[r].numpy()
+        one = R.DeviceState.empty_like(bases[r])
+        w1 = R.workspace(m.n_cells)
+        if a is None:
+            R.rich_stage(meshes[r], srcs[r], bases[r], one, h, ps[r], w1)
+            ref = O.stage(m, Qs, Qb, Xb, h, p)
+        else:
+            R.rich_stage_accel(meshes[r], srcs[r], bases[r], one, h, ps[r], accels[r], w1)
+            ref = O.stage_accel(m, Qs, Qb, Xb, h, p, a)
+        torch.cuda.synchronize()
+        Q1, X1 = one.numpy()
+        assert np.array_equal(Qbat, Q1) and np.array_equal(Xbat, X1), r
+        assert ref.status == 0
+        eq, ex = U.errors(m, Qbat, Xbat, ref.Q, ref.X, Qb, p)
+        assert (eq < U.TOL).all() and ex < U.TOL, (r, eq, ex)
+    # a run with only one of its two components is rejected before any launch
+    import ctypes as C
+    n = len(cases)
+    ax, ay = (C.c_void_p * n)(), (C.c_void_p * n)()
+    ax[0] = accels[0].data_ptr()
+    n_, mp, spp, bpp, opp, hh, ppp, _pc = R._batch_args(meshes, srcs, bases, outs, hs, ps)
+    st = R.lib().rich_stage_batch_accel(n_, mp, spp, bpp, opp, hh, ppp, ax, ay,
+                                        C.c_void_p(ws.data_ptr()), ws.numel(), None)
+    assert st == R.RICH_E_INVAL
+
+
 def test_batch_tile_shapes_bitwise_equal_and_autotune():
     """Every edge-tile shape (128, 256, 512 cells) gives the same results bit
     for bit; the autotuner times each and picks one of them."""
