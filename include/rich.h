@@ -410,6 +410,19 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
                     rich_tess_fn tess, rich_tess_release_fn release,
                     void* const* tess_users, int32_t n_threads, int32_t* status,
                     void* ws, size_t ws_bytes, void* stream);
+/* rich_step_batch with a per-cell external acceleration in every stage of
+ * the runs that carry one (as rich_step_accel): ax[r], ay[r] are device
+ * arrays of run r's n_cells doubles, or both NULL for a run without a field
+ * (a run with only one of them NULL fails with status RICH_E_INVAL; NULL ax
+ * or ay themselves fail the call with RICH_E_INVAL).  Host arrays of n device
+ * pointers, caller-owned.  The results are bitwise identical to n separate
+ * rich_step_accel (or rich_step) calls. */
+int rich_step_batch_accel(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
+                          const double* dt, const rich_params* const* params,
+                          const double* const* ax, const double* const* ay, rich_tess_fn tess,
+                          rich_tess_release_fn release, void* const* tess_users,
+                          int32_t n_threads, int32_t* status, void* ws, size_t ws_bytes,
+                          void* stream);
 
 /*
  * Device re-tessellation (section 2.1: the mesh is the Voronoi tessellation

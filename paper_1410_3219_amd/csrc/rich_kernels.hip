@@ -1880,8 +1880,13 @@ int rich_step_accel(rich_ctx* ctx, rich_state* state, double dt, const rich_para
   return step_impl(ctx, state, dt, p, ax, ay, tess, release, tess_user, stream);
 }
 
-int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
-                    const double* dt, const rich_params* const* params, rich_tess_fn tess,
+namespace {
+
+// The batched step; ax, ay (both null, or host arrays of n device pointers)
+// hold each run's per-cell acceleration, null entries meaning none.
+int step_batch_impl(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
+                    const double* dt, const rich_params* const* params,
+                    const double* const* ax, const double* const* ay, rich_tess_fn tess,
                     rich_tess_release_fn release, void* const* tess_users, int32_t n_threads,
                     int32_t* status, void* ws, size_t ws_bytes, void* stream) {
   if (n <= 0 || !ctxs || !states || !dt || !params || !status || !ws) return RICH_E_INVAL;
@@ -1892,7 +1897,8 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
     status[r] = RICH_OK;
     rich_ctx* c = ctxs[r];
     if (!c || !c->cur.set || !valid_params(params[r]) || !std::isfinite(dt[r]) ||
-        !(dt[r] > 0.0) || !valid_state(states[r], c->cur.n, true)) {
+        !(dt[r] > 0.0) || !valid_state(states[r], c->cur.n, true) ||
+        (ax && (ax[r] == nullptr) != (ay[r] == nullptr))) {
       status[r] = RICH_E_INVAL;
       continue;
     }
@@ -1941,9 +1947,14 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
     std::vector<rich_state*> op(m);
     std::vector<double> h(m);
     std::vector<const rich_params*> pp(m);
+    std::vector<const double*> axk(m, nullptr), ayk(m, nullptr);
     for (size_t k = 0; k < m; ++k) {
       const int32_t r = live[k];
       const bool one = params[r]->integrator == 1;  // extrapolated fluxes: one stage
+      if (ax) {
+        axk[k] = ax[r];
+        ayk[k] = ay[r];
+      }
       mp[k] = &mesh[r];
       sp[k] = second ? &half[r] : states[r];
       bp[k] = states[r];
@@ -1951,8 +1962,11 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
       h[k] = (second || one) ? dt[r] : 0.5 * dt[r];
       pp[k] = params[r];
     }
-    int e = rich_stage_batch((int32_t)m, mp.data(), sp.data(), bp.data(), op.data(), h.data(),
-                             pp.data(), ws, ws_bytes, stream);
+    rich_batch_plan plan;
+    int e = batch_prepare((int32_t)m, mp.data(), sp.data(), bp.data(), op.data(), h.data(),
+                          pp.data(), ax ? axk.data() : nullptr, ax ? ayk.data() : nullptr,
+                          rich::kTile, ws, ws_bytes, stream, &plan);
+    if (!e) e = rich_stage_batch_launch(&plan, ws, stream);
     if (e) return e;
     std::vector<int32_t> fl(m, 0);
     if ((e = rich_batch_flags((int32_t)m, ws, stream, fl.data()))) return e;
@@ -2119,6 +2133,27 @@ int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
   for (int32_t r = 0; r < n; ++r)
     if (status[r]) return status[r];
   return RICH_OK;
+}
+
+}  // namespace
+
+int rich_step_batch(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
+                    const double* dt, const rich_params* const* params, rich_tess_fn tess,
+                    rich_tess_release_fn release, void* const* tess_users, int32_t n_threads,
+                    int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  return step_batch_impl(n, ctxs, states, dt, params, nullptr, nullptr, tess, release,
+                         tess_users, n_threads, status, ws, ws_bytes, stream);
+}
+
+int rich_step_batch_accel(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
+                          const double* dt, const rich_params* const* params,
+                          const double* const* ax, const double* const* ay, rich_tess_fn tess,
+                          rich_tess_release_fn release, void* const* tess_users,
+                          int32_t n_threads, int32_t* status, void* ws, size_t ws_bytes,
+                          void* stream) {
+  if (!ax || !ay) return RICH_E_INVAL;
+  return step_batch_impl(n, ctxs, states, dt, params, ax, ay, tess, release, tess_users,
+                         n_threads, status, ws, ws_bytes, stream);
 }
 
 int rich_profile_enable(int on) {

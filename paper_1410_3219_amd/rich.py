@@ -208,8 +208,12 @@ def lib():
             L.rich_step_batch.argtypes = [C.c_int32, C.POINTER(_vp), C.POINTER(_vp), _dp,
                                           C.POINTER(_vp), _vp, _vp, C.POINTER(_vp), C.c_int32,
                                           _ip, _vp, C.c_size_t, _vp]
+            L.rich_step_batch_accel.argtypes = [C.c_int32, C.POINTER(_vp), C.POINTER(_vp),
+                                                _dp, C.POINTER(_vp), C.POINTER(_vp),
+                                                C.POINTER(_vp), _vp, _vp, C.POINTER(_vp),
+                                                C.c_int32, _ip, _vp, C.c_size_t, _vp]
             for f in ("rich_ctx_create", "rich_ctx_set_mesh", "rich_ctx_mesh", "rich_step",
-                      "rich_step_batch", "rich_ctx_set_device_tess", "rich_ctx_tess_counts"):
+                      "rich_step_batch", "rich_step_batch_accel", "rich_ctx_set_device_tess", "rich_ctx_tess_counts"):
                 getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -792,11 +796,25 @@ class RichCtx:
         _check(st, "rich_step_accel")
 
 
-def rich_step_batch(ctxs, states, dts, params, ws, n_threads=0, stream=None):
+def rich_step_batch(ctxs, states, dts, params, ws, n_threads=0, stream=None, accels=None):
     """Time-centred step of len(ctxs) runs (RichCtx each) with batched stage
     launches; returns the per-run status list (0: committed).  Raises only
-    when the call as a whole failed."""
+    when the call as a whole failed.  accels: None, or one contiguous (2, n_r)
+    float64 device tensor (or None) per run, a per-cell acceleration applied
+    in every stage of that run."""
     n = len(ctxs)
+    if accels is not None:
+        if len(accels) != n:
+            raise RichError(RICH_E_INVAL, "rich_step_batch: one field (or None) per run")
+        ax, ay = (_vp * n)(), (_vp * n)()
+        for r, a in enumerate(accels):
+            if a is None:
+                continue
+            nc = states[r].Q.shape[1]
+            if tuple(a.shape) != (2, nc) or a.element_size() != 8 or not a.is_contiguous():
+                raise RichError(RICH_E_INVAL,
+                                "rich_step_batch: accels[r] must be contiguous (2, n_r) float64")
+            ax[r], ay[r] = a.data_ptr(), a.data_ptr() + 8 * nc
     ad = C.addressof
     cp = (_vp * n)(*[c.h.value for c in ctxs])
     spp = (_vp * n)(*[ad(s.c()) for s in states])
@@ -807,9 +825,15 @@ def rich_step_batch(ctxs, states, dts, params, ws, n_threads=0, stream=None):
     status = (C.c_int32 * n)()
     t0 = ctxs[0]
     nt = int(n_threads) if n_threads > 0 else (os.cpu_count() or 1)
-    rc = lib().rich_step_batch(n, cp, spp, dd, ppp, t0.tess_fn, t0.release_fn, users, nt,
-                               status, C.c_void_p(ws.data_ptr()), ws.numel(),
-                               _stream_ptr(stream))
+    if accels is None:
+        rc = lib().rich_step_batch(n, cp, spp, dd, ppp, t0.tess_fn, t0.release_fn, users, nt,
+                                   status, C.c_void_p(ws.data_ptr()), ws.numel(),
+                                   _stream_ptr(stream))
+    else:
+        rc = lib().rich_step_batch_accel(n, cp, spp, dd, ppp, ax, ay, t0.tess_fn,
+                                         t0.release_fn, users, nt, status,
+                                         C.c_void_p(ws.data_ptr()), ws.numel(),
+                                         _stream_ptr(stream))
     st = list(status)
     if rc != RICH_OK and not any(st):   # rejected before any run was looked at
         _check(rc, "rich_step_batch")

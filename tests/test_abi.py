@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function(header, lib):
 def test_declared_entry_points_are_the_expected_set():
     names = set(declared("rich.h"))
     for must in ("rich_stage", "rich_stage_debug", "rich_stage_accel", "rich_step_accel",
-                 "rich_stage_batch_accel",
+                 "rich_stage_batch_accel", "rich_step_batch_accel",
                  "rich_stage_flags", "rich_cfl_dt",
                  "rich_workspace_size",
                  "rich_stage_batch", "rich_batch_flags", "rich_batch_workspace_size",

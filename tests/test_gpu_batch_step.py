@@ -496,3 +496,71 @@ def test_step_with_acceleration_field_follows_oracle_chain(integrator):
     eq, ex = U.errors(mo, Qg, Xg, Qo, Xo, Q, p)
     print(f"\nintegrator {integrator}: 3 steps with a field, err {eq} x {ex}")
     assert (eq < 1e-11).all() and ex < 1e-11, (eq, ex)
+
+
+def test_step_batch_with_acceleration_fields_equals_separate_steps_bitwise():
+    """rich_step_batch_accel: runs with a per-cell field (moving and static
+    meshes, both integrators) and runs without one equal separate
+    rich_step_accel / rich_step calls bit for bit over three steps; a run
+    with only one field component fails alone."""
+    import torch
+    from paper_1410_3219_amd import rich as R
+    runs = _step_batch_runs()
+    fields = []
+    for r, (m, *_rest) in enumerate(runs):
+        if r % 3 == 2:
+            fields.append(None)
+        else:
+            fields.append(torch.from_numpy(np.stack(
+                [0.4 * np.sin(2 * np.pi * m.py), -0.6 * np.cos(2 * np.pi * m.px)])).cuda())
+    ctxs, states = [], []
+    for m, Q, X, p, dt in runs:
+        c = R.RichCtx(n_threads=1)
+        c.set_mesh(m)
+        ctxs.append(c)
+        states.append(R.DeviceState.from_host(Q, X))
+    ws = R.batch_workspace([m.n_cells for m, *_ in runs])
+    for _ in range(3):
+        st = R.rich_step_batch(ctxs, states, [r[4] for r in runs],
+                               [U.gpu_params(r[3]) for r in runs], ws, n_threads=4,
+                               accels=fields)
+        assert st == [0] * len(runs), st
+    torch.cuda.synchronize()
+    for c in ctxs:
+        c.close()
+    for (m, Q, X, p, dt), a, s in zip(runs, fields, states):
+        c = R.RichCtx(n_threads=1)
+        c.set_mesh(m)
+        one = R.DeviceState.from_host(Q, X)
+        for _ in range(3):
+            c.step(one, dt, U.gpu_params(p), accel=a)
+        torch.cuda.synchronize()
+        c.close()
+        (Qb, Xb), (Q1, X1) = s.numpy(), one.numpy()
+        assert np.array_equal(Qb, Q1) and np.array_equal(Xb, X1)
+    # run 0 with ax only: that run fails with RICH_E_INVAL, the others commit
+    import ctypes as C
+    ctxs = []
+    for m, Q, X, p, dt in runs[:2]:
+        c = R.RichCtx(n_threads=1)
+        c.set_mesh(m)
+        ctxs.append(c)
+    sts = [R.DeviceState.from_host(Q, X) for m, Q, X, p, dt in runs[:2]]
+    ax, ay = (C.c_void_p * 2)(), (C.c_void_p * 2)()
+    ax[0] = fields[0].data_ptr()
+    ax[1], ay[1] = fields[1].data_ptr(), fields[1].data_ptr() + 8 * runs[1][0].n_cells
+    cp = (C.c_void_p * 2)(*[c.h.value for c in ctxs])
+    spp = (C.c_void_p * 2)(*[C.addressof(s.c()) for s in sts])
+    dd = (C.c_double * 2)(*[r[4] for r in runs[:2]])
+    pc = [U.gpu_params(r[3]).c() for r in runs[:2]]
+    ppp = (C.c_void_p * 2)(*[C.addressof(x) for x in pc])
+    users = (C.c_void_p * 2)(*[c.tess_user.value for c in ctxs])
+    status = (C.c_int32 * 2)()
+    ws2 = R.batch_workspace([r[0].n_cells for r in runs[:2]])
+    rc = R.lib().rich_step_batch_accel(2, cp, spp, dd, ppp, ax, ay, ctxs[0].tess_fn,
+                                       ctxs[0].release_fn, users, 1, status,
+                                       C.c_void_p(ws2.data_ptr()), ws2.numel(), None)
+    torch.cuda.synchronize()
+    for c in ctxs:
+        c.close()
+    assert rc == R.RICH_E_INVAL and list(status) == [R.RICH_E_INVAL, R.RICH_OK]
