@@ -237,6 +237,21 @@ def _stream_ptr(stream):
     return C.c_void_p(s.cuda_stream)
 
 
+def _dense(t, stream):
+    """t itself when contiguous, else a contiguous copy that is safe to hand
+    to work enqueued on `stream`: the copy is made on torch's current stream,
+    so `stream` first waits for it, and the allocator is told the copy is in
+    use there (it is not reused before that stream's work completes)."""
+    if t.is_contiguous():
+        return t
+    import torch
+    c = t.contiguous()
+    if stream is not None:
+        stream.wait_stream(torch.cuda.current_stream())
+        c.record_stream(stream)
+    return c
+
+
 # ---------------------------------------------------------------------------
 # device-resident mesh and state (torch tensors)
 # ---------------------------------------------------------------------------
@@ -343,7 +358,7 @@ def rich_stage_accel(mesh: DeviceMesh, src: DeviceState, base: DeviceState, out:
                      h, params: Params, accel, ws, stream=None):
     """Enqueue one stage with a per-cell acceleration accel (2, n), a float64
     device tensor, added to the uniform one of params."""
-    a = accel if accel.is_contiguous() else accel.contiguous()
+    a = _dense(accel, stream)
     n = mesh.n_cells
     if tuple(a.shape) != (2, n) or a.element_size() != 8:
         raise RichError(RICH_E_INVAL, "rich_stage_accel: accel must be (2, n_cells) float64")
@@ -478,7 +493,7 @@ class DeviceMeshBufs:
 def rich_retess(prev: DeviceMesh, X, bufs: DeviceMeshBufs, ws, stream=None):
     """Enqueue the re-tessellation of points X (2, n) (device) with candidates
     from `prev` into `bufs`; read the outcome with rich_retess_result."""
-    X = X if X.is_contiguous() else X.contiguous()
+    X = _dense(X, stream)
     n = prev.n_cells
     xp = C.c_void_p(X.data_ptr())
     yp = C.c_void_p(X.data_ptr() + 8 * n)
@@ -508,7 +523,7 @@ def rich_retess_batch(prevs, Xs, bufs, wss, bws=None, stream=None):
         _check(lib().rich_retess_batch_workspace_size(n, C.byref(b)),
                "rich_retess_batch_workspace_size")
         bws = torch.empty(int(b.value), dtype=torch.uint8, device=Xs[0].device)
-    Xs = [X if X.is_contiguous() else X.contiguous() for X in Xs]
+    Xs = [_dense(X, stream) for X in Xs]
     ad = C.addressof
     pm = (_vp * n)(*[ad(m.c()) for m in prevs])
     xp = (_vp * n)(*[X.data_ptr() for X in Xs])
@@ -785,7 +800,7 @@ class RichCtx:
                                  _stream_ptr(stream))
             _check(st, "rich_step")
             return
-        a = accel if accel.is_contiguous() else accel.contiguous()
+        a = _dense(accel, stream)
         n = state.n
         if tuple(a.shape) != (2, n) or a.element_size() != 8:
             raise RichError(RICH_E_INVAL, "rich_step_accel: accel must be (2, n_cells) float64")

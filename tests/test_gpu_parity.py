@@ -264,6 +264,33 @@ def test_stage_acceleration_field(name, k, pass2, riemann):
         assert np.abs((Qg[q] - Q0[q]) - want).max() < tol, q
 
 
+def test_stage_field_view_on_side_stream_equals_contiguous_field():
+    """A non-contiguous (2, n) field passed with a stream other than torch's
+    current one: the binding's contiguous copy is ordered before the stage on
+    that stream and kept alive for it; the result equals the contiguous
+    field's bit for bit."""
+    import torch
+    from paper_1410_3219_amd import rich as R
+    m, Qs, Qb, Xb, h, p = U.case("kh", k=22, pass2=True, g=(0.1, -0.2))
+    a = np.stack([0.3 * np.sin(2 * np.pi * m.py), -0.4 * np.cos(2 * np.pi * m.px)])
+    Qc, Xc, fc = _gpu_stage_accel(m, Qs, Qb, Xb, h, p, a)
+    dm = R.DeviceMesh.from_host(m)
+    src = R.DeviceState.from_host(Qs, Xb)
+    base = R.DeviceState.from_host(Qb, Xb)
+    out = R.DeviceState.empty_like(base)
+    ws = R.workspace(m.n_cells)
+    view = torch.from_numpy(np.ascontiguousarray(a.T)).cuda().T   # (2, n), strides (1, 2)
+    assert not view.is_contiguous()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    R.rich_stage_accel(dm, src, base, out, h, U.gpu_params(p), view, ws, stream=side)
+    del view
+    side.synchronize()
+    Qv, Xv = out.numpy()
+    assert fc == 0 and R.rich_stage_flags(ws) == 0
+    assert np.array_equal(Qv, Qc) and np.array_equal(Xv, Xc)
+
+
 def test_stage_constant_field_equals_uniform_acceleration():
     """A field equal to (cx, cy) everywhere gives the stage of the uniform
     acceleration (cx, cy) bit for bit; a missing field is rejected."""
