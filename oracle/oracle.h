@@ -16,6 +16,26 @@
  *   CSR      off[n+1], idx = 2*edge + side (side 1: the cell is e_j)
  * State arrays are planar: Q[4*n] = M | Px | Py | E (extensive totals over the
  * cell), X[2*n] = x | y.
+ *
+ * Parity unpinned.  Where the paper leaves a choice open, the oracle takes
+ * one reading and the device path takes the same; no fact of the paper or of
+ * the mathematics distinguishes it from the alternatives, so only the shared
+ * reading pins these (every other function is pinned by a test that does
+ * not re-run the oracle's own formula):
+ *   - which variables are reconstructed: the primitives rho, p, vx, vy,
+ *     limited one by one (section 2.2 names them, not the alternatives);
+ *   - the reconstruction starts at the centroid s_i with the cell's value,
+ *     although the gradient belongs to the point r_i (section 2.2);
+ *   - the shock detector beyond its special cases (section 2.2: the
+ *     compression test per cell with the unlimited gradient, strict
+ *     inequalities, the pressure-ratio test over all neighbours);
+ *   - the HLLC wave-speed estimates (Davis bounds; section 2.4 does not
+ *     state them);
+ *   - the on/off shape of the cell-rounding correction (section 6 gives its
+ *     parameters, not its form near d = eta R).
+ * The wall ghost (mirrored point, state, extrapolated edge state and edge
+ * velocity) is pinned by the method of images: a walled run equals the
+ * periodic run of the points and their mirror images.
  */
 #ifndef RICH_ORACLE_H
 #define RICH_ORACLE_H

@@ -351,12 +351,14 @@ class use_library:
         return False
 
 
-def build_variant(src_text, out_path):
-    """Compile oracle source text (a modified copy) to out_path."""
+def build_variant(src_text, out_path, fp_flags=("-ffp-contract=off",)):
+    """Compile oracle source text (a modified copy) to out_path.  fp_flags
+    replaces the default floating-point flags (the tests of the parity
+    metric build the unmodified source with fused multiply-adds)."""
     src = out_path + ".c"
     with open(src, "w") as f:
         f.write(src_text)
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC",
+    subprocess.check_call(["gcc", "-O2", "-std=c99", *fp_flags, "-fPIC",
                            "-shared", "-I", _HERE, src, "-o", out_path, "-lm"])
     return out_path
 

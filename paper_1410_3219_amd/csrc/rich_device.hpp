@@ -5,8 +5,12 @@
 // (section 2.2), the HLLC and exact Riemann solvers (section 2.4) in the frame
 // of the moving edge (section 1, section 5), and the lab-frame flux.
 //
-// Arithmetic is FP64 throughout; divisions and square roots are the
-// correctly rounded IEEE operations (no fast-math).  Floating-point
+// Arithmetic is FP64 throughout, without fast-math: every division and
+// square root written as such is the correctly rounded IEEE operation.  The
+// inverse distances of the gradient terms and of the edge normals are
+// reciprocal square roots (rsqrt), which are accurate to a few units in the
+// last place but not correctly rounded; the oracle divides by a square root
+// there, and the difference stays at rounding level.  Floating-point
 // contraction is per source expression (-ffp-contract=on), so every call of
 // these functions on the same inputs produces the same bits, wherever it is
 // inlined: a cell or an edge computed by two different tiles agrees bitwise.

@@ -252,6 +252,24 @@ def _dense(t, stream):
     return c
 
 
+def _accel_field(a, n, device, name, contiguous=False):
+    """Check a per-cell acceleration field before its pointer is taken: a
+    (2, n) float64 tensor on the state's GPU (a host tensor's pointer, or
+    another dtype's bits read as doubles, would reach the kernels)."""
+    import torch
+    if not isinstance(a, torch.Tensor):
+        raise RichError(RICH_E_INVAL, f"{name}: the field must be a torch tensor")
+    if a.dtype != torch.float64:
+        raise RichError(RICH_E_INVAL, f"{name}: the field must be float64, not {a.dtype}")
+    if a.device.type != "cuda" or a.device != device:
+        raise RichError(RICH_E_INVAL,
+                        f"{name}: the field must be on the state's device {device}, not {a.device}")
+    if tuple(a.shape) != (2, n):
+        raise RichError(RICH_E_INVAL, f"{name}: the field must be (2, {n}), not {tuple(a.shape)}")
+    if contiguous and not a.is_contiguous():
+        raise RichError(RICH_E_INVAL, f"{name}: the field must be contiguous")
+
+
 # ---------------------------------------------------------------------------
 # device-resident mesh and state (torch tensors)
 # ---------------------------------------------------------------------------
@@ -358,10 +376,9 @@ def rich_stage_accel(mesh: DeviceMesh, src: DeviceState, base: DeviceState, out:
                      h, params: Params, accel, ws, stream=None):
     """Enqueue one stage with a per-cell acceleration accel (2, n), a float64
     device tensor, added to the uniform one of params."""
-    a = _dense(accel, stream)
     n = mesh.n_cells
-    if tuple(a.shape) != (2, n) or a.element_size() != 8:
-        raise RichError(RICH_E_INVAL, "rich_stage_accel: accel must be (2, n_cells) float64")
+    _accel_field(accel, n, base.Q.device, "rich_stage_accel")
+    a = _dense(accel, stream)
     st = lib().rich_stage_accel(C.byref(mesh.c()), C.byref(src.c()), C.byref(base.c()),
                                 C.byref(out.c()), float(h), C.byref(params.c()),
                                 C.c_void_p(a.data_ptr()), C.c_void_p(a.data_ptr() + 8 * n),
@@ -624,7 +641,7 @@ def rich_stage_batch(meshes, srcs, bases, outs, hs, params, ws, stream=None):
 def rich_stage_batch_accel(meshes, srcs, bases, outs, hs, params, accels, ws, stream=None):
     """rich_stage_batch with per-run per-cell accelerations: accels[r] is a
     contiguous (2, n_r) float64 device tensor, or None for a run without one."""
-    n, mp, spp, bpp, opp, hh, ppp, _pc = _batch_args(meshes, srcs, bases, outs, hs, params)
+    n = len(meshes)
     if len(accels) != n:
         raise RichError(RICH_E_INVAL, "rich_stage_batch_accel: one field (or None) per run")
     ax, ay = (_vp * n)(), (_vp * n)()
@@ -632,10 +649,9 @@ def rich_stage_batch_accel(meshes, srcs, bases, outs, hs, params, accels, ws, st
         if a is None:
             continue
         nc = meshes[r].n_cells
-        if tuple(a.shape) != (2, nc) or a.element_size() != 8 or not a.is_contiguous():
-            raise RichError(RICH_E_INVAL,
-                            "rich_stage_batch_accel: accels[r] must be contiguous (2, n_r) float64")
+        _accel_field(a, nc, bases[r].Q.device, "rich_stage_batch_accel", contiguous=True)
         ax[r], ay[r] = a.data_ptr(), a.data_ptr() + 8 * nc
+    n, mp, spp, bpp, opp, hh, ppp, _pc = _batch_args(meshes, srcs, bases, outs, hs, params)
     st = lib().rich_stage_batch_accel(n, mp, spp, bpp, opp, hh, ppp, ax, ay,
                                       C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
     _check(st, "rich_stage_batch_accel")
@@ -800,10 +816,9 @@ class RichCtx:
                                  _stream_ptr(stream))
             _check(st, "rich_step")
             return
-        a = _dense(accel, stream)
         n = state.n
-        if tuple(a.shape) != (2, n) or a.element_size() != 8:
-            raise RichError(RICH_E_INVAL, "rich_step_accel: accel must be (2, n_cells) float64")
+        _accel_field(accel, n, state.Q.device, "rich_step_accel")
+        a = _dense(accel, stream)
         st = lib().rich_step_accel(self.h, C.byref(state.c()), float(dt), C.byref(params.c()),
                                    C.c_void_p(a.data_ptr()), C.c_void_p(a.data_ptr() + 8 * n),
                                    self.tess_fn, self.release_fn, self.tess_user,
@@ -826,9 +841,7 @@ def rich_step_batch(ctxs, states, dts, params, ws, n_threads=0, stream=None, acc
             if a is None:
                 continue
             nc = states[r].Q.shape[1]
-            if tuple(a.shape) != (2, nc) or a.element_size() != 8 or not a.is_contiguous():
-                raise RichError(RICH_E_INVAL,
-                                "rich_step_batch: accels[r] must be contiguous (2, n_r) float64")
+            _accel_field(a, nc, states[r].Q.device, "rich_step_batch", contiguous=True)
             ax[r], ay[r] = a.data_ptr(), a.data_ptr() + 8 * nc
     ad = C.addressof
     cp = (_vp * n)(*[c.h.value for c in ctxs])

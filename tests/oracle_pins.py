@@ -29,6 +29,10 @@ AssertionError when the oracle disagrees.  What each pin fixes:
   galilean             a constant boost changes nothing but the velocity and
                        the point positions (section 4.4)
   mirror_symmetry      a mirror-symmetric problem stays symmetric
+  wall_images          reflecting walls equal the periodic run of the points
+                       and their mirror images (method of images): the
+                       wall ghost's point, state, extrapolated edge state
+                       and edge velocity
   point_velocity       section 6 rounding correction: none on a centroidal
                        lattice, |w - v| = chi c_s towards the centroid
   cfl_uniform          Courant step of a uniform state in closed form
@@ -878,9 +882,60 @@ def voronoi_host_agreement(O):
                 assert abs(mine[key][0] - L) < 1e-14
 
 
+def wall_images(O):
+    """Reflecting walls by the method of images (C-13).  A walled unit box
+    holds the same flow as the periodic box [0,2]^2 filled with the points
+    and their mirror images across x = 1, y = 1 and both (a reflection of a
+    point across x = 1 is, shifted by the period, its reflection across
+    x = 0): the images carry the mirrored states, so the periodic run's
+    cells of the unit box must equal the walled run to round-off, over two
+    time-centred steps on a moving mesh.  This fixes the wall ghost: its
+    point, its state for the gradient and the limiter, the extrapolated
+    state of the wall edge and the edge's velocity."""
+    # points kept off the walls, so that none crosses a wall in two steps
+    hx, hy = I.uniform_points(140, seed=31, box=(0.03, 0.03, 0.97, 0.97), sort=False)
+    n = hx.shape[0]
+    box2 = (0.0, 0.0, 2.0, 2.0)
+    px = np.concatenate([hx, 2.0 - hx, hx, 2.0 - hx])
+    py = np.concatenate([hy, hy, 2.0 - hy, 2.0 - hy])
+    sx = np.concatenate([np.ones(n), -np.ones(n), np.ones(n), -np.ones(n)])
+    sy = np.concatenate([np.ones(n), np.ones(n), -np.ones(n), -np.ones(n)])
+    g = 5.0 / 3.0
+    # a flow without symmetry of its own inside the unit box
+    r2 = (hx - 0.3) ** 2 + (hy - 0.6) ** 2
+    rho = 1.0 + 0.6 * np.exp(-r2 / 0.03) + 0.2 * hx
+    pr = 1.0 + 2.0 * np.exp(-r2 / 0.01) + 0.3 * hy
+    vx = 0.4 * np.sin(2.0 * hy + 1.0) + 0.2
+    vy = -0.3 * np.cos(3.0 * hx) + 0.1
+    for riemann, limiter in ((0, 0), (1, 2)):
+        p = O.Params(gamma=g, riemann=riemann, limiter=limiter, motion=1)
+        mw = mesh(hx, hy, BOX, 0)
+        mp = mesh(px, py, box2, 1)
+        Qw = I.conserved(rho, vx, vy, pr, mw.area, g)
+        Qp = I.conserved(np.tile(rho, 4), sx * np.tile(vx, 4), sy * np.tile(vy, 4),
+                         np.tile(pr, 4), mp.area, g)
+        Xw = np.stack([mw.px, mw.py])
+        Xp = np.stack([mp.px, mp.py])
+        # every wall edge of the walled mesh is an edge to the cell's own image
+        assert np.allclose(mp.area[:n], mw.area, rtol=1e-12, atol=0.0)
+        for _ in range(2):
+            dt, st = O.cfl_dt(mw, Qw, p)
+            assert st == 0
+            Qw, Xw, mw, _, st = O.step(mw, Qw, Xw, dt, p, tessf)
+            assert st == 0
+            Qp, Xp, mp, _, st = O.step(mp, Qp, Xp, dt, p, tessf)
+            assert st == 0
+        sc = np.abs(Qw).max(axis=1)
+        d = np.abs(Qp[:, :n] - Qw).max(axis=1) / sc
+        assert (d < 1e-12).all(), (riemann, limiter, d)
+        assert np.abs(Xp[:, :n] - Xw).max() < 1e-13
+        # and the images still mirror the cells (the periodic run is symmetric)
+        assert np.abs(Qp[1, n:2 * n] + Qp[1, :n]).max() < 1e-12 * sc[1]
+
+
 ALL = [gradient_linear, gradient_periodic, tvd_example, limiter_bounds, hllc_cases,
        hllc_weak_waves, exact_shock_tube, exact_two_shocks, area_rate_fd,
        uniform_state_moving, uniform_flow, advection, conservation, galilean,
        mirror_symmetry, shock_detector, point_velocity, cfl_uniform, sod_accuracy,
        free_fall, extrapolated_second_order, voronoi_lattices, voronoi_identities,
-       voronoi_host_agreement, edge_waves_uniform, accel_field]
+       voronoi_host_agreement, edge_waves_uniform, accel_field, wall_images]

@@ -131,3 +131,32 @@ def test_argument_validation_without_gpu():
     arr = (C.c_int64 * 2)(100, 0)
     assert L.rich_batch_workspace_size(2, arr, C.byref(wsz)) == R.RICH_E_INVAL
     assert L.rich_stage_batch(0, None, None, None, None, None, None, None, 0, None) == R.RICH_E_INVAL
+
+
+def test_acceleration_fields_are_checked_before_any_launch():
+    """Every wrapper that takes a per-cell acceleration field rejects a host
+    tensor and a tensor of another dtype (whose bits would be read as
+    doubles) with RICH_E_INVAL, before it takes the field's pointer."""
+    import types
+    import torch
+    from paper_1410_3219_amd import rich as R
+    n = 10
+    st = R.DeviceState(torch.zeros(4, n, dtype=torch.float64), torch.zeros(2, n, dtype=torch.float64))
+    mesh = types.SimpleNamespace(n_cells=n)
+    bad_fields = [torch.zeros(2, n, dtype=torch.float64),        # host memory
+                  torch.zeros(2, n, dtype=torch.int64),          # wrong dtype, 8 bytes
+                  torch.zeros(2, n, dtype=torch.complex64),      # wrong dtype, 8 bytes
+                  torch.zeros(2, n + 1, dtype=torch.float64)]    # wrong shape
+    for a in bad_fields:
+        with pytest.raises(R.RichError) as e:
+            R.rich_stage_accel(mesh, st, st, st, 0.1, R.Params(), a, None)
+        assert e.value.status == R.RICH_E_INVAL
+        with pytest.raises(R.RichError) as e:
+            R.rich_stage_batch_accel([mesh], [st], [st], [st], [0.1], [R.Params()], [a], None)
+        assert e.value.status == R.RICH_E_INVAL
+        with pytest.raises(R.RichError) as e:
+            R.RichCtx.step(types.SimpleNamespace(), st, 0.1, R.Params(), accel=a)
+        assert e.value.status == R.RICH_E_INVAL
+        with pytest.raises(R.RichError) as e:
+            R.rich_step_batch([None], [st], [0.1], [R.Params()], None, accels=[a])
+        assert e.value.status == R.RICH_E_INVAL

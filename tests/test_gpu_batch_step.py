@@ -60,9 +60,7 @@ def test_batch_equals_single_runs_bitwise_and_oracle():
         Qg, Xg, f = U.gpu_stage(m, Qs, Qb, Xb, h, p)
         assert f == 0
         assert np.array_equal(Qbat, Qg) and np.array_equal(Xbat, Xg)
-        ref = O.stage(m, Qs, Qb, Xb, h, p)
-        eq, ex = U.errors(m, Qbat, Xbat, ref.Q, ref.X, Qb, p)
-        assert (eq < U.TOL).all() and ex < U.TOL, (eq, ex)
+        U.check_stage(m, Qs, Qb, Xb, h, p, Qbat, Xbat, label="batched run")
 
 
 def test_batch_with_acceleration_fields_equals_single_runs_and_oracle():
@@ -112,8 +110,7 @@ def test_batch_with_acceleration_fields_equals_single_runs_and_oracle():
         Q1, X1 = one.numpy()
         assert np.array_equal(Qbat, Q1) and np.array_equal(Xbat, X1), r
         assert ref.status == 0
-        eq, ex = U.errors(m, Qbat, Xbat, ref.Q, ref.X, Qb, p)
-        assert (eq < U.TOL).all() and ex < U.TOL, (r, eq, ex)
+        U.check_stage(m, Qs, Qb, Xb, h, p, Qbat, Xbat, ref=ref, accel=a, label=f"batched run {r}")
     # a run with only one of its two components is rejected before any launch
     import ctypes as C
     n = len(cases)
@@ -452,15 +449,11 @@ def test_batch_full_size_sampled_oracle_parity():
     for k in sorted(pick):
         r = runs[k]
         Qh, Xh = r["half"].numpy()
-        ref1 = O.stage(r["hm"], r["Q0"], r["Q0"], r["X0"], 0.5 * r["dt"], r["op"])
-        assert ref1.status == 0
-        eq, ex = U.errors(r["hm"], Qh, Xh, ref1.Q, ref1.X, r["Q0"], r["op"])
-        assert (eq < U.TOL).all() and ex < U.TOL, (k, 1, eq, ex)
+        U.check_stage(r["hm"], r["Q0"], r["Q0"], r["X0"], 0.5 * r["dt"], r["op"], Qh, Xh,
+                      label=f"run {k} stage 1")
         Qo, Xo = r["out"].numpy()
-        ref2 = O.stage(r["hmh"], Qh, r["Q0"], r["X0"], r["dt"], r["op"])
-        assert ref2.status == 0
-        eq, ex = U.errors(r["hmh"], Qo, Xo, ref2.Q, ref2.X, Qh, r["op"])
-        assert (eq < U.TOL).all() and ex < U.TOL, (k, 2, eq, ex)
+        U.check_stage(r["hmh"], Qh, r["Q0"], r["X0"], r["dt"], r["op"], Qo, Xo,
+                      label=f"run {k} stage 2")
     print(f"\n{len(runs)} runs, {total} cells, tiles {tile1}/{tile2}, "
           f"{len(pick)} runs checked against the oracle")
 

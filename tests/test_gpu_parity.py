@@ -16,14 +16,11 @@ pytestmark = pytest.mark.gpu
 
 def _run(name, **kw):
     m, Qs, Qb, Xb, h, p = U.case(name, **kw)
-    ref = O.stage(m, Qs, Qb, Xb, h, p)
+    ref = O.stage(m, Qs, Qb, Xb, h, p, diag=True)
     assert ref.status == 0
     Qg, Xg, flags = U.gpu_stage(m, Qs, Qb, Xb, h, p)
     assert flags == 0
-    eq, ex = U.errors(m, Qg, Xg, ref.Q, ref.X, Qb, p)
-    print(f"\n{name} {kw} n={m.n_cells} err M,Px,Py,E={eq} x={ex}", flush=True)
-    assert (eq < U.TOL).all(), eq
-    assert ex < U.TOL, ex
+    U.check_stage(m, Qs, Qb, Xb, h, p, Qg, Xg, ref=ref, label=f"{name} {kw}")
     return m
 
 
@@ -90,19 +87,18 @@ def test_stage_cells_in_random_order(bc):
     p = O.Params(gamma=5.0 / 3.0)
     dt, st = O.cfl_dt(m, Q, p)
     assert st == 0
-    ref = O.stage(m, Q, Q, X, 0.5 * dt, p)
+    ref = O.stage(m, Q, Q, X, 0.5 * dt, p, diag=True)
     assert ref.status == 0
     Qg, Xg, flags = U.gpu_stage(m, Q, Q, X, 0.5 * dt, p)
     assert flags == 0
-    eq, ex = U.errors(m, Qg, Xg, ref.Q, ref.X, Q, p)
-    assert (eq < U.TOL).all() and ex < U.TOL, (eq, ex)
+    U.check_stage(m, Q, Q, X, 0.5 * dt, p, Qg, Xg, ref=ref, label=f"random order bc={bc} stage 1")
     mh = T.rich_tess_build(ref.X[0], ref.X[1], box, bc)
-    ref2 = O.stage(mh, ref.Q, Q, X, dt, p)
+    ref2 = O.stage(mh, ref.Q, Q, X, dt, p, diag=True)
     assert ref2.status == 0
     Qg2, Xg2, flags = U.gpu_stage(mh, ref.Q, Q, X, dt, p)
     assert flags == 0
-    eq, ex = U.errors(mh, Qg2, Xg2, ref2.Q, ref2.X, Q, p)
-    assert (eq < U.TOL).all() and ex < U.TOL, (eq, ex)
+    U.check_stage(mh, ref.Q, Q, X, dt, p, Qg2, Xg2, ref=ref2,
+                  label=f"random order bc={bc} stage 2")
 
 
 def test_deterministic_repeat():
@@ -187,13 +183,12 @@ def test_full_size_wave_stage(integrator):
     dt, st = O.cfl_dt(m, Q, p)
     assert st == 0
     h = 0.5 * dt if integrator == 0 else dt
-    ref = O.stage(m, Q, Q, X, h, p)
+    ref = O.stage(m, Q, Q, X, h, p, diag=True)
     assert ref.status == 0
     Qg, Xg, flags = U.gpu_stage(m, Q, Q, X, h, p)
     assert flags == 0
-    eq, ex = U.errors(m, Qg, Xg, ref.Q, ref.X, Q, p)
-    print(f"\nfull size, integrator {integrator}: err M,Px,Py,E={eq} x={ex}", flush=True)
-    assert (eq < U.TOL).all() and ex < U.TOL, (eq, ex)
+    U.check_stage(m, Q, Q, X, h, p, Qg, Xg, ref=ref,
+                  label=f"full-size wave, integrator {integrator}")
 
 
 def test_full_size_point_explosion_step():
@@ -209,21 +204,19 @@ def test_full_size_point_explosion_step():
         p = O.Params(gamma=P.gamma, riemann=riemann)
         dt, st = O.cfl_dt(m, Q, p)
         assert st == 0
-        ref1 = O.stage(m, Q, Q, X, 0.5 * dt, p)
+        ref1 = O.stage(m, Q, Q, X, 0.5 * dt, p, diag=True)
         assert ref1.status == 0
         Qh, Xh, flags = U.gpu_stage(m, Q, Q, X, 0.5 * dt, p)
         assert flags == 0
-        eq, ex = U.errors(m, Qh, Xh, ref1.Q, ref1.X, Q, p)
-        assert (eq < U.TOL).all() and ex < U.TOL, (riemann, 1, eq, ex)
+        U.check_stage(m, Q, Q, X, 0.5 * dt, p, Qh, Xh, ref=ref1,
+                      label=f"sedov 512^2 riemann={riemann} stage 1")
         mh = T.rich_tess_build(Xh[0], Xh[1], m.box, m.bc)
-        ref2 = O.stage(mh, Qh, Q, X, dt, p)
+        ref2 = O.stage(mh, Qh, Q, X, dt, p, diag=True)
         assert ref2.status == 0
         Qn, Xn, flags = U.gpu_stage(mh, Qh, Q, X, dt, p)
         assert flags == 0
-        eq2, ex2 = U.errors(mh, Qn, Xn, ref2.Q, ref2.X, Qh, p)
-        print(f"\nsedov 512^2 riemann={riemann}: stage 1 {eq.max():.2e}, stage 2 {eq2.max():.2e}",
-              flush=True)
-        assert (eq2 < U.TOL).all() and ex2 < U.TOL, (riemann, 2, eq2, ex2)
+        U.check_stage(mh, Qh, Q, X, dt, p, Qn, Xn, ref=ref2,
+                      label=f"sedov 512^2 riemann={riemann} stage 2")
 
 
 def _gpu_stage_accel(m, Qs, Qb, Xb, h, p, a):
@@ -254,8 +247,7 @@ def test_stage_acceleration_field(name, k, pass2, riemann):
     assert ref.status == 0
     Qg, Xg, flags = _gpu_stage_accel(m, Qs, Qb, Xb, h, p, a)
     assert flags == 0
-    eq, ex = U.errors(m, Qg, Xg, ref.Q, ref.X, Qs, p)
-    assert (eq < U.TOL).all() and ex < U.TOL, (eq, ex)
+    U.check_stage(m, Qs, Qb, Xb, h, p, Qg, Xg, ref=ref, accel=a, label=f"accel field {name}")
     # the field adds h M_src a to the momentum of the stage without it
     Q0, _, _ = U.gpu_stage(m, Qs, Qb, Xb, h, p)
     for q in (1, 2):

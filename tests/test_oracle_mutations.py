@@ -3,7 +3,12 @@ dropped term, a swapped operand) must make at least one pin fail.  The
 mistakes are planted in a temporary copy of oracle.c compiled on the CPU.
 
 Not pinned: the HLLC wave-speed estimate (the paper does not state it; the
-Davis bounds are a reading), so a change there is only caught by parity."""
+Davis bounds are a reading), so a change there is only caught by parity.
+
+Not a mistake: reversing the wall ghost's tangential velocity.  The wall's
+Riemann problem is symmetric, so its contact speed is exactly zero and both
+solvers take the tangential velocity from the cell's side only; the flux is
+the same either way."""
 import os
 
 import pytest
@@ -87,6 +92,29 @@ MUTATIONS = [
      "WR[0] = phiL[0]; WR[1] = -WL[1];",
      "WR[0] = phiL[0]; WR[1] = WL[1];",
      [pins.conservation]),
+    ("wall ghost does not reverse the normal velocity (images)",
+     "WR[0] = phiL[0]; WR[1] = -WL[1];",
+     "WR[0] = phiL[0]; WR[1] = WL[1];",
+     [pins.wall_images]),
+    ("wall ghost state taken at the cell centre (not extrapolated)",
+     "    WR[0] = phiL[0]; WR[1] = -WL[1]; WR[2] = WL[2]; WR[3] = phiL[3];",
+     "    WR[0] = prim[i]; WR[1] = -WL[1]; WR[2] = WL[2]; WR[3] = prim[3 * n + i];",
+     [pins.wall_images]),
+    ("wall ghost gradient not mirrored (ghost extrapolated from the mirrored centroid)",
+     "    WR[0] = phiL[0]; WR[1] = -WL[1]; WR[2] = WL[2]; WR[3] = phiL[3];",
+     "    { double smx, smy, g[4];\n"
+     "      mirror_point(m, code, m->sx[i], m->sy[i], &smx, &smy);\n"
+     "      face_state(prim, lgrad, n, i, fx - smx, fy - smy, g);\n"
+     "      WR[0] = g[0]; WR[1] = -WL[1]; WR[2] = WL[2]; WR[3] = g[3]; }",
+     [pins.wall_images]),
+    ("wall edge moves with the cell's normal velocity",
+     "    wex = w[i] - wn * nx;\n    wey = w[n + i] - wn * ny;",
+     "    wex = w[i];\n    wey = w[n + i];",
+     [pins.wall_images]),
+    ("wall ghost in the gradient keeps the cell's velocity (not mirrored)",
+     "    mirror_vec(v->wall, prim[1 * n + i], prim[2 * n + i], &phi[1], &phi[2]);",
+     "    phi[1] = prim[1 * n + i]; phi[2] = prim[2 * n + i];",
+     [pins.wall_images]),
     ("rounding correction points away from the centroid",
      "double dx = m->sx[i] - m->px[i], dy = m->sy[i] - m->py[i];\n    double d = sqrt(dx * dx + dy * dy);\n    double R = sqrt(m->area[i] / OR_PI);\n    if (d > p->eta * R) {",
      "double dx = m->px[i] - m->sx[i], dy = m->py[i] - m->sy[i];\n    double d = sqrt(dx * dx + dy * dy);\n    double R = sqrt(m->area[i] / OR_PI);\n    if (d > p->eta * R) {",
