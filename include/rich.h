@@ -127,13 +127,9 @@ typedef struct rich_params {
 /* Fill p with the paper's defaults for adiabatic index gamma. */
 void rich_params_default(rich_params* p, double gamma);
 
-/* Workspace bytes one stage of a run with n_cells cells needs: the flag
- * word, the Courant minimum and the device dt, the list of tiles whose halo
- * did not fit the on-chip memory (8 bytes per 128 cells), the Courant block
- * minima (8 bytes per 256 cells) and the point velocities of
- * rich_area_rate (16 bytes per cell).  The reconstruction of the cells never
- * leaves the chip.  The workspace is caller-allocated device memory,
- * 256-byte aligned. */
+/* Workspace bytes one stage of a run with n_cells cells needs (scratch for
+ * the per-cell reconstruction records, the Courant minimum and the flag word).
+ * The workspace is caller-allocated device memory, 256-byte aligned. */
 int rich_workspace_size(int64_t n_cells, size_t* bytes);
 
 /*
@@ -174,9 +170,8 @@ int rich_stage_accel(const rich_mesh* m, const rich_state* src, const rich_state
  *                       bit 1 = (0 <= S*), bit 2 = (0 < S_R); exact solver:
  *                       bit 1 = (0 <= u*), the side of the contact sampled;
  *                       bit 3 = no flux could be formed (vacuum, bad index)
- * Each edge's record is written by its first cell (e_i) while it computes
- * the flux; the arithmetic is the stage's own.  RICH_E_INVAL for null
- * record pointers.
+ * The edge record is taken by a separate launch after the cell pass; the
+ * arithmetic is the stage's own.  RICH_E_INVAL for null record pointers.
  */
 int rich_stage_debug(const rich_mesh* m, const rich_state* src, const rich_state* base,
                      rich_state* out, double h, const rich_params* p, void* ws,
@@ -205,21 +200,20 @@ int rich_area_rate(const rich_mesh* m, const rich_state* s, const rich_params* p
                    double* adot, void* ws, size_t ws_bytes, void* stream);
 
 /*
- * Courant step on the device in front of a stage, with no host round trip
- * (section 2.3): a light pass over the cells of src takes the Courant
- * minimum (the same quantity rich_cfl_dt reduces), a one-block reduction
- * writes dt = cfl * minimum into workspace ws, and the stage is then
- * rich_stage with h = h_factor * dt read from device memory.  (The update of
- * every cell needs the minimum over all of them, so it cannot come from the
- * stage kernel itself.)  A time-centred step is
+ * Courant step fused into a stage, with no host round trip (sections 2.3 and
+ * 2.2): the cell pass of this stage also takes the Courant minimum of src
+ * (the same quantity rich_cfl_dt reduces), a one-block reduction writes
+ * dt = cfl * minimum into workspace ws, and the stage is then rich_stage with
+ * h = h_factor * dt read from device memory.  A time-centred step is
  *   rich_stage_courant(m, s, s, half, 0.5, p, ws, ...)
  *   (tessellate the half-step points)
  *   rich_stage_dt_of(m', half, s, out, 1.0, ws, p, ws, ...)
  * with results bitwise equal to rich_cfl_dt followed by rich_stage with
  * h = dt / 2 and h = dt.  Enqueued on `stream`; nothing synchronises.
  * Arguments are those of rich_stage; h_factor must be finite and >= 0, and
- * p->cfl positive.  A dt that is not positive and finite sets
- * RICH_FLAG_DOMAIN in this stage's flag word.
+ * p->cfl positive.  Returns RICH_E_INVAL, without enqueuing, for integrator 1
+ * (its cell pass needs the step before the minimum exists).  A dt that is
+ * not positive and finite sets RICH_FLAG_DOMAIN in this stage's flag word.
  */
 int rich_stage_courant(const rich_mesh* m, const rich_state* src, const rich_state* base,
                        rich_state* out, double h_factor, const rich_params* p, void* ws,
@@ -282,13 +276,12 @@ int rich_stage_batch_accel(int32_t n, const rich_mesh* const* meshes,
  */
 typedef struct rich_batch_plan {
   int32_t n_runs;
-  int32_t tile;             /* cells per tile of the stage kernel (128, 256, 512) */
-  int32_t n_tiles[2];       /* tiles of the HLLC runs, of the exact-solver runs */
+  int32_t n_cell_tiles;     /* tiles of the cell kernel over all runs          */
+  int32_t n_flux_tiles[2];  /* flux tiles of the HLLC runs, of the exact runs  */
   int32_t n_group[2];       /* number of HLLC runs, of exact-solver runs        */
-  int32_t grid[2];          /* persistent grids of the two stage launches      */
-  int64_t tiles_off[2];     /* workspace byte offsets of the two tile tables    */
-  int64_t ovf_off[2];       /* ... of the two overflow lists                    */
-  int64_t ovfc_off;         /* ... of the two overflow counts                   */
+  int32_t grid_cell;        /* persistent grid of the cell kernel              */
+  int32_t grid_flux[2];     /* persistent grids of the two flux kernels        */
+  int32_t flux_tile;        /* cells per flux tile (edge-tile shape)           */
 } rich_batch_plan;
 int rich_stage_batch_prepare(int32_t n, const rich_mesh* const* meshes,
                              const rich_state* const* src, const rich_state* const* base,
@@ -296,18 +289,18 @@ int rich_stage_batch_prepare(int32_t n, const rich_mesh* const* meshes,
                              const rich_params* const* params, void* ws, size_t ws_bytes,
                              void* stream, rich_batch_plan* plan);
 int rich_stage_batch_launch(const rich_batch_plan* plan, void* ws, void* stream);
-/* As rich_stage_batch_prepare, with tiles of `tile` cells (128, 256 or
+/* As rich_stage_batch_prepare, with flux tiles of `tile` cells (128, 256 or
  * 512; rich_stage_batch_prepare takes 256).  A tile is a group of
- * consecutive cells that one workgroup reconstructs, with their two-ring
- * halo, and updates; the results do not depend on it, bit for bit (a cell's
- * reconstruction and each edge's flux are computed with the same arithmetic
- * wherever they are computed, and each cell sums its edges in CSR order). */
+ * consecutive cells whose owned edges one workgroup solves; the results do
+ * not depend on it, bit for bit (each edge's flux is computed with the same
+ * arithmetic wherever it is computed, and each cell sums its edges in CSR
+ * order). */
 int rich_stage_batch_prepare_tile(int32_t n, const rich_mesh* const* meshes,
                                   const rich_state* const* src, const rich_state* const* base,
                                   rich_state* const* out, const double* h,
                                   const rich_params* const* params, int32_t tile, void* ws,
                                   size_t ws_bytes, void* stream, rich_batch_plan* plan);
-/* Autotune the tile size of a batched stage: prepares and times (HIP
+/* Autotune the edge-tile shape of a batched stage: prepares and times (HIP
  * events, `reps` launches after one warm-up) the stage with each tile of
  * 128, 256 and 512 cells on these runs, writing the mean milliseconds per
  * launch into ms[3] and the fastest tile into *best_tile.  Runs the stage
@@ -532,9 +525,8 @@ int rich_retess_batch_result(int32_t n, void* bws, void* stream, rich_retess_inf
 
 /*
  * Kernel timing for benchmarks.  While enabled, every stage records HIP
- * events on its launch stream around its stage kernel ("k_stage") and
- * around the device Courant pass ("k_cfl": k_cfl and k_cfl_final);
- * rich_profile_read
+ * events on its launch stream around each of its kernels ("k_cell",
+ * "k_flux", or "k_stage" for the fused variant); rich_profile_read
  * synchronises those events, returns the summed duration in milliseconds
  * and the number of launches of the named kernel since the last read, and
  * forgets them.  Not thread-safe; off by default.

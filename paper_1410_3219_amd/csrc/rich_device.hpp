@@ -27,18 +27,6 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr uint32_t kCellMask = 0x0FFFFFFFu;
 constexpr int kRecDoubles = 16;  // reconstruction record: 128 bytes per cell
 
-constexpr int kNumXcd = 8;
-
-// block -> tile, so that XCD x (blocks x, x+8, ...) gets one contiguous range
-// of tiles.  A bijection on [0, nb) for any nb; persistent grids pass the
-// virtual block index of each grid-stride round (their size is a multiple of
-// the CU count, so that index keeps the hardware block's XCD).
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-  const int q = nb / kNumXcd, rem = nb % kNumXcd;
-  const int x = b % kNumXcd, k = b / kNumXcd;
-  return x * q + min(x, rem) + k;
-}
-
 // Everything one stage of one run needs (device pointers).  Passed by value
 // as a kernel argument for a single run, stored in device memory for a batch.
 struct RunDesc {
@@ -56,8 +44,6 @@ struct RunDesc {
   const double* h_dev;  // if set, the step is h_factor * (*h_dev) (device dt)
   double h_factor;
   int32_t* flag;     // status word
-  int32_t* ovf_count;   // tiles whose halo did not fit the LDS ...
-  int2* ovf_list;       // ... as (run, local tile)
   unsigned long long* cfl_min;  // bit pattern of the smallest R/(c+|v-w|)
   // geometry and parameters
   double x0, y0, x1, y1, Lx, Ly;

@@ -1,15 +1,16 @@
 // Kernels and C-ABI of one stage of RICH's moving-mesh Godunov scheme on
-// gfx950 (MI355X).  See rich.h for the interface, rich_fused.hpp for the
-// stage kernel and rich_device.hpp for the per-cell and per-edge arithmetic.
+// gfx950 (MI355X).  See rich.h for the interface and rich_device.hpp for the
+// per-cell and per-edge arithmetic.
 //
-// One stage is one kernel over tiles of consecutive cells (cells come in
-// Hilbert order, so a tile is a compact patch of the mesh): each tile
-// reconstructs its cells and their two-ring halo in LDS and then every cell
-// sums the fluxes of its edges in CSR order (k_stage).  Tiles whose halo does
-// not fit the LDS are finished from global memory by k_stage_overflow.  The
-// Courant step (k_cfl, k_cfl_final) is a separate light pass, since the
-// update of every cell needs the minimum over all of them.
-//
+// One stage is two kernels over tiles of kTile consecutive cells (cells come
+// in Hilbert order, so a tile is a compact patch of the mesh):
+//   k_cell  one thread per cell: primitives, point velocity, gradient and
+//           limiter (A1-A4); writes a 128-byte record per cell.
+//   k_flux  one block per tile: the fluxes of the edges the tile owns (edges
+//           are sorted by their first cell) are computed once each and kept
+//           in LDS; then every cell sums the fluxes of its edges in CSR order
+//           (fluxes of edges owned by another tile are recomputed, bitwise
+//           identical), and writes the updated state and point (A5-A8).
 // No atomics touch the state: the sum order is fixed by the CSR, so the
 // result does not depend on the tile size, the grid or the batch.
 //
@@ -34,34 +35,652 @@
 
 #include "rich.h"
 #include "rich_device.hpp"
-#include "rich_fused.hpp"
 
 static_assert(sizeof(rich_cell) == 48, "rich_cell is three 16-byte chunks");
 static_assert(sizeof(rich_edge) == 32, "rich_edge is two 16-byte chunks");
 
 namespace rich {
 
+#ifndef RICH_LPC
+#define RICH_LPC 2
+#endif
+#ifndef RICH_CELL_MAXE
+#define RICH_CELL_MAXE 6  // CSR entries per cell loaded level by level (the rest in a loop)
+#endif
+#ifndef RICH_CELL_WAVES
+#define RICH_CELL_WAVES 1  // minimum waves per SIMD the register budget must allow
+#endif
+#ifndef RICH_FLUX_WAVES
+#define RICH_FLUX_WAVES 1
+#endif
+#ifndef RICH_FLUX_TILE
+#define RICH_FLUX_TILE 256
+#endif
+constexpr int kTile = RICH_FLUX_TILE;          // k_flux: default cells per tile = threads per block
+constexpr int kCellThreads = 256;   // k_cell: threads per block
+constexpr int kLpc = RICH_LPC;      // k_cell: lanes per cell
+constexpr int kNumXcd = 8;
 constexpr size_t kHeader = 256;  // per-run workspace header
+
+// block -> tile, so that XCD x (blocks x, x+8, ...) gets one contiguous range
+// of tiles.  A bijection on [0, nb) for any nb; persistent grids pass the
+// virtual block index of each grid-stride round (their size is a multiple of
+// the CU count, so that index keeps the hardware block's XCD).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb / kNumXcd, rem = nb % kNumXcd;
+  const int x = b % kNumXcd, k = b / kNumXcd;
+  return x * q + min(x, rem) + k;
+}
+
+// Batched launches take a plan: tile_start[0..n_runs] is the exclusive prefix
+// of the tiles of the runs in this launch, tile_start[n_runs + 1 + k] the
+// descriptor index of the k-th of them.  find_run returns k for tile t.
+__device__ __forceinline__ int find_run(const int32_t* __restrict__ tile_start, int n_runs,
+                                        int t) {
+  int lo = 0, hi = n_runs - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (tile_start[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 // ---------------------------------------------------------------------------
 // workspace header: flag word and Courant minimum
 // ---------------------------------------------------------------------------
-__global__ void k_clear(int32_t* flag, unsigned long long* cfl_min, int32_t* ovf_count) {
+__global__ void k_clear(int32_t* flag, unsigned long long* cfl_min) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     *flag = 0;
     *cfl_min = 0x7FF0000000000000ull;  // +inf
-    *ovf_count = 0;
   }
 }
 
-__global__ void k_clear_batch(const RunDesc* __restrict__ descs, int n_runs,
-                              int32_t* ovf_counts) {
+__global__ void k_clear_batch(const RunDesc* __restrict__ descs, int n_runs) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n_runs) {
     *descs[r].flag = 0;
     *descs[r].cfl_min = 0x7FF0000000000000ull;
   }
-  if (r < 2) ovf_counts[r] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// A1-A4: LPC lanes per cell.  Lane l of a cell's group walks the CSR entries
+// l, l+LPC, ... (neighbour gathers, gradient terms of eq. slope, neighbour
+// bounds, pressure-ratio test), the partial results are combined with a fixed
+// xor-shuffle tree (so every lane of the group holds the same bits), then the
+// limiter pass is split the same way and each lane writes 16/LPC doubles of
+// the cell's 128-byte record.  More lanes per cell shorten each lane's chain
+// of dependent gathers and put more loads in flight.
+// ---------------------------------------------------------------------------
+// The value of lane (lane ^ O).  Within a quad of lanes (O = 1, 2) this is
+// a DPP quad permutation on the vector ALU (no LDS round trip); further
+// apart it is a shuffle.  Moves bits exactly.
+template <int O>
+__device__ __forceinline__ int lane_xor(int v) {
+  if constexpr (O == 1) {
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (O == 2) {
+    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else {
+    return __shfl_xor(v, O);
+  }
+}
+template <int O>
+__device__ __forceinline__ double lane_xor(double v) {
+  const int lo = lane_xor<O>(__double2loint(v));
+  const int hi = lane_xor<O>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Reductions over the LPC lanes of a cell (a fixed xor tree: every lane of
+// the group ends with the same bits).
+template <int LPC, int O = 1>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (O < LPC) return group_sum<LPC, 2 * O>(v + lane_xor<O>(v));
+  return v;
+}
+template <int LPC, int O = 1>
+__device__ __forceinline__ double group_max(double v) {
+  if constexpr (O < LPC) return group_max<LPC, 2 * O>(fmax(v, lane_xor<O>(v)));
+  return v;
+}
+template <int LPC, int O = 1>
+__device__ __forceinline__ double group_min(double v) {
+  if constexpr (O < LPC) return group_min<LPC, 2 * O>(fmin(v, lane_xor<O>(v)));
+  return v;
+}
+template <int LPC, int O = 1>
+__device__ __forceinline__ int group_or(int v) {
+  if constexpr (O < LPC) return group_or<LPC, 2 * O>(v | lane_xor<O>(v));
+  return v;
+}
+
+// Minimum over the block of the cell kernel (kCellThreads lanes).
+__device__ __forceinline__ double block_min_cells(double t) {
+  __shared__ double sm[kCellThreads / 64];
+  for (int o = 32; o > 0; o >>= 1) t = fmin(t, __shfl_xor(t, o));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = t;
+  __syncthreads();
+  double m = sm[0];
+#pragma unroll
+  for (int w = 1; w < kCellThreads / 64; ++w) m = fmin(m, sm[w]);
+  __syncthreads();
+  return m;
+}
+
+// DBG: also write each cell's branch record to dbg[i]: bit 0 the shock
+// flag, bit 1 the cell-rounding correction applied, bits 2..5 alpha < 1 for
+// rho, vx, vy, p.  The production instantiations have DBG = false.
+template <int LPC, bool BATCH, bool DBG = false>
+__global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc one,
+                                                       const RunDesc* __restrict__ descs,
+                                                       const int32_t* __restrict__ tile_start,
+                                                       int n_runs, int n_tiles,
+                                                       uint8_t* __restrict__ dbg) {
+  constexpr int CPB = kCellThreads / LPC;  // cells per block
+  constexpr int MAXE = RICH_CELL_MAXE / LPC;  // entries per lane whose edge offsets stay in registers
+  const int lane = (int)threadIdx.x % LPC;
+  const int cl = (int)threadIdx.x / LPC;
+  for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
+    const int tt = xcd_tile(b, n_tiles);
+    const int pos = BATCH ? find_run(tile_start, n_runs, tt) : 0;
+    const RunDesc& d = BATCH ? descs[tile_start[n_runs + 1 + pos]] : one;
+    const int i0 = (tt - (BATCH ? tile_start[pos] : 0)) * CPB + cl;
+    const bool active = i0 < d.n;
+    const int i = active ? i0 : 0;
+    bool bad = false;
+
+    double rix, riy, A, six, siy;
+    load_cell(d, i, rix, riy, A, six, siy);
+    if (active && !(A > 0.0 && A < INFINITY)) bad = true;  // a mesh cell without a volume
+    double rho, vx, vy, p;
+    prim_of(d, i, A, rho, vx, vy, p);
+    const double c = sqrt(d.gamma * p / rho);
+    const double R = sqrt(A / kPi);
+    double wx = 0.0, wy = 0.0;
+    bool rounded = false;
+    if (d.motion) {
+      // A2 (section 6): Lagrangian motion plus the cell-rounding correction
+      wx = vx;
+      wy = vy;
+      const double dx = six - rix, dy = siy - riy;
+      const double dd = sqrt(dx * dx + dy * dy);
+      if (dd > d.eta * R) {
+        wx += d.chi * c * dx / dd;
+        wy += d.chi * c * dy / dd;
+        rounded = true;
+      }
+    }
+    if (d.cfl_blocks != nullptr) {
+      // A0 fused into the cell pass: the Courant ratio of this cell, as in
+      // k_cfl, reduced to the block's minimum (each cell's lanes agree)
+      const double ux = vx - wx, uy = vy - wy;
+      const double cs = c + sqrt(ux * ux + uy * uy);
+      double ti = R / cs;
+      if (!(ti > 0.0) || !isfinite(ti)) ti = 0.0;
+      if (!active) ti = INFINITY;
+      const double bm = block_min_cells(ti);
+      if (threadIdx.x == 0) d.cfl_blocks[tt] = bm;
+    }
+    const double phi[4] = {rho, vx, vy, p};
+    int k0 = d.off[i], k1 = d.off[i + 1];
+    if (!active || k0 < 0 || k1 < k0 || k1 > d.n_csr) {
+      if (active) bad = true;
+      k1 = k0;
+    }
+    // neighbour values and point across one CSR entry (mirror for a wall)
+    auto nb_values = [&](const NbE& v, double* pj, double& rjx, double& rjy) {
+      if (v.wall) {
+        pj[0] = rho;
+        mirror_vec(v.wall, vx, vy, pj[1], pj[2]);
+        pj[3] = p;
+        mirror_point(d, v.wall, rix, riy, rjx, rjy);
+      } else {
+        double Aj;
+        load_point_area(d, v.j, rjx, rjy, Aj);
+        prim_of(d, v.j, Aj, pj[0], pj[1], pj[2], pj[3]);
+        rjx += v.shx;
+        rjy += v.shy;
+      }
+    };
+
+    // A3: eq. (slope), r_ij = r_i - r_j; each term rounded before it is added
+    double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double pmax[4] = {rho, vx, vy, p}, pmin[4] = {rho, vx, vy, p};
+    int pflag = 0;
+    double fdx[MAXE], fdy[MAXE];
+    auto accumulate = [&](const NbE& v, const double* pj, double vrx, double vry) {
+      const double rx = rix - vrx, ry = riy - vry;
+      const double inv_r = rsqrt(rx * rx + ry * ry);
+      const double cx = v.fx - 0.5 * (rix + vrx), cy = v.fy - 0.5 * (riy + vry);
+      const double ux = cx * inv_r, uy = cy * inv_r, nx = rx * inv_r, ny = ry * inv_r;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double dphi = pj[q] - phi[q];
+        const double mean = 0.5 * (phi[q] + pj[q]);
+        const double tx = v.L * (dphi * ux - mean * nx);
+        const double ty = v.L * (dphi * uy - mean * ny);
+        g[2 * q] += tx;
+        g[2 * q + 1] += ty;
+        pmax[q] = fmax(pmax[q], pj[q]);
+        pmin[q] = fmin(pmin[q], pj[q]);
+      }
+      if (pressure_jump(d.delta_p, p, pj[3])) pflag = 1;
+    };
+    // The first MAXE/LPC entries of each lane go level by level: all CSR
+    // entries, then all edges, then all neighbours, each level's loads issued
+    // together with in-range indices and no branch between them (an entry
+    // past the cell's end reads entry k0 and is ignored), so that a lane waits
+    // for three memory round trips instead of three per entry.
+    {
+      const int kc = max(0, min(k0, d.n_csr - 1));
+      bool val[MAXE];
+      int ent[MAXE];
+#pragma unroll
+      for (int m = 0; m < MAXE; ++m) {
+        const int k = k0 + lane + m * LPC;
+        val[m] = k < k1;
+        ent[m] = d.idx[val[m] ? k : kc];
+      }
+      int ee[MAXE];
+#pragma unroll
+      for (int m = 0; m < MAXE; ++m) {
+        int e = ent[m] >> 1;
+        if (val[m] && (e < 0 || e >= d.n_edges)) {
+          bad = true;
+          val[m] = false;
+        }
+        ee[m] = val[m] ? e : 0;
+      }
+      uint32_t ej[MAXE];
+      int ei[MAXE];
+      double eL[MAXE], efx[MAXE], efy[MAXE];
+#pragma unroll
+      for (int m = 0; m < MAXE; ++m) {
+        const EdgeRec er = load_edge(d, ee[m]);
+        ej[m] = er.j;
+        ei[m] = er.i;
+        eL[m] = er.L;
+        efx[m] = er.fx;
+        efy[m] = er.fy;
+      }
+      NbE v[MAXE];
+#pragma unroll
+      for (int m = 0; m < MAXE; ++m) {
+        const int side = ent[m] & 1;
+        const int code = (int)(ej[m] >> 28);
+        v[m].L = eL[m];
+        v[m].fx = efx[m];
+        v[m].fy = efy[m];
+        shift_of(d, code, v[m].shx, v[m].shy);
+        v[m].wall = (side == 0 && code >= 9) ? code : 0;
+        int j = side == 0 ? (int)(ej[m] & kCellMask) : ei[m];
+        if (side) {
+          v[m].shx = -v[m].shx;
+          v[m].shy = -v[m].shy;
+          v[m].fx += v[m].shx;
+          v[m].fy += v[m].shy;
+        }
+        if (v[m].wall) j = i;
+        if (val[m] && (j < 0 || j >= d.n)) {
+          bad = true;
+          j = i;
+        }
+        v[m].j = val[m] ? j : i;
+      }
+      double nA[MAXE], nM[MAXE], nPx[MAXE], nPy[MAXE], nE[MAXE], nx_[MAXE], ny_[MAXE];
+#pragma unroll
+      for (int m = 0; m < MAXE; ++m) {
+        const int j = v[m].j;
+        load_point_area(d, j, nx_[m], ny_[m], nA[m]);
+        nM[m] = d.sM[j];
+        nPx[m] = d.sPx[j];
+        nPy[m] = d.sPy[j];
+        nE[m] = d.sE[j];
+      }
+#pragma unroll
+      for (int m = 0; m < MAXE; ++m) {
+        fdx[m] = 0.0;
+        fdy[m] = 0.0;
+        if (val[m]) {
+          double pj[4], vrx, vry;
+          if (v[m].wall) {
+            pj[0] = rho;
+            mirror_vec(v[m].wall, vx, vy, pj[1], pj[2]);
+            pj[3] = p;
+            mirror_point(d, v[m].wall, rix, riy, vrx, vry);
+          } else {
+            prim_from(d, nA[m], nM[m], nPx[m], nPy[m], nE[m], pj[0], pj[1], pj[2], pj[3]);
+            vrx = nx_[m] + v[m].shx;
+            vry = ny_[m] + v[m].shy;
+          }
+          accumulate(v[m], pj, vrx, vry);
+          fdx[m] = v[m].fx - six;
+          fdy[m] = v[m].fy - siy;
+        }
+      }
+    }
+    for (int k = k0 + lane + MAXE * LPC; k < k1; k += LPC) {
+      const NbE v = nb_edge(d, i, d.idx[k], bad);
+      double pj[4], vrx, vry;
+      nb_values(v, pj, vrx, vry);
+      accumulate(v, pj, vrx, vry);
+    }
+    double G[8];
+    const double rA = 1.0 / A;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) G[q] = group_sum<LPC>(g[q]) * rA;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      pmax[q] = group_max<LPC>(pmax[q]);
+      pmin[q] = group_min<LPC>(pmin[q]);
+    }
+    bool shock = group_or<LPC>(pflag) != 0;
+    if (-(G[2] + G[5]) > d.delta_v * c / R) shock = true;
+
+    // A4: limiter
+    double alpha[4] = {1.0, 1.0, 1.0, 1.0};
+    int local = -1;
+    if (d.limiter == 0) local = shock ? 1 : 0;
+    if (d.limiter == 1) local = 0;
+    if (d.limiter == 2) local = 1;
+    if (d.limiter == 4) alpha[0] = alpha[1] = alpha[2] = alpha[3] = 0.0;
+    if (local == 0) {
+      // global limiter: min_j psi_ij is attained at the largest positive and
+      // the most negative change (division is monotone in the denominator)
+      double dmax[4] = {0, 0, 0, 0}, dmin[4] = {0, 0, 0, 0};
+      auto bound = [&](double dx, double dy) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double dphi = G[2 * q] * dx + G[2 * q + 1] * dy;
+          dmax[q] = fmax(dmax[q], dphi);
+          dmin[q] = fmin(dmin[q], dphi);
+        }
+      };
+#pragma unroll
+      for (int m = 0; m < MAXE; ++m)
+        if (k0 + lane + m * LPC < k1) bound(fdx[m], fdy[m]);
+      for (int k = k0 + lane + MAXE * LPC; k < k1; k += LPC) {
+        const NbE v = nb_edge(d, i, d.idx[k], bad);
+        bound(v.fx - six, v.fy - siy);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        dmax[q] = group_max<LPC>(dmax[q]);
+        dmin[q] = group_min<LPC>(dmin[q]);
+        if (dmax[q] > 0.0) alpha[q] = fmin(alpha[q], (pmax[q] - phi[q]) / dmax[q]);
+        if (dmin[q] < 0.0) alpha[q] = fmin(alpha[q], (pmin[q] - phi[q]) / dmin[q]);
+      }
+    } else if (local == 1) {
+      for (int k = k0 + lane; k < k1; k += LPC) {
+        const NbE v = nb_edge(d, i, d.idx[k], bad);
+        double pj[4], vrx, vry;
+        nb_values(v, pj, vrx, vry);
+        const double dx = v.fx - six, dy = v.fy - siy;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double dphi = G[2 * q] * dx + G[2 * q + 1] * dy;
+          const double psi =
+              (dphi != 0.0) ? fmax(d.theta * (pj[q] - phi[q]) / dphi, 0.0) : 1.0;
+          alpha[q] = fmin(alpha[q], psi);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) alpha[q] = group_min<LPC>(alpha[q]);
+    }
+    const int bad_any = group_or<LPC>(bad ? 1 : 0);
+    if (active) {
+      double rec[kRecDoubles];
+      rec[R_RHO] = rho;
+      rec[R_VX] = vx;
+      rec[R_VY] = vy;
+      rec[R_P] = p;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) rec[R_G + q] = G[q] * alpha[q / 2];
+      if (d.integrator == 1) {
+        // extrapolated fluxes (section 2.3): the primitives advanced half a
+        // step with the time derivatives the limited gradients give in the
+        // primitive Euler equations, following the cell's point (v - w)
+        const double* g = rec + R_G;
+        const double ux = vx - wx, uy = vy - wy;
+        const double div = g[2] + g[5];
+        const double rho_t = -(ux * g[0] + uy * g[1]) - rho * div;
+        const double vx_t = -(ux * g[2] + uy * g[3]) - g[6] / rho;
+        const double vy_t = -(ux * g[4] + uy * g[5]) - g[7] / rho;
+        const double p_t = -(ux * g[6] + uy * g[7]) - d.gamma * p * div;
+        const double hh = 0.5 * (d.h_dev != nullptr ? d.h_factor * (*d.h_dev) : d.h);
+        rec[R_RHO] = rho + hh * rho_t;
+        rec[R_VX] = vx + hh * vx_t;
+        rec[R_VY] = vy + hh * vy_t;
+        rec[R_P] = p + hh * p_t;
+      }
+      rec[R_WX] = wx;
+      rec[R_WY] = wy;
+      rec[R_SX] = six;
+      rec[R_SY] = siy;
+      constexpr int PER = kRecDoubles / LPC;  // doubles written by each lane
+      double2* dst = reinterpret_cast<double2*>(d.rec + (size_t)i * kRecDoubles + lane * PER);
+#pragma unroll
+      for (int k = 0; k < PER / 2; ++k) {
+        // select this lane's slice with compile-time indices only
+        double a0 = rec[2 * k], a1 = rec[2 * k + 1];
+#pragma unroll
+        for (int l = 1; l < LPC; ++l)
+          if (lane == l) {
+            a0 = rec[l * PER + 2 * k];
+            a1 = rec[l * PER + 2 * k + 1];
+          }
+        dst[k] = make_double2(a0, a1);
+      }
+      if (bad_any && lane == 0) atomicOr(d.flag, RICH_FLAG_DOMAIN);
+      if constexpr (DBG) {
+        if (lane == 0) {
+          int bits = (shock ? 1 : 0) | (rounded ? 2 : 0);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bits |= (alpha[q] < 1.0 ? 4 << q : 0);
+          dbg[i] = (uint8_t)bits;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A5-A8: one block per tile of kTile cells.
+//   phase 0  classify the tile's CSR entries: an edge the tile owns (first
+//            cell inside the tile, within the LDS capacity) is found at its
+//            position in the owned range; any other edge goes on a list
+//   phase 1  all lanes compute the owned edges and the listed edges, once
+//            each, into LDS
+//   phase 2  one lane per cell sums its entries in CSR order
+// Fluxes of edges whose first cell lies in another tile are computed by both
+// tiles, with the same code on the same inputs, hence the same bits.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wrap_once(double v, double lo, double hi) {
+  const double L = hi - lo;
+  if (v < lo) v += L;
+  if (v >= hi) v -= L;
+  return v;
+}
+
+// A5-A7 for edge e from the records of its two cells in the workspace.
+template <int RIEMANN>
+__device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF,
+                                             uint8_t* br = nullptr) {
+  double ri[kRecDoubles], rj[kRecDoubles];
+  if (e < 0 || e >= d.n_edges) {
+    LF[0] = LF[1] = LF[2] = LF[3] = 0.0;
+    return false;
+  }
+  const EdgeRec er = load_edge(d, e);
+  const int i = er.i;
+  const uint32_t ej = er.j;
+  if (i < 0 || i >= d.n) {
+    LF[0] = LF[1] = LF[2] = LF[3] = 0.0;
+    return false;
+  }
+  load_rec(d.rec, i, ri);
+  if ((ej >> 28) < 9) {
+    int j = (int)(ej & kCellMask);
+    if (j >= d.n) j = i;
+    load_rec(d.rec, j, rj);
+  }
+  double rix, riy;
+  load_point(d, i, rix, riy);
+  return edge_flux_at<RIEMANN>(d, i, ej, er.fx, er.fy, er.L, rix, riy, ri, rj, LF, br);
+}
+
+// Debug record of the Riemann solver's branch on every edge (one thread per
+// edge), from the cell records of the stage; arithmetic identical to k_flux.
+template <int RIEMANN>
+__global__ __launch_bounds__(256) void k_edge_bits(RunDesc d, uint8_t* bits) {
+  const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (e >= d.n_edges) return;
+  double LF[4];
+  uint8_t b = 0;
+  if (!flux_of_edge<RIEMANN>(d, e, LF, &b)) b |= 8;
+  bits[e] = b;
+}
+
+template <int RIEMANN, bool BATCH, int TILE = kTile>
+__global__ __launch_bounds__(TILE, RICH_FLUX_WAVES) void k_flux(RunDesc one, const RunDesc* __restrict__ descs,
+                                                const int32_t* __restrict__ tile_start,
+                                                int n_runs, int n_tiles) {
+  // LDS capacities in proportion to the tile: fluxes of the owned edges
+  // (about 3 per cell), of other edges the tile's cells need (its border),
+  // and the classification of the tile's CSR entries (about 6 per cell)
+  constexpr int kEdgeCap = TILE * 25 / 8, kForCap = TILE * 3 / 4, kMapCap = TILE * 9;
+  __shared__ double sF[4][kEdgeCap + kForCap];
+  __shared__ int s_forE[kForCap];
+  __shared__ short s_map[kMapCap];  // (flux slot << 1) | side, or -1
+  __shared__ int s_off[TILE + 1];  // the tile's CSR offsets
+  __shared__ int s_nfor;
+  const int tid = (int)threadIdx.x;
+  for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
+    const int t = xcd_tile(b, n_tiles);
+    const int pos = BATCH ? find_run(tile_start, n_runs, t) : 0;
+    const RunDesc& d = BATCH ? descs[tile_start[n_runs + 1 + pos]] : one;
+    const int c0 = (t - (BATCH ? tile_start[pos] : 0)) * TILE;
+    const int c1 = min(c0 + TILE, d.n);
+    const int e0 = d.eoff[c0];
+    const int ne = max(0, min(d.eoff[c1] - e0, kEdgeCap));
+    const int kb = d.off[c0];
+    const int S = max(0, min(d.off[c1], d.n_csr) - kb);
+    const int Sm = min(S, kMapCap);
+    bool ok = true;
+    if (tid == 0) s_nfor = 0;
+    for (int c = tid; c <= c1 - c0; c += TILE) s_off[c] = d.off[c0 + c];
+    __syncthreads();
+    // all of a lane's CSR entries are loaded first (independent loads in
+    // flight together), then classified
+    constexpr int MPT = kMapCap / TILE;
+    int ent[MPT];
+#pragma unroll
+    for (int r = 0; r < MPT; ++r) {
+      const int s = tid + r * TILE;
+      ent[r] = s < Sm ? d.idx[kb + s] : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < MPT; ++r) {
+      const int s = tid + r * TILE;
+      if (s >= Sm) break;
+      const int entry = ent[r];
+      const int e = entry >> 1;
+      int m = -1;
+      if (e >= e0 && e < e0 + ne) {
+        m = e - e0;
+      } else if (e >= 0 && e < d.n_edges) {
+        const int f = atomicAdd(&s_nfor, 1);
+        if (f < kForCap) {
+          s_forE[f] = e;
+          m = kEdgeCap + f;
+        }
+      }
+      s_map[s] = (short)(m < 0 ? -1 : (m << 1) | (entry & 1));
+    }
+    __syncthreads();
+    const int nfor = min(s_nfor, kForCap);
+    for (int w = tid; w < ne + nfor; w += TILE) {
+      const int e = w < ne ? e0 + w : s_forE[w - ne];
+      const int pos = w < ne ? w : kEdgeCap + (w - ne);
+      double LF[4];
+      if (!flux_of_edge<RIEMANN>(d, e, LF)) ok = false;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sF[q][pos] = LF[q];
+    }
+    __syncthreads();
+    const int i = c0 + tid;
+    if (i < c1) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      int k0 = s_off[tid], k1 = s_off[tid + 1];
+      if (k0 < kb || k1 < k0 || k1 > kb + S) {
+        ok = false;
+        k1 = k0;
+      }
+      for (int k = k0; k < k1; ++k) {
+        const int s = k - kb;
+        const int ms = s < Sm ? (int)s_map[s] : -1;
+        double LF[4];
+        int side;
+        if (ms >= 0) {
+          const int m = ms >> 1;
+          side = ms & 1;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) LF[q] = sF[q][m];
+        } else {
+          const int entry = d.idx[k];
+          side = entry & 1;
+          if (!flux_of_edge<RIEMANN>(d, entry >> 1, LF)) ok = false;
+        }
+        if (side) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q] -= LF[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q] += LF[q];
+        }
+      }
+      const double h = d.h_dev != nullptr ? d.h_factor * (*d.h_dev) : d.h;
+      const double M = d.bM[i] - h * acc[0];
+      double Px = d.bPx[i] - h * acc[1];
+      double Py = d.bPy[i] - h * acc[2];
+      double E = d.bE[i] - h * acc[3];
+      double gx = d.gx, gy = d.gy;
+      if (d.ax != nullptr) {  // the cell's own acceleration
+        gx += d.ax[i];
+        gy += d.ay[i];
+      }
+      if (gx != 0.0 || gy != 0.0) {
+        // external acceleration: h (0, M g, P.g) of the stage's source totals
+        const double sm = d.sM[i], spx = d.sPx[i], spy = d.sPy[i];
+        Px += h * (sm * gx);
+        Py += h * (sm * gy);
+        E += h * (spx * gx + spy * gy);
+      }
+      const double* rec = d.rec + (size_t)i * kRecDoubles;
+      const double wxi = rec[R_WX], wyi = rec[R_WY];
+      double x = d.bx[i] + h * wxi;
+      double y = d.by[i] + h * wyi;
+      if (d.bc == RICH_BOUNDARY_PERIODIC) {
+        x = wrap_once(x, d.x0, d.x1);
+        y = wrap_once(y, d.y0, d.y1);
+        if (!(x >= d.x0 && x < d.x1 && y >= d.y0 && y < d.y1)) ok = false;
+      }
+      d.oM[i] = M;
+      d.oPx[i] = Px;
+      d.oPy[i] = Py;
+      d.oE[i] = E;
+      d.ox[i] = x;
+      d.oy[i] = y;
+      const double eint = E - 0.5 * (Px * Px + Py * Py) / M;
+      if (!(M > 0.0) || !(eint > 0.0) || !isfinite(E) || !isfinite(Px) || !isfinite(Py) ||
+          !isfinite(x) || !isfinite(y))
+        ok = false;
+    }
+    if (!ok) atomicOr(d.flag, RICH_FLAG_DOMAIN);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -88,25 +707,14 @@ __device__ __forceinline__ double block_min(double t, double* smin) {
 // the moving frame, so dA_i/dt = -sum_j L_ij ((w_j - w_i).c_ij - (w_i + w_j)/2 .
 // r_ij) / |r_ij| with r_ij from point i to the neighbour (image or mirror) and
 // c_ij from their midpoint to the edge centre.  The point velocities come
-// from k_wvel (w[2i], w[2i+1]).
-__global__ __launch_bounds__(kCflThreads) void k_wvel(RunDesc d, double* w) {
-  const int i = blockIdx.x * kCflThreads + threadIdx.x;
-  if (i >= d.n) return;
-  Own o;
-  double q[4];
-  own_load(d, i, o, q);
-  own_from(d, q[0], q[1], q[2], q[3], o);
-  w[2 * (size_t)i] = o.wx;
-  w[2 * (size_t)i + 1] = o.wy;
-}
-
-__global__ __launch_bounds__(kCflThreads) void k_adot(RunDesc d, const double* w,
-                                                      double* adot) {
+// from the records that k_cell wrote.
+__global__ __launch_bounds__(kCflThreads) void k_adot(RunDesc d, double* adot) {
   const int i = blockIdx.x * kCflThreads + threadIdx.x;
   if (i >= d.n) return;
   double rix, riy;
   load_point(d, i, rix, riy);
-  const double wix = w[2 * (size_t)i], wiy = w[2 * (size_t)i + 1];
+  const double* ri = d.rec + (size_t)i * kRecDoubles;
+  const double wix = ri[R_WX], wiy = ri[R_WY];
   int k0 = d.off[i], k1 = d.off[i + 1];
   bool bad = false;
   if (k0 < 0 || k1 < k0 || k1 > d.n_csr) {
@@ -124,8 +732,9 @@ __global__ __launch_bounds__(kCflThreads) void k_adot(RunDesc d, const double* w
       load_point(d, v.j, rjx, rjy);
       rjx += v.shx;
       rjy += v.shy;
-      wjx = w[2 * (size_t)v.j];
-      wjy = w[2 * (size_t)v.j + 1];
+      const double* rj = d.rec + (size_t)v.j * kRecDoubles;
+      wjx = rj[R_WX];
+      wjy = rj[R_WY];
     }
     const double rx = rjx - rix, ry = rjy - riy;
     const double r = sqrt(rx * rx + ry * ry);
@@ -217,31 +826,13 @@ int hip_status(hipError_t e) { return e == hipSuccess ? RICH_OK : RICH_E_DEVICE;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Workspace of one run: a 256-byte header (flag word @0, Courant minimum @8,
-// device dt @16, overflow count @24), the overflow list (one (run, tile)
-// pair per tile of the smallest tile size), the Courant block minima, and
-// the point velocities of the area-rate call.
-constexpr size_t kDtOffset = 16;
-constexpr size_t kOvfOffset = 24;
-constexpr int kMinTile = 128;
-struct RunWs {
-  size_t ovf, cfl, w, total;
-};
-RunWs run_ws(int64_t n) {
-  RunWs L;
-  size_t o = rich::kHeader;
-  L.ovf = o;
-  o += align_up(sizeof(int2) * (size_t)((n + kMinTile - 1) / kMinTile), 256);
-  L.cfl = o;
-  o += align_up(sizeof(double) * (size_t)std::min<int64_t>(
-                                     (n + rich::kCflThreads - 1) / rich::kCflThreads,
-                                     rich::kCflMaxBlocks), 256);
-  L.w = o;
-  o += align_up(2 * sizeof(double) * (size_t)n, 256);
-  L.total = o;
-  return L;
+constexpr int64_t kCellsPerBlock = rich::kCellThreads / rich::kLpc;
+constexpr size_t kDtOffset = 16;  // header: flag @0, Courant minimum @8, dt @16
+
+size_t run_ws_bytes(int64_t n) {
+  return rich::kHeader + align_up((size_t)n * rich::kRecDoubles * sizeof(double), 256) +
+         align_up((size_t)((n + kCellsPerBlock - 1) / kCellsPerBlock) * sizeof(double), 256);
 }
-size_t run_ws_bytes(int64_t n) { return run_ws(n).total; }
 
 bool valid_mesh(const rich_mesh* m) {
   return m && m->n_cells > 0 && m->n_cells <= (int64_t)rich::kCellMask && m->n_edges >= 0 &&
@@ -281,12 +872,9 @@ RunDesc make_desc(const rich_mesh* m, const rich_state* src, const rich_state* b
     d.oM = out->M; d.oPx = out->Px; d.oPy = out->Py; d.oE = out->E;
     d.ox = out->x; d.oy = out->y;
   }
-  const RunWs L = run_ws(m->n_cells);
   d.flag = reinterpret_cast<int32_t*>(ws);
   d.cfl_min = reinterpret_cast<unsigned long long*>(ws + 8);
-  d.ovf_count = reinterpret_cast<int32_t*>(ws + kOvfOffset);
-  d.ovf_list = reinterpret_cast<int2*>(ws + L.ovf);
-  d.rec = reinterpret_cast<double*>(ws + L.w);
+  d.rec = reinterpret_cast<double*>(ws + rich::kHeader);
   d.x0 = m->box[0]; d.y0 = m->box[1]; d.x1 = m->box[2]; d.y1 = m->box[3];
   d.Lx = m->box[2] - m->box[0];
   d.Ly = m->box[3] - m->box[1];
@@ -346,89 +934,53 @@ void prof_end(int k, hipStream_t st) {
   if (k >= 0) (void)hipEventRecord(profiler().pending[k].b, st);
 }
 
-#ifndef RICH_STAGE_TILE
-#define RICH_STAGE_TILE 256
-#endif
-constexpr int kStageTile = RICH_STAGE_TILE;   // cells per tile of the fused stage kernel
-
-// Courant step on the device: per-block minima of R/(c + |v - w|) into
-// d.cfl_blocks, then dt = cfl * minimum into *d.h_dev (the workspace's dt
-// slot), before the stage that reads it.
-int launch_courant(const RunDesc& d, hipStream_t st) {
-  const int nb = std::min<int>((d.n + rich::kCflThreads - 1) / rich::kCflThreads,
-                               rich::kCflMaxBlocks);
-  int pc = prof_begin("k_cfl", st);
-  hipLaunchKernelGGL(rich::k_cfl, dim3(nb), dim3(rich::kCflThreads), 0, st, d, d.cfl_blocks);
-  hipLaunchKernelGGL(rich::k_cfl_final, dim3(1), dim3(rich::kCflFinalThreads), 0, st,
-                     (const double*)d.cfl_blocks, nb, d.cfl_min, d.cfl,
-                     const_cast<double*>(d.h_dev), d.flag);
-  prof_end(pc, st);
-  return RICH_OK;
-}
-
-constexpr int kOverflowGrid = 256;  // blocks of the overflow pass (most exit at once)
-
 int launch_stage(const RunDesc& d, int riemann, hipStream_t st, uint8_t* dbg_cell = nullptr,
                  uint8_t* dbg_edge = nullptr) {
-  constexpr int T = kStageTile;
+  constexpr int T = rich::kTile;
   const int n_tiles = (d.n + T - 1) / T;
-  const int og = std::min(n_tiles, kOverflowGrid);
-  hipLaunchKernelGGL(rich::k_clear, dim3(1), dim3(64), 0, st, d.flag, d.cfl_min, d.ovf_count);
-  if (d.cfl_blocks != nullptr) launch_courant(d, st);
-  const bool dbg = dbg_cell != nullptr;
-  int pf = prof_begin("k_stage", st);
-  if (riemann == 1) {
-    if (dbg)
-      hipLaunchKernelGGL((rich::k_stage<T, 1, false, true>), dim3(n_tiles), dim3(rich::TileCfg<T>::kThreads), 0, st, d,
-                         (const RunDesc*)nullptr, (const int2*)nullptr, n_tiles, dbg_cell,
-                         dbg_edge);
+  constexpr int CPB = rich::kCellThreads / rich::kLpc;
+  const int n_ctiles = (d.n + CPB - 1) / CPB;
+  hipLaunchKernelGGL(rich::k_clear, dim3(1), dim3(64), 0, st, d.flag, d.cfl_min);
+  int pc = prof_begin("k_cell", st);
+  if (dbg_cell != nullptr)
+    hipLaunchKernelGGL((rich::k_cell<rich::kLpc, false, true>), dim3(n_ctiles),
+                       dim3(rich::kCellThreads), 0, st, d, (const RunDesc*)nullptr,
+                       (const int32_t*)nullptr, 1, n_ctiles, dbg_cell);
+  else
+    hipLaunchKernelGGL((rich::k_cell<rich::kLpc, false>), dim3(n_ctiles),
+                       dim3(rich::kCellThreads), 0, st, d, (const RunDesc*)nullptr,
+                       (const int32_t*)nullptr, 1, n_ctiles, (uint8_t*)nullptr);
+  prof_end(pc, st);
+  if (dbg_edge != nullptr && d.n_edges > 0) {
+    const int eb = (int)((d.n_edges + 255) / 256);
+    if (riemann == 1)
+      hipLaunchKernelGGL(rich::k_edge_bits<1>, dim3(eb), dim3(256), 0, st, d, dbg_edge);
     else
-      hipLaunchKernelGGL((rich::k_stage<T, 1, false>), dim3(n_tiles), dim3(rich::TileCfg<T>::kThreads), 0, st, d,
-                         (const RunDesc*)nullptr, (const int2*)nullptr, n_tiles,
-                         (uint8_t*)nullptr, (uint8_t*)nullptr);
-  } else {
-    if (dbg)
-      hipLaunchKernelGGL((rich::k_stage<T, 0, false, true>), dim3(n_tiles), dim3(rich::TileCfg<T>::kThreads), 0, st, d,
-                         (const RunDesc*)nullptr, (const int2*)nullptr, n_tiles, dbg_cell,
-                         dbg_edge);
-    else
-      hipLaunchKernelGGL((rich::k_stage<T, 0, false>), dim3(n_tiles), dim3(rich::TileCfg<T>::kThreads), 0, st, d,
-                         (const RunDesc*)nullptr, (const int2*)nullptr, n_tiles,
-                         (uint8_t*)nullptr, (uint8_t*)nullptr);
+      hipLaunchKernelGGL(rich::k_edge_bits<0>, dim3(eb), dim3(256), 0, st, d, dbg_edge);
   }
+  if (d.cfl_blocks != nullptr)   // dt from the cell kernel's Courant minima
+    hipLaunchKernelGGL(rich::k_cfl_final, dim3(1), dim3(rich::kCflFinalThreads), 0, st,
+                       (const double*)d.cfl_blocks, n_ctiles, d.cfl_min, d.cfl,
+                       const_cast<double*>(d.h_dev), d.flag);
+  int pf = prof_begin("k_flux", st);
+  if (riemann == 1)
+    hipLaunchKernelGGL((rich::k_flux<1, false>), dim3(n_tiles), dim3(T), 0, st, d,
+                       (const RunDesc*)nullptr, (const int32_t*)nullptr, 1, n_tiles);
+  else
+    hipLaunchKernelGGL((rich::k_flux<0, false>), dim3(n_tiles), dim3(T), 0, st, d,
+                       (const RunDesc*)nullptr, (const int32_t*)nullptr, 1, n_tiles);
   prof_end(pf, st);
-  const int* oc = d.ovf_count;
-  const int2* ol = d.ovf_list;
-  const RunDesc* nd = nullptr;
-  if (riemann == 1) {
-    if (dbg)
-      hipLaunchKernelGGL((rich::k_stage_overflow<T, 1, false, true>), dim3(og), dim3(T), 0, st, d,
-                         nd, oc, ol, dbg_cell, dbg_edge);
-    else
-      hipLaunchKernelGGL((rich::k_stage_overflow<T, 1, false>), dim3(og), dim3(T), 0, st, d, nd,
-                         oc, ol, (uint8_t*)nullptr, (uint8_t*)nullptr);
-  } else {
-    if (dbg)
-      hipLaunchKernelGGL((rich::k_stage_overflow<T, 0, false, true>), dim3(og), dim3(T), 0, st, d,
-                         nd, oc, ol, dbg_cell, dbg_edge);
-    else
-      hipLaunchKernelGGL((rich::k_stage_overflow<T, 0, false>), dim3(og), dim3(T), 0, st, d, nd,
-                         oc, ol, (uint8_t*)nullptr, (uint8_t*)nullptr);
-  }
   return hip_status(hipGetLastError());
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// batch workspace: a fixed part that depends on the number of runs only
-// (descriptors, flag words, Courant minima, the two overflow counts), then
-// the tile table and the two overflow lists, each with room for the tiles
-// of the smallest tile size
+// batch workspace:  [descriptors][plans][flags][Courant minima][records...]
 // ---------------------------------------------------------------------------
 struct BatchLayout {
-  size_t desc, flags, cfl, ovfc, tiles, ovf[2], total;
-  int64_t max_tiles;
+  size_t desc, plan, flags, cfl, rec, total;
+  std::vector<size_t> rec_off;
 };
 
 BatchLayout batch_layout(int32_t n, const int64_t* n_cells) {
@@ -436,26 +988,24 @@ BatchLayout batch_layout(int32_t n, const int64_t* n_cells) {
   size_t o = 0;
   L.desc = o;
   o += align_up((size_t)n * sizeof(RunDesc), 256);
+  L.plan = o;
+  o += align_up((size_t)3 * (2 * (size_t)n + 1) * sizeof(int32_t), 256);
   L.flags = o;
   o += align_up((size_t)n * sizeof(int32_t), 256);
   L.cfl = o;
   o += align_up((size_t)n * sizeof(unsigned long long), 256);
-  L.ovfc = o;
-  o += 256;
-  L.max_tiles = 0;
-  if (n_cells)
-    for (int32_t r = 0; r < n; ++r) L.max_tiles += (n_cells[r] + kMinTile - 1) / kMinTile;
-  const size_t tb = align_up(sizeof(int2) * (size_t)L.max_tiles, 256);
-  L.tiles = o;
-  o += tb;
-  L.ovf[0] = o;
-  o += tb;
-  L.ovf[1] = o;
-  o += tb;
+  L.rec = o;
+  L.rec_off.resize(n);
+  for (int32_t r = 0; r < n; ++r) {
+    L.rec_off[r] = o;
+    o += align_up((size_t)n_cells[r] * rich::kRecDoubles * sizeof(double), 256);
+  }
   L.total = o;
   return L;
 }
 
+// Pinned host staging for the descriptor uploads: a ring of buffers, each
+// reused only after the copy that last read it has completed.
 struct Staging {
   struct Buf {
     void* p = nullptr;
@@ -507,6 +1057,19 @@ int upload_staged(void* dst1, const void* src1, size_t b1, void* dst2, const voi
       hipEventRecord(ev, st) != hipSuccess)
     return RICH_E_DEVICE;
   return RICH_OK;
+}
+
+// The batched flux kernel of solver k (0 HLLC, 1 exact) with tiles of `tile` cells.
+void launch_flux_batch(int k, int tile, int grid, hipStream_t st, const RunDesc& dummy,
+                       const RunDesc* dd, const int32_t* dpf, int n_group, int n_tiles) {
+  switch (k * 4 + (tile == 128 ? 0 : tile == 256 ? 1 : 2)) {
+    case 0: hipLaunchKernelGGL((rich::k_flux<0, true, 128>), dim3(grid), dim3(128), 0, st, dummy, dd, dpf, n_group, n_tiles); break;
+    case 1: hipLaunchKernelGGL((rich::k_flux<0, true, 256>), dim3(grid), dim3(256), 0, st, dummy, dd, dpf, n_group, n_tiles); break;
+    case 2: hipLaunchKernelGGL((rich::k_flux<0, true, 512>), dim3(grid), dim3(512), 0, st, dummy, dd, dpf, n_group, n_tiles); break;
+    case 4: hipLaunchKernelGGL((rich::k_flux<1, true, 128>), dim3(grid), dim3(128), 0, st, dummy, dd, dpf, n_group, n_tiles); break;
+    case 5: hipLaunchKernelGGL((rich::k_flux<1, true, 256>), dim3(grid), dim3(256), 0, st, dummy, dd, dpf, n_group, n_tiles); break;
+    default: hipLaunchKernelGGL((rich::k_flux<1, true, 512>), dim3(grid), dim3(512), 0, st, dummy, dd, dpf, n_group, n_tiles); break;
+  }
 }
 
 int resident_blocks(const void* kernel, int threads) {
@@ -786,6 +1349,8 @@ int stage_with_device_dt(const rich_mesh* m, const rich_state* src, const rich_s
     return RICH_E_INVAL;
   if (!std::isfinite(h_factor) || h_factor < 0.0) return RICH_E_INVAL;
   if (!(p->cfl > 0.0) || !std::isfinite(p->cfl)) return RICH_E_INVAL;
+  // extrapolated fluxes need the step inside the cell pass, before its minimum exists
+  if (courant && p->integrator == 1) return RICH_E_INVAL;
   if (out->M == src->M || out->M == base->M || out->x == base->x) return RICH_E_INVAL;
   if (ws_bytes < run_ws_bytes(n) || (reinterpret_cast<uintptr_t>(ws) & 255)) return RICH_E_NOMEM;
   if (dt_ws && (reinterpret_cast<uintptr_t>(dt_ws) & 255)) return RICH_E_INVAL;
@@ -793,7 +1358,8 @@ int stage_with_device_dt(const rich_mesh* m, const rich_state* src, const rich_s
   RunDesc d = make_desc(m, src, base, out, 0.0, p, w);
   d.h_factor = h_factor;
   if (courant) {
-    d.cfl_blocks = reinterpret_cast<double*>(w + run_ws(n).cfl);
+    d.cfl_blocks = reinterpret_cast<double*>(
+        w + rich::kHeader + align_up((size_t)n * rich::kRecDoubles * sizeof(double), 256));
     d.h_dev = reinterpret_cast<const double*>(w + kDtOffset);
   } else {
     d.h_dev = reinterpret_cast<const double*>(static_cast<const char*>(dt_ws) + kDtOffset);
@@ -842,12 +1408,15 @@ int rich_area_rate(const rich_mesh* m, const rich_state* s, const rich_params* p
     return RICH_E_NOMEM;
   hipStream_t st = static_cast<hipStream_t>(stream);
   RunDesc d = make_desc(m, s, nullptr, nullptr, 0.0, p, static_cast<char*>(ws));
-  const int nb = (d.n + rich::kCflThreads - 1) / rich::kCflThreads;
-  // the point velocities into the workspace, then the rates
-  hipLaunchKernelGGL(rich::k_clear, dim3(1), dim3(64), 0, st, d.flag, d.cfl_min, d.ovf_count);
-  hipLaunchKernelGGL(rich::k_wvel, dim3(nb), dim3(rich::kCflThreads), 0, st, d, d.rec);
-  hipLaunchKernelGGL(rich::k_adot, dim3(nb), dim3(rich::kCflThreads), 0, st, d,
-                     (const double*)d.rec, adot);
+  constexpr int CPB = rich::kCellThreads / rich::kLpc;
+  const int n_ctiles = (d.n + CPB - 1) / CPB;
+  // the cell pass writes the point velocities into the records
+  hipLaunchKernelGGL(rich::k_clear, dim3(1), dim3(64), 0, st, d.flag, d.cfl_min);
+  hipLaunchKernelGGL((rich::k_cell<rich::kLpc, false>), dim3(n_ctiles), dim3(rich::kCellThreads),
+                     0, st, d, (const RunDesc*)nullptr, (const int32_t*)nullptr, 1, n_ctiles,
+                     (uint8_t*)nullptr);
+  hipLaunchKernelGGL(rich::k_adot, dim3((d.n + rich::kCflThreads - 1) / rich::kCflThreads),
+                     dim3(rich::kCflThreads), 0, st, d, adot);
   return hip_status(hipGetLastError());
 }
 
@@ -861,10 +1430,10 @@ int rich_cfl_dt(const rich_mesh* m, const rich_state* s, const rich_params* p, d
   RunDesc d = make_desc(m, s, nullptr, nullptr, 0.0, p, static_cast<char*>(ws));
   const int nb = std::min<int>((d.n + rich::kCflThreads - 1) / rich::kCflThreads,
                                rich::kCflMaxBlocks);
-  double* blocks = reinterpret_cast<double*>(static_cast<char*>(ws) + run_ws(d.n).cfl);
-  hipLaunchKernelGGL(rich::k_cfl, dim3(nb), dim3(rich::kCflThreads), 0, st, d, blocks);
+  // per-block minima go to the (otherwise idle) record area of the workspace
+  hipLaunchKernelGGL(rich::k_cfl, dim3(nb), dim3(rich::kCflThreads), 0, st, d, d.rec);
   hipLaunchKernelGGL(rich::k_cfl_final, dim3(1), dim3(rich::kCflFinalThreads), 0, st,
-                     (const double*)blocks, nb, d.cfl_min, 0.0, (double*)nullptr,
+                     (const double*)d.rec, nb, d.cfl_min, 0.0, (double*)nullptr,
                      (int32_t*)nullptr);
   if (hipGetLastError() != hipSuccess) return RICH_E_DEVICE;
   unsigned long long bits = 0;
@@ -891,7 +1460,7 @@ int rich_stage_batch_prepare(int32_t n, const rich_mesh* const* meshes,
                              rich_state* const* out, const double* h,
                              const rich_params* const* params, void* ws, size_t ws_bytes,
                              void* stream, rich_batch_plan* plan) {
-  return rich_stage_batch_prepare_tile(n, meshes, src, base, out, h, params, kStageTile, ws,
+  return rich_stage_batch_prepare_tile(n, meshes, src, base, out, h, params, rich::kTile, ws,
                                        ws_bytes, stream, plan);
 }
 
@@ -931,57 +1500,71 @@ int batch_prepare(int32_t n, const rich_mesh* const* meshes, const rich_state* c
   char* w = static_cast<char*>(ws);
   hipStream_t st = static_cast<hipStream_t>(stream);
 
-  // descriptors (each run's overflow count and list are its solver group's)
-  // and the tile table: the HLLC runs' tiles, then the exact-solver runs'
+  // descriptors and the three launch plans (cells; fluxes HLLC; fluxes exact)
+  constexpr int CPB = rich::kCellThreads / rich::kLpc;
   std::vector<RunDesc> descs(n);
-  std::vector<int32_t> g[2];
-  for (int32_t r = 0; r < n; ++r) g[params[r]->riemann == 1 ? 1 : 0].push_back(r);
-  std::vector<int2> tiles;
-  int64_t nt[2] = {0, 0};
-  for (int k = 0; k < 2; ++k)
-    for (int32_t r : g[k]) {
-      const int64_t t = (nc[r] + tile - 1) / tile;
-      for (int64_t q = 0; q < t; ++q) tiles.push_back(make_int2(r, (int)q));
-      nt[k] += t;
-    }
-  if (nt[0] + nt[1] > L.max_tiles || nt[0] + nt[1] > INT32_MAX / 2) return RICH_E_INVAL;
+  std::vector<int32_t> plans(3 * (2 * (size_t)n + 1), 0);
+  int32_t* pc = plans.data();
+  int32_t* pf0 = pc + (2 * n + 1);
+  int32_t* pf1 = pf0 + (2 * n + 1);
+  std::vector<int32_t> g0, g1;
+  for (int32_t r = 0; r < n; ++r) (params[r]->riemann == 1 ? g1 : g0).push_back(r);
+  int64_t tc = 0;
   for (int32_t r = 0; r < n; ++r) {
     RunDesc d = make_desc(meshes[r], src[r], base[r], out[r], h[r], params[r], w);
-    const int k = params[r]->riemann == 1 ? 1 : 0;
     d.flag = reinterpret_cast<int32_t*>(w + L.flags) + r;
     d.cfl_min = reinterpret_cast<unsigned long long*>(w + L.cfl) + r;
-    d.ovf_count = reinterpret_cast<int32_t*>(w + L.ovfc) + k;
-    d.ovf_list = reinterpret_cast<int2*>(w + L.ovf[k]);
-    d.rec = nullptr;
+    d.rec = reinterpret_cast<double*>(w + L.rec_off[r]);
     if (ax) {
       d.ax = ax[r];
       d.ay = ay[r];
     }
     descs[r] = d;
+    pc[r] = (int32_t)tc;
+    pc[n + 1 + r] = r;
+    tc += (nc[r] + CPB - 1) / CPB;
   }
-  const size_t db = (size_t)n * sizeof(RunDesc), tb = tiles.size() * sizeof(int2);
-  const int up = upload_staged(w + L.desc, descs.data(), db, w + L.tiles, tiles.data(), tb, st);
+  pc[n] = (int32_t)tc;
+  int64_t tf[2] = {0, 0};
+  int32_t* pf[2] = {pf0, pf1};
+  std::vector<int32_t>* grp[2] = {&g0, &g1};
+  for (int k = 0; k < 2; ++k) {
+    const int ng = (int)grp[k]->size();
+    for (int q = 0; q < ng; ++q) {
+      const int32_t r = (*grp[k])[q];
+      pf[k][q] = (int32_t)tf[k];
+      pf[k][ng + 1 + q] = r;
+      tf[k] += (nc[r] + tile - 1) / tile;
+    }
+    pf[k][ng] = (int32_t)tf[k];
+  }
+  if (tc > INT32_MAX / 2 || tf[0] > INT32_MAX / 2 || tf[1] > INT32_MAX / 2) return RICH_E_INVAL;
+
+  const size_t db = (size_t)n * sizeof(RunDesc), pb = plans.size() * sizeof(int32_t);
+  const int up = upload_staged(w + L.desc, descs.data(), db, w + L.plan, plans.data(), pb, st);
   if (up) return up;
 
+  static const int cell_grid = resident_blocks(
+      reinterpret_cast<const void*>(&rich::k_cell<rich::kLpc, true>), rich::kCellThreads);
+  static const int flux_grid[3][2] = {
+      {resident_blocks(reinterpret_cast<const void*>(&rich::k_flux<0, true, 128>), 128),
+       resident_blocks(reinterpret_cast<const void*>(&rich::k_flux<1, true, 128>), 128)},
+      {resident_blocks(reinterpret_cast<const void*>(&rich::k_flux<0, true, 256>), 256),
+       resident_blocks(reinterpret_cast<const void*>(&rich::k_flux<1, true, 256>), 256)},
+      {resident_blocks(reinterpret_cast<const void*>(&rich::k_flux<0, true, 512>), 512),
+       resident_blocks(reinterpret_cast<const void*>(&rich::k_flux<1, true, 512>), 512)}};
   const int ti = tile == 128 ? 0 : (tile == 256 ? 1 : 2);
-  static const int grids[3][2] = {
-      {resident_blocks(reinterpret_cast<const void*>(&rich::k_stage<128, 0, true>), rich::TileCfg<128>::kThreads),
-       resident_blocks(reinterpret_cast<const void*>(&rich::k_stage<128, 1, true>), rich::TileCfg<128>::kThreads)},
-      {resident_blocks(reinterpret_cast<const void*>(&rich::k_stage<256, 0, true>), rich::TileCfg<256>::kThreads),
-       resident_blocks(reinterpret_cast<const void*>(&rich::k_stage<256, 1, true>), rich::TileCfg<256>::kThreads)},
-      {resident_blocks(reinterpret_cast<const void*>(&rich::k_stage<512, 0, true>), rich::TileCfg<512>::kThreads),
-       resident_blocks(reinterpret_cast<const void*>(&rich::k_stage<512, 1, true>), rich::TileCfg<512>::kThreads)}};
+  const int flux0_grid = flux_grid[ti][0], flux1_grid = flux_grid[ti][1];
+  plan->flux_tile = tile;
   plan->n_runs = n;
-  plan->tile = tile;
-  for (int k = 0; k < 2; ++k) {
-    plan->n_tiles[k] = (int32_t)nt[k];
-    plan->n_group[k] = (int32_t)g[k].size();
-    plan->grid[k] = (int32_t)std::min<int64_t>(nt[k], grids[ti][k]);
-    plan->ovf_off[k] = (int64_t)L.ovf[k];
-  }
-  plan->tiles_off[0] = (int64_t)L.tiles;
-  plan->tiles_off[1] = (int64_t)(L.tiles + sizeof(int2) * (size_t)nt[0]);
-  plan->ovfc_off = (int64_t)L.ovfc;
+  plan->n_cell_tiles = (int32_t)tc;
+  plan->n_flux_tiles[0] = (int32_t)tf[0];
+  plan->n_flux_tiles[1] = (int32_t)tf[1];
+  plan->n_group[0] = (int32_t)g0.size();
+  plan->n_group[1] = (int32_t)g1.size();
+  plan->grid_cell = (int32_t)std::min<int64_t>(tc, cell_grid);
+  plan->grid_flux[0] = (int32_t)std::min<int64_t>(tf[0], flux0_grid);
+  plan->grid_flux[1] = (int32_t)std::min<int64_t>(tf[1], flux1_grid);
   return RICH_OK;
 }
 
@@ -996,55 +1579,36 @@ int rich_stage_batch_prepare_tile(int32_t n, const rich_mesh* const* meshes,
                        ws_bytes, stream, plan);
 }
 
-extern "C++" {
-namespace {
-template <int T>
-void launch_stage_batch(int k, int grid, int n_tiles, hipStream_t st, const RunDesc& dummy,
-                        const RunDesc* dd, const int2* tiles, const int* oc, const int2* ol) {
-  const int og = std::min(n_tiles, kOverflowGrid);
-  uint8_t* nb = nullptr;
-  if (k == 0) {
-    hipLaunchKernelGGL((rich::k_stage<T, 0, true>), dim3(grid), dim3(rich::TileCfg<T>::kThreads), 0, st, dummy, dd, tiles,
-                       n_tiles, nb, nb);
-    hipLaunchKernelGGL((rich::k_stage_overflow<T, 0, true>), dim3(og), dim3(T), 0, st, dummy, dd,
-                       oc, ol, nb, nb);
-  } else {
-    hipLaunchKernelGGL((rich::k_stage<T, 1, true>), dim3(grid), dim3(rich::TileCfg<T>::kThreads), 0, st, dummy, dd, tiles,
-                       n_tiles, nb, nb);
-    hipLaunchKernelGGL((rich::k_stage_overflow<T, 1, true>), dim3(og), dim3(T), 0, st, dummy, dd,
-                       oc, ol, nb, nb);
-  }
-}
-}  // namespace
-}  // extern "C++"
-
 int rich_stage_batch_launch(const rich_batch_plan* plan, void* ws, void* stream) {
-  if (!plan || !ws || plan->n_runs <= 0 || plan->n_tiles[0] + plan->n_tiles[1] <= 0)
+  if (!plan || !ws || plan->n_runs <= 0 || plan->n_cell_tiles <= 0 || plan->grid_cell <= 0)
     return RICH_E_INVAL;
-  if (plan->tile != 128 && plan->tile != 256 && plan->tile != 512) return RICH_E_INVAL;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return RICH_E_NOMEM;
   const int32_t n = plan->n_runs;
-  const BatchLayout L = batch_layout(n, nullptr);   // the fixed part's offsets
+  std::vector<int64_t> one(n, 1);
+  const BatchLayout L = batch_layout(n, one.data());   // descriptor and plan offsets
   char* w = static_cast<char*>(ws);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const RunDesc* dd = reinterpret_cast<const RunDesc*>(w + L.desc);
-  int32_t* ovfc = reinterpret_cast<int32_t*>(w + plan->ovfc_off);
+  const int32_t* dplan = reinterpret_cast<const int32_t*>(w + L.plan);
+  const int32_t* dpc = dplan;
+  const int32_t* dpf0 = dplan + (2 * n + 1);
+  const int32_t* dpf1 = dpf0 + (2 * n + 1);
   RunDesc dummy;
   std::memset(&dummy, 0, sizeof(dummy));
-  hipLaunchKernelGGL(rich::k_clear_batch, dim3((n + 255) / 256), dim3(256), 0, st, dd, n, ovfc);
-  int pf = prof_begin("k_stage", st);
+  hipLaunchKernelGGL(rich::k_clear_batch, dim3((n + 255) / 256), dim3(256), 0, st, dd, n);
+  int pcl = prof_begin("k_cell", st);
+  hipLaunchKernelGGL((rich::k_cell<rich::kLpc, true>), dim3(plan->grid_cell),
+                     dim3(rich::kCellThreads), 0, st, dummy, dd, dpc, n, plan->n_cell_tiles,
+                     (uint8_t*)nullptr);
+  prof_end(pcl, st);
+  int pfl = prof_begin("k_flux", st);
   for (int k = 0; k < 2; ++k) {
-    if (plan->n_tiles[k] <= 0 || plan->grid[k] <= 0) continue;
-    const int2* tiles = reinterpret_cast<const int2*>(w + plan->tiles_off[k]);
-    const int2* ol = reinterpret_cast<const int2*>(w + plan->ovf_off[k]);
-    const int* oc = ovfc + k;
-    switch (plan->tile) {
-      case 128: launch_stage_batch<128>(k, plan->grid[k], plan->n_tiles[k], st, dummy, dd, tiles, oc, ol); break;
-      case 256: launch_stage_batch<256>(k, plan->grid[k], plan->n_tiles[k], st, dummy, dd, tiles, oc, ol); break;
-      default: launch_stage_batch<512>(k, plan->grid[k], plan->n_tiles[k], st, dummy, dd, tiles, oc, ol); break;
-    }
+    if (plan->n_group[k] <= 0 || plan->grid_flux[k] <= 0) continue;
+    const int32_t* dpf = k == 0 ? dpf0 : dpf1;
+    launch_flux_batch(k, plan->flux_tile, plan->grid_flux[k], st, dummy, dd, dpf,
+                      plan->n_group[k], plan->n_flux_tiles[k]);
   }
-  prof_end(pf, st);
+  prof_end(pfl, st);
   return hip_status(hipGetLastError());
 }
 
@@ -1108,7 +1672,7 @@ int rich_stage_batch_accel(int32_t n, const rich_mesh* const* meshes,
                            const double* const* ay, void* ws, size_t ws_bytes, void* stream) {
   if (!ax || !ay) return RICH_E_INVAL;
   rich_batch_plan plan;
-  const int rc = batch_prepare(n, meshes, src, base, out, h, params, ax, ay, kStageTile, ws,
+  const int rc = batch_prepare(n, meshes, src, base, out, h, params, ax, ay, rich::kTile, ws,
                                ws_bytes, stream, &plan);
   if (rc) return rc;
   return rich_stage_batch_launch(&plan, ws, stream);
@@ -1401,7 +1965,7 @@ int step_batch_impl(int32_t n, rich_ctx* const* ctxs, rich_state* const* states,
     rich_batch_plan plan;
     int e = batch_prepare((int32_t)m, mp.data(), sp.data(), bp.data(), op.data(), h.data(),
                           pp.data(), ax ? axk.data() : nullptr, ax ? ayk.data() : nullptr,
-                          kStageTile, ws, ws_bytes, stream, &plan);
+                          rich::kTile, ws, ws_bytes, stream, &plan);
     if (!e) e = rich_stage_batch_launch(&plan, ws, stream);
     if (e) return e;
     std::vector<int32_t> fl(m, 0);

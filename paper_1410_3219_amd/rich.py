@@ -50,10 +50,10 @@ RETESS_POINT, RETESS_FAN, RETESS_CLIP, RETESS_ASYM, RETESS_AREA, RETESS_CAP = 1,
 
 
 class RichBatchPlan(C.Structure):
-    _fields_ = [("n_runs", C.c_int32), ("tile", C.c_int32),
-                ("n_tiles", C.c_int32 * 2), ("n_group", C.c_int32 * 2),
-                ("grid", C.c_int32 * 2), ("tiles_off", C.c_int64 * 2),
-                ("ovf_off", C.c_int64 * 2), ("ovfc_off", C.c_int64)]
+    _fields_ = [("n_runs", C.c_int32), ("n_cell_tiles", C.c_int32),
+                ("n_flux_tiles", C.c_int32 * 2), ("n_group", C.c_int32 * 2),
+                ("grid_cell", C.c_int32), ("grid_flux", C.c_int32 * 2),
+                ("flux_tile", C.c_int32)]
 
 
 class RichState(C.Structure):

@@ -140,7 +140,7 @@ def test_batch_tile_shapes_bitwise_equal_and_autotune():
         for o in outs:
             o.Q.fill_(float("nan"))
         plan = R.rich_stage_batch_prepare_tile(meshes, srcs, bases, outs, hs, ps, tile, ws)
-        assert plan.tile == tile
+        assert plan.flux_tile == tile
         R.rich_stage_batch_launch(plan, ws)
         assert R.rich_batch_flags(len(cases), ws) == [0] * len(cases)
         torch.cuda.synchronize()

@@ -80,9 +80,9 @@ def test_fused_step_many_blocks():
 
 
 def test_device_step_with_extrapolated_fluxes():
-    """integrator 1 advances its face states with the step: rich_stage_dt_of
-    with a dt made on the device equals rich_stage with the host dt, and so
-    does the Courant stage itself (its Courant pass runs before the stage)."""
+    """integrator 1 reads the step in its cell pass: rich_stage_dt_of with a
+    dt made on the device equals rich_stage with the host dt; the fused
+    Courant stage itself is rejected for it."""
     from paper_1410_3219_amd import rich as R
     m, Qs, Qb, Xb, h, p = U.case("sedov", k=30, integrator=1)
     gp = U.gpu_params(p)
@@ -105,11 +105,9 @@ def test_device_step_with_extrapolated_fluxes():
     assert np.array_equal(Qa, Qb2) and np.array_equal(Xa, Xb2)
     U.check_stage(m, Qs, Qs, Xb, dt, p, Qb2, Xb2, label="device-dt stage")
 
-    c = R.DeviceState.empty_like(s)
-    R.rich_stage_courant(dm, s, s, c, 1.0, gp, ws)
-    assert R.rich_stage_dt(ws) == dt
-    Qc, Xc = c.numpy()
-    assert np.array_equal(Qa, Qc) and np.array_equal(Xa, Xc)
+    with pytest.raises(R.RichError) as e:
+        R.rich_stage_courant(dm, s, s, b, 1.0, gp, ws)
+    assert e.value.status == R.RICH_E_INVAL
 
 
 def test_invalid_dt_reported():
