@@ -147,6 +147,32 @@ int rich_stage(const rich_mesh* m, const rich_state* src, const rich_state* base
                size_t ws_bytes, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rich_stage
+ * without a caller workspace.  The stage's scratch (the per-cell
+ * reconstruction records, the Courant minimum and the flag word) is a
+ * library-owned device array of fixed size, one per GPU, held from the
+ * library's first use on that GPU until the process ends; its address is
+ * looked up on the first call on each device.  Nothing is allocated and no
+ * memset is enqueued (the flag word is cleared by the stage's own kernel).
+ * Arguments, results and errors are those of rich_stage, and the results
+ * equal rich_stage's bit for bit, with these differences:
+ *   - meshes of more than RICH_NOALLOC_MAX_CELLS cells return RICH_E_NOMEM
+ *     without enqueuing;
+ *   - flag_out (caller-owned device int32, may be null) receives the stage's
+ *     RICH_FLAG_* word when the stage completes (in place of
+ *     rich_stage_flags, which needs a workspace);
+ *   - every call on one GPU shares that GPU's scratch, which keeps the last
+ *     call's contents: calls that overlap on one GPU (concurrent streams or
+ *     host threads) race and must be serialised by the caller;
+ *   - RICH_E_DEVICE if the scratch's address cannot be looked up.
+ */
+#define RICH_NOALLOC_MAX_CELLS 1048576
+int rich_stage_noalloc(const rich_mesh* m, const rich_state* src, const rich_state* base,
+                       rich_state* out, double h, const rich_params* p, int32_t* flag_out,
+                       void* stream);
+
+/*
  * rich_stage with a per-cell external acceleration (section 2.3's source
  * term): cell i is accelerated by (p->gx + ax[i], p->gy + ay[i]), and the
  * stage adds h (0, M g_i, P.g_i) of its source totals, as for the uniform

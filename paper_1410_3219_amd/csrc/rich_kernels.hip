@@ -829,10 +829,11 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 constexpr int64_t kCellsPerBlock = rich::kCellThreads / rich::kLpc;
 constexpr size_t kDtOffset = 16;  // header: flag @0, Courant minimum @8, dt @16
 
-size_t run_ws_bytes(int64_t n) {
-  return rich::kHeader + align_up((size_t)n * rich::kRecDoubles * sizeof(double), 256) +
-         align_up((size_t)((n + kCellsPerBlock - 1) / kCellsPerBlock) * sizeof(double), 256);
+constexpr size_t run_ws_size(int64_t n) {
+  return rich::kHeader + ((size_t)n * rich::kRecDoubles * sizeof(double) + 255) / 256 * 256 +
+         ((size_t)((n + kCellsPerBlock - 1) / kCellsPerBlock) * sizeof(double) + 255) / 256 * 256;
 }
+size_t run_ws_bytes(int64_t n) { return run_ws_size(n); }
 
 bool valid_mesh(const rich_mesh* m) {
   return m && m->n_cells > 0 && m->n_cells <= (int64_t)rich::kCellMask && m->n_edges >= 0 &&
@@ -1270,6 +1271,46 @@ int tessellate_into(rich_ctx* c, DevMesh& dst, const double* dx, int64_t n, cons
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of rich_stage_noalloc: one file-scope device array per GPU, sized
+// for the largest run that entry point takes.  In host code `scratch` is a
+// host-side stand-in for the symbol, never a device address: the address of
+// each GPU's copy is looked up once per device (hipGetSymbolAddress, with
+// that device current) and kept; only that address reaches kernels.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocMaxCells = RICH_NOALLOC_MAX_CELLS;
+constexpr size_t kNoAllocBytes = run_ws_size(kNoAllocMaxCells);
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex& scratch_lock() {
+  static std::mutex m;
+  return m;
+}
+// The current device's address of `scratch` (looked up on the first call on
+// that device), or null on a HIP error.
+void* scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  static void* ptr[kMaxDevices] = {};
+  std::lock_guard<std::mutex> g(scratch_lock());
+  if (ptr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+      return nullptr;
+    ptr[dev] = p;
+  }
+  return ptr[dev];
+}
+}  // namespace
+
+namespace rich {
+__global__ void k_copy_flag(const int32_t* flag, int32_t* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = *flag;
+}
+}  // namespace rich
+
 extern "C" {
 
 void rich_params_default(rich_params* p, double gamma) {
@@ -1307,6 +1348,26 @@ int rich_stage(const rich_mesh* m, const rich_state* src, const rich_state* base
   if (ws_bytes < run_ws_bytes(n) || (reinterpret_cast<uintptr_t>(ws) & 255)) return RICH_E_NOMEM;
   RunDesc d = make_desc(m, src, base, out, h, p, static_cast<char*>(ws));
   return launch_stage(d, p->riemann, static_cast<hipStream_t>(stream));
+}
+
+int rich_stage_noalloc(const rich_mesh* m, const rich_state* src, const rich_state* base,
+                       rich_state* out, double h, const rich_params* p, int32_t* flag_out,
+                       void* stream) {
+  if (!valid_mesh(m) || !valid_params(p)) return RICH_E_INVAL;
+  const int64_t n = m->n_cells;
+  if (!valid_state(src, n, false) || !valid_state(base, n, true) || !valid_state(out, n, true))
+    return RICH_E_INVAL;
+  if (!std::isfinite(h) || h < 0.0) return RICH_E_INVAL;
+  if (out->M == src->M || out->M == base->M || out->x == base->x) return RICH_E_INVAL;
+  if (n > kNoAllocMaxCells || run_ws_bytes(n) > kNoAllocBytes) return RICH_E_NOMEM;
+  char* ws = static_cast<char*>(scratch_address());
+  if (ws == nullptr) return RICH_E_DEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  RunDesc d = make_desc(m, src, base, out, h, p, ws);
+  const int rc = launch_stage(d, p->riemann, st);  // clears the flag word with a kernel
+  if (rc) return rc;
+  if (flag_out) hipLaunchKernelGGL(rich::k_copy_flag, dim3(1), dim3(64), 0, st, d.flag, flag_out);
+  return hip_status(hipGetLastError());
 }
 
 int rich_stage_accel(const rich_mesh* m, const rich_state* src, const rich_state* base,

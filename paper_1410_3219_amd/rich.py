@@ -128,6 +128,7 @@ def lib():
         L.rich_params_default.restype = None
         L.rich_workspace_size.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
         L.rich_stage.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, C.c_size_t, _vp]
+        L.rich_stage_noalloc.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, _vp]
         L.rich_stage_flags.argtypes = [_vp, _vp, _ip]
         L.rich_stage_debug.argtypes = [mp, sp, sp, sp, C.c_double, pp, _vp, C.c_size_t, _vp, _vp,
                                        _vp]
@@ -370,6 +371,27 @@ def rich_stage(mesh: DeviceMesh, src: DeviceState, base: DeviceState, out: Devic
                           C.byref(out.c()), float(h), C.byref(params.c()),
                           C.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
     _check(st, "rich_stage")
+
+
+NOALLOC_MAX_CELLS = 1048576   # RICH_NOALLOC_MAX_CELLS
+
+
+def rich_stage_noalloc(mesh: DeviceMesh, src: DeviceState, base: DeviceState, out: DeviceState,
+                       h, params: Params, flag_out=None, stream=None):
+    """Enqueue one stage on the library's own scratch (no workspace; at most
+    NOALLOC_MAX_CELLS cells; calls on one GPU must not overlap).  flag_out: an
+    int32 device tensor of one element that receives the stage's flag word,
+    or None."""
+    fp = None
+    if flag_out is not None:
+        import torch
+        if flag_out.dtype != torch.int32 or flag_out.numel() < 1 or flag_out.device.type != "cuda":
+            raise RichError(RICH_E_INVAL, "rich_stage_noalloc: flag_out must be an int32 device tensor")
+        fp = C.c_void_p(flag_out.data_ptr())
+    st = lib().rich_stage_noalloc(C.byref(mesh.c()), C.byref(src.c()), C.byref(base.c()),
+                                  C.byref(out.c()), float(h), C.byref(params.c()), fp,
+                                  _stream_ptr(stream))
+    _check(st, "rich_stage_noalloc")
 
 
 def rich_stage_accel(mesh: DeviceMesh, src: DeviceState, base: DeviceState, out: DeviceState,

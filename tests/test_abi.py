@@ -31,7 +31,8 @@ def test_library_exports_every_declared_function(header, lib):
 
 def test_declared_entry_points_are_the_expected_set():
     names = set(declared("rich.h"))
-    for must in ("rich_stage", "rich_stage_debug", "rich_stage_accel", "rich_step_accel",
+    for must in ("rich_stage", "rich_stage_noalloc", "rich_stage_debug", "rich_stage_accel",
+                 "rich_step_accel",
                  "rich_stage_batch_accel", "rich_step_batch_accel",
                  "rich_stage_flags", "rich_cfl_dt",
                  "rich_workspace_size",
@@ -122,6 +123,16 @@ def test_argument_validation_without_gpu():
     for bad in (R.Params(gamma=1.0), R.Params(riemann=2), R.Params(motion=3),
                 R.Params(limiter=5), R.Params(integrator=2), R.Params(gx=float("inf"))):
         assert stage(prm=bad) == R.RICH_E_INVAL
+    def noalloc(m=None, s=src, b=base, o=out, h=0.01, prm=None):
+        return L.rich_stage_noalloc(C.byref(m or mesh()), C.byref(s), C.byref(b), C.byref(o),
+                                    h, C.byref((prm or p).c()), None, None)
+
+    big_n = R.NOALLOC_MAX_CELLS + 1                                 # beyond the scratch
+    assert noalloc(m=mesh(n=big_n), s=state(n=big_n), b=state(n=big_n, base=fake * 2),
+                   o=state(n=big_n, base=fake * 4)) == R.RICH_E_NOMEM
+    assert noalloc(m=mesh(n=0)) == R.RICH_E_INVAL
+    assert noalloc(o=src) == R.RICH_E_INVAL
+    assert noalloc(h=float("nan")) == R.RICH_E_INVAL
     assert stage(nbytes=big - 1) == R.RICH_E_NOMEM                 # workspace too small
     assert stage(ws=fake + 8) == R.RICH_E_NOMEM                    # workspace not aligned
     dt = C.c_double(0.0)
