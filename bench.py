@@ -311,9 +311,10 @@ def bench_serve(args, R, log):
     # runs saturated, so its throughput is the most the served path delivers
     sat, _ = S.run(tpl, rate=10 * args.serve_rate, duration=0.25 * args.serve_seconds,
                    seed=10, log=log)
-    res["saturated"] = {k: sat[k] for k in ("requests", "launches", "mean_batch", "p50_ms",
-                                            "p99_ms", "cell_updates_per_s", "wall_s",
-                                            "offered_rate", "offered_cell_updates_per_s")}
+    res["saturated"] = {k: sat[k] for k in ("requests", "launches", "mean_batch", "max_batch",
+                                            "mixed_launches", "p50_ms", "p99_ms",
+                                            "cell_updates_per_s", "wall_s", "offered_rate",
+                                            "offered_cell_updates_per_s")}
     return res
 
 
@@ -454,6 +455,73 @@ def bench_device_chain(args, R, P, make_state, hm0, dm0, live_final, n_steps, lo
     return out
 
 
+SOD_CHAINS = {}
+
+
+def per_quantity_scale(Q, area, gamma):
+    """Scale of each conserved quantity for the parity metric: max|M|,
+    max M (c + |v|) for both momenta, max|E|."""
+    import numpy as np
+    M = Q[0]
+    v2 = (Q[1] ** 2 + Q[2] ** 2) / (M * M)
+    p = (gamma - 1.0) * (Q[3] / area - 0.5 * (M / area) * v2)
+    mom = np.max(M * (np.sqrt(gamma * p / (M / area)) + np.sqrt(v2)))
+    return np.array([np.abs(M).max(), mom, mom, np.abs(Q[3]).max()])
+
+
+def l_shock(O, P, mesh, Q, t):
+    """eq. (Lshock): sum |phi - phi_exact|^(1/4) / (|phi_exact|^(1/4) N) for
+    density and pressure, the velocity difference normalised by the exact
+    sound speed; the exact solution is the 1D Riemann problem of the tube
+    sampled at (x - 1/2) / t."""
+    import numpy as np
+    g = P.gamma
+    rho = Q[0] / mesh.area
+    vx = Q[1] / Q[0]
+    pr = (g - 1.0) * (Q[3] / mesh.area - 0.5 * rho * (vx * vx + (Q[2] / Q[0]) ** 2))
+    WL, WR = np.array([1.0, 0.0, 0.0, 1.0]), np.array([0.125, 0.0, 0.0, 0.1])
+    ex = np.array([O.exact_sample(g, WL, WR, (x - 0.5) / t)[0] for x in mesh.px])
+    Lr = float(np.mean(np.abs(rho - ex[:, 0]) ** 0.25 / np.abs(ex[:, 0]) ** 0.25))
+    Lp = float(np.mean(np.abs(pr - ex[:, 3]) ** 0.25 / np.abs(ex[:, 3]) ** 0.25))
+    cs = np.sqrt(g * ex[:, 3] / ex[:, 0])
+    Lv = float(np.mean(np.abs(vx - ex[:, 1]) ** 0.25 / cs ** 0.25))
+    return {"density": Lr, "pressure": Lp, "velocity": Lv}
+
+
+def sod_oracle_checks(O, T, log):
+    """For each 100-step shock-tube chain the GPU ran: the oracle's own chain
+    from the same initial state with the same time steps (its meshes built
+    from its own points), the drift between the two end states per conserved
+    quantity (largest difference over that quantity's scale, the parity
+    metric), and both chains' error against the exact solution by eq.
+    (Lshock)."""
+    import numpy as np
+    res = {}
+    for key, c in SOD_CHAINS.items():
+        P = c["P"]
+        op = O.Params(gamma=P.gamma, riemann=c["riemann"])
+        m = T.rich_tess_build(P.px, P.py, P.box, P.bc)
+        Q = P.state(m.area)
+        X = np.stack([m.px, m.py])
+        t0 = time.perf_counter()
+        for dt in c["dts"]:
+            Q, X, m, _, st = O.step(m, Q, X, dt, op,
+                                    lambda x, y, b, bc: T.rich_tess_build(x, y, b, bc))
+            if st:
+                raise SystemExit(f"{key}: oracle chain status {st}")
+        sc = per_quantity_scale(Q, m.area, P.gamma)
+        drift = (np.max(np.abs(c["Q"] - Q), axis=1) / sc).tolist()
+        t = float(sum(c["dts"]))
+        res[key] = {"steps": len(c["dts"]), "t_end": t,
+                    "drift_vs_oracle_per_quantity": dict(zip(["M", "Px", "Py", "E"], drift)),
+                    "points_drift": float(np.max(np.abs(c["X"] - X))),
+                    "L_shock_gpu": l_shock(O, P, c["mesh"], c["Q"], t),
+                    "L_shock_oracle": l_shock(O, P, m, Q, t),
+                    "oracle_chain_s": time.perf_counter() - t0}
+        log(f"[bench] {key} vs oracle: {res[key]}")
+    return res
+
+
 def bench_config(args, R, T, name, riemann, steps, log):
     """Another configuration of the same path (time-centred steps): a live
     chain builds the meshes, then the steps are replayed with all inputs in
@@ -510,6 +578,12 @@ def bench_config(args, R, T, name, riemann, steps, log):
     ms = e0.elapsed_time(e1) / steps
     kern_ms = (kc[0] + kf[0]) / steps
     ok = ok and bool(torch.equal(cur.Q, live[0]) and torch.equal(cur.X, live[1]))
+    if name == "sod":
+        # the GPU chain's end state, for the oracle comparison of the CPU
+        # baseline leg (the only leg that runs the oracle)
+        SOD_CHAINS["sod_64sq_exact_100_steps" if riemann else "sod_64sq_hllc_100_steps"] = {
+            "P": P, "riemann": riemann, "dts": list(dts), "mesh": hm,
+            "Q": live[0].cpu().numpy(), "X": live[1].cpu().numpy()}
     out = {"workload": desc, "riemann": "exact" if riemann else "hllc", "n_cells": n,
            "steps": steps, "ms_per_step": ms, "cell_updates_per_s": n / (ms / 1e3),
            "kernel_ms_per_step": kern_ms,
@@ -839,20 +913,38 @@ def main():
                       eta=params.eta, riemann=params.riemann, motion=params.motion,
                       limiter=params.limiter)
         hmh, Qh_gpu = host_half0
-        t = time.perf_counter()
-        r1 = O.stage(hm0, Q0, Q0, X0, 0.5 * dts[0], op)
-        r2 = O.stage(hmh, Qh_gpu, Q0, X0, dts[0], op)
-        t_cpu = time.perf_counter() - t
+        O.build()
+
+        def oracle_step():
+            t = time.perf_counter()
+            r1 = O.stage(hm0, Q0, Q0, X0, 0.5 * dts[0], op)
+            O.stage(hmh, Qh_gpu, Q0, X0, dts[0], op)
+            return time.perf_counter() - t, r1
+
+        # the reference (serial) build, then the same source with its
+        # per-cell and per-edge loops on all host cores (OpenMP)
+        t_cpu, r1 = oracle_step()
+        with O.use_library(O.OMP_LIB_PATH):
+            n_threads = O.threads()
+            t_all, r1_all = oracle_step()
+        same = bool(np.array_equal(r1.Q, r1_all.Q))
         err = float(np.max(np.abs(r1.Q - Qh_gpu), axis=1).max() / np.abs(Q0).max())
-        log(f"[bench] oracle step {t_cpu:.1f}s (stage-1 max |diff| / max|Q| = {err:.2e})")
+        log(f"[bench] oracle step {t_cpu:.1f}s on 1 core, {t_all:.2f}s on {n_threads} threads "
+            f"(same bits: {same}; stage-1 max |diff| / max|Q| = {err:.2e})")
         out["cpu_baseline"] = {
-            "value": n / t_cpu,
+            "value": n / t_all,
             "unit": "cell-updates/s",
-            "cores": 1,
+            "cores": n_threads,
             "kind": "oracle",
-            "sample": f"one full time-centred step (both stages) of the same {n}-cell workload, serial C oracle, step 0 meshes",
+            "sample": f"one full time-centred step (both stages) of the same {n}-cell workload, C oracle with its per-cell and per-edge loops on {n_threads} OpenMP threads, step 0 meshes",
+            "single_core": {"value": n / t_cpu, "cores": 1,
+                            "sample": "the same step, serial reference build"},
+            "parallel_build_bitwise_equal": same,
+            "host_cpus": os.cpu_count(),
         }
         out["full_size_stage1_max_rel_diff_vs_oracle"] = err
+        if SOD_CHAINS:
+            out["cpu_baseline"]["sod_64sq_oracle_checks"] = sod_oracle_checks(O, T, log)
     print(json.dumps(out), flush=True)
 
 

@@ -24,6 +24,9 @@
  * Readings of points the paper leaves open are listed where they are used.
  * Build: gcc -O2 -std=c99 -ffp-contract=off (no fast-math).
  */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include "oracle.h"
 
 #include <math.h>
@@ -142,8 +145,21 @@ static void nb_prim(const or_mesh* m, const double* prim, int64_t i,
 /* energy); the primitives are those totals divided by the cell area.      */
 /* Ideal gas: p = (gamma-1) * internal energy density, c = sqrt(gamma p/rho) */
 /* ---------------------------------------------------------------------- */
+/* Threads the per-cell and per-edge loops run on: 1 in the serial build
+ * (the reference), the OpenMP team size in the parallel build of the same
+ * source (used only to time the oracle on all host cores; each iteration
+ * writes only its own cell or edge, so both builds give the same bits). */
+int or_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 int or_primitives(const or_mesh* m, const double* Q, const or_params* p, double* prim) {
   int64_t n = m->n_cells;
+  #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     double A = m->area[i];
     double M = Q[i], Px = Q[n + i], Py = Q[2 * n + i], E = Q[3 * n + i];
@@ -167,6 +183,7 @@ int or_primitives(const or_mesh* m, const double* Q, const or_params* p, double*
 int or_point_velocity(const or_mesh* m, const double* prim, const or_params* p,
                       double* w) {
   int64_t n = m->n_cells;
+  #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     if (p->motion == 0) {
       w[i] = 0.0;
@@ -198,6 +215,7 @@ int or_point_velocity(const or_mesh* m, const double* prim, const or_params* p,
 /* ---------------------------------------------------------------------- */
 int or_gradients(const or_mesh* m, const double* prim, double* grad) {
   int64_t n = m->n_cells;
+  #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     double phi_i[4] = {prim[i], prim[n + i], prim[2 * n + i], prim[3 * n + i]};
     double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -240,6 +258,7 @@ int or_gradients(const or_mesh* m, const double* prim, double* grad) {
 int or_limiter(const or_mesh* m, const double* prim, const double* grad,
                const or_params* p, double* alpha, int32_t* flag) {
   int64_t n = m->n_cells;
+  #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     double phi_i[4] = {prim[i], prim[n + i], prim[2 * n + i], prim[3 * n + i]};
     double G[8];
@@ -586,6 +605,7 @@ int or_edge_fluxes(const or_mesh* m, const double* prim, const double* lgrad,
                    const double* w, const or_params* p, double* flux) {
   int64_t ne = m->n_edges;
   int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
   for (int64_t e = 0; e < ne; ++e) {
     double WL[4], WR[4], nx, ny, wex, wey;
     edge_frame(m, prim, lgrad, w, e, WL, WR, &nx, &ny, &wex, &wey);
@@ -696,6 +716,7 @@ static void half_step_primitives(const or_mesh* m, const double* prim, const dou
                                  double* out) {
   int64_t n = m->n_cells;
   memcpy(out, prim, sizeof(double) * 5 * (size_t)n);
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     double rho = prim[i], vx = prim[n + i], vy = prim[2 * n + i], pr = prim[3 * n + i];
     double ux = vx - w[i], uy = vy - w[n + i];
@@ -736,8 +757,9 @@ static int stage(const or_mesh* m, const double* Qsrc, const double* Qbase,
   or_point_velocity(m, prim, p, w);
   or_gradients(m, prim, grad);
   or_limiter(m, prim, grad, p, alpha, flag);
-  for (int q = 0; q < 8; ++q)
-    for (int64_t i = 0; i < n; ++i) grad[(int64_t)q * n + i] *= alpha[(int64_t)(q / 2) * n + i];
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    for (int q = 0; q < 8; ++q) grad[(int64_t)q * n + i] *= alpha[(int64_t)(q / 2) * n + i];
   const double* fprim = prim;
   double* prim_h = NULL;
   if (p->integrator == 1) {
@@ -752,6 +774,8 @@ static int stage(const or_mesh* m, const double* Qsrc, const double* Qbase,
   int st = or_edge_fluxes(m, fprim, grad, w, p, flux);
   free(prim_h);
 
+  int dom = 0;
+#pragma omp parallel for schedule(static) reduction(| : dom)
   for (int64_t i = 0; i < n; ++i) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int32_t k = m->off[i]; k < m->off[i + 1]; ++k) {
@@ -787,8 +811,9 @@ static int stage(const or_mesh* m, const double* Qsrc, const double* Qbase,
     double eint = E - 0.5 * (Px * Px + Py * Py) / M;
     if (!(M > 0.0) || !(eint > 0.0) || !isfinite(E) || !isfinite(Px) ||
         !isfinite(Py) || !isfinite(x) || !isfinite(y))
-      st = OR_E_DOMAIN;
+      dom = 1;
   }
+  if (dom) st = OR_E_DOMAIN;
   if (d_prim) memcpy(d_prim, prim, sizeof(double) * 5 * (size_t)n);
   if (d_w) memcpy(d_w, w, sizeof(double) * 2 * (size_t)n);
   if (d_alpha) memcpy(d_alpha, alpha, sizeof(double) * 4 * (size_t)n);

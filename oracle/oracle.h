@@ -108,6 +108,11 @@ int or_edge_waves(const or_mesh* m, const double* prim, const double* lgrad,
 /* Area change rate of every cell implied by the edge velocities (eq. areachange) */
 int or_area_rate(const or_mesh* m, const double* w, double* adot);
 
+/* Threads the per-cell and per-edge loops run on (1 in the serial build;
+ * the OpenMP team size in the parallel build used to time the oracle on all
+ * host cores; both builds give the same bits). */
+int or_threads(void);
+
 /* One stage: Qout = Qbase - h * sum_edges(L F), Xout = Xbase + h w.
  * Optional diagnostics (may be NULL): prim[5n], w[2n], alpha[4n], flag[n],
  * flux[4E]. Returns OR_E_DOMAIN if a produced cell has M<=0, internal energy

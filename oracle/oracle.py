@@ -29,15 +29,27 @@ _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
 
 
+OMP_LIB_PATH = os.path.join(_HERE, "liboracle_omp.so")
+
+
 def build(force=False):
-    """Compile liboracle.so with gcc (plain C99, -O2, no FMA contraction)."""
-    if force or not os.path.exists(LIB_PATH) or \
-            os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
-        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
-               SRC_PATH, "-o", LIB_PATH + ".tmp", "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    """Compile liboracle.so with gcc (plain C99, -O2, no FMA contraction),
+    the reference build, and liboracle_omp.so, the same source with its
+    per-cell and per-edge loops spread over OpenMP threads (only for timing
+    the oracle on all host cores)."""
+    for path, extra in ((LIB_PATH, []), (OMP_LIB_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path) or \
+                os.path.getmtime(path) < os.path.getmtime(SRC_PATH):
+            cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", *extra, "-fPIC", "-shared",
+                   SRC_PATH, "-o", path + ".tmp", "-lm"]
+            subprocess.check_call(cmd)
+            os.replace(path + ".tmp", path)
     return LIB_PATH
+
+
+def threads():
+    """Threads the loaded build runs its loops on (1 for the reference)."""
+    return int(lib().or_threads())
 
 
 class OrMesh(C.Structure):

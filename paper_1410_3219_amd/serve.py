@@ -156,6 +156,8 @@ class Server:
         self.fallbacks = 0         # moving: steps redone with host-built meshes
         self.launches = 0
         self.batch_sizes = []
+        self.launch_templates = []   # per launch: the sorted template indices it carried
+        self._tpl_index = {id(t): k for k, t in enumerate(templates)}
         self.cells_done = 0
         self.stream = torch.cuda.current_stream()
 
@@ -288,6 +290,7 @@ class Server:
         self.inflight.append((ev, items, ws1, ws2, flags, rt))
         self.launches += 1
         self.batch_sizes.append(len(items))
+        self.launch_templates.append(tuple(sorted({self._tpl_index[id(s.tpl)] for s in ss})))
         return True
 
     def _complete(self, now_fn):
@@ -408,6 +411,8 @@ def run(templates, rate=2000.0, duration=2.0, steps_per_session=8, seed=9,
                evicted_sessions=sum(1 for x in srv.sessions.values() if x.error),
                sessions=n_sess, launches=srv.launches,
                mean_batch=float(np.mean(srv.batch_sizes)) if srv.batch_sizes else 0.0,
+               max_batch=int(max(srv.batch_sizes)) if srv.batch_sizes else 0,
+               mixed_launches=sum(1 for t in srv.launch_templates if len(t) > 1),
                p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
                cell_updates_per_s=srv.cells_done / wall, wall_s=wall, offered_rate=rate,
                offered_cell_updates_per_s=rate * float(np.mean([t.n for t in templates])),

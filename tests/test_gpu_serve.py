@@ -1,9 +1,14 @@
 """Serving loop (continuous batching of step requests): a session served
 among many others ends in exactly the state of the same steps run alone with
-single-run stage calls, every request completes, and admission keeps the
-device memory of admitted sessions within the budget."""
+single-run stage calls and within the parity bars of the oracle's chain of
+the same steps, launches do carry sessions of different templates, every
+request completes, and admission keeps the device memory of admitted
+sessions within the budget."""
 import numpy as np
 import pytest
+
+import oracle as O
+import parity_util as U
 
 pytestmark = pytest.mark.gpu
 
@@ -31,7 +36,9 @@ def test_served_sessions_match_alone_bitwise():
                      hbm_budget_bytes=budget, keep_final=True)
     assert res["requests"] == len(S.I.poisson_arrivals(3000.0, 0.05, 9))
     assert 0 < srv.max_used <= budget
-    assert res["mean_batch"] >= 1.0
+    print(f"\nserved: {res['launches']} launches, max batch {res['max_batch']}, "
+          f"{res['mixed_launches']} with sessions of different templates", flush=True)
+    assert res["max_batch"] >= 2 and res["mixed_launches"] >= 1
     # every session's final state equals its steps run alone
     per_sess = {}
     for r in srv.done:
@@ -44,6 +51,68 @@ def test_served_sessions_match_alone_bitwise():
         assert np.array_equal(sess.final[0], ref[0]) and np.array_equal(sess.final[1], ref[1])
         checked += 1
     assert checked == len(srv.sessions)
+
+
+def _oracle_chain_static(tpl, steps):
+    """The oracle's time-centred steps of a static-mesh template: stage 1
+    (dt/2) and stage 2 (dt) on the template's own mesh, rebuilt on the host
+    from its points; returns (mesh, final Q, last stage's diagnostics and
+    inputs for the per-cell bar)."""
+    from paper_1410_3219_amd import tess as T
+    m = T.rich_tess_build(tpl.X0[0], tpl.X0[1], tpl.mesh.box, tpl.mesh.bc)
+    assert np.array_equal(m.area, np.asarray(R_area(tpl)))
+    p = O.Params(gamma=tpl.params.gamma, motion=0)
+    Q, X = tpl.Q0.copy(), tpl.X0.copy()
+    last = None
+    for _ in range(steps):
+        s1 = O.stage(m, Q, Q, X, 0.5 * tpl.dt, p)
+        assert s1.status == 0
+        s2 = O.stage(m, s1.Q, Q, X, tpl.dt, p, diag=True)
+        assert s2.status == 0
+        last = (s1.Q, Q, X, s2)
+        Q, X = s2.Q, s2.X
+    return m, Q, X, p, last
+
+
+def R_area(tpl):
+    from paper_1410_3219_amd import rich as R
+    return R.mesh_to_host(tpl.mesh).area
+
+
+def test_mixed_launch_sessions_follow_oracle_chains():
+    """Sessions of four templates (shock tubes and point explosions of
+    different sizes) with all their requests queued at once: the first
+    launch carries all four, so their stages run in one batched launch.
+    Each session ends bit for bit as its steps run alone, and within the
+    parity bars of the oracle's chain of the same steps (per conserved
+    quantity, and per cell against the last stage's terms)."""
+    import time
+    from paper_1410_3219_amd import serve as S
+    tpl = S.build_templates([900, 1600, 2500, 1200], ["sod", "sedov", "sod", "sedov"])
+    srv = S.Server(tpl, hbm_budget_bytes=1 << 30, keep_final=True)
+    steps = 3
+    for sid in range(4):
+        srv.open_session(sid, sid, steps)
+    rid = 0
+    for _ in range(steps):
+        for sid in range(4):
+            srv.submit(rid, sid, 0.0)
+            rid += 1
+    t0 = time.perf_counter()
+    srv.drain(lambda: time.perf_counter() - t0, timeout_s=120.0)
+    assert len(srv.done) == 4 * steps and not srv.failed
+    assert srv.launch_templates[0] == (0, 1, 2, 3), srv.launch_templates
+    for sid in range(4):
+        sess = srv.sessions[sid]
+        ref = _alone(sess.tpl, steps)
+        assert np.array_equal(sess.final[0], ref[0]) and np.array_equal(sess.final[1], ref[1])
+        m, Qo, Xo, p, (Qs, Qb, Xb, diag) = _oracle_chain_static(sess.tpl, steps)
+        eq, ex = U.errors(m, sess.final[0], sess.final[1], Qo, Xo, Qo, p)
+        ec, where = U.cell_errors(m, sess.final[0], Qb, Qo, sess.tpl.dt, p, diag, Qs=Qs)
+        print(f"\nserved {sess.tpl.name}: {steps} steps vs oracle chain: per quantity {eq}, "
+              f"per cell {ec}", flush=True)
+        assert (eq < 1e-11).all() and ex < 1e-12, (sess.tpl.name, eq, ex)
+        assert (ec < 1e-11).all(), (sess.tpl.name, ec, where)
 
 
 def test_flagged_session_is_evicted_and_others_go_on():
