@@ -180,6 +180,66 @@ __device__ __forceinline__ NbE nb_edge(const RunDesc& d, int i, int entry, bool&
 }
 
 // ---------------------------------------------------------------------------
+// arithmetic helpers
+// ---------------------------------------------------------------------------
+#ifndef RICH_NOCANON
+#define RICH_NOCANON 1
+#endif
+#ifndef RICH_FASTDIV
+#define RICH_FASTDIV 1
+#endif
+// Larger / smaller of two doubles, as fmax / fmin (a NaN operand yields the
+// other one).  fmax and fmin first quiet each operand the compiler cannot
+// prove already canonical (one extra instruction per operand); the hardware
+// instruction alone does the same for every operand that is not a
+// signalling NaN, and none of the stage's values is one.
+__device__ __forceinline__ double dmax(double a, double b) {
+#if RICH_NOCANON
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+#else
+  return fmax(a, b);
+#endif
+}
+__device__ __forceinline__ double dmin(double a, double b) {
+#if RICH_NOCANON
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+#else
+  return fmin(a, b);
+#endif
+}
+
+// 1/b: the hardware estimate refined by two Newton steps
+// r <- r + r (1 - b r), each squaring the relative error, so the result is
+// within an ulp or so of the correctly rounded reciprocal for every finite
+// nonzero b whose reciprocal is a normal number.
+__device__ __forceinline__ double rcp(double b) {
+#if RICH_FASTDIV
+  double r = __builtin_amdgcn_rcp(b);
+  double e = fma(-b, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-b, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / b;
+#endif
+}
+// a/b: a times the reciprocal, then one correction with the exact residual
+// a - b q (an fma), which brings the quotient to within an ulp of a/b.
+__device__ __forceinline__ double ddiv(double a, double b) {
+#if RICH_FASTDIV
+  const double r = rcp(b);
+  const double q = a * r;
+  return fma(r, fma(-b, q, a), q);
+#else
+  return a / b;
+#endif
+}
+
+// ---------------------------------------------------------------------------
 // A1: primitives of cell j from the extensive totals (ideal gas)
 // ---------------------------------------------------------------------------
 // Two reciprocals instead of four divisions: the results may differ from the
@@ -187,8 +247,8 @@ __device__ __forceinline__ NbE nb_edge(const RunDesc& d, int i, int entry, bool&
 __device__ __forceinline__ void prim_from(const RunDesc& d, double A, double M, double Px,
                                           double Py, double E, double& rho, double& vx,
                                           double& vy, double& p) {
-  const double rA = 1.0 / A;
-  const double rM = 1.0 / M;
+  const double rA = rcp(A);
+  const double rM = rcp(M);
   rho = M * rA;
   vx = Px * rM;
   vy = Py * rM;
@@ -197,6 +257,47 @@ __device__ __forceinline__ void prim_from(const RunDesc& d, double A, double M, 
 __device__ __forceinline__ void prim_of(const RunDesc& d, int j, double area, double& rho,
                                         double& vx, double& vy, double& p) {
   prim_from(d, area, d.sM[j], d.sPx[j], d.sPy[j], d.sE[j], rho, vx, vy, p);
+}
+
+// A2 (section 6) and the Courant ratio of section 2.3 for one cell: sound
+// speed c, effective radius R = sqrt(A/pi), point velocity w (Lagrangian
+// motion plus the cell-rounding correction chi c (s - r)/|s - r| when the
+// centroid s lies more than eta R from the point r; w = 0 without motion)
+// and R / (c + |v - w|).  Shared by the cell pass and the Courant kernel,
+// which must agree bitwise.
+struct Kin {
+  double c, R, wx, wy;
+  bool rounded;
+};
+__device__ __forceinline__ Kin kinematics(const RunDesc& d, double A, double rho, double vx,
+                                          double vy, double p, double rix, double riy,
+                                          double six, double siy) {
+  constexpr double kInvPi = 0.31830988618379067154;
+  Kin k;
+  k.c = sqrt(d.gamma * ddiv(p, rho));
+  k.R = sqrt(A * kInvPi);
+  k.wx = 0.0;
+  k.wy = 0.0;
+  k.rounded = false;
+  if (d.motion) {
+    k.wx = vx;
+    k.wy = vy;
+    const double dx = six - rix, dy = siy - riy;
+    const double dd = sqrt(dx * dx + dy * dy);
+    if (dd > d.eta * k.R) {
+      const double s = d.chi * k.c * rcp(dd);
+      k.wx += s * dx;
+      k.wy += s * dy;
+      k.rounded = true;
+    }
+  }
+  return k;
+}
+__device__ __forceinline__ double courant_ratio(const Kin& k, double vx, double vy) {
+  const double ux = vx - k.wx, uy = vy - k.wy;
+  const double cs = k.c + sqrt(ux * ux + uy * uy);
+  const double ti = ddiv(k.R, cs);
+  return (ti > 0.0 && isfinite(ti)) ? ti : 0.0;
 }
 
 // Pressure-ratio test of the shock detector, min(pi/pj, pj/pi) < delta_p,
@@ -225,11 +326,11 @@ __device__ inline void hllc(double g, double rgm1, const double* WL, const doubl
                             double* F, uint8_t* br = nullptr) {
   const double rl = WL[0], ul = WL[1], pl = WL[3];
   const double rr = WR[0], ur = WR[1], pr = WR[3];
-  const double cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
-  const double sl = fmin(ul - cl, ur - cr);
-  const double sr = fmax(ul + cl, ur + cr);
-  const double ss = (pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur)) /
-                    (rl * (sl - ul) - rr * (sr - ur));
+  const double cl = sqrt(g * ddiv(pl, rl)), cr = sqrt(g * ddiv(pr, rr));
+  const double sl = dmin(ul - cl, ur - cr);
+  const double sr = dmax(ul + cl, ur + cr);
+  const double ss = ddiv(pr - pl + rl * ul * (sl - ul) - rr * ur * (sr - ur),
+                         rl * (sl - ul) - rr * (sr - ur));
   if (br != nullptr)
     *br = (uint8_t)((0.0 <= sl ? 1 : 0) | (0.0 <= ss ? 2 : 0) | (0.0 < sr ? 4 : 0));
   if (0.0 <= sl) {
@@ -245,9 +346,9 @@ __device__ inline void hllc(double g, double rgm1, const double* WL, const doubl
   const double sk = left ? sl : sr;
   const double rho = W[0], u = W[1], vt = W[2], pk = W[3];
   const double E = pk * rgm1 + 0.5 * rho * (u * u + vt * vt);
-  const double rs = rho * (sk - u) / (sk - ss);
+  const double rs = ddiv(rho * (sk - u), sk - ss);
   const double ps = pk + rho * (sk - u) * (ss - u);
-  const double Es = rs * (E / rho + (ss - u) * (ss + pk / (rho * (sk - u))));
+  const double Es = rs * (ddiv(E, rho) + (ss - u) * (ss + ddiv(pk, rho * (sk - u))));
   F[0] = rs * ss;
   F[1] = rs * ss * ss + ps;
   F[2] = rs * ss * vt;

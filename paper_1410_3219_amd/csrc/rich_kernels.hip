@@ -142,12 +142,12 @@ __device__ __forceinline__ double group_sum(double v) {
 }
 template <int LPC, int O = 1>
 __device__ __forceinline__ double group_max(double v) {
-  if constexpr (O < LPC) return group_max<LPC, 2 * O>(fmax(v, lane_xor<O>(v)));
+  if constexpr (O < LPC) return group_max<LPC, 2 * O>(dmax(v, lane_xor<O>(v)));
   return v;
 }
 template <int LPC, int O = 1>
 __device__ __forceinline__ double group_min(double v) {
-  if constexpr (O < LPC) return group_min<LPC, 2 * O>(fmin(v, lane_xor<O>(v)));
+  if constexpr (O < LPC) return group_min<LPC, 2 * O>(dmin(v, lane_xor<O>(v)));
   return v;
 }
 template <int LPC, int O = 1>
@@ -196,30 +196,13 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
     if (active && !(A > 0.0 && A < INFINITY)) bad = true;  // a mesh cell without a volume
     double rho, vx, vy, p;
     prim_of(d, i, A, rho, vx, vy, p);
-    const double c = sqrt(d.gamma * p / rho);
-    const double R = sqrt(A / kPi);
-    double wx = 0.0, wy = 0.0;
-    bool rounded = false;
-    if (d.motion) {
-      // A2 (section 6): Lagrangian motion plus the cell-rounding correction
-      wx = vx;
-      wy = vy;
-      const double dx = six - rix, dy = siy - riy;
-      const double dd = sqrt(dx * dx + dy * dy);
-      if (dd > d.eta * R) {
-        wx += d.chi * c * dx / dd;
-        wy += d.chi * c * dy / dd;
-        rounded = true;
-      }
-    }
+    // A2 (section 6) and, fused into the cell pass, the cell's Courant ratio
+    // (A0), reduced to the block's minimum (each cell's lanes agree)
+    const Kin kin = kinematics(d, A, rho, vx, vy, p, rix, riy, six, siy);
+    const double c = kin.c, R = kin.R, wx = kin.wx, wy = kin.wy;
+    const bool rounded = kin.rounded;
     if (d.cfl_blocks != nullptr) {
-      // A0 fused into the cell pass: the Courant ratio of this cell, as in
-      // k_cfl, reduced to the block's minimum (each cell's lanes agree)
-      const double ux = vx - wx, uy = vy - wy;
-      const double cs = c + sqrt(ux * ux + uy * uy);
-      double ti = R / cs;
-      if (!(ti > 0.0) || !isfinite(ti)) ti = 0.0;
-      if (!active) ti = INFINITY;
+      const double ti = active ? courant_ratio(kin, vx, vy) : INFINITY;
       const double bm = block_min_cells(ti);
       if (threadIdx.x == 0) d.cfl_blocks[tt] = bm;
     }
@@ -263,8 +246,8 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
         const double ty = v.L * (dphi * uy - mean * ny);
         g[2 * q] += tx;
         g[2 * q + 1] += ty;
-        pmax[q] = fmax(pmax[q], pj[q]);
-        pmin[q] = fmin(pmin[q], pj[q]);
+        pmax[q] = dmax(pmax[q], pj[q]);
+        pmin[q] = dmin(pmin[q], pj[q]);
       }
       if (pressure_jump(d.delta_p, p, pj[3])) pflag = 1;
     };
@@ -368,7 +351,7 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
       accumulate(v, pj, vrx, vry);
     }
     double G[8];
-    const double rA = 1.0 / A;
+    const double rA = rcp(A);
 #pragma unroll
     for (int q = 0; q < 8; ++q) G[q] = group_sum<LPC>(g[q]) * rA;
 #pragma unroll
@@ -377,7 +360,7 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
       pmin[q] = group_min<LPC>(pmin[q]);
     }
     bool shock = group_or<LPC>(pflag) != 0;
-    if (-(G[2] + G[5]) > d.delta_v * c / R) shock = true;
+    if (-(G[2] + G[5]) > ddiv(d.delta_v * c, R)) shock = true;
 
     // A4: limiter
     double alpha[4] = {1.0, 1.0, 1.0, 1.0};
@@ -394,8 +377,8 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const double dphi = G[2 * q] * dx + G[2 * q + 1] * dy;
-          dmax[q] = fmax(dmax[q], dphi);
-          dmin[q] = fmin(dmin[q], dphi);
+          dmax[q] = rich::dmax(dmax[q], dphi);
+          dmin[q] = rich::dmin(dmin[q], dphi);
         }
       };
 #pragma unroll
@@ -409,8 +392,8 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
       for (int q = 0; q < 4; ++q) {
         dmax[q] = group_max<LPC>(dmax[q]);
         dmin[q] = group_min<LPC>(dmin[q]);
-        if (dmax[q] > 0.0) alpha[q] = fmin(alpha[q], (pmax[q] - phi[q]) / dmax[q]);
-        if (dmin[q] < 0.0) alpha[q] = fmin(alpha[q], (pmin[q] - phi[q]) / dmin[q]);
+        if (dmax[q] > 0.0) alpha[q] = rich::dmin(alpha[q], ddiv(pmax[q] - phi[q], dmax[q]));
+        if (dmin[q] < 0.0) alpha[q] = rich::dmin(alpha[q], ddiv(pmin[q] - phi[q], dmin[q]));
       }
     } else if (local == 1) {
       for (int k = k0 + lane; k < k1; k += LPC) {
@@ -422,8 +405,8 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
         for (int q = 0; q < 4; ++q) {
           const double dphi = G[2 * q] * dx + G[2 * q + 1] * dy;
           const double psi =
-              (dphi != 0.0) ? fmax(d.theta * (pj[q] - phi[q]) / dphi, 0.0) : 1.0;
-          alpha[q] = fmin(alpha[q], psi);
+              (dphi != 0.0) ? dmax(ddiv(d.theta * (pj[q] - phi[q]), dphi), 0.0) : 1.0;
+          alpha[q] = dmin(alpha[q], psi);
         }
       }
 #pragma unroll
@@ -755,23 +738,8 @@ __global__ __launch_bounds__(kCflThreads) void k_cfl(RunDesc d, double* block_ou
     load_cell(d, i, pxi, pyi, A, sxi, syi);
     double rho, vx, vy, p;
     prim_of(d, i, A, rho, vx, vy, p);
-    const double c = sqrt(d.gamma * p / rho);
-    const double R = sqrt(A / kPi);
-    double wx = 0.0, wy = 0.0;
-    if (d.motion) {
-      wx = vx;
-      wy = vy;
-      const double dx = sxi - pxi, dy = syi - pyi;
-      const double dd = sqrt(dx * dx + dy * dy);
-      if (dd > d.eta * R) {
-        wx += d.chi * c * dx / dd;
-        wy += d.chi * c * dy / dd;
-      }
-    }
-    const double ux = vx - wx, uy = vy - wy;
-    const double s = c + sqrt(ux * ux + uy * uy);
-    double ti = R / s;
-    if (!(ti > 0.0) || !isfinite(ti)) ti = 0.0;
+    const Kin kin = kinematics(d, A, rho, vx, vy, p, pxi, pyi, sxi, syi);
+    const double ti = courant_ratio(kin, vx, vy);
     t = fmin(t, ti);
   }
   const double m = block_min(t, smin);
