@@ -47,6 +47,9 @@ namespace rich {
 #ifndef RICH_CELL_MAXE
 #define RICH_CELL_MAXE 6  // CSR entries per cell loaded level by level (the rest in a loop)
 #endif
+#ifndef RICH_CELL_PRE
+#define RICH_CELL_PRE 1  // further CSR entries per lane whose entry and edge load with the first
+#endif
 #ifndef RICH_CELL_WAVES
 #define RICH_CELL_WAVES 1  // minimum waves per SIMD the register budget must allow
 #endif
@@ -179,7 +182,8 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
                                                        int n_runs, int n_tiles,
                                                        uint8_t* __restrict__ dbg) {
   constexpr int CPB = kCellThreads / LPC;  // cells per block
-  constexpr int MAXE = RICH_CELL_MAXE / LPC;  // entries per lane whose edge offsets stay in registers
+  constexpr int MAXE = RICH_CELL_MAXE / LPC;  // entries per lane loaded level by level
+  constexpr int PRE = RICH_CELL_PRE;
   const int lane = (int)threadIdx.x % LPC;
   const int cl = (int)threadIdx.x / LPC;
   for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
@@ -232,7 +236,8 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
     double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double pmax[4] = {rho, vx, vy, p}, pmin[4] = {rho, vx, vy, p};
     int pflag = 0;
-    double fdx[MAXE], fdy[MAXE];
+    constexpr int ME = MAXE + PRE;  // entries whose CSR entry and edge are loaded early
+    double fdx[ME], fdy[ME];
     auto accumulate = [&](const NbE& v, const double* pj, double vrx, double vry) {
       const double rx = rix - vrx, ry = riy - vry;
       const double inv_r = rsqrt(rx * rx + ry * ry);
@@ -258,17 +263,17 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
     // for three memory round trips instead of three per entry.
     {
       const int kc = max(0, min(k0, d.n_csr - 1));
-      bool val[MAXE];
-      int ent[MAXE];
+      bool val[ME];
+      int ent[ME];
 #pragma unroll
-      for (int m = 0; m < MAXE; ++m) {
+      for (int m = 0; m < ME; ++m) {
         const int k = k0 + lane + m * LPC;
         val[m] = k < k1;
         ent[m] = d.idx[val[m] ? k : kc];
       }
-      int ee[MAXE];
+      int ee[ME];
 #pragma unroll
-      for (int m = 0; m < MAXE; ++m) {
+      for (int m = 0; m < ME; ++m) {
         int e = ent[m] >> 1;
         if (val[m] && (e < 0 || e >= d.n_edges)) {
           bad = true;
@@ -276,11 +281,11 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
         }
         ee[m] = val[m] ? e : 0;
       }
-      uint32_t ej[MAXE];
-      int ei[MAXE];
-      double eL[MAXE], efx[MAXE], efy[MAXE];
+      uint32_t ej[ME];
+      int ei[ME];
+      double eL[ME], efx[ME], efy[ME];
 #pragma unroll
-      for (int m = 0; m < MAXE; ++m) {
+      for (int m = 0; m < ME; ++m) {
         const EdgeRec er = load_edge(d, ee[m]);
         ej[m] = er.j;
         ei[m] = er.i;
@@ -288,9 +293,9 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
         efx[m] = er.fx;
         efy[m] = er.fy;
       }
-      NbE v[MAXE];
+      NbE v[ME];
 #pragma unroll
-      for (int m = 0; m < MAXE; ++m) {
+      for (int m = 0; m < ME; ++m) {
         const int side = ent[m] & 1;
         const int code = (int)(ej[m] >> 28);
         v[m].L = eL[m];
@@ -343,8 +348,22 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
           fdy[m] = v[m].fy - siy;
         }
       }
+      // entries loaded early past the level-by-level ones: their neighbours
+      // cost one more round trip, not three
+#pragma unroll
+      for (int m = MAXE; m < ME; ++m) {
+        fdx[m] = 0.0;
+        fdy[m] = 0.0;
+        if (val[m]) {
+          double pj[4], vrx, vry;
+          nb_values(v[m], pj, vrx, vry);
+          accumulate(v[m], pj, vrx, vry);
+          fdx[m] = v[m].fx - six;
+          fdy[m] = v[m].fy - siy;
+        }
+      }
     }
-    for (int k = k0 + lane + MAXE * LPC; k < k1; k += LPC) {
+    for (int k = k0 + lane + ME * LPC; k < k1; k += LPC) {
       const NbE v = nb_edge(d, i, d.idx[k], bad);
       double pj[4], vrx, vry;
       nb_values(v, pj, vrx, vry);
@@ -382,9 +401,9 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
         }
       };
 #pragma unroll
-      for (int m = 0; m < MAXE; ++m)
+      for (int m = 0; m < ME; ++m)
         if (k0 + lane + m * LPC < k1) bound(fdx[m], fdy[m]);
-      for (int k = k0 + lane + MAXE * LPC; k < k1; k += LPC) {
+      for (int k = k0 + lane + ME * LPC; k < k1; k += LPC) {
         const NbE v = nb_edge(d, i, d.idx[k], bad);
         bound(v.fx - six, v.fy - siy);
       }
@@ -625,10 +644,15 @@ __global__ __launch_bounds__(TILE, RICH_FLUX_WAVES) void k_flux(RunDesc one, con
         }
       }
       const double h = d.h_dev != nullptr ? d.h_factor * (*d.h_dev) : d.h;
-      const double M = d.bM[i] - h * acc[0];
-      double Px = d.bPx[i] - h * acc[1];
-      double Py = d.bPy[i] - h * acc[2];
-      double E = d.bE[i] - h * acc[3];
+      // (loading these before the flux sum keeps them live across the
+      // foreign-edge fallback and costs occupancy)
+      const double bM = d.bM[i], bPx = d.bPx[i], bPy = d.bPy[i], bE = d.bE[i];
+      const double bx = d.bx[i], by = d.by[i];
+      const double2 wi = *reinterpret_cast<const double2*>(d.rec + (size_t)i * kRecDoubles + R_WX);
+      const double M = bM - h * acc[0];
+      double Px = bPx - h * acc[1];
+      double Py = bPy - h * acc[2];
+      double E = bE - h * acc[3];
       double gx = d.gx, gy = d.gy;
       if (d.ax != nullptr) {  // the cell's own acceleration
         gx += d.ax[i];
@@ -641,10 +665,8 @@ __global__ __launch_bounds__(TILE, RICH_FLUX_WAVES) void k_flux(RunDesc one, con
         Py += h * (sm * gy);
         E += h * (spx * gx + spy * gy);
       }
-      const double* rec = d.rec + (size_t)i * kRecDoubles;
-      const double wxi = rec[R_WX], wyi = rec[R_WY];
-      double x = d.bx[i] + h * wxi;
-      double y = d.by[i] + h * wyi;
+      double x = bx + h * wi.x;
+      double y = by + h * wi.y;
       if (d.bc == RICH_BOUNDARY_PERIODIC) {
         x = wrap_once(x, d.x0, d.x1);
         y = wrap_once(y, d.y0, d.y1);
