@@ -284,11 +284,130 @@ def bench_batch(args, R, T, log):
                            "autotune_ms_per_stage": {"stage1": ms1, "stage2": ms2}}
     del graph
     flags = R.rich_batch_flags(len(runs), wsb)
+    res["device_dt"] = bench_batch_device_dt(runs, total, tile1, tile2, log)
+    res["plain_sod"] = bench_plain_sod(args, R, T, total, log)
     return {"runs": len(runs), "cells": total, "flags_ok": not any(flags),
-            "graph_replay": res["graph_replay"],
+            "graph_replay": res["graph_replay"], "device_dt": res["device_dt"],
+            "plain_sod": res["plain_sod"],
+            "device_dt_graph_over_plain_sod": res["device_dt"]["graph_replay"]["cell_updates_per_s"]
+            / res["plain_sod"]["cell_updates_per_s"],
             "batched": res["batched"], "per_run_launches": res["per_run_launches"],
             "batched_over_per_run": res["batched"]["cell_updates_per_s"] /
             res["per_run_launches"]["cell_updates_per_s"]}
+
+
+def bench_batch_device_dt(runs, total, tile1, tile2, log):
+    """The batched step with every run's step taken on the device (a batched
+    Courant stage, then the second stage reading its steps): eager (prepare
+    and launch of both stages per step) and both launches replayed from one
+    graph.  Each run's step equals its host step bitwise, so the half-step
+    meshes built for the host-step legs serve here too."""
+    import torch
+    from paper_1410_3219_amd import rich as R
+    n = len(runs)
+    ns = [r["hm"].n_cells for r in runs]
+    ws1, ws2 = R.batch_workspace(ns), R.batch_workspace(ns)
+    m1 = [r["dm"] for r in runs]
+    m2 = [r["dmh"] for r in runs]
+    s0 = [r["s0"] for r in runs]
+    half = [r["half"] for r in runs]
+    out = [r["out"] for r in runs]
+    prm = [r["p"] for r in runs]
+
+    def prepare():
+        q1 = R.rich_stage_batch_prepare_courant(m1, s0, s0, half, [0.5] * n, prm, ws1, tile=tile1)
+        q2 = R.rich_stage_batch_prepare_courant(m2, half, s0, out, [1.0] * n, prm, ws2,
+                                                dt_ws=ws1, tile=tile2)
+        return q1, q2
+
+    def eager():
+        q1, q2 = prepare()
+        R.rich_stage_batch_launch(q1, ws1)
+        R.rich_stage_batch_launch(q2, ws2)
+
+    eager()
+    torch.cuda.synchronize()
+    dts = R.rich_batch_dt(n, ws1)
+    same_dt = all(d == r["dt"] for d, r in zip(dts, runs))
+    want = [o.Q.clone() for o in out]
+    res = {"steps_equal_host_steps": same_dt,
+           "flags_ok": not any(R.rich_batch_flags(n, ws1) + R.rich_batch_flags(n, ws2))}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        eager()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    res["eager"] = {"ms_per_step": ms, "cell_updates_per_s": total / (ms / 1e3)}
+    q1, q2 = prepare()
+    gs = torch.cuda.Stream()
+    gs.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    with torch.cuda.stream(gs):
+        R.rich_stage_batch_launch(q1, ws1, gs)
+        R.rich_stage_batch_launch(q2, ws2, gs)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=gs):
+        R.rich_stage_batch_launch(q1, ws1, gs)
+        R.rich_stage_batch_launch(q2, ws2, gs)
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    gms = e0.elapsed_time(e1) / reps
+    res["graph_replay"] = {"ms_per_step": gms, "cell_updates_per_s": total / (gms / 1e3),
+                           "bitwise_equal_to_eager": all(torch.equal(o.Q, w)
+                                                         for o, w in zip(out, want))}
+    del graph
+    log(f"[bench] batch with device steps: eager {ms:.3f} ms, graph {gms:.3f} ms per step")
+    return res
+
+
+def bench_plain_sod(args, R, T, cells, log):
+    """One shock-tube run of about `cells` cells (the batch's total) as a
+    plain single run with its step on the device, for a comparison of the
+    batch with the same physics at the same size."""
+    import numpy as np
+    import torch
+    from paper_1410_3219_amd import inputs as I
+    k = int(round(cells ** 0.5))
+    t0 = time.time()
+    P = I.sod(k=k, seed=11)
+    hm = T.rich_tess_build(P.px, P.py, P.box, P.bc, args.threads)
+    prm = R.Params(gamma=P.gamma)
+    dm = R.DeviceMesh.from_host(hm)
+    cur = R.DeviceState.from_host(P.state(hm.area), np.stack([hm.px, hm.py]))
+    half, nxt = R.DeviceState.empty_like(cur), R.DeviceState.empty_like(cur)
+    ws, ws2 = R.workspace(hm.n_cells), R.workspace(hm.n_cells)
+    R.rich_stage_courant(dm, cur, cur, half, 0.5, prm, ws)
+    xh = half.X.cpu().numpy()
+    dmh = R.DeviceMesh.from_host(T.rich_tess_build(xh[0], xh[1], P.box, P.bc, args.threads))
+    log(f"[bench] plain shock tube: {hm.n_cells} cells ({time.time() - t0:.1f}s setup)")
+
+    def step():
+        R.rich_stage_courant(dm, cur, cur, half, 0.5, prm, ws)
+        R.rich_stage_dt_of(dmh, half, cur, nxt, 1.0, ws, prm, ws2)
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"cells": hm.n_cells, "ms_per_step": ms,
+            "cell_updates_per_s": hm.n_cells / (ms / 1e3),
+            "flags_ok": R.rich_stage_flags(ws) == 0 and R.rich_stage_flags(ws2) == 0}
 
 
 def bench_serve(args, R, log):

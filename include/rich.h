@@ -297,6 +297,11 @@ int rich_stage_batch_accel(int32_t n, const rich_mesh* const* meshes,
  *                             memsets, no allocation, no host synchronisation).
  * A launch reads the device and host memory named when the plan was made, so
  * every replay runs the stage again on whatever those buffers then hold.
+ * A plan is valid on its workspace until the next prepare on that
+ * workspace, which overwrites the descriptors: rich_stage_batch_launch
+ * returns RICH_E_INVAL for any plan but the last one prepared on ws (a graph
+ * that captured a launch replays whatever the workspace then holds, so
+ * prepare nothing else on it while the graph is in use).
  * rich_stage_batch is prepare followed by launch.  Kernel timing must be off
  * while a launch is captured.
  */
@@ -308,6 +313,8 @@ typedef struct rich_batch_plan {
   int32_t grid_cell;        /* persistent grid of the cell kernel              */
   int32_t grid_flux[2];     /* persistent grids of the two flux kernels        */
   int32_t flux_tile;        /* cells per flux tile (edge-tile shape)           */
+  int32_t courant;          /* 1: the stage computes each run's step          */
+  int64_t serial;           /* identifies the prepare that made the plan       */
 } rich_batch_plan;
 int rich_stage_batch_prepare(int32_t n, const rich_mesh* const* meshes,
                              const rich_state* const* src, const rich_state* const* base,
@@ -326,6 +333,34 @@ int rich_stage_batch_prepare_tile(int32_t n, const rich_mesh* const* meshes,
                                   rich_state* const* out, const double* h,
                                   const rich_params* const* params, int32_t tile, void* ws,
                                   size_t ws_bytes, void* stream, rich_batch_plan* plan);
+/* A batched stage whose steps are taken on the device, per run, from the
+ * Courant condition of section 2.3 (the batched form of rich_stage_courant /
+ * rich_stage_dt_of), prepared as rich_stage_batch_prepare_tile and launched
+ * with rich_stage_batch_launch; a step of every run then needs no host
+ * round trip, and both of its stages can be captured in one graph.
+ *   dt_ws == NULL  the stage computes run r's step
+ *                  dt_r = params[r]->cfl * min over cells of R/(c + |v - w|)
+ *                  from src[r] in its cell pass, keeps it in ws (slot r,
+ *                  read with rich_batch_dt) and applies h_r = factor[r] * dt_r
+ *                  (factor 0.5 for the first stage of a time-centred step).
+ *                  Runs with params[r]->integrator == 1 are RICH_E_INVAL
+ *                  (their cell pass reads the step).  A step that is not a
+ *                  positive finite number sets the run's domain flag.
+ *   dt_ws != NULL  h_r = factor[r] * dt_r, with dt_r slot r of the batch
+ *                  workspace dt_ws of an earlier Courant stage over the same
+ *                  runs in the same order (dt_ws may be ws itself: a stage
+ *                  leaves the slots of the steps alone).
+ * factor[r] finite and >= 0.  Each run's step and result are bitwise those
+ * of rich_stage_courant / rich_stage_dt_of on that run alone. */
+int rich_stage_batch_prepare_courant(int32_t n, const rich_mesh* const* meshes,
+                                     const rich_state* const* src,
+                                     const rich_state* const* base, rich_state* const* out,
+                                     const double* factor, const rich_params* const* params,
+                                     int32_t tile, const void* dt_ws, void* ws, size_t ws_bytes,
+                                     void* stream, rich_batch_plan* plan);
+/* Synchronise `stream` and copy the n per-run steps the last Courant stage on
+ * the batch workspace ws computed into the host array dt. */
+int rich_batch_dt(int32_t n, void* ws, void* stream, double* dt);
 /* Autotune the edge-tile shape of a batched stage: prepares and times (HIP
  * events, `reps` launches after one warm-up) the stage with each tile of
  * 128, 256 and 512 cells on these runs, writing the mean milliseconds per

@@ -31,6 +31,7 @@
 #include <string>
 #include <mutex>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "rich.h"
@@ -77,16 +78,27 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 
 // Batched launches take a plan: tile_start[0..n_runs] is the exclusive prefix
 // of the tiles of the runs in this launch, tile_start[n_runs + 1 + k] the
-// descriptor index of the k-th of them.  find_run returns k for tile t.
+// descriptor index of the k-th of them.  find_run returns k for tile t,
+// searching runs lo..n_runs-1.
 __device__ __forceinline__ int find_run(const int32_t* __restrict__ tile_start, int n_runs,
-                                        int t) {
-  int lo = 0, hi = n_runs - 1;
+                                        int t, int lo = 0) {
+  int hi = n_runs - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
     if (tile_start[mid] <= t) lo = mid;
     else hi = mid - 1;
   }
   return lo;
+}
+// The run of tile t given the run `prev` of the block's previous tile: the
+// tiles of a persistent block grow (see xcd_tile), so this is usually the
+// same run or the next one, found with a load or two; else a search.
+__device__ __forceinline__ int next_run(const int32_t* __restrict__ tile_start, int n_runs,
+                                        int t, int prev) {
+  if (tile_start[prev] > t) return find_run(tile_start, n_runs, t, 0);
+  if (prev + 1 >= n_runs || tile_start[prev + 1] > t) return prev;
+  if (prev + 2 >= n_runs || tile_start[prev + 2] > t) return prev + 1;
+  return find_run(tile_start, n_runs, t, prev + 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -186,9 +198,10 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
   constexpr int PRE = RICH_CELL_PRE;
   const int lane = (int)threadIdx.x % LPC;
   const int cl = (int)threadIdx.x / LPC;
+  int pos = 0;   // run of the block's current tile (batched launches)
   for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
     const int tt = xcd_tile(b, n_tiles);
-    const int pos = BATCH ? find_run(tile_start, n_runs, tt) : 0;
+    if constexpr (BATCH) pos = next_run(tile_start, n_runs, tt, pos);
     const RunDesc& d = BATCH ? descs[tile_start[n_runs + 1 + pos]] : one;
     const int i0 = (tt - (BATCH ? tile_start[pos] : 0)) * CPB + cl;
     const bool active = i0 < d.n;
@@ -559,9 +572,10 @@ __global__ __launch_bounds__(TILE, RICH_FLUX_WAVES) void k_flux(RunDesc one, con
   __shared__ int s_off[TILE + 1];  // the tile's CSR offsets
   __shared__ int s_nfor;
   const int tid = (int)threadIdx.x;
+  int pos = 0;   // run of the block's current tile (batched launches)
   for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
     const int t = xcd_tile(b, n_tiles);
-    const int pos = BATCH ? find_run(tile_start, n_runs, t) : 0;
+    if constexpr (BATCH) pos = next_run(tile_start, n_runs, t, pos);
     const RunDesc& d = BATCH ? descs[tile_start[n_runs + 1 + pos]] : one;
     const int c0 = (t - (BATCH ? tile_start[pos] : 0)) * TILE;
     const int c1 = min(c0 + TILE, d.n);
@@ -769,31 +783,33 @@ __global__ __launch_bounds__(kCflThreads) void k_cfl(RunDesc d, double* block_ou
 }
 
 constexpr int kCflFinalThreads = 1024;
-// The minimum of the block minima, as a bit pattern in *out; with dt_out
-// also dt = cfl * minimum in *dt_out, and the domain flag when that is not
-// a positive number.
-__global__ __launch_bounds__(kCflFinalThreads) void k_cfl_final(const double* block_in, int nb,
-                                                                unsigned long long* out,
-                                                                double cfl, double* dt_out,
-                                                                int32_t* flag) {
-  __shared__ double smin[kCflFinalThreads / 64];
+constexpr int kCflBatchThreads = 256;
+// The minimum of nb block minima, as a bit pattern in *out; with dt_out also
+// dt = cfl * minimum in *dt_out, and the domain flag when that is not a
+// positive number.  NT threads; min is order-free, so the result does not
+// depend on NT.
+template <int NT>
+__device__ __forceinline__ void cfl_finish(const double* block_in, int nb,
+                                           unsigned long long* out, double cfl, double* dt_out,
+                                           int32_t* flag) {
+  __shared__ double smin[NT / 64];
   // four independent minima per thread, so the loads of a thread overlap
   double t0 = INFINITY, t1 = INFINITY, t2 = INFINITY, t3 = INFINITY;
   int b = threadIdx.x;
-  for (; b + 3 * kCflFinalThreads < nb; b += 4 * kCflFinalThreads) {
+  for (; b + 3 * NT < nb; b += 4 * NT) {
     t0 = fmin(t0, block_in[b]);
-    t1 = fmin(t1, block_in[b + kCflFinalThreads]);
-    t2 = fmin(t2, block_in[b + 2 * kCflFinalThreads]);
-    t3 = fmin(t3, block_in[b + 3 * kCflFinalThreads]);
+    t1 = fmin(t1, block_in[b + NT]);
+    t2 = fmin(t2, block_in[b + 2 * NT]);
+    t3 = fmin(t3, block_in[b + 3 * NT]);
   }
-  for (; b < nb; b += kCflFinalThreads) t0 = fmin(t0, block_in[b]);
+  for (; b < nb; b += NT) t0 = fmin(t0, block_in[b]);
   double t = fmin(fmin(t0, t1), fmin(t2, t3));
   for (int o = 32; o > 0; o >>= 1) t = fmin(t, __shfl_xor(t, o));
   if ((threadIdx.x & 63) == 0) smin[threadIdx.x >> 6] = t;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = smin[0];
-    for (int w = 1; w < kCflFinalThreads / 64; ++w) m = fmin(m, smin[w]);
+    for (int w = 1; w < NT / 64; ++w) m = fmin(m, smin[w]);
     *out = (unsigned long long)__double_as_longlong(m);
     if (dt_out != nullptr) {
       const double dt = cfl * m;
@@ -801,6 +817,32 @@ __global__ __launch_bounds__(kCflFinalThreads) void k_cfl_final(const double* bl
       if (!(dt > 0.0) || !isfinite(dt)) atomicOr(flag, RICH_FLAG_DOMAIN);
     }
   }
+}
+
+__global__ __launch_bounds__(kCflFinalThreads) void k_cfl_final(const double* block_in, int nb,
+                                                                unsigned long long* out,
+                                                                double cfl, double* dt_out,
+                                                                int32_t* flag) {
+  cfl_finish<kCflFinalThreads>(block_in, nb, out, cfl, dt_out, flag);
+}
+
+// Batched Courant stage: block k finishes run k of the cell plan (entries
+// tile_start[k] .. tile_start[k + 1] - 1 of the batch's block minima, which
+// every descriptor's cfl_blocks points to, are its cell tiles) and writes
+// the run's step where its descriptor's h_dev points.
+__global__ __launch_bounds__(kCflBatchThreads) void k_cfl_final_batch(
+    const RunDesc* __restrict__ descs, const int32_t* __restrict__ tile_start, int n_runs) {
+  const int k = blockIdx.x;
+  if (k >= n_runs) return;
+  const RunDesc& d = descs[tile_start[n_runs + 1 + k]];
+  if (d.cfl_blocks == nullptr || d.h_dev == nullptr) {
+    // descriptors of a stage without device steps: nothing to finish
+    if (threadIdx.x == 0) atomicOr(d.flag, RICH_FLAG_DOMAIN);
+    return;
+  }
+  const int t0 = tile_start[k];
+  cfl_finish<kCflBatchThreads>(d.cfl_blocks + t0, tile_start[k + 1] - t0, d.cfl_min, d.cfl,
+                               const_cast<double*>(d.h_dev), d.flag);
 }
 
 }  // namespace rich
@@ -967,14 +1009,17 @@ int launch_stage(const RunDesc& d, int riemann, hipStream_t st, uint8_t* dbg_cel
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// batch workspace:  [descriptors][plans][flags][Courant minima][records...]
+// batch workspace:  [descriptors][plans][flags][Courant minima][steps]
+//                   [records...][Courant block minima]
+// Everything before the records depends on the number of runs only.
 // ---------------------------------------------------------------------------
 struct BatchLayout {
-  size_t desc, plan, flags, cfl, rec, total;
+  size_t desc, plan, flags, cfl, dt, rec, cflb, total;
   std::vector<size_t> rec_off;
 };
 
 BatchLayout batch_layout(int32_t n, const int64_t* n_cells) {
+  constexpr int CPB = rich::kCellThreads / rich::kLpc;
   BatchLayout L;
   size_t o = 0;
   L.desc = o;
@@ -985,12 +1030,18 @@ BatchLayout batch_layout(int32_t n, const int64_t* n_cells) {
   o += align_up((size_t)n * sizeof(int32_t), 256);
   L.cfl = o;
   o += align_up((size_t)n * sizeof(unsigned long long), 256);
+  L.dt = o;
+  o += align_up((size_t)n * sizeof(double), 256);
   L.rec = o;
   L.rec_off.resize(n);
+  size_t tiles = 0;
   for (int32_t r = 0; r < n; ++r) {
     L.rec_off[r] = o;
     o += align_up((size_t)n_cells[r] * rich::kRecDoubles * sizeof(double), 256);
+    tiles += (size_t)((n_cells[r] + CPB - 1) / CPB);
   }
+  L.cflb = o;
+  o += align_up(tiles * sizeof(double), 256);
   L.total = o;
   return L;
 }
@@ -1048,6 +1099,31 @@ int upload_staged(void* dst1, const void* src1, size_t b1, void* dst2, const voi
       hipEventRecord(ev, st) != hipSuccess)
     return RICH_E_DEVICE;
   return RICH_OK;
+}
+
+// The last plan prepared on each batch workspace: a launch runs only the plan
+// whose descriptors the workspace holds (a later prepare on the same
+// workspace overwrites them, and kernels launched with another plan's sizes
+// would read them out of step).
+std::mutex& plan_lock() {
+  static std::mutex m;
+  return m;
+}
+std::unordered_map<const void*, int64_t>& plan_registry() {
+  static std::unordered_map<const void*, int64_t> r;
+  return r;
+}
+int64_t register_plan(const void* ws) {
+  static int64_t serial = 0;
+  std::lock_guard<std::mutex> g(plan_lock());
+  const int64_t s = ++serial;
+  plan_registry()[ws] = s;
+  return s;
+}
+bool plan_is_current(const void* ws, int64_t s) {
+  std::lock_guard<std::mutex> g(plan_lock());
+  auto it = plan_registry().find(ws);
+  return it != plan_registry().end() && it->second == s;
 }
 
 // The batched flux kernel of solver k (0 HLLC, 1 exact) with tiles of `tile` cells.
@@ -1519,13 +1595,19 @@ namespace {
 
 // The batched stage's validation and upload; ax, ay (either both null or both
 // set) hold each run's per-cell acceleration, null entries meaning none.
+// courant: 0 host steps h[r]; 1 each run's step computed in this stage
+// (Courant condition on src) and h = h[r] * step; 2 h = h[r] * the step of
+// run r that an earlier Courant stage left in the batch workspace dt_ws.
 int batch_prepare(int32_t n, const rich_mesh* const* meshes, const rich_state* const* src,
                   const rich_state* const* base, rich_state* const* out, const double* h,
                   const rich_params* const* params, const double* const* ax,
                   const double* const* ay, int32_t tile, void* ws, size_t ws_bytes,
-                  void* stream, rich_batch_plan* plan) {
+                  void* stream, rich_batch_plan* plan, int courant = 0,
+                  const void* dt_ws = nullptr) {
   if (n <= 0 || !meshes || !src || !base || !out || !h || !params || !ws || !plan)
     return RICH_E_INVAL;
+  if (courant < 0 || courant > 2 || (courant == 2) != (dt_ws != nullptr)) return RICH_E_INVAL;
+  if (dt_ws && (reinterpret_cast<uintptr_t>(dt_ws) & 255)) return RICH_E_INVAL;
   if ((ax == nullptr) != (ay == nullptr)) return RICH_E_INVAL;
   if (ax)
     for (int32_t r = 0; r < n; ++r)
@@ -1543,6 +1625,9 @@ int batch_prepare(int32_t n, const rich_mesh* const* meshes, const rich_state* c
     if (!std::isfinite(h[r]) || h[r] < 0.0) return RICH_E_INVAL;
     if (out[r]->M == src[r]->M || out[r]->M == base[r]->M || out[r]->x == base[r]->x)
       return RICH_E_INVAL;
+    // extrapolated fluxes read the step in the cell pass, before this
+    // stage's Courant minimum exists
+    if (courant == 1 && params[r]->integrator == 1) return RICH_E_INVAL;
     nc[r] = cnt;
   }
   if (reinterpret_cast<uintptr_t>(ws) & 255) return RICH_E_NOMEM;
@@ -1566,6 +1651,16 @@ int batch_prepare(int32_t n, const rich_mesh* const* meshes, const rich_state* c
     d.flag = reinterpret_cast<int32_t*>(w + L.flags) + r;
     d.cfl_min = reinterpret_cast<unsigned long long*>(w + L.cfl) + r;
     d.rec = reinterpret_cast<double*>(w + L.rec_off[r]);
+    if (courant == 1) {
+      d.cfl_blocks = reinterpret_cast<double*>(w + L.cflb);   // indexed by batch cell tile
+      d.h_dev = reinterpret_cast<double*>(w + L.dt) + r;
+    } else if (courant == 2) {
+      d.h_dev = reinterpret_cast<const double*>(static_cast<const char*>(dt_ws) + L.dt) + r;
+    }
+    if (courant) {
+      d.h_factor = h[r];
+      d.h = 0.0;
+    }
     if (ax) {
       d.ax = ax[r];
       d.ay = ay[r];
@@ -1594,6 +1689,7 @@ int batch_prepare(int32_t n, const rich_mesh* const* meshes, const rich_state* c
   const size_t db = (size_t)n * sizeof(RunDesc), pb = plans.size() * sizeof(int32_t);
   const int up = upload_staged(w + L.desc, descs.data(), db, w + L.plan, plans.data(), pb, st);
   if (up) return up;
+  plan->serial = register_plan(ws);
 
   static const int cell_grid = resident_blocks(
       reinterpret_cast<const void*>(&rich::k_cell<rich::kLpc, true>), rich::kCellThreads);
@@ -1607,6 +1703,7 @@ int batch_prepare(int32_t n, const rich_mesh* const* meshes, const rich_state* c
   const int ti = tile == 128 ? 0 : (tile == 256 ? 1 : 2);
   const int flux0_grid = flux_grid[ti][0], flux1_grid = flux_grid[ti][1];
   plan->flux_tile = tile;
+  plan->courant = courant == 1 ? 1 : 0;
   plan->n_runs = n;
   plan->n_cell_tiles = (int32_t)tc;
   plan->n_flux_tiles[0] = (int32_t)tf[0];
@@ -1630,10 +1727,33 @@ int rich_stage_batch_prepare_tile(int32_t n, const rich_mesh* const* meshes,
                        ws_bytes, stream, plan);
 }
 
+int rich_stage_batch_prepare_courant(int32_t n, const rich_mesh* const* meshes,
+                                     const rich_state* const* src,
+                                     const rich_state* const* base, rich_state* const* out,
+                                     const double* factor, const rich_params* const* params,
+                                     int32_t tile, const void* dt_ws, void* ws, size_t ws_bytes,
+                                     void* stream, rich_batch_plan* plan) {
+  return batch_prepare(n, meshes, src, base, out, factor, params, nullptr, nullptr, tile, ws,
+                       ws_bytes, stream, plan, dt_ws ? 2 : 1, dt_ws);
+}
+
+int rich_batch_dt(int32_t n, void* ws, void* stream, double* dt) {
+  if (n <= 0 || !ws || !dt) return RICH_E_INVAL;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return RICH_E_INVAL;
+  std::vector<int64_t> one(n, 1);
+  const BatchLayout L = batch_layout(n, one.data());
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return RICH_E_DEVICE;
+  if (hipMemcpy(dt, static_cast<char*>(ws) + L.dt, (size_t)n * sizeof(double),
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return RICH_E_DEVICE;
+  return RICH_OK;
+}
+
 int rich_stage_batch_launch(const rich_batch_plan* plan, void* ws, void* stream) {
   if (!plan || !ws || plan->n_runs <= 0 || plan->n_cell_tiles <= 0 || plan->grid_cell <= 0)
     return RICH_E_INVAL;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return RICH_E_NOMEM;
+  if (!plan_is_current(ws, plan->serial)) return RICH_E_INVAL;
   const int32_t n = plan->n_runs;
   std::vector<int64_t> one(n, 1);
   const BatchLayout L = batch_layout(n, one.data());   // descriptor and plan offsets
@@ -1652,6 +1772,9 @@ int rich_stage_batch_launch(const rich_batch_plan* plan, void* ws, void* stream)
                      dim3(rich::kCellThreads), 0, st, dummy, dd, dpc, n, plan->n_cell_tiles,
                      (uint8_t*)nullptr);
   prof_end(pcl, st);
+  if (plan->courant)   // each run's step from its cell kernel's Courant minima
+    hipLaunchKernelGGL(rich::k_cfl_final_batch, dim3(n), dim3(rich::kCflBatchThreads), 0, st,
+                       dd, dpc, n);
   int pfl = prof_begin("k_flux", st);
   for (int k = 0; k < 2; ++k) {
     if (plan->n_group[k] <= 0 || plan->grid_flux[k] <= 0) continue;

@@ -53,7 +53,7 @@ class RichBatchPlan(C.Structure):
     _fields_ = [("n_runs", C.c_int32), ("n_cell_tiles", C.c_int32),
                 ("n_flux_tiles", C.c_int32 * 2), ("n_group", C.c_int32 * 2),
                 ("grid_cell", C.c_int32), ("grid_flux", C.c_int32 * 2),
-                ("flux_tile", C.c_int32)]
+                ("flux_tile", C.c_int32), ("courant", C.c_int32), ("serial", C.c_int64)]
 
 
 class RichState(C.Structure):
@@ -187,6 +187,10 @@ def lib():
                                                         C.POINTER(_vp), C.POINTER(_vp), _dp,
                                                         C.POINTER(_vp), C.c_int32, _vp,
                                                         C.c_size_t, _vp, C.POINTER(RichBatchPlan)]
+            L.rich_stage_batch_prepare_courant.argtypes = [
+                C.c_int32, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), _dp,
+                C.POINTER(_vp), C.c_int32, _vp, _vp, C.c_size_t, _vp, C.POINTER(RichBatchPlan)]
+            L.rich_batch_dt.argtypes = [C.c_int32, _vp, _vp, _dp]
             L.rich_stage_batch_autotune.argtypes = [C.c_int32, C.POINTER(_vp), C.POINTER(_vp),
                                                     C.POINTER(_vp), C.POINTER(_vp), _dp,
                                                     C.POINTER(_vp), C.c_int32, _vp, C.c_size_t,
@@ -194,7 +198,8 @@ def lib():
             for f in ("rich_batch_workspace_size", "rich_stage_batch", "rich_batch_flags",
                       "rich_batch_flags_async", "rich_stage_batch_prepare",
                       "rich_stage_batch_launch", "rich_stage_batch_prepare_tile",
-                      "rich_stage_batch_autotune"):
+                      "rich_stage_batch_autotune", "rich_stage_batch_prepare_courant",
+                      "rich_batch_dt"):
                 getattr(L, f).restype = C.c_int
         if hasattr(L, "rich_step"):
             L.rich_ctx_create.argtypes = [C.POINTER(_vp)]
@@ -702,6 +707,33 @@ def rich_stage_batch_prepare_tile(meshes, srcs, bases, outs, hs, params, tile, w
                                              _stream_ptr(stream), C.byref(plan))
     _check(st, "rich_stage_batch_prepare_tile")
     return plan
+
+
+def rich_stage_batch_prepare_courant(meshes, srcs, bases, outs, factors, params, ws,
+                                     dt_ws=None, tile=256, stream=None):
+    """A batched stage with each run's step taken on the device (Courant
+    condition, section 2.3): with dt_ws None the stage computes every run's
+    step from srcs and applies factors[r] times it; otherwise it applies
+    factors[r] times the step an earlier Courant stage left in the batch
+    workspace dt_ws (which may be ws).  Returns the plan for
+    rich_stage_batch_launch."""
+    n, mp, spp, bpp, opp, hh, ppp, _pc = _batch_args(meshes, srcs, bases, outs, factors, params)
+    plan = RichBatchPlan()
+    dtp = None if dt_ws is None else C.c_void_p(dt_ws.data_ptr())
+    st = lib().rich_stage_batch_prepare_courant(n, mp, spp, bpp, opp, hh, ppp, int(tile), dtp,
+                                                C.c_void_p(ws.data_ptr()), ws.numel(),
+                                                _stream_ptr(stream), C.byref(plan))
+    _check(st, "rich_stage_batch_prepare_courant")
+    return plan
+
+
+def rich_batch_dt(n, ws, stream=None):
+    """The n per-run steps the last Courant stage on the batch workspace ws
+    computed (synchronises the stream)."""
+    d = (C.c_double * n)()
+    _check(lib().rich_batch_dt(n, C.c_void_p(ws.data_ptr()), _stream_ptr(stream), d),
+           "rich_batch_dt")
+    return list(d)
 
 
 def rich_stage_batch_autotune(meshes, srcs, bases, outs, hs, params, ws, reps=3, stream=None):

@@ -37,6 +37,7 @@ def test_declared_entry_points_are_the_expected_set():
                  "rich_stage_flags", "rich_cfl_dt",
                  "rich_workspace_size",
                  "rich_stage_batch", "rich_batch_flags", "rich_batch_workspace_size",
+                 "rich_stage_batch_prepare_courant", "rich_batch_dt",
                  "rich_step", "rich_step_batch", "rich_ctx_create", "rich_ctx_destroy",
                  "rich_ctx_set_mesh", "rich_ctx_mesh", "rich_strerror"):
         assert must in names
@@ -142,6 +143,27 @@ def test_argument_validation_without_gpu():
     arr = (C.c_int64 * 2)(100, 0)
     assert L.rich_batch_workspace_size(2, arr, C.byref(wsz)) == R.RICH_E_INVAL
     assert L.rich_stage_batch(0, None, None, None, None, None, None, None, 0, None) == R.RICH_E_INVAL
+    # batched stage with device steps: a run with extrapolated fluxes cannot
+    # take the Courant stage, factors must be finite and >= 0, and the step
+    # workspace must be aligned
+    bsz = C.c_size_t(0)
+    assert L.rich_batch_workspace_size(1, (C.c_int64 * 1)(100), C.byref(bsz)) == R.RICH_OK
+    m1 = mesh()
+    one = lambda x: (C.c_void_p * 1)(C.addressof(x))  # noqa: E731
+    plan = R.RichBatchPlan()
+
+    def courant(prm, factor=0.5, dt_ws=None):
+        pc = prm.c()
+        return L.rich_stage_batch_prepare_courant(
+            1, one(m1), one(src), one(base), one(out), (C.c_double * 1)(factor), one(pc), 256,
+            dt_ws, C.c_void_p(fake), bsz.value, None, C.byref(plan))
+
+    assert courant(R.Params(integrator=1)) == R.RICH_E_INVAL
+    assert courant(p, factor=float("nan")) == R.RICH_E_INVAL
+    assert courant(p, factor=-0.5) == R.RICH_E_INVAL
+    assert courant(p, dt_ws=C.c_void_p(fake + 8)) == R.RICH_E_INVAL
+    d1 = (C.c_double * 1)()
+    assert L.rich_batch_dt(0, C.c_void_p(fake), None, d1) == R.RICH_E_INVAL
 
 
 def test_acceleration_fields_are_checked_before_any_launch():
