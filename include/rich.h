@@ -310,11 +310,12 @@ typedef struct rich_batch_plan {
   int32_t n_cell_tiles;     /* tiles of the cell kernel over all runs          */
   int32_t n_flux_tiles[2];  /* flux tiles of the HLLC runs, of the exact runs  */
   int32_t n_group[2];       /* number of HLLC runs, of exact-solver runs        */
-  int32_t grid_cell;        /* persistent grid of the cell kernel              */
-  int32_t grid_flux[2];     /* persistent grids of the two flux kernels        */
+  int32_t grid_cell;        /* blocks of the cell kernel (one per tile)        */
+  int32_t grid_flux[2];     /* blocks of the two flux kernels (one per tile)   */
   int32_t flux_tile;        /* cells per flux tile (edge-tile shape)           */
   int32_t courant;          /* 1: the stage computes each run's step          */
   int64_t serial;           /* identifies the prepare that made the plan       */
+  int64_t table_offset;     /* bytes from ws to the tile -> run tables         */
 } rich_batch_plan;
 int rich_stage_batch_prepare(int32_t n, const rich_mesh* const* meshes,
                              const rich_state* const* src, const rich_state* const* base,

@@ -53,7 +53,8 @@ class RichBatchPlan(C.Structure):
     _fields_ = [("n_runs", C.c_int32), ("n_cell_tiles", C.c_int32),
                 ("n_flux_tiles", C.c_int32 * 2), ("n_group", C.c_int32 * 2),
                 ("grid_cell", C.c_int32), ("grid_flux", C.c_int32 * 2),
-                ("flux_tile", C.c_int32), ("courant", C.c_int32), ("serial", C.c_int64)]
+                ("flux_tile", C.c_int32), ("courant", C.c_int32), ("serial", C.c_int64),
+                ("table_offset", C.c_int64)]
 
 
 class RichState(C.Structure):
