@@ -75,37 +75,75 @@ def algorithmic_bytes(m, pass2):
     return b
 
 
+GATHER_PROBE_DOUBLES = (4, 8, 16)   # gather probe rows of 32, 64, 128 bytes
+
+
 def _pmc_per_kernel(d):
-    """Mean counter value per dispatch, by kernel name (rocprofv3 csv)."""
+    """Counters of one rocprofv3 --pmc run, by kernel: the mean per dispatch
+    for k_cell and k_flux, the largest dispatch of the calibration copy, and
+    each gather probe (torch's gather kernel behind index_select, in launch
+    order: rows of 32, 64, 128 bytes).  Values are summed over a dispatch's instances."""
     import csv
     f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if not f:
         raise SystemExit(f"no counter_collection.csv under {d}")
-    acc = {}
+    disp = {}
     for row in csv.DictReader(open(f[0])):
-        name = row["Kernel_Name"]
-        key = ("k_cell" if "k_cell" in name else "k_flux" if "k_flux" in name else
-               "copy" if "copyBuffer" in name else None)
-        if key is None:
-            continue
-        a = acc.setdefault((key, row["Counter_Name"]), {})
-        a[row["Dispatch_Id"]] = a.get(row["Dispatch_Id"], 0.0) + float(row["Counter_Value"])
-    # the calibration copy is the largest copy dispatch
-    return {k: max(v.values()) if k[0] == "copy" else sum(v.values()) / len(v)
-            for k, v in acc.items()}
+        e = disp.setdefault(int(row["Dispatch_Id"]), {"name": row["Kernel_Name"], "c": {}})
+        c = row["Counter_Name"]
+        e["c"][c] = e["c"].get(c, 0.0) + float(row["Counter_Value"])
+    out, acc = {}, {}
+    for i in sorted(disp):
+        name, c = disp[i]["name"], disp[i]["c"]
+        key = "k_cell" if "k_cell" in name else "k_flux" if "k_flux" in name else None
+        if key:
+            for k, v in c.items():
+                acc.setdefault((key, k), []).append(v)
+    for k, v in acc.items():
+        out[k] = sum(v) / len(v)
+    copies = [disp[i]["c"] for i in disp if "copyBuffer" in disp[i]["name"]]
+    if copies:
+        first = sorted(copies[0])[0]
+        big = max(copies, key=lambda c: c.get(first, 0.0))
+        for k, v in big.items():
+            out[("copy", k)] = v
+    gathers = [disp[i]["c"] for i in sorted(disp) if "gather_kernel" in disp[i]["name"]]
+    if len(gathers) == len(GATHER_PROBE_DOUBLES):
+        for w, c in zip(GATHER_PROBE_DOUBLES, gathers):
+            for k, v in c.items():
+                out[(f"gather{8 * w}", k)] = v
+    return out
+
+
+def _probe_bytes(key, copy_bytes):
+    """(read, write) bytes a calibration dispatch moves by construction."""
+    if key == "copy":
+        return copy_bytes, copy_bytes
+    w = int(key[len("gather"):]) // 8
+    nsel = (64 << 20) // (8 * w)
+    return nsel * 8 * w + 8 * nsel, nsel * 8 * w
 
 
 TRAFFIC_HEADER = """\
-# HBM traffic per launch of k_cell and k_flux, workload '{w}', from two counter runs
-# on one MI355X (program directly after --, from /tmp with TMPDIR=/tmp):
-#   timeout -s KILL 300 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/{fd} -o p \\
-#     -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --copy-probe-mib {mib}
-#   timeout -s KILL 300 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <repo>/{wd} -o p \\
+# HBM traffic per launch of k_cell and k_flux, workload '{w}', from rocprofv3 --pmc runs
+# on one MI355X (program directly after --, from /tmp with TMPDIR=/tmp), one counter set
+# per run:  FETCH_SIZE | WRITE_SIZE |
+#   TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_BUBBLE_sum TCC_EA0_RDREQ_DRAM_sum |
+#   TCC_MISS_sum TCC_HIT_sum TCC_READ_sum TCC_WRITE_sum
+#   timeout -s KILL 300 rocprofv3 --pmc <set> --output-format csv -d <repo>/<dir> -o p \\
 #     -- python3 <repo>/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras --copy-probe-mib {mib}
 # summarised with:
-#   python bench.py --summarize-pmc {fd} {wd} --copy-probe-mib {mib}
-# Each counter (KiB per dispatch) is scaled by the factor that makes it read the known
-# size of a {mib} MiB device-to-device copy (copyBuffer) run after a 1 GiB cache flush.
+#   python bench.py --summarize-pmc {dirs} --copy-probe-mib {mib}
+# fetch/write_bytes_per_launch: FETCH_SIZE / WRITE_SIZE scaled by the factor that makes
+# each read the size of a {mib} MiB device-to-device copy (copyBuffer) run after a 1 GiB
+# flush.  Cross-check (read_requests): in the copy, k_cell and k_flux the EA read
+# requests equal the L2 read-line misses (TCC_MISS less written bytes / 128) to 0.02%,
+# so each request is one 128-byte line fill; FETCH_SIZE counts such a request as 64
+# bytes, hence the copy's factor of 2, and the copy-scaled figure is 128 bytes per
+# request for the two kernels.  The
+# gather probes (torch's gather kernel over scattered 32-, 64- and 128-byte rows, 64 MiB
+# of rows each) show what a fill can carry: 20-68 bytes of each 128 that the gather
+# asked for.
 # source_hash is a hash of the kernel sources the counters were taken on.
 """
 
@@ -119,20 +157,39 @@ def read_traffic(workload):
 
 
 def summarize_pmc(args):
-    """HBM bytes per launch of k_cell and k_flux from FETCH_SIZE / WRITE_SIZE
-    (KiB per dispatch), each scaled by the factor that makes the same counter
-    read the known size of the calibration copy."""
-    fd, wd = args.summarize_pmc
-    fetch, write = _pmc_per_kernel(fd), _pmc_per_kernel(wd)
+    """HBM bytes per launch of k_cell and k_flux from rocprofv3 --pmc runs of
+    this script with --copy-probe-mib: FETCH_SIZE and WRITE_SIZE scaled by the
+    calibration copy (the bench line's `traffic`), cross-checked, where the
+    runs hold them, with the EA read-request and L2 miss counters."""
+    pm = {}
+    for d in args.summarize_pmc:
+        pm.update(_pmc_per_kernel(d))
     nbytes = args.copy_probe_mib << 20
-    cf = nbytes / (fetch[("copy", "FETCH_SIZE")] * 1024.0)
-    cw = nbytes / (write[("copy", "WRITE_SIZE")] * 1024.0)
+    cf = nbytes / (pm[("copy", "FETCH_SIZE")] * 1024.0)
+    cw = nbytes / (pm[("copy", "WRITE_SIZE")] * 1024.0)
     out = {"source_hash": kernel_source_hash(), "copy_bytes": nbytes,
            "fetch_scale": cf, "write_scale": cw, "kernels": {}}
+    keys = ["copy"] + [f"gather{8 * w}" for w in GATHER_PROBE_DOUBLES] + ["k_cell", "k_flux"]
+    if all((k, c) in pm for k in keys for c in ("TCC_EA0_RDREQ_sum", "TCC_MISS_sum",
+                                                "WRITE_SIZE")):
+        xc = {}
+        for k in keys:
+            req = pm[(k, "TCC_EA0_RDREQ_sum")]
+            rmiss = pm[(k, "TCC_MISS_sum")] - pm[(k, "WRITE_SIZE")] * 1024.0 / 128.0
+            e = {"ea_read_requests": req, "l2_read_line_misses": rmiss,
+                 "requests_per_miss": req / rmiss if rmiss > 0 else None}
+            if not k.startswith("k_"):
+                known = _probe_bytes(k, nbytes)[0]
+                e["read_bytes_by_construction"] = known
+                e["bytes_per_request"] = known / req
+            else:
+                e["read_bytes_at_128_per_request"] = 128.0 * req
+            xc[k] = e
+        out["read_requests"] = xc
     tot = 0.0
     for k in ("k_cell", "k_flux"):
-        fb = fetch[(k, "FETCH_SIZE")] * 1024.0 * cf
-        wb = write[(k, "WRITE_SIZE")] * 1024.0 * cw
+        fb = pm[(k, "FETCH_SIZE")] * 1024.0 * cf
+        wb = pm[(k, "WRITE_SIZE")] * 1024.0 * cw
         out["kernels"][k] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb}
         tot += fb + wb
     out["bytes_per_stage"] = tot
@@ -143,9 +200,36 @@ def summarize_pmc(args):
     path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.txt")
     with open(path, "w") as f:
         f.write(TRAFFIC_HEADER.format(w=args.workload, mib=args.copy_probe_mib,
-                                      fd=fd, wd=wd))
+                                      dirs=" ".join(args.summarize_pmc)))
         f.write(json.dumps(out) + "\n")
-    print(json.dumps(out))
+    print(json.dumps(out, indent=1))
+
+
+def summarize_trace(d, name, title, command):
+    """Per-kernel durations of a rocprofv3 --kernel-trace --stats run (its
+    *_kernel_stats.csv, nanoseconds) into profiles/NAME.txt."""
+    import csv
+    import re
+    f = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no kernel_stats.csv under {d}")
+    rows = list(csv.DictReader(open(f[0])))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    path = os.path.join(ROOT, "profiles", f"{name}.txt")
+    with open(path, "w") as out:
+        out.write(f"# Kernel durations: {title}\n#\n# command (from the repository root, on one "
+                  f"MI355X):\n#   {command}\n# summarised with:\n#   python bench.py "
+                  f"--summarize-trace <dir> {name} '<title>' '<command>'\n#\n# source: "
+                  f"*_kernel_stats.csv (durations in microseconds); copyBuffer entries are the\n"
+                  f"# host<->device transfers of the host tessellation stage, outside the timed "
+                  f"region.\n#\n")
+        out.write(f"{'kernel':62s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s}\n")
+        for r in rows:
+            name = re.sub(r"\(.*$", "", r["Name"].replace("void ", ""))
+            out.write(f"{name[:62]:62s} {int(r['Calls']):6d} "
+                      f"{float(r['AverageNs']) / 1e3:10.1f} {float(r['MinNs']) / 1e3:10.1f} "
+                      f"{float(r['MaxNs']) / 1e3:10.1f}\n")
+    print(open(path).read())
 
 
 def summarize_counters(d, name, command):
@@ -788,12 +872,19 @@ def main():
     ap.add_argument("--summarize-counters", nargs=3, metavar=("PMC_DIR", "NAME", "COMMAND"),
                     help="average each counter per kernel over a rocprofv3 --pmc run into "
                          "profiles/NAME.txt, recording COMMAND as the run that made it")
-    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
-                         "script with --copy-probe-mib into profiles/traffic_<workload>.json")
+    ap.add_argument("--summarize-trace", nargs=4, metavar=("TRACE_DIR", "NAME", "TITLE", "COMMAND"),
+                    help="per-kernel durations of a rocprofv3 --kernel-trace --stats run into "
+                         "profiles/NAME.txt, recording TITLE and COMMAND")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="PMC_DIR",
+                    help="turn rocprofv3 --pmc runs (FETCH_SIZE; WRITE_SIZE; optionally the "
+                         "raw TCC read-request counters) of this script with --copy-probe-mib "
+                         "into profiles/traffic_<workload>.txt")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(args)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
         return
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters)
@@ -847,7 +938,21 @@ def main():
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
-        del a, b, flush
+        del a, b
+        # gather probes of known size: rows of 32, 64 and 128 bytes at
+        # distinct scattered rows (odd multiplicative hash, a bijection on a
+        # power-of-two row count) of a 1 GiB table, 64 MiB of rows each,
+        # each after a 1 GiB flush; read = rows + 8-byte indices, write = rows
+        tab = torch.empty((1 << 30) // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        for w in GATHER_PROBE_DOUBLES:
+            rows = tab.view(-1, w)
+            nsel = (64 << 20) // (8 * w)
+            idx = (torch.arange(nsel, dtype=torch.int64, device=dev) * 0x9E3779B1) & (rows.shape[0] - 1)
+            flush.fill_(3.0)
+            torch.cuda.synchronize()
+            rows.index_select(0, idx)
+            torch.cuda.synchronize()
+        del tab, flush
 
     # ---------------- live chain: GPU stages + host tessellation -----------
     hm0 = tessellate(P.px, P.py)
@@ -950,9 +1055,18 @@ def main():
     stage_ms = (kern["k_cell"][0] + kern["k_flux"][0]) / max(1, kern["k_cell"][1]) * 2
     achieved = bytes_step / (stage_ms / 1e3) / 1e9
     traffic = None
+    traffic_kernels = None
     tj = read_traffic(args.workload)
     if tj and tj.get("source_hash") == kernel_source_hash() and tj.get("n_cells") == n:
         traffic = tj.get("bytes_per_step")
+        # per kernel: counter bytes per launch, and the rate they move at in
+        # this run's own launches
+        traffic_kernels = {}
+        for k_, e in tj["kernels"].items():
+            b = e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+            launch_ms = kern[k_][0] / max(1, kern[k_][1])
+            traffic_kernels[k_] = {"bytes_per_launch": b, "bytes_per_cell": b / n,
+                                   "GBps_at_measured_duration": b / (launch_ms / 1e3) / 1e9}
 
     out = {
         "metric": METRIC,
@@ -983,6 +1097,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "traffic_over_algorithmic": traffic / bytes_step if traffic else None,
+            "traffic_per_kernel": traffic_kernels,
             "measured_copy_GBps": copy_gbs,
             "frac_of_measured_copy": achieved / copy_gbs if copy_gbs else None,
             "algorithmic_bytes_per_step": bytes_step,
