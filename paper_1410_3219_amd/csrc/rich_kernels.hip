@@ -4,7 +4,7 @@
 //
 // One stage is two kernels over tiles of kTile consecutive cells (cells come
 // in Hilbert order, so a tile is a compact patch of the mesh):
-//   k_cell  one thread per cell: primitives, point velocity, gradient and
+//   k_cell  two lanes per cell: primitives, point velocity, gradient and
 //           limiter (A1-A4); writes a 128-byte record per cell.
 //   k_flux  one block per tile: the fluxes of the edges the tile owns (edges
 //           are sorted by their first cell) are computed once each and kept
@@ -16,7 +16,8 @@
 //
 // Tiles are mapped to blocks so that each of the 8 XCDs (each with its own
 // L2) processes one contiguous range of tiles: neighbouring tiles, whose
-// cells are each other's halo, then share an L2.
+// cells are each other's halo, then share an L2.  Batched launches run one
+// block per tile of all runs and find each tile's run in a table.
 //
 // All HIP code is built with packed-FP32 instructions disabled and without
 // fast-math; nothing here writes through the scalar cache.
@@ -67,14 +68,24 @@ constexpr int kNumXcd = 8;
 constexpr size_t kHeader = 256;  // per-run workspace header
 
 // block -> tile, so that XCD x (blocks x, x+8, ...) gets one contiguous range
-// of tiles.  A bijection on [0, nb) for any nb; persistent grids pass the
-// virtual block index of each grid-stride round (their size is a multiple of
-// the CU count, so that index keeps the hardware block's XCD).
+// of tiles.  A bijection on [0, nb) for any nb; a grid smaller than nb passes
+// the virtual block index of each grid-stride round.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int q = nb / kNumXcd, rem = nb % kNumXcd;
   const int x = b % kNumXcd, k = b / kNumXcd;
   return x * q + min(x, rem) + k;
 }
+// The same ranges, each walked from its end: XCD x's k-th block takes the
+// k-th tile from the end of the range (a bijection as well).  The flux pass
+// walks this way, so that it starts on the records the cell pass wrote last,
+// which the caches still hold (2048^2 wave: 512 -> 503 us).
+__device__ __forceinline__ int xcd_tile_rev(int b, int nb) {
+  const int q = nb / kNumXcd, rem = nb % kNumXcd;
+  const int x = b % kNumXcd, k = b / kNumXcd;
+  const int cnt = q + (x < rem ? 1 : 0);
+  return x * q + min(x, rem) + (cnt - 1 - k);
+}
+
 
 // Batched launches take a table with one entry per tile of the launch:
 // {descriptor index of the tile's run, index of the run's first tile}, so a
@@ -551,7 +562,7 @@ __global__ __launch_bounds__(TILE, RICH_FLUX_WAVES) void k_flux(RunDesc one, con
   __shared__ int s_nfor;
   const int tid = (int)threadIdx.x;
   for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
-    const int t = xcd_tile(b, n_tiles);
+    const int t = xcd_tile_rev(b, n_tiles);
     const int2 tr = BATCH ? tile_run[t] : make_int2(0, 0);
     const RunDesc& d = BATCH ? descs[tr.x] : one;
     const int c0 = (t - tr.y) * TILE;
