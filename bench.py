@@ -648,9 +648,19 @@ def bench_device_chain(args, R, P, make_state, hm0, dm0, live_final, n_steps, lo
     Q = state["s"].Q
     scale = Q.abs().amax(dim=1)
     diff = ((Q - live_final[0]).abs().amax(dim=1) / scale).max().item()
+    # a re-tessellation's algorithmic bytes: the points in, the previous mesh's
+    # CSR and edges (an entry's neighbour is named by its edge), the new mesh
+    # out (cell records, edge records, CSR, first-edge offsets)
+    ne, nc = info2["n_edges"], info2["n_csr"]
+    rt_bytes = (16 * n + 4 * (n + 1) + 4 * hm0.n_csr + 32 * hm0.n_edges
+                + 48 * n + 32 * ne + 4 * (n + 1) + 4 * nc + 4 * (n + 1))
+    rt_gbs = rt_bytes / (ms_rt / 1e3) / 1e9
     out = {"steps": n_steps, "timed_steps": K, "ms_per_step": ms,
            "cell_updates_per_s": n / (ms / 1e3), "retess_ms": ms_rt,
            "retess_cells_per_s": n / (ms_rt / 1e3),
+           "retess_roofline": {"bound": "alu (FP64 VALU issue; see the counter profile)",
+                               "algorithmic_bytes": rt_bytes, "achieved_GBps": rt_gbs,
+                               "frac_of_hbm_peak": rt_gbs / HBM_PEAK_GBS},
            "all_certified": st == 0 and st2 == 0 and info["sticky"] == 0 and flags == 0,
            "n_edges": info2["n_edges"],
            "max_rel_diff_vs_host_mesh_chain": diff}
