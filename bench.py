@@ -723,9 +723,24 @@ def sod_oracle_checks(O, T, log):
                 raise SystemExit(f"{key}: oracle chain status {st}")
         sc = per_quantity_scale(Q, m.area, P.gamma)
         drift = (np.max(np.abs(c["Q"] - Q), axis=1) / sc).tolist()
+        # the same chain on the oracle built with fused multiply-adds: how far
+        # two correctly rounded runs of the method drift apart on this problem
+        fma = None
+        if os.path.exists(O.FMA_LIB_PATH):
+            mf = T.rich_tess_build(P.px, P.py, P.box, P.bc)
+            Qf, Xf = P.state(mf.area), np.stack([mf.px, mf.py])
+            with O.use_library(O.FMA_LIB_PATH):
+                for dt in c["dts"]:
+                    Qf, Xf, mf, _, st = O.step(mf, Qf, Xf, dt, op,
+                                               lambda x, y, b, bc: T.rich_tess_build(x, y, b, bc))
+                    if st:
+                        raise SystemExit(f"{key}: FMA oracle chain status {st}")
+            fma = dict(zip(["M", "Px", "Py", "E"],
+                           (np.max(np.abs(Qf - Q), axis=1) / sc).tolist()))
         t = float(sum(c["dts"]))
         res[key] = {"steps": len(c["dts"]), "t_end": t,
                     "drift_vs_oracle_per_quantity": dict(zip(["M", "Px", "Py", "E"], drift)),
+                    "oracle_fma_build_vs_oracle_per_quantity": fma,
                     "points_drift": float(np.max(np.abs(c["X"] - X))),
                     "L_shock_gpu": l_shock(O, P, c["mesh"], c["Q"], t),
                     "L_shock_oracle": l_shock(O, P, m, Q, t),

@@ -30,17 +30,22 @@ _ip = C.POINTER(C.c_int32)
 
 
 OMP_LIB_PATH = os.path.join(_HERE, "liboracle_omp.so")
+FMA_LIB_PATH = os.path.join(_HERE, "liboracle_fma.so")
 
 
 def build(force=False):
     """Compile liboracle.so with gcc (plain C99, -O2, no FMA contraction),
-    the reference build, and liboracle_omp.so, the same source with its
-    per-cell and per-edge loops spread over OpenMP threads (only for timing
-    the oracle on all host cores)."""
-    for path, extra in ((LIB_PATH, []), (OMP_LIB_PATH, ["-fopenmp"])):
+    the reference build; liboracle_omp.so, the same source with its per-cell
+    and per-edge loops spread over OpenMP threads (only for timing the
+    oracle on all host cores); and liboracle_fma.so, the same source with
+    fused multiply-adds, which rounds differently (only for measuring how
+    much a long chain amplifies rounding differences)."""
+    fp_off = ["-ffp-contract=off"]
+    for path, extra in ((LIB_PATH, fp_off), (OMP_LIB_PATH, fp_off + ["-fopenmp"]),
+                        (FMA_LIB_PATH, ["-mfma", "-ffp-contract=fast"])):
         if force or not os.path.exists(path) or \
                 os.path.getmtime(path) < os.path.getmtime(SRC_PATH):
-            cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", *extra, "-fPIC", "-shared",
+            cmd = ["gcc", "-O2", "-std=c99", *extra, "-fPIC", "-shared",
                    SRC_PATH, "-o", path + ".tmp", "-lm"]
             subprocess.check_call(cmd)
             os.replace(path + ".tmp", path)
