@@ -438,7 +438,48 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
   }
 
   // second ring: a candidate enters when its bisector crosses the polygon
-  // (a candidate further than twice the largest vertex distance cannot)
+  // (a candidate further than twice the largest vertex distance cannot).
+  // The cheap tests (distance, already a slot) run as the candidates are
+  // loaded; the survivors wait in a short queue and meet the polygon test
+  // in their order when the queue is full or the ring is done, so that the
+  // wave runs the costly test a few times per cell instead of once per
+  // candidate position (whichever lane of the wave needed it).  Candidates
+  // meet the test in the same order, against the same slots, as one by one.
+  constexpr int QN = 4;   // 2, 6 and 8 measured slower
+  double qx[QN], qy[QN];
+  int32_t qid[QN];
+  int qn = 0;
+  auto flush = [&]() {
+#pragma unroll
+    for (int p = 0; p < QN; ++p) {
+      if (p >= qn || bad) continue;
+      double tlo, thi;
+      bool bounded;
+      if (!bisector_part<WALLS>(S, wy0, wx1, wy2, wx3, vm, nv, -1, qx[p], qy[p], qid[p], tlo,
+                                thi, bounded))
+        continue;
+      // a new slot, else one whose bisector bounds nothing (it stays
+      // redundant as candidates are added)
+      int u = nv;
+      if (nv < NS) {
+        ++nv;
+      } else {
+        // (a mirror is never reused)
+        const uint32_t usable = ~em & ((1u << NS) - 1u) & ~((1u << BASE) - 1u);
+        if (usable == 0u) {
+          bad |= RICH_RETESS_FAN;
+          continue;
+        }
+        u = __ffs(usable) - 1;
+      }
+      S.x(u) = qx[p];
+      S.y(u) = qy[p];
+      S.n(u) = qid[p];
+      vm |= 1u << u;
+      em |= 1u << u;   // holds a cutting candidate now: not reusable
+    }
+    qn = 0;
+  };
   for (int k = k0; k < k1 && !bad; ++k) {
     const int j = prev_neighbour(a, k);
     if (j < 0 || j >= a.n || j == i) continue;
@@ -456,34 +497,26 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
         double dx, dy;
         const int32_t id = displacement(cc[m], ccx[m], ccy[m], dx, dy);
         if (4.0 * r2 <= dx * dx + dy * dy) continue;
+        // (over every slot, the loads issued together; vm marks the live ones)
         bool known = false;
-        for (int v = BASE; v < nv; ++v) known = known || (((vm >> v) & 1u) && S.n(v) == id);
+#pragma unroll
+        for (int v = BASE; v < NS; ++v) known = known || (v < nv && ((vm >> v) & 1u) && S.n(v) == id);
+#pragma unroll
+        for (int p = 0; p < QN; ++p) known = known || (p < qn && qid[p] == id);
         if (known) continue;
-        double tlo, thi;
-        bool bounded;
-        if (!bisector_part<WALLS>(S, wy0, wx1, wy2, wx3, vm, nv, -1, dx, dy, id, tlo, thi, bounded)) continue;
-        // a new slot, else one whose bisector bounds nothing (it stays
-        // redundant as candidates are added)
-        int u = nv;
-        if (nv < NS) {
-          ++nv;
-        } else {
-          // (a mirror is never reused)
-          const uint32_t usable = ~em & ((1u << NS) - 1u) & ~((1u << BASE) - 1u);
-          if (usable == 0u) {
-            bad |= RICH_RETESS_FAN;
-            break;
+#pragma unroll
+        for (int p = 0; p < QN; ++p) {
+          if (p == qn) {
+            qx[p] = dx;
+            qy[p] = dy;
+            qid[p] = id;
           }
-          u = __ffs(usable) - 1;
         }
-        S.x(u) = dx;
-        S.y(u) = dy;
-        S.n(u) = id;
-        vm |= 1u << u;
-        em |= 1u << u;   // holds a cutting candidate now: not reusable
+        if (++qn == QN) flush();
       }
     }
   }
+  if (!bad) flush();
 
   rich_cell cr;
   cr.px = xi;
