@@ -55,9 +55,13 @@ struct RunDesc {
   int32_t riemann, motion, limiter, integrator;
 };
 
-// Record layout (doubles): 0..3 rho, vx, vy, p; 4..11 limited gradients
-// (d/dx, d/dy of rho, vx, vy, p); 12..13 point velocity; 14..15 centroid.
-enum { R_RHO = 0, R_VX, R_VY, R_P, R_G = 4, R_WX = 12, R_WY, R_SX, R_SY };
+// Record layout (doubles): 0..3 rho, vx, vy, p of the limited linear
+// reconstruction evaluated at the cell's point (the cell averages moved from
+// the centroid s to the point r along the limited gradient, so that the value
+// at an edge midpoint f is rec + G (f - r)); 4..11 limited gradients (d/dx,
+// d/dy of rho, vx, vy, p); 12..13 point velocity; 14..15 the point itself.
+// The flux pass thus needs no mesh cell data.
+enum { R_RHO = 0, R_VX, R_VY, R_P, R_G = 4, R_WX = 12, R_WY, R_PX, R_PY };
 
 // ---------------------------------------------------------------------------
 // mesh records: 16-byte loads
@@ -106,15 +110,16 @@ __device__ __forceinline__ void load_cell(const RunDesc& d, int c, double& px, d
 // ---------------------------------------------------------------------------
 // mesh access
 // ---------------------------------------------------------------------------
+// Image shift of a ghost code: codes 1..4 are k = code - 1 and 5..8 are
+// k = code of the 3x3 grid of images, shifted by (k/3 - 1, k%3 - 1) box
+// lengths; code 0 and the wall codes have none.  Each code's two offsets are
+// read from 2-bit fields (offset + 1) of two constants instead of dividing.
 __device__ __forceinline__ void shift_of(const RunDesc& d, int code, double& shx,
                                          double& shy) {
-  shx = 0.0;
-  shy = 0.0;
-  if (code >= 1 && code <= 8) {
-    int k = code <= 4 ? code - 1 : code;
-    shx = (double)(k / 3 - 1) * d.Lx;
-    shy = (double)(k % 3 - 1) * d.Ly;
-  }
+  constexpr uint32_t kOffX = 0x5556a501u, kOffY = 0x55564891u;
+  const uint32_t sh = 2u * ((uint32_t)code & 15u);
+  shx = (double)((int)((kOffX >> sh) & 3u) - 1) * d.Lx;
+  shy = (double)((int)((kOffY >> sh) & 3u) - 1) * d.Ly;
 }
 
 // Both coordinates are always computed and selected, so that the compiler
@@ -472,18 +477,19 @@ __device__ __forceinline__ void load_rec(const double* __restrict__ rec, int c, 
   }
 }
 
-// The flux of edge e = (i, ej) with midpoint (fx, fy), length L; point r_i
-// and the records of both sides given (rj unused for a wall).  br, when not
-// null, receives the Riemann solver's branch record.
+// The flux of edge e = (i, ej) with midpoint (fx, fy), length L, from the
+// records of both sides (rj unused for a wall), which carry the points.  br,
+// when not null, receives the Riemann solver's branch record.
 template <int RIEMANN>
 __device__ inline bool edge_flux_at(const RunDesc& d, int i, uint32_t ej, double fx, double fy,
-                                    double L, double rix, double riy, const double* ri,
-                                    const double* rj_in, double* LF, uint8_t* br = nullptr) {
+                                    double L, const double* ri, const double* rj_in, double* LF,
+                                    uint8_t* br = nullptr) {
   bool ok = true;
   const int code = (int)(ej >> 28);
+  const double rix = ri[R_PX], riy = ri[R_PY];
   double phL[4], phR[4];
   {
-    const double dx = fx - ri[R_SX], dy = fy - ri[R_SY];
+    const double dx = fx - rix, dy = fy - riy;
 #pragma unroll
     for (int q = 0; q < 4; ++q) phL[q] = ri[q] + ri[R_G + 2 * q] * dx + ri[R_G + 2 * q + 1] * dy;
   }
@@ -508,13 +514,9 @@ __device__ inline bool edge_flux_at(const RunDesc& d, int i, uint32_t ej, double
     const double* rj = rj_in;
     double shx, shy;
     shift_of(d, code, shx, shy);
-    double rjx, rjy;
-    load_point(d, j, rjx, rjy);
-    rjx += shx;
-    rjy += shy;
-    const double sjx = rj[R_SX] + shx, sjy = rj[R_SY] + shy;
+    const double rjx = rj[R_PX] + shx, rjy = rj[R_PY] + shy;
     {
-      const double dx = fx - sjx, dy = fy - sjy;
+      const double dx = fx - rjx, dy = fy - rjy;
 #pragma unroll
       for (int q = 0; q < 4; ++q) phR[q] = rj[q] + rj[R_G + 2 * q] * dx + rj[R_G + 2 * q + 1] * dy;
     }
@@ -556,9 +558,7 @@ template <int RIEMANN>
 __device__ inline bool edge_flux(const RunDesc& d, int e, const double* ri, const double* rj_in,
                                  double* LF) {
   const EdgeRec er = load_edge(d, e);
-  double rix, riy;
-  load_point(d, er.i, rix, riy);
-  return edge_flux_at<RIEMANN>(d, er.i, er.j, er.fx, er.fy, er.L, rix, riy, ri, rj_in, LF);
+  return edge_flux_at<RIEMANN>(d, er.i, er.j, er.fx, er.fy, er.L, ri, rj_in, LF);
 }
 
 }  // namespace rich

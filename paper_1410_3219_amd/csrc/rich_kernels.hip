@@ -56,7 +56,10 @@ namespace rich {
 #define RICH_CELL_WAVES 1  // minimum waves per SIMD the register budget must allow
 #endif
 #ifndef RICH_FLUX_WAVES
-#define RICH_FLUX_WAVES 1
+// minimum waves per SIMD of the HLLC flux pass: four (a 128-register budget,
+// met without spills) hide its gathers better than three (2048^2 wave:
+// 477 -> 438 us); the exact solver's pass would spill at four
+#define RICH_FLUX_WAVES 4
 #endif
 #ifndef RICH_FLUX_TILE
 #define RICH_FLUX_TILE 256
@@ -234,25 +237,29 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
       }
     };
 
-    // A3: eq. (slope), r_ij = r_i - r_j; each term rounded before it is added
+    // A3: eq. (slope), r_ij = r_i - r_j
     double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double pmax[4] = {rho, vx, vy, p}, pmin[4] = {rho, vx, vy, p};
     int pflag = 0;
     constexpr int ME = MAXE + PRE;  // entries whose CSR entry and edge are loaded early
     double fdx[ME], fdy[ME];
+    // Per entry the weights L c_ij / |r_ij| and L r_ij / (2 |r_ij|) are
+    // formed once; each field then adds (phi_j - phi_i) times the first minus
+    // (phi_i + phi_j) times the second with two fused multiply-adds per
+    // component.
     auto accumulate = [&](const NbE& v, const double* pj, double vrx, double vry) {
       const double rx = rix - vrx, ry = riy - vry;
-      const double inv_r = rsqrt(rx * rx + ry * ry);
+      const double Lr = v.L * rsqrt(rx * rx + ry * ry);
       const double cx = v.fx - 0.5 * (rix + vrx), cy = v.fy - 0.5 * (riy + vry);
-      const double ux = cx * inv_r, uy = cy * inv_r, nx = rx * inv_r, ny = ry * inv_r;
+      const double ux = Lr * cx, uy = Lr * cy;
+      const double hLr = 0.5 * Lr;
+      const double nx = hLr * rx, ny = hLr * ry;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const double dphi = pj[q] - phi[q];
-        const double mean = 0.5 * (phi[q] + pj[q]);
-        const double tx = v.L * (dphi * ux - mean * nx);
-        const double ty = v.L * (dphi * uy - mean * ny);
-        g[2 * q] += tx;
-        g[2 * q + 1] += ty;
+        const double sum = phi[q] + pj[q];
+        g[2 * q] = fma(-sum, nx, fma(dphi, ux, g[2 * q]));
+        g[2 * q + 1] = fma(-sum, ny, fma(dphi, uy, g[2 * q + 1]));
         pmax[q] = dmax(pmax[q], pj[q]);
         pmin[q] = dmin(pmin[q], pj[q]);
       }
@@ -459,10 +466,16 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
         rec[R_VY] = vy + hh * vy_t;
         rec[R_P] = p + hh * p_t;
       }
+      {
+        // the reconstruction moved from the centroid to the point
+        const double ox = rix - six, oy = riy - siy;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rec[q] = rec[q] + rec[R_G + 2 * q] * ox + rec[R_G + 2 * q + 1] * oy;
+      }
       rec[R_WX] = wx;
       rec[R_WY] = wy;
-      rec[R_SX] = six;
-      rec[R_SY] = siy;
+      rec[R_PX] = rix;
+      rec[R_PY] = riy;
       constexpr int PER = kRecDoubles / LPC;  // doubles written by each lane
       double2* dst = reinterpret_cast<double2*>(d.rec + (size_t)i * kRecDoubles + lane * PER);
 #pragma unroll
@@ -530,9 +543,7 @@ __device__ __forceinline__ bool flux_of_edge(const RunDesc& d, int e, double* LF
     if (j >= d.n) j = i;
     load_rec(d.rec, j, rj);
   }
-  double rix, riy;
-  load_point(d, i, rix, riy);
-  return edge_flux_at<RIEMANN>(d, i, ej, er.fx, er.fy, er.L, rix, riy, ri, rj, LF, br);
+  return edge_flux_at<RIEMANN>(d, i, ej, er.fx, er.fy, er.L, ri, rj, LF, br);
 }
 
 // Debug record of the Riemann solver's branch on every edge (one thread per
@@ -548,7 +559,7 @@ __global__ __launch_bounds__(256) void k_edge_bits(RunDesc d, uint8_t* bits) {
 }
 
 template <int RIEMANN, bool BATCH, int TILE = kTile>
-__global__ __launch_bounds__(TILE, RICH_FLUX_WAVES) void k_flux(RunDesc one, const RunDesc* __restrict__ descs,
+__global__ __launch_bounds__(TILE, RIEMANN == 0 ? RICH_FLUX_WAVES : 1) void k_flux(RunDesc one, const RunDesc* __restrict__ descs,
                                                 const int2* __restrict__ tile_run,
                                                 int n_tiles) {
   // LDS capacities in proportion to the tile: fluxes of the owned edges
