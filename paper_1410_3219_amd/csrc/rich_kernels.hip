@@ -189,6 +189,7 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
   constexpr int CPB = kCellThreads / LPC;  // cells per block
   constexpr int MAXE = RICH_CELL_MAXE / LPC;  // entries per lane loaded level by level
   constexpr int PRE = RICH_CELL_PRE;
+  constexpr int ME = MAXE + PRE;  // entries whose CSR entry and edge are loaded early
   const int lane = (int)threadIdx.x % LPC;
   const int cl = (int)threadIdx.x / LPC;
   for (int b = blockIdx.x; b < n_tiles; b += gridDim.x) {
@@ -202,25 +203,36 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
 
     double rix, riy, A, six, siy;
     load_cell(d, i, rix, riy, A, six, siy);
-    if (active && !(A > 0.0 && A < INFINITY)) bad = true;  // a mesh cell without a volume
-    double rho, vx, vy, p;
-    prim_of(d, i, A, rho, vx, vy, p);
-    // A2 (section 6) and, fused into the cell pass, the cell's Courant ratio
-    // (A0), reduced to the block's minimum (each cell's lanes agree)
-    const Kin kin = kinematics(d, A, rho, vx, vy, p, rix, riy, six, siy);
-    const double c = kin.c, R = kin.R, wx = kin.wx, wy = kin.wy;
-    const bool rounded = kin.rounded;
-    if (d.cfl_blocks != nullptr) {
-      const double ti = active ? courant_ratio(kin, vx, vy) : INFINITY;
-      const double bm = block_min_cells(ti);
-      if (threadIdx.x == 0) d.cfl_blocks[tt] = bm;
-    }
-    const double phi[4] = {rho, vx, vy, p};
+    // The CSR range and the first entries go out with the cell's own loads
+    // (an inactive lane or a range outside the CSR gets no entries, and a
+    // bad range flags the run; an entry past the cell's end reads entry k0,
+    // in range, and is marked invalid).
     int k0 = d.off[i], k1 = d.off[i + 1];
     if (!active || k0 < 0 || k1 < k0 || k1 > d.n_csr) {
       if (active) bad = true;
       k1 = k0;
     }
+    bool val[ME];
+    int ent[ME];
+    {
+      const int kc = max(0, min(k0, d.n_csr - 1));
+#pragma unroll
+      for (int m = 0; m < ME; ++m) {
+        const int k = k0 + lane + m * LPC;
+        val[m] = k < k1;
+        ent[m] = d.idx[val[m] ? k : kc];
+      }
+    }
+    if (active && !(A > 0.0 && A < INFINITY)) bad = true;  // a mesh cell without a volume
+    double rho, vx, vy, p;
+    prim_of(d, i, A, rho, vx, vy, p);
+    // A2 (section 6) and, fused into the cell pass, the cell's Courant ratio
+    // (A0), reduced to the block's minimum at the end of the tile (each
+    // cell's lanes agree)
+    const Kin kin = kinematics(d, A, rho, vx, vy, p, rix, riy, six, siy);
+    const double c = kin.c, R = kin.R, wx = kin.wx, wy = kin.wy;
+    const bool rounded = kin.rounded;
+    const double phi[4] = {rho, vx, vy, p};
     // neighbour values and point across one CSR entry (mirror for a wall)
     auto nb_values = [&](const NbE& v, double* pj, double& rjx, double& rjy) {
       if (v.wall) {
@@ -241,7 +253,6 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
     double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double pmax[4] = {rho, vx, vy, p}, pmin[4] = {rho, vx, vy, p};
     int pflag = 0;
-    constexpr int ME = MAXE + PRE;  // entries whose CSR entry and edge are loaded early
     double fdx[ME], fdy[ME];
     // Per entry the weights L c_ij / |r_ij| and L r_ij / (2 |r_ij|) are
     // formed once; each field then adds (phi_j - phi_i) times the first minus
@@ -271,15 +282,6 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
     // past the cell's end reads entry k0 and is ignored), so that a lane waits
     // for three memory round trips instead of three per entry.
     {
-      const int kc = max(0, min(k0, d.n_csr - 1));
-      bool val[ME];
-      int ent[ME];
-#pragma unroll
-      for (int m = 0; m < ME; ++m) {
-        const int k = k0 + lane + m * LPC;
-        val[m] = k < k1;
-        ent[m] = d.idx[val[m] ? k : kc];
-      }
       int ee[ME];
 #pragma unroll
       for (int m = 0; m < ME; ++m) {
@@ -499,6 +501,11 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
           dbg[i] = (uint8_t)bits;
         }
       }
+    }
+    if (d.cfl_blocks != nullptr) {
+      const double ti = active ? courant_ratio(kin, vx, vy) : INFINITY;
+      const double bm = block_min_cells(ti);
+      if (threadIdx.x == 0) d.cfl_blocks[tt] = bm;
     }
   }
 }
@@ -1539,7 +1546,8 @@ int rich_area_rate(const rich_mesh* m, const rich_state* s, const rich_params* p
   const int n_ctiles = (d.n + CPB - 1) / CPB;
   // the cell pass writes the point velocities into the records
   hipLaunchKernelGGL(rich::k_clear, dim3(1), dim3(64), 0, st, d.flag, d.cfl_min);
-  hipLaunchKernelGGL((rich::k_cell<rich::kLpc, false>), dim3(n_ctiles), dim3(rich::kCellThreads),
+  hipLaunchKernelGGL((rich::k_cell<rich::kLpc, false>), dim3(n_ctiles),
+                     dim3(rich::kCellThreads),
                      0, st, d, (const RunDesc*)nullptr, (const int2*)nullptr, n_ctiles,
                      (uint8_t*)nullptr);
   hipLaunchKernelGGL(rich::k_adot, dim3((d.n + rich::kCflThreads - 1) / rich::kCflThreads),
