@@ -5,12 +5,14 @@
 // (section 2.2), the HLLC and exact Riemann solvers (section 2.4) in the frame
 // of the moving edge (section 1, section 5), and the lab-frame flux.
 //
-// Arithmetic is FP64 throughout, without fast-math: every division and
-// square root written as such is the correctly rounded IEEE operation.  The
-// inverse distances of the gradient terms and of the edge normals are
-// reciprocal square roots (rsqrt), which are accurate to a few units in the
-// last place but not correctly rounded; the oracle divides by a square root
-// there, and the difference stays at rounding level.  Floating-point
+// Arithmetic is FP64 throughout, without fast-math: every division written
+// with '/' and every sqrt is the correctly rounded IEEE operation.  The
+// divisions of the hot paths (rcp, ddiv below) are the hardware reciprocal
+// refined by Newton steps, within about an ulp of the quotient; the inverse
+// distances of the gradient terms, of the edge normals and of the rounding
+// correction are reciprocal square roots (rsqrt), accurate to a few units in
+// the last place.  The oracle divides correctly rounded there, and the
+// differences stay at rounding level.  Floating-point
 // contraction is per source expression (-ffp-contract=on), so every call of
 // these functions on the same inputs produces the same bits, wherever it is
 // inlined: a cell or an edge computed by two different tiles agrees bitwise.
@@ -287,10 +289,13 @@ __device__ __forceinline__ Kin kinematics(const RunDesc& d, double A, double rho
   if (d.motion) {
     k.wx = vx;
     k.wy = vy;
+    // |s - r| > eta R compared in squares; 1/|s - r| as one reciprocal
+    // square root
     const double dx = six - rix, dy = siy - riy;
-    const double dd = sqrt(dx * dx + dy * dy);
-    if (dd > d.eta * k.R) {
-      const double s = d.chi * k.c * rcp(dd);
+    const double dd2 = dx * dx + dy * dy;
+    const double er = d.eta * k.R;
+    if (dd2 > er * er) {
+      const double s = d.chi * k.c * rsqrt(dd2);
       k.wx += s * dx;
       k.wy += s * dy;
       k.rounded = true;

@@ -390,7 +390,7 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
       pmin[q] = group_min<LPC>(pmin[q]);
     }
     bool shock = group_or<LPC>(pflag) != 0;
-    if (-(G[2] + G[5]) > ddiv(d.delta_v * c, R)) shock = true;
+    if (-(G[2] + G[5]) * R > d.delta_v * c) shock = true;  // -div v > delta_v c / R, R > 0
 
     // A4: limiter
     double alpha[4] = {1.0, 1.0, 1.0, 1.0};
@@ -418,12 +418,19 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
         const NbE v = nb_edge(d, i, d.idx[k], bad);
         bound(v.fx - six, v.fy - siy);
       }
+      // alpha = min(1, (phi_max - phi)/dmax, (phi_min - phi)/dmin) over the
+      // bounds that apply (dmax > 0, dmin < 0): both ratios are >= 0, the
+      // smaller one is picked by cross-multiplication and only it is divided
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         dmax[q] = group_max<LPC>(dmax[q]);
         dmin[q] = group_min<LPC>(dmin[q]);
-        if (dmax[q] > 0.0) alpha[q] = rich::dmin(alpha[q], ddiv(pmax[q] - phi[q], dmax[q]));
-        if (dmin[q] < 0.0) alpha[q] = rich::dmin(alpha[q], ddiv(pmin[q] - phi[q], dmin[q]));
+        const bool ua = dmax[q] > 0.0, ub = dmin[q] < 0.0;
+        const double na = pmax[q] - phi[q], da = dmax[q];
+        const double nb = phi[q] - pmin[q], db = -dmin[q];
+        const bool pick_a = ua && (!ub || na * db < nb * da);
+        const double r = ddiv(pick_a ? na : nb, pick_a ? da : db);
+        if (ua || ub) alpha[q] = rich::dmin(alpha[q], r);
       }
     } else if (local == 1) {
       for (int k = k0 + lane; k < k1; k += LPC) {
