@@ -164,15 +164,18 @@ __device__ __forceinline__ int group_or(int v) {
   return v;
 }
 
-// Minimum over the block of the cell kernel (kCellThreads lanes).
+// Minimum over the block of the cell kernel (kCellThreads lanes, whose
+// groups of LPC lanes hold equal values), of values that are never NaN.
+template <int LPC>
 __device__ __forceinline__ double block_min_cells(double t) {
   __shared__ double sm[kCellThreads / 64];
-  for (int o = 32; o > 0; o >>= 1) t = fmin(t, __shfl_xor(t, o));
+#pragma unroll
+  for (int o = 32; o >= LPC; o >>= 1) t = dmin(t, __shfl_xor(t, o));
   if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = t;
   __syncthreads();
   double m = sm[0];
 #pragma unroll
-  for (int w = 1; w < kCellThreads / 64; ++w) m = fmin(m, sm[w]);
+  for (int w = 1; w < kCellThreads / 64; ++w) m = dmin(m, sm[w]);
   __syncthreads();
   return m;
 }
@@ -452,16 +455,14 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
     const int bad_any = group_or<LPC>(bad ? 1 : 0);
     if (active) {
       double rec[kRecDoubles];
-      rec[R_RHO] = rho;
-      rec[R_VX] = vx;
-      rec[R_VY] = vy;
-      rec[R_P] = p;
 #pragma unroll
       for (int q = 0; q < 8; ++q) rec[R_G + q] = G[q] * alpha[q / 2];
+      // the change of the stored primitives: with extrapolated fluxes
+      // (section 2.3) they are advanced half a step with the time derivatives
+      // the limited gradients give in the primitive Euler equations,
+      // following the cell's point (v - w); otherwise none
+      double adv[4] = {0.0, 0.0, 0.0, 0.0};
       if (d.integrator == 1) {
-        // extrapolated fluxes (section 2.3): the primitives advanced half a
-        // step with the time derivatives the limited gradients give in the
-        // primitive Euler equations, following the cell's point (v - w)
         const double* g = rec + R_G;
         const double ux = vx - wx, uy = vy - wy;
         const double div = g[2] + g[5];
@@ -470,16 +471,17 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
         const double vy_t = -(ux * g[4] + uy * g[5]) - g[7] / rho;
         const double p_t = -(ux * g[6] + uy * g[7]) - d.gamma * p * div;
         const double hh = 0.5 * (d.h_dev != nullptr ? d.h_factor * (*d.h_dev) : d.h);
-        rec[R_RHO] = rho + hh * rho_t;
-        rec[R_VX] = vx + hh * vx_t;
-        rec[R_VY] = vy + hh * vy_t;
-        rec[R_P] = p + hh * p_t;
+        adv[0] = hh * rho_t;
+        adv[1] = hh * vx_t;
+        adv[2] = hh * vy_t;
+        adv[3] = hh * p_t;
       }
       {
         // the reconstruction moved from the centroid to the point
         const double ox = rix - six, oy = riy - siy;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) rec[q] = rec[q] + rec[R_G + 2 * q] * ox + rec[R_G + 2 * q + 1] * oy;
+        for (int q = 0; q < 4; ++q)
+          rec[q] = (phi[q] + adv[q]) + rec[R_G + 2 * q] * ox + rec[R_G + 2 * q + 1] * oy;
       }
       rec[R_WX] = wx;
       rec[R_WY] = wy;
@@ -511,7 +513,7 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
     }
     if (d.cfl_blocks != nullptr) {
       const double ti = active ? courant_ratio(kin, vx, vy) : INFINITY;
-      const double bm = block_min_cells(ti);
+      const double bm = block_min_cells<LPC>(ti);
       if (threadIdx.x == 0) d.cfl_blocks[tt] = bm;
     }
   }
