@@ -50,6 +50,7 @@ constexpr int kSlotsLds = 12;  // candidate slots of a cell in LDS: neighbours a
 constexpr int kRingMax = 64;   // CSR entries read per cell of the previous mesh
 constexpr int kThreads = 64;
 constexpr int kScanThreads = 1024;
+static_assert(kScanThreads % kThreads == 0, "a scan block covers whole cell blocks");
 constexpr double kPi = 3.14159265358979323846;
 // neighbour codes of the reflecting walls x = x0, x = x1, y = y0, y = y1 in
 // the top bits of rich_edge.j (the neighbour is the cell's own mirror image)
@@ -63,6 +64,15 @@ struct Hdr {  // first 64 bytes of the workspace
   int64_t pad[2];
 };
 static_assert(sizeof(Hdr) == 64, "result header");
+
+// One classify block's sums: area of its cells, dropped edge slots, kept
+// wall edges.  Written per block and reduced in a fixed order by the scan,
+// rather than added into the header with atomics (every block's atomics on
+// one header line serialised the kernel).
+struct CPart {
+  double area;
+  long long drop, walls, pad;
+};
 
 struct Args {
   // previous mesh (candidates)
@@ -85,6 +95,7 @@ struct Args {
   uint8_t* s_back;     // [n][kMaxFan] owned edge: its slot in the neighbour's row
   int32_t* s_edge;     // [n][kMaxFan] kept, not owned: the owner's edge index
   int64_t* bsum;       // [2][n_scan_blocks] block totals of kept / owned
+  CPart* cpart;        // [cell blocks] classify block sums, reduced by the scan
   // geometry
   double x0, y0, x1, y1, Lx, Ly;
   int32_t n, bc, n_scan_blocks;
@@ -719,16 +730,17 @@ __global__ __launch_bounds__(kGroupThreads) void k_rt_classify(Args one, Batch b
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t = 0.0;
-    long long u = 0, v = 0;
+    CPart c;
+    c.area = 0.0;
+    c.drop = 0;
+    c.walls = 0;
+    c.pad = 0;
     for (int w = 0; w < NW; ++w) {
-      t += s_area[w];
-      u += s_drop[w];
-      v += s_wall[w];
+      c.area += s_area[w];
+      c.drop += s_drop[w];
+      c.walls += s_wall[w];
     }
-    atomicAdd(&a.hdr->area_sum, t);
-    atomicAdd((unsigned long long*)&a.hdr->n_dropped, (unsigned long long)u);
-    if (v) atomicAdd((unsigned long long*)&a.hdr->n_wall, (unsigned long long)v);
+    a.cpart[blk] = c;
   }
 }
 
@@ -779,6 +791,20 @@ __global__ __launch_bounds__(kScanThreads) void k_rt_scan_local(Args one, Batch 
     a.bsum[blk] = t0;
     a.bsum[a.n_scan_blocks + blk] = t1;
   }
+  // the sums of the classify blocks of this block's cells, in order, into
+  // the first of them (the scan of the block totals reads only those)
+  constexpr int CPB = kScanThreads / kThreads;
+  const int nc = (a.n + kThreads - 1) / kThreads;
+  if (threadIdx.x == 0) {
+    CPart c = a.cpart[blk * CPB];
+    for (int t = 1; t < CPB && blk * CPB + t < nc; ++t) {
+      const CPart p = a.cpart[blk * CPB + t];
+      c.area += p.area;
+      c.drop += p.drop;
+      c.walls += p.walls;
+    }
+    a.cpart[blk * CPB] = c;
+  }
 }
 
 // one block: exclusive scan of the block totals, totals and the checks that
@@ -787,6 +813,35 @@ template <bool B>
 __global__ __launch_bounds__(kScanThreads) void k_rt_scan_blocks(Args one, Batch bt) {
   const Args& a = B ? bt.descs[blockIdx.x] : one;
   __shared__ long long s0[kScanThreads], s1[kScanThreads];
+  constexpr int NW = kScanThreads / 64;
+  __shared__ double s_area[NW];
+  __shared__ long long s_drop[NW], s_wall[NW];
+  // the classify blocks' sums (those of each scan block gathered by
+  // k_rt_scan_local): each thread every kScanThreads-th scan block, a fixed
+  // xor tree over each wave, then thread 0 over the waves in order (a fixed
+  // order throughout, so the area sum is reproducible)
+  const int nb_scan = a.n_scan_blocks;
+  {
+    constexpr int CPB = kScanThreads / kThreads;   // classify blocks per scan block
+    double ar = 0.0;
+    long long dr = 0, wl = 0;
+    for (int c = threadIdx.x; c < nb_scan; c += kScanThreads) {
+      const CPart p = a.cpart[c * CPB];
+      ar += p.area;
+      dr += p.drop;
+      wl += p.walls;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      ar += __shfl_xor(ar, o);
+      dr += __shfl_xor(dr, o);
+      wl += __shfl_xor(wl, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      s_area[threadIdx.x >> 6] = ar;
+      s_drop[threadIdx.x >> 6] = dr;
+      s_wall[threadIdx.x >> 6] = wl;
+    }
+  }
   const int nb = a.n_scan_blocks;
   const int per = (nb + kScanThreads - 1) / kScanThreads;
   const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
@@ -798,6 +853,18 @@ __global__ __launch_bounds__(kScanThreads) void k_rt_scan_blocks(Args one, Batch
   s0[threadIdx.x] = c0;
   s1[threadIdx.x] = c1;
   __syncthreads();
+  if (threadIdx.x == 0) {
+    double ar = 0.0;
+    long long dr = 0, wl = 0;
+    for (int w = 0; w < NW; ++w) {
+      ar += s_area[w];
+      dr += s_drop[w];
+      wl += s_wall[w];
+    }
+    a.hdr->area_sum = ar;
+    a.hdr->n_dropped = dr;
+    a.hdr->n_wall = wl;
+  }
   // serial over the 1024 chunk sums by one thread: 1024 additions
   if (threadIdx.x == 0) {
     long long r0 = 0, r1 = 0;
@@ -930,7 +997,7 @@ namespace {
 size_t rt_align(size_t v) { return (v + 255) / 256 * 256; }
 
 struct RtLayout {
-  size_t deg, s_nb, s_geo, s_flag, s_back, s_edge, bsum, total;
+  size_t deg, s_nb, s_geo, s_flag, s_back, s_edge, bsum, cpart, total;
   int nb;
 };
 
@@ -946,6 +1013,8 @@ RtLayout rt_layout(int64_t n) {
   L.s_back = o; o += rt_align(slots);
   L.s_edge = o; o += rt_align(4 * slots);
   L.bsum = o;   o += rt_align(16 * (size_t)L.nb);
+  L.cpart = o;
+  o += rt_align(sizeof(retess::CPart) * (size_t)((n + retess::kThreads - 1) / retess::kThreads));
   L.total = o;
   return L;
 }
@@ -1005,6 +1074,7 @@ int make_args(const rich_mesh* prev, const double* x, const double* y,
   a.s_back = reinterpret_cast<uint8_t*>(w + L.s_back);
   a.s_edge = reinterpret_cast<int32_t*>(w + L.s_edge);
   a.bsum = reinterpret_cast<int64_t*>(w + L.bsum);
+  a.cpart = reinterpret_cast<retess::CPart*>(w + L.cpart);
   a.x0 = prev->box[0];
   a.y0 = prev->box[1];
   a.x1 = prev->box[2];
