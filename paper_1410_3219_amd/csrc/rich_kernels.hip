@@ -176,9 +176,7 @@ __device__ __forceinline__ double dpp_of(double v) {
 // values) of values that are never NaN, held by lane 63, with DPP moves
 // only: quads (quad permutations), eights (half-row mirror), rows (row
 // mirror), then each row's last lane broadcast into the next row and lane 31
-// into the upper half.  The cell pass writes one such minimum per wave, so
-// that no barrier holds the block's waves together.
-constexpr int kCflPerTile = kCellThreads / 64;  // Courant minima per cell tile
+// into the upper half.
 template <int LPC>
 __device__ __forceinline__ double wave_min_cells(double t) {
   if constexpr (LPC < 2) t = dmin(t, dpp_of<0xB1>(t));  // quad_perm [1,0,3,2]
@@ -188,6 +186,21 @@ __device__ __forceinline__ double wave_min_cells(double t) {
   t = dmin(t, dpp_of<0x142, 0xA>(t));                    // row_bcast:15 into rows 1, 3
   t = dmin(t, dpp_of<0x143, 0xC>(t));                    // row_bcast:31 into rows 2, 3
   return t;
+}
+// Minimum over the block of the cell pass: the waves' minima through LDS,
+// one barrier, valid in thread 0.  (One minimum per wave instead, with no
+// barrier, was no faster, and the final reduction then reads four times as
+// many minima.)
+template <int LPC>
+__device__ __forceinline__ double block_min_cells(double t) {
+  __shared__ double sm[kCellThreads / 64];
+  t = wave_min_cells<LPC>(t);
+  if ((threadIdx.x & 63) == 63) sm[threadIdx.x >> 6] = t;
+  __syncthreads();
+  double m = sm[0];
+#pragma unroll
+  for (int w = 1; w < kCellThreads / 64; ++w) m = dmin(m, sm[w]);
+  return m;
 }
 
 // DBG: also write each cell's branch record to dbg[i]: bit 0 the shock
@@ -523,8 +536,8 @@ __global__ __launch_bounds__(kCellThreads, RICH_CELL_WAVES) void k_cell(RunDesc 
     }
     if (d.cfl_blocks != nullptr) {
       const double ti = active ? courant_ratio(kin, vx, vy) : INFINITY;
-      const double wm = wave_min_cells<LPC>(ti);
-      if ((threadIdx.x & 63) == 63) d.cfl_blocks[tt * kCflPerTile + (threadIdx.x >> 6)] = wm;
+      const double bm = block_min_cells<LPC>(ti);
+      if (threadIdx.x == 0) d.cfl_blocks[tt] = bm;
     }
   }
 }
@@ -851,8 +864,8 @@ __global__ __launch_bounds__(kCflFinalThreads) void k_cfl_final(const double* bl
   cfl_finish<kCflFinalThreads>(block_in, nb, out, cfl, dt_out, flag);
 }
 
-// Batched Courant stage: block k finishes run k of the cell plan (the wave
-// minima of cell tiles tile_start[k] .. tile_start[k + 1] - 1 of the batch, which
+// Batched Courant stage: block k finishes run k of the cell plan (entries
+// tile_start[k] .. tile_start[k + 1] - 1 of the batch's block minima, which
 // every descriptor's cfl_blocks points to, are its cell tiles) and writes
 // the run's step where its descriptor's h_dev points.
 __global__ __launch_bounds__(kCflBatchThreads) void k_cfl_final_batch(
@@ -865,9 +878,8 @@ __global__ __launch_bounds__(kCflBatchThreads) void k_cfl_final_batch(
     if (threadIdx.x == 0) atomicOr(d.flag, RICH_FLAG_DOMAIN);
     return;
   }
-  const int t0 = tile_start[k] * kCflPerTile;
-  cfl_finish<kCflBatchThreads>(d.cfl_blocks + t0, tile_start[k + 1] * kCflPerTile - t0,
-                               d.cfl_min, d.cfl,
+  const int t0 = tile_start[k];
+  cfl_finish<kCflBatchThreads>(d.cfl_blocks + t0, tile_start[k + 1] - t0, d.cfl_min, d.cfl,
                                const_cast<double*>(d.h_dev), d.flag);
 }
 
@@ -889,8 +901,7 @@ constexpr size_t kDtOffset = 16;  // header: flag @0, Courant minimum @8, dt @16
 
 constexpr size_t run_ws_size(int64_t n) {
   return rich::kHeader + ((size_t)n * rich::kRecDoubles * sizeof(double) + 255) / 256 * 256 +
-         ((size_t)((n + kCellsPerBlock - 1) / kCellsPerBlock) * rich::kCflPerTile *
-              sizeof(double) + 255) / 256 * 256;
+         ((size_t)((n + kCellsPerBlock - 1) / kCellsPerBlock) * sizeof(double) + 255) / 256 * 256;
 }
 size_t run_ws_bytes(int64_t n) { return run_ws_size(n); }
 
@@ -1020,7 +1031,7 @@ int launch_stage(const RunDesc& d, int riemann, hipStream_t st, uint8_t* dbg_cel
   }
   if (d.cfl_blocks != nullptr)   // dt from the cell kernel's Courant minima
     hipLaunchKernelGGL(rich::k_cfl_final, dim3(1), dim3(rich::kCflFinalThreads), 0, st,
-                       (const double*)d.cfl_blocks, n_ctiles * rich::kCflPerTile, d.cfl_min, d.cfl,
+                       (const double*)d.cfl_blocks, n_ctiles, d.cfl_min, d.cfl,
                        const_cast<double*>(d.h_dev), d.flag);
   int pf = prof_begin("k_flux", st);
   if (riemann == 1)
@@ -1037,7 +1048,7 @@ int launch_stage(const RunDesc& d, int riemann, hipStream_t st, uint8_t* dbg_cel
 
 // ---------------------------------------------------------------------------
 // batch workspace:  [descriptors][plans][flags][Courant minima][steps]
-//                   [records...][Courant wave minima][tile -> run tables]
+//                   [records...][Courant block minima][tile -> run tables]
 // Everything before the records depends on the number of runs only.
 // ---------------------------------------------------------------------------
 struct BatchLayout {
@@ -1069,7 +1080,7 @@ BatchLayout batch_layout(int32_t n, const int64_t* n_cells) {
     flux_tiles += (size_t)((n_cells[r] + 127) / 128);
   }
   L.cflb = o;
-  o += align_up(tiles * rich::kCflPerTile * sizeof(double), 256);
+  o += align_up(tiles * sizeof(double), 256);
   // tile -> run tables: cell tiles, then the flux tiles of the two solver
   // groups (which partition the runs)
   L.tab = o;
