@@ -230,8 +230,11 @@ __device__ __forceinline__ bool bisector_part(const Slots<WALLS ? 4 : 0>& S, dou
                                               bool& bounded) {
   const double mux = 0.5 * dux, muy = 0.5 * duy;
   const double eux = -duy, euy = dux;
-  double ln = 0.0, ld = 1.0, hn = 0.0, hd = 1.0;
-  bool has_lo = false, has_hi = false, empty = false;
+  // No bound yet is hn / hd = +inf and ln / ld = -inf: the first finite
+  // bound of each side then wins its comparison (b and a are finite), so
+  // no flag tracks whether a side is bounded.
+  double ln = -INFINITY, ld = 1.0, hn = INFINITY, hd = 1.0;
+  bool empty = false;
   // straight-line bodies (selects, no branches); the mirrors' constraints
   auto cut = [&](double dvx, double dvy, bool act) {
     const double a0 = eux * dvx + euy * dvy;
@@ -239,14 +242,12 @@ __device__ __forceinline__ bool bisector_part(const Slots<WALLS ? 4 : 0>& S, dou
     const double a = act ? a0 : 0.0;
     const double b = act ? b0 : 1.0;
     // a > 0: t <= b / a;  a < 0: t >= (-b) / (-a);  a = 0, b < 0: no t
-    const bool up = a > 0.0 && (!has_hi || b * hd < hn * a);
+    const bool up = a > 0.0 && b * hd < hn * a;
     hn = up ? b : hn;
     hd = up ? a : hd;
-    has_hi = has_hi || up;
-    const bool dn = a < 0.0 && (!has_lo || -b * ld > ln * -a);
+    const bool dn = a < 0.0 && -b * ld > ln * -a;
     ln = dn ? -b : ln;
     ld = dn ? -a : ld;
-    has_lo = has_lo || dn;
     empty = empty || (a == 0.0 && b < 0.0);
   };
   constexpr int BASE = WALLS ? 4 : 0;
@@ -269,17 +270,15 @@ __device__ __forceinline__ bool bisector_part(const Slots<WALLS ? 4 : 0>& S, dou
     const double a = act ? a0 : 0.0;
     const double b = act ? b0 : 1.0;
     // a > 0: t <= b / a;  a < 0: t >= (-b) / (-a);  a = 0, b < 0: no t
-    const bool up = a > 0.0 && (!has_hi || b * hd < hn * a);
+    const bool up = a > 0.0 && b * hd < hn * a;
     hn = up ? b : hn;
     hd = up ? a : hd;
-    has_hi = has_hi || up;
-    const bool dn = a < 0.0 && (!has_lo || -b * ld > ln * -a);
+    const bool dn = a < 0.0 && -b * ld > ln * -a;
     ln = dn ? -b : ln;
     ld = dn ? -a : ld;
-    has_lo = has_lo || dn;
     empty = empty || (a == 0.0 && b < 0.0);
   }
-  bounded = has_lo && has_hi;
+  bounded = ln != -INFINITY && hn != INFINITY;
   if (empty || !bounded || !(ln * hd < hn * ld)) return false;
   tlo = ln / ld;
   thi = hn / hd;
