@@ -28,8 +28,7 @@
 //   k_rt_classify keep / own each slot by the input stage's rules, check
 //                 each kept edge against the neighbour's slot, count
 //   k_rt_scan_*   prefix sums of the counts into off[] and eoff[]
-//   k_rt_emit     edge records (each also told to the neighbour's slot)
-//   k_rt_emit_csr CSR entries
+//   k_rt_emit     edge records and the CSR entries of both sides of each edge
 //   k_rt_end      fold the flags into the sticky word
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -93,7 +92,6 @@ struct Args {
   double* s_geo;       // [n][kMaxFan][3] edge length, midpoint x, midpoint y
   uint8_t* s_flag;     // [n][kMaxFan] bit 0 kept, bit 1 owned
   uint8_t* s_back;     // [n][kMaxFan] owned edge: its slot in the neighbour's row
-  int32_t* s_edge;     // [n][kMaxFan] kept, not owned: the owner's edge index
   int64_t* bsum;       // [2][n_scan_blocks] block totals of kept / owned
   CPart* cpart;        // [cell blocks] classify block sums, reduced by the scan
   // geometry
@@ -913,50 +911,35 @@ __global__ __launch_bounds__(kScanThreads) void k_rt_scan_add(Args one, Batch bt
 // ---------------------------------------------------------------------------
 // edge records and CSR entries
 // ---------------------------------------------------------------------------
+// Kept-slot bits of a row of kMaxFan flag bytes (bit t for slot t), read as
+// 4-byte words: each word's four bit-0s gathered by one multiplication.
+__device__ __forceinline__ uint32_t kept_bits(const uint8_t* row) {
+  static_assert(kMaxFan % 4 == 0, "rows of whole words");
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(row);
+  uint32_t m = 0u;
+#pragma unroll
+  for (int k = 0; k < kMaxFan / 4; ++k)
+    m |= (((w[k] & 0x01010101u) * 0x01020408u) >> 24) << (4 * k);
+  return m;
+}
+
+// Each cell writes, for every edge it owns (its owned slots in slot order
+// from eoff[i]): the edge record, its own CSR entry 2 e at the slot's rank
+// among its kept slots, and, unless the edge is a wall, the neighbour's entry
+// 2 e + 1 at the rank among the neighbour's kept slots of the slot that sees
+// the edge.  A certified mesh has every kept slot the owned or the other side
+// of exactly one owned edge (classify matched each owned edge to one slot of
+// the neighbour, and kept = 2 owned - walls), so each CSR entry is written
+// once, and each cell's entries run counter-clockwise (slot order).  A
+// failed re-tessellation leaves a mesh without edges.
 template <bool B>
 __global__ __launch_bounds__(kGroupThreads) void k_rt_emit(Args one, Batch bt) {
   int blk;
   const Args& a = block_run<B>(one, bt.cstart, bt, blk);
   const int l = (int)threadIdx.x % kGroup;
   const int i = blk * kThreads + (int)threadIdx.x / kGroup;
-  if (i >= a.n || a.hdr->flags != 0) return;  // whole groups
-  // the cell's owned edges, in slot order from eoff[i], and each one's index
-  // into the slot that sees it from the neighbour's side
-  const int d = a.deg[i];
-  const size_t s0 = (size_t)i * kMaxFan;
-  int e = a.eoff[i];
-  for (int base = 0; base < d; base += kGroup) {
-    const int q = base + l;
-    const bool owned = q < d && (a.s_flag[s0 + q] & 3) == 3;
-    const uint32_t gm = group_bits(owned);
-    if (owned) {
-      const int ee = e + __popc(gm & ((1u << l) - 1u));
-      const int32_t id = a.s_nb[s0 + q];
-      const double* g = a.s_geo + 3 * (s0 + q);
-      rich_edge r;
-      r.fx = g[1];
-      r.fy = g[2];
-      r.len = g[0];
-      r.i = i;
-      r.j = id;
-      a.edges[ee] = r;
-      if ((int)((uint32_t)id >> kShift) < kWallX0) {
-        const int j = (int)((uint32_t)id & kMask);
-        a.s_edge[(size_t)j * kMaxFan + a.s_back[s0 + q]] = ee;
-      }
-    }
-    e += __popc(gm);
-  }
-}
-
-template <bool B>
-__global__ __launch_bounds__(kGroupThreads) void k_rt_emit_csr(Args one, Batch bt) {
-  int blk;
-  const Args& a = block_run<B>(one, bt.cstart, bt, blk);
-  const int l = (int)threadIdx.x % kGroup;
-  const int i = blk * kThreads + (int)threadIdx.x / kGroup;
   if (i >= a.n) return;  // whole groups
-  if (a.hdr->flags != 0) {  // failed: leave a mesh without edges
+  if (a.hdr->flags != 0) {
     if (l == 0) {
       a.off[i + 1] = 0;
       a.eoff[i + 1] = 0;
@@ -967,8 +950,6 @@ __global__ __launch_bounds__(kGroupThreads) void k_rt_emit_csr(Args one, Batch b
     }
     return;
   }
-  // the cell's CSR entries, counter-clockwise (slot order): 2 * edge for its
-  // own edges, 2 * edge + 1 for its neighbours'
   const int d = a.deg[i];
   const size_t s0 = (size_t)i * kMaxFan;
   int k = a.off[i], e = a.eoff[i];
@@ -976,11 +957,27 @@ __global__ __launch_bounds__(kGroupThreads) void k_rt_emit_csr(Args one, Batch b
     const int q = base + l;
     const uint8_t f = q < d ? a.s_flag[s0 + q] : (uint8_t)0;
     const uint32_t mk = group_bits((f & 1) != 0);
-    const uint32_t mo = group_bits((f & 2) != 0);
+    const uint32_t mo = group_bits((f & 3) == 3);
     const uint32_t below = (1u << l) - 1u;
-    if (f & 1)
-      a.idx[k + __popc(mk & below)] =
-          (f & 2) ? 2 * (e + __popc(mo & below)) : 2 * a.s_edge[s0 + q] + 1;
+    if ((f & 3) == 3) {
+      const int ee = e + __popc(mo & below);
+      const int32_t id = a.s_nb[s0 + q];
+      const double* g = a.s_geo + 3 * (s0 + q);
+      rich_edge r;
+      r.fx = g[1];
+      r.fy = g[2];
+      r.len = g[0];
+      r.i = i;
+      r.j = id;
+      a.edges[ee] = r;
+      a.idx[k + __popc(mk & below)] = 2 * ee;
+      if ((int)((uint32_t)id >> kShift) < kWallX0) {
+        const int j = (int)((uint32_t)id & kMask);
+        const int t = a.s_back[s0 + q];
+        const uint32_t kj = kept_bits(a.s_flag + (size_t)j * kMaxFan);
+        a.idx[a.off[j] + __popc(kj & ((1u << t) - 1u))] = 2 * ee + 1;
+      }
+    }
     k += __popc(mk);
     e += __popc(mo);
   }
@@ -996,7 +993,7 @@ namespace {
 size_t rt_align(size_t v) { return (v + 255) / 256 * 256; }
 
 struct RtLayout {
-  size_t deg, s_nb, s_geo, s_flag, s_back, s_edge, bsum, cpart, total;
+  size_t deg, s_nb, s_geo, s_flag, s_back, bsum, cpart, total;
   int nb;
 };
 
@@ -1010,7 +1007,6 @@ RtLayout rt_layout(int64_t n) {
   L.s_geo = o;  o += rt_align(24 * slots);
   L.s_flag = o; o += rt_align(slots);
   L.s_back = o; o += rt_align(slots);
-  L.s_edge = o; o += rt_align(4 * slots);
   L.bsum = o;   o += rt_align(16 * (size_t)L.nb);
   L.cpart = o;
   o += rt_align(sizeof(retess::CPart) * (size_t)((n + retess::kThreads - 1) / retess::kThreads));
@@ -1071,7 +1067,6 @@ int make_args(const rich_mesh* prev, const double* x, const double* y,
   a.s_geo = reinterpret_cast<double*>(w + L.s_geo);
   a.s_flag = reinterpret_cast<uint8_t*>(w + L.s_flag);
   a.s_back = reinterpret_cast<uint8_t*>(w + L.s_back);
-  a.s_edge = reinterpret_cast<int32_t*>(w + L.s_edge);
   a.bsum = reinterpret_cast<int64_t*>(w + L.bsum);
   a.cpart = reinterpret_cast<retess::CPart*>(w + L.cpart);
   a.x0 = prev->box[0];
@@ -1086,7 +1081,7 @@ int make_args(const rich_mesh* prev, const double* x, const double* y,
   return RICH_OK;
 }
 
-// The nine launches of one re-tessellation (B: of n_runs runs at once, with
+// The eight launches of one re-tessellation (B: of n_runs runs at once, with
 // gc cell blocks and gs scan blocks in all).
 template <bool B>
 void launch_all(const retess::Args& a, const retess::Batch& bt, int gc, int gs, int n_runs,
@@ -1102,7 +1097,6 @@ void launch_all(const retess::Args& a, const retess::Batch& bt, int gc, int gs, 
   hipLaunchKernelGGL(k_rt_scan_blocks<B>, dim3(n_runs), dim3(kScanThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_scan_add<B>, dim3(gs), dim3(kScanThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_emit<B>, dim3(gc), dim3(kGroupThreads), 0, st, a, bt);
-  hipLaunchKernelGGL(k_rt_emit_csr<B>, dim3(gc), dim3(kGroupThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_end<B>, dim3(n_runs), dim3(64), 0, st, a.hdr, bt);
 }
 
