@@ -201,6 +201,41 @@ def test_retess_repeat_is_bitwise_deterministic():
     assert np.array_equal(outs[0]["idx"][:nc].numpy(), outs[1]["idx"][:nc].numpy())
 
 
+@pytest.mark.parametrize("name,k", [("wave", 100), ("sod", 90)])
+def test_retess_sums_reproducible_over_many_blocks(name, k):
+    """The result header's area sum and dropped-edge count come from per-block
+    sums reduced in a fixed order (over several scan blocks of 1024 cells
+    here): two calls give the same bits, the area sum equals the box area and
+    the cells' own areas summed on the host to rounding, and the kept CSR
+    entries are twice the edges less the wall edges."""
+    from paper_1410_3219_amd import rich as R
+    P, m, Q, X = _initial(name, k)
+    assert m.n_cells > 4 * 1024
+    dm = R.DeviceMesh.from_host(m)
+    p = R.Params(gamma=P.gamma)
+    s, half = _half_step_points(R, dm, Q, X, p)
+    infos, areas = [], []
+    for _ in range(2):
+        bufs = R.DeviceMeshBufs(m.n_cells, m.box, m.bc)
+        tws = R.retess_workspace(m.n_cells)
+        R.rich_retess(dm, half.X, bufs, tws)
+        st, info = R.rich_retess_result(tws)
+        assert st == 0, info
+        infos.append(info)
+        cells = bufs.t["cells"].cpu().numpy().view(np.float64).reshape(-1, 6)
+        areas.append(cells[:, 2].copy())
+    assert infos[0] == infos[1]
+    assert np.array_equal(areas[0], areas[1])
+    box = (m.box[2] - m.box[0]) * (m.box[3] - m.box[1])
+    a_host = float(np.sum(areas[0]))
+    assert abs(infos[0]["area_sum"] - a_host) <= 1e-13 * box, (infos[0]["area_sum"], a_host)
+    assert abs(infos[0]["area_sum"] - box) <= 1e-10 * box
+    edges = bufs.t["edges"][: R.EDGE_BYTES * infos[0]["n_edges"]].cpu().numpy()
+    codes = edges.view(np.int32).reshape(-1, 8)[:, 7].view(np.uint32) >> 28
+    n_wall = int(np.count_nonzero(codes >= 9))
+    assert infos[0]["n_csr"] == 2 * infos[0]["n_edges"] - n_wall
+
+
 @pytest.mark.parametrize("name", ["sod", "wave", "sedov"])
 def test_stage_on_device_mesh_matches_oracle(name):
     """Stage 2 of a time-centred step on the device-built half-step mesh
