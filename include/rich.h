@@ -555,11 +555,13 @@ int rich_retess_view(const rich_mesh_bufs* out, const double box[4], uint32_t bc
 /* Many re-tessellations at once, one launch per kernel for all n runs: run
  * r as rich_retess(prev[r], x[r], y[r], out[r], ws[r], ws_bytes[r]), each
  * run with its own workspace and output buffers.  bws is device memory of
- * rich_retess_batch_workspace_size bytes, 256-byte aligned; the call
- * synchronises `stream` once, to upload the runs' descriptors into it, and
- * then enqueues the kernels.  Any run's bad arguments fail the whole call
- * with that run's status, before anything is enqueued.  The results are
- * read with rich_retess_batch_result (or per run with rich_retess_result). */
+ * rich_retess_batch_workspace_size bytes, 256-byte aligned; the runs'
+ * descriptors are copied into it on `stream` from a pinned staging buffer
+ * of the library (the call does not wait on the stream), then the kernels
+ * are enqueued.  Any run's bad arguments fail the whole call with that
+ * run's status, before anything is enqueued.  The results are read with
+ * rich_retess_batch_result (or per run with rich_retess_result), or the
+ * runs' flags without a wait with rich_retess_batch_flags_async. */
 int rich_retess_batch_workspace_size(int32_t n, size_t* bytes);
 int rich_retess_batch(int32_t n, const rich_mesh* const* prev, const double* const* x,
                       const double* const* y, const rich_mesh_bufs* const* out,
@@ -572,8 +574,8 @@ typedef struct rich_retess_info {
   int64_t n_edges;    /* edges and CSR entries of the last mesh             */
   int64_t n_csr;
   int64_t n_dropped;  /* degenerate edges left out                          */
-  double area_sum;    /* sum of the cell areas (a check value, summed with
-                         atomics: its last bits vary from call to call)    */
+  double area_sum;    /* sum of the cell areas (a check value, summed in a
+                         fixed order: the same bits on every call)         */
 } rich_retess_info;
 
 /* Synchronise `stream` and read the header of ws.  Returns RICH_E_MESH when
@@ -584,6 +586,15 @@ int rich_retess_result(void* ws, void* stream, rich_retess_info* info);
  * its n runs. */
 int rich_retess_batch_result(int32_t n, void* bws, void* stream, rich_retess_info* info,
                              int32_t* status);
+/* Enqueue on `stream` a copy of the RICH_RETESS_* flags of the last
+ * rich_retess_batch on bws (n runs, in the batch's order) into host_flags[n]
+ * (caller-owned host memory; pinned memory keeps the copy asynchronous).
+ * The values are valid once the stream has passed this point (an event
+ * recorded after the call has completed); nonzero flags mean the run's mesh
+ * was not built (RICH_E_MESH from rich_retess_batch_result).  For serving
+ * loops that poll events instead of synchronising.  RICH_E_INVAL for a null
+ * pointer or n <= 0. */
+int rich_retess_batch_flags_async(int32_t n, void* bws, void* stream, int32_t* host_flags);
 
 /*
  * Kernel timing for benchmarks.  While enabled, every stage records HIP

@@ -2422,3 +2422,14 @@ const char* rich_strerror(int status) {
 }
 
 }  // extern "C"
+
+// Two host blocks copied to device memory through the pinned staging ring of
+// the batched stage (enqueued on st; the caller's blocks may be reused at
+// once): the batched re-tessellation's descriptors travel this way, so that
+// it need not wait on the stream.
+namespace rich_host {
+int upload2(void* d0, const void* h0, size_t n0, void* d1, const void* h1, size_t n1,
+            hipStream_t st) {
+  return upload_staged({{d0, {h0, n0}}, {d1, {h1, n1}}}, st);
+}
+}  // namespace rich_host

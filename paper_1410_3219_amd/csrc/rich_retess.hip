@@ -108,6 +108,7 @@ struct Batch {
   const int32_t* cstart;
   const int32_t* sstart;
   Hdr* hdr_out;
+  int32_t* flags_out;   // each run's flags, for rich_retess_batch_flags_async
   int32_t n_runs;
 };
 
@@ -188,7 +189,10 @@ __global__ void k_rt_end(Hdr* one, Batch bt) {
   Hdr* h = B ? bt.descs[blockIdx.x].hdr : one;
   if (threadIdx.x == 0) {
     h->sticky |= h->flags;
-    if (B) bt.hdr_out[blockIdx.x] = *h;
+    if (B) {
+      bt.hdr_out[blockIdx.x] = *h;
+      bt.flags_out[blockIdx.x] = h->flags;
+    }
   }
 }
 
@@ -988,6 +992,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_rt_emit(Args one, Batch bt) {
 // ===========================================================================
 // Host side
 // ===========================================================================
+// (rich_kernels.hip) two host blocks to device memory through a pinned
+// staging ring, enqueued on the stream
+namespace rich_host {
+int upload2(void* d0, const void* h0, size_t n0, void* d1, const void* h1, size_t n1,
+            hipStream_t st);
+}
 namespace {
 
 size_t rt_align(size_t v) { return (v + 255) / 256 * 256; }
@@ -1100,10 +1110,14 @@ void launch_all(const retess::Args& a, const retess::Batch& bt, int gc, int gs, 
   hipLaunchKernelGGL(k_rt_end<B>, dim3(n_runs), dim3(64), 0, st, a.hdr, bt);
 }
 
-size_t batch_bytes(int32_t n) {
-  return rt_align(sizeof(retess::Args) * (size_t)n) + rt_align(8 * ((size_t)n + 1)) +
-         rt_align(sizeof(retess::Hdr) * (size_t)n);
+// Batch workspace: descriptors, the two start tables, result headers, flags.
+size_t batch_hdr_offset(int32_t n) {
+  return rt_align(sizeof(retess::Args) * (size_t)n) + rt_align(8 * ((size_t)n + 1));
 }
+size_t batch_flags_offset(int32_t n) {
+  return batch_hdr_offset(n) + rt_align(sizeof(retess::Hdr) * (size_t)n);
+}
+size_t batch_bytes(int32_t n) { return batch_flags_offset(n) + rt_align(4 * (size_t)n); }
 
 }  // namespace
 
@@ -1184,20 +1198,19 @@ int rich_retess_batch(int32_t n, const rich_mesh* const* prev, const double* con
   starts[2 * (size_t)n + 1] = (int32_t)gs;
   char* b = static_cast<char*>(bws);
   const size_t o_start = rt_align(sizeof(retess::Args) * (size_t)n);
-  const size_t o_hdr = o_start + rt_align(8 * ((size_t)n + 1));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  // the host arrays die with this call: upload, then wait for the copies
-  if (hipMemcpyAsync(b, args.data(), sizeof(retess::Args) * (size_t)n, hipMemcpyHostToDevice,
-                     st) != hipSuccess ||
-      hipMemcpyAsync(b + o_start, starts.data(), starts.size() * sizeof(int32_t),
-                     hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return RICH_E_DEVICE;
+  // the host arrays die with this call: they go through the pinned staging
+  // ring, whose copies are enqueued on the stream (no wait)
+  const int up = rich_host::upload2(b, args.data(), sizeof(retess::Args) * (size_t)n,
+                                    b + o_start, starts.data(), starts.size() * sizeof(int32_t),
+                                    st);
+  if (up != RICH_OK) return up;
   retess::Batch bt;
   bt.descs = reinterpret_cast<const retess::Args*>(b);
   bt.cstart = reinterpret_cast<const int32_t*>(b + o_start);
   bt.sstart = bt.cstart + n + 1;
-  bt.hdr_out = reinterpret_cast<retess::Hdr*>(b + o_hdr);
+  bt.hdr_out = reinterpret_cast<retess::Hdr*>(b + batch_hdr_offset(n));
+  bt.flags_out = reinterpret_cast<int32_t*>(b + batch_flags_offset(n));
   bt.n_runs = n;
   bool walls = false, periodic = false;
   for (const retess::Args& r : args) {
@@ -1211,7 +1224,7 @@ int rich_retess_batch(int32_t n, const rich_mesh* const* prev, const double* con
 int rich_retess_batch_result(int32_t n, void* bws, void* stream, rich_retess_info* info,
                              int32_t* status) {
   if (n <= 0 || !bws || !info || !status) return RICH_E_INVAL;
-  const size_t o_hdr = rt_align(sizeof(retess::Args) * (size_t)n) + rt_align(8 * ((size_t)n + 1));
+  const size_t o_hdr = batch_hdr_offset(n);
   std::vector<retess::Hdr> h((size_t)n);
   if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess ||
       hipMemcpy(h.data(), static_cast<char*>(bws) + o_hdr, sizeof(retess::Hdr) * (size_t)n,
@@ -1226,6 +1239,15 @@ int rich_retess_batch_result(int32_t n, void* bws, void* stream, rich_retess_inf
     info[r].area_sum = h[r].area_sum;
     status[r] = h[r].flags ? RICH_E_MESH : RICH_OK;
   }
+  return RICH_OK;
+}
+
+int rich_retess_batch_flags_async(int32_t n, void* bws, void* stream, int32_t* host_flags) {
+  if (n <= 0 || !bws || !host_flags) return RICH_E_INVAL;
+  if (hipMemcpyAsync(host_flags, static_cast<char*>(bws) + batch_flags_offset(n),
+                     sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost,
+                     static_cast<hipStream_t>(stream)) != hipSuccess)
+    return RICH_E_DEVICE;
   return RICH_OK;
 }
 

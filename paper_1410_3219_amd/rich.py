@@ -153,6 +153,7 @@ def lib():
                                         C.POINTER(C.c_size_t), _vp, C.c_size_t, _vp]
         L.rich_retess_batch_result.argtypes = [C.c_int32, _vp, _vp, C.POINTER(RichRetessInfo),
                                                _ip]
+        L.rich_retess_batch_flags_async.argtypes = [C.c_int32, _vp, _vp, _vp]
         L.rich_mesh_pack.argtypes = [C.POINTER(HostMeshView), _vp, _vp]
         L.rich_mesh_pack.restype = C.c_int
         L.rich_strerror.argtypes = [C.c_int]
@@ -164,7 +165,7 @@ def lib():
                   "rich_retess_capacity", "rich_retess_workspace_size", "rich_retess",
                   "rich_retess_view", "rich_retess_result", "rich_retess_batch_workspace_size",
                   "rich_retess_batch", "rich_retess_batch_result",
-                  "rich_profile_enable", "rich_profile_read"):
+                  "rich_retess_batch_flags_async", "rich_profile_enable", "rich_profile_read"):
             getattr(L, f).restype = C.c_int
         if hasattr(L, "rich_stage_batch"):
             L.rich_batch_workspace_size.argtypes = [C.c_int32, C.POINTER(C.c_int64),
@@ -591,6 +592,21 @@ def rich_retess_batch_result(n, bws, stream=None):
                           "n_edges": info[r].n_edges, "n_csr": info[r].n_csr,
                           "n_dropped": info[r].n_dropped, "area_sum": info[r].area_sum})
             for r in range(n)]
+
+
+def rich_retess_batch_flags_async(n, bws, host_flags, stream=None):
+    """Enqueue the copy of the n runs' RICH_RETESS_* flags of the last
+    rich_retess_batch on bws into host_flags (a pinned int32 CPU tensor of at
+    least n elements); valid once the stream passes it (nonzero: the run's
+    mesh was not built)."""
+    import torch
+    if host_flags.dtype != torch.int32 or host_flags.numel() < n or host_flags.is_cuda:
+        raise RichError(RICH_E_INVAL, "rich_retess_batch_flags_async: host_flags must be an "
+                                      f"int32 CPU tensor of at least {n} elements")
+    _check(lib().rich_retess_batch_flags_async(n, C.c_void_p(bws.data_ptr()),
+                                               _stream_ptr(stream),
+                                               C.c_void_p(host_flags.data_ptr())),
+           "rich_retess_batch_flags_async")
 
 
 def mesh_to_host(dm: DeviceMesh, n_edges=None, n_csr=None):

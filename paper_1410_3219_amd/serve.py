@@ -29,9 +29,10 @@ half-step points, stage 2 on that mesh, re-tessellation of the new points;
 each session keeps three mesh buffers in rotation and a re-tessellation
 workspace.  A step whose device-built mesh is not certified is redone for
 that session with the host stage (as the step driver does), at host speed;
-the loop counts such steps.  The batched re-tessellation uploads its descriptors with a
-wait on the stream, so moving sessions keep one launch pair in flight.
-Static launches are asynchronous; the host polls completion events.
+the loop counts such steps.  Launches are asynchronous, the batched
+re-tessellation's included (its descriptors go through the library's pinned
+staging ring, and its flags come back with the launch's flag words); the
+host polls completion events.
 
 All arithmetic is in the batched HIP stage; this module only schedules.
 """
@@ -126,8 +127,7 @@ class Server:
     no host round trip; up to `max_inflight` such launch pairs are on the
     device at once, each with its own workspaces, while the host gathers the
     next.  With moving templates each stage is followed by a batched
-    re-tessellation, whose descriptor upload waits on the stream, so one
-    launch pair is in flight.  Sessions are admitted in arrival order while
+    re-tessellation, enqueued the same way.  Sessions are admitted in arrival order while
     their device memory fits the budget and released when their last request
     completes."""
 
@@ -142,7 +142,7 @@ class Server:
         self.budget = hbm_budget_bytes
         self.keep_final = keep_final
         # the batched re-tessellation waits on the stream: one pair in flight
-        self.max_inflight = 1 if self.moving else max_inflight
+        self.max_inflight = max_inflight
         self.used = 0
         self.max_used = 0
         self.sessions = {}
@@ -277,7 +277,11 @@ class Server:
         if self.moving:
             bws2 = R.rich_retess_batch(hmeshes, [s.nxt.X for s in ss], nb,
                                        [s.rws for s in ss], stream=self.stream)
-            rt = (bws1, bws2)
+            # both meshes' flags come back with the launch as well
+            mflags = self.torch.empty((2, len(items)), dtype=self.torch.int32, pin_memory=True)
+            R.rich_retess_batch_flags_async(len(items), bws1, mflags[0], self.stream)
+            R.rich_retess_batch_flags_async(len(items), bws2, mflags[1], self.stream)
+            rt = (bws1, bws2, mflags)
         # both stages' flag words come back with the launch (no stream sync)
         flags = self.torch.empty((2, len(items)), dtype=self.torch.int32, pin_memory=True)
         R.rich_batch_flags_async(len(items), ws1, flags[0], self.stream)
@@ -300,11 +304,9 @@ class Server:
             f1, f2 = flags[0].tolist(), flags[1].tolist()
             half_ok = [True] * len(items)
             new_ok = [True] * len(items)
-            if rt is not None:   # both meshes of each session's step
-                half_ok = [r[0] == 0 for r in R.rich_retess_batch_result(len(items), rt[0],
-                                                                        self.stream)]
-                new_ok = [r[0] == 0 for r in R.rich_retess_batch_result(len(items), rt[1],
-                                                                       self.stream)]
+            if rt is not None:   # both meshes of each session's step (their flags)
+                half_ok = [f == 0 for f in rt[2][0].tolist()]
+                new_ok = [f == 0 for f in rt[2][1].tolist()]
             self.ws_pool += [ws1, ws2]
             if len(self.ws_pool) > 4 * self.max_inflight:   # keep the largest idle ones
                 self.ws_pool.sort(key=lambda t: t.numel())

@@ -164,6 +164,11 @@ def test_argument_validation_without_gpu():
     assert courant(p, dt_ws=C.c_void_p(fake + 8)) == R.RICH_E_INVAL
     d1 = (C.c_double * 1)()
     assert L.rich_batch_dt(0, C.c_void_p(fake), None, d1) == R.RICH_E_INVAL
+    # batched re-tessellation flags: a count, a workspace and a host array
+    hf = (C.c_int32 * 2)()
+    assert L.rich_retess_batch_flags_async(0, C.c_void_p(fake), None, hf) == R.RICH_E_INVAL
+    assert L.rich_retess_batch_flags_async(2, None, None, hf) == R.RICH_E_INVAL
+    assert L.rich_retess_batch_flags_async(2, C.c_void_p(fake), None, None) == R.RICH_E_INVAL
 
 
 def test_acceleration_fields_are_checked_before_any_launch():

@@ -542,10 +542,18 @@ def test_retess_batch_equals_single_runs_bitwise():
     bufs = [R.DeviceMeshBufs(n, dm.box, dm.bc) for dm, n in zip(prevs, ns)]
     wss = [R.retess_workspace(n) for n in ns]
     bws = R.rich_retess_batch(prevs, Xs, bufs, wss)
+    # the runs' flags without a wait: valid once the stream passes the copy
+    hf = torch.full((len(prevs),), -1, dtype=torch.int32).pin_memory()
+    R.rich_retess_batch_flags_async(len(prevs), bws, hf)
+    ev = torch.cuda.Event()
+    ev.record()
+    ev.synchronize()
     res = R.rich_retess_batch_result(len(prevs), bws)
-    def same(i1, i2):   # the area sum is a check value summed with atomics
-        a1, a2 = dict(i1), dict(i2)
-        return abs(a1.pop("area_sum") - a2.pop("area_sum")) < 1e-13 and a1 == a2
+    assert [int(f) for f in hf] == [info["flags"] for _, info in res]
+    assert [f != 0 for f in hf.tolist()] == [st == R.RICH_E_MESH for st, _ in res]
+
+    def same(i1, i2):   # the area sum too: it is summed in a fixed order
+        return dict(i1) == dict(i2)
 
     for r, ((st1, info1), t1) in enumerate(single):
         st2, info2 = res[r]
