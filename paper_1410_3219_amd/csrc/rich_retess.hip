@@ -15,9 +15,10 @@
 // No polygon is edited: each candidate's bisector is cut down to the part
 // that every other candidate allows (two bounds kept as fractions), and the
 // candidates with a non-empty part are the cell's edges; their parts' ends
-// are the vertices.  The candidates (in LDS: 12 slots per cell, and 4 more
-// for the mirrors of a walled box) are the wall mirrors and the previous
-// neighbours; a neighbour's neighbour enters only
+// are the vertices.  The candidates (in LDS: 10 slots per cell, 16 for the
+// few cells that need more, and the 4 mirrors of a walled box in registers)
+// are the wall mirrors and the previous neighbours; a neighbour's neighbour
+// enters only
 // when its bisector crosses the cell those give (one further than twice the
 // largest vertex distance cannot, and is skipped at once).  The loops over
 // candidates have straight-line bodies, so the lanes of a wave stay together.
@@ -25,6 +26,7 @@
 // Pipeline (one launch each, all on the caller's stream):
 //   k_rt_begin    clear the result header
 //   k_rt_clip     one thread per cell: the cell's edges, area, centroid
+//                 (twice: 10 candidate slots, then 16 for the cells left over)
 //   k_rt_classify keep / own each slot by the input stage's rules, check
 //                 each kept edge against the neighbour's slot, count
 //   k_rt_scan_*   prefix sums of the counts into off[] and eoff[]
@@ -44,7 +46,14 @@ namespace retess {
 constexpr uint32_t kMask = 0x0FFFFFFFu;
 constexpr int kShift = 28;
 constexpr int kMaxFan = 20;    // edges of a finished cell (RICH_RETESS_FAN beyond)
-constexpr int kSlotsLds = 12;  // candidate slots of a cell in LDS: neighbours and entrants
+// Candidate slots of a cell in LDS (neighbours and entrants): the clip runs
+// with kSlotsFast of them, which lets a compute unit hold 3 waves per SIMD
+// (LDS bound: 2.5 with 12); the few cells that need more are marked and
+// clipped again by a second launch with kSlotsWide.
+constexpr int kSlotsFast = 10;
+constexpr int kSlotsWide = 16;
+constexpr int32_t kDegRetry = -1;   // deg[i] of a cell left to the wide launch
+constexpr int kRetry = 1 << 30;     // (private bit) more candidates than slots
                                // (a walled box adds its 4 mirrors, held in registers)
 constexpr int kRingMax = 64;   // CSR entries read per cell of the previous mesh
 constexpr int kThreads = 64;
@@ -333,22 +342,28 @@ __device__ __forceinline__ bool ccw_before(double ax, double ay, double bx, doub
 // order.  Every slot v is tried against every slot u (a fixed loop with no
 // polygon to edit), so lanes of a wave stay together.  The candidate slots
 // are the block's LDS, which sets how many waves a compute unit holds: a cell
-// has kSlotsLds of them, and a walled box's four mirrors (slots 0-3) are held
-// in registers, so both kinds of run give 12 slots to neighbours and
-// entrants.  Each launch serves one kind of run (a batch of both kinds takes
-// two launches), so a run's results never depend on the other runs.
-template <bool B, bool WALLS>
+// has SL of them, and a walled box's four mirrors (slots 0-3) are held in
+// registers, so both kinds of run give SL slots to neighbours and entrants.
+// The first launch (SL = kSlotsFast) leaves a cell that needs more slots
+// marked (deg = kDegRetry) instead of failing the mesh; the second (WIDE,
+// SL = kSlotsWide) clips only those cells, with the same arithmetic, and
+// fails the mesh if even that is not enough.  Each launch serves one kind of
+// run (a batch of both kinds takes two launches of each), so a run's results
+// never depend on the other runs.
+template <bool B, bool WALLS, int SL, bool WIDE>
 __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
   constexpr int BASE = WALLS ? 4 : 0;   // mirror slots, held in registers
-  constexpr int NS = kSlotsLds + BASE;  // candidates per cell
+  constexpr int NS = SL + BASE;         // candidates per cell
   static_assert(NS <= 32, "slot masks are 32-bit");
-  __shared__ double s_dx[kSlotsLds * kThreads], s_dy[kSlotsLds * kThreads];
-  __shared__ int32_t s_id[kSlotsLds * kThreads];
+  constexpr int kFull = WIDE ? RICH_RETESS_FAN : kRetry;   // out of slots
+  __shared__ double s_dx[SL * kThreads], s_dy[SL * kThreads];
+  __shared__ int32_t s_id[SL * kThreads];
   int blk;
   const Args& a = block_run<B>(one, bt.cstart, bt, blk);
   const int i = blk * kThreads + threadIdx.x;
   if (i >= a.n) return;
   if ((a.bc == (int)RICH_BOUNDARY_PERIODIC) == WALLS) return;  // the other launch's run
+  if (WIDE && a.deg[i] != kDegRetry) return;   // done by the first launch
   const Slots<BASE> S{s_dx + threadIdx.x, s_dy + threadIdx.x, s_id + threadIdx.x};
   // a walled box: the point's mirrors across the walls y0, x1, y1, x0 (slots
   // 0-3) are the displacements (0, wy0), (wx1, 0), (0, wy2), (wx3, 0)
@@ -407,7 +422,7 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
       bad |= RICH_RETESS_CLIP;
       k1 = k0;
     } else if (k1 - k0 > NS - nv) {
-      bad |= RICH_RETESS_FAN;
+      bad |= kFull;
       k1 = k0;
     }
   }
@@ -479,7 +494,7 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
         // (a mirror is never reused)
         const uint32_t usable = ~em & ((1u << NS) - 1u) & ~((1u << BASE) - 1u);
         if (usable == 0u) {
-          bad |= RICH_RETESS_FAN;
+          bad |= kFull;
           continue;
         }
         u = __ffs(usable) - 1;
@@ -535,8 +550,10 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
   cr.py = yi;
   cr.pad = 0.0;
   if (bad) {
-    atomicOr(&a.hdr->flags, bad);
-    a.deg[i] = 0;
+    // out of slots alone: left to the wide launch; anything else fails the mesh
+    const int pub = bad & ~kRetry;
+    if (pub) atomicOr(&a.hdr->flags, pub);
+    a.deg[i] = pub ? 0 : kDegRetry;
     cr.area = 0.0;
     cr.sx = xi;
     cr.sy = yi;
@@ -1091,17 +1108,25 @@ int make_args(const rich_mesh* prev, const double* x, const double* y,
   return RICH_OK;
 }
 
-// The eight launches of one re-tessellation (B: of n_runs runs at once, with
+// The nine launches of one re-tessellation of one kind of box (B: of n_runs runs at once, with
 // gc cell blocks and gs scan blocks in all).
 template <bool B>
 void launch_all(const retess::Args& a, const retess::Batch& bt, int gc, int gs, int n_runs,
                 bool walls, bool periodic, hipStream_t st) {
   using namespace retess;
   hipLaunchKernelGGL(k_rt_begin<B>, dim3(n_runs), dim3(64), 0, st, a.hdr, bt);
-  if (walls)
-    hipLaunchKernelGGL((k_rt_clip<B, true>), dim3(gc), dim3(kThreads), 0, st, a, bt);
-  if (periodic)
-    hipLaunchKernelGGL((k_rt_clip<B, false>), dim3(gc), dim3(kThreads), 0, st, a, bt);
+  if (walls) {
+    hipLaunchKernelGGL((k_rt_clip<B, true, kSlotsFast, false>), dim3(gc), dim3(kThreads), 0, st,
+                       a, bt);
+    hipLaunchKernelGGL((k_rt_clip<B, true, kSlotsWide, true>), dim3(gc), dim3(kThreads), 0, st,
+                       a, bt);
+  }
+  if (periodic) {
+    hipLaunchKernelGGL((k_rt_clip<B, false, kSlotsFast, false>), dim3(gc), dim3(kThreads), 0, st,
+                       a, bt);
+    hipLaunchKernelGGL((k_rt_clip<B, false, kSlotsWide, true>), dim3(gc), dim3(kThreads), 0, st,
+                       a, bt);
+  }
   hipLaunchKernelGGL(k_rt_classify<B>, dim3(gc), dim3(kGroupThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_scan_local<B>, dim3(gs), dim3(kScanThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_scan_blocks<B>, dim3(n_runs), dim3(kScanThreads), 0, st, a, bt);

@@ -143,6 +143,41 @@ def test_retess_matches_oracle_voronoi(name, k):
     assert abs(info["area_sum"] - (m.box[2] - m.box[0]) * (m.box[3] - m.box[1])) < 1e-12
 
 
+@pytest.mark.parametrize("petals,box", [(12, "walls"), (14, "walls"), (16, "walls"),
+                                         (13, "periodic")])
+def test_retess_wide_cells_match_oracle_voronoi(petals, box):
+    """A cell with more candidates than the first clip launch holds (a point
+    inside a ring of 12 to 16): it is left to the wide launch, and the mesh
+    is certified and equals the oracle's Voronoi cells; the rest of the mesh
+    comes from the first launch."""
+    from paper_1410_3219_amd import rich as R
+    P = I.sod(k=20, seed=4) if box == "walls" else I.advected_wave(k=20, seed=4)
+    keep = np.hypot(P.px - 0.5, P.py - 0.5) > 0.1
+    a = 2 * np.pi * np.arange(petals) / petals
+    px = np.concatenate([P.px[keep], [0.5], 0.5 + 0.06 * np.cos(a)])
+    py = np.concatenate([P.py[keep], [0.5], 0.5 + 0.06 * np.sin(a)])
+    m = T.rich_tess_build(px, py, P.box, P.bc)
+    assert np.diff(m.off).max() == petals
+    dm = R.DeviceMesh.from_host(m)
+    X = torch_points(R, m)
+    bufs = R.DeviceMeshBufs(m.n_cells, m.box, m.bc)
+    tws = R.retess_workspace(m.n_cells)
+    R.rich_retess(dm, X, bufs, tws)
+    st, info = R.rich_retess_result(tws)
+    assert st == 0 and info["flags"] == 0, info
+    dev = R.mesh_to_host(bufs.mesh(), info["n_edges"], info["n_csr"])
+    check_structure(dev)
+    assert np.diff(dev.off).max() == petals
+    ref = O.voronoi_mesh(O.voronoi(m.px, m.py, m.box, m.bc))
+    h_cell = math.sqrt((m.box[2] - m.box[0]) * (m.box[3] - m.box[1]) / m.n_cells)
+    compare_meshes(dev, ref, h_cell)
+
+
+def torch_points(R, m):
+    import torch
+    return torch.from_numpy(np.stack([m.px, m.py])).cuda()
+
+
 @pytest.mark.parametrize("name", ["sod", "wave"])
 def test_retess_after_edge_flips_matches_oracle_voronoi(name):
     """Points jostled by up to a fifth of the spacing from the previous

@@ -201,21 +201,21 @@ def test_served_moving_sessions_match_alone_bitwise():
 
 
 def _flower_template():
-    """A walled box whose central cell has 14 neighbours (a point inside a
-    ring of 14), more candidates than a device-rebuilt cell holds: every
-    device mesh of it is reported, not certified."""
+    """A walled box whose central cell has 18 neighbours (a point inside a
+    ring of 18), more candidates than a device-rebuilt cell holds (16 slots):
+    every device mesh of it is reported, not certified."""
     from paper_1410_3219_amd import inputs as I
     from paper_1410_3219_amd import rich as R
     from paper_1410_3219_amd import serve as S
     from paper_1410_3219_amd import tess as T
     P = I.sod(k=20, seed=4)
     keep = np.hypot(P.px - 0.5, P.py - 0.5) > 0.1
-    a = 2 * np.pi * np.arange(14) / 14
+    a = 2 * np.pi * np.arange(18) / 18
     px = np.concatenate([P.px[keep], [0.5], 0.5 + 0.06 * np.cos(a)])
     py = np.concatenate([P.py[keep], [0.5], 0.5 + 0.06 * np.sin(a)])
     m = T.rich_tess_build(px, py, P.box, P.bc)
     deg = np.diff(m.off)
-    assert deg.max() >= 14
+    assert deg.max() >= 18
     n = m.n_cells
     rho = np.where(px < 0.5, 1.0, 0.125)
     pr = np.where(px < 0.5, 1.0, 0.1)
