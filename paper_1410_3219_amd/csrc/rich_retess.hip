@@ -704,9 +704,19 @@ __global__ __launch_bounds__(kGroupThreads) void k_rt_classify(Args one, Batch b
       const int32_t want = pack(i, back_code(code));
       const int dj = a.deg[j];
       const size_t t0 = (size_t)j * kMaxFan;
+      // the first match among the neighbour's slots: its first eight in two
+      // 16-byte loads (a row holds kMaxFan slots, so they are in bounds;
+      // those past its degree are ignored), the rest one at a time
+      static_assert(kMaxFan >= 8 && (kMaxFan * 4) % 16 == 0, "rows of 16-byte chunks");
+      const int4* rowv = reinterpret_cast<const int4*>(a.s_nb + t0);
+      const int4 v0 = rowv[0], v1 = rowv[1];
+      const int32_t ids[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
       int found = -1;
-      for (int t = 0; t < dj; ++t)
-        if (a.s_nb[t0 + t] == want) { found = t; break; }
+#pragma unroll
+      for (int t = 7; t >= 0; --t)
+        if (t < dj && ids[t] == want) found = t;
+      for (int t = 8; found < 0 && t < dj; ++t)
+        if (a.s_nb[t0 + t] == want) found = t;
       if (found < 0) { bad |= RICH_RETESS_ASYM; continue; }
       a.s_back[s0 + q] = (uint8_t)found;
       const double* gj = a.s_geo + 3 * (t0 + found);
