@@ -46,6 +46,7 @@ namespace retess {
 constexpr uint32_t kMask = 0x0FFFFFFFu;
 constexpr int kShift = 28;
 constexpr int kMaxFan = 20;    // edges of a finished cell (RICH_RETESS_FAN beyond)
+static_assert(kMaxFan <= 64, "a kept slot's rank fits the six upper bits of its flag byte");
 // Candidate slots of a cell in LDS (neighbours and entrants): the clip runs
 // with kSlotsFast of them, which lets a compute unit hold 3 waves per SIMD
 // (LDS bound: 2.5 with 12); the few cells that need more are marked and
@@ -99,7 +100,7 @@ struct Args {
   int32_t* deg;        // [n]
   int32_t* s_nb;       // [n][kMaxFan] generating point: cell | code << 28
   double* s_geo;       // [n][kMaxFan][3] edge length, midpoint x, midpoint y
-  uint8_t* s_flag;     // [n][kMaxFan] bit 0 kept, bit 1 owned
+  uint8_t* s_flag;     // [n][kMaxFan] bit 0 kept, bit 1 owned, bits 2-6 rank among kept
   uint8_t* s_back;     // [n][kMaxFan] owned edge: its slot in the neighbour's row
   int64_t* bsum;       // [2][n_scan_blocks] block totals of kept / owned
   CPart* cpart;        // [cell blocks] classify block sums, reduced by the scan
@@ -674,6 +675,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_rt_classify(Args one, Batch b
     }
     const double Ri = sqrt(Ai / kPi);
     const size_t s0 = (size_t)i * kMaxFan;
+    int kept_before = 0;   // kept slots of the group's earlier rounds
     for (int q = l; q < d; q += kGroup) {
       const int32_t id = a.s_nb[s0 + q];
       const int j = (int)((uint32_t)id & kMask);
@@ -686,7 +688,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_rt_classify(Args one, Batch b
       if (code >= kWallX0) own = true;
       else if (j != i) own = i < j;
       else own = code >= 5;
-      a.s_flag[s0 + q] = (uint8_t)((keep ? 1 : 0) | (keep && own ? 2 : 0));
+      // a kept slot's rank among the cell's kept slots (its CSR position)
+      const uint32_t km = group_bits(keep);
+      const int rank = kept_before + __popc(km & ((1u << l) - 1u));
+      kept_before += __popc(km);
+      a.s_flag[s0 + q] = (uint8_t)((keep ? 1 : 0) | (keep && own ? 2 : 0) | (rank << 2));
       if (!keep) {
         ++drop;
         continue;
@@ -942,23 +948,11 @@ __global__ __launch_bounds__(kScanThreads) void k_rt_scan_add(Args one, Batch bt
 // ---------------------------------------------------------------------------
 // edge records and CSR entries
 // ---------------------------------------------------------------------------
-// Kept-slot bits of a row of kMaxFan flag bytes (bit t for slot t), read as
-// 4-byte words: each word's four bit-0s gathered by one multiplication.
-__device__ __forceinline__ uint32_t kept_bits(const uint8_t* row) {
-  static_assert(kMaxFan % 4 == 0, "rows of whole words");
-  const uint32_t* w = reinterpret_cast<const uint32_t*>(row);
-  uint32_t m = 0u;
-#pragma unroll
-  for (int k = 0; k < kMaxFan / 4; ++k)
-    m |= (((w[k] & 0x01010101u) * 0x01020408u) >> 24) << (4 * k);
-  return m;
-}
-
 // Each cell writes, for every edge it owns (its owned slots in slot order
 // from eoff[i]): the edge record, its own CSR entry 2 e at the slot's rank
 // among its kept slots, and, unless the edge is a wall, the neighbour's entry
 // 2 e + 1 at the rank among the neighbour's kept slots of the slot that sees
-// the edge.  A certified mesh has every kept slot the owned or the other side
+// the edge (classify stored each kept slot's rank in its flag byte).  A certified mesh has every kept slot the owned or the other side
 // of exactly one owned edge (classify matched each owned edge to one slot of
 // the neighbour, and kept = 2 owned - walls), so each CSR entry is written
 // once, and each cell's entries run counter-clockwise (slot order).  A
@@ -983,11 +977,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_rt_emit(Args one, Batch bt) {
   }
   const int d = a.deg[i];
   const size_t s0 = (size_t)i * kMaxFan;
-  int k = a.off[i], e = a.eoff[i];
+  const int k = a.off[i];
+  int e = a.eoff[i];
   for (int base = 0; base < d; base += kGroup) {
     const int q = base + l;
     const uint8_t f = q < d ? a.s_flag[s0 + q] : (uint8_t)0;
-    const uint32_t mk = group_bits((f & 1) != 0);
     const uint32_t mo = group_bits((f & 3) == 3);
     const uint32_t below = (1u << l) - 1u;
     if ((f & 3) == 3) {
@@ -1001,15 +995,13 @@ __global__ __launch_bounds__(kGroupThreads) void k_rt_emit(Args one, Batch bt) {
       r.i = i;
       r.j = id;
       a.edges[ee] = r;
-      a.idx[k + __popc(mk & below)] = 2 * ee;
+      a.idx[k + (f >> 2)] = 2 * ee;
       if ((int)((uint32_t)id >> kShift) < kWallX0) {
         const int j = (int)((uint32_t)id & kMask);
         const int t = a.s_back[s0 + q];
-        const uint32_t kj = kept_bits(a.s_flag + (size_t)j * kMaxFan);
-        a.idx[a.off[j] + __popc(kj & ((1u << t) - 1u))] = 2 * ee + 1;
+        a.idx[a.off[j] + (a.s_flag[(size_t)j * kMaxFan + t] >> 2)] = 2 * ee + 1;
       }
     }
-    k += __popc(mk);
     e += __popc(mo);
   }
 }
