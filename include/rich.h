@@ -511,7 +511,8 @@ int rich_step_batch_accel(int32_t n, rich_ctx* const* ctxs, rich_state* const* s
  * edge), and the caller rebuilds the mesh on the host (rich_tess_build).
  */
 #define RICH_RETESS_POINT    1   /* a point outside the box or not finite       */
-#define RICH_RETESS_FAN      2   /* a cell with more than 20 edges              */
+#define RICH_RETESS_FAN      2   /* a cell with more than 16 candidates (previous
+                                    neighbours and entrants) or 20 edges         */
 #define RICH_RETESS_CLIP     4   /* a clip left nothing, or parallel bisectors  */
 #define RICH_RETESS_ASYM     8   /* an edge not seen alike from both cells      */
 #define RICH_RETESS_AREA    16   /* cell areas do not sum to the box area       */
