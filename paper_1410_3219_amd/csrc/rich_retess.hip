@@ -23,10 +23,18 @@
 // largest vertex distance cannot, and is skipped at once).  The loops over
 // candidates have straight-line bodies, so the lanes of a wave stay together.
 //
+// Most cells keep their neighbours from one step to the next; for those a
+// cheaper proof suffices (k_rt_vertex: each vertex of the previous ring's
+// consecutive neighbours checked against the other candidates), and the
+// clip handles only the cells it leaves.
+//
 // Pipeline (one launch each, all on the caller's stream):
-//   k_rt_begin    clear the result header
-//   k_rt_clip     one thread per cell: the cell's edges, area, centroid
-//                 (twice: 10 candidate slots, then 16 for the cells left over)
+//   k_rt_begin    clear the result header and the queue counters
+//   k_rt_vertex   one thread per cell: the cell from its previous ring, when
+//                 every vertex passes (else queued for the clip)
+//   k_rt_clip     one thread per queued cell: the cell's edges, area, centroid
+//                 (twice: 10 candidate slots over the queue, then 16 for the
+//                 cells left over)
 //   k_rt_classify keep / own each slot by the input stage's rules, check
 //                 each kept edge against the neighbour's slot, count
 //   k_rt_scan_*   prefix sums of the counts into off[] and eoff[]
@@ -54,6 +62,13 @@ static_assert(kMaxFan <= 64, "a kept slot's rank fits the six upper bits of its 
 constexpr int kSlotsFast = 10;
 constexpr int kSlotsWide = 16;
 constexpr int32_t kDegRetry = -1;   // deg[i] of a cell left to the wide launch
+constexpr int32_t kDegClip = -2;    // deg[i] of a cell the vertex check left to the clip
+// The cells the vertex check leaves are queued for the clip in kSeg
+// segments (block b of a run appends to segment b % kSeg), each with its own
+// counter on its own 128-byte line, so that the blocks' appends do not all
+// meet on one address; the clip then runs dense waves over the queue.
+constexpr int kSeg = 64;
+constexpr int kSegStride = 32;      // int32 counters 128 bytes apart
 constexpr int kRetry = 1 << 30;     // (private bit) more candidates than slots
                                // (a walled box adds its 4 mirrors, held in registers)
 constexpr int kRingMax = 64;   // CSR entries read per cell of the previous mesh
@@ -104,6 +119,9 @@ struct Args {
   uint8_t* s_back;     // [n][kMaxFan] owned edge: its slot in the neighbour's row
   int64_t* bsum;       // [2][n_scan_blocks] block totals of kept / owned
   CPart* cpart;        // [cell blocks] classify block sums, reduced by the scan
+  int32_t* qcnt;       // [kSeg * kSegStride] queue segment counters (every kSegStride-th)
+  int32_t* queue;      // [kSeg][qcap] cells left to the clip
+  int32_t qcap;        // capacity of a segment: kThreads * ceil(cell blocks / kSeg)
   // geometry
   double x0, y0, x1, y1, Lx, Ly;
   int32_t n, bc, n_scan_blocks;
@@ -182,8 +200,10 @@ __device__ __forceinline__ int prev_neighbour(const Args& a, int k) {
 }
 
 template <bool B>
-__global__ void k_rt_begin(Hdr* one, Batch bt) {
-  Hdr* h = B ? bt.descs[blockIdx.x].hdr : one;
+__global__ void k_rt_begin(Args one, Batch bt) {
+  const Args& a = B ? bt.descs[blockIdx.x] : one;
+  Hdr* h = a.hdr;
+  for (int t = threadIdx.x; t < kSeg; t += blockDim.x) a.qcnt[t * kSegStride] = 0;
   if (threadIdx.x == 0) {
     h->flags = 0;
     h->n_edges = 0;
@@ -335,7 +355,8 @@ __device__ __forceinline__ bool ccw_before(double ax, double ay, double bx, doub
   return ax * by - ay * bx > 0.0;
 }
 
-// One thread per cell.  With walls, slots 0-3 hold the point's mirrors
+// One thread per cell that the vertex check left (deg = kDegClip; the
+// other lanes return at once).  With walls, slots 0-3 hold the point's mirrors
 // (they bound it); then come the cell's neighbours in the previous mesh; the
 // first pass finds the polygon those allow.  The neighbours' neighbours then enter only when their
 // bisector crosses that polygon, into slots that bound nothing; the second
@@ -361,10 +382,19 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
   __shared__ int32_t s_id[SL * kThreads];
   int blk;
   const Args& a = block_run<B>(one, bt.cstart, bt, blk);
-  const int i = blk * kThreads + threadIdx.x;
-  if (i >= a.n) return;
   if ((a.bc == (int)RICH_BOUNDARY_PERIODIC) == WALLS) return;  // the other launch's run
-  if (WIDE && a.deg[i] != kDegRetry) return;   // done by the first launch
+  int i;
+  if (WIDE) {
+    i = blk * kThreads + threadIdx.x;
+    if (i >= a.n || a.deg[i] != kDegRetry) return;   // done by an earlier launch
+  } else {
+    // entry e of queue segment blk % kSeg (e < qcap for every block of the run)
+    const int seg = blk % kSeg;
+    const int e = (blk / kSeg) * kThreads + (int)threadIdx.x;
+    if (e >= a.qcnt[seg * kSegStride]) return;
+    i = a.queue[(size_t)seg * a.qcap + e];
+    if (i < 0 || i >= a.n || a.deg[i] != kDegClip) return;
+  }
   const Slots<BASE> S{s_dx + threadIdx.x, s_dy + threadIdx.x, s_id + threadIdx.x};
   // a walled box: the point's mirrors across the walls y0, x1, y1, x0 (slots
   // 0-3) are the displacements (0, wy0), (wx1, 0), (0, wy2), (wx3, 0)
@@ -634,6 +664,227 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
   cr.area = 0.5 * A2;
   cr.sx = xi + cx / (3.0 * A2);
   cr.sy = yi + cy / (3.0 * A2);
+  a.cells[i] = cr;
+}
+
+// ---------------------------------------------------------------------------
+// the cell of one point when it keeps its previous neighbours
+// ---------------------------------------------------------------------------
+// Under the small moves of a time step most cells keep their neighbours, and
+// the previous mesh lists them counter-clockwise.  Then the cell's vertices
+// are the points equidistant from r_i and two consecutive neighbours, and
+// the cell is proved by checking each vertex against every other candidate
+// (one dot product), instead of cutting every bisector by every other one.
+// The proof holds in exact arithmetic when every consecutive pair turns
+// counter-clockwise by less than half a turn (and more than kVertexSin), the
+// ring winds once, and every vertex lies inside every other candidate's half
+// plane by a margin far above the rounding of the test (kVertexMargin of the
+// squared lengths involved): the polygon is then the intersection of the
+// candidates' half planes, and its edges (all of positive length, well above
+// the input stage's cut for dropping one) are the ring's neighbours.  The
+// candidates are the clip's: the mirrors of a walled box, the ring, and the
+// neighbours' neighbours that could reach a vertex.  A cell that fails any
+// of these tests (a new neighbour, a lost one, a near-degenerate vertex, a
+// ring longer than kRingFast or next to a wall) is marked (deg = kDegClip)
+// and left to the clip launches, which decide every case.
+constexpr int kRingFast = 8;            // ring entries held in registers
+constexpr double kVertexMargin = 1e-9;  // relative margin of every vertex test
+constexpr double kVertexSin = 0.05;     // least sine of a consecutive pair's angle
+
+template <bool B, bool WALLS>
+__global__ __launch_bounds__(kThreads) void k_rt_vertex(Args one, Batch bt) {
+  constexpr int N = kRingFast;
+  int blk;
+  const Args& a = block_run<B>(one, bt.cstart, bt, blk);
+  const int i = blk * kThreads + threadIdx.x;
+  if (i >= a.n) return;
+  if ((a.bc == (int)RICH_BOUNDARY_PERIODIC) == WALLS) return;  // the other launch's run
+  const double xi = a.x[i], yi = a.y[i];
+  bool ok = WALLS ? (xi > a.x0 && xi < a.x1 && yi > a.y0 && yi < a.y1)
+                  : (xi >= a.x0 && xi < a.x1 && yi >= a.y0 && yi < a.y1);
+  int k0 = a.p_off[i], k1 = a.p_off[i + 1];
+  const int n = k1 - k0;
+  ok = ok && k0 >= 0 && n >= 3 && n <= N && k1 <= a.p_n_csr;
+  if (!ok) k1 = k0;   // (nothing of the ring is loaded)
+
+  // displacement of cell c from r_i (nearest periodic image) and its id
+  auto displacement = [&](int c, double xc, double yc, double& dx, double& dy) -> int32_t {
+    dx = xc - xi;
+    dy = yc - yi;
+    int code = 0;
+    if (!WALLS) {
+      int sx = 0, sy = 0;
+      if (dx > 0.5 * a.Lx) { dx -= a.Lx; sx = -1; } else if (dx < -0.5 * a.Lx) { dx += a.Lx; sx = 1; }
+      if (dy > 0.5 * a.Ly) { dy -= a.Ly; sy = -1; } else if (dy < -0.5 * a.Ly) { dy += a.Ly; sy = 1; }
+      if (sx != 0 || sy != 0) code = shift_code(sx, sy);
+    }
+    return pack(c, code);
+  };
+
+  // the ring: displacements, half squared lengths, ids (a wall entry or an
+  // entry out of range fails the cell)
+  int c[N];
+  double dx[N], dy[N], h[N];
+  int32_t id[N];
+  {
+    double cx[N], cy[N];
+    ring_chunk<N>(a, k0, k1, i, c, cx, cy);
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      ok = ok && (m >= n || c[m] >= 0);
+      id[m] = displacement(c[m] < 0 ? 0 : c[m], cx[m], cy[m], dx[m], dy[m]);
+      h[m] = 0.5 * (dx[m] * dx[m] + dy[m] * dy[m]);
+    }
+  }
+
+  // vertex k: equidistant from r_i, ring entries k and k+1 (cyclically)
+  double vx[N], vy[N], mq[N];
+  double r2 = 0.0;
+  int wraps = 0, start = 0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const bool last = k + 1 >= n;
+    const double ax = dx[k], ay = dy[k], ha = h[k];
+    const double bx = last ? dx[0] : dx[k + 1 < N ? k + 1 : 0];
+    const double by = last ? dy[0] : dy[k + 1 < N ? k + 1 : 0];
+    const double hb = last ? h[0] : h[k + 1 < N ? k + 1 : 0];
+    const double det = ax * by - ay * bx;
+    // det = |a| |b| sin(angle); a turn of less than half a turn, by a margin
+    const bool turn = det > 0.0 && det * det > (4.0 * kVertexSin * kVertexSin) * ha * hb;
+    const double inv = 1.0 / (turn ? det : 1.0);
+    vx[k] = (ha * by - hb * ay) * inv;
+    vy[k] = (ax * hb - ha * bx) * inv;
+    const double q = vx[k] * vx[k] + vy[k] * vy[k];
+    mq[k] = kVertexMargin * q;
+    if (k < n) {
+      ok = ok && turn;
+      r2 = fmax(r2, q);
+      // the ring winds once: exactly one step passes angle 0
+      if (ccw_before(bx, by, ax, ay)) {
+        ++wraps;
+        start = last ? 0 : k + 1;
+      }
+    }
+  }
+  ok = ok && wraps == 1;
+
+  // every vertex inside every other candidate's half plane, by the margin
+  auto inside = [&](int k, double ux, double uy, double hu) -> bool {
+    return hu - (vx[k] * ux + vy[k] * uy) > kVertexMargin * hu + mq[k];
+  };
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+#pragma unroll
+    for (int v = 0; v < N; ++v) {
+      // not the vertex's own two entries (k and k+1, cyclically)
+      const bool own = v == k || (v == k + 1 && k + 1 < n) || (v == 0 && k + 1 == n);
+      if (k < n && v < n && !own) ok = ok && inside(k, dx[v], dy[v], h[v]);
+    }
+  }
+  if (WALLS) {
+    // the point's mirrors across the walls y0, x1, y1, x0
+    const double wy0 = 2.0 * (a.y0 - yi), wx1 = 2.0 * (a.x1 - xi);
+    const double wy2 = 2.0 * (a.y1 - yi), wx3 = 2.0 * (a.x0 - xi);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      if (k < n) {
+        ok = ok && inside(k, 0.0, wy0, 0.5 * wy0 * wy0) && inside(k, wx1, 0.0, 0.5 * wx1 * wx1) &&
+             inside(k, 0.0, wy2, 0.5 * wy2 * wy2) && inside(k, wx3, 0.0, 0.5 * wx3 * wx3);
+      }
+    }
+  }
+
+  // the neighbours' neighbours: one nearer than twice the largest vertex
+  // distance (with the margin) that is not in the ring must leave every
+  // vertex inside its half plane
+  const double reach = 4.0 * r2 * (1.0 + kVertexMargin);
+  for (int m = 0; m < n && ok; ++m) {
+    int j = c[0];
+#pragma unroll
+    for (int t = 1; t < N; ++t) j = t == m ? c[t] : j;
+    const int l0 = a.p_off[j], l1 = a.p_off[j + 1];
+    if (l0 < 0 || l1 < l0 || l1 > a.p_n_csr || l1 - l0 > kRingMax) {
+      ok = false;
+      break;
+    }
+    constexpr int CH = 8;
+    for (int l = l0; l < l1 && ok; l += CH) {
+      int cc[CH];
+      double ccx[CH], ccy[CH];
+      ring_chunk<CH>(a, l, l1, i, cc, ccx, ccy);
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        if (cc[t] < 0) continue;
+        double ux, uy;
+        const int32_t idu = displacement(cc[t], ccx[t], ccy[t], ux, uy);
+        const double d2 = ux * ux + uy * uy;
+        if (!(d2 < reach)) continue;
+        bool known = false;
+#pragma unroll
+        for (int v = 0; v < N; ++v) known = known || (v < n && id[v] == idu);
+        if (known) continue;
+        const double hu = 0.5 * d2;
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+          if (k < n) ok = ok && inside(k, ux, uy, hu);
+      }
+    }
+  }
+
+  // a failing cell is appended to the block's queue segment (one atomic
+  // per wave; a block is one wave)
+  static_assert(kThreads == 64, "a block is one wave");
+  const unsigned long long fails = __ballot(!ok);
+  if (fails != 0ull) {
+    const int lane = (int)threadIdx.x;
+    const int leader = __ffsll((long long)__ballot(true)) - 1;
+    const int seg = blk % kSeg;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&a.qcnt[seg * kSegStride], __popcll(fails));
+    base = __shfl(base, leader);
+    if (!ok) {
+      a.queue[(size_t)seg * a.qcap + base + __popcll(fails & ((1ull << lane) - 1ull))] = i;
+      a.deg[i] = kDegClip;
+      return;
+    }
+  }
+  // edge k runs from vertex k-1 to vertex k; its slot is its counter-
+  // clockwise rank, counted from the entry of least angle
+  double pvx = vx[0], pvy = vy[0];
+#pragma unroll
+  for (int t = 1; t < N; ++t) {
+    pvx = t == n - 1 ? vx[t] : pvx;
+    pvy = t == n - 1 ? vy[t] : pvy;
+  }
+  double A2 = 0.0, sx = 0.0, sy = 0.0;
+  const size_t s0 = (size_t)i * kMaxFan;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    if (k < n) {
+      const double ux = pvx, uy = pvy, wx = vx[k], wy = vy[k];
+      const double cr = ux * wy - uy * wx;
+      A2 += cr;
+      sx += (ux + wx) * cr;
+      sy += (uy + wy) * cr;
+      const double ex = wx - ux, ey = wy - uy;
+      const int rank = k >= start ? k - start : k - start + n;
+      a.s_nb[s0 + rank] = id[k];
+      double* g = a.s_geo + 3 * (s0 + rank);
+      g[0] = sqrt(ex * ex + ey * ey);
+      g[1] = xi + 0.5 * (ux + wx);
+      g[2] = yi + 0.5 * (uy + wy);
+      pvx = wx;
+      pvy = wy;
+    }
+  }
+  a.deg[i] = n;
+  rich_cell cr;
+  cr.px = xi;
+  cr.py = yi;
+  cr.pad = 0.0;
+  cr.area = 0.5 * A2;
+  cr.sx = xi + sx / (3.0 * A2);
+  cr.sy = yi + sy / (3.0 * A2);
   a.cells[i] = cr;
 }
 
@@ -1022,8 +1273,8 @@ namespace {
 size_t rt_align(size_t v) { return (v + 255) / 256 * 256; }
 
 struct RtLayout {
-  size_t deg, s_nb, s_geo, s_flag, s_back, bsum, cpart, total;
-  int nb;
+  size_t deg, s_nb, s_geo, s_flag, s_back, bsum, cpart, qcnt, queue, total;
+  int nb, qcap;
 };
 
 RtLayout rt_layout(int64_t n) {
@@ -1038,7 +1289,11 @@ RtLayout rt_layout(int64_t n) {
   L.s_back = o; o += rt_align(slots);
   L.bsum = o;   o += rt_align(16 * (size_t)L.nb);
   L.cpart = o;
-  o += rt_align(sizeof(retess::CPart) * (size_t)((n + retess::kThreads - 1) / retess::kThreads));
+  const int64_t blocks = (n + retess::kThreads - 1) / retess::kThreads;
+  o += rt_align(sizeof(retess::CPart) * (size_t)blocks);
+  L.qcnt = o;   o += rt_align(4 * (size_t)retess::kSeg * retess::kSegStride);
+  L.qcap = (int)(retess::kThreads * ((blocks + retess::kSeg - 1) / retess::kSeg));
+  L.queue = o;  o += rt_align(4 * (size_t)retess::kSeg * (size_t)L.qcap);
   L.total = o;
   return L;
 }
@@ -1098,6 +1353,9 @@ int make_args(const rich_mesh* prev, const double* x, const double* y,
   a.s_back = reinterpret_cast<uint8_t*>(w + L.s_back);
   a.bsum = reinterpret_cast<int64_t*>(w + L.bsum);
   a.cpart = reinterpret_cast<retess::CPart*>(w + L.cpart);
+  a.qcnt = reinterpret_cast<int32_t*>(w + L.qcnt);
+  a.queue = reinterpret_cast<int32_t*>(w + L.queue);
+  a.qcap = L.qcap;
   a.x0 = prev->box[0];
   a.y0 = prev->box[1];
   a.x1 = prev->box[2];
@@ -1110,20 +1368,22 @@ int make_args(const rich_mesh* prev, const double* x, const double* y,
   return RICH_OK;
 }
 
-// The nine launches of one re-tessellation of one kind of box (B: of n_runs runs at once, with
+// The ten launches of one re-tessellation of one kind of box (B: of n_runs runs at once, with
 // gc cell blocks and gs scan blocks in all).
 template <bool B>
 void launch_all(const retess::Args& a, const retess::Batch& bt, int gc, int gs, int n_runs,
                 bool walls, bool periodic, hipStream_t st) {
   using namespace retess;
-  hipLaunchKernelGGL(k_rt_begin<B>, dim3(n_runs), dim3(64), 0, st, a.hdr, bt);
+  hipLaunchKernelGGL(k_rt_begin<B>, dim3(n_runs), dim3(64), 0, st, a, bt);
   if (walls) {
+    hipLaunchKernelGGL((k_rt_vertex<B, true>), dim3(gc), dim3(kThreads), 0, st, a, bt);
     hipLaunchKernelGGL((k_rt_clip<B, true, kSlotsFast, false>), dim3(gc), dim3(kThreads), 0, st,
                        a, bt);
     hipLaunchKernelGGL((k_rt_clip<B, true, kSlotsWide, true>), dim3(gc), dim3(kThreads), 0, st,
                        a, bt);
   }
   if (periodic) {
+    hipLaunchKernelGGL((k_rt_vertex<B, false>), dim3(gc), dim3(kThreads), 0, st, a, bt);
     hipLaunchKernelGGL((k_rt_clip<B, false, kSlotsFast, false>), dim3(gc), dim3(kThreads), 0, st,
                        a, bt);
     hipLaunchKernelGGL((k_rt_clip<B, false, kSlotsWide, true>), dim3(gc), dim3(kThreads), 0, st,
