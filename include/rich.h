@@ -493,7 +493,11 @@ int rich_step_batch_accel(int32_t n, rich_ctx* const* ctxs, rich_state* const* s
  * square bounded by the point's own periodic images against the bisectors
  * with candidate points: the neighbours and neighbours' neighbours of the
  * cell in a previous mesh `prev` of the same points (periodic: the nearest
- * image of each candidate).  The result has the input stage's layout and
+ * image of each candidate).  A cell that keeps its previous neighbours
+ * (each vertex of two consecutive ones inside every other candidate's half
+ * plane, by a margin of 1e-9 of the squared lengths) is taken from that
+ * ring directly; only the others are clipped.  The result has the input
+ * stage's layout and
  * rules: the same neighbour codes, edges shorter than 1e-12 (R_i + R_j)/2
  * dropped, an edge owned by the lower-numbered cell (a wall edge by its
  * cell; an edge with the cell's own periodic image by the side with code
