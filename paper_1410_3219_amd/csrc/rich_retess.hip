@@ -679,7 +679,9 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
 // counter-clockwise by less than half a turn (and more than kVertexSin), the
 // ring winds once, and every vertex lies inside every other candidate's half
 // plane by a margin far above the rounding of the test (kVertexMargin of the
-// squared lengths involved): the polygon is then the intersection of the
+// candidate's half squared distance plus the largest squared vertex distance;
+// with one margin for all vertices, the vertex of largest projection on a
+// candidate decides for all of them): the polygon is then the intersection of the
 // candidates' half planes, and its edges (all of positive length, well above
 // the input stage's cut for dropping one) are the ring's neighbours.  The
 // candidates are the clip's: the mirrors of a walled box, the ring, and the
@@ -691,8 +693,10 @@ constexpr int kRingFast = 8;            // ring entries held in registers
 constexpr double kVertexMargin = 1e-9;  // relative margin of every vertex test
 constexpr double kVertexSin = 0.05;     // least sine of a consecutive pair's angle
 
+// (launch bounds for 4 waves per SIMD: a few registers spill, which costs
+// less than the latency 3 waves leave exposed)
 template <bool B, bool WALLS>
-__global__ __launch_bounds__(kThreads) void k_rt_vertex(Args one, Batch bt) {
+__global__ __launch_bounds__(kThreads, 4) void k_rt_vertex(Args one, Batch bt) {
   constexpr int N = kRingFast;
   int blk;
   const Args& a = block_run<B>(one, bt.cstart, bt, blk);
@@ -738,7 +742,7 @@ __global__ __launch_bounds__(kThreads) void k_rt_vertex(Args one, Batch bt) {
   }
 
   // vertex k: equidistant from r_i, ring entries k and k+1 (cyclically)
-  double vx[N], vy[N], mq[N];
+  double vx[N], vy[N];
   double r2 = 0.0;
   int wraps = 0, start = 0;
 #pragma unroll
@@ -755,7 +759,6 @@ __global__ __launch_bounds__(kThreads) void k_rt_vertex(Args one, Batch bt) {
     vx[k] = (ha * by - hb * ay) * inv;
     vy[k] = (ax * hb - ha * bx) * inv;
     const double q = vx[k] * vx[k] + vy[k] * vy[k];
-    mq[k] = kVertexMargin * q;
     if (k < n) {
       ok = ok && turn;
       r2 = fmax(r2, q);
@@ -769,8 +772,9 @@ __global__ __launch_bounds__(kThreads) void k_rt_vertex(Args one, Batch bt) {
   ok = ok && wraps == 1;
 
   // every vertex inside every other candidate's half plane, by the margin
+  const double mr = kVertexMargin * r2;
   auto inside = [&](int k, double ux, double uy, double hu) -> bool {
-    return hu - (vx[k] * ux + vy[k] * uy) > kVertexMargin * hu + mq[k];
+    return hu - (vx[k] * ux + vy[k] * uy) > kVertexMargin * hu + mr;
   };
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -823,10 +827,13 @@ __global__ __launch_bounds__(kThreads) void k_rt_vertex(Args one, Batch bt) {
 #pragma unroll
         for (int v = 0; v < N; ++v) known = known || (v < n && id[v] == idu);
         if (known) continue;
-        const double hu = 0.5 * d2;
+        // the largest projection of a vertex on the candidate
+        double p = vx[0] * ux + vy[0] * uy;
 #pragma unroll
-        for (int k = 0; k < N; ++k)
-          if (k < n) ok = ok && inside(k, ux, uy, hu);
+        for (int k = 1; k < N; ++k)
+          if (k < n) p = fmax(p, vx[k] * ux + vy[k] * uy);
+        const double hu = 0.5 * d2;
+        ok = ok && hu - p > kVertexMargin * hu + mr;
       }
     }
   }
