@@ -581,6 +581,8 @@ typedef struct rich_retess_info {
   int64_t n_dropped;  /* degenerate edges left out                          */
   double area_sum;    /* sum of the cell areas (a check value, summed in a
                          fixed order: the same bits on every call)         */
+  int64_t n_clipped;  /* cells that did not keep their previous ring (or
+                         were not proved to) and were clipped              */
 } rich_retess_info;
 
 /* Synchronise `stream` and read the header of ws.  Returns RICH_E_MESH when

@@ -39,7 +39,7 @@
 //                 each kept edge against the neighbour's slot, count
 //   k_rt_scan_*   prefix sums of the counts into off[] and eoff[]
 //   k_rt_emit     edge records and the CSR entries of both sides of each edge
-//   k_rt_end      fold the flags into the sticky word
+//   k_rt_end      fold the flags into the sticky word, count the clipped cells
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -85,7 +85,8 @@ struct Hdr {  // first 64 bytes of the workspace
   int64_t n_edges, n_csr, n_dropped;
   double area_sum;
   int64_t n_wall;   // kept wall edges (each one CSR entry)
-  int64_t pad[2];
+  int64_t n_clip;   // cells the vertex check left to the clip
+  int64_t pad;
 };
 static_assert(sizeof(Hdr) == 64, "result header");
 
@@ -211,13 +212,21 @@ __global__ void k_rt_begin(Args one, Batch bt) {
     h->n_dropped = 0;
     h->area_sum = 0.0;
     h->n_wall = 0;
+    h->n_clip = 0;
   }
 }
 
 template <bool B>
-__global__ void k_rt_end(Hdr* one, Batch bt) {
-  Hdr* h = B ? bt.descs[blockIdx.x].hdr : one;
+__global__ void k_rt_end(Args one, Batch bt) {
+  const Args& a = B ? bt.descs[blockIdx.x] : one;
+  Hdr* h = a.hdr;
+  // the cells the vertex check queued for the clip (one wave sums the
+  // segment counters)
+  int c = 0;
+  for (int t = threadIdx.x; t < kSeg; t += blockDim.x) c += a.qcnt[t * kSegStride];
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
   if (threadIdx.x == 0) {
+    h->n_clip = c;
     h->sticky |= h->flags;
     if (B) {
       bt.hdr_out[blockIdx.x] = *h;
@@ -1401,7 +1410,7 @@ void launch_all(const retess::Args& a, const retess::Batch& bt, int gc, int gs, 
   hipLaunchKernelGGL(k_rt_scan_blocks<B>, dim3(n_runs), dim3(kScanThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_scan_add<B>, dim3(gs), dim3(kScanThreads), 0, st, a, bt);
   hipLaunchKernelGGL(k_rt_emit<B>, dim3(gc), dim3(kGroupThreads), 0, st, a, bt);
-  hipLaunchKernelGGL(k_rt_end<B>, dim3(n_runs), dim3(64), 0, st, a.hdr, bt);
+  hipLaunchKernelGGL(k_rt_end<B>, dim3(n_runs), dim3(64), 0, st, a, bt);
 }
 
 // Batch workspace: descriptors, the two start tables, result headers, flags.
@@ -1531,6 +1540,7 @@ int rich_retess_batch_result(int32_t n, void* bws, void* stream, rich_retess_inf
     info[r].n_csr = h[r].n_csr;
     info[r].n_dropped = h[r].n_dropped;
     info[r].area_sum = h[r].area_sum;
+    info[r].n_clipped = h[r].n_clip;
     status[r] = h[r].flags ? RICH_E_MESH : RICH_OK;
   }
   return RICH_OK;
@@ -1556,6 +1566,7 @@ int rich_retess_result(void* ws, void* stream, rich_retess_info* info) {
   info->n_csr = h.n_csr;
   info->n_dropped = h.n_dropped;
   info->area_sum = h.area_sum;
+  info->n_clipped = h.n_clip;
   return h.flags ? RICH_E_MESH : RICH_OK;
 }
 

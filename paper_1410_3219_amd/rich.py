@@ -43,7 +43,8 @@ class RichMeshBufs(C.Structure):
 
 class RichRetessInfo(C.Structure):
     _fields_ = [("flags", C.c_int32), ("sticky", C.c_int32), ("n_edges", C.c_int64),
-                ("n_csr", C.c_int64), ("n_dropped", C.c_int64), ("area_sum", C.c_double)]
+                ("n_csr", C.c_int64), ("n_dropped", C.c_int64), ("area_sum", C.c_double),
+                ("n_clipped", C.c_int64)]
 
 
 RETESS_POINT, RETESS_FAN, RETESS_CLIP, RETESS_ASYM, RETESS_AREA, RETESS_CAP = 1, 2, 4, 8, 16, 32
@@ -556,7 +557,8 @@ def rich_retess_result(ws, stream=None):
     if st not in (RICH_OK, RICH_E_MESH):
         _check(st, "rich_retess_result")
     return st, {"flags": info.flags, "sticky": info.sticky, "n_edges": info.n_edges,
-                "n_csr": info.n_csr, "n_dropped": info.n_dropped, "area_sum": info.area_sum}
+                "n_csr": info.n_csr, "n_dropped": info.n_dropped, "area_sum": info.area_sum,
+                "n_clipped": info.n_clipped}
 
 
 def rich_retess_batch(prevs, Xs, bufs, wss, bws=None, stream=None):
@@ -590,7 +592,8 @@ def rich_retess_batch_result(n, bws, stream=None):
                                           info, st), "rich_retess_batch_result")
     return [(int(st[r]), {"flags": info[r].flags, "sticky": info[r].sticky,
                           "n_edges": info[r].n_edges, "n_csr": info[r].n_csr,
-                          "n_dropped": info[r].n_dropped, "area_sum": info[r].area_sum})
+                          "n_dropped": info[r].n_dropped, "area_sum": info[r].area_sum,
+                          "n_clipped": info[r].n_clipped})
             for r in range(n)]
 
 

@@ -209,8 +209,47 @@ def test_retess_after_edge_flips_matches_oracle_voronoi(name):
     compare_meshes(dev, ref, h)
     lost = np.setdiff1d(csr_keys(m)[0], csr_keys(ref)[0])
     gained = np.setdiff1d(csr_keys(ref)[0], csr_keys(m)[0])
-    print(f"\n{name}: {lost.size} CSR entries lost, {gained.size} gained")
+    print(f"\n{name}: {lost.size} CSR entries lost, {gained.size} gained, "
+          f"{info['n_clipped']} of {m.n_cells} cells clipped")
     assert lost.size > 20 and gained.size > 20
+    # both paths ran: the cells that kept their ring were proved by the
+    # vertex check, the others clipped
+    assert 0 < info["n_clipped"] < m.n_cells
+
+
+@pytest.mark.parametrize("name", ["wave", "sod"])
+def test_retess_vertex_check_proves_unchanged_rings(name):
+    """Cells that keep their previous neighbours are proved by the vertex
+    check alone: after a rigid translation of the periodic wave's points no
+    cell is clipped; on the walled shock tube's own points only the cells
+    with a wall edge (which the check leaves to the clip) and at most 1% more
+    are.  Either way the mesh is the oracle's Voronoi mesh."""
+    from paper_1410_3219_amd import rich as R
+    import torch
+    P, m, Q, X = _initial(name, 32)
+    L = (m.box[2] - m.box[0], m.box[3] - m.box[1])
+    h = math.sqrt(L[0] * L[1] / m.n_cells)
+    if m.bc == 1:
+        X1 = np.stack([np.mod(X[0] + 0.37 * h - m.box[0], L[0]) + m.box[0],
+                       np.mod(X[1] + 0.21 * h - m.box[1], L[1]) + m.box[1]])
+    else:
+        X1 = X.copy()
+    dm = R.DeviceMesh.from_host(m)
+    bufs = R.DeviceMeshBufs(m.n_cells, m.box, m.bc)
+    tws = R.retess_workspace(m.n_cells)
+    R.rich_retess(dm, torch.from_numpy(np.ascontiguousarray(X1)).cuda(), bufs, tws)
+    st, info = R.rich_retess_result(tws)
+    assert st == 0 and info["flags"] == 0, info
+    dev = R.mesh_to_host(bufs.mesh(), info["n_edges"], info["n_csr"])
+    check_structure(dev)
+    ref = O.voronoi_mesh(O.voronoi(X1[0], X1[1], m.box, m.bc))
+    compare_meshes(dev, ref, h)
+    if m.bc == 1:
+        assert info["n_clipped"] == 0, info
+    else:
+        walled = np.unique(np.asarray(m.e_i)[m.nb_code() >= 9]).size
+        assert walled > 0
+        assert walled <= info["n_clipped"] <= walled + m.n_cells // 100, (walled, info)
 
 
 def test_retess_repeat_is_bitwise_deterministic():
