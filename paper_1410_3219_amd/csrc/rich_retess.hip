@@ -30,6 +30,7 @@
 //
 // Pipeline (one launch each, all on the caller's stream):
 //   k_rt_begin    clear the result header and the queue counters
+//   k_rt_pack     the new points packed in pairs
 //   k_rt_vertex   one thread per cell: the cell from its previous ring, when
 //                 every vertex passes (else queued for the clip)
 //   k_rt_clip     one thread per queued cell: the cell's edges, area, centroid
@@ -107,6 +108,7 @@ struct Args {
   int64_t p_n_csr, p_n_edges;
   // new points and output
   const double *x, *y;
+  double2* xy;         // [n] the new points packed in pairs (filled by k_rt_pack)
   rich_cell* cells;
   rich_edge* edges;
   int32_t *off, *idx, *eoff;
@@ -214,6 +216,16 @@ __global__ void k_rt_begin(Args one, Batch bt) {
     h->n_wall = 0;
     h->n_clip = 0;
   }
+}
+
+// The new points packed in pairs, so that a candidate's point is one 16-byte
+// load (the kernels gather them by cell index many times over).
+template <bool B>
+__global__ __launch_bounds__(kThreads) void k_rt_pack(Args one, Batch bt) {
+  int blk;
+  const Args& a = block_run<B>(one, bt.cstart, bt, blk);
+  const int i = blk * kThreads + threadIdx.x;
+  if (i < a.n) a.xy[i] = make_double2(a.x[i], a.y[i]);
 }
 
 template <bool B>
@@ -350,8 +362,9 @@ __device__ __forceinline__ void ring_chunk(const Args& a, int k0, int k1, int se
 #pragma unroll
   for (int m = 0; m < CH; ++m) {
     const int cell = c[m] < 0 ? 0 : c[m];
-    cx[m] = a.x[cell];
-    cy[m] = a.y[cell];
+    const double2 p = a.xy[cell];
+    cx[m] = p.x;
+    cy[m] = p.y;
   }
 }
 
@@ -1289,7 +1302,7 @@ namespace {
 size_t rt_align(size_t v) { return (v + 255) / 256 * 256; }
 
 struct RtLayout {
-  size_t deg, s_nb, s_geo, s_flag, s_back, bsum, cpart, qcnt, queue, total;
+  size_t deg, s_nb, s_geo, s_flag, s_back, bsum, cpart, qcnt, queue, xy, total;
   int nb, qcap;
 };
 
@@ -1310,6 +1323,7 @@ RtLayout rt_layout(int64_t n) {
   L.qcnt = o;   o += rt_align(4 * (size_t)retess::kSeg * retess::kSegStride);
   L.qcap = (int)(retess::kThreads * ((blocks + retess::kSeg - 1) / retess::kSeg));
   L.queue = o;  o += rt_align(4 * (size_t)retess::kSeg * (size_t)L.qcap);
+  L.xy = o;     o += rt_align(16 * (size_t)n);
   L.total = o;
   return L;
 }
@@ -1372,6 +1386,7 @@ int make_args(const rich_mesh* prev, const double* x, const double* y,
   a.qcnt = reinterpret_cast<int32_t*>(w + L.qcnt);
   a.queue = reinterpret_cast<int32_t*>(w + L.queue);
   a.qcap = L.qcap;
+  a.xy = reinterpret_cast<double2*>(w + L.xy);
   a.x0 = prev->box[0];
   a.y0 = prev->box[1];
   a.x1 = prev->box[2];
@@ -1384,13 +1399,14 @@ int make_args(const rich_mesh* prev, const double* x, const double* y,
   return RICH_OK;
 }
 
-// The ten launches of one re-tessellation of one kind of box (B: of n_runs runs at once, with
+// The eleven launches of one re-tessellation of one kind of box (B: of n_runs runs at once, with
 // gc cell blocks and gs scan blocks in all).
 template <bool B>
 void launch_all(const retess::Args& a, const retess::Batch& bt, int gc, int gs, int n_runs,
                 bool walls, bool periodic, hipStream_t st) {
   using namespace retess;
   hipLaunchKernelGGL(k_rt_begin<B>, dim3(n_runs), dim3(64), 0, st, a, bt);
+  hipLaunchKernelGGL(k_rt_pack<B>, dim3(gc), dim3(kThreads), 0, st, a, bt);
   if (walls) {
     hipLaunchKernelGGL((k_rt_vertex<B, true>), dim3(gc), dim3(kThreads), 0, st, a, bt);
     hipLaunchKernelGGL((k_rt_clip<B, true, kSlotsFast, false>), dim3(gc), dim3(kThreads), 0, st,
