@@ -893,8 +893,8 @@ def make_problem(name, k):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="wave", choices=["wave", "sedov", "sod"])
     ap.add_argument("--k", type=int, default=0, help="lattice side (default per workload)")
     ap.add_argument("--riemann", type=int, default=0)
