@@ -733,12 +733,15 @@ __global__ __launch_bounds__(kThreads, 4) void k_rt_vertex(Args one, Batch bt) {
   ok = ok && k0 >= 0 && n >= 3 && n <= N && k1 <= a.p_n_csr;
   if (!ok) k1 = k0;   // (nothing of the ring is loaded)
 
-  // displacement of cell c from r_i (nearest periodic image) and its id
+  // displacement of cell c from r_i (nearest periodic image) and its id.
+  // The image is sought only when some lane of the wave needs it (a wave
+  // holds nearby cells, so all but the waves at the box's edges skip it);
+  // otherwise the plain difference is that image and its code is 0.
   auto displacement = [&](int c, double xc, double yc, double& dx, double& dy) -> int32_t {
     dx = xc - xi;
     dy = yc - yi;
     int code = 0;
-    if (!WALLS) {
+    if (!WALLS && __any(fabs(dx) > 0.5 * a.Lx || fabs(dy) > 0.5 * a.Ly)) {
       int sx = 0, sy = 0;
       if (dx > 0.5 * a.Lx) { dx -= a.Lx; sx = -1; } else if (dx < -0.5 * a.Lx) { dx += a.Lx; sx = 1; }
       if (dy > 0.5 * a.Ly) { dy -= a.Ly; sy = -1; } else if (dy < -0.5 * a.Ly) { dy += a.Ly; sy = 1; }
