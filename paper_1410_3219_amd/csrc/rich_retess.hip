@@ -709,8 +709,8 @@ __global__ __launch_bounds__(kThreads) void k_rt_clip(Args one, Batch bt) {
 // candidates are the clip's: the mirrors of a walled box, the ring, and the
 // neighbours' neighbours that could reach a vertex.  A cell that fails any
 // of these tests (a new neighbour, a lost one, a near-degenerate vertex, a
-// ring longer than kRingFast or next to a wall) is marked (deg = kDegClip)
-// and left to the clip launches, which decide every case.
+// ring longer than kRingFast or next to a wall) is queued for the clip
+// launches (deg = kDegClip), which decide every case.
 constexpr int kRingFast = 8;            // ring entries held in registers
 constexpr double kVertexMargin = 1e-9;  // relative margin of every vertex test
 constexpr double kVertexSin = 0.05;     // least sine of a consecutive pair's angle
