@@ -538,11 +538,13 @@ def bench_serve_moving(args, R, log, rate=500.0):
     tpl = S.build_templates(sizes, kinds, n_threads=args.threads, moving=True)
     log(f"[bench] moving serving templates {[t.n for t in tpl]} ({time.time() - t0:.1f}s)")
     res, _ = S.run(tpl, rate=rate, duration=args.serve_seconds, log=log)
+    keys = ("requests", "failed_requests", "launches", "mean_batch", "p50_ms", "p99_ms",
+            "cell_updates_per_s", "wall_s", "offered_rate", "offered_cell_updates_per_s")
+    # the static leg's rate on moving meshes
+    full, _ = S.run(tpl, rate=args.serve_rate, duration=args.serve_seconds, seed=11, log=log)
+    res["at_static_rate"] = {k: full[k] for k in keys + ("host_fallback_steps",)}
     sat, _ = S.run(tpl, rate=10 * rate, duration=0.25 * args.serve_seconds, seed=10, log=log)
-    res["saturated"] = {k: sat[k] for k in ("requests", "failed_requests", "launches",
-                                            "mean_batch", "p50_ms", "p99_ms",
-                                            "cell_updates_per_s", "wall_s", "offered_rate",
-                                            "offered_cell_updates_per_s")}
+    res["saturated"] = {k: sat[k] for k in keys}
     return res
 
 
