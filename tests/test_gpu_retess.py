@@ -252,6 +252,34 @@ def test_retess_vertex_check_proves_unchanged_rings(name):
         assert walled <= info["n_clipped"] <= walled + m.n_cells // 100, (walled, info)
 
 
+@pytest.mark.parametrize("k", [4, 5, 8])
+def test_retess_small_periodic_boxes_match_oracle_voronoi(k):
+    """The smallest periodic boxes the device rebuild takes (16 cells and
+    up): every cell is near the box's edges, so every wave seeks periodic
+    images, and a cell's candidates can hold two images of one cell.  Both
+    the points of the previous mesh and points moved by up to a tenth of the
+    spacing give the oracle's Voronoi mesh."""
+    from paper_1410_3219_amd import rich as R
+    import torch
+    P, m, Q, X = _initial("wave", k, seed=3)
+    L = (m.box[2] - m.box[0], m.box[3] - m.box[1])
+    h = math.sqrt(L[0] * L[1] / m.n_cells)
+    d = np.random.default_rng(k).uniform(-0.1 * h, 0.1 * h, X.shape)
+    for X1 in (X, X + d):
+        X1 = np.stack([np.mod(X1[0] - m.box[0], L[0]) + m.box[0],
+                       np.mod(X1[1] - m.box[1], L[1]) + m.box[1]])
+        dm = R.DeviceMesh.from_host(m)
+        bufs = R.DeviceMeshBufs(m.n_cells, m.box, m.bc)
+        tws = R.retess_workspace(m.n_cells)
+        R.rich_retess(dm, torch.from_numpy(np.ascontiguousarray(X1)).cuda(), bufs, tws)
+        st, info = R.rich_retess_result(tws)
+        assert st == 0 and info["flags"] == 0, info
+        dev = R.mesh_to_host(bufs.mesh(), info["n_edges"], info["n_csr"])
+        check_structure(dev)
+        ref = O.voronoi_mesh(O.voronoi(X1[0], X1[1], m.box, m.bc))
+        compare_meshes(dev, ref, h)
+
+
 def test_retess_repeat_is_bitwise_deterministic():
     from paper_1410_3219_amd import rich as R
     P, m, Q, X = _initial("sedov", 30)
