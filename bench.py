@@ -508,6 +508,7 @@ def bench_serve(args, R, log):
     t0 = time.time()
     tpl = S.build_templates(sizes, kinds, n_threads=args.threads)
     log(f"[bench] serving templates {[t.n for t in tpl]} ({time.time() - t0:.1f}s)")
+    S.run(tpl, rate=args.serve_rate, duration=0.5, seed=8, log=log)   # warm-up, not reported
     res, _ = S.run(tpl, rate=args.serve_rate, duration=args.serve_seconds, log=log)
     # the same mix offered at ten times the rate for a short time: the loop
     # runs saturated, so its throughput is the most the served path delivers
@@ -537,6 +538,7 @@ def bench_serve_moving(args, R, log, rate=500.0):
     t0 = time.time()
     tpl = S.build_templates(sizes, kinds, n_threads=args.threads, moving=True)
     log(f"[bench] moving serving templates {[t.n for t in tpl]} ({time.time() - t0:.1f}s)")
+    S.run(tpl, rate=rate, duration=0.5, seed=8, log=log)   # warm-up, not reported
     res, _ = S.run(tpl, rate=rate, duration=args.serve_seconds, log=log)
     keys = ("requests", "failed_requests", "launches", "mean_batch", "p50_ms", "p99_ms",
             "cell_updates_per_s", "wall_s", "offered_rate", "offered_cell_updates_per_s")
@@ -908,7 +910,7 @@ def main():
     ap.add_argument("--batch-runs", type=int, default=256)
     ap.add_argument("--sweep-steps", type=int, default=20)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--threads", type=int, default=0, help="host tessellation threads")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a device-to-device copy of this size first (counter calibration)")
